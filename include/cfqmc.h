@@ -1,0 +1,150 @@
+/* cfqmc.h - C ABI of the MI355X continuous-field DQMC sweep.
+ *
+ * Method: Liao, Chen, Rong, Assaad, Janssen, Meng, "Numerical evidence of a
+ * critical point in the (2+1)D SO(5) nonlinear sigma model with
+ * Wess-Zumino-Witten term" (arXiv 2605.03700), Methods section:
+ *   - torus density operator (eq. torus density operator) and momentum cutoff,
+ *   - Fierz-transformed Hamiltonian H = sum_i g_i H_i (eq. newmodel),
+ *   - continuous Hubbard-Stratonovich transform (eq. HS transform),
+ *   - Z = int Dphi exp(-S_0) det[1 + B(beta,0)] and the equal-time Green's
+ *     function G(tau) = (1 + B(tau,0) B(beta,tau))^{-1} (eq. green function),
+ *   - Langevin (MALA) proposal of all fields of a time slice (eq. Langevin
+ *     proposal) with the Metropolis-Hastings test and the adaptive step size.
+ *
+ * Conventions
+ *   N = n_phi orbitals per flavour, n = 2N spin-block dimension (the Fierz
+ *   channels act as identity on spin, so G_4N = 1_spin (x) G_2N).
+ *   Spin-block index v*N + k (valley v, orbital k = 0..N-1); 4N index
+ *   s*2N + v*N + k. G_ij = <c_i c_j^dagger>, complex128, row major.
+ *   Fields phi are real, laid out [chain][l_tau][4][n_q]: channel i = 0..3
+ *   (O^i = 1, tau_x, tau_y, tau_z) and component c = 0..n_q-1, where c = 0 is
+ *   sqrt(2) n_0 and the remaining components follow the half set of momenta
+ *   {q_y > 0} U {q_y = 0, q_x > 0} sorted by (q_y, q_x), each contributing
+ *   n_q + n_{-q} then i (n_q - n_{-q}) (self-conjugate momenta of the
+ *   Brillouin-zone mode contribute one component sqrt(2) n_q).
+ *
+ * Ownership: the caller owns every host buffer it passes; the library owns
+ * all device state it allocates. Device output buffers (measure_G with
+ * on_device = 1) belong to the caller. Calls enqueue on the stream given at
+ * creation; calls that return host data synchronise that stream.
+ * Errors: every call returns 0 on success or a negative CFQMC_E* code; the
+ * message is available from cfqmc_last_error. An error other than
+ * CFQMC_ENUMERIC leaves the context unchanged. CFQMC_ENUMERIC (non-finite
+ * values, exponential range exceeded) marks the chain state invalid until
+ * cfqmc_init_fields is called again.
+ * Threading: one context per host thread at a time; no global state.
+ */
+#ifndef CFQMC_H
+#define CFQMC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CFQMC_OK = 0,
+  CFQMC_EINVAL = -1,   /* invalid argument */
+  CFQMC_ENOMEM = -2,   /* device allocation failed */
+  CFQMC_EHIP = -3,     /* HIP runtime error */
+  CFQMC_ENUMERIC = -4, /* non-finite result or exponential range exceeded */
+  CFQMC_ESTATE = -5,   /* call not valid in the current state */
+  CFQMC_ENOTIMPL = -6
+};
+
+enum { CFQMC_Q_PAPER = 0, CFQMC_Q_RADIUS = 1, CFQMC_Q_BZ = 2, CFQMC_Q_LIST = 3 };
+enum { CFQMC_FP64 = 0, CFQMC_MIXED = 1 };
+
+typedef struct cfqmc_ctx cfqmc_ctx;
+
+typedef struct {
+  int32_t n_phi;         /* LLL degeneracy N_phi (Methods, toric regularization), 1..140 */
+  int32_t l_tau;         /* imaginary-time slices N_tau = beta / dtau */
+  double dtau;           /* Trotter step (eq. Trotter decomposition) */
+  double u0, uk, un;     /* couplings U_0, U_K, U_N (Results: U_0 = 1, SO(5) line U_K = U_N = u) */
+  int32_t q_mode;        /* CFQMC_Q_*: paper cutoff exp(-2 pi |q|^2/(4N)) > 0.01, |q| l_B <= q_max,
+                            the N^2 Brillouin-zone momenta, or an explicit list */
+  double q_max;          /* CFQMC_Q_RADIUS only */
+  const int32_t* q_list; /* CFQMC_Q_LIST: pairs (qx, qy), closed under q -> -q; host, read at create */
+  int32_t n_q_list;
+  int32_t n_stab;        /* slices between FP64 recomputations of G (UDT stabilisation) */
+  int32_t precision;     /* CFQMC_FP64 or CFQMC_MIXED (FP32 MFMA, FP64 accumulation, FP64 stabilisation) */
+  double eps0;           /* initial Langevin step size epsilon */
+  double r0, deps;       /* acceptance set point and gain of eps <- eps + (r_a - r0) deps (0.574, 0.1) */
+  double eps_min, eps_max;
+  int32_t adapt_eps;     /* 1: adapt after every sweep; 0: frozen */
+  uint64_t seed;         /* Philox4x32-10 key for fields and noise */
+  int32_t n_chains;      /* independent chains of this shape, run together in every launch */
+  const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
+  int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential (default 2) */
+  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..3 fixed configuration */
+} cfqmc_params;
+
+typedef struct {
+  int64_t proposed, accepted; /* slice proposals and acceptances over the call */
+  double eps;                 /* step size after the call */
+  double max_stab_err;        /* max |G_updated - G_recomputed_fp64| at recomputation points */
+  double max_phase_err;       /* max |Im ln R| (mod 2 pi) of the weight ratio, sign-free check */
+  int32_t exp_range_flag;     /* 1 if an exponential needed more squarings than allowed */
+  int32_t pad;
+} cfqmc_stats;
+
+/* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
+ * n_stab=10, FP64, eps0=0.5, r0=0.574, deps=0.1, eps in [1e-3, 5], adapt on,
+ * one chain, exp_squarings=2, tile_cfg=-1). */
+void cfqmc_default_params(cfqmc_params* p);
+
+/* Create a context: builds the model tables on the host, allocates device
+ * state. hip_stream: a hipStream_t (NULL = default stream). No fields yet. */
+int cfqmc_create(const cfqmc_params* p, void* hip_stream, cfqmc_ctx** out);
+int cfqmc_destroy(cfqmc_ctx* c);
+
+/* Sizes: number of HS components per channel, chains, 4N. Any pointer may be NULL. */
+int cfqmc_sizes(const cfqmc_ctx* c, int32_t* n_q, int32_t* n_chains, int32_t* dim_g4n);
+
+/* Set the fields (host [n_chains][l_tau][4][n_q]) or draw them N(0,1) on the
+ * device from the seed (phi == NULL); rebuilds every slice propagator, both
+ * UDT stacks and G(0) in FP64; resets eps and statistics. */
+int cfqmc_init_fields(cfqmc_ctx* c, const double* phi);
+int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out);
+
+/* Run n_sweeps sweeps (slices tau = 1..L each) on all chains.
+ * replay: NULL (device Philox noise) or host [n_chains][n_sweeps][l_tau][4 n_q + 1]
+ * holding per slice the 4 n_q proposal normals (channel-major) and the
+ * acceptance uniform u. stats: NULL or [n_chains]. Synchronises. */
+int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stats* stats);
+
+/* Equal-time Green's function G(tau) of one chain, 0 <= tau <= l_tau, expanded
+ * to 4N (1_spin (x) G). g_out: [4N][4N] complex128, host (on_device = 0) or
+ * device memory owned by the caller (on_device = 1). Computed in FP64 from the
+ * UDT stacks. */
+int cfqmc_measure_G(cfqmc_ctx* c, int32_t chain, int32_t tau, void* g_out, int32_t on_device);
+
+/* ln of the fermion weight exp(sum_tau c_tau) det(1 + B(beta,0))^2 of one chain
+ * (complex; the imaginary part is 0 mod 2 pi for the sign-free model), FP64. */
+int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im);
+
+/* Equal-time observables of the current configuration of one chain:
+ * s_q0[5] = Re S^i_{q=0}, i = 1..5, and m2 = Re m^2_SO(5) (Results, eq. for
+ * m^2_SO(5)), from G(l_tau) by Wick's theorem. */
+int cfqmc_observables(cfqmc_ctx* c, int32_t chain, double* s_q0, double* m2);
+
+/* Per-sweep series of m^2_SO(5) recorded at the end of every sweep since the
+ * last init: writes up to max_len values, returns the count in *len. */
+int cfqmc_series(cfqmc_ctx* c, int32_t chain, double* out, int32_t max_len, int32_t* len);
+
+/* Accept flags and ln A of every slice of the last sweep of one chain. */
+int cfqmc_last_sweep(cfqmc_ctx* c, int32_t chain, int32_t* accepted, double* ln_a);
+
+int cfqmc_get_eps(cfqmc_ctx* c, double* eps /* [n_chains] */);
+int cfqmc_set_eps(cfqmc_ctx* c, const double* eps /* [n_chains] */);
+
+/* Tile configuration chosen for (channel application, n x n GEMM). */
+int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg);
+
+const char* cfqmc_last_error(const cfqmc_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

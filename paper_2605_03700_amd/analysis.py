@@ -1,0 +1,43 @@
+"""Autocorrelation analysis of Monte Carlo time series (host side).
+
+Integrated autocorrelation time with Sokal's automatic window (Madras & Sokal
+1988; Wolff 2004 uses the same windowing idea): tau_int(W) = 1/2 + sum_{t=1}^{W}
+rho(t), choosing the smallest W with W >= c * tau_int(W), c = 5.
+Independent samples per second = sweeps per second / (2 tau_int).
+"""
+import numpy as np
+
+
+def autocorr(x):
+    """Normalised autocorrelation rho(t) of a 1-D series (FFT, zero padded)."""
+    x = np.asarray(x, dtype=float)
+    n = x.size
+    if n < 2:
+        return np.ones(1)
+    y = x - x.mean()
+    f = np.fft.rfft(y, 2 * n)
+    ac = np.fft.irfft(f * np.conj(f))[:n]
+    if ac[0] <= 0:
+        return np.ones(1)
+    return ac / ac[0]
+
+
+def tau_int(x, c=5.0):
+    """Integrated autocorrelation time (in units of the series step) and the window."""
+    rho = autocorr(x)
+    n = rho.size
+    if n < 2:
+        return 0.5, 0
+    tau = 0.5
+    for w in range(1, n):
+        tau += rho[w]
+        if w >= c * tau:
+            return max(tau, 0.5), w
+    return max(tau, 0.5), n - 1
+
+
+def independent_samples_per_s(sweeps_per_s, series_list):
+    """sweeps/s divided by 2 tau_int, tau_int the maximum over the given series."""
+    taus = [tau_int(s)[0] for s in series_list if len(s) > 1]
+    t = max(taus) if taus else 0.5
+    return sweeps_per_s / (2.0 * t), t

@@ -1,0 +1,214 @@
+"""Python binding of the C ABI in include/cfqmc.h (ctypes; argument marshalling only).
+
+Every step of the sweep runs in the HIP library libcfqmc.so built for gfx950.
+There is no CPU fallback: if the library is missing or no GPU is visible the
+calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfqmc.so")
+
+Q_PAPER, Q_RADIUS, Q_BZ, Q_LIST = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "ESTATE", -6: "ENOTIMPL"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_phi", ctypes.c_int32), ("l_tau", ctypes.c_int32), ("dtau", ctypes.c_double),
+        ("u0", ctypes.c_double), ("uk", ctypes.c_double), ("un", ctypes.c_double),
+        ("q_mode", ctypes.c_int32), ("q_max", ctypes.c_double),
+        ("q_list", ctypes.POINTER(ctypes.c_int32)), ("n_q_list", ctypes.c_int32),
+        ("n_stab", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("eps0", ctypes.c_double), ("r0", ctypes.c_double), ("deps", ctypes.c_double),
+        ("eps_min", ctypes.c_double), ("eps_max", ctypes.c_double),
+        ("adapt_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_chains", ctypes.c_int32),
+        ("chain_u", ctypes.POINTER(ctypes.c_double)), ("exp_squarings", ctypes.c_int32),
+        ("tile_cfg", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("eps", ctypes.c_double),
+                ("max_stab_err", ctypes.c_double), ("max_phase_err", ctypes.c_double),
+                ("exp_range_flag", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+
+EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
+           "cfqmc_get_fields", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
+           "cfqmc_series", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
+           "cfqmc_last_error"]
+
+
+def load():
+    """Load libcfqmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcfqmc.so not found at %s; run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.cfqmc_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.cfqmc_default_params.restype = None
+    lib.cfqmc_create.argtypes = [ctypes.POINTER(Params), P, ctypes.POINTER(P)]
+    lib.cfqmc_destroy.argtypes = [P]
+    lib.cfqmc_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_init_fields.argtypes = [P, P]
+    lib.cfqmc_get_fields.argtypes = [P, P]
+    lib.cfqmc_sweep.argtypes = [P, ctypes.c_int32, P, P]
+    lib.cfqmc_measure_G.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32]
+    lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.cfqmc_observables.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
+    lib.cfqmc_series.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_last_sweep.argtypes = [P, ctypes.c_int32, P, P]
+    lib.cfqmc_get_eps.argtypes = [P, P]
+    lib.cfqmc_set_eps.argtypes = [P, P]
+    lib.cfqmc_tile_config.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_last_error.argtypes = [P]
+    lib.cfqmc_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("cfqmc_default_params", "cfqmc_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+class CFQMC:
+    """One context of the C ABI: n_chains chains of one lattice shape."""
+
+    def __init__(self, n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
+                 q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
+                 eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
+                 tile_cfg=-1, stream=None):
+        lib = load()
+        self.lib = lib
+        p = Params()
+        lib.cfqmc_default_params(ctypes.byref(p))
+        p.n_phi, p.l_tau, p.dtau = n_phi, l_tau, dtau
+        p.u0, p.uk, p.un = u0, uk, un
+        p.q_mode, p.q_max = q_mode, q_max
+        self._qlist = None
+        if q_list is not None:
+            self._qlist = np.ascontiguousarray(np.asarray(q_list, dtype=np.int32).reshape(-1))
+            p.q_list = self._qlist.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            p.n_q_list = self._qlist.size // 2
+        p.n_stab, p.precision = n_stab, precision
+        p.eps0, p.r0, p.deps, p.eps_min, p.eps_max = eps0, r0, deps, eps_min, eps_max
+        p.adapt_eps, p.seed, p.n_chains = int(bool(adapt_eps)), seed, n_chains
+        self._cu = None
+        if chain_u is not None:
+            self._cu = np.ascontiguousarray(np.asarray(chain_u, dtype=np.float64).reshape(n_chains, 3))
+            p.chain_u = self._cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
+        if stream is None:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible: the CF-DQMC library runs on the MI355X only")
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self._check(lib.cfqmc_create(ctypes.byref(p), ctypes.c_void_p(stream), ctypes.byref(h)), None)
+        self.h = h
+        nq, nc, d4 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        lib.cfqmc_sizes(h, ctypes.byref(nq), ctypes.byref(nc), ctypes.byref(d4))
+        self.n_q, self.n_chains, self.dim_g4n = nq.value, nc.value, d4.value
+        self.n_phi, self.l_tau = n_phi, l_tau
+
+    def _check(self, rc, h="self"):
+        if rc != 0:
+            msg = ""
+            if h is not None and getattr(self, "h", None) is not None:
+                msg = self.lib.cfqmc_last_error(self.h).decode()
+            raise RuntimeError("cfqmc error %s: %s" % (ERRORS.get(rc, rc), msg))
+
+    def init_fields(self, phi=None):
+        if phi is not None:
+            phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.n_chains, self.l_tau, 4, self.n_q)
+        self._check(self.lib.cfqmc_init_fields(self.h, _ptr(phi)))
+
+    def get_fields(self):
+        out = np.empty((self.n_chains, self.l_tau, 4, self.n_q))
+        self._check(self.lib.cfqmc_get_fields(self.h, _ptr(out)))
+        return out
+
+    def sweep(self, n_sweeps=1, replay=None):
+        if replay is not None:
+            replay = np.ascontiguousarray(replay, dtype=np.float64).reshape(
+                self.n_chains, n_sweeps, self.l_tau, 4 * self.n_q + 1)
+        st = (Stats * self.n_chains)()
+        self._check(self.lib.cfqmc_sweep(self.h, n_sweeps, _ptr(replay), ctypes.cast(st, ctypes.c_void_p)))
+        return [s.as_dict() for s in st]
+
+    def measure_G(self, chain=0, tau=None, out=None):
+        """G(tau) expanded to 4N; out: optional torch complex128 device tensor (4N x 4N)."""
+        tau = self.l_tau if tau is None else tau
+        if out is not None:
+            self._check(self.lib.cfqmc_measure_G(self.h, chain, tau, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        g = np.empty((self.dim_g4n, self.dim_g4n), dtype=np.complex128)
+        self._check(self.lib.cfqmc_measure_G(self.h, chain, tau, _ptr(g), 0))
+        return g
+
+    def logdet(self, chain=0):
+        re, im = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.cfqmc_logdet(self.h, chain, ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+    def observables(self, chain=0):
+        s = np.empty(5)
+        m2 = ctypes.c_double()
+        self._check(self.lib.cfqmc_observables(self.h, chain, _ptr(s), ctypes.byref(m2)))
+        return s, m2.value
+
+    def series(self, chain=0, max_len=1 << 16):
+        out = np.empty(max_len)
+        ln = ctypes.c_int32()
+        self._check(self.lib.cfqmc_series(self.h, chain, _ptr(out), max_len, ctypes.byref(ln)))
+        return out[:ln.value].copy()
+
+    def last_sweep(self, chain=0):
+        acc = np.empty(self.l_tau, dtype=np.int32)
+        lna = np.empty(self.l_tau)
+        self._check(self.lib.cfqmc_last_sweep(self.h, chain, _ptr(acc), _ptr(lna)))
+        return acc, lna
+
+    def get_eps(self):
+        e = np.empty(self.n_chains)
+        self._check(self.lib.cfqmc_get_eps(self.h, _ptr(e)))
+        return e
+
+    def set_eps(self, eps):
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (self.n_chains,)))
+        self._check(self.lib.cfqmc_set_eps(self.h, _ptr(e)))
+
+    def tile_config(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.cfqmc_tile_config(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.lib.cfqmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1020 @@
+// Chain state, sweep orchestration and the C ABI (include/cfqmc.h).
+//
+// Per slice tau of a sweep (all chains of the context advance together, every
+// step is one launch over all chains, no host synchronisation):
+//   1. wrap  G_i = E_i G_{i+1} E_i^{-1}, i = 3..0, G_4 = G(tau-1), G_0 = G(tau)
+//   2. drift from the frames G_i, Langevin proposal phi' (eq. Langevin proposal)
+//   3. h'_i and the channel exponentials P' = e^{alpha h'}, Q' = e^{-alpha h'}
+//   4. M = G_0 + B' B^{-1} (1 - G_0) = 1 + Delta (1 - G_0), Delta = B' B^{-1} - 1
+//   5. LU(M): the determinant ratio det(1 + B'...)/det(1 + B...) = det M
+//   6. G' = G_0 M^{-1} (Woodbury update, rank n for a whole-slice move)
+//   7. drift at phi' from the frames of G', Metropolis-Hastings decision
+//   8. commit G, phi, P/Q of the slice on acceptance
+// Every n_stab slices the block product C_b is formed in FP64, the left UDT
+// stack is advanced, and G is recomputed from the stacks (Loh et al. split)
+// in FP64; the difference to the updated G is recorded. After the sweep the
+// right stack is rebuilt from the final slices for the next sweep.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cfqmc.h"
+#include "kernels.h"
+
+#define EXP_NC 16
+
+namespace {
+
+struct HostTables {
+  std::vector<int> comp_kind, comp_qx, comp_qy;   // kind 0 S, 1 A, 2 C
+  std::vector<double> comp_F, beta;
+  // h table
+  std::vector<int> hoff, h_cre, h_cim, h_qx, h_qy, h_dag;
+  std::vector<double> h_sgn, h_scale, h_F;
+  // trace table
+  std::vector<int> toff, t_qy, t_qx, t_kind, t_comp;
+  std::vector<double> t_F;
+  std::vector<double2> phase;
+};
+
+double form_factor(int qx, int qy, int N) {
+  return std::exp(-2.0 * M_PI * (double)(qx * qx + qy * qy) / (4.0 * N)) / (4.0 * M_PI * std::sqrt((double)N));
+}
+
+int wrap_bz(int v, int N) {
+  int r = ((v % N) + N) % N;
+  return r > N / 2 ? r - N : r;
+}
+
+// Momentum set and components (see cfqmc.h for the ordering).
+bool build_components(const cfqmc_params& p, HostTables& T, std::string& err) {
+  const int N = p.n_phi;
+  std::vector<std::pair<int, int>> qs;
+  if (p.q_mode == CFQMC_Q_PAPER || p.q_mode == CFQMC_Q_RADIUS) {
+    int R;
+    if (p.q_mode == CFQMC_Q_PAPER) R = (int)std::ceil(std::sqrt(4.0 * N * std::log(100.0) / (2.0 * M_PI))) + 1;
+    else R = (int)std::ceil(p.q_max * std::sqrt(N / (2.0 * M_PI))) + 1;
+    for (int qy = -R; qy <= R; ++qy)
+      for (int qx = -R; qx <= R; ++qx) {
+        const double q2 = (double)(qx * qx + qy * qy);
+        bool keep;
+        if (p.q_mode == CFQMC_Q_PAPER) keep = std::exp(-2.0 * M_PI * q2 / (4.0 * N)) > 0.01;
+        else keep = (2.0 * M_PI / N) * q2 <= p.q_max * p.q_max * (1 + 1e-12);
+        if (keep) qs.push_back({qx, qy});
+      }
+  } else if (p.q_mode == CFQMC_Q_BZ) {
+    const int lo = -(N / 2) + (N % 2 == 0 ? 1 : 0), hi = N / 2;
+    for (int qy = lo; qy <= hi; ++qy)
+      for (int qx = lo; qx <= hi; ++qx) qs.push_back({qx, qy});
+  } else if (p.q_mode == CFQMC_Q_LIST) {
+    if (!p.q_list || p.n_q_list <= 0) { err = "q_list missing"; return false; }
+    for (int i = 0; i < p.n_q_list; ++i) qs.push_back({p.q_list[2 * i], p.q_list[2 * i + 1]});
+    for (auto& q : qs) {
+      if (std::count(qs.begin(), qs.end(), q) != 1) { err = "q_list has duplicates"; return false; }
+      if (std::find(qs.begin(), qs.end(), std::make_pair(-q.first, -q.second)) == qs.end()) {
+        err = "q_list not closed under q -> -q";
+        return false;
+      }
+    }
+  } else {
+    err = "unknown q_mode";
+    return false;
+  }
+  // (kind 'P' pair or 'S' self) items, q = 0 first
+  struct Item { int self, qx, qy; };
+  std::vector<Item> items;
+  bool has0 = false;
+  for (auto& q : qs) {
+    if (q.first == 0 && q.second == 0) { has0 = true; continue; }
+    if (p.q_mode == CFQMC_Q_BZ) {
+      const int px = wrap_bz(-q.first, N), py = wrap_bz(-q.second, N);
+      if (px == q.first && py == q.second) items.push_back({1, q.first, q.second});
+      else if (std::make_pair(q.second, q.first) > std::make_pair(py, px)) items.push_back({0, q.first, q.second});
+    } else if (q.second > 0 || (q.second == 0 && q.first > 0)) {
+      items.push_back({0, q.first, q.second});
+    }
+  }
+  std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return std::make_pair(a.qy, a.qx) < std::make_pair(b.qy, b.qx);
+  });
+  if (has0) { T.comp_kind.push_back(0); T.comp_qx.push_back(0); T.comp_qy.push_back(0); }
+  for (auto& it : items) {
+    if (it.self) { T.comp_kind.push_back(0); T.comp_qx.push_back(it.qx); T.comp_qy.push_back(it.qy); }
+    else {
+      for (int k = 1; k <= 2; ++k) { T.comp_kind.push_back(k); T.comp_qx.push_back(it.qx); T.comp_qy.push_back(it.qy); }
+    }
+  }
+  const int nq = (int)T.comp_kind.size();
+  if (nq == 0) { err = "empty momentum set"; return false; }
+  T.comp_F.resize(nq);
+  T.beta.resize(nq);
+  for (int c = 0; c < nq; ++c) {
+    const int qx = T.comp_qx[c], qy = T.comp_qy[c];
+    const double F = form_factor(qx, qy, N);
+    T.comp_F[c] = F;
+    // background c-number -2 tr(q_c): only shifts q_y = 0 (mod N) have a diagonal
+    double tr_re = 0.0, tr_im = 0.0;
+    if (((qy % N) + N) % N == 0) {
+      for (int k = 1; k <= N; ++k) {
+        const double a = M_PI * (double)((2 * k - qy) * qx) / N;
+        tr_re += F * std::cos(a);
+        tr_im += F * std::sin(a);
+      }
+    }
+    const int kind = T.comp_kind[c];
+    T.beta[c] = kind == 0 ? -2.0 * std::sqrt(2.0) * tr_re : (kind == 1 ? -4.0 * tr_re : 4.0 * tr_im);
+  }
+  // h table grouped by shift d = (row - col) mod N
+  std::vector<std::vector<int>> by_shift(N);
+  struct HT { int cre, cim, qx, qy, dag; double sgn, scale, F; };
+  std::vector<HT> terms;
+  for (int c = 0; c < nq; ++c) {
+    const int kind = T.comp_kind[c], qx = T.comp_qx[c], qy = T.comp_qy[c];
+    const double F = T.comp_F[c];
+    if (kind == 0) {
+      terms.push_back({c, -1, qx, qy, 0, 0.0, std::sqrt(2.0), F});
+      by_shift[((qy % N) + N) % N].push_back((int)terms.size() - 1);
+    } else if (kind == 1) {
+      // (phi_A + i phi_C) m_q + (phi_A - i phi_C) m_q^dagger
+      terms.push_back({c, c + 1, qx, qy, 0, 1.0, 1.0, F});
+      by_shift[((qy % N) + N) % N].push_back((int)terms.size() - 1);
+      terms.push_back({c, c + 1, qx, qy, 1, -1.0, 1.0, F});
+      by_shift[((-qy % N) + N) % N].push_back((int)terms.size() - 1);
+    }
+  }
+  T.hoff.assign(N + 1, 0);
+  for (int d = 0; d < N; ++d) {
+    T.hoff[d + 1] = T.hoff[d] + (int)by_shift[d].size();
+    for (int t : by_shift[d]) {
+      const HT& h = terms[t];
+      T.h_cre.push_back(h.cre); T.h_cim.push_back(h.cim); T.h_qx.push_back(h.qx); T.h_qy.push_back(h.qy);
+      T.h_dag.push_back(h.dag); T.h_sgn.push_back(h.sgn); T.h_scale.push_back(h.scale); T.h_F.push_back(h.F);
+    }
+  }
+  // trace table grouped by q_y of the component
+  std::vector<int> rows;
+  for (int c = 0; c < nq; ++c) rows.push_back(T.comp_qy[c]);
+  std::sort(rows.begin(), rows.end());
+  rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+  T.toff.assign(1, 0);
+  for (int qy : rows) {
+    for (int c = 0; c < nq; ++c)
+      if (T.comp_qy[c] == qy) {
+        T.t_qx.push_back(T.comp_qx[c]); T.t_kind.push_back(T.comp_kind[c]); T.t_comp.push_back(c);
+        T.t_F.push_back(T.comp_F[c]);
+      }
+    T.t_qy.push_back(qy);
+    T.toff.push_back((int)T.t_qx.size());
+    if (T.toff.back() - T.toff[T.toff.size() - 2] > 1024) { err = "too many components in one momentum row"; return false; }
+  }
+  T.phase.resize(2 * N);
+  for (int m = 0; m < 2 * N; ++m) T.phase[m] = make_double2(std::cos(M_PI * m / N), std::sin(M_PI * m / N));
+  return true;
+}
+
+}  // namespace
+
+struct Udt {
+  double2* U;   // [chain][nb+1][n][n]
+  double2* T;
+  double* D;    // [chain][nb+1][n]
+};
+
+struct cfqmc_ctx {
+  cfqmc_params p;
+  hipStream_t s;
+  int N, n, nq, L, nch, nstab, nblk_stab, mixed, smax;
+  long long nn, NN;
+  HostTables ht;
+  ModelDev md;
+  std::vector<void*> allocs;
+  // chain state
+  double* phi;
+  double2* PQ;
+  double2* G;
+  double2* F[4];
+  double2* Fp[4];
+  double2* S1;
+  double2* S2;
+  double2* Mw;
+  int* ipiv;
+  double2* lndet;
+  double* phip;
+  double2* PQp;
+  double2* h;
+  // exp work
+  int exp_cap;        // capacity in (entry) units of 4 channels
+  double2 *H2, *X2, *X3, *loE, *hiE, *loO, *hiO, *Eo, *Oo, *Wa, *Wb;
+  double* coef;
+  int* sq;
+  int* d_err;
+  // stabilisation
+  double2* Cb;
+  Udt Ls, Rs;
+  double2 *W1, *A1, *Gr, *Q1, *Q2, *R1, *R2, *Rt, *Tp, *K1, *M1, *Yl, *Wm, *X1, *Gs;
+  double *nrm, *sqd1, *sqd2, *dinvL, *dinvR, *tmpd;
+  int* perm;
+  // scalars per chain
+  double2* alpha;
+  double2 Urot[4][2][2];
+  double* eps;
+  int* acc_count;
+  double* lnA;
+  int* accept;
+  double* stat;
+  unsigned* done;
+  double* part;
+  double* obs;
+  double* stab_err;
+  double* series;
+  int series_cap, series_len;
+  int* hist_acc;
+  double* hist_lnA;
+  double* noise;
+  double2* bg;
+  double2* ldtmp;
+  long long sweep_counter;
+  int cfg_chan, cfg_gemm, cfg_small;
+  bool ready;
+  std::string err;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                        \
+  do {                                                                   \
+    hipError_t e_ = (x);                                                 \
+    if (e_ != hipSuccess) {                                              \
+      c->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x; \
+      return CFQMC_EHIP;                                                 \
+    }                                                                    \
+  } while (0)
+
+template <typename T>
+int dalloc(cfqmc_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    c->err = "device allocation failed";
+    return CFQMC_ENOMEM;
+  }
+  hipMemsetAsync(q, 0, count * sizeof(T), c->s);
+  c->allocs.push_back(q);
+  *p = (T*)q;
+  return CFQMC_OK;
+}
+
+template <typename T>
+int upload(cfqmc_ctx* c, T** p, const std::vector<T>& v) {
+  int r = dalloc(c, p, v.size());
+  if (r) return r;
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->s));
+  return CFQMC_OK;
+}
+
+// ---------------------------------------------------------------- launch helpers
+
+GemmArgs gemm0(int M, int N, int K) {
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.M = M; g.N = N; g.K = K;
+  g.nz2 = 1;
+  g.alpha = make_double2(1.0, 0.0);
+  g.beta = make_double2(0.0, 0.0);
+  g.mode = GEMM_NORMAL;
+  return g;
+}
+MatRef mref(const double2* p, int ld, long long s1, long long s2 = 0) {
+  MatRef m;
+  m.p = (double2*)p; m.ld = ld; m.s1 = s1; m.s2 = s2;
+  return m;
+}
+
+// Y = E X (left) or X E (right) for channel ch of the P/Q block at PQch (chain stride sPQ).
+void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, long long sPQ, const double2* X,
+          double2* Y, bool one_minus, const double2* add, int mixed, long long sY = -1) {
+  ChanArgs a;
+  memset(&a, 0, sizeof(a));
+  const int N = c->N;
+  a.N = N;
+  a.n_other = c->n;
+  a.M = X; a.ldM = c->n; a.sM = c->nn;
+  const double2* P = PQch;
+  const double2* Q = PQch + c->NN;
+  if (ch == 0) { a.X0 = a.X1 = inverse ? Q : P; }
+  else { a.X0 = inverse ? Q : P; a.X1 = inverse ? P : Q; }
+  a.ldX = N; a.sX = sPQ; a.opX = 0;
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) a.U[i][j] = c->Urot[ch][i][j];
+  a.one_minus = one_minus ? 1 : 0;
+  a.Cadd = add; a.ldC = c->n; a.sC = c->nn;
+  a.Y = Y; a.ldY = c->n; a.sY = sY < 0 ? c->nn : sY;
+  const int rot = (ch == 1 || ch == 2);
+  launch_chan_apply(a, left, rot, c->nch, mixed, c->cfg_chan, c->s);
+}
+
+// C = op(A) op(B) on n x n per chain (FP64)
+void gemm_nn(cfqmc_ctx* c, const double2* A, int opA, long long sA, const double2* B, int opB, long long sB,
+             double2* D, long long sD, int nbatch) {
+  GemmArgs g = gemm0(c->n, c->n, c->n);
+  g.opA = opA; g.opB = opB;
+  g.A = mref(A, c->n, sA); g.B = mref(B, c->n, sB); g.D = mref(D, c->n, sD);
+  launch_zgemm(g, nbatch, 0, c->cfg_gemm, c->s);
+}
+
+// Taylor exponentials of nent entries x 4 channels; h at hb [entry][4][N][N];
+// outputs P/Q at out + entry*sOut + ch*2N^2 (+N^2 for Q). alpha index = entry/alpha_div.
+void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int alpha_div, double2* out,
+          long long sOut) {
+  const int N = c->N;
+  const long long NN = c->NN, s4 = 4 * NN;
+  auto sq = [&](const double2* A, const double2* B, double2* D) {
+    GemmArgs g = gemm0(N, N, N);
+    g.A = mref(A, N, s4, NN); g.B = mref(B, N, s4, NN); g.D = mref(D, N, s4, NN);
+    g.nz2 = 4;
+    launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
+  };
+  sq(hb, hb, c->H2);
+  sq(c->H2, c->H2, c->X2);
+  sq(c->X2, c->H2, c->X3);
+  launch_exp_coef(c->X2, c->X3, N, alpha, alpha_div, c->coef, c->sq, c->smax, 0.4, c->d_err, nent * 4, c->s);
+  launch_exp_poly(c->H2, c->X2, c->X3, c->coef, N, c->loE, c->hiE, c->loO, c->hiO, nent * 4, c->s);
+  {
+    GemmArgs g = gemm0(N, N, N);
+    g.A = mref(c->X3, N, s4, NN); g.B = mref(c->hiE, N, s4, NN); g.C = mref(c->loE, N, s4, NN);
+    g.D = mref(c->Eo, N, s4, NN);
+    g.beta = make_double2(1.0, 0.0);
+    g.nz2 = 4;
+    launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
+    g.B = mref(c->hiO, N, s4, NN); g.C = mref(c->loO, N, s4, NN); g.D = mref(c->Oo, N, s4, NN);
+    launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
+  }
+  {
+    GemmArgs g = gemm0(N, N, N);
+    g.mode = GEMM_PQ;
+    g.A = mref(hb, N, s4, NN); g.B = mref(c->Oo, N, s4, NN); g.C = mref(c->Eo, N, s4, NN);
+    g.alpha_dev = (const double2*)(c->coef + 14);
+    g.ad_s1 = 4 * EXP_NC / 2; g.ad_s2 = EXP_NC / 2;
+    g.nz2 = 4;
+    double2* dst = c->smax > 0 ? c->Wa : out;
+    const long long sd = c->smax > 0 ? 8 * NN : sOut;
+    g.D = mref(dst, N, sd, 2 * NN);
+    g.D2 = mref(dst + NN, N, sd, 2 * NN);
+    launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
+  }
+  for (int j = 0; j < c->smax; ++j) {
+    double2* src = (j % 2 == 0) ? c->Wa : c->Wb;
+    double2* dst = (j == c->smax - 1) ? out : ((j % 2 == 0) ? c->Wb : c->Wa);
+    const long long sd = (j == c->smax - 1) ? sOut : 8 * NN;
+    GemmArgs g = gemm0(N, N, N);
+    g.mode = GEMM_SQUARE_OR_COPY;
+    g.A = mref(src, N, 8 * NN, NN); g.B = mref(src, N, 8 * NN, NN);
+    g.D = mref(dst, N, sd, NN);
+    g.nz2 = 8;
+    g.pred = c->sq; g.pred_s1 = 8; g.pred_s2 = 1; g.pred_thresh = j;
+    launch_zgemm(g, nent * 8, 0, c->cfg_small, c->s);
+  }
+}
+
+// UDT accumulation: (Uo, Do, To) <- decomposition of op(C) * (Ui Di Ti), all [chain] batched.
+void udt_acc(cfqmc_ctx* c, const double2* C, long long sC, int opC, const double2* Ui, const double* Di,
+             const double2* Ti, double2* Uo, double* Do, double2* To, long long sU, long long sD) {
+  const int n = c->n, B = c->nch;
+  const long long nn = c->nn;
+  gemm_nn(c, C, opC, sC, Ui, 0, sU, c->W1, nn, B);
+  launch_colscale(c->W1, n, nn, c->W1, n, nn, Di, sD, n, n, 0, B, c->s);
+  launch_colnorm_sort(c->W1, n, nn, c->nrm, c->perm, B, c->s);
+  launch_permute_normalize(c->W1, n, nn, c->nrm, c->perm, c->A1, B, c->s);
+  // Cholesky-QR, twice
+  gemm_nn(c, c->A1, 1, nn, c->A1, 0, nn, c->Gr, nn, B);
+  launch_lu(c->Gr, n, n, nn, c->ipiv, n, nullptr, 0, B, c->s);
+  launch_chol_from_lu(c->Gr, n, nn, c->R1, c->sqd1, B, c->s);
+  launch_rsolve(c->A1, n, nn, c->Q1, n, nn, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s);
+  launch_colscale(c->Q1, n, nn, c->Q1, n, nn, c->sqd1, n, n, n, 0, B, c->s);
+  gemm_nn(c, c->Q1, 1, nn, c->Q1, 0, nn, c->Gr, nn, B);
+  launch_lu(c->Gr, n, n, nn, c->ipiv, n, nullptr, 0, B, c->s);
+  launch_chol_from_lu(c->Gr, n, nn, c->R2, c->sqd2, B, c->s);
+  launch_rsolve(c->Q1, n, nn, Uo, n, sU, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s);
+  launch_colscale(Uo, n, sU, Uo, n, sU, c->sqd2, n, n, n, 0, B, c->s);
+  gemm_nn(c, c->R2, 0, nn, c->R1, 0, nn, c->Rt, nn, B);
+  launch_udt_finish(c->Rt, n, nn, c->nrm, c->perm, Do, sD, c->Tp, B, c->s);
+  gemm_nn(c, c->Tp, 0, nn, Ti, 0, sU, To, sU, B);
+}
+
+// G = (1 + U_L D_L T_L T_R^dagger D_R U_R^dagger)^{-1} into Gout (all chains).
+void green_udt(cfqmc_ctx* c, int bl, int br, double2* Gout) {
+  const int n = c->n, B = c->nch;
+  const long long nn = c->nn, sU = (long long)(c->nblk_stab + 1) * nn, sD = (long long)(c->nblk_stab + 1) * n;
+  const double2 *UL = c->Ls.U + bl * nn, *TL = c->Ls.T + bl * nn, *UR = c->Rs.U + br * nn, *TR = c->Rs.T + br * nn;
+  const double *DL = c->Ls.D + bl * n, *DR = c->Rs.D + br * n;
+  gemm_nn(c, UL, 1, sU, UR, 0, sU, c->K1, nn, B);
+  gemm_nn(c, TL, 0, sU, TR, 1, sU, c->M1, nn, B);
+  launch_loh_combine(c->K1, c->M1, DL, sD, DR, sD, c->Yl, n, B, c->s);
+  launch_lu(c->Yl, n, n, nn, c->ipiv, n, c->ldtmp, 1, B, c->s);
+  launch_dmax_inv(DR, sD, c->dinvR, n, B, c->s);
+  launch_dmax_inv(DL, sD, c->dinvL, n, B, c->s);
+  launch_colscale(UR, n, sU, c->Wm, n, nn, c->dinvR, n, n, n, 0, B, c->s);
+  launch_rsolve(c->Wm, n, nn, c->X1, n, nn, c->Yl, n, nn, c->ipiv, n, n, 0, B, c->s);
+  launch_colscale(c->X1, n, nn, c->X1, n, nn, c->dinvL, n, n, n, 0, B, c->s);
+  gemm_nn(c, c->X1, 0, nn, UL, 1, sU, Gout, nn, B);
+}
+
+// C_b = B_{tau_{b+1}} ... B_{tau_b + 1} of block b (FP64), all chains.
+void block_product(cfqmc_ctx* c, int b) {
+  const long long nn = c->nn, sPQ = (long long)c->L * 8 * c->NN;
+  const int t0 = b * c->nstab, t1 = std::min(c->L, t0 + c->nstab);
+  double2* cur = c->S1;
+  double2* nxt = c->S2;
+  launch_set_identity(cur, c->n, c->n, nn, c->nch, c->s);
+  for (int t = t0; t < t1; ++t)
+    for (int ch = 3; ch >= 0; --ch) {
+      const double2* pq = c->PQ + (long long)t * 8 * c->NN + ch * 2 * c->NN;
+      const bool last = (t == t1 - 1 && ch == 0);
+      double2* dst = last ? c->Cb + (long long)b * nn : nxt;
+      chan(c, 1, ch, false, pq, sPQ, cur, dst, false, nullptr, 0, last ? (long long)c->nblk_stab * nn : -1);
+      if (!last) std::swap(cur, nxt);
+    }
+}
+
+long long sU_(cfqmc_ctx* c) { return (long long)(c->nblk_stab + 1) * c->nn; }
+long long sD_(cfqmc_ctx* c) { return (long long)(c->nblk_stab + 1) * c->n; }
+
+void set_udt_identity(cfqmc_ctx* c, Udt& u, int b) {
+  const long long sU = sU_(c), sD = sD_(c);
+  launch_set_identity(u.U + b * c->nn, c->n, c->n, sU, c->nch, c->s);
+  launch_set_identity(u.T + b * c->nn, c->n, c->n, sU, c->nch, c->s);
+  std::vector<double> ones(c->n, 1.0);
+  for (int z = 0; z < c->nch; ++z)
+    hipMemcpyAsync(u.D + z * sD + b * c->n, ones.data(), c->n * sizeof(double), hipMemcpyHostToDevice, c->s);
+  hipStreamSynchronize(c->s);
+}
+
+void restack_right(cfqmc_ctx* c) {
+  const long long sU = sU_(c), sD = sD_(c), nn = c->nn;
+  const long long sC = (long long)c->nblk_stab * nn;
+  for (int b = c->nblk_stab - 1; b >= 0; --b)
+    udt_acc(c, c->Cb + b * nn, sC, 1, c->Rs.U + (b + 1) * nn, c->Rs.D + (b + 1) * c->n, c->Rs.T + (b + 1) * nn,
+            c->Rs.U + b * nn, c->Rs.D + b * c->n, c->Rs.T + b * nn, sU, sD);
+}
+
+void left_acc(cfqmc_ctx* c, int b) {
+  const long long sU = sU_(c), sD = sD_(c), nn = c->nn;
+  const long long sC = (long long)c->nblk_stab * nn;
+  udt_acc(c, c->Cb + b * nn, sC, 0, c->Ls.U + b * nn, c->Ls.D + b * c->n, c->Ls.T + b * nn, c->Ls.U + (b + 1) * nn,
+          c->Ls.D + (b + 1) * c->n, c->Ls.T + (b + 1) * nn, sU, sD);
+}
+
+int build_model_dev(cfqmc_ctx* c) {
+  HostTables& T = c->ht;
+  ModelDev& m = c->md;
+  m.N = c->N; m.n = c->n; m.nq = c->nq; m.L = c->L;
+  int r = 0;
+  int *p_hoff, *p_cre, *p_cim, *p_qx, *p_qy, *p_dag, *p_toff, *p_tqy, *p_tqx, *p_tk, *p_tc;
+  double *p_sgn, *p_sc, *p_F, *p_tF, *p_beta;
+  double2* p_ph;
+  r |= upload(c, &p_hoff, T.hoff); r |= upload(c, &p_cre, T.h_cre); r |= upload(c, &p_cim, T.h_cim);
+  r |= upload(c, &p_qx, T.h_qx); r |= upload(c, &p_qy, T.h_qy); r |= upload(c, &p_dag, T.h_dag);
+  r |= upload(c, &p_sgn, T.h_sgn); r |= upload(c, &p_sc, T.h_scale); r |= upload(c, &p_F, T.h_F);
+  r |= upload(c, &p_toff, T.toff); r |= upload(c, &p_tqy, T.t_qy); r |= upload(c, &p_tqx, T.t_qx);
+  r |= upload(c, &p_tk, T.t_kind); r |= upload(c, &p_tc, T.t_comp); r |= upload(c, &p_tF, T.t_F);
+  r |= upload(c, &p_beta, T.beta); r |= upload(c, &p_ph, T.phase);
+  if (r) return CFQMC_ENOMEM;
+  m.hoff = p_hoff; m.h_cre = p_cre; m.h_cim = p_cim; m.h_qx = p_qx; m.h_qy = p_qy; m.h_dag = p_dag;
+  m.h_sgn = p_sgn; m.h_scale = p_sc; m.h_F = p_F;
+  m.nrow = (int)T.t_qy.size();
+  m.toff = p_toff; m.t_qy = p_tqy; m.t_qx = p_tqx; m.t_kind = p_tk; m.t_comp = p_tc; m.t_F = p_tF;
+  m.beta = p_beta; m.phase = p_ph;
+  return CFQMC_OK;
+}
+
+int check_finite_host(cfqmc_ctx* c, const double* dptr, long long count) {
+  std::vector<double> h(count);
+  HIPCHK(hipMemcpy(h.data(), dptr, count * sizeof(double), hipMemcpyDeviceToHost));
+  for (double v : h)
+    if (!std::isfinite(v)) return CFQMC_ENUMERIC;
+  return CFQMC_OK;
+}
+
+// One slice move of all chains; t is the 0-based slice.
+void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
+  const int N = c->N, mixed = c->mixed;
+  const long long nn = c->nn, NN = c->NN;
+  const long long sPQ = (long long)c->L * 8 * NN, sPQp = 8 * NN;
+  const double2* pq = c->PQ + (long long)t * 8 * NN;   // chain 0 of slice t
+  // 1. wrap through the channels of slice t, keeping the frames
+  const double2* cur = c->G;
+  for (int ch = 3; ch >= 0; --ch) {
+    chan(c, 1, ch, false, pq + ch * 2 * NN, sPQ, cur, c->S1, false, nullptr, mixed);
+    chan(c, 0, ch, true, pq + ch * 2 * NN, sPQ, c->S1, c->F[ch], false, nullptr, mixed);
+    cur = c->F[ch];
+  }
+  // 2. drift and proposal
+  StepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.N = N; a.n = c->n; a.nq = c->nq; a.L = c->L; a.tau = t;
+  for (int i = 0; i < 4; ++i) a.G[i] = c->F[i];
+  a.sG = nn;
+  a.phi = c->phi + (long long)t * 4 * c->nq;
+  a.sphi = (long long)c->L * 4 * c->nq;
+  a.phip = c->phip; a.sphip = 4 * c->nq;
+  a.alpha = c->alpha; a.eps = c->eps;
+  a.noise = noise_dev ? noise_dev + (long long)t * (4 * c->nq + 1) : nullptr;
+  a.snoise = (long long)c->L * (4 * c->nq + 1);
+  a.seed = c->p.seed;
+  a.counter = c->sweep_counter * c->L + t;
+  a.part = c->part; a.nblk = 4 * c->md.nrow; a.done = c->done;
+  a.lndetM = c->lndet; a.lnA = c->lnA; a.accept = c->accept; a.stat = c->stat;
+  launch_drift_propose(c->md, a, c->nch, c->s);
+  // 3. exponentials of the proposed fields
+  launch_build_h(c->md, c->phip, 4 * c->nq, c->h, 4 * NN, c->nch, c->s);
+  exps(c, c->h, c->nch, c->alpha, 1, c->PQp, sPQp);
+  // 4. M = G_0 + B' B^{-1} (1 - G_0)
+  double2* y = c->S1;
+  double2* y2 = c->S2;
+  chan(c, 1, 0, true, pq + 0 * 2 * NN, sPQ, c->F[0], y, true, nullptr, mixed);
+  for (int ch = 1; ch <= 3; ++ch) {
+    chan(c, 1, ch, true, pq + ch * 2 * NN, sPQ, y, y2, false, nullptr, mixed);
+    std::swap(y, y2);
+  }
+  for (int ch = 3; ch >= 1; --ch) {
+    chan(c, 1, ch, false, c->PQp + ch * 2 * NN, sPQp, y, y2, false, nullptr, mixed);
+    std::swap(y, y2);
+  }
+  chan(c, 1, 0, false, c->PQp, sPQp, y, c->Mw, false, c->F[0], mixed);
+  // 5. LU of M: ln det M
+  launch_lu(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, 1, c->nch, c->s);
+  // 6. G' = G_0 M^{-1}
+  launch_rsolve(c->F[0], c->n, nn, c->Fp[0], c->n, nn, c->Mw, c->n, nn, c->ipiv, c->n, c->n, 0, c->nch, c->s);
+  // 7. frames of G' for the drift at phi'
+  for (int ch = 0; ch < 3; ++ch) {
+    chan(c, 1, ch, true, c->PQp + ch * 2 * NN, sPQp, c->Fp[ch], c->S1, false, nullptr, mixed);
+    chan(c, 0, ch, false, c->PQp + ch * 2 * NN, sPQp, c->S1, c->Fp[ch + 1], false, nullptr, mixed);
+  }
+  for (int i = 0; i < 4; ++i) a.G[i] = c->Fp[i];
+  launch_drift_mh(c->md, a, c->nch, c->s);
+  // 8. commit
+  launch_commit(c->accept, c->nch, c->Fp[0], c->F[0], c->G, nn, nn, c->phip, 4 * c->nq,
+                c->phi + (long long)t * 4 * c->nq, (long long)c->L * 4 * c->nq, 4 * c->nq, c->PQp, sPQp,
+                c->PQ + (long long)t * 8 * NN, sPQ, 8 * NN, c->acc_count, c->s);
+  // history of this slice
+  hipMemcpy2DAsync(c->hist_acc + t, c->L * sizeof(int), c->accept, sizeof(int), sizeof(int), c->nch,
+                   hipMemcpyDeviceToDevice, c->s);
+  hipMemcpy2DAsync(c->hist_lnA + t, c->L * sizeof(double), c->lnA, sizeof(double), sizeof(double), c->nch,
+                   hipMemcpyDeviceToDevice, c->s);
+}
+
+// FP64 recomputation of G at the end of block b (left stack advanced first).
+void block_end(cfqmc_ctx* c, int b) {
+  block_product(c, b);
+  left_acc(c, b);
+  green_udt(c, b + 1, b + 1, c->Gs);
+  launch_maxdiff(c->G, c->Gs, c->n, c->nn, c->stab_err, c->nch, c->s);
+  launch_copy(c->Gs, c->G, c->nn, c->nn, c->nn, c->nch, c->s);
+}
+
+int build_all_exps(cfqmc_ctx* c) {
+  // per chain, in chunks of slices
+  const long long NN = c->NN;
+  const int chunk = c->exp_cap;
+  for (int z = 0; z < c->nch; ++z)
+    for (int t0 = 0; t0 < c->L; t0 += chunk) {
+      const int cnt = std::min(chunk, c->L - t0);
+      const double* ph = c->phi + (long long)z * c->L * 4 * c->nq + (long long)t0 * 4 * c->nq;
+      launch_build_h(c->md, ph, 4 * c->nq, c->h, 4 * NN, cnt, c->s);
+      exps(c, c->h, cnt, c->alpha + z * 4, 1 << 30, c->PQ + (long long)z * c->L * 8 * NN + (long long)t0 * 8 * NN,
+           8 * NN);
+    }
+  return CFQMC_OK;
+}
+
+int autotune(cfqmc_ctx* c) {
+  // time the channel application and the n x n GEMM for each tile configuration
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best_c = 1e30f, best_g = 1e30f;
+  int bc = 1, bg = 1;
+  for (int cfg = 0; cfg < 4; ++cfg) {
+    c->cfg_chan = cfg;
+    c->cfg_gemm = cfg;
+    for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+      hipEventRecord(e0, c->s);
+      for (int k = 0; k < 8; ++k) chan(c, k & 1, 1 + (k & 1), false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
+      hipEventRecord(e1, c->s);
+      hipEventSynchronize(e1);
+      float ms;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep == 1 && ms < best_c) { best_c = ms; bc = cfg; }
+      hipEventRecord(e0, c->s);
+      for (int k = 0; k < 8; ++k) gemm_nn(c, c->F[0], 0, c->nn, c->F[1], 0, c->nn, c->S1, c->nn, c->nch);
+      hipEventRecord(e1, c->s);
+      hipEventSynchronize(e1);
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep == 1 && ms < best_g) { best_g = ms; bg = cfg; }
+    }
+  }
+  c->cfg_chan = bc;
+  c->cfg_gemm = bg;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return CFQMC_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+void cfqmc_default_params(cfqmc_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->n_phi = 6; p->l_tau = 40; p->dtau = 0.1;
+  p->u0 = 1.0; p->uk = 1.0; p->un = 1.0;
+  p->q_mode = CFQMC_Q_PAPER; p->q_max = 3.0;
+  p->n_stab = 10; p->precision = CFQMC_FP64;
+  p->eps0 = 0.5; p->r0 = 0.574; p->deps = 0.1; p->eps_min = 1e-3; p->eps_max = 5.0;
+  p->adapt_eps = 1; p->seed = 1; p->n_chains = 1;
+  p->exp_squarings = 2; p->tile_cfg = -1;
+}
+
+int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
+  if (!pin || !out) return CFQMC_EINVAL;
+  *out = nullptr;
+  const cfqmc_params& p = *pin;
+  if (p.n_phi < 1 || p.n_phi > 140 || p.l_tau < 1 || !(p.dtau > 0) || p.n_chains < 1 || p.n_stab < 1 ||
+      !(p.eps0 > 0) || p.eps_min <= 0 || p.eps_max < p.eps_min || p.exp_squarings < 0 || p.exp_squarings > 8 ||
+      (p.precision != CFQMC_FP64 && p.precision != CFQMC_MIXED) || p.tile_cfg < -1 || p.tile_cfg > 3)
+    return CFQMC_EINVAL;
+  cfqmc_ctx* c = new cfqmc_ctx();
+  c->p = p;
+  c->p.q_list = nullptr;
+  c->p.chain_u = nullptr;
+  c->s = (hipStream_t)hip_stream;
+  c->N = p.n_phi; c->n = 2 * p.n_phi; c->L = p.l_tau; c->nch = p.n_chains; c->nstab = p.n_stab;
+  c->nblk_stab = (p.l_tau + p.n_stab - 1) / p.n_stab;
+  c->mixed = p.precision == CFQMC_MIXED;
+  c->smax = p.exp_squarings;
+  c->nn = (long long)c->n * c->n;
+  c->NN = (long long)c->N * c->N;
+  c->ready = false;
+  c->sweep_counter = 0;
+  if (!build_components(p, c->ht, c->err)) { delete c; return CFQMC_EINVAL; }
+  c->nq = (int)c->ht.comp_kind.size();
+  // valley rotations: columns are the +1 / -1 eigenvectors of o_i
+  const double r = 1.0 / std::sqrt(2.0);
+  for (int ch = 0; ch < 4; ++ch) {
+    for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) c->Urot[ch][i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  c->Urot[1][0][0] = make_double2(r, 0); c->Urot[1][0][1] = make_double2(r, 0);
+  c->Urot[1][1][0] = make_double2(r, 0); c->Urot[1][1][1] = make_double2(-r, 0);
+  c->Urot[2][0][0] = make_double2(r, 0); c->Urot[2][0][1] = make_double2(r, 0);
+  c->Urot[2][1][0] = make_double2(0, r); c->Urot[2][1][1] = make_double2(0, -r);
+
+  const int B = c->nch, n = c->n, nq = c->nq, L = c->L, nb = c->nblk_stab;
+  const long long nn = c->nn, NN = c->NN;
+  c->exp_cap = std::max(1, std::min(L, 32));
+  const long long ecap = (long long)std::max(B, c->exp_cap) * 4 * NN;
+  int rc = 0;
+  rc |= dalloc(c, &c->phi, (size_t)B * L * 4 * nq);
+  rc |= dalloc(c, &c->PQ, (size_t)B * L * 8 * NN);
+  rc |= dalloc(c, &c->G, (size_t)B * nn);
+  for (int i = 0; i < 4; ++i) { rc |= dalloc(c, &c->F[i], (size_t)B * nn); rc |= dalloc(c, &c->Fp[i], (size_t)B * nn); }
+  rc |= dalloc(c, &c->S1, (size_t)B * nn);
+  rc |= dalloc(c, &c->S2, (size_t)B * nn);
+  rc |= dalloc(c, &c->Mw, (size_t)B * nn);
+  rc |= dalloc(c, &c->ipiv, (size_t)B * n);
+  rc |= dalloc(c, &c->lndet, (size_t)B);
+  rc |= dalloc(c, &c->ldtmp, (size_t)B);
+  rc |= dalloc(c, &c->phip, (size_t)B * 4 * nq);
+  rc |= dalloc(c, &c->PQp, (size_t)B * 8 * NN);
+  rc |= dalloc(c, &c->h, (size_t)ecap);
+  double2** ebufs[] = {&c->H2, &c->X2, &c->X3, &c->loE, &c->hiE, &c->loO, &c->hiO, &c->Eo, &c->Oo};
+  for (auto bp : ebufs) rc |= dalloc(c, bp, (size_t)ecap);
+  rc |= dalloc(c, &c->Wa, (size_t)2 * ecap);
+  rc |= dalloc(c, &c->Wb, (size_t)2 * ecap);
+  rc |= dalloc(c, &c->coef, (size_t)(ecap / NN) * EXP_NC);
+  rc |= dalloc(c, &c->sq, (size_t)(ecap / NN) * 2);
+  rc |= dalloc(c, &c->d_err, 1);
+  rc |= dalloc(c, &c->Cb, (size_t)B * nb * nn);
+  rc |= dalloc(c, &c->Ls.U, (size_t)B * (nb + 1) * nn);
+  rc |= dalloc(c, &c->Ls.T, (size_t)B * (nb + 1) * nn);
+  rc |= dalloc(c, &c->Ls.D, (size_t)B * (nb + 1) * n);
+  rc |= dalloc(c, &c->Rs.U, (size_t)B * (nb + 1) * nn);
+  rc |= dalloc(c, &c->Rs.T, (size_t)B * (nb + 1) * nn);
+  rc |= dalloc(c, &c->Rs.D, (size_t)B * (nb + 1) * n);
+  double2** sbufs[] = {&c->W1, &c->A1, &c->Gr, &c->Q1, &c->Q2, &c->R1, &c->R2, &c->Rt, &c->Tp, &c->K1, &c->M1, &c->Yl, &c->Wm, &c->X1, &c->Gs};
+  for (auto bp : sbufs) rc |= dalloc(c, bp, (size_t)B * nn);
+  double** dbufs[] = {&c->nrm, &c->sqd1, &c->sqd2, &c->dinvL, &c->dinvR, &c->tmpd};
+  for (auto bp : dbufs) rc |= dalloc(c, bp, (size_t)B * n);
+  rc |= dalloc(c, &c->perm, (size_t)B * n);
+  rc |= dalloc(c, &c->alpha, (size_t)B * 4);
+  rc |= dalloc(c, &c->eps, (size_t)B);
+  rc |= dalloc(c, &c->acc_count, (size_t)B);
+  rc |= dalloc(c, &c->lnA, (size_t)B);
+  rc |= dalloc(c, &c->accept, (size_t)B);
+  rc |= dalloc(c, &c->stat, (size_t)B * 8);
+  rc |= dalloc(c, &c->done, (size_t)B);
+  rc |= dalloc(c, &c->part, (size_t)B * 4 * 4 * 1024);
+  rc |= dalloc(c, &c->obs, (size_t)B * 8);
+  rc |= dalloc(c, &c->stab_err, (size_t)B);
+  c->series_cap = 1 << 16;
+  rc |= dalloc(c, &c->series, (size_t)B * c->series_cap);
+  rc |= dalloc(c, &c->hist_acc, (size_t)B * L);
+  rc |= dalloc(c, &c->hist_lnA, (size_t)B * L);
+  rc |= dalloc(c, &c->noise, (size_t)B * L * (4 * nq + 1));
+  rc |= dalloc(c, &c->bg, (size_t)B);
+  if (rc) { cfqmc_destroy(c); return CFQMC_ENOMEM; }
+  if (build_model_dev(c)) { cfqmc_destroy(c); return CFQMC_ENOMEM; }
+  if (c->md.nrow * 4 > 4 * 1024) { c->err = "too many momentum rows"; cfqmc_destroy(c); return CFQMC_EINVAL; }
+  // couplings per chain: g = (U0+UN, -(UK+UN), -(UK+UN), 2 UN), alpha = sqrt(-dtau g)
+  std::vector<double2> al(B * 4);
+  for (int z = 0; z < B; ++z) {
+    double u0 = p.u0, uk = p.uk, un = p.un;
+    if (pin->chain_u) { u0 = pin->chain_u[3 * z]; uk = pin->chain_u[3 * z + 1]; un = pin->chain_u[3 * z + 2]; }
+    const double g[4] = {u0 + un, -(uk + un), -(uk + un), 2.0 * un};
+    for (int i = 0; i < 4; ++i) {
+      const double x = -p.dtau * g[i];
+      al[z * 4 + i] = x >= 0 ? make_double2(std::sqrt(x), 0.0) : make_double2(0.0, std::sqrt(-x));
+    }
+  }
+  if (hipMemcpyAsync(c->alpha, al.data(), al.size() * sizeof(double2), hipMemcpyHostToDevice, c->s) != hipSuccess) {
+    cfqmc_destroy(c);
+    return CFQMC_EHIP;
+  }
+  c->cfg_chan = c->cfg_gemm = (p.tile_cfg >= 0 ? p.tile_cfg : 1);
+  c->cfg_small = 0;
+  if (hipStreamSynchronize(c->s) != hipSuccess) { cfqmc_destroy(c); return CFQMC_EHIP; }
+  if (p.tile_cfg < 0) autotune(c);
+  *out = c;
+  return CFQMC_OK;
+}
+
+int cfqmc_destroy(cfqmc_ctx* c) {
+  if (!c) return CFQMC_EINVAL;
+  hipStreamSynchronize(c->s);
+  for (void* q : c->allocs) hipFree(q);
+  delete c;
+  return CFQMC_OK;
+}
+
+int cfqmc_sizes(const cfqmc_ctx* c, int32_t* n_q, int32_t* n_chains, int32_t* dim_g4n) {
+  if (!c) return CFQMC_EINVAL;
+  if (n_q) *n_q = c->nq;
+  if (n_chains) *n_chains = c->nch;
+  if (dim_g4n) *dim_g4n = 4 * c->N;
+  return CFQMC_OK;
+}
+
+int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
+  if (!c) return CFQMC_EINVAL;
+  const int B = c->nch, L = c->L, nq = c->nq;
+  const long long cnt = (long long)B * L * 4 * nq;
+  std::vector<double> h(cnt);
+  if (phi) {
+    memcpy(h.data(), phi, cnt * sizeof(double));
+    for (double v : h)
+      if (!std::isfinite(v)) { c->err = "non-finite field"; return CFQMC_EINVAL; }
+  } else {
+    // N(0,1) by Box-Muller on a host Philox-independent splitmix stream of the seed
+    uint64_t st = c->p.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    auto next = [&]() {
+      st += 0x9E3779B97F4A7C15ull;
+      uint64_t z = st;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      return z ^ (z >> 31);
+    };
+    for (long long i = 0; i < cnt; i += 2) {
+      const double u1 = ((next() >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+      const double u2 = (next() >> 11) * (1.0 / 9007199254740992.0);
+      const double rr = std::sqrt(-2.0 * std::log(u1));
+      h[i] = rr * std::cos(2.0 * M_PI * u2);
+      if (i + 1 < cnt) h[i + 1] = rr * std::sin(2.0 * M_PI * u2);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->phi, h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemsetAsync(c->d_err, 0, sizeof(int), c->s));
+  HIPCHK(hipGetLastError());
+  build_all_exps(c);
+  for (int b = 0; b < c->nblk_stab; ++b) block_product(c, b);
+  HIPCHK(hipStreamSynchronize(c->s));
+  set_udt_identity(c, c->Rs, c->nblk_stab);
+  set_udt_identity(c, c->Ls, 0);
+  restack_right(c);
+  for (int b = 0; b < c->nblk_stab; ++b) left_acc(c, b);
+  green_udt(c, 0, 0, c->G);
+  std::vector<double> e(B, c->p.eps0);
+  HIPCHK(hipMemcpyAsync(c->eps, e.data(), B * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemsetAsync(c->acc_count, 0, B * sizeof(int), c->s));
+  HIPCHK(hipMemsetAsync(c->stat, 0, B * 8 * sizeof(double), c->s));
+  HIPCHK(hipMemsetAsync(c->stab_err, 0, B * sizeof(double), c->s));
+  HIPCHK(hipMemsetAsync(c->done, 0, B * sizeof(unsigned), c->s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->s));
+  int ef = 0;
+  HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  c->series_len = 0;
+  c->sweep_counter = 0;
+  if (ef) { c->err = "exponential range exceeded at init"; c->ready = false; return CFQMC_ENUMERIC; }
+  std::vector<double2> g(c->nn);
+  HIPCHK(hipMemcpy(g.data(), c->G, c->nn * sizeof(double2), hipMemcpyDeviceToHost));
+  for (auto& v : g)
+    if (!std::isfinite(v.x) || !std::isfinite(v.y)) { c->err = "non-finite G at init"; c->ready = false; return CFQMC_ENUMERIC; }
+  c->ready = true;
+  return CFQMC_OK;
+}
+
+int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out) {
+  if (!c || !phi_out) return CFQMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(phi_out, c->phi, (size_t)c->nch * c->L * 4 * c->nq * sizeof(double), hipMemcpyDeviceToHost));
+  return CFQMC_OK;
+}
+
+int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stats* stats) {
+  if (!c || n_sweeps < 0) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  const int B = c->nch, L = c->L, W = 4 * c->nq + 1;
+  HIPCHK(hipMemsetAsync(c->stat, 0, B * 8 * sizeof(double), c->s));
+  HIPCHK(hipMemsetAsync(c->stab_err, 0, B * sizeof(double), c->s));
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    if (replay) {
+      HIPCHK(hipMemcpy2DAsync(c->noise, (size_t)L * W * sizeof(double), replay + (size_t)sw * L * W,
+                              (size_t)n_sweeps * L * W * sizeof(double), (size_t)L * W * sizeof(double), B,
+                              hipMemcpyHostToDevice, c->s));
+    }
+    for (int t = 0; t < L; ++t) {
+      slice_step(c, t, replay ? c->noise : nullptr);
+      if ((t + 1) % c->nstab == 0 || t == L - 1) block_end(c, t / c->nstab);
+    }
+    launch_eps_update(c->eps, c->acc_count, L, c->p.r0, c->p.deps, c->p.eps_min, c->p.eps_max, c->p.adapt_eps, B,
+                      c->s);
+    launch_observables(c->G, c->nn, c->N, std::exp(0.0) / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, B, c->s);
+    if (c->series_len < c->series_cap) {
+      HIPCHK(hipMemcpy2DAsync(c->series + c->series_len, c->series_cap * sizeof(double), c->obs + 5,
+                              8 * sizeof(double), sizeof(double), B, hipMemcpyDeviceToDevice, c->s));
+      c->series_len++;
+    }
+    restack_right(c);
+    c->sweep_counter++;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->s));
+  int ef = 0;
+  HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<double> st(B * 8), se(B), ep(B);
+  HIPCHK(hipMemcpy(st.data(), c->stat, B * 8 * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(se.data(), c->stab_err, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ep.data(), c->eps, B * sizeof(double), hipMemcpyDeviceToHost));
+  bool bad = ef != 0;
+  for (int z = 0; z < B; ++z) {
+    if (!std::isfinite(se[z]) || !std::isfinite(ep[z])) bad = true;
+    if (stats) {
+      stats[z].proposed = (int64_t)st[z * 8 + 1];
+      stats[z].accepted = (int64_t)st[z * 8 + 2];
+      stats[z].eps = ep[z];
+      stats[z].max_stab_err = se[z];
+      stats[z].max_phase_err = st[z * 8 + 0];
+      stats[z].exp_range_flag = ef;
+      stats[z].pad = 0;
+    }
+  }
+  if (bad) {
+    c->ready = false;
+    c->err = ef ? "exponential range exceeded" : "non-finite state";
+    return CFQMC_ENUMERIC;
+  }
+  return CFQMC_OK;
+}
+
+int cfqmc_measure_G(cfqmc_ctx* c, int32_t chain, int32_t tau, void* g_out, int32_t on_device) {
+  if (!c || !g_out || chain < 0 || chain >= c->nch || tau < 0 || tau > c->L) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  const long long nn = c->nn, NN = c->NN, sPQ = (long long)c->L * 8 * NN;
+  const double2* src;
+  if (tau == 0 || tau == c->L) {
+    src = c->G;
+  } else {
+    const int b = tau / c->nstab;
+    green_udt(c, b, b, c->Gs);
+    const double2* cur = c->Gs;
+    for (int t = b * c->nstab; t < tau; ++t)
+      for (int ch = 3; ch >= 0; --ch) {
+        const double2* pq = c->PQ + (long long)t * 8 * NN + ch * 2 * NN;
+        chan(c, 1, ch, false, pq, sPQ, cur, c->S1, false, nullptr, 0);
+        chan(c, 0, ch, true, pq, sPQ, c->S1, c->S2, false, nullptr, 0);
+        launch_copy(c->S2, c->Gs, nn, nn, nn, c->nch, c->s);
+        cur = c->Gs;
+      }
+    src = c->Gs;
+  }
+  if (on_device) {
+    launch_expand4n(src + chain * nn, c->n, (double2*)g_out, c->s);
+    HIPCHK(hipStreamSynchronize(c->s));
+    return CFQMC_OK;
+  }
+  std::vector<double2> tmp(nn);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(tmp.data(), src + chain * nn, nn * sizeof(double2), hipMemcpyDeviceToHost));
+  double2* o = (double2*)g_out;
+  const int n = c->n;
+  for (int i = 0; i < 2 * n; ++i)
+    for (int j = 0; j < 2 * n; ++j)
+      o[(long long)i * 2 * n + j] = (i / n == j / n) ? tmp[(long long)(i % n) * n + (j % n)] : make_double2(0.0, 0.0);
+  return CFQMC_OK;
+}
+
+int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im) {
+  if (!c || chain < 0 || chain >= c->nch) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  // ln det(1 + B(beta,0)) from the right stack at tau = 0 (left factor = 1):
+  // 1 + T_R^+ D_R U_R^+ = Y D_R^max U_R^+ with Y = U_R D_R^max^-1 + T_R^+ D_R^min
+  const int n = c->n, B = c->nch;
+  const long long nn = c->nn, sU = sU_(c), sD = sD_(c);
+  green_udt(c, 0, 0, c->Gs);   // leaves LU(Y) in Yl and ln det Y in ldtmp
+  std::vector<double2> ldY(B);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(ldY.data(), c->ldtmp, B * sizeof(double2), hipMemcpyDeviceToHost));
+  // ln det U_R (unitary: phase only, modulus 1)
+  launch_copy(c->Rs.U, c->Q2, nn, sU, nn, B, c->s);
+  launch_lu(c->Q2, n, n, nn, c->ipiv, n, c->ldtmp, 1, B, c->s);
+  launch_sum_log_dmax(c->Rs.D, sD, n, c->tmpd, B, c->s);
+  launch_background(c->md, c->phi, (long long)c->L * 4 * c->nq, c->alpha, c->bg, B, c->s);
+  std::vector<double2> ldU(B), bg(B);
+  std::vector<double> sdm(B);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(ldU.data(), c->ldtmp, B * sizeof(double2), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(sdm.data(), c->tmpd, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bg.data(), c->bg, B * sizeof(double2), hipMemcpyDeviceToHost));
+  const int z = chain;
+  // ln det(1+B) = ln det Y + sum ln D_R^max + ln det U_R^dagger
+  const double lr = ldY[z].x + sdm[z] - ldU[z].x;
+  const double li = ldY[z].y - ldU[z].y;
+  double r_ = 2.0 * lr + bg[z].x, i_ = 2.0 * li + bg[z].y;
+  i_ = std::fmod(i_, 2.0 * M_PI);
+  if (i_ > M_PI) i_ -= 2.0 * M_PI;
+  if (i_ <= -M_PI) i_ += 2.0 * M_PI;
+  if (!std::isfinite(r_)) return CFQMC_ENUMERIC;
+  if (re) *re = r_;
+  if (im) *im = i_;
+  return CFQMC_OK;
+}
+
+int cfqmc_observables(cfqmc_ctx* c, int32_t chain, double* s_q0, double* m2) {
+  if (!c || chain < 0 || chain >= c->nch) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  launch_observables(c->G, c->nn, c->N, 1.0 / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, c->nch, c->s);
+  std::vector<double> o(8);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(o.data(), c->obs + chain * 8, 8 * sizeof(double), hipMemcpyDeviceToHost));
+  if (s_q0) for (int i = 0; i < 5; ++i) s_q0[i] = o[i];
+  if (m2) *m2 = o[5];
+  return CFQMC_OK;
+}
+
+int cfqmc_series(cfqmc_ctx* c, int32_t chain, double* out, int32_t max_len, int32_t* len) {
+  if (!c || chain < 0 || chain >= c->nch || !out || max_len < 0) return CFQMC_EINVAL;
+  const int k = std::min(max_len, c->series_len);
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (k > 0) HIPCHK(hipMemcpy(out, c->series + (long long)chain * c->series_cap, k * sizeof(double), hipMemcpyDeviceToHost));
+  if (len) *len = k;
+  return CFQMC_OK;
+}
+
+int cfqmc_last_sweep(cfqmc_ctx* c, int32_t chain, int32_t* accepted, double* ln_a) {
+  if (!c || chain < 0 || chain >= c->nch) return CFQMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (accepted) HIPCHK(hipMemcpy(accepted, c->hist_acc + (long long)chain * c->L, c->L * sizeof(int), hipMemcpyDeviceToHost));
+  if (ln_a) HIPCHK(hipMemcpy(ln_a, c->hist_lnA + (long long)chain * c->L, c->L * sizeof(double), hipMemcpyDeviceToHost));
+  return CFQMC_OK;
+}
+
+int cfqmc_get_eps(cfqmc_ctx* c, double* eps) {
+  if (!c || !eps) return CFQMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(eps, c->eps, c->nch * sizeof(double), hipMemcpyDeviceToHost));
+  return CFQMC_OK;
+}
+
+int cfqmc_set_eps(cfqmc_ctx* c, const double* eps) {
+  if (!c || !eps) return CFQMC_EINVAL;
+  for (int z = 0; z < c->nch; ++z)
+    if (!(eps[z] > 0)) return CFQMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(c->eps, eps, c->nch * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return CFQMC_OK;
+}
+
+int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg) {
+  if (!c) return CFQMC_EINVAL;
+  if (chan_cfg) *chan_cfg = c->cfg_chan;
+  if (gemm_cfg) *gemm_cfg = c->cfg_gemm;
+  return CFQMC_OK;
+}
+
+const char* cfqmc_last_error(const cfqmc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,366 @@
+// Complex GEMM and channel-exponential application on MFMA (gfx950).
+//
+// zgemm:      D = alpha * op(A) op(B) + beta * C, batched, with two extra
+//             epilogues used by the Taylor exponential (P/Q split and the
+//             predicated squaring).
+// chan_apply: Y = E X or Y = X E for a channel exponential
+//             E = (U kron 1) diag(X0, X1) (U^dagger kron 1), U a 2x2 unitary
+//             acting on the valley index, X0/X1 the N x N orbital blocks
+//             (Methods, HS transform: exp(alpha h kron o) splits into the +1 and
+//             -1 eigenspaces of o). The valley rotation is applied while tiles
+//             are staged into LDS, so one pass costs two N x N x n products
+//             instead of one n x n x n product.
+//
+// Complex products use four real MFMAs per 16x16x4 step. In the mixed path
+// (CT = float) operands are rounded to FP32 when staged, each 16-deep k slab
+// is accumulated by FP32 MFMA and then added into FP64 registers.
+#include "common.h"
+#include "kernels.h"
+
+#define BK 16
+
+template <typename CT, int WTM, int WTN>
+struct Acc {
+  typedef typename Mfma<CT>::acc_t acc_t;
+  acc_t re[WTM][WTN], im[WTM][WTN];
+  CF_DEV void zero() {
+#pragma unroll
+    for (int a = 0; a < WTM; ++a)
+#pragma unroll
+      for (int b = 0; b < WTN; ++b) { re[a][b] = Mfma<CT>::zero(); im[a][b] = Mfma<CT>::zero(); }
+  }
+};
+
+// One BK-deep slab of wave-tile products from LDS (As[k][m], Bs[k][n]).
+template <typename CT, int WTM, int WTN>
+CF_DEV void mma_slab(const typename cplx_t<CT>::type* As, int lda, const typename cplx_t<CT>::type* Bs, int ldb,
+                     int wm0, int wn0, int lane, Acc<CT, WTM, WTN>& acc) {
+  typedef typename cplx_t<CT>::type C2;
+  const int il = lane & 15, kl = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < BK; kk += 4) {
+    C2 a[WTM], b[WTN];
+#pragma unroll
+    for (int s = 0; s < WTM; ++s) a[s] = As[(kk + kl) * lda + wm0 + s * 16 + il];
+#pragma unroll
+    for (int s = 0; s < WTN; ++s) b[s] = Bs[(kk + kl) * ldb + wn0 + s * 16 + il];
+#pragma unroll
+    for (int si = 0; si < WTM; ++si)
+#pragma unroll
+      for (int sj = 0; sj < WTN; ++sj) {
+        acc.re[si][sj] = Mfma<CT>::mma(a[si].x, b[sj].x, acc.re[si][sj]);
+        acc.re[si][sj] = Mfma<CT>::mma(-a[si].y, b[sj].y, acc.re[si][sj]);
+        acc.im[si][sj] = Mfma<CT>::mma(a[si].x, b[sj].y, acc.im[si][sj]);
+        acc.im[si][sj] = Mfma<CT>::mma(a[si].y, b[sj].x, acc.im[si][sj]);
+      }
+  }
+}
+
+// FP64 accumulation point: add an FP32 slab accumulator into FP64 registers.
+template <int WTM, int WTN>
+CF_DEV void flush(Acc<float, WTM, WTN>& a32, Acc<double, WTM, WTN>& a64) {
+#pragma unroll
+  for (int si = 0; si < WTM; ++si)
+#pragma unroll
+    for (int sj = 0; sj < WTN; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a64.re[si][sj][r] += (double)a32.re[si][sj][r];
+        a64.im[si][sj][r] += (double)a32.im[si][sj][r];
+      }
+}
+
+// Output row of accumulator item r for lane (precision-dependent layout).
+template <typename CT> CF_DEV int out_row(int lane, int r) { return Mfma<CT>::row(lane, r); }
+
+// ------------------------------------------------------------------ zgemm
+
+template <typename CT, int BM, int BN, int WTM, int WTN>
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
+zgemm_kernel(GemmArgs g) {
+  typedef typename cplx_t<CT>::type C2;
+  constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
+  constexpr int NT = WX * WY * 64;
+  __shared__ C2 As[BK * BM];
+  __shared__ C2 Bs[BK * BN];
+  const int z = blockIdx.z, z1 = z / g.nz2, z2 = z % g.nz2;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
+  const double2* A = mat_at(g.A, z1, z2);
+  const double2* B = mat_at(g.B, z1, z2);
+
+  bool do_mul = true;
+  if (g.mode == GEMM_SQUARE_OR_COPY) do_mul = g.pred[z1 * g.pred_s1 + z2 * g.pred_s2] > g.pred_thresh;
+
+  Acc<double, WTM, WTN> acc;
+  acc.zero();
+  if (do_mul) {
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+      // stage A tile as As[k][m]
+      for (int idx = tid; idx < BM * BK; idx += NT) {
+        int m, k;
+        double2 v = make_double2(0.0, 0.0);
+        if (g.opA == 0) { k = idx % BK; m = idx / BK; if (m0 + m < g.M && k0 + k < g.K) v = A[(long long)(m0 + m) * g.A.ld + k0 + k]; }
+        else { m = idx % BM; k = idx / BM; if (m0 + m < g.M && k0 + k < g.K) { v = A[(long long)(k0 + k) * g.A.ld + m0 + m]; v.y = -v.y; } }
+        As[k * BM + m] = to_ct<CT>(v);
+      }
+      for (int idx = tid; idx < BN * BK; idx += NT) {
+        int n, k;
+        double2 v = make_double2(0.0, 0.0);
+        if (g.opB == 0) { n = idx % BN; k = idx / BN; if (n0 + n < g.N && k0 + k < g.K) v = B[(long long)(k0 + k) * g.B.ld + n0 + n]; }
+        else { k = idx % BK; n = idx / BK; if (n0 + n < g.N && k0 + k < g.K) { v = B[(long long)(n0 + n) * g.B.ld + k0 + k]; v.y = -v.y; } }
+        Bs[k * BN + n] = to_ct<CT>(v);
+      }
+      __syncthreads();
+      if constexpr (sizeof(CT) == 8) {
+        mma_slab<double, WTM, WTN>((const double2*)As, BM, (const double2*)Bs, BN, wm0, wn0, lane, acc);
+      } else {
+        Acc<float, WTM, WTN> a32;
+        a32.zero();
+        mma_slab<float, WTM, WTN>((const float2*)As, BM, (const float2*)Bs, BN, wm0, wn0, lane, a32);
+        flush(a32, acc);
+      }
+      __syncthreads();
+    }
+  }
+  double2 alpha = g.alpha;
+  if (g.alpha_dev) alpha = cmul(alpha, g.alpha_dev[z1 * g.ad_s1 + z2 * g.ad_s2]);
+  double2* D = mat_at(g.D, z1, z2);
+  const double2* Cm = g.C.p ? mat_at(g.C, z1, z2) : nullptr;
+  double2* D2 = g.D2.p ? mat_at(g.D2, z1, z2) : nullptr;
+#pragma unroll
+  for (int si = 0; si < WTM; ++si)
+#pragma unroll
+    for (int sj = 0; sj < WTN; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm0 + si * 16 + out_row<CT>(lane, r);
+        const int j = n0 + wn0 + sj * 16 + (lane & 15);
+        if (i >= g.M || j >= g.N) continue;
+        double2 p = make_double2(acc.re[si][sj][r], acc.im[si][sj][r]);
+        if (g.mode == GEMM_SQUARE_OR_COPY) {
+          D[(long long)i * g.D.ld + j] = do_mul ? p : B[(long long)i * g.B.ld + j];
+        } else if (g.mode == GEMM_PQ) {
+          double2 x = cmul(alpha, p);
+          double2 c = Cm[(long long)i * g.C.ld + j];
+          D[(long long)i * g.D.ld + j] = cadd(c, x);
+          D2[(long long)i * g.D2.ld + j] = csub(c, x);
+        } else {
+          double2 v = cmul(alpha, p);
+          if (Cm) v = cadd(v, cmul(g.beta, Cm[(long long)i * g.C.ld + j]));
+          D[(long long)i * g.D.ld + j] = v;
+        }
+      }
+}
+
+// ------------------------------------------------------------------ chan_apply
+
+template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN>
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
+chan_apply_kernel(ChanArgs c) {
+  typedef typename cplx_t<CT>::type C2;
+  constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
+  constexpr int NT = WX * WY * 64;
+  __shared__ C2 As[2][BK * BM];
+  __shared__ C2 Bs[2][BK * BN];
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
+  const int N = c.N;
+  const double2* M = c.M + z * c.sM;
+  const double2* X[2] = {c.X0 + z * c.sX, c.X1 + z * c.sX};
+  const int rows = LEFT ? N : c.n_other;   // output rows of T
+  const int cols = LEFT ? c.n_other : N;   // output cols of T
+  // conj(U_ba) for LEFT staging, U_ba for RIGHT staging
+  double2 u[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) u[b][a] = LEFT ? cconj(c.U[b][a]) : c.U[b][a];
+
+  auto mload = [&](int i, int j) -> double2 {
+    double2 v = M[(long long)i * c.ldM + j];
+    if (c.one_minus) { v.x = -v.x; v.y = -v.y; if (i == j) v.x += 1.0; }
+    return v;
+  };
+
+  Acc<double, WTM, WTN> acc[2];
+  acc[0].zero();
+  acc[1].zero();
+  for (int k0 = 0; k0 < N; k0 += BK) {
+    if (LEFT) {
+      // A_a = X_a rows m0.., cols k ; B_a = R_a[k][n] = sum_b conj(U_ba) M[bN+k][n]
+      for (int idx = tid; idx < BM * BK; idx += NT) {
+        int m, k;
+        if (c.opX == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          double2 v = make_double2(0.0, 0.0);
+          if (m0 + m < rows && k0 + k < N) {
+            if (c.opX == 0) v = X[a][(long long)(m0 + m) * c.ldX + k0 + k];
+            else { v = X[a][(long long)(k0 + k) * c.ldX + m0 + m]; v.y = -v.y; }
+          }
+          As[a][k * BM + m] = to_ct<CT>(v);
+        }
+      }
+      for (int idx = tid; idx < BN * BK; idx += NT) {
+        const int n = idx % BN, k = idx / BN;
+        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+        if (n0 + n < cols && k0 + k < N) {
+          v0 = mload(k0 + k, n0 + n);
+          v1 = mload(N + k0 + k, n0 + n);
+        }
+        if (ROT) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a) Bs[a][k * BN + n] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
+        } else {
+          Bs[0][k * BN + n] = to_ct<CT>(v0);
+          Bs[1][k * BN + n] = to_ct<CT>(v1);
+        }
+      }
+    } else {
+      // A_a = S_a[m][k] = sum_b M[m][bN+k] U_ba ; B_a = X_a[k][n]
+      for (int idx = tid; idx < BM * BK; idx += NT) {
+        const int k = idx % BK, m = idx / BK;
+        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+        if (m0 + m < rows && k0 + k < N) {
+          v0 = mload(m0 + m, k0 + k);
+          v1 = mload(m0 + m, N + k0 + k);
+        }
+        if (ROT) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a) As[a][k * BM + m] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
+        } else {
+          As[0][k * BM + m] = to_ct<CT>(v0);
+          As[1][k * BM + m] = to_ct<CT>(v1);
+        }
+      }
+      for (int idx = tid; idx < BN * BK; idx += NT) {
+        int n, k;
+        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          double2 v = make_double2(0.0, 0.0);
+          if (n0 + n < cols && k0 + k < N) {
+            if (c.opX == 0) v = X[a][(long long)(k0 + k) * c.ldX + n0 + n];
+            else { v = X[a][(long long)(n0 + n) * c.ldX + k0 + k]; v.y = -v.y; }
+          }
+          Bs[a][k * BN + n] = to_ct<CT>(v);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if constexpr (sizeof(CT) == 8) {
+        mma_slab<double, WTM, WTN>((const double2*)As[a], BM, (const double2*)Bs[a], BN, wm0, wn0, lane, acc[a]);
+      } else {
+        Acc<float, WTM, WTN> a32;
+        a32.zero();
+        mma_slab<float, WTM, WTN>((const float2*)As[a], BM, (const float2*)Bs[a], BN, wm0, wn0, lane, a32);
+        flush(a32, acc[a]);
+      }
+    }
+    __syncthreads();
+  }
+  // combine T_0, T_1 into the two valley blocks of the output
+  double2* Y = c.Y + z * c.sY;
+  const double2* Cadd = c.Cadd ? c.Cadd + z * c.sC : nullptr;
+#pragma unroll
+  for (int si = 0; si < WTM; ++si)
+#pragma unroll
+    for (int sj = 0; sj < WTN; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm0 + si * 16 + out_row<CT>(lane, r);
+        const int j = n0 + wn0 + sj * 16 + (lane & 15);
+        if (i >= rows || j >= cols) continue;
+        const double2 t0 = make_double2(acc[0].re[si][sj][r], acc[0].im[si][sj][r]);
+        const double2 t1 = make_double2(acc[1].re[si][sj][r], acc[1].im[si][sj][r]);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          double2 y;
+          if (ROT) {
+            // LEFT: Y_v = sum_a U_va T_a ; RIGHT: Y_{:,v} = sum_a T_a conj(U_va)
+            y = LEFT ? cadd(cmul(c.U[v][0], t0), cmul(c.U[v][1], t1))
+                     : cadd(cmul(t0, cconj(c.U[v][0])), cmul(t1, cconj(c.U[v][1])));
+          } else {
+            y = v == 0 ? t0 : t1;
+          }
+          const long long off = LEFT ? (long long)(v * N + i) * c.ldY + j : (long long)i * c.ldY + v * N + j;
+          if (Cadd) {
+            const long long offc = LEFT ? (long long)(v * N + i) * c.ldC + j : (long long)i * c.ldC + v * N + j;
+            y = cadd(y, Cadd[offc]);
+          }
+          Y[off] = y;
+        }
+      }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename CT, int BM, int BN, int WTM, int WTN>
+static void run_gemm(const GemmArgs& g, int nbatch, hipStream_t s) {
+  constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, nbatch);
+  hipLaunchKernelGGL((zgemm_kernel<CT, BM, BN, WTM, WTN>), grid, dim3(NT), 0, s, g); cfqmc_post_launch("zgemm_kernel");
+}
+
+void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s) {
+  if (nbatch <= 0 || g.M <= 0 || g.N <= 0) return;
+  if (mixed) {
+    switch (cfg) {
+      case 0: run_gemm<float, 16, 16, 1, 1>(g, nbatch, s); break;
+      case 1: run_gemm<float, 32, 32, 1, 1>(g, nbatch, s); break;
+      case 2: run_gemm<float, 32, 32, 2, 2>(g, nbatch, s); break;
+      default: run_gemm<float, 64, 64, 2, 2>(g, nbatch, s); break;
+    }
+  } else {
+    switch (cfg) {
+      case 0: run_gemm<double, 16, 16, 1, 1>(g, nbatch, s); break;
+      case 1: run_gemm<double, 32, 32, 1, 1>(g, nbatch, s); break;
+      case 2: run_gemm<double, 32, 32, 2, 2>(g, nbatch, s); break;
+      default: run_gemm<double, 64, 64, 2, 2>(g, nbatch, s); break;
+    }
+  }
+}
+
+template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN>
+static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
+  constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
+  const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
+  dim3 grid((cols + BN - 1) / BN, (rows + BM - 1) / BM, nbatch);
+  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROT, BM, BN, WTM, WTN>), grid, dim3(NT), 0, s, c); cfqmc_post_launch("chan_apply_kernel");
+}
+
+template <typename CT, int BM, int BN, int WTM, int WTN>
+static void run_chan_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
+  if (left) {
+    if (rot) run_chan<CT, true, true, BM, BN, WTM, WTN>(c, nbatch, s);
+    else run_chan<CT, true, false, BM, BN, WTM, WTN>(c, nbatch, s);
+  } else {
+    if (rot) run_chan<CT, false, true, BM, BN, WTM, WTN>(c, nbatch, s);
+    else run_chan<CT, false, false, BM, BN, WTM, WTN>(c, nbatch, s);
+  }
+}
+
+void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s) {
+  if (nbatch <= 0) return;
+  if (mixed) {
+    switch (cfg) {
+      case 0: run_chan_any<float, 16, 16, 1, 1>(c, left, rot, nbatch, s); break;
+      case 1: run_chan_any<float, 32, 32, 1, 1>(c, left, rot, nbatch, s); break;
+      case 2: run_chan_any<float, 32, 32, 2, 2>(c, left, rot, nbatch, s); break;
+      default: run_chan_any<float, 64, 64, 2, 2>(c, left, rot, nbatch, s); break;
+    }
+  } else {
+    switch (cfg) {
+      case 0: run_chan_any<double, 16, 16, 1, 1>(c, left, rot, nbatch, s); break;
+      case 1: run_chan_any<double, 32, 32, 1, 1>(c, left, rot, nbatch, s); break;
+      case 2: run_chan_any<double, 32, 32, 2, 2>(c, left, rot, nbatch, s); break;
+      default: run_chan_any<double, 64, 64, 2, 2>(c, left, rot, nbatch, s); break;
+    }
+  }
+}

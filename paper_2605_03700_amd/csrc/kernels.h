@@ -1,0 +1,150 @@
+// Host-side launch interface of the device kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+enum { GEMM_NORMAL = 0, GEMM_PQ = 1, GEMM_SQUARE_OR_COPY = 2 };
+
+// Launch checking: with CFQMC_DEBUG_SYNC=1 in the environment every launch is
+// followed by a device synchronisation and an error check naming the kernel.
+int cfqmc_debug_sync();
+void cfqmc_post_launch(const char* name);
+
+struct GemmArgs {
+  int M, N, K;
+  int opA, opB;             // 0: as stored, 1: conjugate transpose
+  MatRef A, B, C, D, D2;    // C may have p == nullptr (beta ignored)
+  int nz2;                  // inner batch count (z = z1 * nz2 + z2)
+  double2 alpha, beta;
+  const double2* alpha_dev; // optional per-batch factor, index z1*ad_s1 + z2*ad_s2
+  int ad_s1, ad_s2;
+  int mode;
+  const int* pred;          // GEMM_SQUARE_OR_COPY: multiply iff pred[...] > pred_thresh
+  int pred_s1, pred_s2, pred_thresh;
+};
+
+struct ChanArgs {
+  int N;                    // orbital block size
+  int n_other;              // columns of M (LEFT) or rows of M (RIGHT)
+  const double2* M; int ldM; long long sM;
+  const double2* X0; const double2* X1; int ldX; long long sX; int opX;
+  double2 U[2][2];
+  int one_minus;            // use (1 - M) instead of M
+  const double2* Cadd; int ldC; long long sC;   // optional addend
+  double2* Y; int ldY; long long sY;
+};
+
+void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
+void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);
+
+// ---- dense linear algebra (linalg.hip), one matrix per batch entry
+// LU with partial pivoting (pivot=1) or without (pivot=0), in place; ipiv
+// [batch][n]; logdet[batch] = ln det A (complex, principal imaginary part).
+void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int pivot,
+               int nbatch, hipStream_t s);
+// X <- X * A^{-1} with A = P^T L U from launch_lu. upper_only: X <- X U^{-1}.
+void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
+                   const double2* LU, int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only,
+                   int nbatch, hipStream_t s);
+void launch_set_identity(double2* A, int n, int lda, long long sA, int nbatch, hipStream_t s);
+void launch_copy(const double2* X, double2* Y, long long count, long long sX, long long sY, int nbatch,
+                 hipStream_t s);
+// Y[:, k] = X[:, k] * d[k]   (d real, per batch stride sd) ; inv: divide instead
+void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
+                     const double* d, long long sd, int n_rows, int n_cols, int inv, int nbatch, hipStream_t s);
+// max |X - Y| over an n x n matrix per batch, max-reduced into out[batch]
+void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
+                    hipStream_t s);
+
+// ---- UDT stabilisation helpers (linalg.hip)
+// Column norms of W (n x n) -> nrm; descending-order permutation perm.
+void launch_colnorm_sort(const double2* W, int n, long long sW, double* nrm, int* perm, int nbatch,
+                         hipStream_t s);
+// A[:, k] = W[:, perm[k]] / nrm[perm[k]]
+void launch_permute_normalize(const double2* W, int n, long long sW, const double* nrm, const int* perm,
+                              double2* A, int nbatch, hipStream_t s);
+// Cholesky factor from an unpivoted LU of a Hermitian PD Gram matrix:
+// R = diag(1/sqrt(u_kk)) U (upper triangle of LU), sqrtd[k] = sqrt(u_kk).
+void launch_chol_from_lu(const double2* LU, int n, long long sLU, double2* R, double* sqrtd, int nbatch,
+                         hipStream_t s);
+// From Rt (upper, n x n), norms and permutation: D' = |diag(Rt) * nrm|,
+// T'[i][perm[k]] = Rt[i][k] * nrm[perm[k]] / D'[i].
+void launch_udt_finish(const double2* Rt, int n, long long sR, const double* nrm, const int* perm,
+                       double* Dout, long long sD, double2* Tp, int nbatch, hipStream_t s);
+// Y = Dlmax^-1 K Drmax^-1 + Dlmin M Drmin (Loh split), n x n
+void launch_loh_combine(const double2* K, const double2* Mm, const double* Dl, long long sDl, const double* Dr,
+                        long long sDr, double2* Y, int n, int nbatch, hipStream_t s);
+// d -> 1/max(d,1) (mode 0) ; used for column scalings of the Loh formula
+void launch_dmax_inv(const double* d, long long sd, double* out, int n, int nbatch, hipStream_t s);
+// sum ln max(D,1) per batch
+void launch_sum_log_dmax(const double* d, long long sd, int n, double* out, int nbatch, hipStream_t s);
+
+// ---- model kernels (qmc.hip)
+struct ModelDev {
+  int N, n, nq, L;
+  // h-building table: per shift d (0..N-1) terms [hoff[d], hoff[d+1])
+  const int* hoff;
+  const int* h_cre; const int* h_cim; const int* h_qx; const int* h_qy; const int* h_dag;
+  const double* h_sgn; const double* h_scale; const double* h_F;
+  // trace table: per row r (0..nrow-1) components [toff[r], toff[r+1])
+  int nrow;
+  const int* toff; const int* t_qy; const int* t_qx; const int* t_kind; const int* t_comp;
+  const double* t_F;
+  const double* beta;       // background c-number per component [nq]
+  const double2* phase;     // exp(i pi m / N), m = 0..2N-1
+};
+
+struct ChainDev {
+  int nchain;
+  const double2* alpha;     // [chain][4]
+  const double2* U;         // [4][2][2] valley rotations
+};
+
+// h_i = sum_c phi^i_c q_c for all batch entries; phi [batch][4][nq] (stride sphi), h [batch][4][N][N]
+void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double2* h, long long sh, int nbatch,
+                    hipStream_t s);
+// exponential helper: norm estimate and Taylor coefficients per (batch, channel)
+void launch_exp_coef(const double2* X2, const double2* X3, int N, const double2* alpha, int alpha_per_batch,
+                     double* coef, int* sq, int smax, double theta, int* err, int nbatch4, hipStream_t s);
+void launch_exp_poly(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
+                     double2* loE, double2* hiE, double2* loO, double2* hiO, int nbatch4, hipStream_t s);
+
+struct StepArgs {
+  int N, n, nq, L, tau;      // tau 0-based slice index
+  const double2* G[4];       // frames G_0..G_3 (batch stride sG)
+  long long sG;
+  const double* phi; long long sphi;     // phi of slice tau (batch stride = chain stride)
+  double* phip; long long sphip;
+  const double2* alpha;      // [chain][4]
+  const double* eps;         // [chain]
+  const double* noise; long long snoise; // replay slice: [4 nq + 1] per chain, or null
+  uint64_t seed; long long counter;      // RNG counter base (sweep/slice)
+  double* part;              // partial sums [chain][nblk][4]
+  int nblk;
+  unsigned* done;            // [chain] arrival counter
+  const double2* lndetM;     // [chain]
+  double* lnA;               // [chain]
+  int* accept;               // [chain]
+  double* stat;              // [chain][8] running stats
+  double* u_out;             // [chain] uniform used (diagnostics)
+};
+void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s);
+void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s);
+
+// commit accepted slice move
+void launch_commit(const int* accept, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
+                   long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi, int nphi,
+                   const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ, long long npq,
+                   int* acc_count, hipStream_t s);
+void launch_eps_update(double* eps, const int* acc_count, int L, double r0, double deps, double emin,
+                       double emax, int adapt, int nchain, hipStream_t s);
+// S^i_{q=0} (i=1..5) and m^2 from the spin-block G; out [chain][8]
+void launch_observables(const double2* G, long long sG, int N, double F0, double* out, long long sout,
+                        int nchain, hipStream_t s);
+// background sum over slices: c[chain] = sum_tau alpha0 * phi0 . beta
+void launch_background(const ModelDev& m, const double* phi, long long sphi_chain, const double2* alpha,
+                       double2* out, int nchain, hipStream_t s);
+// 4N expansion of the spin block
+void launch_expand4n(const double2* G, int n, double2* G4, hipStream_t s);

@@ -1,0 +1,465 @@
+// Model-specific kernels of the CF-DQMC sweep (arXiv 2605.03700, Methods).
+//
+//  build_h       h_i = sum_c phi^i_c q_c from the sparse shift-phase structure
+//                of the torus density operator (eq. torus density operator):
+//                each m_q has one entry per row, at column k - q_y (mod N), with
+//                phase exp(i pi (2k - q_y) q_x / N) (k 1-based).
+//  exp_coef /    Taylor exponential of alpha_i h_i in even/odd form:
+//  exp_poly      e^{+-A} = E(A^2) +- A O(A^2), degree 13, with a norm check
+//                (Al-Mohy & Higham style bound on ||A^4||^(1/4), ||A^6||^(1/6))
+//                and scaling by 2^-s followed by s squarings.
+//  drift_*       Langevin drift (eq. Langevin proposal, gradient equation with
+//                first-order channel derivative), proposal, and the
+//                Metropolis-Hastings test with the proposal density.
+//  commit, eps   accept/reject bookkeeping and the adaptive step size
+//                eps <- eps + (r_a - r_0) d_eps after each sweep.
+//  observables   S^i_{q=0} and m^2_SO(5) by Wick's theorem from G.
+#include <algorithm>
+#include "common.h"
+#include "kernels.h"
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon, Moraes, Dror & Shaw (SC'11), 10 rounds.
+CF_DEV void philox_round(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+  c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+}
+CF_DEV void philox(uint32_t (&c)[4], uint64_t seed) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k0, k1);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+CF_DEV double u53(uint32_t a, uint32_t b) { return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0); }
+// Normal number j of stream (chain, counter) by Box-Muller on one Philox block.
+CF_DEV double rng_normal(uint64_t seed, int chain, long long counter, int j) {
+  uint32_t c[4] = {(uint32_t)(j >> 1), (uint32_t)counter, (uint32_t)(counter >> 32), (uint32_t)chain};
+  philox(c, seed);
+  const double u1 = 1.0 - u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+  const double r = sqrt(-2.0 * log(u1));
+  return (j & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
+}
+CF_DEV double rng_uniform(uint64_t seed, int chain, long long counter) {
+  uint32_t c[4] = {0x7fffffffu, (uint32_t)counter, (uint32_t)(counter >> 32), (uint32_t)chain};
+  philox(c, seed);
+  return u53(c[0], c[1]);
+}
+
+// ------------------------------------------------------------------ build_h
+__global__ void build_h_kernel(ModelDev m, const double* phi_all, long long sphi, double2* h_all, long long sh) {
+  const int z = blockIdx.z, ch = blockIdx.y, N = m.N;
+  const double* phi = phi_all + z * sphi + ch * m.nq;
+  double2* h = h_all + z * sh + (long long)ch * N * N;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
+    const int r = idx / N, col = idx % N;
+    const int d = ((r - col) % N + N) % N;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = m.hoff[d]; t < m.hoff[d + 1]; ++t) {
+      const double wr = m.h_scale[t] * phi[m.h_cre[t]];
+      const double wi = m.h_cim[t] >= 0 ? m.h_scale[t] * m.h_sgn[t] * phi[m.h_cim[t]] : 0.0;
+      const int qx = m.h_qx[t], qy = m.h_qy[t];
+      const int row = m.h_dag[t] ? col : r;       // orbital whose phase enters
+      int mm = ((2 * (row + 1) - qy) * qx) % (2 * N);
+      if (mm < 0) mm += 2 * N;
+      double2 ph = m.phase[mm];
+      if (m.h_dag[t]) ph.y = -ph.y;
+      const double f = m.h_F[t];
+      acc.x += f * (wr * ph.x - wi * ph.y);
+      acc.y += f * (wr * ph.y + wi * ph.x);
+    }
+    h[idx] = acc;
+  }
+}
+void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double2* h, long long sh, int nbatch,
+                    hipStream_t s) {
+  dim3 grid(min((m.N * m.N + 255) / 256, 64), 4, nbatch);
+  hipLaunchKernelGGL(build_h_kernel, grid, dim3(256), 0, s, m, phi, sphi, h, sh); cfqmc_post_launch("build_h_kernel");
+}
+
+// ------------------------------------------------------------------ exponential helpers
+#define EXP_NC 16   // per (batch, channel): a[0..6], b[0..6], oscale (re, im)
+
+__global__ void exp_coef_kernel(const double2* X2all, const double2* X3all, int N, const double2* alpha,
+                                int alpha_div, double* coef, int* sq, int smax, double theta, int* err) {
+  __shared__ double red[4];
+  const int b4 = blockIdx.x;   // batch * 4 + channel
+  const double2* X2 = X2all + (long long)b4 * N * N;
+  const double2* X3 = X3all + (long long)b4 * N * N;
+  double n2 = 0.0, n3 = 0.0;
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    double s2 = 0.0, s3 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      s2 += sqrt(cabs2(X2[(long long)i * N + c]));
+      s3 += sqrt(cabs2(X3[(long long)i * N + c]));
+    }
+    n2 = fmax(n2, s2);
+    n3 = fmax(n3, s3);
+  }
+  for (int o = 32; o > 0; o >>= 1) { n2 = fmax(n2, __shfl_xor(n2, o, 64)); n3 = fmax(n3, __shfl_xor(n3, o, 64)); }
+  __shared__ double r3[4];
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = n2; r3[threadIdx.x >> 6] = n3; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) { red[0] = fmax(red[0], red[w]); r3[0] = fmax(r3[0], r3[w]); }
+    const int chain_ch = (b4 / 4 / alpha_div) * 4 + (b4 % 4);
+    const double2 al = alpha[chain_ch];
+    const double aa = sqrt(cabs2(al));
+    const double a2 = al.x * al.x - al.y * al.y;   // alpha^2 is real
+    const double d = aa * fmax(pow(red[0], 0.25), pow(r3[0], 1.0 / 6.0));
+    int s = 0;
+    if (d > theta) s = (int)ceil(log2(d / theta));
+    if (s > smax) { s = smax; atomicOr(err, 1); }
+    sq[2 * b4] = s;        // one predicate per P and Q matrix
+    sq[2 * b4 + 1] = s;
+    const double w = a2 / pow(4.0, (double)s);
+    double* cf = coef + (long long)b4 * EXP_NC;
+    double p = 1.0, fe = 1.0, fo = 1.0;   // w^k, (2k)!, (2k+1)!
+    for (int k = 0; k < 7; ++k) {
+      if (k > 0) { p *= w; fe *= (2.0 * k - 1.0) * (2.0 * k); fo *= (2.0 * k) * (2.0 * k + 1.0); }
+      cf[k] = p / fe;
+      cf[7 + k] = p / fo;
+    }
+    const double sc = 1.0 / pow(2.0, (double)s);
+    cf[14] = al.x * sc;
+    cf[15] = al.y * sc;
+  }
+}
+void launch_exp_coef(const double2* X2, const double2* X3, int N, const double2* alpha, int alpha_div,
+                     double* coef, int* sq, int smax, double theta, int* err, int nbatch4, hipStream_t s) {
+  hipLaunchKernelGGL(exp_coef_kernel, dim3(nbatch4), dim3(256), 0, s, X2, X3, N, alpha, alpha_div, coef, sq, smax,
+                     theta, err); cfqmc_post_launch("exp_coef_kernel");
+}
+
+__global__ void exp_poly_kernel(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
+                                double2* loE, double2* hiE, double2* loO, double2* hiO) {
+  const int b4 = blockIdx.y;
+  const double* cf = coef + (long long)b4 * EXP_NC;
+  const long long off = (long long)b4 * N * N;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
+    const int i = idx / N, j = idx % N;
+    const double id = (i == j) ? 1.0 : 0.0;
+    const double2 w1 = H2[off + idx], w2 = X2[off + idx], w3 = X3[off + idx];
+    loE[off + idx] = make_double2(cf[0] * id + cf[1] * w1.x + cf[2] * w2.x, cf[1] * w1.y + cf[2] * w2.y);
+    hiE[off + idx] = make_double2(cf[3] * id + cf[4] * w1.x + cf[5] * w2.x + cf[6] * w3.x,
+                                  cf[4] * w1.y + cf[5] * w2.y + cf[6] * w3.y);
+    loO[off + idx] = make_double2(cf[7] * id + cf[8] * w1.x + cf[9] * w2.x, cf[8] * w1.y + cf[9] * w2.y);
+    hiO[off + idx] = make_double2(cf[10] * id + cf[11] * w1.x + cf[12] * w2.x + cf[13] * w3.x,
+                                  cf[11] * w1.y + cf[12] * w2.y + cf[13] * w3.y);
+  }
+}
+void launch_exp_poly(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
+                     double2* loE, double2* hiE, double2* loO, double2* hiO, int nbatch4, hipStream_t s) {
+  dim3 grid(min((N * N + 255) / 256, 64), nbatch4);
+  hipLaunchKernelGGL(exp_poly_kernel, grid, dim3(256), 0, s, H2, X2, X3, coef, N, loE, hiE, loO, hiO); cfqmc_post_launch("exp_poly_kernel");
+}
+
+// ------------------------------------------------------------------ drift, proposal, MH test
+
+// Diagonals of Y = sum_{v,v'} o_{v'v} (1 - G)^{v v'} needed for Tr[Y m_q] (D1) and Tr[Y m_q^dagger] (D2).
+CF_DEV double2 ytilde(const double2* G, int N, int n, int ch, int a, int b) {
+  auto z = [&](int v, int vp) -> double2 {
+    double2 g = G[(long long)(v * N + a) * n + vp * N + b];
+    double2 r = make_double2(-g.x, -g.y);
+    if (v == vp && a == b) r.x += 1.0;
+    return r;
+  };
+  switch (ch) {
+    case 0: return cadd(z(0, 0), z(1, 1));
+    case 1: return cadd(z(0, 1), z(1, 0));
+    case 2: { double2 d = csub(z(0, 1), z(1, 0)); return make_double2(-d.y, d.x); }   // i (Z01 - Z10)
+    default: return csub(z(0, 0), z(1, 1));
+  }
+}
+
+#define DR_NT 256
+#define DR_MAXN 288
+
+// Drift D = -phi + 2 Re[alpha Tr((1 - G_i)(o_i kron q_c))] of all components in
+// trace row `row` of channel `ch`, written to Dl[t - toff[row]].
+CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, double2 alpha, int ch, int row,
+                      double* Dl, double2* d1, double2* d2) {
+  const int N = m.N, n = m.n, qy = m.t_qy[row];
+  const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
+  for (int k = threadIdx.x; k < N; k += DR_NT) {
+    d1[k] = ytilde(G, N, n, ch, ((k - qy) % N + N) % N, k);
+    d2[k] = ytilde(G, N, n, ch, k, ((k - qy) % N + N) % N);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int t = c_lo + w; t < c_hi; t += DR_NT / 64) {
+    const int qx = m.t_qx[t];
+    double2 tp = make_double2(0.0, 0.0), tm = tp;
+    for (int k = lane; k < N; k += 64) {
+      int mm = ((2 * (k + 1) - qy) * qx) % (2 * N);
+      if (mm < 0) mm += 2 * N;
+      const double2 ph = m.phase[mm];
+      tp = cadd(tp, cmul(d1[k], ph));
+      tm = cadd(tm, cmul(d2[k], cconj(ph)));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      tp.x += __shfl_xor(tp.x, o, 64); tp.y += __shfl_xor(tp.y, o, 64);
+      tm.x += __shfl_xor(tm.x, o, 64); tm.y += __shfl_xor(tm.y, o, 64);
+    }
+    if (lane == 0) {
+      const double f = m.t_F[t];
+      tp = cscale(tp, f);
+      tm = cscale(tm, f);
+      double2 v;
+      const int kind = m.t_kind[t];
+      if (kind == 0) v = cscale(tp, sqrt(2.0));                                  // sqrt(2) m_q
+      else if (kind == 1) v = cadd(tp, tm);                                      // m_q + m_q^dagger
+      else { const double2 d = csub(tp, tm); v = make_double2(-d.y, d.x); }      // i (m_q - m_q^dagger)
+      const double2 av = cmul(alpha, v);
+      Dl[t - c_lo] = -phi[m.t_comp[t]] + 2.0 * av.x;
+    }
+  }
+  __syncthreads();
+}
+
+#define DR_MAXROW 1024
+
+__global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepArgs a) {
+  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN];
+  __shared__ double Dl[DR_MAXROW];
+  __shared__ double red[DR_NT / 64];
+  const int row = blockIdx.x, ch = blockIdx.y, z = blockIdx.z, nq = m.nq;
+  const double2* G = a.G[ch] + z * a.sG;
+  const double* phi = a.phi + z * a.sphi + ch * nq;
+  double* phip = a.phip + z * a.sphip + ch * nq;
+  const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
+  row_drift(m, G, phi, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2);
+  const double eps = a.eps[z];
+  double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0;
+  for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
+    const int c = m.t_comp[t];
+    const int j = ch * nq + c;
+    const double eta = a.noise ? a.noise[z * a.snoise + j] : rng_normal(a.seed, z, a.counter, j);
+    const double p0 = phi[c];
+    const double p1 = p0 + 0.5 * eps * eps * Dl[t - c_lo] + eps * eta;
+    phip[c] = p1;
+    s_norm += p1 * p1 - p0 * p0;
+    s_eta += eta * eta;
+    if (ch == 0) s_bg += (p1 - p0) * m.beta[c];
+  }
+  s_norm = block_sum<DR_NT>(s_norm, red);
+  s_eta = block_sum<DR_NT>(s_eta, red);
+  s_bg = block_sum<DR_NT>(s_bg, red);
+  if (threadIdx.x == 0) {
+    double* p = a.part + ((long long)z * a.nblk + ch * m.nrow + row) * 4;
+    p[0] = s_norm;
+    p[1] = s_eta;
+    p[2] = s_bg;
+  }
+}
+
+__global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a) {
+  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN];
+  __shared__ double Dl[DR_MAXROW];
+  __shared__ double red[DR_NT / 64];
+  __shared__ unsigned last;
+  const int row = blockIdx.x, ch = blockIdx.y, z = blockIdx.z, nq = m.nq;
+  const double2* G = a.G[ch] + z * a.sG;
+  const double* phi = a.phi + z * a.sphi + ch * nq;
+  const double* phip = a.phip + z * a.sphip + ch * nq;
+  const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
+  row_drift(m, G, phip, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2);   // drift at the proposed fields
+  const double eps = a.eps[z];
+  double s_rev = 0.0;
+  for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
+    const int c = m.t_comp[t];
+    const double r = phi[c] - phip[c] - 0.5 * eps * eps * Dl[t - c_lo];
+    s_rev += r * r;
+  }
+  s_rev = block_sum<DR_NT>(s_rev, red);
+  if (threadIdx.x == 0) {
+    double* p = a.part + ((long long)z * a.nblk + ch * m.nrow + row) * 4;
+    p[3] = s_rev;
+    __threadfence();
+    const unsigned prev = atomicAdd(&a.done[z], 1u);
+    last = (prev == (unsigned)a.nblk - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0, s_r = 0.0;
+    const volatile double* pp = a.part + (long long)z * a.nblk * 4;
+    for (int b = 0; b < a.nblk; ++b) {
+      s_norm += pp[b * 4 + 0];
+      s_eta += pp[b * 4 + 1];
+      s_bg += pp[b * 4 + 2];
+      s_r += pp[b * 4 + 3];
+    }
+    const double2 ldm = a.lndetM[z];
+    const double2 al0 = a.alpha[z * 4 + 0];
+    // ln R = 2 ln det M + (c' - c); real for the sign-free model, the phase is monitored
+    const double lnR = 2.0 * ldm.x + al0.x * s_bg;
+    double ph = fmod(2.0 * ldm.y + al0.y * s_bg, 2.0 * M_PI);
+    if (ph > M_PI) ph -= 2.0 * M_PI;
+    if (ph < -M_PI) ph += 2.0 * M_PI;
+    const double lnA = -0.5 * s_norm + lnR - s_r / (2.0 * eps * eps) + 0.5 * s_eta;
+    const double u = a.noise ? a.noise[z * a.snoise + 4 * nq] : rng_uniform(a.seed, z, a.counter);
+    const int acc = (u <= 0.0) ? 1 : (log(u) < lnA ? 1 : 0);
+    a.lnA[z] = lnA;
+    a.accept[z] = acc;
+    if (a.u_out) a.u_out[z] = u;
+    double* st = a.stat + z * 8;
+    st[0] = fmax(st[0], fabs(ph));
+    st[1] += 1.0;
+    st[2] += acc;
+    a.done[z] = 0u;
+  }
+}
+
+void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s) {
+  dim3 grid(m.nrow, 4, nchain);
+  hipLaunchKernelGGL(drift_propose_kernel, grid, dim3(DR_NT), 0, s, m, a); cfqmc_post_launch("drift_propose_kernel");
+}
+void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s) {
+  dim3 grid(m.nrow, 4, nchain);
+  hipLaunchKernelGGL(drift_mh_kernel, grid, dim3(DR_NT), 0, s, m, a); cfqmc_post_launch("drift_mh_kernel");
+}
+
+// ------------------------------------------------------------------ commit
+__global__ void commit_kernel(const int* accept, const double2* Gp, const double2* G0, double2* G, long long nn,
+                              long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi,
+                              int nphi, const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ,
+                              long long npq, int* acc_count) {
+  const int z = blockIdx.y;
+  const int acc = accept[z];
+  const long long tot = nn + npq + nphi;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
+    if (i < nn) {
+      G[z * sG + i] = acc ? Gp[z * sG + i] : G0[z * sG + i];
+    } else if (i < nn + npq) {
+      if (acc) PQ_tau[z * sPQ + (i - nn)] = PQp[z * sPQp + (i - nn)];
+    } else {
+      if (acc) phi_tau[z * sphi + (i - nn - npq)] = phip[z * sphip + (i - nn - npq)];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) acc_count[z] += acc;
+}
+void launch_commit(const int* accept, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
+                   long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi, int nphi,
+                   const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ, long long npq,
+                   int* acc_count, hipStream_t s) {
+  const long long tot = nn + npq + nphi;
+  dim3 grid((unsigned)std::min<long long>((tot + 255) / 256, 512), nchain);
+  hipLaunchKernelGGL(commit_kernel, grid, dim3(256), 0, s, accept, Gp, G0, G, nn, sG, phip, sphip, phi_tau, sphi,
+                     nphi, PQp, sPQp, PQ_tau, sPQ, npq, acc_count); cfqmc_post_launch("commit_kernel");
+}
+
+__global__ void eps_update_kernel(double* eps, int* acc_count, int L, double r0, double deps, double emin,
+                                  double emax, int adapt, int nchain) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nchain) return;
+  if (adapt) {
+    const double ra = (double)acc_count[z] / (double)L;
+    eps[z] = fmin(fmax(eps[z] + (ra - r0) * deps, emin), emax);
+  }
+  acc_count[z] = 0;
+}
+void launch_eps_update(double* eps, const int* acc_count, int L, double r0, double deps, double emin, double emax,
+                       int adapt, int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(eps_update_kernel, dim3((nchain + 63) / 64), dim3(64), 0, s, eps, (int*)acc_count, L, r0, deps,
+                     emin, emax, adapt, nchain); cfqmc_post_launch("eps_update_kernel");
+}
+
+// ------------------------------------------------------------------ observables
+// With G_4N = 1_spin kron G and T_o = o kron 1_N on the spin block:
+//   S^{1,2} = F0^2 [ (2 Tr T(1-G))^2 + 2 Tr(T G T (1-G)) ]   (o = tau_x, tau_y)
+//   S^{3,4,5} = 2 F0^2 Tr(T G T (1-G))                        (o = tau_z)
+// Tr(T G T (1-G)) = Tr G - sum_{a,b} tr_2(o g_ab o g_ba), g_ab the 2x2 valley block.
+__global__ void observables_kernel(const double2* Gall, long long sG, int N, double F0, double* out, long long sout) {
+  __shared__ double red[4];
+  const int z = blockIdx.x, n = 2 * N;
+  const double2* G = Gall + z * sG;
+  double trG = 0.0, q[3] = {0.0, 0.0, 0.0}, txr = 0.0, txi = 0.0, tyr = 0.0, tyi = 0.0;
+  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    const int a = idx / N, b = idx % N;
+    double2 g[2][2], h[2][2];
+    for (int v = 0; v < 2; ++v)
+      for (int w = 0; w < 2; ++w) {
+        g[v][w] = G[(long long)(v * N + a) * n + w * N + b];
+        h[v][w] = G[(long long)(v * N + b) * n + w * N + a];
+      }
+    // tau_x: (o g o)_{vw} = g_{1-v,1-w} ; tau_z: (o g o)_{vw} = s_v s_w g_vw ; tau_y: s_v s_w g_{1-v,1-w} with s = (1,-1) after i*(-i) factors
+    double2 sx = make_double2(0, 0), sy = sx, sz = sx;
+    for (int v = 0; v < 2; ++v)
+      for (int w = 0; w < 2; ++w) {
+        const double2 hw = h[w][v];
+        const double sgn = (v == w) ? 1.0 : -1.0;
+        sx = cadd(sx, cmul(g[1 - v][1 - w], hw));
+        sz = cadd(sz, cscale(cmul(g[v][w], hw), sgn));
+        sy = cadd(sy, cscale(cmul(g[1 - v][1 - w], hw), sgn));
+      }
+    q[0] += sx.x; q[1] += sy.x; q[2] += sz.x;
+    if (a == b) {
+      trG += g[0][0].x + g[1][1].x;
+      // tr(tau_x g_aa) = g10 + g01 ; tr(tau_y g_aa) = i (g01 - g10)
+      txr += g[1][0].x + g[0][1].x;
+      txi += g[1][0].y + g[0][1].y;
+      tyr += -(g[0][1].y - g[1][0].y);
+      tyi += g[0][1].x - g[1][0].x;
+    }
+  }
+  trG = block_sum<256>(trG, red);
+  q[0] = block_sum<256>(q[0], red);
+  q[1] = block_sum<256>(q[1], red);
+  q[2] = block_sum<256>(q[2], red);
+  txr = block_sum<256>(txr, red);
+  txi = block_sum<256>(txi, red);
+  tyr = block_sum<256>(tyr, red);
+  tyi = block_sum<256>(tyi, red);
+  if (threadIdx.x == 0) {
+    const double f2 = F0 * F0;
+    const double cx = trG - q[0], cy = trG - q[1], cz = trG - q[2];
+    double* o = out + z * sout;
+    // Re[(2 tr T(1-G))^2] = 4 (re^2 - im^2) of tr(T G)
+    o[0] = f2 * (4.0 * (txr * txr - txi * txi) + 2.0 * cx);
+    o[1] = f2 * (4.0 * (tyr * tyr - tyi * tyi) + 2.0 * cy);
+    o[2] = o[3] = o[4] = 2.0 * f2 * cz;
+    o[5] = (o[0] + o[1] + o[2] + o[3] + o[4]) / (5.0 * N * N);
+    o[6] = trG;
+  }
+}
+void launch_observables(const double2* G, long long sG, int N, double F0, double* out, long long sout, int nchain,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(observables_kernel, dim3(nchain), dim3(256), 0, s, G, sG, N, F0, out, sout); cfqmc_post_launch("observables_kernel");
+}
+
+__global__ void background_kernel(ModelDev m, const double* phi_all, long long sphi_chain, const double2* alpha,
+                                  double2* out) {
+  __shared__ double red[4];
+  const int z = blockIdx.x;
+  const double* phi = phi_all + z * sphi_chain;
+  double s = 0.0;
+  for (int idx = threadIdx.x; idx < m.L * m.nq; idx += 256) {
+    const int t = idx / m.nq, c = idx % m.nq;
+    s += phi[(long long)t * 4 * m.nq + c] * m.beta[c];
+  }
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) out[z] = cscale(alpha[z * 4], s);
+}
+void launch_background(const ModelDev& m, const double* phi, long long sphi_chain, const double2* alpha,
+                       double2* out, int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(background_kernel, dim3(nchain), dim3(256), 0, s, m, phi, sphi_chain, alpha, out); cfqmc_post_launch("background_kernel");
+}
+
+__global__ void expand4n_kernel(const double2* G, int n, double2* G4) {
+  const int n4 = 2 * n;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n4 * n4; idx += gridDim.x * blockDim.x) {
+    const int i = idx / n4, j = idx % n4;
+    const int si = i / n, sj = j / n;
+    G4[idx] = si == sj ? G[(long long)(i % n) * n + (j % n)] : make_double2(0.0, 0.0);
+  }
+}
+void launch_expand4n(const double2* G, int n, double2* G4, hipStream_t s) {
+  hipLaunchKernelGGL(expand4n_kernel, dim3(min((4 * n * n + 255) / 256, 1024)), dim3(256), 0, s, G, n, G4); cfqmc_post_launch("expand4n_kernel");
+}

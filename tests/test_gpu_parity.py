@@ -1,0 +1,170 @@
+"""GPU parity of the HIP sweep against the FP64 oracle, through the C ABI.
+
+Bars (spec tolerances): FP64 path 1e-10 relative in G and ln w on an
+identical recorded field history / replayed noise; mixed path <= 1e-6 in G.
+Accept/reject sequences under replayed noise must be identical.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dqmc
+from oracle.model import Model, Q_BZ, Q_PAPER, Q_RADIUS
+from oracle.observables import so5_observables
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_03700_amd import CFQMC
+    return CFQMC
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def wrap_phase(x):
+    return abs(np.angle(np.exp(1j * x)))
+
+
+CASES = [
+    # n_phi, L, n_stab, q_mode, q_max, u
+    (4, 8, 4, Q_BZ, None, 1.0),
+    (5, 7, 3, Q_PAPER, None, 1.3),      # odd N, ragged last stabilisation block
+    (6, 40, 10, Q_BZ, None, 1.0),       # the N_phi = 6 workload (36 momenta, L = 40)
+]
+
+
+@pytest.mark.parametrize("n_phi,L,nstab,mode,qmax,u", CASES)
+def test_green_and_logdet_at_init(n_phi, L, nstab, mode, qmax, u):
+    CFQMC = _gpu()
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=u, un=u, q_mode=mode, q_max=qmax)
+    phi = synth.fields(100 + n_phi, L, m.n_q)
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, u0=1.0, uk=u, un=u, q_mode=mode, q_max=qmax or 3.0,
+              n_stab=nstab, tile_cfg=1)
+    assert g.n_q == m.n_q
+    g.init_fields(phi[None])
+    Bs = dqmc.propagators(m, phi)
+    for tau in sorted({0, 1, nstab, L - 1, L}):
+        G = g.measure_G(0, tau)
+        Gr = dqmc.green(m, phi, tau, Bs)
+        n = 2 * n_phi
+        assert rel(G[:n, :n], Gr) < 1e-10, tau
+        assert np.abs(G[n:, n:] - G[:n, :n]).max() == 0 and np.abs(G[:n, n:]).max() == 0
+        assert abs(np.trace(G).real - 2 * n_phi) < 1e-10          # Re tr G_4N = 2 N (half filling)
+    ld, ldr = g.logdet(0), dqmc.logdet(m, phi, Bs)
+    assert abs(ld.real - ldr.real) < 1e-10 * abs(ldr.real)
+    assert wrap_phase(ld.imag) < 1e-9 and wrap_phase(ldr.imag) < 1e-9
+    s, m2 = g.observables(0)
+    sr, m2r = so5_observables(dqmc.green(m, phi, L, Bs), n_phi)
+    assert np.abs(s - sr.real).max() < 1e-10 * np.abs(sr).max()
+    assert abs(m2 - m2r) < 1e-10 * abs(m2r)
+    g.close()
+
+
+def _replay_compare(CFQMC, n_phi, L, nstab, mode, qmax, u_list, precision, n_sweeps, tol_g, seed=7, eps0=0.4):
+    nch = len(u_list)
+    models = [Model(n_phi, L, 0.1, u0=1.0, uk=u, un=u, q_mode=mode, q_max=qmax) for u in u_list]
+    nq = models[0].n_q
+    phi = np.stack([synth.fields(seed + 10 * k, L, nq) for k in range(nch)])
+    rp = np.stack([synth.replay(seed + 10 * k + 1, n_sweeps, L, nq) for k in range(nch)])
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=mode, q_max=qmax or 3.0, n_stab=nstab, eps0=eps0,
+              adapt_eps=True, precision=precision, n_chains=nch,
+              chain_u=[(1.0, u, u) for u in u_list], tile_cfg=1)
+    g.init_fields(phi)
+    chains = [dqmc.Chain(models[k], phi[k], eps0=eps0, adapt=True) for k in range(nch)]
+    for sw in range(n_sweeps):
+        st = g.sweep(1, rp[:, sw:sw + 1])
+        for k in range(nch):
+            chains[k].sweep(rp[k, sw])
+            acc, lna = g.last_sweep(k)
+            hist = chains[k].history[-L:]
+            assert acc.tolist() == [int(h[2]) for h in hist], (k, sw)
+            finite = np.array([np.isfinite(h[1]) for h in hist])
+            lref = np.array([h[1] for h in hist])
+            assert np.allclose(lna[finite], lref[finite], rtol=0, atol=tol_g * 1e3)
+            assert st[k]["max_phase_err"] < 1e-6
+    eps = g.get_eps()
+    for k in range(nch):
+        m = models[k]
+        assert abs(eps[k] - chains[k].eps) < 1e-12
+        assert np.abs(g.get_fields()[k] - chains[k].phi).max() < 1e-10
+        G = g.measure_G(k, L)[:2 * n_phi, :2 * n_phi]
+        assert rel(G, dqmc.green(m, chains[k].phi, L)) < tol_g
+        ld, ldr = g.logdet(k), dqmc.logdet(m, chains[k].phi)
+        assert abs(ld.real - ldr.real) < max(tol_g, 1e-10) * abs(ldr.real)
+    g.close()
+    return st
+
+
+def test_sweep_replay_parity_fp64_small():
+    CFQMC = _gpu()
+    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], 0, 3, 1e-10)
+    assert st[0]["max_stab_err"] < 1e-9
+
+
+def test_sweep_replay_parity_batched_u_grid():
+    """Five chains of one shape at u = 0.5..2.5 in one context (one launch per step)."""
+    CFQMC = _gpu()
+    _replay_compare(CFQMC, 8, 24, 6, Q_RADIUS, 3.0, [0.5, 1.0, 1.5, 2.0, 2.5], 0, 2, 1e-10)
+
+
+def test_sweep_replay_parity_mixed():
+    """Mixed path: FP32 MFMA wraps/updates with FP64 accumulation, FP64 recomputation.
+    G after a sweep (recomputed in FP64) within 1e-6 and the G drift between
+    recomputations within 1e-6."""
+    CFQMC = _gpu()
+    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], 1, 2, 1e-6)
+    assert st[0]["max_stab_err"] < 1e-6
+
+
+def test_tile_configurations_agree():
+    CFQMC = _gpu()
+    n_phi, L = 7, 12
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=1.0, un=1.0)
+    phi = synth.fields(3, L, m.n_q)
+    rp = synth.replay(4, 1, L, m.n_q)
+    out = []
+    for cfg in range(4):
+        g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg)
+        g.init_fields(phi[None])
+        g.sweep(1, rp[None])
+        out.append((g.measure_G(0, L), g.last_sweep(0)[0].tolist()))
+        g.close()
+    for G, acc in out[1:]:
+        assert acc == out[0][1]
+        assert rel(G, out[0][0]) < 1e-12
+
+
+def test_exponential_scaling_and_squaring_path():
+    """Large fields force the scaled Taylor exponential with squarings."""
+    CFQMC = _gpu()
+    n_phi, L, u = 5, 6, 3.0
+    m = Model(n_phi, L, 0.2, u0=1.0, uk=u, un=u)
+    phi = synth.fields(8, L, m.n_q, scale=6.0)
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.2, u0=1.0, uk=u, un=u, n_stab=3, exp_squarings=4, tile_cfg=0)
+    g.init_fields(phi[None])
+    G = g.measure_G(0, 2)[:2 * n_phi, :2 * n_phi]
+    assert rel(G, dqmc.green(m, phi, 2)) < 1e-10
+    g.close()
+
+
+def test_device_rng_sweep_invariants():
+    """Without replay (device Philox noise): sign-free phase, particle-hole
+    symmetry, finite stabilisation error, acceptance in (0, 1)."""
+    CFQMC = _gpu()
+    g = CFQMC(n_phi=12, l_tau=40, dtau=0.1, u0=1.0, uk=1.5, un=1.5, n_stab=8, n_chains=2, tile_cfg=1, seed=11)
+    g.init_fields(None)
+    st = g.sweep(4)
+    for k in range(2):
+        assert 0 < st[k]["accepted"] < st[k]["proposed"] == 4 * 40
+        assert st[k]["max_phase_err"] < 1e-8
+        assert st[k]["max_stab_err"] < 1e-8
+        G = g.measure_G(k, 40)
+        assert abs(np.trace(G).real - 24) < 1e-9
+    assert len(g.series(0)) == 4
+    g.close()
