@@ -1,0 +1,138 @@
+"""Benchmark of the CF-DQMC sweep on one MI355X.
+
+Workload (default): torus N_phi = 100 (spin block n = 200, 4N = 400), paper
+momentum cutoff (933 HS components per channel), L = 400 slices of dtau = 0.1,
+u = 1.5 on the SO(5) line, FP64 recomputation every 8 slices, complex FP32
+MFMA wraps and updates with FP64 accumulation (--precision fp64 for the plain
+path). A step is one sweep of every chain: L Langevin slice moves of
+4 n_q fields each, with wraps, Woodbury updates and stabilisation.
+
+Prints one JSON line (see the fields below). Synthetic fields N(0,1).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "mixed": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
+
+
+def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
+    """The FP64 oracle timed on the host on a bounded sample of the same
+    workload: the first slices of one sweep (suffix products included)."""
+    import numpy as np
+    import synth
+    from oracle import dqmc
+    from oracle.model import Model
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    m = Model(n_phi, l_tau, dtau, u0=1.0, uk=u, un=u)
+    phi = synth.fields(1, l_tau, m.n_q)
+    rp = synth.replay(2, 1, l_tau, m.n_q)[0]
+    ch = dqmc.Chain(m, phi, eps0=0.3, adapt=False)
+    # estimate cost per slice on a short probe, then size the sample to ~seconds
+    t0 = time.perf_counter()
+    ch.sweep(rp, max_slices=2)
+    t_probe = time.perf_counter() - t0
+    k = max(2, min(l_tau, int(2 * seconds / max(t_probe, 1e-3))))
+    ch = dqmc.Chain(m, phi, eps0=0.3, adapt=False)
+    t0 = time.perf_counter()
+    ch.sweep(rp, max_slices=k)
+    dt = time.perf_counter() - t0
+    return {"value": k * 4 * m.n_q / dt, "unit": "field updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d slices of one sweep at N_phi=%d (n_q=%d), FP64 numpy/LAPACK, %.1f s"
+                      % (k, l_tau, n_phi, m.n_q, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-phi", type=int, default=100)
+    ap.add_argument("--l-tau", type=int, default=400)
+    ap.add_argument("--dtau", type=float, default=0.1)
+    ap.add_argument("--u", type=float, default=1.5)
+    ap.add_argument("--n-stab", type=int, default=8)
+    ap.add_argument("--chains", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--tile-cfg", type=int, default=-1)
+    ap.add_argument("--tau-sweeps", type=int, default=0, help="extra untimed sweeps for tau_int")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (chains shard "
+              "independently; see the design notes). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2605_03700_amd import CFQMC, FP64, MIXED
+    from paper_2605_03700_amd.analysis import tau_int
+    assert torch.cuda.is_available(), "needs the GPU"
+    prec = MIXED if args.precision == "mixed" else FP64
+    g = CFQMC(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+              n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3,
+              n_chains=args.chains, tile_cfg=args.tile_cfg)
+    g.init_fields(None)
+    if args.warmup:
+        g.sweep(args.warmup)
+    torch.cuda.synchronize()
+    g.kernel_timing(True)
+    t0 = time.perf_counter()
+    st = g.sweep(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_count, k_flops = g.kernel_timing_read()
+    g.kernel_timing(False)
+    fields = args.chains * args.l_tau * 4 * g.n_q * args.steps
+    value = fields / dt
+    sweeps_per_s = args.steps / dt
+    acc = sum(s["accepted"] for s in st) / max(1, sum(s["proposed"] for s in st))
+    g_err = max(s["max_stab_err"] for s in st)
+    out = {
+        "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
+        "value": value, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if prec == MIXED else "f64", "data": "synthetic",
+        "config": {"workload": "torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chain(s), "
+                               "recompute every %d slices" % (args.n_phi, args.l_tau, args.dtau, args.u, g.n_q,
+                                                              args.chains, args.n_stab),
+                   "chains": args.chains, "precision": args.precision, "n_q": g.n_q,
+                   "tile_cfg": list(g.tile_config())},
+        "acceptance": acc,
+        "eps": float(np.mean(g.get_eps())),
+        "g_err_max": g_err,
+        "sweeps_per_s_per_chain": sweeps_per_s,
+    }
+    if k_count > 0 and k_ms > 0:
+        ach = k_flops / (k_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": "chan_apply", "achieved": ach,
+                           "peak": PEAK[args.precision], "unit": "TFLOP/s", "frac": ach / PEAK[args.precision],
+                           "traffic": None, "avg_launch_ms": k_ms, "launches_timed": k_count,
+                           "flops_per_launch": k_flops}
+    if args.tau_sweeps > 0:
+        g.set_eps(g.get_eps())
+        n0 = len(g.series(0))
+        t1 = time.perf_counter()
+        g.sweep(args.tau_sweeps)
+        dt2 = time.perf_counter() - t1
+        taus = [tau_int(g.series(k)[n0:])[0] for k in range(args.chains)]
+        tau = float(np.mean(taus))
+        out["tau_int_sweeps"] = tau
+        out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds)
+    g.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -142,6 +142,15 @@ int cfqmc_set_eps(cfqmc_ctx* c, const double* eps /* [n_chains] */);
 /* Tile configuration chosen for (channel application, n x n GEMM). */
 int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg);
 
+/* Sampled HIP-event timing of the dominant kernel, the channel-exponential
+ * application (two N x N x n complex products per chain on MFMA): when enabled,
+ * one launch per slice is bracketed by events on the context's stream (up to
+ * 4096 launches per sample set). enable = 1 starts a new sample set. */
+int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable);
+/* Mean duration (ms) and count of the sampled launches, and the algorithmic
+ * real flops of one launch (16 N^2 n per chain). Synchronises. */
+int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch);
+
 const char* cfqmc_last_error(const cfqmc_ctx* c);
 
 #ifdef __cplusplus

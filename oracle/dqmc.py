@@ -152,8 +152,9 @@ class Chain:
         self.history = []          # per slice: (sweep, tau, lnA, accepted)
         self.phase_err = 0.0
 
-    def sweep(self, replay):
-        """One sweep tau = 1..L. replay: [L][4 n_q + 1] (eta..., u)."""
+    def sweep(self, replay, max_slices=None):
+        """One sweep tau = 1..L (or the first max_slices slices, for timing
+        samples). replay: [L][4 n_q + 1] (eta..., u)."""
         m = self.m
         n, L, nq = m.n, m.l_tau, m.n_q
         I = np.eye(n)
@@ -168,6 +169,8 @@ class Chain:
         acc = 0
         eps = self.eps
         for t in range(1, L + 1):
+            if max_slices is not None and t > max_slices:
+                return acc
             ph = self.phi[t - 1]
             A = Bs[t - 1] @ P @ S[t]
             G = np.linalg.inv(I + A)

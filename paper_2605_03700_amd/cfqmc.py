@@ -47,7 +47,7 @@ _lib = None
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
            "cfqmc_get_fields", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
-           "cfqmc_last_error"]
+           "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read"]
 
 
 def load():
@@ -76,6 +76,9 @@ def load():
     lib.cfqmc_get_eps.argtypes = [P, P]
     lib.cfqmc_set_eps.argtypes = [P, P]
     lib.cfqmc_tile_config.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_kernel_timing.argtypes = [P, ctypes.c_int32]
+    lib.cfqmc_kernel_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_last_error.argtypes = [P]
     lib.cfqmc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -201,6 +204,15 @@ class CFQMC:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         self._check(self.lib.cfqmc_tile_config(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def kernel_timing(self, enable=True):
+        self._check(self.lib.cfqmc_kernel_timing(self.h, int(bool(enable))))
+
+    def kernel_timing_read(self):
+        """(mean ms per sampled channel-application launch, count, flops per launch)."""
+        a, k, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._check(self.lib.cfqmc_kernel_timing_read(self.h, ctypes.byref(a), ctypes.byref(k), ctypes.byref(f)))
+        return a.value, k.value, f.value
 
     def close(self):
         if getattr(self, "h", None) is not None:

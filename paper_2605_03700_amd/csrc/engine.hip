@@ -200,6 +200,8 @@ struct cfqmc_ctx {
   double2* S1;
   double2* S2;
   double2* Mw;
+  double2* Mb;
+  int* lu_flag;
   int* ipiv;
   double2* lndet;
   double* phip;
@@ -238,6 +240,10 @@ struct cfqmc_ctx {
   double2* ldtmp;
   long long sweep_counter;
   int cfg_chan, cfg_gemm, cfg_small;
+  // sampled HIP-event timing of the channel application (one launch per slice)
+  bool timing;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used;
   bool ready;
   std::string err;
 };
@@ -295,7 +301,7 @@ MatRef mref(const double2* p, int ld, long long s1, long long s2 = 0) {
 
 // Y = E X (left) or X E (right) for channel ch of the P/Q block at PQch (chain stride sPQ).
 void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, long long sPQ, const double2* X,
-          double2* Y, bool one_minus, const double2* add, int mixed, long long sY = -1) {
+          double2* Y, bool one_minus, const double2* add, int mixed, long long sY = -1, double2* Y2 = nullptr) {
   ChanArgs a;
   memset(&a, 0, sizeof(a));
   const int N = c->N;
@@ -311,6 +317,7 @@ void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, lon
   a.one_minus = one_minus ? 1 : 0;
   a.Cadd = add; a.ldC = c->n; a.sC = c->nn;
   a.Y = Y; a.ldY = c->n; a.sY = sY < 0 ? c->nn : sY;
+  a.Y2 = Y2;
   const int rot = (ch == 1 || ch == 2);
   launch_chan_apply(a, left, rot, c->nch, mixed, c->cfg_chan, c->s);
 }
@@ -389,12 +396,12 @@ void udt_acc(cfqmc_ctx* c, const double2* C, long long sC, int opC, const double
   launch_permute_normalize(c->W1, n, nn, c->nrm, c->perm, c->A1, B, c->s);
   // Cholesky-QR, twice
   gemm_nn(c, c->A1, 1, nn, c->A1, 0, nn, c->Gr, nn, B);
-  launch_lu(c->Gr, n, n, nn, c->ipiv, n, nullptr, 0, B, c->s);
+  launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
   launch_chol_from_lu(c->Gr, n, nn, c->R1, c->sqd1, B, c->s);
   launch_rsolve(c->A1, n, nn, c->Q1, n, nn, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s);
   launch_colscale(c->Q1, n, nn, c->Q1, n, nn, c->sqd1, n, n, n, 0, B, c->s);
   gemm_nn(c, c->Q1, 1, nn, c->Q1, 0, nn, c->Gr, nn, B);
-  launch_lu(c->Gr, n, n, nn, c->ipiv, n, nullptr, 0, B, c->s);
+  launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
   launch_chol_from_lu(c->Gr, n, nn, c->R2, c->sqd2, B, c->s);
   launch_rsolve(c->Q1, n, nn, Uo, n, sU, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s);
   launch_colscale(Uo, n, sU, Uo, n, sU, c->sqd2, n, n, n, 0, B, c->s);
@@ -505,8 +512,11 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   const double2* pq = c->PQ + (long long)t * 8 * NN;   // chain 0 of slice t
   // 1. wrap through the channels of slice t, keeping the frames
   const double2* cur = c->G;
+  const bool tm = c->timing && c->ev_used + 2 <= c->ev.size();
   for (int ch = 3; ch >= 0; --ch) {
+    if (tm && ch == 2) hipEventRecord(c->ev[c->ev_used], c->s);
     chan(c, 1, ch, false, pq + ch * 2 * NN, sPQ, cur, c->S1, false, nullptr, mixed);
+    if (tm && ch == 2) { hipEventRecord(c->ev[c->ev_used + 1], c->s); c->ev_used += 2; }
     chan(c, 0, ch, true, pq + ch * 2 * NN, sPQ, c->S1, c->F[ch], false, nullptr, mixed);
     cur = c->F[ch];
   }
@@ -542,9 +552,12 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
     chan(c, 1, ch, false, c->PQp + ch * 2 * NN, sPQp, y, y2, false, nullptr, mixed);
     std::swap(y, y2);
   }
-  chan(c, 1, 0, false, c->PQp, sPQp, y, c->Mw, false, c->F[0], mixed);
-  // 5. LU of M: ln det M
-  launch_lu(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, 1, c->nch, c->s);
+  chan(c, 1, 0, false, c->PQp, sPQp, y, c->Mw, false, c->F[0], mixed, -1, c->Mb);
+  // 5. LU of M: ln det M. M is close to the identity, so the blocked LU without
+  //    pivoting is tried first; chains whose multipliers exceed the threshold
+  //    are refactorised with partial pivoting from the saved copy.
+  launch_lu_np(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, c->lu_flag, 8.0, c->nch, c->s);
+  launch_lu(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, 1, c->nch, c->s, c->lu_flag, c->Mb);
   // 6. G' = G_0 M^{-1}
   launch_rsolve(c->F[0], c->n, nn, c->Fp[0], c->n, nn, c->Mw, c->n, nn, c->ipiv, c->n, c->n, 0, c->nch, c->s);
   // 7. frames of G' for the drift at phi'
@@ -590,33 +603,45 @@ int build_all_exps(cfqmc_ctx* c) {
 }
 
 int autotune(cfqmc_ctx* c) {
-  // time the channel application and the n x n GEMM for each tile configuration
+  // time the channel application, the n x n GEMM and the batched N x N GEMM of
+  // the exponential for each tile configuration; keep the fastest of each
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
-  float best_c = 1e30f, best_g = 1e30f;
-  int bc = 1, bg = 1;
+  float best_c = 1e30f, best_g = 1e30f, best_s = 1e30f;
+  int bc = 1, bg = 1, bs = 0;
+  const long long NN = c->NN, s4 = 4 * NN;
+  auto timeit = [&](auto&& fn) {
+    float ms = 0.f;
+    fn();   // warm-up
+    hipEventRecord(e0, c->s);
+    for (int k = 0; k < 8; ++k) fn();
+    hipEventRecord(e1, c->s);
+    hipEventSynchronize(e1);
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
   for (int cfg = 0; cfg < 4; ++cfg) {
     c->cfg_chan = cfg;
     c->cfg_gemm = cfg;
-    for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
-      hipEventRecord(e0, c->s);
-      for (int k = 0; k < 8; ++k) chan(c, k & 1, 1 + (k & 1), false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
-      hipEventRecord(e1, c->s);
-      hipEventSynchronize(e1);
-      float ms;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (rep == 1 && ms < best_c) { best_c = ms; bc = cfg; }
-      hipEventRecord(e0, c->s);
-      for (int k = 0; k < 8; ++k) gemm_nn(c, c->F[0], 0, c->nn, c->F[1], 0, c->nn, c->S1, c->nn, c->nch);
-      hipEventRecord(e1, c->s);
-      hipEventSynchronize(e1);
-      hipEventElapsedTime(&ms, e0, e1);
-      if (rep == 1 && ms < best_g) { best_g = ms; bg = cfg; }
-    }
+    const float tc = timeit([&]() {
+      chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
+      chan(c, 0, 2, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, c->mixed);
+    });
+    if (tc < best_c) { best_c = tc; bc = cfg; }
+    const float tg = timeit([&]() { gemm_nn(c, c->F[0], 0, c->nn, c->F[1], 0, c->nn, c->S1, c->nn, c->nch); });
+    if (tg < best_g) { best_g = tg; bg = cfg; }
+    const float ts = timeit([&]() {
+      GemmArgs g = gemm0(c->N, c->N, c->N);
+      g.A = mref(c->H2, c->N, s4, NN); g.B = mref(c->X2, c->N, s4, NN); g.D = mref(c->X3, c->N, s4, NN);
+      g.nz2 = 4;
+      launch_zgemm(g, c->nch * 4, 0, cfg, c->s);
+    });
+    if (ts < best_s) { best_s = ts; bs = cfg; }
   }
   c->cfg_chan = bc;
   c->cfg_gemm = bg;
+  c->cfg_small = bs;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return CFQMC_OK;
@@ -660,6 +685,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->nn = (long long)c->n * c->n;
   c->NN = (long long)c->N * c->N;
   c->ready = false;
+  c->timing = false;
+  c->ev_used = 0;
   c->sweep_counter = 0;
   if (!build_components(p, c->ht, c->err)) { delete c; return CFQMC_EINVAL; }
   c->nq = (int)c->ht.comp_kind.size();
@@ -685,6 +712,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->S1, (size_t)B * nn);
   rc |= dalloc(c, &c->S2, (size_t)B * nn);
   rc |= dalloc(c, &c->Mw, (size_t)B * nn);
+  rc |= dalloc(c, &c->Mb, (size_t)B * nn);
+  rc |= dalloc(c, &c->lu_flag, (size_t)B);
   rc |= dalloc(c, &c->ipiv, (size_t)B * n);
   rc |= dalloc(c, &c->lndet, (size_t)B);
   rc |= dalloc(c, &c->ldtmp, (size_t)B);
@@ -755,6 +784,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
 int cfqmc_destroy(cfqmc_ctx* c) {
   if (!c) return CFQMC_EINVAL;
   hipStreamSynchronize(c->s);
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
   for (void* q : c->allocs) hipFree(q);
   delete c;
   return CFQMC_OK;
@@ -1012,6 +1042,35 @@ int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg) 
   if (!c) return CFQMC_EINVAL;
   if (chan_cfg) *chan_cfg = c->cfg_chan;
   if (gemm_cfg) *gemm_cfg = c->cfg_gemm;
+  return CFQMC_OK;
+}
+
+int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable) {
+  if (!c) return CFQMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * 4096);
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+  }
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  return CFQMC_OK;
+}
+
+int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch) {
+  if (!c) return CFQMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->s));
+  double tot = 0.0;
+  const int64_t k = (int64_t)(c->ev_used / 2);
+  for (int64_t i = 0; i < k; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    tot += ms;
+  }
+  if (avg_ms) *avg_ms = k ? tot / k : 0.0;
+  if (count) *count = k;
+  // two N x N x n complex products per chain = 8 * 2 N^2 n real flops
+  if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
   return CFQMC_OK;
 }
 

@@ -13,7 +13,11 @@
 //
 // Complex products use four real MFMAs per 16x16x4 step. In the mixed path
 // (CT = float) operands are rounded to FP32 when staged, each 16-deep k slab
-// is accumulated by FP32 MFMA and then added into FP64 registers.
+// is accumulated by FP32 MFMA and then added into FP64 registers. chan_apply
+// additionally works in correction form there: it stages X_a - 1 (formed in
+// FP64 before rounding; ||X_a - 1|| is the small channel exponent) and adds
+// the FP64 input back in the epilogue, E M = M + (E - 1) M, so the FP32
+// rounding only touches the increment.
 #include "common.h"
 #include "kernels.h"
 
@@ -93,26 +97,52 @@ zgemm_kernel(GemmArgs g) {
   bool do_mul = true;
   if (g.mode == GEMM_SQUARE_OR_COPY) do_mul = g.pred[z1 * g.pred_s1 + z2 * g.pred_s2] > g.pred_thresh;
 
+  constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+  double2 ra[EA], rb[EB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      int m, k;
+      double2 v = make_double2(0.0, 0.0);
+      if (g.opA == 0) { k = idx % BK; m = idx / BK; if (m0 + m < g.M && k0 + k < g.K) v = A[(long long)(m0 + m) * g.A.ld + k0 + k]; }
+      else { m = idx % BM; k = idx / BM; if (m0 + m < g.M && k0 + k < g.K) { v = A[(long long)(k0 + k) * g.A.ld + m0 + m]; v.y = -v.y; } }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      int n, k;
+      double2 v = make_double2(0.0, 0.0);
+      if (g.opB == 0) { n = idx % BN; k = idx / BN; if (n0 + n < g.N && k0 + k < g.K) v = B[(long long)(k0 + k) * g.B.ld + n0 + n]; }
+      else { k = idx % BK; n = idx / BK; if (n0 + n < g.N && k0 + k < g.K) { v = B[(long long)(n0 + n) * g.B.ld + k0 + k]; v.y = -v.y; } }
+      rb[e] = v;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      int m, k;
+      if (g.opA == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+      As[k * BM + m] = to_ct<CT>(ra[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      int n, k;
+      if (g.opB == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
+      Bs[k * BN + n] = to_ct<CT>(rb[e]);
+    }
+  };
   Acc<double, WTM, WTN> acc;
   acc.zero();
   if (do_mul) {
+    fetch(0);
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-      // stage A tile as As[k][m]
-      for (int idx = tid; idx < BM * BK; idx += NT) {
-        int m, k;
-        double2 v = make_double2(0.0, 0.0);
-        if (g.opA == 0) { k = idx % BK; m = idx / BK; if (m0 + m < g.M && k0 + k < g.K) v = A[(long long)(m0 + m) * g.A.ld + k0 + k]; }
-        else { m = idx % BM; k = idx / BM; if (m0 + m < g.M && k0 + k < g.K) { v = A[(long long)(k0 + k) * g.A.ld + m0 + m]; v.y = -v.y; } }
-        As[k * BM + m] = to_ct<CT>(v);
-      }
-      for (int idx = tid; idx < BN * BK; idx += NT) {
-        int n, k;
-        double2 v = make_double2(0.0, 0.0);
-        if (g.opB == 0) { n = idx % BN; k = idx / BN; if (n0 + n < g.N && k0 + k < g.K) v = B[(long long)(k0 + k) * g.B.ld + n0 + n]; }
-        else { k = idx % BK; n = idx / BK; if (n0 + n < g.N && k0 + k < g.K) { v = B[(long long)(n0 + n) * g.B.ld + k0 + k]; v.y = -v.y; } }
-        Bs[k * BN + n] = to_ct<CT>(v);
-      }
+      stage();
       __syncthreads();
+      if (k0 + BK < g.K) fetch(k0 + BK);
       if constexpr (sizeof(CT) == 8) {
         mma_slab<double, WTM, WTN>((const double2*)As, BM, (const double2*)Bs, BN, wm0, wn0, lane, acc);
       } else {
@@ -168,6 +198,7 @@ chan_apply_kernel(ChanArgs c) {
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
+  constexpr bool CORR = sizeof(CT) == 4;   // correction form in the mixed path
   const int N = c.N;
   const double2* M = c.M + z * c.sM;
   const double2* X[2] = {c.X0 + z * c.sX, c.X1 + z * c.sX};
@@ -186,13 +217,15 @@ chan_apply_kernel(ChanArgs c) {
     return v;
   };
 
-  Acc<double, WTM, WTN> acc[2];
-  acc[0].zero();
-  acc[1].zero();
-  for (int k0 = 0; k0 < N; k0 += BK) {
-    if (LEFT) {
-      // A_a = X_a rows m0.., cols k ; B_a = R_a[k][n] = sum_b conj(U_ba) M[bN+k][n]
-      for (int idx = tid; idx < BM * BK; idx += NT) {
+  // Staging with register prefetch: the global loads of slab k0+BK are in flight
+  // while slab k0 is multiplied out of LDS.
+  constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+  double2 ra[EA][2], rb[EB][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      if (LEFT) {
         int m, k;
         if (c.opX == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
 #pragma unroll
@@ -201,43 +234,30 @@ chan_apply_kernel(ChanArgs c) {
           if (m0 + m < rows && k0 + k < N) {
             if (c.opX == 0) v = X[a][(long long)(m0 + m) * c.ldX + k0 + k];
             else { v = X[a][(long long)(k0 + k) * c.ldX + m0 + m]; v.y = -v.y; }
+            if (CORR && m0 + m == k0 + k) v.x -= 1.0;
           }
-          As[a][k * BM + m] = to_ct<CT>(v);
+          ra[e][a] = v;
         }
-      }
-      for (int idx = tid; idx < BN * BK; idx += NT) {
-        const int n = idx % BN, k = idx / BN;
-        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
-        if (n0 + n < cols && k0 + k < N) {
-          v0 = mload(k0 + k, n0 + n);
-          v1 = mload(N + k0 + k, n0 + n);
-        }
-        if (ROT) {
-#pragma unroll
-          for (int a = 0; a < 2; ++a) Bs[a][k * BN + n] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
-        } else {
-          Bs[0][k * BN + n] = to_ct<CT>(v0);
-          Bs[1][k * BN + n] = to_ct<CT>(v1);
-        }
-      }
-    } else {
-      // A_a = S_a[m][k] = sum_b M[m][bN+k] U_ba ; B_a = X_a[k][n]
-      for (int idx = tid; idx < BM * BK; idx += NT) {
+      } else {
         const int k = idx % BK, m = idx / BK;
-        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+        ra[e][0] = ra[e][1] = make_double2(0.0, 0.0);
         if (m0 + m < rows && k0 + k < N) {
-          v0 = mload(m0 + m, k0 + k);
-          v1 = mload(m0 + m, N + k0 + k);
-        }
-        if (ROT) {
-#pragma unroll
-          for (int a = 0; a < 2; ++a) As[a][k * BM + m] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
-        } else {
-          As[0][k * BM + m] = to_ct<CT>(v0);
-          As[1][k * BM + m] = to_ct<CT>(v1);
+          ra[e][0] = mload(m0 + m, k0 + k);
+          ra[e][1] = mload(m0 + m, N + k0 + k);
         }
       }
-      for (int idx = tid; idx < BN * BK; idx += NT) {
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      if (LEFT) {
+        const int n = idx % BN, k = idx / BN;
+        rb[e][0] = rb[e][1] = make_double2(0.0, 0.0);
+        if (n0 + n < cols && k0 + k < N) {
+          rb[e][0] = mload(k0 + k, n0 + n);
+          rb[e][1] = mload(N + k0 + k, n0 + n);
+        }
+      } else {
         int n, k;
         if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
 #pragma unroll
@@ -246,12 +266,65 @@ chan_apply_kernel(ChanArgs c) {
           if (n0 + n < cols && k0 + k < N) {
             if (c.opX == 0) v = X[a][(long long)(k0 + k) * c.ldX + n0 + n];
             else { v = X[a][(long long)(n0 + n) * c.ldX + k0 + k]; v.y = -v.y; }
+            if (CORR && n0 + n == k0 + k) v.x -= 1.0;
           }
-          Bs[a][k * BN + n] = to_ct<CT>(v);
+          rb[e][a] = v;
         }
       }
     }
+  };
+  // rotate (conj(U_ba) for LEFT, U_ba for RIGHT) and store to LDS
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      int m, k;
+      if (LEFT) {
+        if (c.opX == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+        As[0][k * BM + m] = to_ct<CT>(ra[e][0]);
+        As[1][k * BM + m] = to_ct<CT>(ra[e][1]);
+      } else {
+        k = idx % BK; m = idx / BK;
+        if (ROT) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            As[a][k * BM + m] = to_ct<CT>(cadd(cmul(u[0][a], ra[e][0]), cmul(u[1][a], ra[e][1])));
+        } else {
+          As[0][k * BM + m] = to_ct<CT>(ra[e][0]);
+          As[1][k * BM + m] = to_ct<CT>(ra[e][1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      int n, k;
+      if (LEFT) {
+        n = idx % BN; k = idx / BN;
+        if (ROT) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            Bs[a][k * BN + n] = to_ct<CT>(cadd(cmul(u[0][a], rb[e][0]), cmul(u[1][a], rb[e][1])));
+        } else {
+          Bs[0][k * BN + n] = to_ct<CT>(rb[e][0]);
+          Bs[1][k * BN + n] = to_ct<CT>(rb[e][1]);
+        }
+      } else {
+        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
+        Bs[0][k * BN + n] = to_ct<CT>(rb[e][0]);
+        Bs[1][k * BN + n] = to_ct<CT>(rb[e][1]);
+      }
+    }
+  };
+
+  Acc<double, WTM, WTN> acc[2];
+  acc[0].zero();
+  acc[1].zero();
+  fetch(0);
+  for (int k0 = 0; k0 < N; k0 += BK) {
+    stage();
     __syncthreads();
+    if (k0 + BK < N) fetch(k0 + BK);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if constexpr (sizeof(CT) == 8) {
@@ -290,11 +363,13 @@ chan_apply_kernel(ChanArgs c) {
             y = v == 0 ? t0 : t1;
           }
           const long long off = LEFT ? (long long)(v * N + i) * c.ldY + j : (long long)i * c.ldY + v * N + j;
+          if (CORR) y = cadd(y, LEFT ? mload(v * N + i, j) : mload(i, v * N + j));
           if (Cadd) {
             const long long offc = LEFT ? (long long)(v * N + i) * c.ldC + j : (long long)i * c.ldC + v * N + j;
             y = cadd(y, Cadd[offc]);
           }
           Y[off] = y;
+          if (c.Y2) c.Y2[z * c.sY + off] = y;
         }
       }
 }

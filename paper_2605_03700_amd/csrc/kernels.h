@@ -34,6 +34,7 @@ struct ChanArgs {
   int one_minus;            // use (1 - M) instead of M
   const double2* Cadd; int ldC; long long sC;   // optional addend
   double2* Y; int ldY; long long sY;
+  double2* Y2;              // optional second copy of the output (same layout as Y)
 };
 
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
@@ -42,8 +43,13 @@ void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mix
 // ---- dense linear algebra (linalg.hip), one matrix per batch entry
 // LU with partial pivoting (pivot=1) or without (pivot=0), in place; ipiv
 // [batch][n]; logdet[batch] = ln det A (complex, principal imaginary part).
+// only_if: optional [batch] predicate (run only where nonzero); restore: optional
+// source copied into A before factorising (fallback after launch_lu_np).
 void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int pivot,
-               int nbatch, hipStream_t s);
+               int nbatch, hipStream_t s, const int* only_if = nullptr, const double2* restore = nullptr);
+// LU without pivoting (ipiv = identity); flag[batch] = 1 if a multiplier exceeds lmax_allowed.
+void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int* flag,
+                  double lmax_allowed, int nbatch, hipStream_t s);
 // X <- X * A^{-1} with A = P^T L U from launch_lu. upper_only: X <- X U^{-1}.
 void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
                    const double2* LU, int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only,

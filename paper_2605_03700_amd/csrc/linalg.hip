@@ -15,168 +15,515 @@
 
 #define LU_NB 16
 #define LU_NT 512
+#define LU_MAXN 288
 
+// One workgroup per matrix, implicit pivoting: rows are never moved in memory;
+// perm[i] is the physical row holding logical row i, so P A = L U with
+// (P A)[i] = A[perm[i]]. Each thread keeps one row of the current 16-wide panel
+// in registers (two barriers per column step: pivot choice and pivot-row
+// broadcast); U12 = L11^{-1} A12 is one load/solve/store per column; the
+// trailing update A22 -= L21 U12 runs on FP64 MFMA with L21 staged in LDS.
+// On exit ipiv[i] = perm[i] and logdet = ln det A.
 __global__ void __launch_bounds__(LU_NT) lu_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
-                                                   int sP, double2* logdet, int pivot) {
-  extern __shared__ double2 P[];          // panel: rows x LU_NB
-  __shared__ double rv[LU_NT / 64];
-  __shared__ int ri[LU_NT / 64];
-  __shared__ int piv_s;
+                                                   int sP, double2* logdet, int pivot, const int* only_if,
+                                                   const double2* restore) {
+  extern __shared__ double2 Ls[];          // panel rows x LU_NB (L11 / L21)
+  __shared__ unsigned long long rk[LU_NT / 64];
+  __shared__ double2 prow[LU_NB], jrow[LU_NB];
+  __shared__ int perm[LU_MAXN];
+  __shared__ double2 diag[LU_MAXN];
+  __shared__ double2 Linv[LU_NB][LU_NB];
+  __shared__ double red2[LU_NT / 64][2];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (only_if && only_if[blockIdx.x] == 0) return;   // fallback launch: nothing to do
   double2* A = Aall + blockIdx.x * sA;
   int* ipiv = ipiv_all + blockIdx.x * sP;
-  double ld_re = 0.0, ld_im = 0.0;   // accumulated in thread 0
+  if (restore) {
+    const double2* Rm = restore + blockIdx.x * sA;
+    for (int idx = tid; idx < n * n; idx += LU_NT) A[(long long)(idx / n) * lda + idx % n] = Rm[(long long)(idx / n) * lda + idx % n];
+    __syncthreads();
+  }
+  int nswap = 0;                     // thread 0
+  for (int i = tid; i < n; i += LU_NT) perm[i] = i;
+  __syncthreads();
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int nb = min(LU_NB, n - k0), rows = n - k0;
-    for (int idx = tid; idx < rows * LU_NB; idx += LU_NT) {
-      const int r = idx / LU_NB, c = idx % LU_NB;
-      P[idx] = c < nb ? A[(long long)(k0 + r) * lda + k0 + c] : make_double2(0.0, 0.0);
+    const int r = tid;                 // logical panel row owned by this thread
+    double2 row[LU_NB];
+    {
+      const int ph = r < rows ? perm[k0 + r] : 0;
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c)
+        row[c] = (r < rows && c < nb) ? A[(long long)ph * lda + k0 + c] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
     for (int j = 0; j < nb; ++j) {
+      double2 rj = row[0];
+#pragma unroll
+      for (int c = 1; c < LU_NB; ++c)
+        if (c == j) rj = row[c];
+      int p = j;
       if (pivot) {
-        double best = -1.0;
-        int bi = j;
-        for (int r = j + tid; r < rows; r += LU_NT) {
-          const double2 v = P[r * LU_NB + j];
-          const double a = fabs(v.x) + fabs(v.y);
-          if (a > best) { best = a; bi = r; }
+        // pivot key: |re|+|im| with its low 12 mantissa bits replaced by the
+        // complemented row index, so one unsigned max picks the largest
+        // magnitude and the first row among (near) ties
+        unsigned long long key = 0ull;
+        if (r >= j && r < rows) {
+          const double a = fabs(rj.x) + fabs(rj.y);
+          key = ((unsigned long long)__double_as_longlong(a) & ~0xFFFull) | (unsigned long long)(0xFFF - r);
         }
         for (int o = 32; o > 0; o >>= 1) {
-          const double ob = __shfl_xor(best, o, 64);
-          const int oi = __shfl_xor(bi, o, 64);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+          const unsigned long long ok = __shfl_xor(key, o, 64);
+          key = ok > key ? ok : key;
         }
-        if (lane == 0) { rv[wid] = best; ri[wid] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-          double b = rv[0];
-          int i = ri[0];
-          for (int w = 1; w < LU_NT / 64; ++w)
-            if (rv[w] > b || (rv[w] == b && ri[w] < i)) { b = rv[w]; i = ri[w]; }
-          piv_s = i;
-          ipiv[k0 + j] = k0 + i;
-        }
-        __syncthreads();
-        const int p = piv_s;
-        if (p != j && tid < LU_NB) {
-          const double2 t = P[j * LU_NB + tid];
-          P[j * LU_NB + tid] = P[p * LU_NB + tid];
-          P[p * LU_NB + tid] = t;
-        }
-        if (tid == 0 && p != j) ld_im += M_PI;
-      } else if (tid == 0) {
-        ipiv[k0 + j] = k0 + j;
+        if (lane == 0) rk[wid] = key;
       }
       __syncthreads();
-      const double2 d = P[j * LU_NB + j];
-      if (tid == 0) {
-        ld_re += 0.5 * log(cabs2(d));
-        ld_im += atan2(d.y, d.x);
-      }
-      for (int r = j + 1 + tid; r < rows; r += LU_NT) {
-        const double2 l = cdiv(P[r * LU_NB + j], d);
-        P[r * LU_NB + j] = l;
-        for (int c = j + 1; c < nb; ++c) P[r * LU_NB + c] = csub(P[r * LU_NB + c], cmul(l, P[j * LU_NB + c]));
-      }
-      __syncthreads();
-    }
-    for (int idx = tid; idx < rows * nb; idx += LU_NT) {
-      const int r = idx / nb, c = idx % nb;
-      A[(long long)(k0 + r) * lda + k0 + c] = P[r * LU_NB + c];
-    }
-    // row interchanges outside the panel, then U12 = L11^{-1} A12 (one column per thread)
-    for (int col = tid; col < n; col += LU_NT) {
-      if (col >= k0 && col < k0 + nb) continue;
-      for (int j = 0; j < nb; ++j) {
-        const int p = ipiv[k0 + j];
-        if (p != k0 + j) {
-          const double2 t = A[(long long)(k0 + j) * lda + col];
-          A[(long long)(k0 + j) * lda + col] = A[(long long)p * lda + col];
-          A[(long long)p * lda + col] = t;
-        }
-      }
-      if (col >= k0 + nb) {
-        double2 u[LU_NB];
+      if (pivot) {
+        unsigned long long kv[LU_NT / 64];
 #pragma unroll
-        for (int i = 0; i < LU_NB; ++i) {
-          if (i < nb) {
-            double2 v = A[(long long)(k0 + i) * lda + col];
-            for (int l = 0; l < i; ++l) v = csub(v, cmul(P[i * LU_NB + l], u[l]));
-            u[i] = v;
-            A[(long long)(k0 + i) * lda + col] = v;
+        for (int w = 0; w < LU_NT / 64; ++w) kv[w] = rk[w];
+        unsigned long long best = kv[0];
+#pragma unroll
+        for (int w = 1; w < LU_NT / 64; ++w) best = kv[w] > best ? kv[w] : best;
+        p = 0xFFF - (int)(best & 0xFFFull);
+      }
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) prow[c] = row[c];
+      }
+      if (r == j && p != j) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) jrow[c] = row[c];
+      }
+      if (tid == 0) {
+        if (p != j) {
+          const int t = perm[k0 + j];
+          perm[k0 + j] = perm[k0 + p];
+          perm[k0 + p] = t;
+        }
+        nswap += (p != j);
+      }
+      __syncthreads();
+      if (p != j) {
+        if (r == p) {
+#pragma unroll
+          for (int c = 0; c < LU_NB; ++c) row[c] = jrow[c];
+        } else if (r == j) {
+#pragma unroll
+          for (int c = 0; c < LU_NB; ++c) row[c] = prow[c];
+        }
+      }
+      const double2 d = prow[j];
+      if (r > j && r < rows) {
+        double2 x = row[0];
+#pragma unroll
+        for (int c = 1; c < LU_NB; ++c)
+          if (c == j) x = row[c];
+        const double2 l = cdiv(x, d);
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) {
+          if (c == j) row[c] = l;
+          else if (c > j) row[c] = csub(row[c], cmul(l, prow[c]));
+        }
+      }
+      if (tid == 0) diag[k0 + j] = d;
+    }
+    __syncthreads();
+    if (r < rows) {
+      const int ph = perm[k0 + r];
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) {
+        if (c < nb) A[(long long)ph * lda + k0 + c] = row[c];
+        Ls[r * LU_NB + c] = c < nb ? row[c] : make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    // U12 = L11^{-1} A12: invert the unit lower 16 x 16 block once (16 lanes,
+    // one column each), then one MFMA product per 16-column tile
+    if (wid == 0 && lane < LU_NB) {
+      for (int i = 0; i < LU_NB; ++i) {
+        double2 x = make_double2(i == lane ? 1.0 : 0.0, 0.0);
+        if (i < nb)
+          for (int l = 0; l < i; ++l) x = csub(x, cmul(Ls[i * LU_NB + l], Linv[l][lane]));
+        Linv[i][lane] = x;
+      }
+    }
+    __syncthreads();
+    {
+      const int c_lo = k0 + nb, ncol = n - c_lo;
+      const int ntc = (ncol + 15) / 16;
+      const int il = lane & 15, kl = lane >> 4;
+      for (int tt = wid; tt < ntc; tt += LU_NT / 64) {
+        const int c0 = c_lo + tt * 16;
+        double2 b[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = kk * 4 + kl;
+          b[kk] = (k < nb && c0 + il < n) ? A[(long long)perm[k0 + k] * lda + c0 + il] : make_double2(0.0, 0.0);
+        }
+        d4v ure = Mfma<double>::zero(), uim = Mfma<double>::zero();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double2 a = Linv[il][kk * 4 + kl];
+          ure = Mfma<double>::mma(a.x, b[kk].x, ure);
+          ure = Mfma<double>::mma(-a.y, b[kk].y, ure);
+          uim = Mfma<double>::mma(a.x, b[kk].y, uim);
+          uim = Mfma<double>::mma(a.y, b[kk].x, uim);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = Mfma<double>::row(lane, q), jc = c0 + il;
+          if (i < nb && jc < n) A[(long long)perm[k0 + i] * lda + jc] = make_double2(ure[q], uim[q]);
+        }
+      }
+    }
+    __syncthreads();
+    // trailing update on MFMA, tiles of 16 x 16, K = nb zero-padded to 16; 2 tiles per wave per pass
+    const int t0 = k0 + nb, rem = n - t0;
+    if (rem > 0) {
+      const int nt = (rem + 15) / 16, ntt = nt * nt;
+      const int il = lane & 15, kl = lane >> 4;
+      for (int tb = wid * 2; tb < ntt; tb += (LU_NT / 64) * 2) {
+        d4v cre[2], cim[2];
+        double2 bu[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int t = tb + q;
+          const int r0 = t0 + (t / nt) * 16, c0 = t0 + (t % nt) * 16;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = r0 + Mfma<double>::row(lane, rr), jc = c0 + il;
+            double2 v = make_double2(0.0, 0.0);
+            if (t < ntt && i < n && jc < n) v = A[(long long)perm[i] * lda + jc];
+            cre[q][rr] = v.x;
+            cim[q][rr] = v.y;
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            bu[q][kk] = (t < ntt && k < nb && c0 + il < n) ? A[(long long)perm[k0 + k] * lda + c0 + il]
+                                                          : make_double2(0.0, 0.0);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int t = tb + q;
+          const int r0 = t0 + (t / nt) * 16;
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            const int ar = r0 + il - k0;
+            const double2 a = (t < ntt && k < nb && r0 + il < n) ? Ls[ar * LU_NB + k] : make_double2(0.0, 0.0);
+            const double2 b = bu[q][kk];
+            cre[q] = Mfma<double>::mma(-a.x, b.x, cre[q]);
+            cre[q] = Mfma<double>::mma(a.y, b.y, cre[q]);
+            cim[q] = Mfma<double>::mma(-a.x, b.y, cim[q]);
+            cim[q] = Mfma<double>::mma(-a.y, b.x, cim[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int t = tb + q;
+          if (t >= ntt) continue;
+          const int r0 = t0 + (t / nt) * 16, c0 = t0 + (t % nt) * 16;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = r0 + Mfma<double>::row(lane, rr), jc = c0 + il;
+            if (i < n && jc < n) A[(long long)perm[i] * lda + jc] = make_double2(cre[q][rr], cim[q][rr]);
           }
         }
       }
     }
     __syncthreads();
-    // trailing update on MFMA: tiles of 16 x 16, K = nb (zero padded to 16)
+  }
+  for (int i = tid; i < n; i += LU_NT) ipiv[i] = perm[i];
+  if (logdet) {
+    // ln det = sum ln u_kk + i pi (number of interchanges), summed in parallel
+    double lr = 0.0, li = 0.0;
+    for (int i = tid; i < n; i += LU_NT) {
+      const double2 d = diag[i];
+      lr += 0.5 * log(cabs2(d));
+      li += atan2(d.y, d.x);
+    }
+    for (int o = 32; o > 0; o >>= 1) { lr += __shfl_xor(lr, o, 64); li += __shfl_xor(li, o, 64); }
+    if (lane == 0) { red2[wid][0] = lr; red2[wid][1] = li; }
+    __syncthreads();
+    if (tid == 0) {
+      lr = 0.0; li = nswap * M_PI;
+      for (int w = 0; w < LU_NT / 64; ++w) { lr += red2[w][0]; li += red2[w][1]; }
+      double im = fmod(li, 2.0 * M_PI);
+      if (im > M_PI) im -= 2.0 * M_PI;
+      if (im <= -M_PI) im += 2.0 * M_PI;
+      logdet[blockIdx.x] = make_double2(lr, im);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ LU without pivoting
+// Blocked LU for matrices close to the identity (the Woodbury matrix
+// M = 1 + Delta (1 - G)) and Hermitian positive definite Gram matrices. The
+// 16 x 16 diagonal block is factored by one wave in LDS; L11^{-1} and U11^{-1}
+// turn the panel solves into MFMA products (U12 = L11^{-1} A12,
+// L21 = A21 U11^{-1}), followed by the MFMA trailing update. Threshold test:
+// if a multiplier exceeds lmax_allowed (or a value is not finite) flag[z] = 1
+// and the caller runs the pivoted factorisation on the saved matrix.
+#define NP_NT 256
+#define NP_NB 16
+
+CF_DEV void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+__global__ void __launch_bounds__(NP_NT) lu_np_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
+                                                      int sP, double2* logdet, int* flag_all, double lmax_allowed) {
+  __shared__ double2 D[NP_NB][NP_NB];
+  __shared__ double2 Li[NP_NB][NP_NB], Ui[NP_NB][NP_NB];
+  __shared__ double2 diag[LU_MAXN];
+  __shared__ double red[NP_NT / 64][3];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int il = lane & 15, kl = lane >> 4;
+  double2* A = Aall + blockIdx.x * sA;
+  double lmax = 0.0;
+  for (int k0 = 0; k0 < n; k0 += NP_NB) {
+    const int nb = min(NP_NB, n - k0);
+    {
+      const int r = tid / NP_NB, c = tid % NP_NB;
+      D[r][c] = (r < nb && c < nb) ? A[(long long)(k0 + r) * lda + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    if (wid == 0) {
+      for (int j = 0; j < nb; ++j) {
+        const double2 inv = cdiv(make_double2(1.0, 0.0), D[j][j]);
+        double2 nv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = lane + 64 * q, r = e / NP_NB, c = e % NP_NB;
+          nv[q] = D[r][c];
+          if (r > j) {
+            const double2 l = cmul(D[r][j], inv);
+            if (c == j) nv[q] = l;
+            else if (c > j) nv[q] = csub(nv[q], cmul(l, D[j][c]));
+          }
+        }
+        lds_order();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = lane + 64 * q;
+          D[e / NP_NB][e % NP_NB] = nv[q];
+        }
+        lds_order();
+      }
+    }
+    __syncthreads();
+    // inverses of the unit lower and the upper triangle (one column per lane)
+    if (wid == 0 && lane < NP_NB) {
+      const int t = lane;
+      for (int i = 0; i < NP_NB; ++i) {
+        double2 x = make_double2(i == t ? 1.0 : 0.0, 0.0);
+        if (i < nb)
+          for (int l = 0; l < i; ++l) x = csub(x, cmul(D[i][l], Li[l][t]));
+        Li[i][t] = x;
+      }
+    } else if (wid == 1 && lane < NP_NB) {
+      const int t = lane;
+      for (int i = NP_NB - 1; i >= 0; --i) {
+        double2 x = make_double2(i == t ? 1.0 : 0.0, 0.0);
+        if (i < nb) {
+          for (int l = i + 1; l < NP_NB; ++l) x = csub(x, cmul(D[i][l], Ui[l][t]));
+          x = cdiv(x, D[i][i]);
+        }
+        Ui[i][t] = x;
+      }
+    } else if (wid == 2) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, r = e / NP_NB, c = e % NP_NB;
+        if (r < nb && c < nb) {
+          const double2 v = D[r][c];
+          A[(long long)(k0 + r) * lda + k0 + c] = v;
+          if (r > c) lmax = fmax(lmax, sqrt(cabs2(v)));
+          if (r == c) diag[k0 + r] = v;
+        }
+      }
+    }
+    __syncthreads();
+    // panel solves on MFMA: U12 tiles (columns) and L21 tiles (rows)
     const int t0 = k0 + nb, rem = n - t0;
     if (rem > 0) {
       const int nt = (rem + 15) / 16;
-      const int il = lane & 15, kl = lane >> 4;
-      for (int t = wid; t < nt * nt; t += LU_NT / 64) {
-        const int r0 = t0 + (t / nt) * 16, c0 = t0 + (t % nt) * 16;
-        d4v cre, cim;
+      for (int task = wid; task < 2 * nt; task += NP_NT / 64) {
+        d4v cre = Mfma<double>::zero(), cim = Mfma<double>::zero();
+        const int tt = task % nt, o0 = t0 + tt * 16;
+        if (task < nt) {
+          // U12[:, o0..] = L11^{-1} A12
+          double2 b[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = r0 + Mfma<double>::row(lane, r), j = c0 + il;
-          double2 v = make_double2(0.0, 0.0);
-          if (i < n && j < n) v = A[(long long)i * lda + j];
-          cre[r] = v.x;
-          cim[r] = v.y;
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            b[kk] = (k < nb && o0 + il < n) ? A[(long long)(k0 + k) * lda + o0 + il] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double2 a = Li[il][kk * 4 + kl];
+            cre = Mfma<double>::mma(a.x, b[kk].x, cre);
+            cre = Mfma<double>::mma(-a.y, b[kk].y, cre);
+            cim = Mfma<double>::mma(a.x, b[kk].y, cim);
+            cim = Mfma<double>::mma(a.y, b[kk].x, cim);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = Mfma<double>::row(lane, q), jc = o0 + il;
+            if (i < nb && jc < n) A[(long long)(k0 + i) * lda + jc] = make_double2(cre[q], cim[q]);
+          }
+        } else {
+          // L21[o0.., :] = A21 U11^{-1}
+          double2 a[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            a[kk] = (k < nb && o0 + il < n) ? A[(long long)(o0 + il) * lda + k0 + k] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double2 b = Ui[kk * 4 + kl][il];
+            cre = Mfma<double>::mma(a[kk].x, b.x, cre);
+            cre = Mfma<double>::mma(-a[kk].y, b.y, cre);
+            cim = Mfma<double>::mma(a[kk].x, b.y, cim);
+            cim = Mfma<double>::mma(a[kk].y, b.x, cim);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = o0 + Mfma<double>::row(lane, q), jc = il;
+            if (i < n && jc < nb) {
+              const double2 v = make_double2(cre[q], cim[q]);
+              A[(long long)i * lda + k0 + jc] = v;
+              lmax = fmax(lmax, sqrt(cabs2(v)));
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 U12 on MFMA, 2 tiles per wave per pass
+    if (rem > 0) {
+      const int nt = (rem + 15) / 16, ntt = nt * nt;
+      for (int tb = wid * 2; tb < ntt; tb += (NP_NT / 64) * 2) {
+        d4v cre[2], cim[2];
+        double2 au[2][4], bu[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int t = tb + q;
+          const int r0 = t0 + (t / nt) * 16, c0 = t0 + (t % nt) * 16;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = r0 + Mfma<double>::row(lane, rr), jc = c0 + il;
+            double2 v = make_double2(0.0, 0.0);
+            if (t < ntt && i < n && jc < n) v = A[(long long)i * lda + jc];
+            cre[q][rr] = v.x;
+            cim[q][rr] = v.y;
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            const bool ok = t < ntt && k < nb;
+            au[q][kk] = (ok && r0 + il < n) ? A[(long long)(r0 + il) * lda + k0 + k] : make_double2(0.0, 0.0);
+            bu[q][kk] = (ok && c0 + il < n) ? A[(long long)(k0 + k) * lda + c0 + il] : make_double2(0.0, 0.0);
+          }
         }
 #pragma unroll
-        for (int kk = 0; kk < LU_NB; kk += 4) {
-          const int k = kk + kl;
-          const int ar = r0 + il - k0;           // panel row of L21
-          double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-          if (k < nb && r0 + il < n) a = P[ar * LU_NB + k];
-          if (k < nb && c0 + il < n) b = A[(long long)(k0 + k) * lda + c0 + il];
-          cre = Mfma<double>::mma(-a.x, b.x, cre);
-          cre = Mfma<double>::mma(a.y, b.y, cre);
-          cim = Mfma<double>::mma(-a.x, b.y, cim);
-          cim = Mfma<double>::mma(-a.y, b.x, cim);
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double2 a = au[q][kk], b = bu[q][kk];
+            cre[q] = Mfma<double>::mma(-a.x, b.x, cre[q]);
+            cre[q] = Mfma<double>::mma(a.y, b.y, cre[q]);
+            cim[q] = Mfma<double>::mma(-a.x, b.y, cim[q]);
+            cim[q] = Mfma<double>::mma(-a.y, b.x, cim[q]);
+          }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = r0 + Mfma<double>::row(lane, r), j = c0 + il;
-          if (i < n && j < n) A[(long long)i * lda + j] = make_double2(cre[r], cim[r]);
+        for (int q = 0; q < 2; ++q) {
+          const int t = tb + q;
+          if (t >= ntt) continue;
+          const int r0 = t0 + (t / nt) * 16, c0 = t0 + (t % nt) * 16;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int i = r0 + Mfma<double>::row(lane, rr), jc = c0 + il;
+            if (i < n && jc < n) A[(long long)i * lda + jc] = make_double2(cre[q][rr], cim[q][rr]);
+          }
         }
       }
     }
     __syncthreads();
   }
-  if (tid == 0 && logdet) {
-    double im = fmod(ld_im, 2.0 * M_PI);
-    if (im > M_PI) im -= 2.0 * M_PI;
-    if (im <= -M_PI) im += 2.0 * M_PI;
-    logdet[blockIdx.x] = make_double2(ld_re, im);
+  for (int i = tid; i < n; i += NP_NT) ipiv_all[blockIdx.x * sP + i] = i;
+  // ln det and the threshold test
+  double lr = 0.0, li = 0.0;
+  for (int i = tid; i < n; i += NP_NT) {
+    const double2 d = diag[i];
+    lr += 0.5 * log(cabs2(d));
+    li += atan2(d.y, d.x);
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    lr += __shfl_xor(lr, o, 64);
+    li += __shfl_xor(li, o, 64);
+    lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
+  }
+  if (lane == 0) { red[wid][0] = lr; red[wid][1] = li; red[wid][2] = lmax; }
+  __syncthreads();
+  if (tid == 0) {
+    lr = 0.0; li = 0.0; lmax = 0.0;
+    for (int w = 0; w < NP_NT / 64; ++w) { lr += red[w][0]; li += red[w][1]; lmax = fmax(lmax, red[w][2]); }
+    const bool bad = !(lmax <= lmax_allowed) || !isfinite(lr);
+    if (flag_all) flag_all[blockIdx.x] = bad ? 1 : 0;
+    if (logdet) {
+      double im = fmod(li, 2.0 * M_PI);
+      if (im > M_PI) im -= 2.0 * M_PI;
+      if (im <= -M_PI) im += 2.0 * M_PI;
+      logdet[blockIdx.x] = make_double2(lr, im);
+    }
+  }
+}
+
+void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int* flag,
+                  double lmax_allowed, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(lu_np_kernel, dim3(nbatch), dim3(NP_NT), 0, s, A, n, lda, sA, ipiv, sP, logdet, flag,
+                     lmax_allowed); cfqmc_post_launch("lu_np_kernel");
+}
+
+// Allow more than 64 KB of dynamic LDS (gfx950 has 160 KB per workgroup); returns false if refused.
+static bool set_lds_limit(const void* fn, size_t shm) {
+  if (shm <= 65536 - 24 * 1024) return true;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  (void)hipGetLastError();
+  return e == hipSuccess;
 }
 
 void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int pivot,
-               int nbatch, hipStream_t s) {
+               int nbatch, hipStream_t s, const int* only_if, const double2* restore) {
   const size_t shm = (size_t)n * LU_NB * sizeof(double2);
-  if (shm > 65536) {
-    (void)hipFuncSetAttribute((const void*)lu_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    (void)hipGetLastError();
-  }
-  hipLaunchKernelGGL(lu_kernel, dim3(nbatch), dim3(LU_NT), shm, s, A, n, lda, sA, ipiv, sP, logdet, pivot); cfqmc_post_launch("lu_kernel");
+  if (!set_lds_limit((const void*)lu_kernel, shm)) fprintf(stderr, "[cfqmc] LU: %zu B of LDS refused\n", shm);
+  hipLaunchKernelGGL(lu_kernel, dim3(nbatch), dim3(LU_NT), shm, s, A, n, lda, sA, ipiv, sP, logdet, pivot, only_if,
+                     restore); cfqmc_post_launch("lu_kernel");
 }
 
 // ------------------------------------------------------------------ right solve
-// Y = X A^{-1}, A = P_0..P_{n-1} L U: Y = ((X U^{-1}) L^{-1}) P_{n-1} ... P_0.
-// A workgroup owns RS_ROWS rows of X in LDS; columns are eliminated one at a
-// time with a right-looking row update (rows of U and L are read contiguously).
-#define RS_ROWS 8
+// Y = X A^{-1} with P A = L U, (P A)[i] = A[perm[i]] (lu_kernel): Y = X U^{-1} L^{-1} P,
+// i.e. W = X U^{-1} L^{-1} and Y[:, perm[i]] = W[:, i]. Row k of the factors is
+// physical row perm[k]. A workgroup owns 16 rows of X in LDS and eliminates
+// 16-column blocks: the coupling to the solved blocks is one MFMA product (K
+// split over 4 waves, operands prefetched into registers), the 16 x 16 diagonal
+// block is solved wave-synchronously with shuffles.
+#define RS_ROWS 16
 #define RS_NT 256
+#define RS_MAXIT 18
 
 __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
                                                        int ldy, long long sY, const double2* LUall, int ldlu,
                                                        long long sLU, const int* ipiv_all, int sP, int n,
                                                        int upper_only) {
-  extern __shared__ double2 Ys[];          // RS_ROWS x n
+  extern __shared__ double2 Zs[];          // 16 x n row block
+  __shared__ double2 red[4][16][16];
+  __shared__ double2 Db[16][16];           // diagonal block of U or L
+  __shared__ int perm[LU_MAXN];
   const int z = blockIdx.y;
   const double2* X = Xall + z * sX;
   double2* Yo = Yall + z * sY;
@@ -184,48 +531,125 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
   const int* ipiv = ipiv_all + z * sP;
   const int r0 = blockIdx.x * RS_ROWS;
   const int nr = min(RS_ROWS, n - r0);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int il = lane & 15, kl = lane >> 4;
+  // thread layout of the block solve: row rr = wid*4 + lane/16, column cc = lane%16
+  const int rr = wid * 4 + (lane >> 4), cc = lane & 15;
+  for (int i = tid; i < n; i += RS_NT) perm[i] = upper_only ? i : ipiv[i];
   for (int idx = tid; idx < RS_ROWS * n; idx += RS_NT) {
     const int r = idx / n, c = idx % n;
-    Ys[idx] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
+    Zs[idx] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int nJ = (n + 15) / 16;
+  for (int phase = 0; phase < (upper_only ? 1 : 2); ++phase) {
+    for (int jj = 0; jj < nJ; ++jj) {
+      const int J = phase == 0 ? jj : nJ - 1 - jj;
+      const int c0 = 16 * J, bw = min(16, n - c0);
+      // coupling: acc[r][c] = sum_k Z[r][k] T[k][c0+c] over the solved columns k
+      const int klo = phase == 0 ? 0 : c0 + 16, khi = phase == 0 ? c0 : n;
+      double2 bb[RS_MAXIT];
+#pragma unroll
+      for (int it = 0; it < RS_MAXIT; ++it) {
+        const int k = klo + wid * 4 + it * 16 + kl;
+        bb[it] = (k < khi && il < bw) ? LU[(long long)perm[k] * ldlu + c0 + il] : make_double2(0.0, 0.0);
+      }
+      d4v are = Mfma<double>::zero(), aim = Mfma<double>::zero();
+#pragma unroll
+      for (int it = 0; it < RS_MAXIT; ++it) {
+        const int k = klo + wid * 4 + it * 16 + kl;
+        if (klo + wid * 4 + it * 16 < khi) {
+          const double2 a = k < khi ? Zs[il * n + k] : make_double2(0.0, 0.0);
+          const double2 b = bb[it];
+          are = Mfma<double>::mma(a.x, b.x, are);
+          are = Mfma<double>::mma(-a.y, b.y, are);
+          aim = Mfma<double>::mma(a.x, b.y, aim);
+          aim = Mfma<double>::mma(a.y, b.x, aim);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wid][Mfma<double>::row(lane, q)][il] = make_double2(are[q], aim[q]);
+      Db[rr][cc] = (rr < bw && cc < bw) ? LU[(long long)perm[c0 + rr] * ldlu + c0 + cc]
+                                        : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+      __syncthreads();
+      double2 y = Zs[rr * n + c0 + min(cc, bw - 1)];
+      for (int w = 0; w < 4; ++w) y = csub(y, red[w][rr][cc]);
+      if (phase == 0) {
+        // z U_JJ = y, columns ascending
+        for (int cp = 0; cp < 16; ++cp) {
+          double2 zv = cdiv(y, Db[cp][cp]);
+          zv.x = __shfl(zv.x, (lane & ~15) + cp, 64);
+          zv.y = __shfl(zv.y, (lane & ~15) + cp, 64);
+          if (cc == cp) y = zv;
+          else if (cc > cp) y = csub(y, cmul(zv, Db[cp][cc]));
+        }
+      } else {
+        // w L_JJ = y with unit diagonal, columns descending
+        for (int cp = 15; cp >= 0; --cp) {
+          double2 wv;
+          wv.x = __shfl(y.x, (lane & ~15) + cp, 64);
+          wv.y = __shfl(y.y, (lane & ~15) + cp, 64);
+          if (cc < cp) y = csub(y, cmul(wv, Db[cp][cc]));
+        }
+      }
+      __syncthreads();
+      if (cc < bw) Zs[rr * n + c0 + cc] = y;
+      __syncthreads();
+    }
+  }
+  for (int idx = tid; idx < nr * n; idx += RS_NT) {
+    const int r = idx / n, c = idx % n;
+    Yo[(long long)(r0 + r) * ldy + perm[c]] = Zs[r * n + c];
+  }
+}
+
+// Fallback when the large-LDS configuration is refused: one column at a time.
+#define RSS_ROWS 8
+#define RSS_NT 256
+
+__global__ void __launch_bounds__(RSS_NT) rsolve_simple_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
+                                                       int ldy, long long sY, const double2* LUall, int ldlu,
+                                                       long long sLU, const int* ipiv_all, int sP, int n,
+                                                       int upper_only) {
+  extern __shared__ double2 Ysm[];          // RSS_ROWS x n
+  const int z = blockIdx.y;
+  const double2* X = Xall + z * sX;
+  double2* Yo = Yall + z * sY;
+  const double2* LU = LUall + z * sLU;
+  const int* ipiv = ipiv_all + z * sP;
+  const int r0 = blockIdx.x * RSS_ROWS;
+  const int nr = min(RSS_ROWS, n - r0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < RSS_ROWS * n; idx += RSS_NT) {
+    const int r = idx / n, c = idx % n;
+    Ysm[idx] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   // z U = x, columns ascending
   for (int j = 0; j < n; ++j) {
-    const double2 d = LU[(long long)j * ldlu + j];
-    if (tid < RS_ROWS) Ys[tid * n + j] = cdiv(Ys[tid * n + j], d);
+    const double2 d = LU[(long long)(upper_only ? j : ipiv[j]) * ldlu + j];
+    if (tid < RSS_ROWS) Ysm[tid * n + j] = cdiv(Ysm[tid * n + j], d);
     __syncthreads();
     const int w = n - j - 1;
-    for (int idx = tid; idx < RS_ROWS * w; idx += RS_NT) {
+    for (int idx = tid; idx < RSS_ROWS * w; idx += RSS_NT) {
       const int r = idx / w, c = j + 1 + idx % w;
-      Ys[r * n + c] = csub(Ys[r * n + c], cmul(Ys[r * n + j], LU[(long long)j * ldlu + c]));
+      Ysm[r * n + c] = csub(Ysm[r * n + c], cmul(Ysm[r * n + j], LU[(long long)(upper_only ? j : ipiv[j]) * ldlu + c]));
     }
     __syncthreads();
   }
   if (!upper_only) {
     // w L = z (unit lower), columns descending
     for (int j = n - 1; j > 0; --j) {
-      for (int idx = tid; idx < RS_ROWS * j; idx += RS_NT) {
+      for (int idx = tid; idx < RSS_ROWS * j; idx += RSS_NT) {
         const int r = idx / j, c = idx % j;
-        Ys[r * n + c] = csub(Ys[r * n + c], cmul(Ys[r * n + j], LU[(long long)j * ldlu + c]));
+        Ysm[r * n + c] = csub(Ysm[r * n + c], cmul(Ysm[r * n + j], LU[(long long)ipiv[j] * ldlu + c]));
       }
       __syncthreads();
     }
-    if (tid < RS_ROWS) {
-      for (int k = n - 1; k >= 0; --k) {
-        const int p = ipiv[k];
-        if (p != k) {
-          const double2 t = Ys[tid * n + k];
-          Ys[tid * n + k] = Ys[tid * n + p];
-          Ys[tid * n + p] = t;
-        }
-      }
-    }
-    __syncthreads();
   }
-  for (int idx = tid; idx < nr * n; idx += RS_NT) {
+  for (int idx = tid; idx < nr * n; idx += RSS_NT) {
     const int r = idx / n, c = idx % n;
-    Yo[(long long)(r0 + r) * ldy + c] = Ys[r * n + c];
+    Yo[(long long)(r0 + r) * ldy + (upper_only ? c : ipiv[c])] = Ysm[r * n + c];
   }
 }
 
@@ -234,6 +658,12 @@ void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy,
                    hipStream_t s) {
   dim3 grid((n + RS_ROWS - 1) / RS_ROWS, nbatch);
   const size_t shm = (size_t)RS_ROWS * n * sizeof(double2);
+  if (!set_lds_limit((const void*)rsolve_kernel, shm)) {
+    dim3 g2((n + RSS_ROWS - 1) / RSS_ROWS, nbatch);
+    hipLaunchKernelGGL(rsolve_simple_kernel, g2, dim3(RSS_NT), (size_t)RSS_ROWS * n * sizeof(double2), s, X, ldx, sX,
+                       Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n, upper_only); cfqmc_post_launch("rsolve_simple_kernel");
+    return;
+  }
   hipLaunchKernelGGL(rsolve_kernel, grid, dim3(RS_NT), shm, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n,
                      upper_only); cfqmc_post_launch("rsolve_kernel");
 }
@@ -282,20 +712,25 @@ void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ld
 
 __global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long long sX, double* out) {
   __shared__ double red[4];
-  const int z = blockIdx.x;
+  const int z = blockIdx.y;
   double m = 0.0;
-  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
     const double2 a = X[z * sX + idx], b = Y[z * sX + idx];
     m = fmax(m, sqrt(cabs2(csub(a, b))));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) out[z] = fmax(out[z], fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    // non-negative doubles order like their bit patterns
+    atomicMax((unsigned long long*)&out[z], (unsigned long long)__double_as_longlong(m));
+  }
 }
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
                     hipStream_t s) {
-  hipLaunchKernelGGL(maxdiff_kernel, dim3(nbatch), dim3(256), 0, s, X, Y, n, sX, out); cfqmc_post_launch("maxdiff_kernel");
+  dim3 grid(min((n * n + 1023) / 1024, 64), nbatch);
+  hipLaunchKernelGGL(maxdiff_kernel, grid, dim3(256), 0, s, X, Y, n, sX, out); cfqmc_post_launch("maxdiff_kernel");
 }
 
 // ------------------------------------------------------------------ UDT helpers

@@ -53,34 +53,54 @@ CF_DEV double rng_uniform(uint64_t seed, int chain, long long counter) {
 }
 
 // ------------------------------------------------------------------ build_h
-__global__ void build_h_kernel(ModelDev m, const double* phi_all, long long sphi, double2* h_all, long long sh) {
-  const int z = blockIdx.z, ch = blockIdx.y, N = m.N;
+// One workgroup per (shift d, channel, batch entry): the terms whose matrix
+// has its nonzeros on the diagonal col = row - d (mod N) are staged in LDS with
+// their field weights, each thread then sums them for one row.
+#define BH_NT 256
+__global__ void __launch_bounds__(BH_NT) build_h_kernel(ModelDev m, const double* phi_all, long long sphi,
+                                                         double2* h_all, long long sh) {
+  __shared__ double s_wr[BH_NT], s_wi[BH_NT], s_f[BH_NT];
+  __shared__ int s_qx[BH_NT], s_qy[BH_NT], s_dag[BH_NT];
+  const int d = blockIdx.x, ch = blockIdx.y, z = blockIdx.z, N = m.N;
   const double* phi = phi_all + z * sphi + ch * m.nq;
   double2* h = h_all + z * sh + (long long)ch * N * N;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
-    const int r = idx / N, col = idx % N;
-    const int d = ((r - col) % N + N) % N;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int t = m.hoff[d]; t < m.hoff[d + 1]; ++t) {
-      const double wr = m.h_scale[t] * phi[m.h_cre[t]];
-      const double wi = m.h_cim[t] >= 0 ? m.h_scale[t] * m.h_sgn[t] * phi[m.h_cim[t]] : 0.0;
-      const int qx = m.h_qx[t], qy = m.h_qy[t];
-      const int row = m.h_dag[t] ? col : r;       // orbital whose phase enters
-      int mm = ((2 * (row + 1) - qy) * qx) % (2 * N);
-      if (mm < 0) mm += 2 * N;
-      double2 ph = m.phase[mm];
-      if (m.h_dag[t]) ph.y = -ph.y;
-      const double f = m.h_F[t];
-      acc.x += f * (wr * ph.x - wi * ph.y);
-      acc.y += f * (wr * ph.y + wi * ph.x);
+  const int r = threadIdx.x;
+  const int col = ((r - d) % N + N) % N;
+  double2 acc = make_double2(0.0, 0.0);
+  const int tb = m.hoff[d], te = m.hoff[d + 1];
+  for (int c0 = tb; c0 < te; c0 += BH_NT) {
+    const int t = c0 + threadIdx.x;
+    if (t < te) {
+      s_wr[threadIdx.x] = m.h_scale[t] * phi[m.h_cre[t]];
+      s_wi[threadIdx.x] = m.h_cim[t] >= 0 ? m.h_scale[t] * m.h_sgn[t] * phi[m.h_cim[t]] : 0.0;
+      s_f[threadIdx.x] = m.h_F[t];
+      s_qx[threadIdx.x] = m.h_qx[t];
+      s_qy[threadIdx.x] = m.h_qy[t];
+      s_dag[threadIdx.x] = m.h_dag[t];
     }
-    h[idx] = acc;
+    __syncthreads();
+    const int cnt = min(BH_NT, te - c0);
+    if (r < N) {
+      for (int k = 0; k < cnt; ++k) {
+        const int qx = s_qx[k], qy = s_qy[k];
+        const int row = s_dag[k] ? col : r;        // orbital whose phase enters
+        int mm = ((2 * (row + 1) - qy) * qx) % (2 * N);
+        if (mm < 0) mm += 2 * N;
+        double2 ph = m.phase[mm];
+        if (s_dag[k]) ph.y = -ph.y;
+        const double f = s_f[k], wr = s_wr[k], wi = s_wi[k];
+        acc.x += f * (wr * ph.x - wi * ph.y);
+        acc.y += f * (wr * ph.y + wi * ph.x);
+      }
+    }
+    __syncthreads();
   }
+  if (r < N) h[(long long)r * N + col] = acc;
 }
 void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double2* h, long long sh, int nbatch,
                     hipStream_t s) {
-  dim3 grid(min((m.N * m.N + 255) / 256, 64), 4, nbatch);
-  hipLaunchKernelGGL(build_h_kernel, grid, dim3(256), 0, s, m, phi, sphi, h, sh); cfqmc_post_launch("build_h_kernel");
+  dim3 grid(m.N, 4, nbatch);
+  hipLaunchKernelGGL(build_h_kernel, grid, dim3(BH_NT), 0, s, m, phi, sphi, h, sh); cfqmc_post_launch("build_h_kernel");
 }
 
 // ------------------------------------------------------------------ exponential helpers
@@ -95,6 +115,7 @@ __global__ void exp_coef_kernel(const double2* X2all, const double2* X3all, int 
   double n2 = 0.0, n3 = 0.0;
   for (int c = threadIdx.x; c < N; c += blockDim.x) {
     double s2 = 0.0, s3 = 0.0;
+#pragma unroll 8
     for (int i = 0; i < N; ++i) {
       s2 += sqrt(cabs2(X2[(long long)i * N + c]));
       s3 += sqrt(cabs2(X3[(long long)i * N + c]));
@@ -286,16 +307,21 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
     last = (prev == (unsigned)a.nblk - 1) ? 1u : 0u;
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
+  if (last) {
     __threadfence();
     double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0, s_r = 0.0;
     const volatile double* pp = a.part + (long long)z * a.nblk * 4;
-    for (int b = 0; b < a.nblk; ++b) {
+    for (int b = threadIdx.x; b < a.nblk; b += DR_NT) {
       s_norm += pp[b * 4 + 0];
       s_eta += pp[b * 4 + 1];
       s_bg += pp[b * 4 + 2];
       s_r += pp[b * 4 + 3];
     }
+    s_norm = block_sum<DR_NT>(s_norm, red);
+    s_eta = block_sum<DR_NT>(s_eta, red);
+    s_bg = block_sum<DR_NT>(s_bg, red);
+    s_r = block_sum<DR_NT>(s_r, red);
+    if (threadIdx.x != 0) return;
     const double2 ldm = a.lndetM[z];
     const double2 al0 = a.alpha[z * 4 + 0];
     // ln R = 2 ln det M + (c' - c); real for the sign-free model, the phase is monitored

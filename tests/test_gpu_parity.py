@@ -92,7 +92,8 @@ def _replay_compare(CFQMC, n_phi, L, nstab, mode, qmax, u_list, precision, n_swe
     for k in range(nch):
         m = models[k]
         assert abs(eps[k] - chains[k].eps) < 1e-12
-        assert np.abs(g.get_fields()[k] - chains[k].phi).max() < 1e-10
+        # fields differ only through the drift computed from the (mixed) G frames
+        assert np.abs(g.get_fields()[k] - chains[k].phi).max() < max(1e-10, 1e-2 * tol_g)
         G = g.measure_G(k, L)[:2 * n_phi, :2 * n_phi]
         assert rel(G, dqmc.green(m, chains[k].phi, L)) < tol_g
         ld, ldr = g.logdet(k), dqmc.logdet(m, chains[k].phi)
