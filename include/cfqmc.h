@@ -151,6 +151,21 @@ int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable);
  * real flops of one launch (16 N^2 n per chain). Synchronises. */
 int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch);
 
+/* Heterogeneous batch: groups of chains with different shapes (N_phi, L_tau,
+ * q-set, couplings), one context per group on its own HIP stream (default
+ * priority). A batch sweep interleaves the slice steps of all groups on the
+ * host so the groups' kernels run concurrently on the GPU. Contexts stay
+ * owned by the batch; cfqmc_batch_context gives a view for measure_G,
+ * logdet, init_fields and the other per-context calls. */
+typedef struct cfqmc_batch cfqmc_batch;
+int cfqmc_batch_create(const cfqmc_params* groups, int32_t n_groups, cfqmc_batch** out);
+int cfqmc_batch_context(cfqmc_batch* b, int32_t group, cfqmc_ctx** ctx);
+/* n_sweeps per group (equal_time = 0), or scaled by L_max / L_group so every
+ * group runs the same number of slice steps (equal_time = 1). stats: NULL or
+ * [total chains], group-major. Synchronises. */
+int cfqmc_batch_sweep(cfqmc_batch* b, int32_t n_sweeps, int32_t equal_time, cfqmc_stats* stats);
+int cfqmc_batch_destroy(cfqmc_batch* b);
+
 const char* cfqmc_last_error(const cfqmc_ctx* c);
 
 #ifdef __cplusplus

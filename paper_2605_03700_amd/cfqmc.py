@@ -47,7 +47,8 @@ _lib = None
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
            "cfqmc_get_fields", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
-           "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read"]
+           "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
+           "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy"]
 
 
 def load():
@@ -79,6 +80,10 @@ def load():
     lib.cfqmc_kernel_timing.argtypes = [P, ctypes.c_int32]
     lib.cfqmc_kernel_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_double)]
+    lib.cfqmc_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(P)]
+    lib.cfqmc_batch_context.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.cfqmc_batch_sweep.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
+    lib.cfqmc_batch_destroy.argtypes = [P]
     lib.cfqmc_last_error.argtypes = [P]
     lib.cfqmc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -92,15 +97,48 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
+def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
+                q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
+                eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1):
+    """Fill a Params structure; returns (params, keep-alive arrays)."""
+    lib = load()
+    p = Params()
+    lib.cfqmc_default_params(ctypes.byref(p))
+    p.n_phi, p.l_tau, p.dtau = n_phi, l_tau, dtau
+    p.u0, p.uk, p.un = u0, uk, un
+    p.q_mode, p.q_max = q_mode, q_max
+    keep = []
+    if q_list is not None:
+        ql = np.ascontiguousarray(np.asarray(q_list, dtype=np.int32).reshape(-1))
+        keep.append(ql)
+        p.q_list = ql.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        p.n_q_list = ql.size // 2
+    p.n_stab, p.precision = n_stab, precision
+    p.eps0, p.r0, p.deps, p.eps_min, p.eps_max = eps0, r0, deps, eps_min, eps_max
+    p.adapt_eps, p.seed, p.n_chains = int(bool(adapt_eps)), seed, n_chains
+    if chain_u is not None:
+        cu = np.ascontiguousarray(np.asarray(chain_u, dtype=np.float64).reshape(n_chains, 3))
+        keep.append(cu)
+        p.chain_u = cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
+    return p, keep
+
+
 class CFQMC:
     """One context of the C ABI: n_chains chains of one lattice shape."""
 
     def __init__(self, n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                  q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                  eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
-                 tile_cfg=-1, stream=None):
+                 tile_cfg=-1, stream=None, _handle=None):
         lib = load()
         self.lib = lib
+        if _handle is not None:          # view of a context owned by a batch
+            self.h = _handle
+            self._owned = False
+            self._init_sizes(n_phi, l_tau)
+            return
+        self._owned = True
         p = Params()
         lib.cfqmc_default_params(ctypes.byref(p))
         p.n_phi, p.l_tau, p.dtau = n_phi, l_tau, dtau
@@ -128,8 +166,11 @@ class CFQMC:
         h = ctypes.c_void_p()
         self._check(lib.cfqmc_create(ctypes.byref(p), ctypes.c_void_p(stream), ctypes.byref(h)), None)
         self.h = h
+        self._init_sizes(n_phi, l_tau)
+
+    def _init_sizes(self, n_phi, l_tau):
         nq, nc, d4 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        lib.cfqmc_sizes(h, ctypes.byref(nq), ctypes.byref(nc), ctypes.byref(d4))
+        self.lib.cfqmc_sizes(self.h, ctypes.byref(nq), ctypes.byref(nc), ctypes.byref(d4))
         self.n_q, self.n_chains, self.dim_g4n = nq.value, nc.value, d4.value
         self.n_phi, self.l_tau = n_phi, l_tau
 
@@ -215,8 +256,58 @@ class CFQMC:
         return a.value, k.value, f.value
 
     def close(self):
-        if getattr(self, "h", None) is not None:
+        if getattr(self, "h", None) is not None and getattr(self, "_owned", True):
             self.lib.cfqmc_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Heterogeneous batch: one context per group of chains, each on its own stream."""
+
+    def __init__(self, groups):
+        """groups: list of dicts of CFQMC keyword arguments (n_phi, l_tau, n_chains, chain_u, ...)."""
+        lib = load()
+        self.lib = lib
+        arr = (Params * len(groups))()
+        keep = []
+        for k, kw in enumerate(groups):
+            p, kp = make_params(**kw)
+            arr[k] = p
+            keep.extend(kp)
+        h = ctypes.c_void_p()
+        rc = lib.cfqmc_batch_create(arr, len(groups), ctypes.byref(h))
+        if rc != 0:
+            raise RuntimeError("cfqmc_batch_create failed: %s" % ERRORS.get(rc, rc))
+        self.h = h
+        self.groups = []
+        for k, kw in enumerate(groups):
+            c = ctypes.c_void_p()
+            lib.cfqmc_batch_context(h, k, ctypes.byref(c))
+            self.groups.append(CFQMC(n_phi=kw.get("n_phi", 6), l_tau=kw.get("l_tau", 40), _handle=c))
+        self.n_chains = sum(g.n_chains for g in self.groups)
+
+    def init_fields(self):
+        for g in self.groups:
+            g.init_fields(None)
+
+    def sweep(self, n_sweeps=1, equal_time=False):
+        st = (Stats * self.n_chains)()
+        rc = self.lib.cfqmc_batch_sweep(self.h, n_sweeps, int(bool(equal_time)), ctypes.cast(st, ctypes.c_void_p))
+        if rc != 0:
+            raise RuntimeError("cfqmc_batch_sweep failed: %s" % ERRORS.get(rc, rc))
+        return [s.as_dict() for s in st]
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            for g in self.groups:
+                g.h = None
+            self.lib.cfqmc_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -864,33 +864,37 @@ int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out) {
   return CFQMC_OK;
 }
 
-int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stats* stats) {
-  if (!c || n_sweeps < 0) return CFQMC_EINVAL;
-  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
-  const int B = c->nch, L = c->L, W = 4 * c->nq + 1;
-  HIPCHK(hipMemsetAsync(c->stat, 0, B * 8 * sizeof(double), c->s));
-  HIPCHK(hipMemsetAsync(c->stab_err, 0, B * sizeof(double), c->s));
-  for (int sw = 0; sw < n_sweeps; ++sw) {
-    if (replay) {
-      HIPCHK(hipMemcpy2DAsync(c->noise, (size_t)L * W * sizeof(double), replay + (size_t)sw * L * W,
-                              (size_t)n_sweeps * L * W * sizeof(double), (size_t)L * W * sizeof(double), B,
-                              hipMemcpyHostToDevice, c->s));
-    }
-    for (int t = 0; t < L; ++t) {
-      slice_step(c, t, replay ? c->noise : nullptr);
-      if ((t + 1) % c->nstab == 0 || t == L - 1) block_end(c, t / c->nstab);
-    }
-    launch_eps_update(c->eps, c->acc_count, L, c->p.r0, c->p.deps, c->p.eps_min, c->p.eps_max, c->p.adapt_eps, B,
-                      c->s);
-    launch_observables(c->G, c->nn, c->N, std::exp(0.0) / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, B, c->s);
-    if (c->series_len < c->series_cap) {
-      HIPCHK(hipMemcpy2DAsync(c->series + c->series_len, c->series_cap * sizeof(double), c->obs + 5,
-                              8 * sizeof(double), sizeof(double), B, hipMemcpyDeviceToDevice, c->s));
-      c->series_len++;
-    }
-    restack_right(c);
-    c->sweep_counter++;
+}  // extern "C"
+
+namespace {
+
+// Sweep pieces shared by cfqmc_sweep and the heterogeneous batch.
+void sweep_reset_stats(cfqmc_ctx* c) {
+  hipMemsetAsync(c->stat, 0, c->nch * 8 * sizeof(double), c->s);
+  hipMemsetAsync(c->stab_err, 0, c->nch * sizeof(double), c->s);
+}
+
+void sweep_slice(cfqmc_ctx* c, int t, const double* noise_dev) {
+  slice_step(c, t, noise_dev);
+  if ((t + 1) % c->nstab == 0 || t == c->L - 1) block_end(c, t / c->nstab);
+}
+
+void sweep_end(cfqmc_ctx* c) {
+  const int B = c->nch;
+  launch_eps_update(c->eps, c->acc_count, c->L, c->p.r0, c->p.deps, c->p.eps_min, c->p.eps_max, c->p.adapt_eps, B,
+                    c->s);
+  launch_observables(c->G, c->nn, c->N, 1.0 / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, B, c->s);
+  if (c->series_len < c->series_cap) {
+    hipMemcpy2DAsync(c->series + c->series_len, c->series_cap * sizeof(double), c->obs + 5, 8 * sizeof(double),
+                     sizeof(double), B, hipMemcpyDeviceToDevice, c->s);
+    c->series_len++;
   }
+  restack_right(c);
+  c->sweep_counter++;
+}
+
+int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
+  const int B = c->nch;
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   int ef = 0;
@@ -918,6 +922,100 @@ int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stat
     return CFQMC_ENUMERIC;
   }
   return CFQMC_OK;
+}
+
+}  // namespace
+
+struct cfqmc_batch {
+  std::vector<cfqmc_ctx*> g;
+  std::vector<hipStream_t> streams;
+  std::string err;
+};
+
+extern "C" {
+
+int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stats* stats) {
+  if (!c || n_sweeps < 0) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  const int B = c->nch, L = c->L, W = 4 * c->nq + 1;
+  sweep_reset_stats(c);
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    if (replay) {
+      HIPCHK(hipMemcpy2DAsync(c->noise, (size_t)L * W * sizeof(double), replay + (size_t)sw * L * W,
+                              (size_t)n_sweeps * L * W * sizeof(double), (size_t)L * W * sizeof(double), B,
+                              hipMemcpyHostToDevice, c->s));
+    }
+    for (int t = 0; t < L; ++t) sweep_slice(c, t, replay ? c->noise : nullptr);
+    sweep_end(c);
+  }
+  return sweep_collect(c, stats);
+}
+
+int cfqmc_batch_create(const cfqmc_params* groups, int32_t n_groups, cfqmc_batch** out) {
+  if (!groups || n_groups < 1 || !out) return CFQMC_EINVAL;
+  *out = nullptr;
+  cfqmc_batch* b = new cfqmc_batch();
+  for (int k = 0; k < n_groups; ++k) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreate(&st) != hipSuccess) { cfqmc_batch_destroy(b); return CFQMC_EHIP; }
+    b->streams.push_back(st);
+    cfqmc_ctx* c = nullptr;
+    const int rc = cfqmc_create(&groups[k], (void*)st, &c);
+    if (rc) { cfqmc_batch_destroy(b); return rc; }
+    b->g.push_back(c);
+  }
+  *out = b;
+  return CFQMC_OK;
+}
+
+int cfqmc_batch_destroy(cfqmc_batch* b) {
+  if (!b) return CFQMC_EINVAL;
+  for (auto c : b->g) cfqmc_destroy(c);
+  for (auto st : b->streams) hipStreamDestroy(st);
+  delete b;
+  return CFQMC_OK;
+}
+
+int cfqmc_batch_context(cfqmc_batch* b, int32_t group, cfqmc_ctx** ctx) {
+  if (!b || !ctx || group < 0 || group >= (int)b->g.size()) return CFQMC_EINVAL;
+  *ctx = b->g[group];
+  return CFQMC_OK;
+}
+
+int cfqmc_batch_sweep(cfqmc_batch* b, int32_t n_sweeps, int32_t equal_time, cfqmc_stats* stats) {
+  if (!b || n_sweeps < 0) return CFQMC_EINVAL;
+  const int G = (int)b->g.size();
+  int Lmax = 0;
+  for (auto c : b->g) {
+    if (!c->ready) { b->err = "fields not initialised"; return CFQMC_ESTATE; }
+    Lmax = std::max(Lmax, c->L);
+  }
+  // sweeps per group: equal count, or scaled so every group runs for the same number of slice steps
+  std::vector<long long> steps(G);
+  long long kmax = 0;
+  for (int k = 0; k < G; ++k) {
+    const cfqmc_ctx* c = b->g[k];
+    const long long ns = equal_time ? std::max(1LL, (long long)std::llround((double)n_sweeps * Lmax / c->L)) : n_sweeps;
+    steps[k] = ns * c->L;
+    kmax = std::max(kmax, steps[k]);
+    sweep_reset_stats(b->g[k]);
+  }
+  // interleave slice steps of all groups; each group's kernels go to its own stream
+  for (long long k = 0; k < kmax; ++k)
+    for (int q = 0; q < G; ++q) {
+      if (k >= steps[q]) continue;
+      cfqmc_ctx* c = b->g[q];
+      const int t = (int)(k % c->L);
+      sweep_slice(c, t, nullptr);
+      if (t == c->L - 1) sweep_end(c);
+    }
+  int rc = CFQMC_OK, off = 0;
+  for (int q = 0; q < G; ++q) {
+    const int r = sweep_collect(b->g[q], stats ? stats + off : nullptr);
+    if (r && !rc) rc = r;
+    off += b->g[q]->nch;
+  }
+  return rc;
 }
 
 int cfqmc_measure_G(cfqmc_ctx* c, int32_t chain, int32_t tau, void* g_out, int32_t on_device) {
