@@ -18,7 +18,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6, "mixed": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
+PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
 
 
 def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
@@ -62,7 +62,9 @@ def main():
     ap.add_argument("--u", type=float, default=1.5)
     ap.add_argument("--n-stab", type=int, default=8)
     ap.add_argument("--chains", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
+    ap.add_argument("--workload", choices=["c3", "batched"], default="c3",
+                    help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid")
     ap.add_argument("--tile-cfg", type=int, default=-1)
     ap.add_argument("--tau-sweeps", type=int, default=0, help="extra untimed sweeps for tau_int")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -74,10 +76,12 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_2605_03700_amd import CFQMC, FP64, MIXED
+    from paper_2605_03700_amd import CFQMC, FP64, MIXED, MIXED_ALL
     from paper_2605_03700_amd.analysis import tau_int
     assert torch.cuda.is_available(), "needs the GPU"
-    prec = MIXED if args.precision == "mixed" else FP64
+    prec = {"fp64": FP64, "mixed": MIXED, "mixed_all": MIXED_ALL}[args.precision]
+    if args.workload == "batched":
+        return bench_batched(args, prec)
     g = CFQMC(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
               n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3,
               n_chains=args.chains, tile_cfg=args.tile_cfg)
@@ -101,7 +105,7 @@ def main():
         "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
         "value": value, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if prec == MIXED else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if prec == FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": "torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chain(s), "
                                "recompute every %d slices" % (args.n_phi, args.l_tau, args.dtau, args.u, g.n_q,
                                                               args.chains, args.n_stab),
@@ -131,6 +135,57 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds)
     g.close()
+    print(json.dumps(out))
+
+
+def bench_batched(args, prec):
+    """64 independent chains in one job: 32 at N_phi=24 (L=60), 16 at N_phi=48
+    (L=120), 16 at N_phi=72 (L=180), paper cutoff, u on the grid 0.5 + j/6
+    (j = 0..15), dtau = 0.1. One context per N_phi group, each on its own
+    stream; a step is one sweep of every chain."""
+    import numpy as np
+    import torch
+    from paper_2605_03700_amd import Batch
+    grid = [0.5 + j / 6.0 for j in range(16)]
+    groups = []
+    for k, (n_phi, nch) in enumerate([(24, 32), (48, 16), (72, 16)]):
+        groups.append(dict(n_phi=n_phi, l_tau=10 * n_phi // 4, dtau=args.dtau, n_stab=10, precision=prec,
+                           eps0=0.3, adapt_eps=True, seed=400 + k, n_chains=nch,
+                           chain_u=[(1.0, grid[c % 16], grid[c % 16]) for c in range(nch)],
+                           tile_cfg=args.tile_cfg))
+    b = Batch(groups)
+    b.init_fields()
+    if args.warmup:
+        b.sweep(args.warmup)
+    torch.cuda.synchronize()
+    g72 = b.groups[2]
+    g72.kernel_timing(True)
+    t0 = time.perf_counter()
+    st = b.sweep(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_count, k_flops = g72.kernel_timing_read()
+    g72.kernel_timing(False)
+    fields = sum(g.n_chains * g.l_tau * 4 * g.n_q for g in b.groups) * args.steps
+    out = {
+        "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
+        "value": fields / dt, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "batched: 64 chains, N_phi 24/48/72 (32/16/16 chains, L_tau 60/120/180), "
+                               "paper cutoff, u grid 0.5..3.0 (16 points), recompute every 10 slices",
+                   "chains": b.n_chains, "precision": args.precision, "n_q": [g.n_q for g in b.groups],
+                   "tile_cfg": [list(g.tile_config()) for g in b.groups]},
+        "acceptance": sum(s["accepted"] for s in st) / max(1, sum(s["proposed"] for s in st)),
+        "g_err_max": max(s["max_stab_err"] for s in st),
+    }
+    if k_count > 0 and k_ms > 0:
+        ach = k_flops / (k_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "kernel": "chan_apply (N_phi=72 group)", "achieved": ach,
+                           "peak": PEAK[args.precision], "unit": "TFLOP/s", "frac": ach / PEAK[args.precision],
+                           "traffic": None, "avg_launch_ms": k_ms, "launches_timed": k_count,
+                           "flops_per_launch": k_flops}
+    b.close()
     print(json.dumps(out))
 
 

@@ -53,7 +53,11 @@ enum {
 };
 
 enum { CFQMC_Q_PAPER = 0, CFQMC_Q_RADIUS = 1, CFQMC_Q_BZ = 2, CFQMC_Q_LIST = 3 };
-enum { CFQMC_FP64 = 0, CFQMC_MIXED = 1 };
+/* Precision of the slice work. FP64: everything in FP64. MIXED: the wraps and
+ * the drift frames in complex FP32 on MFMA with FP64 accumulation (FP64 master
+ * G), the Woodbury product M in FP64. MIXED_ALL: M in FP32 as well. LU,
+ * G' = G M^-1, exponentials, stabilisation and recomputation stay FP64. */
+enum { CFQMC_FP64 = 0, CFQMC_MIXED = 1, CFQMC_MIXED_ALL = 2 };
 
 typedef struct cfqmc_ctx cfqmc_ctx;
 
@@ -68,7 +72,7 @@ typedef struct {
   const int32_t* q_list; /* CFQMC_Q_LIST: pairs (qx, qy), closed under q -> -q; host, read at create */
   int32_t n_q_list;
   int32_t n_stab;        /* slices between FP64 recomputations of G (UDT stabilisation) */
-  int32_t precision;     /* CFQMC_FP64 or CFQMC_MIXED (FP32 MFMA, FP64 accumulation, FP64 stabilisation) */
+  int32_t precision;     /* CFQMC_FP64, CFQMC_MIXED or CFQMC_MIXED_ALL (see above) */
   double eps0;           /* initial Langevin step size epsilon */
   double r0, deps;       /* acceptance set point and gain of eps <- eps + (r_a - r0) deps (0.574, 0.1) */
   double eps_min, eps_max;

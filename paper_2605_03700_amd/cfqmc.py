@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcfqmc.so")
 
 Q_PAPER, Q_RADIUS, Q_BZ, Q_LIST = 0, 1, 2, 3
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_ALL = 0, 1, 2
 
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "ESTATE", -6: "ENOTIMPL"}
 

@@ -186,7 +186,7 @@ struct Udt {
 struct cfqmc_ctx {
   cfqmc_params p;
   hipStream_t s;
-  int N, n, nq, L, nch, nstab, nblk_stab, mixed, smax;
+  int N, n, nq, L, nch, nstab, nblk_stab, mixed, mixed_m, smax;
   long long nn, NN;
   HostTables ht;
   ModelDev md;
@@ -506,7 +506,7 @@ int check_finite_host(cfqmc_ctx* c, const double* dptr, long long count) {
 
 // One slice move of all chains; t is the 0-based slice.
 void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
-  const int N = c->N, mixed = c->mixed;
+  const int N = c->N, mixed = c->mixed, mixed_m = c->mixed_m;
   const long long nn = c->nn, NN = c->NN;
   const long long sPQ = (long long)c->L * 8 * NN, sPQp = 8 * NN;
   const double2* pq = c->PQ + (long long)t * 8 * NN;   // chain 0 of slice t
@@ -543,16 +543,16 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   // 4. M = G_0 + B' B^{-1} (1 - G_0)
   double2* y = c->S1;
   double2* y2 = c->S2;
-  chan(c, 1, 0, true, pq + 0 * 2 * NN, sPQ, c->F[0], y, true, nullptr, mixed);
+  chan(c, 1, 0, true, pq + 0 * 2 * NN, sPQ, c->F[0], y, true, nullptr, mixed_m);
   for (int ch = 1; ch <= 3; ++ch) {
-    chan(c, 1, ch, true, pq + ch * 2 * NN, sPQ, y, y2, false, nullptr, mixed);
+    chan(c, 1, ch, true, pq + ch * 2 * NN, sPQ, y, y2, false, nullptr, mixed_m);
     std::swap(y, y2);
   }
   for (int ch = 3; ch >= 1; --ch) {
-    chan(c, 1, ch, false, c->PQp + ch * 2 * NN, sPQp, y, y2, false, nullptr, mixed);
+    chan(c, 1, ch, false, c->PQp + ch * 2 * NN, sPQp, y, y2, false, nullptr, mixed_m);
     std::swap(y, y2);
   }
-  chan(c, 1, 0, false, c->PQp, sPQp, y, c->Mw, false, c->F[0], mixed, -1, c->Mb);
+  chan(c, 1, 0, false, c->PQp, sPQp, y, c->Mw, false, c->F[0], mixed_m, -1, c->Mb);
   // 5. LU of M: ln det M. M is close to the identity, so the blocked LU without
   //    pivoting is tried first; chains whose multipliers exceed the threshold
   //    are refactorised with partial pivoting from the saved copy.
@@ -671,7 +671,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   const cfqmc_params& p = *pin;
   if (p.n_phi < 1 || p.n_phi > 140 || p.l_tau < 1 || !(p.dtau > 0) || p.n_chains < 1 || p.n_stab < 1 ||
       !(p.eps0 > 0) || p.eps_min <= 0 || p.eps_max < p.eps_min || p.exp_squarings < 0 || p.exp_squarings > 8 ||
-      (p.precision != CFQMC_FP64 && p.precision != CFQMC_MIXED) || p.tile_cfg < -1 || p.tile_cfg > 3)
+      (p.precision < CFQMC_FP64 || p.precision > CFQMC_MIXED_ALL) || p.tile_cfg < -1 || p.tile_cfg > 3)
     return CFQMC_EINVAL;
   cfqmc_ctx* c = new cfqmc_ctx();
   c->p = p;
@@ -680,7 +680,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->s = (hipStream_t)hip_stream;
   c->N = p.n_phi; c->n = 2 * p.n_phi; c->L = p.l_tau; c->nch = p.n_chains; c->nstab = p.n_stab;
   c->nblk_stab = (p.l_tau + p.n_stab - 1) / p.n_stab;
-  c->mixed = p.precision == CFQMC_MIXED;
+  c->mixed = p.precision != CFQMC_FP64;
+  c->mixed_m = p.precision == CFQMC_MIXED_ALL;
   c->smax = p.exp_squarings;
   c->nn = (long long)c->n * c->n;
   c->NN = (long long)c->N * c->N;

@@ -114,12 +114,13 @@ def test_sweep_replay_parity_batched_u_grid():
     _replay_compare(CFQMC, 8, 24, 6, Q_RADIUS, 3.0, [0.5, 1.0, 1.5, 2.0, 2.5], 0, 2, 1e-10)
 
 
-def test_sweep_replay_parity_mixed():
-    """Mixed path: FP32 MFMA wraps/updates with FP64 accumulation, FP64 recomputation.
-    G after a sweep (recomputed in FP64) within 1e-6 and the G drift between
-    recomputations within 1e-6."""
+@pytest.mark.parametrize("precision", [1, 2])
+def test_sweep_replay_parity_mixed(precision):
+    """Mixed paths: FP32 MFMA wraps and frames (1), also the Woodbury product (2),
+    with FP64 accumulation and FP64 recomputation. G after a sweep (recomputed
+    in FP64) within 1e-6 and the G drift between recomputations within 1e-6."""
     CFQMC = _gpu()
-    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], 1, 2, 1e-6)
+    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], precision, 2, 1e-6)
     assert st[0]["max_stab_err"] < 1e-6
 
 
