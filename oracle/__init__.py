@@ -17,4 +17,7 @@ Parity status per module:
   dqmc.py         pinned (closed forms, Fock-trace identity, mpmath brute
                   force, finite-difference gradient, Gaussian MALA limit)
   observables.py  pinned (Fock-space expectation values at small size)
+  slmc.py         pinned (Parseval, closed-form periodogram, translation
+                  invariance, finite differences, torch bfloat16 and Adam,
+                  leapfrog reversibility, stationary law of the global move)
 """
