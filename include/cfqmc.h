@@ -170,6 +170,77 @@ int cfqmc_batch_context(cfqmc_batch* b, int32_t group, cfqmc_ctx** ctx);
 int cfqmc_batch_sweep(cfqmc_batch* b, int32_t n_sweeps, int32_t equal_time, cfqmc_stats* stats);
 int cfqmc_batch_destroy(cfqmc_batch* b);
 
+/* ---- Learned global proposal (self-learning Monte Carlo).
+ * The paper samples with whole-slice Langevin moves (Methods, eq. Langevin
+ * proposal); these calls add global moves proposed by a Markov chain on a
+ * learned effective action S_eff(phi) = |phi|^2/2 + S_NN(phi) and accepted by
+ * the exact weight: ln A = ln w_F(phi') - ln w_F(phi) + S_NN(phi') - S_NN(phi),
+ * with ln w_F = sum_tau c_tau + 2 ln det(1 + B(beta,0)) computed from scratch in
+ * FP64 (eq. green function / HS transform). The local sweep stays unchanged.
+ *
+ * S_NN: three-layer perceptron tanh(W1 x + b1) -> tanh(W2 . + b2) -> w3 . + b3,
+ * output s_y * out + y_bar, on standardised features x = (f - mu) / sigma of:
+ *   f[i][s][w]: mean over components c of |q|^2 shell s (s = floor(n_qbins r2 /
+ *     (r2_max + 1)), r2 = qx^2 + qy^2) and frequencies of bin w (floor(n_wbins w /
+ *     (L/2 + 1))) of |sum_tau phi^i_{tau,c} e^{-2 pi i w tau / L}|^2 / L;
+ *   f[4 n_qbins n_wbins + i] = sum_tau phi^i_{tau,0} / sqrt(L).
+ * n_feat = 4 n_qbins n_wbins + 4. Weights BF16 in every product (FP32 master
+ * copy, Adam), FP32 accumulation, biases and activations. Parameters flat, FP32:
+ * W1 [H][n_feat], b1 [H], W2 [H][H], b2 [H], w3 [H], b3 [1].
+ * An SLMC object belongs to one context and uses its stream; it must be
+ * destroyed before the context. */
+typedef struct cfqmc_slmc cfqmc_slmc;
+typedef struct {
+  int32_t hidden;            /* H, default 256 */
+  int32_t n_qbins, n_wbins;  /* feature bins, default 16 x 16 (n_wbins capped at L/2 + 1) */
+  int32_t capacity;          /* stored training configurations, default 10000 */
+  int32_t max_batch;         /* largest minibatch, default 256 */
+  uint64_t seed;             /* initial weights, minibatch order, host uniforms */
+} cfqmc_slmc_params;
+typedef struct {
+  int32_t accepted;          /* global move accepted */
+  int32_t inner_accepted;    /* accepted HMC trajectories of the inner chain */
+  double ln_a;               /* ln A of the global test */
+  double d_lnw, d_snn;       /* ln w_F(phi') - ln w_F(phi), S_NN(phi') - S_NN(phi) */
+  double max_abs_dh;         /* largest |Delta H| of the inner trajectories */
+} cfqmc_slmc_move;
+
+void cfqmc_slmc_default_params(cfqmc_slmc_params* p);
+int cfqmc_slmc_create(cfqmc_ctx* c, const cfqmc_slmc_params* p, cfqmc_slmc** out);
+int cfqmc_slmc_destroy(cfqmc_slmc* s);
+int cfqmc_slmc_sizes(const cfqmc_slmc* s, int32_t* n_feat, int64_t* n_params, int32_t* n_data);
+int cfqmc_slmc_set_params(cfqmc_slmc* s, const float* w);   /* host [n_params]; resets Adam */
+int cfqmc_slmc_get_params(cfqmc_slmc* s, float* w);
+int cfqmc_slmc_set_norm(cfqmc_slmc* s, const float* mu, const float* sigma, double y_bar, double s_y);
+int cfqmc_slmc_get_norm(cfqmc_slmc* s, float* mu, float* sigma, double* y_bar, double* s_y);
+/* Raw features of n host configurations phi [n][l_tau][4][n_q] -> feat [n][n_feat]. */
+int cfqmc_slmc_features(cfqmc_slmc* s, const double* phi, int32_t n, float* feat);
+/* S_NN of n host configurations, and dS_NN/dphi [n][l_tau][4][n_q] if grad_phi != NULL. */
+int cfqmc_slmc_action(cfqmc_slmc* s, const double* phi, int32_t n, double* s_nn, double* grad_phi);
+/* Mean squared error of the network on n <= max_batch standardised inputs x [n][n_feat]
+ * against standardised targets y [n], its parameter gradient [n_params] and the outputs
+ * [n] (any output may be NULL). No parameter update. */
+int cfqmc_slmc_loss_grad(cfqmc_slmc* s, const float* x, const double* y, int32_t n, double* loss, float* grad,
+                         float* out);
+/* Append the current configuration of every chain (features and -ln w_F). */
+int cfqmc_slmc_collect(cfqmc_slmc* s);
+int cfqmc_slmc_clear_data(cfqmc_slmc* s);
+/* Adam training on the stored configurations (MSE on standardised targets).
+ * refit_norm = 1 (or the first call) sets mu, sigma, y_bar, s_y from the data.
+ * loss_out: mean minibatch loss of the last epoch. */
+int cfqmc_slmc_train(cfqmc_slmc* s, int32_t epochs, int32_t batch, double lr, int32_t refit_norm, double* loss_out);
+/* One global move of every chain: n_traj HMC trajectories of n_leap leapfrog steps
+ * of size step on S_eff, each with its own Metropolis test, then the exact test.
+ * Accepted chains keep phi', rejected chains return to phi; the chain state (UDT
+ * stacks, G) is rebuilt from scratch. replay: NULL (Philox momenta, host uniforms)
+ * or host [n_chains][n_traj * l_tau * 4 * n_q + n_traj + 1]: the momenta of every
+ * trajectory, the inner uniforms, then the uniform of the global test.
+ * out: NULL or [n_chains]. Synchronises. */
+int cfqmc_slmc_global_move(cfqmc_slmc* s, int32_t n_traj, int32_t n_leap, double step, const double* replay,
+                           cfqmc_slmc_move* out);
+/* Proposal phi' of the last global move of one chain (host [l_tau][4][n_q]). */
+int cfqmc_slmc_last_proposal(cfqmc_slmc* s, int32_t chain, double* phi_out);
+
 const char* cfqmc_last_error(const cfqmc_ctx* c);
 
 #ifdef __cplusplus

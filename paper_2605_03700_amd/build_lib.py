@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcfqmc.so")
-SOURCES = ["gemm.hip", "linalg.hip", "qmc.hip", "engine.hip"]
+SOURCES = ["gemm.hip", "linalg.hip", "qmc.hip", "slmc.hip", "engine.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I", os.path.join(os.path.dirname(HERE), "include")]

@@ -33,6 +33,19 @@ class Params(ctypes.Structure):
     ]
 
 
+class SlmcParams(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("n_qbins", ctypes.c_int32), ("n_wbins", ctypes.c_int32),
+                ("capacity", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class SlmcMove(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("inner_accepted", ctypes.c_int32), ("ln_a", ctypes.c_double),
+                ("d_lnw", ctypes.c_double), ("d_snn", ctypes.c_double), ("max_abs_dh", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("eps", ctypes.c_double),
                 ("max_stab_err", ctypes.c_double), ("max_phase_err", ctypes.c_double),
@@ -48,7 +61,11 @@ EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes
            "cfqmc_get_fields", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
-           "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy"]
+           "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
+           "cfqmc_slmc_create", "cfqmc_slmc_destroy", "cfqmc_slmc_sizes", "cfqmc_slmc_set_params",
+           "cfqmc_slmc_get_params", "cfqmc_slmc_set_norm", "cfqmc_slmc_get_norm", "cfqmc_slmc_features",
+           "cfqmc_slmc_action", "cfqmc_slmc_loss_grad", "cfqmc_slmc_collect", "cfqmc_slmc_clear_data",
+           "cfqmc_slmc_train", "cfqmc_slmc_global_move", "cfqmc_slmc_last_proposal"]
 
 
 def load():
@@ -84,10 +101,29 @@ def load():
     lib.cfqmc_batch_context.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.cfqmc_batch_sweep.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
     lib.cfqmc_batch_destroy.argtypes = [P]
+    D = ctypes.c_double
+    lib.cfqmc_slmc_default_params.argtypes = [ctypes.POINTER(SlmcParams)]
+    lib.cfqmc_slmc_default_params.restype = None
+    lib.cfqmc_slmc_create.argtypes = [P, ctypes.POINTER(SlmcParams), ctypes.POINTER(P)]
+    lib.cfqmc_slmc_destroy.argtypes = [P]
+    lib.cfqmc_slmc_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_slmc_set_params.argtypes = [P, P]
+    lib.cfqmc_slmc_get_params.argtypes = [P, P]
+    lib.cfqmc_slmc_set_norm.argtypes = [P, P, P, D, D]
+    lib.cfqmc_slmc_get_norm.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.cfqmc_slmc_features.argtypes = [P, P, ctypes.c_int32, P]
+    lib.cfqmc_slmc_action.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.cfqmc_slmc_loss_grad.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(D), P, P]
+    lib.cfqmc_slmc_collect.argtypes = [P]
+    lib.cfqmc_slmc_clear_data.argtypes = [P]
+    lib.cfqmc_slmc_train.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, ctypes.c_int32, ctypes.POINTER(D)]
+    lib.cfqmc_slmc_global_move.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, P, P]
+    lib.cfqmc_slmc_last_proposal.argtypes = [P, ctypes.c_int32, P]
     lib.cfqmc_last_error.argtypes = [P]
     lib.cfqmc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("cfqmc_default_params", "cfqmc_last_error"):
+        if name not in ("cfqmc_default_params", "cfqmc_last_error", "cfqmc_slmc_default_params"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -308,6 +344,120 @@ class Batch:
             for g in self.groups:
                 g.h = None
             self.lib.cfqmc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Slmc:
+    """Learned global proposal attached to one context (see cfqmc.h)."""
+
+    def __init__(self, ctx, hidden=256, n_qbins=16, n_wbins=16, capacity=10000, max_batch=256, seed=1):
+        lib = load()
+        self.lib, self.ctx = lib, ctx
+        p = SlmcParams()
+        lib.cfqmc_slmc_default_params(ctypes.byref(p))
+        p.hidden, p.n_qbins, p.n_wbins, p.capacity, p.max_batch, p.seed = (hidden, n_qbins, n_wbins, capacity,
+                                                                           max_batch, seed)
+        h = ctypes.c_void_p()
+        self._check(lib.cfqmc_slmc_create(ctx.h, ctypes.byref(p), ctypes.byref(h)), "create")
+        self.h = h
+        nf, npar, nd = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        lib.cfqmc_slmc_sizes(h, ctypes.byref(nf), ctypes.byref(npar), ctypes.byref(nd))
+        self.n_feat, self.n_params, self.hidden = nf.value, npar.value, hidden
+        self.fields_per_chain = ctx.l_tau * 4 * ctx.n_q
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.cfqmc_last_error(self.ctx.h)
+            raise RuntimeError("cfqmc_slmc_%s failed: %s (%s)" % (what, ERRORS.get(rc, rc),
+                                                                 msg.decode() if msg else ""))
+
+    def n_data(self):
+        nd = ctypes.c_int32()
+        self.lib.cfqmc_slmc_sizes(self.h, None, None, ctypes.byref(nd))
+        return nd.value
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.n_params
+        self._check(self.lib.cfqmc_slmc_set_params(self.h, _ptr(w)), "set_params")
+
+    def get_params(self):
+        w = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.cfqmc_slmc_get_params(self.h, _ptr(w)), "get_params")
+        return w
+
+    def set_norm(self, mu, sigma, y_bar, s_y):
+        mu = np.ascontiguousarray(mu, dtype=np.float32)
+        sg = np.ascontiguousarray(sigma, dtype=np.float32)
+        self._check(self.lib.cfqmc_slmc_set_norm(self.h, _ptr(mu), _ptr(sg), float(y_bar), float(s_y)), "set_norm")
+
+    def get_norm(self):
+        mu = np.empty(self.n_feat, dtype=np.float32)
+        sg = np.empty(self.n_feat, dtype=np.float32)
+        yb, sy = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.cfqmc_slmc_get_norm(self.h, _ptr(mu), _ptr(sg), ctypes.byref(yb), ctypes.byref(sy)),
+                    "get_norm")
+        return mu, sg, yb.value, sy.value
+
+    def features(self, phi):
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, self.fields_per_chain)
+        f = np.empty((phi.shape[0], self.n_feat), dtype=np.float32)
+        self._check(self.lib.cfqmc_slmc_features(self.h, _ptr(phi), phi.shape[0], _ptr(f)), "features")
+        return f
+
+    def action(self, phi, grad=False):
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, self.fields_per_chain)
+        n = phi.shape[0]
+        s = np.empty(n)
+        g = np.empty_like(phi) if grad else None
+        self._check(self.lib.cfqmc_slmc_action(self.h, _ptr(phi), n, _ptr(s), _ptr(g)), "action")
+        if grad:
+            return s, g.reshape(n, self.ctx.l_tau, 4, self.ctx.n_q)
+        return s
+
+    def loss_grad(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        out = np.empty(len(y), dtype=np.float32)
+        self._check(self.lib.cfqmc_slmc_loss_grad(self.h, _ptr(x), _ptr(y), len(y), ctypes.byref(loss), _ptr(g),
+                                                  _ptr(out)), "loss_grad")
+        return loss.value, g, out
+
+    def collect(self):
+        self._check(self.lib.cfqmc_slmc_collect(self.h), "collect")
+
+    def clear_data(self):
+        self._check(self.lib.cfqmc_slmc_clear_data(self.h), "clear_data")
+
+    def train(self, epochs=10, batch=64, lr=1e-3, refit_norm=False):
+        loss = ctypes.c_double()
+        self._check(self.lib.cfqmc_slmc_train(self.h, epochs, batch, lr, int(bool(refit_norm)), ctypes.byref(loss)),
+                    "train")
+        return loss.value
+
+    def global_move(self, n_traj=1, n_leap=8, step=0.2, replay=None):
+        rp = None if replay is None else np.ascontiguousarray(replay, dtype=np.float64)
+        out = (SlmcMove * self.ctx.n_chains)()
+        self._check(self.lib.cfqmc_slmc_global_move(self.h, n_traj, n_leap, step, _ptr(rp),
+                                                    ctypes.cast(out, ctypes.c_void_p)), "global_move")
+        return [m.as_dict() for m in out]
+
+    def last_proposal(self, chain=0):
+        out = np.empty((self.ctx.l_tau, 4, self.ctx.n_q))
+        self._check(self.lib.cfqmc_slmc_last_proposal(self.h, chain, _ptr(out)), "last_proposal")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.lib.cfqmc_slmc_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -602,6 +602,55 @@ int build_all_exps(cfqmc_ctx* c) {
   return CFQMC_OK;
 }
 
+// Everything that depends on the fields, from scratch in FP64: slice
+// exponentials, block products, both UDT stacks and G(0). The identity slots
+// Rs[nb] and Ls[0] are set once at initialisation.
+void rebuild_state(cfqmc_ctx* c) {
+  build_all_exps(c);
+  for (int b = 0; b < c->nblk_stab; ++b) block_product(c, b);
+  restack_right(c);
+  for (int b = 0; b < c->nblk_stab; ++b) left_acc(c, b);
+  green_udt(c, 0, 0, c->G);
+}
+
+// ln w_F = sum_tau c_tau + 2 ln det(1 + B(beta,0)) of every chain from the right
+// stack at tau = 0 (left factor = 1): 1 + T_R^+ D_R U_R^+ = Y D_R^max U_R^+ with
+// Y = U_R D_R^max^-1 + T_R^+ D_R^min (Loh split). Imaginary part wrapped to (-pi, pi].
+int lnw_all(cfqmc_ctx* c, std::vector<double>& re, std::vector<double>& im) {
+  const int n = c->n, B = c->nch;
+  const long long nn = c->nn, sU = sU_(c), sD = sD_(c);
+  green_udt(c, 0, 0, c->Gs);   // leaves LU(Y) in Yl and ln det Y in ldtmp
+  std::vector<double2> ldY(B);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(ldY.data(), c->ldtmp, B * sizeof(double2), hipMemcpyDeviceToHost));
+  // ln det U_R (unitary: phase only)
+  launch_copy(c->Rs.U, c->Q2, nn, sU, nn, B, c->s);
+  launch_lu(c->Q2, n, n, nn, c->ipiv, n, c->ldtmp, 1, B, c->s);
+  launch_sum_log_dmax(c->Rs.D, sD, n, c->tmpd, B, c->s);
+  launch_background(c->md, c->phi, (long long)c->L * 4 * c->nq, c->alpha, c->bg, B, c->s);
+  std::vector<double2> ldU(B), bg(B);
+  std::vector<double> sdm(B);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(ldU.data(), c->ldtmp, B * sizeof(double2), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(sdm.data(), c->tmpd, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bg.data(), c->bg, B * sizeof(double2), hipMemcpyDeviceToHost));
+  re.assign(B, 0.0);
+  im.assign(B, 0.0);
+  for (int z = 0; z < B; ++z) {
+    // ln det(1+B) = ln det Y + sum ln D_R^max + ln det U_R^dagger
+    const double lr = ldY[z].x + sdm[z] - ldU[z].x;
+    const double li = ldY[z].y - ldU[z].y;
+    double r_ = 2.0 * lr + bg[z].x, i_ = 2.0 * li + bg[z].y;
+    i_ = std::fmod(i_, 2.0 * M_PI);
+    if (i_ > M_PI) i_ -= 2.0 * M_PI;
+    if (i_ <= -M_PI) i_ += 2.0 * M_PI;
+    if (!std::isfinite(r_)) { c->err = "non-finite weight"; return CFQMC_ENUMERIC; }
+    re[z] = r_;
+    im[z] = i_;
+  }
+  return CFQMC_OK;
+}
+
 int autotune(cfqmc_ctx* c) {
   // time the channel application, the n x n GEMM and the batched N x N GEMM of
   // the exponential for each tile configuration; keep the fastest of each
@@ -829,14 +878,9 @@ int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
   HIPCHK(hipMemcpyAsync(c->phi, h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemsetAsync(c->d_err, 0, sizeof(int), c->s));
   HIPCHK(hipGetLastError());
-  build_all_exps(c);
-  for (int b = 0; b < c->nblk_stab; ++b) block_product(c, b);
-  HIPCHK(hipStreamSynchronize(c->s));
   set_udt_identity(c, c->Rs, c->nblk_stab);
   set_udt_identity(c, c->Ls, 0);
-  restack_right(c);
-  for (int b = 0; b < c->nblk_stab; ++b) left_acc(c, b);
-  green_udt(c, 0, 0, c->G);
+  rebuild_state(c);
   std::vector<double> e(B, c->p.eps0);
   HIPCHK(hipMemcpyAsync(c->eps, e.data(), B * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemsetAsync(c->acc_count, 0, B * sizeof(int), c->s));
@@ -1059,36 +1103,11 @@ int cfqmc_measure_G(cfqmc_ctx* c, int32_t chain, int32_t tau, void* g_out, int32
 int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im) {
   if (!c || chain < 0 || chain >= c->nch) return CFQMC_EINVAL;
   if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
-  // ln det(1 + B(beta,0)) from the right stack at tau = 0 (left factor = 1):
-  // 1 + T_R^+ D_R U_R^+ = Y D_R^max U_R^+ with Y = U_R D_R^max^-1 + T_R^+ D_R^min
-  const int n = c->n, B = c->nch;
-  const long long nn = c->nn, sU = sU_(c), sD = sD_(c);
-  green_udt(c, 0, 0, c->Gs);   // leaves LU(Y) in Yl and ln det Y in ldtmp
-  std::vector<double2> ldY(B);
-  HIPCHK(hipStreamSynchronize(c->s));
-  HIPCHK(hipMemcpy(ldY.data(), c->ldtmp, B * sizeof(double2), hipMemcpyDeviceToHost));
-  // ln det U_R (unitary: phase only, modulus 1)
-  launch_copy(c->Rs.U, c->Q2, nn, sU, nn, B, c->s);
-  launch_lu(c->Q2, n, n, nn, c->ipiv, n, c->ldtmp, 1, B, c->s);
-  launch_sum_log_dmax(c->Rs.D, sD, n, c->tmpd, B, c->s);
-  launch_background(c->md, c->phi, (long long)c->L * 4 * c->nq, c->alpha, c->bg, B, c->s);
-  std::vector<double2> ldU(B), bg(B);
-  std::vector<double> sdm(B);
-  HIPCHK(hipStreamSynchronize(c->s));
-  HIPCHK(hipMemcpy(ldU.data(), c->ldtmp, B * sizeof(double2), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(sdm.data(), c->tmpd, B * sizeof(double), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(bg.data(), c->bg, B * sizeof(double2), hipMemcpyDeviceToHost));
-  const int z = chain;
-  // ln det(1+B) = ln det Y + sum ln D_R^max + ln det U_R^dagger
-  const double lr = ldY[z].x + sdm[z] - ldU[z].x;
-  const double li = ldY[z].y - ldU[z].y;
-  double r_ = 2.0 * lr + bg[z].x, i_ = 2.0 * li + bg[z].y;
-  i_ = std::fmod(i_, 2.0 * M_PI);
-  if (i_ > M_PI) i_ -= 2.0 * M_PI;
-  if (i_ <= -M_PI) i_ += 2.0 * M_PI;
-  if (!std::isfinite(r_)) return CFQMC_ENUMERIC;
-  if (re) *re = r_;
-  if (im) *im = i_;
+  std::vector<double> r, i;
+  const int rc = lnw_all(c, r, i);
+  if (rc) return rc;
+  if (re) *re = r[chain];
+  if (im) *im = i[chain];
   return CFQMC_OK;
 }
 
@@ -1170,6 +1189,575 @@ int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, doubl
   if (count) *count = k;
   // two N x N x n complex products per chain = 8 * 2 N^2 n real flops
   if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
+  return CFQMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned global proposal
+
+struct cfqmc_slmc {
+  cfqmc_ctx* c;
+  cfqmc_slmc_params p;
+  int L, nq, nw, nqb, nwb, F, Fp, H, NX, Bmax, nch;
+  long long nf, P, oW1, ob1, oW2, ob2, ow3, ob3;
+  std::vector<void*> allocs;
+  int *shell, *wbin, *shell_off, *shell_comp, *w_off;
+  float *inv_cnt, *twc, *tws;
+  float *w, *g, *m, *v, *mu, *sig;
+  uint16_t *W1b, *W2b, *w3b;
+  int t_adam;
+  double ybar, sy;
+  bool norm_set;
+  int cap, n_data;
+  float* dx_raw;
+  std::vector<double> hy;
+  uint16_t* xall;
+  float* yall;
+  float *Xre, *Xim, *feat, *yb, *a1, *a2, *out, *dout, *dz2, *dA1, *dz1, *dX, *gf;
+  uint16_t *xb, *a1b, *a2b, *dz2b, *dz1b;
+  double* loss_acc;
+  double *phi_cur, *phi_save, *mom, *grad, *prop, *sumsq, *rp;
+  int* flag;
+  long long move_counter;
+  uint64_t rng;
+};
+
+namespace {
+
+template <typename T>
+int salloc(cfqmc_slmc* s, T** p, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    s->c->err = "device allocation failed";
+    return CFQMC_ENOMEM;
+  }
+  hipMemsetAsync(q, 0, count * sizeof(T), s->c->s);
+  s->allocs.push_back(q);
+  *p = (T*)q;
+  return CFQMC_OK;
+}
+
+uint64_t splitmix(uint64_t& st) {
+  st += 0x9E3779B97F4A7C15ull;
+  uint64_t z = st;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+double host_uniform(uint64_t& st) { return ((splitmix(st) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+double host_normal(uint64_t& st) {
+  const double u1 = host_uniform(st), u2 = host_uniform(st);
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+}
+
+void slmc_refresh_bf16(cfqmc_slmc* s) {
+  hipStream_t st = s->c->s;
+  launch_slmc_to_bf16(s->w + s->oW1, s->H, s->F, s->W1b, s->Fp, st);
+  launch_slmc_to_bf16(s->w + s->oW2, s->H, s->H, s->W2b, s->H, st);
+  launch_slmc_to_bf16(s->w + s->ow3, 1, s->H, s->w3b, s->H, st);
+}
+
+// Raw features of nb configurations (device fields, stride sphi) into s->feat.
+void slmc_features_dev(cfqmc_slmc* s, const double* phi, long long sphi, int nb) {
+  hipStream_t st = s->c->s;
+  const long long sX = 4LL * s->nq * s->nw;
+  launch_slmc_dft(phi, sphi, s->L, s->nq, s->nw, s->twc, s->tws, s->Xre, s->Xim, sX, nb, st);
+  launch_slmc_bin(s->Xre, s->Xim, sX, s->nq, s->nw, s->L, s->nqb, s->nwb, s->shell_off, s->shell_comp, s->w_off,
+                  s->feat, s->F, nb, st);
+}
+
+void slmc_forward(cfqmc_slmc* s, const uint16_t* xb, int nb) {
+  hipStream_t st = s->c->s;
+  const int H = s->H;
+  launch_slmc_gemm(0, 0, nb, H, s->Fp, xb, s->Fp, s->W1b, s->Fp, s->a1, H, s->w + s->ob1, 1, s->a1b, H, st);
+  launch_slmc_gemm(0, 0, nb, H, H, s->a1b, H, s->W2b, H, s->a2, H, s->w + s->ob2, 1, s->a2b, H, st);
+  launch_slmc_head(s->a2b, H, s->w3b, s->w + s->ob3, s->out, nb, st);
+}
+
+// Back-propagation of sum_b dout[b] out[b]: parameter gradients into s->g
+// (weights) and/or the gradient w.r.t. the standardised inputs into s->dX.
+void slmc_backward(cfqmc_slmc* s, const uint16_t* xb, int nb, bool weights, bool input) {
+  hipStream_t st = s->c->s;
+  const int H = s->H, F = s->F, Fp = s->Fp;
+  launch_slmc_dz2(s->dout, s->w3b, s->a2, H, s->dz2, s->dz2b, nb, st);
+  if (weights) {
+    launch_slmc_head_grad(s->dout, s->a2b, nb, H, s->g + s->ow3, s->g + s->ob3, st);
+    launch_slmc_colsum(s->dz2, nb, H, s->g + s->ob2, st);
+    launch_slmc_gemm(1, 1, H, H, nb, s->dz2b, H, s->a1b, H, s->g + s->oW2, H, nullptr, 0, nullptr, 0, st);
+  }
+  launch_slmc_gemm(0, 1, nb, H, H, s->dz2b, H, s->W2b, H, s->dA1, H, nullptr, 0, nullptr, 0, st);
+  launch_slmc_tanh_bwd(s->dA1, s->a1, (long long)nb * H, s->dz1, s->dz1b, st);
+  if (weights) {
+    launch_slmc_colsum(s->dz1, nb, H, s->g + s->ob1, st);
+    launch_slmc_gemm(1, 1, H, F, nb, s->dz1b, H, xb, Fp, s->g + s->oW1, F, nullptr, 0, nullptr, 0, st);
+  }
+  if (input) launch_slmc_gemm(0, 1, nb, F, H, s->dz1b, H, s->W1b, Fp, s->dX, Fp, nullptr, 0, nullptr, 0, st);
+}
+
+// S_NN and optionally dS_NN/dphi (into s->grad, stride nf) of nb <= NX device
+// configurations. snn: host [nb].
+int slmc_action_dev(cfqmc_slmc* s, const double* phi, int nb, std::vector<double>& snn, bool want_grad) {
+  cfqmc_ctx* c = s->c;
+  hipStream_t st = c->s;
+  slmc_features_dev(s, phi, s->nf, nb);
+  launch_slmc_standardize(s->feat, s->F, s->Fp, s->mu, s->sig, s->xb, nb, st);
+  slmc_forward(s, s->xb, nb);
+  if (want_grad) {
+    launch_slmc_dout(s->out, nullptr, nb, 1, (float)s->sy, s->dout, nullptr, st);
+    slmc_backward(s, s->xb, nb, false, true);
+    launch_slmc_dx_to_gf(s->dX, s->Fp, s->sig, s->F, 1.f, s->gf, nb, st);
+    launch_slmc_vjp(s->Xre, s->Xim, 4LL * s->nq * s->nw, s->gf, s->F, s->nq, s->nw, s->L, s->nqb, s->nwb, s->shell,
+                    s->wbin, s->inv_cnt, s->twc, s->tws, s->grad, s->nf, nb, st);
+  }
+  std::vector<float> o(nb);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(o.data(), s->out, nb * sizeof(float), hipMemcpyDeviceToHost));
+  snn.resize(nb);
+  for (int b = 0; b < nb; ++b) snn[b] = s->sy * (double)o[b] + s->ybar;
+  return CFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cfqmc_slmc_default_params(cfqmc_slmc_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->hidden = 256;
+  p->n_qbins = 16;
+  p->n_wbins = 16;
+  p->capacity = 10000;
+  p->max_batch = 256;
+  p->seed = 1;
+}
+
+int cfqmc_slmc_destroy(cfqmc_slmc* s) {
+  if (!s) return CFQMC_EINVAL;
+  hipStreamSynchronize(s->c->s);
+  for (void* q : s->allocs) hipFree(q);
+  delete s;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_create(cfqmc_ctx* c, const cfqmc_slmc_params* pp, cfqmc_slmc** out) {
+  if (!c || !pp || !out) return CFQMC_EINVAL;
+  *out = nullptr;
+  const cfqmc_slmc_params p = *pp;
+  if (p.hidden < 16 || p.hidden > 4096 || p.n_qbins < 1 || p.n_wbins < 1 || p.capacity < 1 || p.max_batch < 1 ||
+      p.max_batch > 65536) {
+    c->err = "invalid SLMC parameters";
+    return CFQMC_EINVAL;
+  }
+  if (c->L > 2000) { c->err = "SLMC features support L_tau <= 2000"; return CFQMC_EINVAL; }
+  cfqmc_slmc* s = new cfqmc_slmc();
+  s->c = c;
+  s->p = p;
+  s->L = c->L; s->nq = c->nq; s->nw = c->L / 2 + 1;
+  s->nqb = p.n_qbins; s->nwb = std::min(p.n_wbins, s->nw);
+  s->F = 4 * s->nqb * s->nwb + 4;
+  s->Fp = (s->F + 31) / 32 * 32;
+  s->H = p.hidden;
+  s->nch = c->nch;
+  s->NX = std::max(c->nch, 4);
+  s->Bmax = std::max(s->NX, p.max_batch);
+  s->nf = (long long)c->L * 4 * c->nq;
+  const long long F = s->F, H = s->H;
+  s->oW1 = 0; s->ob1 = H * F; s->oW2 = s->ob1 + H; s->ob2 = s->oW2 + H * H; s->ow3 = s->ob2 + H; s->ob3 = s->ow3 + H;
+  s->P = s->ob3 + 1;
+  s->cap = p.capacity;
+  s->rng = p.seed * 0xD1B54A32D192ED03ull + 0x8CB92BA72F3D8DD7ull;
+  // tables: shells by |q|^2, frequency bins, member lists
+  const HostTables& T = c->ht;
+  std::vector<int> sh(s->nq), wb(s->nw);
+  long long r2max = 0;
+  for (int q = 0; q < s->nq; ++q)
+    r2max = std::max(r2max, (long long)T.comp_qx[q] * T.comp_qx[q] + (long long)T.comp_qy[q] * T.comp_qy[q]);
+  for (int q = 0; q < s->nq; ++q) {
+    const long long r2 = (long long)T.comp_qx[q] * T.comp_qx[q] + (long long)T.comp_qy[q] * T.comp_qy[q];
+    sh[q] = (int)((s->nqb * r2) / (r2max + 1));
+  }
+  for (int w = 0; w < s->nw; ++w) wb[w] = (int)(((long long)s->nwb * w) / s->nw);
+  std::vector<int> soff(s->nqb + 1, 0), scomp, woff(s->nwb + 1, 0);
+  for (int b = 0; b < s->nqb; ++b) {
+    for (int q = 0; q < s->nq; ++q)
+      if (sh[q] == b) scomp.push_back(q);
+    soff[b + 1] = (int)scomp.size();
+  }
+  for (int w = 0; w < s->nw; ++w) woff[wb[w] + 1] = w + 1;
+  for (int b = 1; b <= s->nwb; ++b) woff[b] = std::max(woff[b], woff[b - 1]);
+  std::vector<float> icnt(s->nqb * s->nwb), twc(s->L), tws(s->L);
+  for (int a = 0; a < s->nqb; ++a)
+    for (int b = 0; b < s->nwb; ++b) {
+      const long long cnt = (long long)(soff[a + 1] - soff[a]) * (woff[b + 1] - woff[b]);
+      icnt[a * s->nwb + b] = cnt > 0 ? (float)(1.0 / (double)cnt) : 0.f;
+    }
+  for (int k = 0; k < s->L; ++k) {
+    twc[k] = (float)std::cos(2.0 * M_PI * k / s->L);
+    tws[k] = (float)std::sin(2.0 * M_PI * k / s->L);
+  }
+  // initial parameters: N(0, 1/fan_in) weights, zero biases
+  std::vector<float> w0(s->P, 0.f);
+  for (long long e = 0; e < H * F; ++e) w0[s->oW1 + e] = (float)(host_normal(s->rng) / std::sqrt((double)F));
+  for (long long e = 0; e < H * H; ++e) w0[s->oW2 + e] = (float)(host_normal(s->rng) / std::sqrt((double)H));
+  for (long long e = 0; e < H; ++e) w0[s->ow3 + e] = (float)(host_normal(s->rng) / std::sqrt((double)H));
+  std::vector<float> ones(F, 1.f);
+  int r = 0;
+  const long long NX = s->NX, Bm = s->Bmax, nf = s->nf;
+  r |= salloc(s, &s->shell, s->nq); r |= salloc(s, &s->wbin, s->nw); r |= salloc(s, &s->shell_off, s->nqb + 1);
+  r |= salloc(s, &s->shell_comp, s->nq); r |= salloc(s, &s->w_off, s->nwb + 1);
+  r |= salloc(s, &s->inv_cnt, s->nqb * s->nwb); r |= salloc(s, &s->twc, s->L); r |= salloc(s, &s->tws, s->L);
+  r |= salloc(s, &s->w, s->P); r |= salloc(s, &s->g, s->P); r |= salloc(s, &s->m, s->P); r |= salloc(s, &s->v, s->P);
+  r |= salloc(s, &s->mu, F); r |= salloc(s, &s->sig, F);
+  r |= salloc(s, &s->W1b, H * s->Fp); r |= salloc(s, &s->W2b, H * H); r |= salloc(s, &s->w3b, H);
+  r |= salloc(s, &s->dx_raw, (long long)s->cap * F); r |= salloc(s, &s->xall, (long long)s->cap * s->Fp);
+  r |= salloc(s, &s->yall, s->cap);
+  r |= salloc(s, &s->Xre, NX * 4 * s->nq * s->nw); r |= salloc(s, &s->Xim, NX * 4 * s->nq * s->nw);
+  r |= salloc(s, &s->feat, Bm * F); r |= salloc(s, &s->xb, Bm * s->Fp); r |= salloc(s, &s->yb, Bm);
+  r |= salloc(s, &s->a1, Bm * H); r |= salloc(s, &s->a2, Bm * H); r |= salloc(s, &s->out, Bm);
+  r |= salloc(s, &s->dout, Bm); r |= salloc(s, &s->dz2, Bm * H); r |= salloc(s, &s->dA1, Bm * H);
+  r |= salloc(s, &s->dz1, Bm * H); r |= salloc(s, &s->dX, Bm * s->Fp); r |= salloc(s, &s->gf, Bm * F);
+  r |= salloc(s, &s->a1b, Bm * H); r |= salloc(s, &s->a2b, Bm * H); r |= salloc(s, &s->dz2b, Bm * H);
+  r |= salloc(s, &s->dz1b, Bm * H); r |= salloc(s, &s->loss_acc, 4096);
+  r |= salloc(s, &s->phi_cur, NX * nf); r |= salloc(s, &s->phi_save, NX * nf); r |= salloc(s, &s->mom, NX * nf);
+  r |= salloc(s, &s->grad, NX * nf); r |= salloc(s, &s->prop, NX * nf); r |= salloc(s, &s->rp, NX * nf);
+  r |= salloc(s, &s->sumsq, NX); r |= salloc(s, &s->flag, NX);
+  if (r) { cfqmc_slmc_destroy(s); return CFQMC_ENOMEM; }
+  hipStream_t st = c->s;
+  bool ok = true;
+  ok &= hipMemcpyAsync(s->shell, sh.data(), sh.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->wbin, wb.data(), wb.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->shell_off, soff.data(), soff.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->shell_comp, scomp.data(), scomp.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->w_off, woff.data(), woff.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->inv_cnt, icnt.data(), icnt.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->twc, twc.data(), twc.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->tws, tws.data(), tws.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->w, w0.data(), w0.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipMemcpyAsync(s->sig, ones.data(), ones.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+  s->ybar = 0.0;
+  s->sy = 1.0;
+  slmc_refresh_bf16(s);
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  if (!ok || hipGetLastError() != hipSuccess) { c->err = "SLMC set-up failed"; cfqmc_slmc_destroy(s); return CFQMC_EHIP; }
+  *out = s;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_sizes(const cfqmc_slmc* s, int32_t* n_feat, int64_t* n_params, int32_t* n_data) {
+  if (!s) return CFQMC_EINVAL;
+  if (n_feat) *n_feat = s->F;
+  if (n_params) *n_params = s->P;
+  if (n_data) *n_data = s->n_data;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_set_params(cfqmc_slmc* s, const float* w) {
+  if (!s || !w) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  for (long long e = 0; e < s->P; ++e)
+    if (!std::isfinite(w[e])) { c->err = "non-finite parameter"; return CFQMC_EINVAL; }
+  HIPCHK(hipMemcpyAsync(s->w, w, s->P * sizeof(float), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemsetAsync(s->m, 0, s->P * sizeof(float), c->s));
+  HIPCHK(hipMemsetAsync(s->v, 0, s->P * sizeof(float), c->s));
+  s->t_adam = 0;
+  slmc_refresh_bf16(s);
+  HIPCHK(hipStreamSynchronize(c->s));
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_get_params(cfqmc_slmc* s, float* w) {
+  if (!s || !w) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(w, s->w, s->P * sizeof(float), hipMemcpyDeviceToHost));
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_set_norm(cfqmc_slmc* s, const float* mu, const float* sigma, double y_bar, double s_y) {
+  if (!s || !mu || !sigma || !(s_y > 0)) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  for (int j = 0; j < s->F; ++j)
+    if (!(sigma[j] > 0) || !std::isfinite(mu[j])) { c->err = "invalid standardisation"; return CFQMC_EINVAL; }
+  HIPCHK(hipMemcpyAsync(s->mu, mu, s->F * sizeof(float), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(s->sig, sigma, s->F * sizeof(float), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  s->ybar = y_bar;
+  s->sy = s_y;
+  s->norm_set = true;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_get_norm(cfqmc_slmc* s, float* mu, float* sigma, double* y_bar, double* s_y) {
+  if (!s) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (mu) HIPCHK(hipMemcpy(mu, s->mu, s->F * sizeof(float), hipMemcpyDeviceToHost));
+  if (sigma) HIPCHK(hipMemcpy(sigma, s->sig, s->F * sizeof(float), hipMemcpyDeviceToHost));
+  if (y_bar) *y_bar = s->ybar;
+  if (s_y) *s_y = s->sy;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_features(cfqmc_slmc* s, const double* phi, int32_t n, float* feat) {
+  if (!s || !phi || !feat || n < 0) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  for (int b0 = 0; b0 < n; b0 += s->NX) {
+    const int nb = std::min(s->NX, n - b0);
+    HIPCHK(hipMemcpyAsync(s->prop, phi + (long long)b0 * s->nf, nb * s->nf * sizeof(double), hipMemcpyHostToDevice,
+                          c->s));
+    slmc_features_dev(s, s->prop, s->nf, nb);
+    HIPCHK(hipStreamSynchronize(c->s));
+    HIPCHK(hipMemcpy(feat + (long long)b0 * s->F, s->feat, (long long)nb * s->F * sizeof(float),
+                     hipMemcpyDeviceToHost));
+  }
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_action(cfqmc_slmc* s, const double* phi, int32_t n, double* s_nn, double* grad_phi) {
+  if (!s || !phi || !s_nn || n < 0) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  std::vector<double> v;
+  for (int b0 = 0; b0 < n; b0 += s->NX) {
+    const int nb = std::min(s->NX, n - b0);
+    HIPCHK(hipMemcpyAsync(s->prop, phi + (long long)b0 * s->nf, nb * s->nf * sizeof(double), hipMemcpyHostToDevice,
+                          c->s));
+    const int rc = slmc_action_dev(s, s->prop, nb, v, grad_phi != nullptr);
+    if (rc) return rc;
+    for (int b = 0; b < nb; ++b) s_nn[b0 + b] = v[b];
+    if (grad_phi)
+      HIPCHK(hipMemcpy(grad_phi + (long long)b0 * s->nf, s->grad, nb * s->nf * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_loss_grad(cfqmc_slmc* s, const float* x, const double* y, int32_t n, double* loss, float* grad,
+                         float* out) {
+  if (!s || !x || !y || n < 1 || n > s->Bmax) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  hipStream_t st = c->s;
+  // standardised inputs as given (mu = 0, sigma = 1 path), rounded to BF16 by the kernel
+  std::vector<float> zero(s->F, 0.f), one(s->F, 1.f), yf(n);
+  for (int b = 0; b < n; ++b) yf[b] = (float)y[b];
+  float *mu0 = nullptr, *sg1 = nullptr;
+  // feat buffer holds x; temporary unit standardisation in gf scratch
+  HIPCHK(hipMemcpyAsync(s->feat, x, (long long)n * s->F * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->yb, yf.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+  mu0 = s->gf;
+  sg1 = s->gf + s->F;
+  HIPCHK(hipMemcpyAsync(mu0, zero.data(), s->F * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(sg1, one.data(), s->F * sizeof(float), hipMemcpyHostToDevice, st));
+  launch_slmc_standardize(s->feat, s->F, s->Fp, mu0, sg1, s->xb, n, st);
+  HIPCHK(hipMemsetAsync(s->loss_acc, 0, sizeof(double), st));
+  slmc_forward(s, s->xb, n);
+  launch_slmc_dout(s->out, s->yb, n, 0, 0.f, s->dout, s->loss_acc, st);
+  slmc_backward(s, s->xb, n, true, false);
+  HIPCHK(hipStreamSynchronize(st));
+  if (loss) HIPCHK(hipMemcpy(loss, s->loss_acc, sizeof(double), hipMemcpyDeviceToHost));
+  if (grad) HIPCHK(hipMemcpy(grad, s->g, s->P * sizeof(float), hipMemcpyDeviceToHost));
+  if (out) HIPCHK(hipMemcpy(out, s->out, n * sizeof(float), hipMemcpyDeviceToHost));
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_collect(cfqmc_slmc* s) {
+  if (!s) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  if (s->n_data + s->nch > s->cap) { c->err = "SLMC data set full"; return CFQMC_ESTATE; }
+  std::vector<double> re, im;
+  const int rc = lnw_all(c, re, im);
+  if (rc) return rc;
+  slmc_features_dev(s, c->phi, s->nf, s->nch);
+  HIPCHK(hipMemcpyAsync(s->dx_raw + (long long)s->n_data * s->F, s->feat, (long long)s->nch * s->F * sizeof(float),
+                        hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  for (int z = 0; z < s->nch; ++z) s->hy.push_back(-re[z]);
+  s->n_data += s->nch;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_clear_data(cfqmc_slmc* s) {
+  if (!s) return CFQMC_EINVAL;
+  s->n_data = 0;
+  s->hy.clear();
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_train(cfqmc_slmc* s, int32_t epochs, int32_t batch, double lr, int32_t refit_norm, double* loss_out) {
+  if (!s || epochs < 1 || epochs > 4096 || batch < 1 || batch > s->Bmax || !(lr > 0)) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  hipStream_t st = c->s;
+  const int n = s->n_data, F = s->F;
+  if (n < 2) { c->err = "SLMC data set needs at least two configurations"; return CFQMC_ESTATE; }
+  if (!s->norm_set || refit_norm) {
+    std::vector<float> fx((long long)n * F);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(fx.data(), s->dx_raw, fx.size() * sizeof(float), hipMemcpyDeviceToHost));
+    std::vector<float> mu(F), sg(F);
+    for (int j = 0; j < F; ++j) {
+      double a = 0.0, q = 0.0;
+      for (int b = 0; b < n; ++b) a += fx[(long long)b * F + j];
+      a /= n;
+      for (int b = 0; b < n; ++b) {
+        const double d = fx[(long long)b * F + j] - a;
+        q += d * d;
+      }
+      const double sd = std::sqrt(q / n);
+      mu[j] = (float)a;
+      sg[j] = sd > 1e-12 ? (float)sd : 1.f;
+    }
+    double a = 0.0, q = 0.0;
+    for (double v : s->hy) a += v;
+    a /= n;
+    for (double v : s->hy) q += (v - a) * (v - a);
+    const double sy = std::sqrt(q / n);
+    const int rc = cfqmc_slmc_set_norm(s, mu.data(), sg.data(), a, sy > 1e-12 ? sy : 1.0);
+    if (rc) return rc;
+  }
+  std::vector<float> ys(n);
+  for (int b = 0; b < n; ++b) ys[b] = (float)((s->hy[b] - s->ybar) / s->sy);
+  HIPCHK(hipMemcpyAsync(s->yall, ys.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+  launch_slmc_standardize(s->dx_raw, F, s->Fp, s->mu, s->sig, s->xall, n, st);
+  // minibatch order of every epoch (Fisher-Yates on the SLMC generator)
+  std::vector<int> order((long long)epochs * n);
+  for (int e = 0; e < epochs; ++e) {
+    int* o = order.data() + (long long)e * n;
+    for (int b = 0; b < n; ++b) o[b] = b;
+    for (int b = n - 1; b > 0; --b) std::swap(o[b], o[splitmix(s->rng) % (uint64_t)(b + 1)]);
+  }
+  int* idx = nullptr;
+  if (hipMalloc(&idx, order.size() * sizeof(int)) != hipSuccess) { c->err = "device allocation failed"; return CFQMC_ENOMEM; }
+  hipError_t e0 = hipMemcpyAsync(idx, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, st);
+  const int nbatches = (n + batch - 1) / batch;
+  const int nl = std::min(epochs, 4096);
+  hipMemsetAsync(s->loss_acc, 0, nl * sizeof(double), st);
+  for (int e = 0; e < epochs && e0 == hipSuccess; ++e)
+    for (int b0 = 0; b0 < n; b0 += batch) {
+      const int nb = std::min(batch, n - b0);
+      launch_slmc_gather(s->xall, s->yall, s->Fp, idx + (long long)e * n + b0, nb, s->xb, s->yb, st);
+      slmc_forward(s, s->xb, nb);
+      launch_slmc_dout(s->out, s->yb, nb, 0, 0.f, s->dout, s->loss_acc + e, st);
+      slmc_backward(s, s->xb, nb, true, false);
+      launch_slmc_adam(s->w, s->g, s->m, s->v, s->P, lr, ++s->t_adam, st);
+      slmc_refresh_bf16(s);
+    }
+  std::vector<double> la(nl);
+  const hipError_t e1 = hipStreamSynchronize(st);
+  hipFree(idx);
+  HIPCHK(e0);
+  HIPCHK(e1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpy(la.data(), s->loss_acc, nl * sizeof(double), hipMemcpyDeviceToHost));
+  if (loss_out) *loss_out = la[nl - 1] / nbatches;
+  if (!std::isfinite(la[nl - 1])) { c->err = "training diverged"; return CFQMC_ENUMERIC; }
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_global_move(cfqmc_slmc* s, int32_t n_traj, int32_t n_leap, double step, const double* replay,
+                           cfqmc_slmc_move* out) {
+  if (!s || n_traj < 1 || n_traj > 1024 || n_leap < 1 || n_leap > 100000 || !(step > 0)) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  hipStream_t st = c->s;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  const int B = s->nch;
+  const long long nf = s->nf, rs = (long long)n_traj * nf + n_traj + 1;
+  std::vector<double> lw0, li, lw1, snn0, snn_cur, snn_new, q0(B), p0(B), q1(B), p1(B);
+  int rc = lnw_all(c, lw0, li);
+  if (rc) return rc;
+  rc = slmc_action_dev(s, c->phi, B, snn0, false);
+  if (rc) return rc;
+  snn_cur = snn0;
+  HIPCHK(hipMemcpyAsync(s->phi_cur, c->phi, B * nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<int> inner(B, 0), flag(B, 0);
+  std::vector<double> maxdh(B, 0.0);
+  const uint64_t key = c->p.seed ^ 0x5851F42D4C957F2Dull;
+  for (int k = 0; k < n_traj; ++k) {
+    if (replay) {
+      HIPCHK(hipMemcpy2DAsync(s->rp, nf * sizeof(double), replay + (long long)k * nf, rs * sizeof(double),
+                              nf * sizeof(double), B, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    launch_slmc_momenta(s->mom, nf, B, key, s->move_counter * 1024 + k, replay ? s->rp : nullptr, nf, st);
+    launch_slmc_sumsq(s->phi_cur, nf, s->sumsq, B, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(q0.data(), s->sumsq, B * sizeof(double), hipMemcpyDeviceToHost));
+    launch_slmc_sumsq(s->mom, nf, s->sumsq, B, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(p0.data(), s->sumsq, B * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(s->prop, s->phi_cur, B * nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+    rc = slmc_action_dev(s, s->prop, B, snn_new, true);
+    if (rc) return rc;
+    launch_slmc_kick(s->mom, s->prop, s->grad, 0.5 * step, B * nf, st);
+    for (int l = 1; l <= n_leap; ++l) {
+      launch_slmc_drift(s->prop, s->mom, step, B * nf, st);
+      rc = slmc_action_dev(s, s->prop, B, snn_new, true);
+      if (rc) return rc;
+      launch_slmc_kick(s->mom, s->prop, s->grad, l < n_leap ? step : 0.5 * step, B * nf, st);
+    }
+    launch_slmc_sumsq(s->prop, nf, s->sumsq, B, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(q1.data(), s->sumsq, B * sizeof(double), hipMemcpyDeviceToHost));
+    launch_slmc_sumsq(s->mom, nf, s->sumsq, B, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(p1.data(), s->sumsq, B * sizeof(double), hipMemcpyDeviceToHost));
+    for (int z = 0; z < B; ++z) {
+      const double h0 = 0.5 * q0[z] + snn_cur[z] + 0.5 * p0[z];
+      const double h1 = 0.5 * q1[z] + snn_new[z] + 0.5 * p1[z];
+      const double dh = h1 - h0;
+      const double u = replay ? replay[(long long)z * rs + (long long)n_traj * nf + k] : host_uniform(s->rng);
+      flag[z] = std::isfinite(dh) && std::log(u) < -dh;
+      if (std::isfinite(dh)) maxdh[z] = std::max(maxdh[z], std::fabs(dh));
+      if (flag[z]) { snn_cur[z] = snn_new[z]; inner[z]++; }
+    }
+    HIPCHK(hipMemcpy(s->flag, flag.data(), B * sizeof(int), hipMemcpyHostToDevice));
+    launch_slmc_select(s->flag, 1, s->prop, s->phi_cur, nf, B, st);
+  }
+  // exact weight of the proposal from scratch (FP64), then the global test
+  HIPCHK(hipMemcpyAsync(s->phi_save, c->phi, B * nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(c->phi, s->phi_cur, B * nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(c->d_err, 0, sizeof(int), st));
+  rebuild_state(c);
+  int ef = 0;
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  rc = ef ? CFQMC_ENUMERIC : lnw_all(c, lw1, li);
+  if (rc == CFQMC_ENUMERIC) lw1.assign(B, -INFINITY);
+  else if (rc) return rc;
+  bool any_rej = false;
+  for (int z = 0; z < B; ++z) {
+    const double d_lnw = lw1[z] - lw0[z], d_snn = snn_cur[z] - snn0[z];
+    const double lnA = d_lnw + d_snn;
+    const double u = replay ? replay[(long long)z * rs + (long long)n_traj * nf + n_traj] : host_uniform(s->rng);
+    flag[z] = std::isfinite(lnA) && std::log(u) < lnA;
+    any_rej |= !flag[z];
+    if (out) {
+      out[z].accepted = flag[z];
+      out[z].inner_accepted = inner[z];
+      out[z].ln_a = lnA;
+      out[z].d_lnw = d_lnw;
+      out[z].d_snn = d_snn;
+      out[z].max_abs_dh = maxdh[z];
+    }
+  }
+  if (any_rej) {
+    HIPCHK(hipMemcpy(s->flag, flag.data(), B * sizeof(int), hipMemcpyHostToDevice));
+    launch_slmc_select(s->flag, 0, s->phi_save, c->phi, nf, B, st);
+    HIPCHK(hipMemsetAsync(c->d_err, 0, sizeof(int), st));
+    rebuild_state(c);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  s->move_counter++;
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_last_proposal(cfqmc_slmc* s, int32_t chain, double* phi_out) {
+  if (!s || !phi_out || chain < 0 || chain >= s->nch) return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(phi_out, s->phi_cur + (long long)chain * s->nf, s->nf * sizeof(double), hipMemcpyDeviceToHost));
   return CFQMC_OK;
 }
 

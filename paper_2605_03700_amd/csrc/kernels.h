@@ -154,3 +154,39 @@ void launch_background(const ModelDev& m, const double* phi, long long sphi_chai
                        double2* out, int nchain, hipStream_t s);
 // 4N expansion of the spin block
 void launch_expand4n(const double2* G, int n, double2* G4, hipStream_t s);
+
+// ---- learned global proposal (slmc.hip)
+void launch_slmc_dft(const double* phi, long long sphi, int L, int nq, int nw, const float* twc, const float* tws,
+                     float* Xre, float* Xim, long long sX, int nb, hipStream_t s);
+void launch_slmc_bin(const float* Xre, const float* Xim, long long sX, int nq, int nw, int L, int nqb, int nwb,
+                     const int* shell_off, const int* shell_comp, const int* w_off, float* feat, int F, int nb,
+                     hipStream_t s);
+void launch_slmc_standardize(const float* feat, int F, int Fp, const float* mu, const float* sig, uint16_t* xb,
+                             int nb, hipStream_t s);
+void launch_slmc_gemm(int at, int bt, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                      float* C, int ldc, const float* bias, int act, uint16_t* Cb, int ldcb, hipStream_t s);
+void launch_slmc_head(const uint16_t* a2b, int H, const uint16_t* w3b, const float* b3, float* out, int nb,
+                      hipStream_t s);
+void launch_slmc_dout(const float* out, const float* y, int nb, int mode, float const_d, float* dout, double* loss_acc,
+                      hipStream_t s);
+void launch_slmc_dz2(const float* dout, const uint16_t* w3b, const float* a2, int H, float* dz2, uint16_t* dz2b, int nb,
+                     hipStream_t s);
+void launch_slmc_tanh_bwd(const float* dA, const float* a, long long n, float* dz, uint16_t* dzb, hipStream_t s);
+void launch_slmc_colsum(const float* X, int nb, int H, float* out, hipStream_t s);
+void launch_slmc_head_grad(const float* dout, const uint16_t* a2b, int nb, int H, float* gw3, float* gb3,
+                           hipStream_t s);
+void launch_slmc_adam(float* p, const float* g, float* m, float* v, long long n, double lr, int t, hipStream_t s);
+void launch_slmc_to_bf16(const float* src, int rows, int cols, uint16_t* dst, int ldd, hipStream_t s);
+void launch_slmc_gather(const uint16_t* xall, const float* yall, int Fp, const int* idx, int nb, uint16_t* xb, float* yb,
+                        hipStream_t s);
+void launch_slmc_dx_to_gf(const float* dX, int Fp, const float* sig, int F, float scale, float* gf, int nb,
+                          hipStream_t s);
+void launch_slmc_vjp(const float* Xre, const float* Xim, long long sX, const float* gf, int F, int nq, int nw, int L,
+                     int nqb, int nwb, const int* shell, const int* wbin, const float* inv_cnt, const float* twc,
+                     const float* tws, double* grad, long long sg, int nb, hipStream_t s);
+void launch_slmc_momenta(double* p, long long n, int nb, uint64_t key, long long counter, const double* replay,
+                         long long s_replay, hipStream_t s);
+void launch_slmc_kick(double* p, const double* phi, const double* g, double h, long long n, hipStream_t s);
+void launch_slmc_drift(double* phi, const double* p, double h, long long n, hipStream_t s);
+void launch_slmc_sumsq(const double* x, long long n, double* out, int nb, hipStream_t s);
+void launch_slmc_select(const int* flag, int want, const double* src, double* dst, long long n, int nb, hipStream_t s);

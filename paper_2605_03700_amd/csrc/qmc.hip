@@ -18,40 +18,6 @@
 #include "common.h"
 #include "kernels.h"
 
-// ------------------------------------------------------------------ Philox4x32-10
-// Counter-based generator of Salmon, Moraes, Dror & Shaw (SC'11), 10 rounds.
-CF_DEV void philox_round(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
-  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-  const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-  c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-}
-CF_DEV void philox(uint32_t (&c)[4], uint64_t seed) {
-  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    philox_round(c, k0, k1);
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-CF_DEV double u53(uint32_t a, uint32_t b) { return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0); }
-// Normal number j of stream (chain, counter) by Box-Muller on one Philox block.
-CF_DEV double rng_normal(uint64_t seed, int chain, long long counter, int j) {
-  uint32_t c[4] = {(uint32_t)(j >> 1), (uint32_t)counter, (uint32_t)(counter >> 32), (uint32_t)chain};
-  philox(c, seed);
-  const double u1 = 1.0 - u53(c[0], c[1]), u2 = u53(c[2], c[3]);
-  const double r = sqrt(-2.0 * log(u1));
-  return (j & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
-}
-CF_DEV double rng_uniform(uint64_t seed, int chain, long long counter) {
-  uint32_t c[4] = {0x7fffffffu, (uint32_t)counter, (uint32_t)(counter >> 32), (uint32_t)chain};
-  philox(c, seed);
-  return u53(c[0], c[1]);
-}
-
 // ------------------------------------------------------------------ build_h
 // One workgroup per (shift d, channel, batch entry): the terms whose matrix
 // has its nonzeros on the diagonal col = row - d (mod N) are staged in LDS with
