@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--u", type=float, default=1.5)
     ap.add_argument("--n-stab", type=int, default=8)
     ap.add_argument("--chains", type=int, default=1)
+    ap.add_argument("--groups", type=int, default=1, help="split the chains over this many streams")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
     ap.add_argument("--workload", choices=["c3", "batched"], default="c3",
                     help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid")
@@ -76,22 +77,26 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_2605_03700_amd import CFQMC, FP64, MIXED, MIXED_ALL
+    from paper_2605_03700_amd import Batch, FP64, MIXED, MIXED_ALL
     from paper_2605_03700_amd.analysis import tau_int
     assert torch.cuda.is_available(), "needs the GPU"
     prec = {"fp64": FP64, "mixed": MIXED, "mixed_all": MIXED_ALL}[args.precision]
     if args.workload == "batched":
         return bench_batched(args, prec)
-    g = CFQMC(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
-              n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3,
-              n_chains=args.chains, tile_cfg=args.tile_cfg)
-    g.init_fields(None)
+    if args.chains % args.groups:
+        raise SystemExit("--chains must be a multiple of --groups")
+    nper = args.chains // args.groups
+    b = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+                    n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
+                    tile_cfg=args.tile_cfg) for k in range(args.groups)])
+    g = b.groups[0]
+    b.init_fields()
     if args.warmup:
-        g.sweep(args.warmup)
+        b.sweep(args.warmup)
     torch.cuda.synchronize()
     g.kernel_timing(True)
     t0 = time.perf_counter()
-    st = g.sweep(args.steps)
+    st = b.sweep(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms, k_count, k_flops = g.kernel_timing_read()
@@ -106,13 +111,14 @@ def main():
         "value": value, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == FP64 else "f32+f64", "data": "synthetic",
-        "config": {"workload": "torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chain(s), "
-                               "recompute every %d slices" % (args.n_phi, args.l_tau, args.dtau, args.u, g.n_q,
-                                                              args.chains, args.n_stab),
-                   "chains": args.chains, "precision": args.precision, "n_q": g.n_q,
+        "config": {"workload": "torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chain(s) in %d "
+                               "stream group(s), recompute every %d slices"
+                               % (args.n_phi, args.l_tau, args.dtau, args.u, g.n_q, args.chains, args.groups,
+                                  args.n_stab),
+                   "chains": args.chains, "groups": args.groups, "precision": args.precision, "n_q": g.n_q,
                    "tile_cfg": list(g.tile_config())},
         "acceptance": acc,
-        "eps": float(np.mean(g.get_eps())),
+        "eps": float(np.mean(np.concatenate([q.get_eps() for q in b.groups]))),
         "g_err_max": g_err,
         "sweeps_per_s_per_chain": sweeps_per_s,
     }
@@ -123,18 +129,17 @@ def main():
                            "traffic": None, "avg_launch_ms": k_ms, "launches_timed": k_count,
                            "flops_per_launch": k_flops}
     if args.tau_sweeps > 0:
-        g.set_eps(g.get_eps())
-        n0 = len(g.series(0))
+        n0 = [len(q.series(0)) for q in b.groups]
         t1 = time.perf_counter()
-        g.sweep(args.tau_sweeps)
+        b.sweep(args.tau_sweeps)
         dt2 = time.perf_counter() - t1
-        taus = [tau_int(g.series(k)[n0:])[0] for k in range(args.chains)]
+        taus = [tau_int(q.series(k)[n0[i]:])[0] for i, q in enumerate(b.groups) for k in range(nper)]
         tau = float(np.mean(taus))
         out["tau_int_sweeps"] = tau
         out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds)
-    g.close()
+    b.close()
     print(json.dumps(out))
 
 

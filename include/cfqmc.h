@@ -81,7 +81,8 @@ typedef struct {
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential (default 2) */
-  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..3 fixed configuration */
+  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..7 fixed channel-application
+                            configuration (GEMMs use min(tile_cfg, 3)) */
 } cfqmc_params;
 
 typedef struct {

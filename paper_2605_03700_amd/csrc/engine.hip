@@ -670,14 +670,16 @@ int autotune(cfqmc_ctx* c) {
     hipEventElapsedTime(&ms, e0, e1);
     return ms;
   };
-  for (int cfg = 0; cfg < 4; ++cfg) {
+  for (int cfg = 0; cfg < CFQMC_CHAN_CFGS; ++cfg) {
     c->cfg_chan = cfg;
-    c->cfg_gemm = cfg;
     const float tc = timeit([&]() {
       chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
       chan(c, 0, 2, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, c->mixed);
     });
     if (tc < best_c) { best_c = tc; bc = cfg; }
+  }
+  for (int cfg = 0; cfg < CFQMC_GEMM_CFGS; ++cfg) {
+    c->cfg_gemm = cfg;
     const float tg = timeit([&]() { gemm_nn(c, c->F[0], 0, c->nn, c->F[1], 0, c->nn, c->S1, c->nn, c->nch); });
     if (tg < best_g) { best_g = tg; bg = cfg; }
     const float ts = timeit([&]() {
@@ -720,7 +722,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   const cfqmc_params& p = *pin;
   if (p.n_phi < 1 || p.n_phi > 140 || p.l_tau < 1 || !(p.dtau > 0) || p.n_chains < 1 || p.n_stab < 1 ||
       !(p.eps0 > 0) || p.eps_min <= 0 || p.eps_max < p.eps_min || p.exp_squarings < 0 || p.exp_squarings > 8 ||
-      (p.precision < CFQMC_FP64 || p.precision > CFQMC_MIXED_ALL) || p.tile_cfg < -1 || p.tile_cfg > 3)
+      (p.precision < CFQMC_FP64 || p.precision > CFQMC_MIXED_ALL) || p.tile_cfg < -1 || p.tile_cfg >= CFQMC_CHAN_CFGS)
     return CFQMC_EINVAL;
   cfqmc_ctx* c = new cfqmc_ctx();
   c->p = p;
@@ -823,7 +825,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
     cfqmc_destroy(c);
     return CFQMC_EHIP;
   }
-  c->cfg_chan = c->cfg_gemm = (p.tile_cfg >= 0 ? p.tile_cfg : 1);
+  c->cfg_chan = p.tile_cfg >= 0 ? p.tile_cfg : 1;
+  c->cfg_gemm = p.tile_cfg >= 0 ? std::min(p.tile_cfg, CFQMC_GEMM_CFGS - 1) : 1;
   c->cfg_small = 0;
   if (hipStreamSynchronize(c->s) != hipSuccess) { cfqmc_destroy(c); return CFQMC_EHIP; }
   if (p.tile_cfg < 0) autotune(c);

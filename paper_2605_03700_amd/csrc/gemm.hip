@@ -36,13 +36,13 @@ struct Acc {
 };
 
 // One BK-deep slab of wave-tile products from LDS (As[k][m], Bs[k][n]).
-template <typename CT, int WTM, int WTN>
+template <typename CT, int WTM, int WTN, int KD = BK>
 CF_DEV void mma_slab(const typename cplx_t<CT>::type* As, int lda, const typename cplx_t<CT>::type* Bs, int ldb,
                      int wm0, int wn0, int lane, Acc<CT, WTM, WTN>& acc) {
   typedef typename cplx_t<CT>::type C2;
   const int il = lane & 15, kl = lane >> 4;
 #pragma unroll
-  for (int kk = 0; kk < BK; kk += 4) {
+  for (int kk = 0; kk < KD; kk += 4) {
     C2 a[WTM], b[WTN];
 #pragma unroll
     for (int s = 0; s < WTM; ++s) a[s] = As[(kk + kl) * lda + wm0 + s * 16 + il];
@@ -186,16 +186,38 @@ zgemm_kernel(GemmArgs g) {
 
 // ------------------------------------------------------------------ chan_apply
 
-template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN>
+// Tile order: the hardware hands consecutive workgroups to the eight XCDs in
+// turn, so logical tile t = (b % 8) * ceil(T/8) + b / 8 gives every XCD a
+// contiguous range of (chain, row tile, column tile): the tiles of one chain
+// share that XCD's L2.
+CF_DEV bool xcd_tile(int tiles_x, int tiles_y, int nbatch, int& z, int& ty, int& tx) {
+  const int T = tiles_x * tiles_y * nbatch;
+  const int per = (T + 7) / 8;
+  const int b = blockIdx.x;
+  const int t = (b % 8) * per + b / 8;
+  if (t >= T) return false;
+  z = t / (tiles_x * tiles_y);
+  const int r = t % (tiles_x * tiles_y);
+  ty = r / tiles_x;
+  tx = r % tiles_x;
+  return true;
+}
+
+// BKC: k slab depth. DB: two LDS stages and one barrier per slab (the global
+// loads of slab k+1 and the LDS stores into the other stage overlap the MFMAs
+// of slab k); otherwise one stage with register prefetch and two barriers.
+template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
-chan_apply_kernel(ChanArgs c) {
+chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   typedef typename cplx_t<CT>::type C2;
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
   constexpr int NT = WX * WY * 64;
-  __shared__ C2 As[2][BK * BM];
-  __shared__ C2 Bs[2][BK * BN];
-  const int z = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  constexpr int NS = DB ? 2 : 1;
+  __shared__ C2 As[NS][2][BKC * BM];
+  __shared__ C2 Bs[NS][2][BKC * BN];
+  int z, ty, tx;
+  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
   constexpr bool CORR = sizeof(CT) == 4;   // correction form in the mixed path
@@ -217,9 +239,8 @@ chan_apply_kernel(ChanArgs c) {
     return v;
   };
 
-  // Staging with register prefetch: the global loads of slab k0+BK are in flight
-  // while slab k0 is multiplied out of LDS.
-  constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+  constexpr int EA = BM * BKC / NT, EB = BN * BKC / NT;
+  static_assert(EA * NT == BM * BKC && EB * NT == BN * BKC, "tile / thread mismatch");
   double2 ra[EA][2], rb[EB][2];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -227,7 +248,7 @@ chan_apply_kernel(ChanArgs c) {
       const int idx = tid + e * NT;
       if (LEFT) {
         int m, k;
-        if (c.opX == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+        if (c.opX == 0) { k = idx % BKC; m = idx / BKC; } else { m = idx % BM; k = idx / BM; }
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           double2 v = make_double2(0.0, 0.0);
@@ -239,7 +260,7 @@ chan_apply_kernel(ChanArgs c) {
           ra[e][a] = v;
         }
       } else {
-        const int k = idx % BK, m = idx / BK;
+        const int k = idx % BKC, m = idx / BKC;
         ra[e][0] = ra[e][1] = make_double2(0.0, 0.0);
         if (m0 + m < rows && k0 + k < N) {
           ra[e][0] = mload(m0 + m, k0 + k);
@@ -259,7 +280,7 @@ chan_apply_kernel(ChanArgs c) {
         }
       } else {
         int n, k;
-        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
+        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BKC; n = idx / BKC; }
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           double2 v = make_double2(0.0, 0.0);
@@ -273,25 +294,25 @@ chan_apply_kernel(ChanArgs c) {
       }
     }
   };
-  // rotate (conj(U_ba) for LEFT, U_ba for RIGHT) and store to LDS
-  auto stage = [&]() {
+  // rotate (conj(U_ba) for LEFT, U_ba for RIGHT) and store to LDS stage st
+  auto stage = [&](int st) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * NT;
       int m, k;
       if (LEFT) {
-        if (c.opX == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
-        As[0][k * BM + m] = to_ct<CT>(ra[e][0]);
-        As[1][k * BM + m] = to_ct<CT>(ra[e][1]);
+        if (c.opX == 0) { k = idx % BKC; m = idx / BKC; } else { m = idx % BM; k = idx / BM; }
+        As[st][0][k * BM + m] = to_ct<CT>(ra[e][0]);
+        As[st][1][k * BM + m] = to_ct<CT>(ra[e][1]);
       } else {
-        k = idx % BK; m = idx / BK;
+        k = idx % BKC; m = idx / BKC;
         if (ROT) {
 #pragma unroll
           for (int a = 0; a < 2; ++a)
-            As[a][k * BM + m] = to_ct<CT>(cadd(cmul(u[0][a], ra[e][0]), cmul(u[1][a], ra[e][1])));
+            As[st][a][k * BM + m] = to_ct<CT>(cadd(cmul(u[0][a], ra[e][0]), cmul(u[1][a], ra[e][1])));
         } else {
-          As[0][k * BM + m] = to_ct<CT>(ra[e][0]);
-          As[1][k * BM + m] = to_ct<CT>(ra[e][1]);
+          As[st][0][k * BM + m] = to_ct<CT>(ra[e][0]);
+          As[st][1][k * BM + m] = to_ct<CT>(ra[e][1]);
         }
       }
     }
@@ -304,39 +325,56 @@ chan_apply_kernel(ChanArgs c) {
         if (ROT) {
 #pragma unroll
           for (int a = 0; a < 2; ++a)
-            Bs[a][k * BN + n] = to_ct<CT>(cadd(cmul(u[0][a], rb[e][0]), cmul(u[1][a], rb[e][1])));
+            Bs[st][a][k * BN + n] = to_ct<CT>(cadd(cmul(u[0][a], rb[e][0]), cmul(u[1][a], rb[e][1])));
         } else {
-          Bs[0][k * BN + n] = to_ct<CT>(rb[e][0]);
-          Bs[1][k * BN + n] = to_ct<CT>(rb[e][1]);
+          Bs[st][0][k * BN + n] = to_ct<CT>(rb[e][0]);
+          Bs[st][1][k * BN + n] = to_ct<CT>(rb[e][1]);
         }
       } else {
-        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
-        Bs[0][k * BN + n] = to_ct<CT>(rb[e][0]);
-        Bs[1][k * BN + n] = to_ct<CT>(rb[e][1]);
+        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BKC; n = idx / BKC; }
+        Bs[st][0][k * BN + n] = to_ct<CT>(rb[e][0]);
+        Bs[st][1][k * BN + n] = to_ct<CT>(rb[e][1]);
       }
     }
   };
-
   Acc<double, WTM, WTN> acc[2];
   acc[0].zero();
   acc[1].zero();
-  fetch(0);
-  for (int k0 = 0; k0 < N; k0 += BK) {
-    stage();
-    __syncthreads();
-    if (k0 + BK < N) fetch(k0 + BK);
+  auto mma = [&](int st) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if constexpr (sizeof(CT) == 8) {
-        mma_slab<double, WTM, WTN>((const double2*)As[a], BM, (const double2*)Bs[a], BN, wm0, wn0, lane, acc[a]);
+        mma_slab<double, WTM, WTN, BKC>((const double2*)As[st][a], BM, (const double2*)Bs[st][a], BN, wm0, wn0, lane,
+                                        acc[a]);
       } else {
         Acc<float, WTM, WTN> a32;
         a32.zero();
-        mma_slab<float, WTM, WTN>((const float2*)As[a], BM, (const float2*)Bs[a], BN, wm0, wn0, lane, a32);
+        mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], BM, (const float2*)Bs[st][a], BN, wm0, wn0, lane, a32);
         flush(a32, acc[a]);
       }
     }
+  };
+  fetch(0);
+  if (DB) {
+    stage(0);
     __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < N; k0 += BKC) {
+      const bool more = k0 + BKC < N;
+      if (more) fetch(k0 + BKC);
+      mma(cur);
+      if (more) stage(cur ^ (NS - 1));
+      __syncthreads();
+      cur ^= (NS - 1);
+    }
+  } else {
+    for (int k0 = 0; k0 < N; k0 += BKC) {
+      stage(0);
+      __syncthreads();
+      if (k0 + BKC < N) fetch(k0 + BKC);
+      mma(0);
+      __syncthreads();
+    }
   }
   // combine T_0, T_1 into the two valley blocks of the output
   double2* Y = c.Y + z * c.sY;
@@ -402,40 +440,44 @@ void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t
   }
 }
 
-template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN>
+template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
 static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
   constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
   const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
-  dim3 grid((cols + BN - 1) / BN, (rows + BM - 1) / BM, nbatch);
-  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROT, BM, BN, WTM, WTN>), grid, dim3(NT), 0, s, c); cfqmc_post_launch("chan_apply_kernel");
+  const int tx = (cols + BN - 1) / BN, ty = (rows + BM - 1) / BM;
+  const long long T = (long long)tx * ty * nbatch;
+  const int nblk = (int)((T + 7) / 8 * 8);
+  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROT, BM, BN, WTM, WTN, BKC, DB>), dim3(nblk), dim3(NT), 0, s, c, tx,
+                     ty, nbatch); cfqmc_post_launch("chan_apply_kernel");
 }
 
-template <typename CT, int BM, int BN, int WTM, int WTN>
+template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
 static void run_chan_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
   if (left) {
-    if (rot) run_chan<CT, true, true, BM, BN, WTM, WTN>(c, nbatch, s);
-    else run_chan<CT, true, false, BM, BN, WTM, WTN>(c, nbatch, s);
+    if (rot) run_chan<CT, true, true, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else run_chan<CT, true, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
   } else {
-    if (rot) run_chan<CT, false, true, BM, BN, WTM, WTN>(c, nbatch, s);
-    else run_chan<CT, false, false, BM, BN, WTM, WTN>(c, nbatch, s);
+    if (rot) run_chan<CT, false, true, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else run_chan<CT, false, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+  }
+}
+
+template <typename CT>
+static void chan_cfg(const ChanArgs& c, int left, int rot, int nbatch, int cfg, hipStream_t s) {
+  switch (cfg) {
+    case 0: run_chan_any<CT, 16, 16, 1, 1, 16, false>(c, left, rot, nbatch, s); break;
+    case 1: run_chan_any<CT, 32, 32, 1, 1, 16, false>(c, left, rot, nbatch, s); break;
+    case 2: run_chan_any<CT, 32, 32, 1, 1, 8, true>(c, left, rot, nbatch, s); break;
+    case 3: run_chan_any<CT, 32, 32, 1, 1, 16, true>(c, left, rot, nbatch, s); break;
+    case 4: run_chan_any<CT, 64, 32, 1, 1, 16, true>(c, left, rot, nbatch, s); break;
+    case 5: run_chan_any<CT, 32, 64, 1, 1, 16, true>(c, left, rot, nbatch, s); break;
+    case 6: run_chan_any<CT, 64, 64, 2, 2, 8, true>(c, left, rot, nbatch, s); break;
+    default: run_chan_any<CT, 16, 16, 1, 1, 8, true>(c, left, rot, nbatch, s); break;
   }
 }
 
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s) {
   if (nbatch <= 0) return;
-  if (mixed) {
-    switch (cfg) {
-      case 0: run_chan_any<float, 16, 16, 1, 1>(c, left, rot, nbatch, s); break;
-      case 1: run_chan_any<float, 32, 32, 1, 1>(c, left, rot, nbatch, s); break;
-      case 2: run_chan_any<float, 32, 32, 2, 2>(c, left, rot, nbatch, s); break;
-      default: run_chan_any<float, 64, 64, 2, 2>(c, left, rot, nbatch, s); break;
-    }
-  } else {
-    switch (cfg) {
-      case 0: run_chan_any<double, 16, 16, 1, 1>(c, left, rot, nbatch, s); break;
-      case 1: run_chan_any<double, 32, 32, 1, 1>(c, left, rot, nbatch, s); break;
-      case 2: run_chan_any<double, 32, 32, 2, 2>(c, left, rot, nbatch, s); break;
-      default: run_chan_any<double, 64, 64, 2, 2>(c, left, rot, nbatch, s); break;
-    }
-  }
+  if (mixed) chan_cfg<float>(c, left, rot, nbatch, cfg, s);
+  else chan_cfg<double>(c, left, rot, nbatch, cfg, s);
 }

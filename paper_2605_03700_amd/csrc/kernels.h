@@ -37,6 +37,9 @@ struct ChanArgs {
   double2* Y2;              // optional second copy of the output (same layout as Y)
 };
 
+// Tile configurations: zgemm 0..3; chan_apply 0..7 (a fixed tile_cfg applies to both).
+#define CFQMC_GEMM_CFGS 4
+#define CFQMC_CHAN_CFGS 8
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);
 

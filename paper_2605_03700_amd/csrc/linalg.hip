@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(LU_NT) lu_kernel(double2* Aall, int n, int lda
 
 CF_DEV void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-__global__ void __launch_bounds__(NP_NT) lu_np_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
+__global__ void __launch_bounds__(NP_NT) lu_np_global_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
                                                       int sP, double2* logdet, int* flag_all, double lmax_allowed) {
   __shared__ double2 D[NP_NB][NP_NB];
   __shared__ double2 Li[NP_NB][NP_NB], Ui[NP_NB][NP_NB];
@@ -483,10 +483,224 @@ __global__ void __launch_bounds__(NP_NT) lu_np_kernel(double2* Aall, int n, int 
   }
 }
 
+
+
+// Same factorisation with the panel in LDS: the solved L21 (rows x 16, rows
+// padded to 17 entries against bank conflicts) and U12 (16 x columns) of each
+// panel are kept in LDS, so every trailing tile reads only its own A tile from
+// memory; 16 waves share the tiles.
+#define NP2_NT 1024
+#define NP2_LD 17
+__global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
+                                                       int sP, double2* logdet, int* flag_all, double lmax_allowed) {
+  extern __shared__ double2 pan[];
+  __shared__ double2 D[NP_NB][NP_NB];
+  __shared__ double2 Li[NP_NB][NP_NB], Ui[NP_NB][NP_NB];
+  __shared__ double2 diag[LU_MAXN];
+  __shared__ double red[NP2_NT / 64][3];
+  const int capr = n > NP_NB ? n - NP_NB : 1;   // rows of L21 / columns of U12 held
+  double2* L21s = pan;                          // [capr][NP2_LD]
+  double2* U12s = pan + (long long)capr * NP2_LD;   // [NP_NB][capr]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int il = lane & 15, kl = lane >> 4;
+  constexpr int NW = NP2_NT / 64;
+  double2* A = Aall + blockIdx.x * sA;
+  double lmax = 0.0;
+  for (int k0 = 0; k0 < n; k0 += NP_NB) {
+    const int nb = min(NP_NB, n - k0);
+    if (tid < NP_NB * NP_NB) {
+      const int r = tid / NP_NB, c = tid % NP_NB;
+      D[r][c] = (r < nb && c < nb) ? A[(long long)(k0 + r) * lda + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    if (wid == 0) {
+      for (int j = 0; j < nb; ++j) {
+        const double2 inv = cdiv(make_double2(1.0, 0.0), D[j][j]);
+        double2 nv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = lane + 64 * q, r = e / NP_NB, c = e % NP_NB;
+          nv[q] = D[r][c];
+          if (r > j) {
+            const double2 l = cmul(D[r][j], inv);
+            if (c == j) nv[q] = l;
+            else if (c > j) nv[q] = csub(nv[q], cmul(l, D[j][c]));
+          }
+        }
+        lds_order();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = lane + 64 * q;
+          D[e / NP_NB][e % NP_NB] = nv[q];
+        }
+        lds_order();
+      }
+    }
+    __syncthreads();
+    if (wid == 0 && lane < NP_NB) {
+      const int t = lane;
+      for (int i = 0; i < NP_NB; ++i) {
+        double2 x = make_double2(i == t ? 1.0 : 0.0, 0.0);
+        if (i < nb)
+          for (int l = 0; l < i; ++l) x = csub(x, cmul(D[i][l], Li[l][t]));
+        Li[i][t] = x;
+      }
+    } else if (wid == 1 && lane < NP_NB) {
+      const int t = lane;
+      for (int i = NP_NB - 1; i >= 0; --i) {
+        double2 x = make_double2(i == t ? 1.0 : 0.0, 0.0);
+        if (i < nb) {
+          for (int l = i + 1; l < NP_NB; ++l) x = csub(x, cmul(D[i][l], Ui[l][t]));
+          x = cdiv(x, D[i][i]);
+        }
+        Ui[i][t] = x;
+      }
+    } else if (wid == 2) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, r = e / NP_NB, c = e % NP_NB;
+        if (r < nb && c < nb) {
+          const double2 v = D[r][c];
+          A[(long long)(k0 + r) * lda + k0 + c] = v;
+          if (r > c) lmax = fmax(lmax, sqrt(cabs2(v)));
+          if (r == c) diag[k0 + r] = v;
+        }
+      }
+    }
+    __syncthreads();
+    const int t0 = k0 + nb, rem = n - t0;
+    if (rem > 0) {
+      // panel solves: U12 = L11^{-1} A12 (column tiles), L21 = A21 U11^{-1} (row tiles)
+      const int nt = (rem + 15) / 16;
+      for (int task = wid; task < 2 * nt; task += NW) {
+        d4v cre = Mfma<double>::zero(), cim = Mfma<double>::zero();
+        const int tt = task % nt, o0 = t0 + tt * 16;
+        if (task < nt) {
+          double2 b[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            b[kk] = (k < nb && o0 + il < n) ? A[(long long)(k0 + k) * lda + o0 + il] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double2 a = Li[il][kk * 4 + kl];
+            cre = Mfma<double>::mma(a.x, b[kk].x, cre);
+            cre = Mfma<double>::mma(-a.y, b[kk].y, cre);
+            cim = Mfma<double>::mma(a.x, b[kk].y, cim);
+            cim = Mfma<double>::mma(a.y, b[kk].x, cim);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = Mfma<double>::row(lane, q), jc = o0 + il;
+            if (jc < n) {
+              const double2 v = i < nb ? make_double2(cre[q], cim[q]) : make_double2(0.0, 0.0);
+              if (i < nb) A[(long long)(k0 + i) * lda + jc] = v;
+              U12s[(long long)i * capr + (jc - t0)] = v;
+            }
+          }
+        } else {
+          double2 a[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = kk * 4 + kl;
+            a[kk] = (k < nb && o0 + il < n) ? A[(long long)(o0 + il) * lda + k0 + k] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double2 b = Ui[kk * 4 + kl][il];
+            cre = Mfma<double>::mma(a[kk].x, b.x, cre);
+            cre = Mfma<double>::mma(-a[kk].y, b.y, cre);
+            cim = Mfma<double>::mma(a[kk].x, b.y, cim);
+            cim = Mfma<double>::mma(a[kk].y, b.x, cim);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = o0 + Mfma<double>::row(lane, q), jc = il;
+            if (i < n) {
+              const double2 v = jc < nb ? make_double2(cre[q], cim[q]) : make_double2(0.0, 0.0);
+              if (jc < nb) {
+                A[(long long)i * lda + k0 + jc] = v;
+                lmax = fmax(lmax, sqrt(cabs2(v)));
+              }
+              L21s[(long long)(i - t0) * NP2_LD + jc] = v;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // trailing update A22 -= L21 U12, one 16 x 16 tile per wave per pass
+      const int ntt = nt * nt;
+      for (int t = wid; t < ntt; t += NW) {
+        const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
+        d4v cre, cim;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int i = t0 + r0 + Mfma<double>::row(lane, rr), jc = t0 + c0 + il;
+          const double2 v = (i < n && jc < n) ? A[(long long)i * lda + jc] : make_double2(0.0, 0.0);
+          cre[rr] = v.x;
+          cim[rr] = v.y;
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = kk * 4 + kl;
+          const double2 a = r0 + il < rem ? L21s[(long long)(r0 + il) * NP2_LD + k] : make_double2(0.0, 0.0);
+          const double2 b = c0 + il < rem ? U12s[(long long)k * capr + c0 + il] : make_double2(0.0, 0.0);
+          cre = Mfma<double>::mma(-a.x, b.x, cre);
+          cre = Mfma<double>::mma(a.y, b.y, cre);
+          cim = Mfma<double>::mma(-a.x, b.y, cim);
+          cim = Mfma<double>::mma(-a.y, b.x, cim);
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int i = t0 + r0 + Mfma<double>::row(lane, rr), jc = t0 + c0 + il;
+          if (i < n && jc < n) A[(long long)i * lda + jc] = make_double2(cre[rr], cim[rr]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += NP2_NT) ipiv_all[blockIdx.x * sP + i] = i;
+  double lr = 0.0, li = 0.0;
+  for (int i = tid; i < n; i += NP2_NT) {
+    const double2 d = diag[i];
+    lr += 0.5 * log(cabs2(d));
+    li += atan2(d.y, d.x);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lr += __shfl_xor(lr, o, 64);
+    li += __shfl_xor(li, o, 64);
+    lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
+  }
+  if (lane == 0) { red[wid][0] = lr; red[wid][1] = li; red[wid][2] = lmax; }
+  __syncthreads();
+  if (tid == 0) {
+    lr = 0.0; li = 0.0; lmax = 0.0;
+    for (int w = 0; w < NW; ++w) { lr += red[w][0]; li += red[w][1]; lmax = fmax(lmax, red[w][2]); }
+    const bool bad = !(lmax <= lmax_allowed) || !isfinite(lr);
+    if (flag_all) flag_all[blockIdx.x] = bad ? 1 : 0;
+    if (logdet) {
+      double im = fmod(li, 2.0 * M_PI);
+      if (im > M_PI) im -= 2.0 * M_PI;
+      if (im <= -M_PI) im += 2.0 * M_PI;
+      logdet[blockIdx.x] = make_double2(lr, im);
+    }
+  }
+}
+
+static bool set_lds_limit(const void* fn, size_t shm);
+
 void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int* flag,
                   double lmax_allowed, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(lu_np_kernel, dim3(nbatch), dim3(NP_NT), 0, s, A, n, lda, sA, ipiv, sP, logdet, flag,
-                     lmax_allowed); cfqmc_post_launch("lu_np_kernel");
+  const int capr = n > NP_NB ? n - NP_NB : 1;
+  const size_t shm = (size_t)capr * (NP2_LD + NP_NB) * sizeof(double2);
+  if (n <= LU_MAXN && set_lds_limit((const void*)lu_np_kernel, shm)) {
+    hipLaunchKernelGGL(lu_np_kernel, dim3(nbatch), dim3(NP2_NT), shm, s, A, n, lda, sA, ipiv, sP, logdet, flag,
+                       lmax_allowed); cfqmc_post_launch("lu_np_kernel");
+  } else {
+    hipLaunchKernelGGL(lu_np_global_kernel, dim3(nbatch), dim3(NP_NT), 0, s, A, n, lda, sA, ipiv, sP, logdet, flag,
+                       lmax_allowed); cfqmc_post_launch("lu_np_global_kernel");
+  }
 }
 
 // Allow more than 64 KB of dynamic LDS (gfx950 has 160 KB per workgroup); returns false if refused.
@@ -514,14 +728,15 @@ void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, doub
 // block is solved wave-synchronously with shuffles.
 #define RS_ROWS 16
 #define RS_NT 256
-#define RS_MAXIT 18
+#define RS_NW (RS_NT / 64)
+#define RS_MAXIT ((LU_MAXN + 4 * RS_NW - 1) / (4 * RS_NW))
 
 __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
                                                        int ldy, long long sY, const double2* LUall, int ldlu,
                                                        long long sLU, const int* ipiv_all, int sP, int n,
                                                        int upper_only) {
   extern __shared__ double2 Zs[];          // 16 x n row block
-  __shared__ double2 red[4][16][16];
+  __shared__ double2 red[RS_NW][16][16];
   __shared__ double2 Db[16][16];           // diagonal block of U or L
   __shared__ int perm[LU_MAXN];
   const int z = blockIdx.y;
@@ -551,14 +766,14 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
       double2 bb[RS_MAXIT];
 #pragma unroll
       for (int it = 0; it < RS_MAXIT; ++it) {
-        const int k = klo + wid * 4 + it * 16 + kl;
+        const int k = klo + wid * 4 + it * 4 * RS_NW + kl;
         bb[it] = (k < khi && il < bw) ? LU[(long long)perm[k] * ldlu + c0 + il] : make_double2(0.0, 0.0);
       }
       d4v are = Mfma<double>::zero(), aim = Mfma<double>::zero();
 #pragma unroll
       for (int it = 0; it < RS_MAXIT; ++it) {
-        const int k = klo + wid * 4 + it * 16 + kl;
-        if (klo + wid * 4 + it * 16 < khi) {
+        const int k = klo + wid * 4 + it * 4 * RS_NW + kl;
+        if (klo + wid * 4 + it * 4 * RS_NW < khi) {
           const double2 a = k < khi ? Zs[il * n + k] : make_double2(0.0, 0.0);
           const double2 b = bb[it];
           are = Mfma<double>::mma(a.x, b.x, are);
@@ -569,12 +784,18 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wid][Mfma<double>::row(lane, q)][il] = make_double2(are[q], aim[q]);
-      Db[rr][cc] = (rr < bw && cc < bw) ? LU[(long long)perm[c0 + rr] * ldlu + c0 + cc]
-                                        : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+      if (rr < 16)
+        Db[rr][cc] = (rr < bw && cc < bw) ? LU[(long long)perm[c0 + rr] * ldlu + c0 + cc]
+                                          : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
       __syncthreads();
-      double2 y = Zs[rr * n + c0 + min(cc, bw - 1)];
-      for (int w = 0; w < 4; ++w) y = csub(y, red[w][rr][cc]);
-      if (phase == 0) {
+      double2 y = make_double2(0.0, 0.0);
+      if (rr < 16) {
+        y = Zs[rr * n + c0 + min(cc, bw - 1)];
+        for (int w = 0; w < RS_NW; ++w) y = csub(y, red[w][rr][cc]);
+      }
+      if (rr >= 16) {
+        // waves beyond the 16 x 16 block solve only join the barriers
+      } else if (phase == 0) {
         // z U_JJ = y, columns ascending
         for (int cp = 0; cp < 16; ++cp) {
           double2 zv = cdiv(y, Db[cp][cp]);
@@ -593,7 +814,7 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
         }
       }
       __syncthreads();
-      if (cc < bw) Zs[rr * n + c0 + cc] = y;
+      if (rr < 16 && cc < bw) Zs[rr * n + c0 + cc] = y;
       __syncthreads();
     }
   }

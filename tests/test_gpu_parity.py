@@ -131,7 +131,7 @@ def test_tile_configurations_agree():
     phi = synth.fields(3, L, m.n_q)
     rp = synth.replay(4, 1, L, m.n_q)
     out = []
-    for cfg in range(4):
+    for cfg in range(8):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg)
         g.init_fields(phi[None])
         g.sweep(1, rp[None])
