@@ -1,11 +1,13 @@
 """Benchmark of the CF-DQMC sweep on one MI355X.
 
-Workload (default): torus N_phi = 100 (spin block n = 200, 4N = 400), paper
-momentum cutoff (933 HS components per channel), L = 400 slices of dtau = 0.1,
-u = 1.5 on the SO(5) line, FP64 recomputation every 8 slices, complex FP32
-MFMA wraps and updates with FP64 accumulation (--precision fp64 for the plain
-path). A step is one sweep of every chain: L Langevin slice moves of
-4 n_q fields each, with wraps, Woodbury updates and stabilisation.
+Workload (default): 64 independent chains of the torus N_phi = 100 model
+(spin block n = 200, 4N = 400), paper momentum cutoff (933 HS components per
+channel), L = 400 slices of dtau = 0.1, u = 1.5 on the SO(5) line, FP64
+recomputation every 8 slices, complex FP32 MFMA wraps with FP64 accumulation
+(--precision fp64 for the all-FP64 path). A step is one sweep of every chain:
+L Langevin slice moves of 4 n_q fields each, with wraps, Woodbury updates and
+stabilisation. After the timed sweeps: tau_int of m^2_SO(5) over untimed
+sweeps, a one-chain FP64 reference sweep, and the FP64 oracle on the host.
 
 Prints one JSON line (see the fields below). Synthetic fields N(0,1).
 """
@@ -20,11 +22,19 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
 
+# HBM bytes per launch of the timed channel application, (FETCH_SIZE + WRITE_SIZE)
+# from rocprofv3 PMC runs of this command scaled by the copy-kernel factor
+# (profiles/chan_apply_traffic_c3.txt); keyed by (N_phi, chains per context,
+# precision, tile configuration). Absent key: traffic not measured for that case.
+TRAFFIC = {}
+
 
 def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
     """The FP64 oracle timed on the host on a bounded sample of the same
-    workload: the first slices of one sweep (suffix products included)."""
-    import numpy as np
+    workload: the first k slice moves of a sweep of a chain with the same N_phi,
+    momentum set and couplings and at most 40 slices (the oracle's cost per
+    slice move does not depend on L; its per-sweep set-up of all slice
+    exponentials and suffix products does, and is included in the time)."""
     import synth
     from oracle import dqmc
     from oracle.model import Model
@@ -33,48 +43,81 @@ def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    m = Model(n_phi, l_tau, dtau, u0=1.0, uk=u, un=u)
-    phi = synth.fields(1, l_tau, m.n_q)
-    rp = synth.replay(2, 1, l_tau, m.n_q)[0]
-    ch = dqmc.Chain(m, phi, eps0=0.3, adapt=False)
-    # estimate cost per slice on a short probe, then size the sample to ~seconds
+    ls = min(l_tau, 40)
+    m = Model(n_phi, ls, dtau, u0=1.0, uk=u, un=u)
+    phi = synth.fields(1, ls, m.n_q)
+    rp = synth.replay(2, 1, ls, m.n_q)[0]
     t0 = time.perf_counter()
-    ch.sweep(rp, max_slices=2)
-    t_probe = time.perf_counter() - t0
-    k = max(2, min(l_tau, int(2 * seconds / max(t_probe, 1e-3))))
-    ch = dqmc.Chain(m, phi, eps0=0.3, adapt=False)
+    dqmc.Chain(m, phi, eps0=0.3, adapt=False).sweep(rp, max_slices=1)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(ls, int(seconds / max(t1, 1e-3))))
     t0 = time.perf_counter()
-    ch.sweep(rp, max_slices=k)
+    dqmc.Chain(m, phi, eps0=0.3, adapt=False).sweep(rp, max_slices=k)
     dt = time.perf_counter() - t0
     return {"value": k * 4 * m.n_q / dt, "unit": "field updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d slices of one sweep at N_phi=%d (n_q=%d), FP64 numpy/LAPACK, %.1f s"
-                      % (k, l_tau, n_phi, m.n_q, dt)}
+            "sample": "first %d slice moves (with the sweep set-up) of a %d-slice chain at N_phi=%d, n_q=%d, "
+                      "u=%g; FP64 numpy/LAPACK; %.1f s" % (k, ls, n_phi, m.n_q, u, dt)}
+
+
+def progress(msg):
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
+def sweep_each(b, steps):
+    """Run `steps` sweeps one at a time; returns wall time, stats of every
+    chain over all sweeps, and per sweep the max over chains of
+    max|G_updated - G_FP64| / max|G_FP64| (relative, max norm) at the
+    recomputation points."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, g_err = [], []
+    for _ in range(steps):
+        st = b.sweep(1)
+        stats.append(st)
+        g_err.append(max(x["max_stab_rel"] for x in st))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats, g_err
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-phi", type=int, default=100)
     ap.add_argument("--l-tau", type=int, default=400)
     ap.add_argument("--dtau", type=float, default=0.1)
     ap.add_argument("--u", type=float, default=1.5)
     ap.add_argument("--n-stab", type=int, default=8)
-    ap.add_argument("--chains", type=int, default=1)
+    ap.add_argument("--chains", type=int, default=64)
     ap.add_argument("--groups", type=int, default=1, help="split the chains over this many streams")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
     ap.add_argument("--workload", choices=["c3", "batched"], default="c3",
                     help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid")
     ap.add_argument("--tile-cfg", type=int, default=-1)
-    ap.add_argument("--tau-sweeps", type=int, default=0, help="extra untimed sweeps for tau_int")
+    ap.add_argument("--tau-sweeps", type=int, default=10, help="untimed sweeps after the timed ones for tau_int")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-chain FP64 reference sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB between two fresh device buffers three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (chains shard "
               "independently; see the design notes). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.zeros_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8, "copies": 3}))
+        return
     import numpy as np
     import torch
     from paper_2605_03700_amd import Batch, FP64, MIXED, MIXED_ALL
@@ -90,56 +133,79 @@ def main():
                     n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
                     tile_cfg=args.tile_cfg) for k in range(args.groups)])
     g = b.groups[0]
+    progress("contexts created (tiles %s)" % (g.tile_config(),))
     b.init_fields()
+    progress("fields initialised")
     if args.warmup:
         b.sweep(args.warmup)
-    torch.cuda.synchronize()
+        progress("warm-up done")
     g.kernel_timing(True)
-    t0 = time.perf_counter()
-    st = b.sweep(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt, stats, g_err = sweep_each(b, args.steps)
+    progress("timed sweeps done: %.1f ms per sweep" % (1000.0 * dt / args.steps))
     k_ms, k_count, k_flops = g.kernel_timing_read()
     g.kernel_timing(False)
     fields = args.chains * args.l_tau * 4 * g.n_q * args.steps
     value = fields / dt
     sweeps_per_s = args.steps / dt
-    acc = sum(s["accepted"] for s in st) / max(1, sum(s["proposed"] for s in st))
-    g_err = max(s["max_stab_err"] for s in st)
+    flat = [x for st in stats for x in st]
+    acc = sum(x["accepted"] for x in flat) / max(1, sum(x["proposed"] for x in flat))
     out = {
         "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
         "value": value, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": "torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chain(s) in %d "
-                               "stream group(s), recompute every %d slices"
+                               "stream group(s), FP64 recompute every %d slices"
                                % (args.n_phi, args.l_tau, args.dtau, args.u, g.n_q, args.chains, args.groups,
                                   args.n_stab),
                    "chains": args.chains, "groups": args.groups, "precision": args.precision, "n_q": g.n_q,
                    "tile_cfg": list(g.tile_config())},
         "acceptance": acc,
         "eps": float(np.mean(np.concatenate([q.get_eps() for q in b.groups]))),
-        "g_err_max": g_err,
+        "g_err_max": max(g_err),
+        "g_err_per_sweep": g_err,
+        "g_err_definition": "max over chains and recomputation points of max|G - G_FP64| / max|G_FP64|",
+        "g_err_abs_max": max(x["max_stab_err"] for x in flat),
+        "g_err_abs_median_chain": float(np.median([max(st[z]["max_stab_err"] for st in stats)
+                                                    for z in range(len(stats[0]))])),
         "sweeps_per_s_per_chain": sweeps_per_s,
     }
     if k_count > 0 and k_ms > 0:
         ach = k_flops / (k_ms * 1e-3) / 1e12
+        traffic = TRAFFIC.get((args.n_phi, nper, args.precision, g.tile_config()[0]))
         out["roofline"] = {"bound": "mfma", "kernel": "chan_apply", "achieved": ach,
                            "peak": PEAK[args.precision], "unit": "TFLOP/s", "frac": ach / PEAK[args.precision],
-                           "traffic": None, "avg_launch_ms": k_ms, "launches_timed": k_count,
+                           "traffic": traffic, "avg_launch_ms": k_ms, "launches_timed": k_count,
                            "flops_per_launch": k_flops}
+    tau = None
     if args.tau_sweeps > 0:
         n0 = [len(q.series(0)) for q in b.groups]
-        t1 = time.perf_counter()
-        b.sweep(args.tau_sweeps)
-        dt2 = time.perf_counter() - t1
-        taus = [tau_int(q.series(k)[n0[i]:])[0] for i, q in enumerate(b.groups) for k in range(nper)]
-        tau = float(np.mean(taus))
+        dt2, _, _ = sweep_each(b, args.tau_sweeps)
+        series = [q.series(k)[n0[i]:] for i, q in enumerate(b.groups) for k in range(nper)]
+        tau = float(np.mean([tau_int(x)[0] for x in series]))
         out["tau_int_sweeps"] = tau
+        out["tau_int_observable"] = "m2_SO(5), mean over chains of %d-sweep series" % args.tau_sweeps
         out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
+        progress("tau_int sweeps done")
+    b.close()
+    if not args.no_plain:
+        # the plain path for comparison: one chain, FP64, same workload
+        p = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+                        n_stab=args.n_stab, precision=FP64, eps0=0.3, adapt_eps=True, seed=99, n_chains=1,
+                        tile_cfg=args.tile_cfg)])
+        p.init_fields()
+        p.sweep(1)
+        dtp, stp, gep = sweep_each(p, 2)
+        plain = {"chains": 1, "precision": "fp64", "field_updates_per_s": args.l_tau * 4 * g.n_q * 2 / dtp,
+                 "ms_per_sweep": 1000.0 * dtp / 2, "g_err_max": max(gep)}
+        if tau:
+            plain["indep_samples_per_s"] = (2 / dtp) / (2 * tau)
+        out["plain_fp64_1chain"] = plain
+        p.close()
+        progress("one-chain FP64 reference done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds)
-    b.close()
+        progress("CPU oracle baseline done")
     print(json.dumps(out))
 
 
@@ -182,7 +248,9 @@ def bench_batched(args, prec):
                    "chains": b.n_chains, "precision": args.precision, "n_q": [g.n_q for g in b.groups],
                    "tile_cfg": [list(g.tile_config()) for g in b.groups]},
         "acceptance": sum(s["accepted"] for s in st) / max(1, sum(s["proposed"] for s in st)),
-        "g_err_max": max(s["max_stab_err"] for s in st),
+        "g_err_max": max(s["max_stab_rel"] for s in st),
+        "g_err_definition": "max over chains and recomputation points of max|G - G_FP64| / max|G_FP64|",
+        "g_err_abs_max": max(s["max_stab_err"] for s in st),
     }
     if k_count > 0 and k_ms > 0:
         ach = k_flops / (k_ms * 1e-3) / 1e12

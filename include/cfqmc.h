@@ -77,7 +77,7 @@ typedef struct {
   double r0, deps;       /* acceptance set point and gain of eps <- eps + (r_a - r0) deps (0.574, 0.1) */
   double eps_min, eps_max;
   int32_t adapt_eps;     /* 1: adapt after every sweep; 0: frozen */
-  uint64_t seed;         /* Philox4x32-10 key for fields and noise */
+  uint64_t seed;         /* Philox4x32-10 key of the proposal noise; seeds the host draw of initial fields */
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential (default 2) */
@@ -92,6 +92,7 @@ typedef struct {
   double max_phase_err;       /* max |Im ln R| (mod 2 pi) of the weight ratio, sign-free check */
   int32_t exp_range_flag;     /* 1 if an exponential needed more squarings than allowed */
   int32_t pad;
+  double max_stab_rel;        /* max over recomputation points of max|G_updated - G_FP64| / max|G_FP64| */
 } cfqmc_stats;
 
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
@@ -107,9 +108,10 @@ int cfqmc_destroy(cfqmc_ctx* c);
 /* Sizes: number of HS components per channel, chains, 4N. Any pointer may be NULL. */
 int cfqmc_sizes(const cfqmc_ctx* c, int32_t* n_q, int32_t* n_chains, int32_t* dim_g4n);
 
-/* Set the fields (host [n_chains][l_tau][4][n_q]) or draw them N(0,1) on the
- * device from the seed (phi == NULL); rebuilds every slice propagator, both
- * UDT stacks and G(0) in FP64; resets eps and statistics. */
+/* Set the fields (host [n_chains][l_tau][4][n_q]) or, with phi == NULL, draw
+ * them N(0,1) on the host (Box-Muller on a splitmix64 stream of the seed) and
+ * upload them; rebuilds every slice propagator, both UDT stacks and G(0) in
+ * FP64; resets eps and statistics. */
 int cfqmc_init_fields(cfqmc_ctx* c, const double* phi);
 int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out);
 

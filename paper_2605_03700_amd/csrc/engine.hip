@@ -800,7 +800,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->done, (size_t)B);
   rc |= dalloc(c, &c->part, (size_t)B * 4 * 4 * 1024);
   rc |= dalloc(c, &c->obs, (size_t)B * 8);
-  rc |= dalloc(c, &c->stab_err, (size_t)B);
+  rc |= dalloc(c, &c->stab_err, (size_t)B * 4);
   c->series_cap = 1 << 16;
   rc |= dalloc(c, &c->series, (size_t)B * c->series_cap);
   rc |= dalloc(c, &c->hist_acc, (size_t)B * L);
@@ -888,7 +888,7 @@ int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
   HIPCHK(hipMemcpyAsync(c->eps, e.data(), B * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemsetAsync(c->acc_count, 0, B * sizeof(int), c->s));
   HIPCHK(hipMemsetAsync(c->stat, 0, B * 8 * sizeof(double), c->s));
-  HIPCHK(hipMemsetAsync(c->stab_err, 0, B * sizeof(double), c->s));
+  HIPCHK(hipMemsetAsync(c->stab_err, 0, B * 4 * sizeof(double), c->s));
   HIPCHK(hipMemsetAsync(c->done, 0, B * sizeof(unsigned), c->s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
@@ -919,7 +919,7 @@ namespace {
 // Sweep pieces shared by cfqmc_sweep and the heterogeneous batch.
 void sweep_reset_stats(cfqmc_ctx* c) {
   hipMemsetAsync(c->stat, 0, c->nch * 8 * sizeof(double), c->s);
-  hipMemsetAsync(c->stab_err, 0, c->nch * sizeof(double), c->s);
+  hipMemsetAsync(c->stab_err, 0, c->nch * 4 * sizeof(double), c->s);
 }
 
 void sweep_slice(cfqmc_ctx* c, int t, const double* noise_dev) {
@@ -947,18 +947,19 @@ int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
   HIPCHK(hipStreamSynchronize(c->s));
   int ef = 0;
   HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
-  std::vector<double> st(B * 8), se(B), ep(B);
+  std::vector<double> st(B * 8), se(B * 4), ep(B);
   HIPCHK(hipMemcpy(st.data(), c->stat, B * 8 * sizeof(double), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(se.data(), c->stab_err, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(se.data(), c->stab_err, B * 4 * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(ep.data(), c->eps, B * sizeof(double), hipMemcpyDeviceToHost));
   bool bad = ef != 0;
   for (int z = 0; z < B; ++z) {
-    if (!std::isfinite(se[z]) || !std::isfinite(ep[z])) bad = true;
+    if (!std::isfinite(se[4 * z]) || !std::isfinite(ep[z])) bad = true;
     if (stats) {
       stats[z].proposed = (int64_t)st[z * 8 + 1];
       stats[z].accepted = (int64_t)st[z * 8 + 2];
       stats[z].eps = ep[z];
-      stats[z].max_stab_err = se[z];
+      stats[z].max_stab_err = se[4 * z];
+      stats[z].max_stab_rel = se[4 * z + 1];
       stats[z].max_phase_err = st[z * 8 + 0];
       stats[z].exp_range_flag = ef;
       stats[z].pad = 0;

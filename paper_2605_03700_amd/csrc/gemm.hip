@@ -36,13 +36,21 @@ struct Acc {
 };
 
 // One BK-deep slab of wave-tile products from LDS (As[k][m], Bs[k][n]).
+// mrem / nrem: valid rows / columns from the wave tile's origin, krem: valid k
+// in the slab. 16 x 16 subtiles and k steps lying entirely in the zero padding
+// are skipped (wave-uniform branches), which changes no valid output.
 template <typename CT, int WTM, int WTN, int KD = BK>
 CF_DEV void mma_slab(const typename cplx_t<CT>::type* As, int lda, const typename cplx_t<CT>::type* Bs, int ldb,
-                     int wm0, int wn0, int lane, Acc<CT, WTM, WTN>& acc) {
+                     int wm0, int wn0, int lane, Acc<CT, WTM, WTN>& acc, int mrem = 1 << 30, int nrem = 1 << 30,
+                     int krem = 1 << 30) {
   typedef typename cplx_t<CT>::type C2;
   const int il = lane & 15, kl = lane >> 4;
+  mrem = __builtin_amdgcn_readfirstlane(mrem);
+  nrem = __builtin_amdgcn_readfirstlane(nrem);
+  krem = __builtin_amdgcn_readfirstlane(krem);
 #pragma unroll
   for (int kk = 0; kk < KD; kk += 4) {
+    if (kk >= krem) break;
     C2 a[WTM], b[WTN];
 #pragma unroll
     for (int s = 0; s < WTM; ++s) a[s] = As[(kk + kl) * lda + wm0 + s * 16 + il];
@@ -52,6 +60,7 @@ CF_DEV void mma_slab(const typename cplx_t<CT>::type* As, int lda, const typenam
     for (int si = 0; si < WTM; ++si)
 #pragma unroll
       for (int sj = 0; sj < WTN; ++sj) {
+        if (si * 16 >= mrem || sj * 16 >= nrem) continue;
         acc.re[si][sj] = Mfma<CT>::mma(a[si].x, b[sj].x, acc.re[si][sj]);
         acc.re[si][sj] = Mfma<CT>::mma(-a[si].y, b[sj].y, acc.re[si][sj]);
         acc.im[si][sj] = Mfma<CT>::mma(a[si].x, b[sj].y, acc.im[si][sj]);
@@ -85,8 +94,10 @@ zgemm_kernel(GemmArgs g) {
   typedef typename cplx_t<CT>::type C2;
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
   constexpr int NT = WX * WY * 64;
-  __shared__ C2 As[BK * BM];
-  __shared__ C2 Bs[BK * BN];
+  // padded rows: the k-fastest staging stores of a quarter wave hit distinct banks
+  constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
+  __shared__ C2 As[BK * LDA];
+  __shared__ C2 Bs[BK * LDB];
   const int z = blockIdx.z, z1 = z / g.nz2, z2 = z % g.nz2;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -125,14 +136,14 @@ zgemm_kernel(GemmArgs g) {
       const int idx = tid + e * NT;
       int m, k;
       if (g.opA == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
-      As[k * BM + m] = to_ct<CT>(ra[e]);
+      As[k * LDA + m] = to_ct<CT>(ra[e]);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = tid + e * NT;
       int n, k;
       if (g.opB == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
-      Bs[k * BN + n] = to_ct<CT>(rb[e]);
+      Bs[k * LDB + n] = to_ct<CT>(rb[e]);
     }
   };
   Acc<double, WTM, WTN> acc;
@@ -143,12 +154,13 @@ zgemm_kernel(GemmArgs g) {
       stage();
       __syncthreads();
       if (k0 + BK < g.K) fetch(k0 + BK);
+      const int mr = g.M - m0 - wm0, nr = g.N - n0 - wn0, kr = g.K - k0;
       if constexpr (sizeof(CT) == 8) {
-        mma_slab<double, WTM, WTN>((const double2*)As, BM, (const double2*)Bs, BN, wm0, wn0, lane, acc);
+        mma_slab<double, WTM, WTN>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc, mr, nr, kr);
       } else {
         Acc<float, WTM, WTN> a32;
         a32.zero();
-        mma_slab<float, WTM, WTN>((const float2*)As, BM, (const float2*)Bs, BN, wm0, wn0, lane, a32);
+        mma_slab<float, WTM, WTN>((const float2*)As, LDA, (const float2*)Bs, LDB, wm0, wn0, lane, a32, mr, nr, kr);
         flush(a32, acc);
       }
       __syncthreads();
@@ -213,8 +225,9 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
   constexpr int NT = WX * WY * 64;
   constexpr int NS = DB ? 2 : 1;
-  __shared__ C2 As[NS][2][BKC * BM];
-  __shared__ C2 Bs[NS][2][BKC * BN];
+  constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
+  __shared__ C2 As[NS][2][BKC * LDA];
+  __shared__ C2 Bs[NS][2][BKC * LDB];
   int z, ty, tx;
   if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
   const int m0 = ty * BM, n0 = tx * BN;
@@ -302,17 +315,17 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       int m, k;
       if (LEFT) {
         if (c.opX == 0) { k = idx % BKC; m = idx / BKC; } else { m = idx % BM; k = idx / BM; }
-        As[st][0][k * BM + m] = to_ct<CT>(ra[e][0]);
-        As[st][1][k * BM + m] = to_ct<CT>(ra[e][1]);
+        As[st][0][k * LDA + m] = to_ct<CT>(ra[e][0]);
+        As[st][1][k * LDA + m] = to_ct<CT>(ra[e][1]);
       } else {
         k = idx % BKC; m = idx / BKC;
         if (ROT) {
 #pragma unroll
           for (int a = 0; a < 2; ++a)
-            As[st][a][k * BM + m] = to_ct<CT>(cadd(cmul(u[0][a], ra[e][0]), cmul(u[1][a], ra[e][1])));
+            As[st][a][k * LDA + m] = to_ct<CT>(cadd(cmul(u[0][a], ra[e][0]), cmul(u[1][a], ra[e][1])));
         } else {
-          As[st][0][k * BM + m] = to_ct<CT>(ra[e][0]);
-          As[st][1][k * BM + m] = to_ct<CT>(ra[e][1]);
+          As[st][0][k * LDA + m] = to_ct<CT>(ra[e][0]);
+          As[st][1][k * LDA + m] = to_ct<CT>(ra[e][1]);
         }
       }
     }
@@ -325,31 +338,33 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
         if (ROT) {
 #pragma unroll
           for (int a = 0; a < 2; ++a)
-            Bs[st][a][k * BN + n] = to_ct<CT>(cadd(cmul(u[0][a], rb[e][0]), cmul(u[1][a], rb[e][1])));
+            Bs[st][a][k * LDB + n] = to_ct<CT>(cadd(cmul(u[0][a], rb[e][0]), cmul(u[1][a], rb[e][1])));
         } else {
-          Bs[st][0][k * BN + n] = to_ct<CT>(rb[e][0]);
-          Bs[st][1][k * BN + n] = to_ct<CT>(rb[e][1]);
+          Bs[st][0][k * LDB + n] = to_ct<CT>(rb[e][0]);
+          Bs[st][1][k * LDB + n] = to_ct<CT>(rb[e][1]);
         }
       } else {
         if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BKC; n = idx / BKC; }
-        Bs[st][0][k * BN + n] = to_ct<CT>(rb[e][0]);
-        Bs[st][1][k * BN + n] = to_ct<CT>(rb[e][1]);
+        Bs[st][0][k * LDB + n] = to_ct<CT>(rb[e][0]);
+        Bs[st][1][k * LDB + n] = to_ct<CT>(rb[e][1]);
       }
     }
   };
   Acc<double, WTM, WTN> acc[2];
   acc[0].zero();
   acc[1].zero();
-  auto mma = [&](int st) {
+  const int mr = rows - m0 - wm0, nr = cols - n0 - wn0;
+  auto mma = [&](int st, int k0) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if constexpr (sizeof(CT) == 8) {
-        mma_slab<double, WTM, WTN, BKC>((const double2*)As[st][a], BM, (const double2*)Bs[st][a], BN, wm0, wn0, lane,
-                                        acc[a]);
+        mma_slab<double, WTM, WTN, BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
+                                        acc[a], mr, nr, N - k0);
       } else {
         Acc<float, WTM, WTN> a32;
         a32.zero();
-        mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], BM, (const float2*)Bs[st][a], BN, wm0, wn0, lane, a32);
+        mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane, a32,
+                                       mr, nr, N - k0);
         flush(a32, acc[a]);
       }
     }
@@ -362,7 +377,7 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
     for (int k0 = 0; k0 < N; k0 += BKC) {
       const bool more = k0 + BKC < N;
       if (more) fetch(k0 + BKC);
-      mma(cur);
+      mma(cur, k0);
       if (more) stage(cur ^ (NS - 1));
       __syncthreads();
       cur ^= (NS - 1);
@@ -372,7 +387,7 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       stage(0);
       __syncthreads();
       if (k0 + BKC < N) fetch(k0 + BKC);
-      mma(0);
+      mma(0, k0);
       __syncthreads();
     }
   }

@@ -63,7 +63,8 @@ void launch_copy(const double2* X, double2* Y, long long count, long long sX, lo
 // Y[:, k] = X[:, k] * d[k]   (d real, per batch stride sd) ; inv: divide instead
 void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
                      const double* d, long long sd, int n_rows, int n_cols, int inv, int nbatch, hipStream_t s);
-// max |X - Y| over an n x n matrix per batch, max-reduced into out[batch]
+// running max |X - Y| (out[4z]) and max |X - Y| / max |Y| (out[4z+1]) per batch entry;
+// out[4z+2], out[4z+3] are scratch that must start at zero
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
                     hipStream_t s);
 

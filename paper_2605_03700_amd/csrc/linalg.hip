@@ -931,27 +931,47 @@ void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ld
   hipLaunchKernelGGL(colscale_kernel, grid, dim3(256), 0, s, X, ldx, sX, Y, ldy, sY, d, sd, n_rows, n_cols, inv); cfqmc_post_launch("colscale_kernel");
 }
 
+// Per chain: out[4z+2] = max |X - Y| and out[4z+3] = max |Y| (atomic max over
+// blocks), then maxdiff_fold folds them into the running maxima out[4z+0]
+// (absolute) and out[4z+1] (relative to max |Y|) and clears the temporaries.
 __global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long long sX, double* out) {
-  __shared__ double red[4];
+  __shared__ double red[4], redy[4];
   const int z = blockIdx.y;
-  double m = 0.0;
+  double m = 0.0, my = 0.0;
   for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
     const double2 a = X[z * sX + idx], b = Y[z * sX + idx];
     m = fmax(m, sqrt(cabs2(csub(a, b))));
+    my = fmax(my, sqrt(cabs2(b)));
   }
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  for (int o = 32; o > 0; o >>= 1) {
+    m = fmax(m, __shfl_xor(m, o, 64));
+    my = fmax(my, __shfl_xor(my, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = m; redy[threadIdx.x >> 6] = my; }
   __syncthreads();
   if (threadIdx.x == 0) {
     m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    my = fmax(fmax(redy[0], redy[1]), fmax(redy[2], redy[3]));
     // non-negative doubles order like their bit patterns
-    atomicMax((unsigned long long*)&out[z], (unsigned long long)__double_as_longlong(m));
+    atomicMax((unsigned long long*)&out[4 * z + 2], (unsigned long long)__double_as_longlong(m));
+    atomicMax((unsigned long long*)&out[4 * z + 3], (unsigned long long)__double_as_longlong(my));
   }
+}
+__global__ void maxdiff_fold_kernel(double* out, int nbatch) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nbatch) return;
+  const double d = out[4 * z + 2], gm = out[4 * z + 3];
+  out[4 * z + 0] = fmax(out[4 * z + 0], d);
+  out[4 * z + 1] = fmax(out[4 * z + 1], gm > 0.0 ? d / gm : d);
+  out[4 * z + 2] = 0.0;
+  out[4 * z + 3] = 0.0;
 }
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
                     hipStream_t s) {
   dim3 grid(min((n * n + 1023) / 1024, 64), nbatch);
   hipLaunchKernelGGL(maxdiff_kernel, grid, dim3(256), 0, s, X, Y, n, sX, out); cfqmc_post_launch("maxdiff_kernel");
+  hipLaunchKernelGGL(maxdiff_fold_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, out, nbatch);
+  cfqmc_post_launch("maxdiff_fold_kernel");
 }
 
 // ------------------------------------------------------------------ UDT helpers
