@@ -110,40 +110,51 @@ zgemm_kernel(GemmArgs g) {
 
   constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
   double2 ra[EA], rb[EB];
+  const double2 zero2 = make_double2(0.0, 0.0);
+  // bare loads here (out-of-range elements read offset 0 and are zeroed at
+  // staging time, like the conjugation), so the loads stay in flight
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * NT;
       int m, k;
-      double2 v = make_double2(0.0, 0.0);
-      if (g.opA == 0) { k = idx % BK; m = idx / BK; if (m0 + m < g.M && k0 + k < g.K) v = A[(long long)(m0 + m) * g.A.ld + k0 + k]; }
-      else { m = idx % BM; k = idx / BM; if (m0 + m < g.M && k0 + k < g.K) { v = A[(long long)(k0 + k) * g.A.ld + m0 + m]; v.y = -v.y; } }
-      ra[e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int idx = tid + e * NT;
-      int n, k;
-      double2 v = make_double2(0.0, 0.0);
-      if (g.opB == 0) { n = idx % BN; k = idx / BN; if (n0 + n < g.N && k0 + k < g.K) v = B[(long long)(k0 + k) * g.B.ld + n0 + n]; }
-      else { k = idx % BK; n = idx / BK; if (n0 + n < g.N && k0 + k < g.K) { v = B[(long long)(n0 + n) * g.B.ld + k0 + k]; v.y = -v.y; } }
-      rb[e] = v;
-    }
-  };
-  auto stage = [&]() {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = tid + e * NT;
-      int m, k;
       if (g.opA == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
-      As[k * LDA + m] = to_ct<CT>(ra[e]);
+      const bool ok = m0 + m < g.M && k0 + k < g.K;
+      const long long off = !ok ? 0 : g.opA == 0 ? (long long)(m0 + m) * g.A.ld + k0 + k
+                                                  : (long long)(k0 + k) * g.A.ld + m0 + m;
+      ra[e] = A[off];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = tid + e * NT;
       int n, k;
       if (g.opB == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
-      Bs[k * LDB + n] = to_ct<CT>(rb[e]);
+      const bool ok = n0 + n < g.N && k0 + k < g.K;
+      const long long off = !ok ? 0 : g.opB == 0 ? (long long)(k0 + k) * g.B.ld + n0 + n
+                                                  : (long long)(n0 + n) * g.B.ld + k0 + k;
+      rb[e] = B[off];
+    }
+  };
+  auto stage = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      int m, k;
+      if (g.opA == 0) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+      double2 v = ra[e];
+      if (g.opA != 0) v.y = -v.y;
+      if (!(m0 + m < g.M && k0 + k < g.K)) v = zero2;
+      As[k * LDA + m] = to_ct<CT>(v);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      int n, k;
+      if (g.opB == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BK; n = idx / BK; }
+      double2 v = rb[e];
+      if (g.opB != 0) v.y = -v.y;
+      if (!(n0 + n < g.N && k0 + k < g.K)) v = zero2;
+      Bs[k * LDB + n] = to_ct<CT>(v);
     }
   };
   Acc<double, WTM, WTN> acc;
@@ -151,7 +162,7 @@ zgemm_kernel(GemmArgs g) {
   if (do_mul) {
     fetch(0);
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-      stage();
+      stage(k0);
       __syncthreads();
       if (k0 + BK < g.K) fetch(k0 + BK);
       const int mr = g.M - m0 - wm0, nr = g.N - n0 - wn0, kr = g.K - k0;
@@ -251,102 +262,105 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
     if (c.one_minus) { v.x = -v.x; v.y = -v.y; if (i == j) v.x += 1.0; }
     return v;
   };
+  // value fix-ups applied at staging time, so that fetch issues bare loads and
+  // the loads stay in flight across the MFMAs of the current slab
+  // (out-of-range elements were loaded from offset 0 and are zeroed here)
+  auto fix_m = [&](double2 v, int i, int j, bool ok) -> double2 {
+    if (!ok) return make_double2(0.0, 0.0);
+    if (c.one_minus) { v.x = -v.x; v.y = -v.y; if (i == j) v.x += 1.0; }
+    return v;
+  };
+  auto fix_x = [&](double2 v, int i, int j, bool ok) -> double2 {
+    if (!ok) return make_double2(0.0, 0.0);
+    if (c.opX != 0) v.y = -v.y;
+    if (CORR && i == j) v.x -= 1.0;
+    return v;
+  };
 
   constexpr int EA = BM * BKC / NT, EB = BN * BKC / NT;
   static_assert(EA * NT == BM * BKC && EB * NT == BN * BKC, "tile / thread mismatch");
   double2 ra[EA][2], rb[EB][2];
+  // element e of the A (B) tile handled by this thread: tile coordinates
+  auto a_coord = [&](int e, int& m, int& k) {
+    const int idx = tid + e * NT;
+    if (LEFT && c.opX != 0) { m = idx % BM; k = idx / BM; } else { k = idx % BKC; m = idx / BKC; }
+  };
+  auto b_coord = [&](int e, int& n, int& k) {
+    const int idx = tid + e * NT;
+    if (!LEFT && c.opX != 0) { k = idx % BKC; n = idx / BKC; } else { n = idx % BN; k = idx / BN; }
+  };
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int idx = tid + e * NT;
+      int m, k;
+      a_coord(e, m, k);
+      const bool ok = m0 + m < rows && k0 + k < N;
       if (LEFT) {
-        int m, k;
-        if (c.opX == 0) { k = idx % BKC; m = idx / BKC; } else { m = idx % BM; k = idx / BM; }
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          double2 v = make_double2(0.0, 0.0);
-          if (m0 + m < rows && k0 + k < N) {
-            if (c.opX == 0) v = X[a][(long long)(m0 + m) * c.ldX + k0 + k];
-            else { v = X[a][(long long)(k0 + k) * c.ldX + m0 + m]; v.y = -v.y; }
-            if (CORR && m0 + m == k0 + k) v.x -= 1.0;
-          }
-          ra[e][a] = v;
-        }
+        const long long off = !ok ? 0 : c.opX == 0 ? (long long)(m0 + m) * c.ldX + k0 + k
+                                                    : (long long)(k0 + k) * c.ldX + m0 + m;
+        ra[e][0] = X[0][off];
+        ra[e][1] = X[1][off];
       } else {
-        const int k = idx % BKC, m = idx / BKC;
-        ra[e][0] = ra[e][1] = make_double2(0.0, 0.0);
-        if (m0 + m < rows && k0 + k < N) {
-          ra[e][0] = mload(m0 + m, k0 + k);
-          ra[e][1] = mload(m0 + m, N + k0 + k);
-        }
+        const long long off = ok ? (long long)(m0 + m) * c.ldM + k0 + k : 0;
+        ra[e][0] = M[off];
+        ra[e][1] = M[off + N];
       }
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int idx = tid + e * NT;
+      int n, k;
+      b_coord(e, n, k);
+      const bool ok = n0 + n < cols && k0 + k < N;
       if (LEFT) {
-        const int n = idx % BN, k = idx / BN;
-        rb[e][0] = rb[e][1] = make_double2(0.0, 0.0);
-        if (n0 + n < cols && k0 + k < N) {
-          rb[e][0] = mload(k0 + k, n0 + n);
-          rb[e][1] = mload(N + k0 + k, n0 + n);
-        }
+        const long long off = ok ? (long long)(k0 + k) * c.ldM + n0 + n : 0;
+        rb[e][0] = M[off];
+        rb[e][1] = M[off + (long long)N * c.ldM];
       } else {
-        int n, k;
-        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BKC; n = idx / BKC; }
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          double2 v = make_double2(0.0, 0.0);
-          if (n0 + n < cols && k0 + k < N) {
-            if (c.opX == 0) v = X[a][(long long)(k0 + k) * c.ldX + n0 + n];
-            else { v = X[a][(long long)(n0 + n) * c.ldX + k0 + k]; v.y = -v.y; }
-            if (CORR && n0 + n == k0 + k) v.x -= 1.0;
-          }
-          rb[e][a] = v;
-        }
+        const long long off = !ok ? 0 : c.opX == 0 ? (long long)(k0 + k) * c.ldX + n0 + n
+                                                    : (long long)(n0 + n) * c.ldX + k0 + k;
+        rb[e][0] = X[0][off];
+        rb[e][1] = X[1][off];
       }
     }
   };
-  // rotate (conj(U_ba) for LEFT, U_ba for RIGHT) and store to LDS stage st
-  auto stage = [&](int st) {
+  // fix up, rotate (conj(U_ba) for LEFT, U_ba for RIGHT) and store to LDS stage st
+  auto stage = [&](int st, int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int idx = tid + e * NT;
       int m, k;
+      a_coord(e, m, k);
+      const bool ok = m0 + m < rows && k0 + k < N;
       if (LEFT) {
-        if (c.opX == 0) { k = idx % BKC; m = idx / BKC; } else { m = idx % BM; k = idx / BM; }
-        As[st][0][k * LDA + m] = to_ct<CT>(ra[e][0]);
-        As[st][1][k * LDA + m] = to_ct<CT>(ra[e][1]);
+        As[st][0][k * LDA + m] = to_ct<CT>(fix_x(ra[e][0], m0 + m, k0 + k, ok));
+        As[st][1][k * LDA + m] = to_ct<CT>(fix_x(ra[e][1], m0 + m, k0 + k, ok));
       } else {
-        k = idx % BKC; m = idx / BKC;
+        const double2 v0 = fix_m(ra[e][0], m0 + m, k0 + k, ok), v1 = fix_m(ra[e][1], m0 + m, N + k0 + k, ok);
         if (ROT) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
-            As[st][a][k * LDA + m] = to_ct<CT>(cadd(cmul(u[0][a], ra[e][0]), cmul(u[1][a], ra[e][1])));
+          for (int a = 0; a < 2; ++a) As[st][a][k * LDA + m] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
         } else {
-          As[st][0][k * LDA + m] = to_ct<CT>(ra[e][0]);
-          As[st][1][k * LDA + m] = to_ct<CT>(ra[e][1]);
+          As[st][0][k * LDA + m] = to_ct<CT>(v0);
+          As[st][1][k * LDA + m] = to_ct<CT>(v1);
         }
       }
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int idx = tid + e * NT;
       int n, k;
+      b_coord(e, n, k);
+      const bool ok = n0 + n < cols && k0 + k < N;
       if (LEFT) {
-        n = idx % BN; k = idx / BN;
+        const double2 v0 = fix_m(rb[e][0], k0 + k, n0 + n, ok), v1 = fix_m(rb[e][1], N + k0 + k, n0 + n, ok);
         if (ROT) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
-            Bs[st][a][k * LDB + n] = to_ct<CT>(cadd(cmul(u[0][a], rb[e][0]), cmul(u[1][a], rb[e][1])));
+          for (int a = 0; a < 2; ++a) Bs[st][a][k * LDB + n] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
         } else {
-          Bs[st][0][k * LDB + n] = to_ct<CT>(rb[e][0]);
-          Bs[st][1][k * LDB + n] = to_ct<CT>(rb[e][1]);
+          Bs[st][0][k * LDB + n] = to_ct<CT>(v0);
+          Bs[st][1][k * LDB + n] = to_ct<CT>(v1);
         }
       } else {
-        if (c.opX == 0) { n = idx % BN; k = idx / BN; } else { k = idx % BKC; n = idx / BKC; }
-        Bs[st][0][k * LDB + n] = to_ct<CT>(rb[e][0]);
-        Bs[st][1][k * LDB + n] = to_ct<CT>(rb[e][1]);
+        Bs[st][0][k * LDB + n] = to_ct<CT>(fix_x(rb[e][0], k0 + k, n0 + n, ok));
+        Bs[st][1][k * LDB + n] = to_ct<CT>(fix_x(rb[e][1], k0 + k, n0 + n, ok));
       }
     }
   };
@@ -371,20 +385,20 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   };
   fetch(0);
   if (DB) {
-    stage(0);
+    stage(0, 0);
     __syncthreads();
     int cur = 0;
     for (int k0 = 0; k0 < N; k0 += BKC) {
       const bool more = k0 + BKC < N;
       if (more) fetch(k0 + BKC);
       mma(cur, k0);
-      if (more) stage(cur ^ (NS - 1));
+      if (more) stage(cur ^ (NS - 1), k0 + BKC);
       __syncthreads();
       cur ^= (NS - 1);
     }
   } else {
     for (int k0 = 0; k0 < N; k0 += BKC) {
-      stage(0);
+      stage(0, k0);
       __syncthreads();
       if (k0 + BKC < N) fetch(k0 + BKC);
       mma(0, k0);
