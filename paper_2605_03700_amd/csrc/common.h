@@ -19,6 +19,12 @@ CF_DEV double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y 
 CF_DEV double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 CF_DEV double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 CF_DEV double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// 1/b = conj(b) / |b|^2 with a single real division (|b| is O(1) where used:
+// pivots and diagonals of factors of well-scaled matrices)
+CF_DEV double2 crcp(double2 b) {
+  const double r = 1.0 / (b.x * b.x + b.y * b.y);
+  return make_double2(b.x * r, -b.y * r);
+}
 CF_DEV double2 cdiv(double2 a, double2 b) {
   // Smith's algorithm for a/b
   if (fabs(b.x) >= fabs(b.y)) {

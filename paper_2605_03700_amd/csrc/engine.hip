@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -312,13 +313,16 @@ void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, lon
   const double2* Q = PQch + c->NN;
   if (ch == 0) { a.X0 = a.X1 = inverse ? Q : P; }
   else { a.X0 = inverse ? Q : P; a.X1 = inverse ? P : Q; }
-  a.ldX = N; a.sX = sPQ; a.opX = 0;
-  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) a.U[i][j] = c->Urot[ch][i][j];
+  a.ldX = N; a.sX = sPQ;
   a.one_minus = one_minus ? 1 : 0;
   a.Cadd = add; a.ldC = c->n; a.sC = c->nn;
   a.Y = Y; a.ldY = c->n; a.sY = sY < 0 ? c->nn : sY;
   a.Y2 = Y2;
-  const int rot = (ch == 1 || ch == 2);
+  const int rot = ch == 1 ? 1 : ch == 2 ? 2 : 0;   // tau_x, tau_y valley rotations
+  if (one_minus && (!left || rot)) {                // 1 - M exists only for the left, non-rotating application
+    std::fprintf(stderr, "cfqmc: internal error: 1 - M requested for a rotating or right channel\n");
+    std::abort();
+  }
   launch_chan_apply(a, left, rot, c->nch, mixed, c->cfg_chan, c->s);
 }
 

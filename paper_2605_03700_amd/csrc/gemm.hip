@@ -86,11 +86,28 @@ CF_DEV void flush(Acc<float, WTM, WTN>& a32, Acc<double, WTM, WTN>& a64) {
 // Output row of accumulator item r for lane (precision-dependent layout).
 template <typename CT> CF_DEV int out_row(int lane, int r) { return Mfma<CT>::row(lane, r); }
 
+// Tile order: the hardware hands consecutive workgroups to the eight XCDs in
+// turn, so logical tile t = (b % 8) * ceil(T/8) + b / 8 gives every XCD a
+// contiguous range of (chain, row tile, column tile): the tiles of one chain
+// share that XCD's L2.
+CF_DEV bool xcd_tile(int tiles_x, int tiles_y, int nbatch, int& z, int& ty, int& tx) {
+  const int T = tiles_x * tiles_y * nbatch;
+  const int per = (T + 7) / 8;
+  const int b = blockIdx.x;
+  const int t = (b % 8) * per + b / 8;
+  if (t >= T) return false;
+  z = t / (tiles_x * tiles_y);
+  const int r = t % (tiles_x * tiles_y);
+  ty = r / tiles_x;
+  tx = r % tiles_x;
+  return true;
+}
+
 // ------------------------------------------------------------------ zgemm
 
 template <typename CT, int BM, int BN, int WTM, int WTN>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
-zgemm_kernel(GemmArgs g) {
+zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   typedef typename cplx_t<CT>::type C2;
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
   constexpr int NT = WX * WY * 64;
@@ -98,8 +115,10 @@ zgemm_kernel(GemmArgs g) {
   constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
   __shared__ C2 As[BK * LDA];
   __shared__ C2 Bs[BK * LDB];
-  const int z = blockIdx.z, z1 = z / g.nz2, z2 = z % g.nz2;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  int z, ty, tx;
+  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  const int z1 = z / g.nz2, z2 = z % g.nz2;
+  const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
   const double2* A = mat_at(g.A, z1, z2);
@@ -209,27 +228,42 @@ zgemm_kernel(GemmArgs g) {
 
 // ------------------------------------------------------------------ chan_apply
 
-// Tile order: the hardware hands consecutive workgroups to the eight XCDs in
-// turn, so logical tile t = (b % 8) * ceil(T/8) + b / 8 gives every XCD a
-// contiguous range of (chain, row tile, column tile): the tiles of one chain
-// share that XCD's L2.
-CF_DEV bool xcd_tile(int tiles_x, int tiles_y, int nbatch, int& z, int& ty, int& tx) {
-  const int T = tiles_x * tiles_y * nbatch;
-  const int per = (T + 7) / 8;
-  const int b = blockIdx.x;
-  const int t = (b % 8) * per + b / 8;
-  if (t >= T) return false;
-  z = t / (tiles_x * tiles_y);
-  const int r = t % (tiles_x * tiles_y);
-  ty = r / tiles_x;
-  tx = r % tiles_x;
-  return true;
+// Valley rotation of a channel: none (O^0 = 1, O^3 = tau_z are diagonal in the
+// valley index), tau_x or tau_y. With U the matrix of eigenvectors of o_i
+// (columns (1, 1)/sqrt2 and (1, -1)/sqrt2 for tau_x, (1, i)/sqrt2 and
+// (1, -i)/sqrt2 for tau_y) the staged operand is S_a = sum_b w_ab M_b with
+// w = sqrt2 conj(U) (left) or sqrt2 U (right), i.e. M_0 +- w M_1 with w = 1 or
+// -+i, and the output is Y_0 = (T_0 + T_1)/2, Y_1 = z (T_0 - T_1)/2 with z = 1
+// (tau_x), i (tau_y, left) or -i (tau_y, right): additions and swaps only.
+enum { ROT_NONE = 0, ROT_X = 1, ROT_Y = 2 };
+
+template <bool LEFT, int ROTK>
+CF_DEV void rot_stage(double2 m0, double2 m1, double2& s0, double2& s1) {
+  if (ROTK == ROT_X) {
+    s0 = cadd(m0, m1);
+    s1 = csub(m0, m1);
+  } else {
+    // w M_1 with w = -i (left) or +i (right): (-i)(x+iy) = y - ix ; (i)(x+iy) = -y + ix
+    const double2 wm = LEFT ? make_double2(m1.y, -m1.x) : make_double2(-m1.y, m1.x);
+    s0 = cadd(m0, wm);
+    s1 = csub(m0, wm);
+  }
+}
+template <bool LEFT, int ROTK>
+CF_DEV double2 rot_out(double2 t0, double2 t1, int v) {
+  if (v == 0) return make_double2(0.5 * (t0.x + t1.x), 0.5 * (t0.y + t1.y));
+  const double2 d = make_double2(0.5 * (t0.x - t1.x), 0.5 * (t0.y - t1.y));
+  if (ROTK == ROT_X) return d;
+  return LEFT ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);   // i d or -i d
 }
 
 // BKC: k slab depth. DB: two LDS stages and one barrier per slab (the global
 // loads of slab k+1 and the LDS stores into the other stage overlap the MFMAs
 // of slab k); otherwise one stage with register prefetch and two barriers.
-template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
+// OM: the input is 1 - M instead of M (left, non-rotating channel only).
+// Each thread keeps base pointers to its staging elements; a slab advances
+// them by a constant.
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
 chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   typedef typename cplx_t<CT>::type C2;
@@ -247,97 +281,93 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   constexpr bool CORR = sizeof(CT) == 4;   // correction form in the mixed path
   const int N = c.N;
   const double2* M = c.M + z * c.sM;
-  const double2* X[2] = {c.X0 + z * c.sX, c.X1 + z * c.sX};
+  const double2* X0 = c.X0 + z * c.sX;
+  const double2* X1 = c.X1 + z * c.sX;
   const int rows = LEFT ? N : c.n_other;   // output rows of T
   const int cols = LEFT ? c.n_other : N;   // output cols of T
-  // conj(U_ba) for LEFT staging, U_ba for RIGHT staging
-  double2 u[2][2];
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int a = 0; a < 2; ++a) u[b][a] = LEFT ? cconj(c.U[b][a]) : c.U[b][a];
 
   auto mload = [&](int i, int j) -> double2 {
     double2 v = M[(long long)i * c.ldM + j];
-    if (c.one_minus) { v.x = -v.x; v.y = -v.y; if (i == j) v.x += 1.0; }
-    return v;
-  };
-  // value fix-ups applied at staging time, so that fetch issues bare loads and
-  // the loads stay in flight across the MFMAs of the current slab
-  // (out-of-range elements were loaded from offset 0 and are zeroed here)
-  auto fix_m = [&](double2 v, int i, int j, bool ok) -> double2 {
-    if (!ok) return make_double2(0.0, 0.0);
-    if (c.one_minus) { v.x = -v.x; v.y = -v.y; if (i == j) v.x += 1.0; }
-    return v;
-  };
-  auto fix_x = [&](double2 v, int i, int j, bool ok) -> double2 {
-    if (!ok) return make_double2(0.0, 0.0);
-    if (c.opX != 0) v.y = -v.y;
-    if (CORR && i == j) v.x -= 1.0;
+    if (OM) { v.x = -v.x; v.y = -v.y; if (i == j) v.x += 1.0; }
     return v;
   };
 
   constexpr int EA = BM * BKC / NT, EB = BN * BKC / NT;
   static_assert(EA * NT == BM * BKC && EB * NT == BN * BKC, "tile / thread mismatch");
+  // staging elements of this thread: A tile (m, k) with k fastest, B tile (k, n) with n fastest
+  int am[EA], ak[EA], bn_[EB], bk[EB];
+  const double2 *pa0[EA], *pa1[EA], *pb0[EB], *pb1[EB];
+  bool arow[EA], bcol[EB];
+#pragma unroll
+  for (int e = 0; e < EA; ++e) {
+    const int idx = tid + e * NT;
+    ak[e] = idx % BKC;
+    am[e] = idx / BKC;
+    arow[e] = m0 + am[e] < rows;
+    const int mr = arow[e] ? m0 + am[e] : 0;
+    if (LEFT) {
+      pa0[e] = X0 + (long long)mr * c.ldX + ak[e];
+      pa1[e] = X1 + (long long)mr * c.ldX + ak[e];
+    } else {
+      pa0[e] = M + (long long)mr * c.ldM + ak[e];
+      pa1[e] = pa0[e] + N;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    const int idx = tid + e * NT;
+    bn_[e] = idx % BN;
+    bk[e] = idx / BN;
+    bcol[e] = n0 + bn_[e] < cols;
+    const int nc = bcol[e] ? n0 + bn_[e] : 0;
+    if (LEFT) {
+      pb0[e] = M + (long long)bk[e] * c.ldM + nc;
+      pb1[e] = pb0[e] + (long long)N * c.ldM;
+    } else {
+      pb0[e] = X0 + (long long)bk[e] * c.ldX + nc;
+      pb1[e] = X1 + (long long)bk[e] * c.ldX + nc;
+    }
+  }
+  // k advances along a row of A and down a column of B
+  const long long bstep = LEFT ? (long long)c.ldM : (long long)c.ldX;
+
   double2 ra[EA][2], rb[EB][2];
-  // element e of the A (B) tile handled by this thread: tile coordinates
-  auto a_coord = [&](int e, int& m, int& k) {
-    const int idx = tid + e * NT;
-    if (LEFT && c.opX != 0) { m = idx % BM; k = idx / BM; } else { k = idx % BKC; m = idx / BKC; }
-  };
-  auto b_coord = [&](int e, int& n, int& k) {
-    const int idx = tid + e * NT;
-    if (!LEFT && c.opX != 0) { k = idx % BKC; n = idx / BKC; } else { n = idx % BN; k = idx / BN; }
-  };
+  // bare loads (out-of-range elements read the tile origin and are zeroed when staged)
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      int m, k;
-      a_coord(e, m, k);
-      const bool ok = m0 + m < rows && k0 + k < N;
-      if (LEFT) {
-        const long long off = !ok ? 0 : c.opX == 0 ? (long long)(m0 + m) * c.ldX + k0 + k
-                                                    : (long long)(k0 + k) * c.ldX + m0 + m;
-        ra[e][0] = X[0][off];
-        ra[e][1] = X[1][off];
-      } else {
-        const long long off = ok ? (long long)(m0 + m) * c.ldM + k0 + k : 0;
-        ra[e][0] = M[off];
-        ra[e][1] = M[off + N];
-      }
+      const bool ok = arow[e] && k0 + ak[e] < N;
+      const long long o = ok ? k0 : 0;
+      ra[e][0] = pa0[e][o];
+      ra[e][1] = pa1[e][o];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      int n, k;
-      b_coord(e, n, k);
-      const bool ok = n0 + n < cols && k0 + k < N;
-      if (LEFT) {
-        const long long off = ok ? (long long)(k0 + k) * c.ldM + n0 + n : 0;
-        rb[e][0] = M[off];
-        rb[e][1] = M[off + (long long)N * c.ldM];
-      } else {
-        const long long off = !ok ? 0 : c.opX == 0 ? (long long)(k0 + k) * c.ldX + n0 + n
-                                                    : (long long)(n0 + n) * c.ldX + k0 + k;
-        rb[e][0] = X[0][off];
-        rb[e][1] = X[1][off];
-      }
+      const bool ok = bcol[e] && k0 + bk[e] < N;
+      const long long o = ok ? (long long)k0 * bstep : 0;
+      rb[e][0] = pb0[e][o];
+      rb[e][1] = pb1[e][o];
     }
   };
-  // fix up, rotate (conj(U_ba) for LEFT, U_ba for RIGHT) and store to LDS stage st
+  const double2 zero2 = make_double2(0.0, 0.0);
+  // fix up, rotate and store to LDS stage st
   auto stage = [&](int st, int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      int m, k;
-      a_coord(e, m, k);
-      const bool ok = m0 + m < rows && k0 + k < N;
+      const bool ok = arow[e] && k0 + ak[e] < N;
+      double2 v0 = ok ? ra[e][0] : zero2, v1 = ok ? ra[e][1] : zero2;
+      const int m = am[e], k = ak[e];
       if (LEFT) {
-        As[st][0][k * LDA + m] = to_ct<CT>(fix_x(ra[e][0], m0 + m, k0 + k, ok));
-        As[st][1][k * LDA + m] = to_ct<CT>(fix_x(ra[e][1], m0 + m, k0 + k, ok));
+        // X_a; correction form stages X_a - 1
+        if (CORR && ok && m0 + m == k0 + k) { v0.x -= 1.0; v1.x -= 1.0; }
+        As[st][0][k * LDA + m] = to_ct<CT>(v0);
+        As[st][1][k * LDA + m] = to_ct<CT>(v1);
       } else {
-        const double2 v0 = fix_m(ra[e][0], m0 + m, k0 + k, ok), v1 = fix_m(ra[e][1], m0 + m, N + k0 + k, ok);
-        if (ROT) {
-#pragma unroll
-          for (int a = 0; a < 2; ++a) As[st][a][k * LDA + m] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
+        if (ROTK != ROT_NONE) {
+          double2 s0, s1;
+          rot_stage<false, ROTK>(v0, v1, s0, s1);
+          As[st][0][k * LDA + m] = to_ct<CT>(s0);
+          As[st][1][k * LDA + m] = to_ct<CT>(s1);
         } else {
           As[st][0][k * LDA + m] = to_ct<CT>(v0);
           As[st][1][k * LDA + m] = to_ct<CT>(v1);
@@ -346,21 +376,29 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      int n, k;
-      b_coord(e, n, k);
-      const bool ok = n0 + n < cols && k0 + k < N;
+      const bool ok = bcol[e] && k0 + bk[e] < N;
+      double2 v0 = ok ? rb[e][0] : zero2, v1 = ok ? rb[e][1] : zero2;
+      const int n = bn_[e], k = bk[e];
       if (LEFT) {
-        const double2 v0 = fix_m(rb[e][0], k0 + k, n0 + n, ok), v1 = fix_m(rb[e][1], N + k0 + k, n0 + n, ok);
-        if (ROT) {
-#pragma unroll
-          for (int a = 0; a < 2; ++a) Bs[st][a][k * LDB + n] = to_ct<CT>(cadd(cmul(u[0][a], v0), cmul(u[1][a], v1)));
+        if (OM && ok) {
+          v0 = make_double2(-v0.x, -v0.y);
+          v1 = make_double2(-v1.x, -v1.y);
+          if (k0 + k == n0 + n) v0.x += 1.0;
+          if (N + k0 + k == n0 + n) v1.x += 1.0;
+        }
+        if (ROTK != ROT_NONE) {
+          double2 s0, s1;
+          rot_stage<true, ROTK>(v0, v1, s0, s1);
+          Bs[st][0][k * LDB + n] = to_ct<CT>(s0);
+          Bs[st][1][k * LDB + n] = to_ct<CT>(s1);
         } else {
           Bs[st][0][k * LDB + n] = to_ct<CT>(v0);
           Bs[st][1][k * LDB + n] = to_ct<CT>(v1);
         }
       } else {
-        Bs[st][0][k * LDB + n] = to_ct<CT>(fix_x(rb[e][0], k0 + k, n0 + n, ok));
-        Bs[st][1][k * LDB + n] = to_ct<CT>(fix_x(rb[e][1], k0 + k, n0 + n, ok));
+        if (CORR && ok && k0 + k == n0 + n) { v0.x -= 1.0; v1.x -= 1.0; }
+        Bs[st][0][k * LDB + n] = to_ct<CT>(v0);
+        Bs[st][1][k * LDB + n] = to_ct<CT>(v1);
       }
     }
   };
@@ -421,14 +459,7 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
         const double2 t1 = make_double2(acc[1].re[si][sj][r], acc[1].im[si][sj][r]);
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-          double2 y;
-          if (ROT) {
-            // LEFT: Y_v = sum_a U_va T_a ; RIGHT: Y_{:,v} = sum_a T_a conj(U_va)
-            y = LEFT ? cadd(cmul(c.U[v][0], t0), cmul(c.U[v][1], t1))
-                     : cadd(cmul(t0, cconj(c.U[v][0])), cmul(t1, cconj(c.U[v][1])));
-          } else {
-            y = v == 0 ? t0 : t1;
-          }
+          double2 y = ROTK != ROT_NONE ? rot_out<LEFT, ROTK>(t0, t1, v) : (v == 0 ? t0 : t1);
           const long long off = LEFT ? (long long)(v * N + i) * c.ldY + j : (long long)i * c.ldY + v * N + j;
           if (CORR) y = cadd(y, LEFT ? mload(v * N + i, j) : mload(i, v * N + j));
           if (Cadd) {
@@ -446,8 +477,11 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
 template <typename CT, int BM, int BN, int WTM, int WTN>
 static void run_gemm(const GemmArgs& g, int nbatch, hipStream_t s) {
   constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, nbatch);
-  hipLaunchKernelGGL((zgemm_kernel<CT, BM, BN, WTM, WTN>), grid, dim3(NT), 0, s, g); cfqmc_post_launch("zgemm_kernel");
+  const int tx = (g.N + BN - 1) / BN, ty = (g.M + BM - 1) / BM;
+  const long long T = (long long)tx * ty * nbatch;
+  const int nblk = (int)((T + 7) / 8 * 8);
+  hipLaunchKernelGGL((zgemm_kernel<CT, BM, BN, WTM, WTN>), dim3(nblk), dim3(NT), 0, s, g, tx, ty, nbatch);
+  cfqmc_post_launch("zgemm_kernel");
 }
 
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s) {
@@ -469,25 +503,28 @@ void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t
   }
 }
 
-template <typename CT, bool LEFT, bool ROT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
 static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
   constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
   const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
   const int tx = (cols + BN - 1) / BN, ty = (rows + BM - 1) / BM;
   const long long T = (long long)tx * ty * nbatch;
   const int nblk = (int)((T + 7) / 8 * 8);
-  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROT, BM, BN, WTM, WTN, BKC, DB>), dim3(nblk), dim3(NT), 0, s, c, tx,
-                     ty, nbatch); cfqmc_post_launch("chan_apply_kernel");
+  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB>), dim3(nblk), dim3(NT), 0, s,
+                     c, tx, ty, nbatch); cfqmc_post_launch("chan_apply_kernel");
 }
 
 template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
 static void run_chan_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
   if (left) {
-    if (rot) run_chan<CT, true, true, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else run_chan<CT, true, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    if (rot == ROT_X) run_chan<CT, true, ROT_X, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else if (rot == ROT_Y) run_chan<CT, true, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else if (c.one_minus) run_chan<CT, true, ROT_NONE, true, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else run_chan<CT, true, ROT_NONE, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
   } else {
-    if (rot) run_chan<CT, false, true, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else run_chan<CT, false, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    if (rot == ROT_X) run_chan<CT, false, ROT_X, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else if (rot == ROT_Y) run_chan<CT, false, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    else run_chan<CT, false, ROT_NONE, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
   }
 }
 

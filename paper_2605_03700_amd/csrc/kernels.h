@@ -29,9 +29,8 @@ struct ChanArgs {
   int N;                    // orbital block size
   int n_other;              // columns of M (LEFT) or rows of M (RIGHT)
   const double2* M; int ldM; long long sM;
-  const double2* X0; const double2* X1; int ldX; long long sX; int opX;
-  double2 U[2][2];
-  int one_minus;            // use (1 - M) instead of M
+  const double2* X0; const double2* X1; int ldX; long long sX;   // orbital blocks e^{+-alpha h}
+  int one_minus;            // use (1 - M) instead of M (left, non-rotating channel)
   const double2* Cadd; int ldC; long long sC;   // optional addend
   double2* Y; int ldY; long long sY;
   double2* Y2;              // optional second copy of the output (same layout as Y)
@@ -41,6 +40,7 @@ struct ChanArgs {
 #define CFQMC_GEMM_CFGS 4
 #define CFQMC_CHAN_CFGS 8
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
+// rot: 0 none (channels 0, 3), 1 tau_x (channel 1), 2 tau_y (channel 2)
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);
 
 // ---- dense linear algebra (linalg.hip), one matrix per batch entry
@@ -123,6 +123,7 @@ void launch_exp_poly(const double2* H2, const double2* X2, const double2* X3, co
 
 struct StepArgs {
   int N, n, nq, L, tau;      // tau 0-based slice index
+  int nchain;                // chains in the launch (set by the launchers)
   const double2* G[4];       // frames G_0..G_3 (batch stride sG)
   long long sG;
   const double* phi; long long sphi;     // phi of slice tau (batch stride = chain stride)

@@ -488,8 +488,10 @@ __global__ void __launch_bounds__(NP_NT) lu_np_global_kernel(double2* Aall, int 
 // Same factorisation with the panel in LDS: the solved L21 (rows x 16, rows
 // padded to 17 entries against bank conflicts) and U12 (16 x columns) of each
 // panel are kept in LDS, so every trailing tile reads only its own A tile from
-// memory; 16 waves share the tiles.
-#define NP2_NT 1024
+// memory; 8 waves share the tiles, each loading the A tile of its next pass
+// while it multiplies the current one. L11^{-1} and U11^{-1} are formed column
+// by column in registers.
+#define NP2_NT 512
 #define NP2_LD 17
 __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
                                                        int sP, double2* logdet, int* flag_all, double lmax_allowed) {
@@ -515,7 +517,7 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
     __syncthreads();
     if (wid == 0) {
       for (int j = 0; j < nb; ++j) {
-        const double2 inv = cdiv(make_double2(1.0, 0.0), D[j][j]);
+        const double2 inv = crcp(D[j][j]);
         double2 nv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -538,23 +540,37 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
     }
     __syncthreads();
     if (wid == 0 && lane < NP_NB) {
+      // column t of L11^{-1} in registers, forward substitution (rows of D broadcast from LDS)
       const int t = lane;
+      double2 x[NP_NB];
+#pragma unroll
       for (int i = 0; i < NP_NB; ++i) {
-        double2 x = make_double2(i == t ? 1.0 : 0.0, 0.0);
-        if (i < nb)
-          for (int l = 0; l < i; ++l) x = csub(x, cmul(D[i][l], Li[l][t]));
-        Li[i][t] = x;
-      }
-    } else if (wid == 1 && lane < NP_NB) {
-      const int t = lane;
-      for (int i = NP_NB - 1; i >= 0; --i) {
-        double2 x = make_double2(i == t ? 1.0 : 0.0, 0.0);
+        double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
         if (i < nb) {
-          for (int l = i + 1; l < NP_NB; ++l) x = csub(x, cmul(D[i][l], Ui[l][t]));
-          x = cdiv(x, D[i][i]);
+#pragma unroll
+          for (int l = 0; l < i; ++l) v = csub(v, cmul(D[i][l], x[l]));
         }
-        Ui[i][t] = x;
+        x[i] = v;
       }
+#pragma unroll
+      for (int i = 0; i < NP_NB; ++i) Li[i][t] = x[i];
+    } else if (wid == 1 && lane < NP_NB) {
+      // column t of U11^{-1}, backward substitution
+      const int t = lane;
+      double2 x[NP_NB];
+#pragma unroll
+      for (int ii = 0; ii < NP_NB; ++ii) {
+        const int i = NP_NB - 1 - ii;
+        double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
+        if (i < nb) {
+#pragma unroll
+          for (int l = i + 1; l < NP_NB; ++l) v = csub(v, cmul(D[i][l], x[l]));
+          v = cmul(v, crcp(D[i][i]));
+        }
+        x[i] = v;
+      }
+#pragma unroll
+      for (int i = 0; i < NP_NB; ++i) Ui[i][t] = x[i];
     } else if (wid == 2) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -629,17 +645,28 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
         }
       }
       __syncthreads();
-      // trailing update A22 -= L21 U12, one 16 x 16 tile per wave per pass
+      // trailing update A22 -= L21 U12, one 16 x 16 tile per wave per pass; the
+      // A tile of the wave's next pass is loaded while this one is multiplied
       const int ntt = nt * nt;
+      double2 cur[4], nxt[4];
+      auto load_tile = [&](int t, double2 (&r)[4]) {
+        const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int i = t0 + r0 + Mfma<double>::row(lane, rr), jc = t0 + c0 + il;
+          const bool ok = t < ntt && i < n && jc < n;
+          r[rr] = A[ok ? (long long)i * lda + jc : 0];
+        }
+      };
+      if (wid < ntt) load_tile(wid, cur);
       for (int t = wid; t < ntt; t += NW) {
+        if (t + NW < ntt) load_tile(t + NW, nxt);
         const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
         d4v cre, cim;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const int i = t0 + r0 + Mfma<double>::row(lane, rr), jc = t0 + c0 + il;
-          const double2 v = (i < n && jc < n) ? A[(long long)i * lda + jc] : make_double2(0.0, 0.0);
-          cre[rr] = v.x;
-          cim[rr] = v.y;
+          cre[rr] = cur[rr].x;
+          cim[rr] = cur[rr].y;
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -656,6 +683,8 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
           const int i = t0 + r0 + Mfma<double>::row(lane, rr), jc = t0 + c0 + il;
           if (i < n && jc < n) A[(long long)i * lda + jc] = make_double2(cre[rr], cim[rr]);
         }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) cur[rr] = nxt[rr];
       }
     }
     __syncthreads();
@@ -728,23 +757,30 @@ void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, doub
 // block is solved wave-synchronously with shuffles.
 #define RS_ROWS 16
 #define RS_NT 256
-#define RS_NW (RS_NT / 64)
+#define RS_NW 4
 #define RS_MAXIT ((LU_MAXN + 4 * RS_NW - 1) / (4 * RS_NW))
 
 __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
                                                        int ldy, long long sY, const double2* LUall, int ldlu,
                                                        long long sLU, const int* ipiv_all, int sP, int n,
-                                                       int upper_only) {
-  extern __shared__ double2 Zs[];          // 16 x n row block
+                                                       int upper_only, int nbatch) {
+  extern __shared__ double2 Zs[];          // 16 x n row block, rows padded to an odd length
+  const int zl = n | 1;                    // odd row stride: a quarter wave reading one column hits 16 banks
   __shared__ double2 red[RS_NW][16][16];
   __shared__ double2 Db[16][16];           // diagonal block of U or L
+  __shared__ double2 Dr[16];               // reciprocals of the diagonal of U_JJ
   __shared__ int perm[LU_MAXN];
-  const int z = blockIdx.y;
+  // all row blocks of one chain on one XCD (consecutive workgroups go to the
+  // eight XCDs in turn), so the chain's factors are read into one L2
+  const int nrb = (n + RS_ROWS - 1) / RS_ROWS, T = nrb * nbatch, per = (T + 7) / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= T) return;
+  const int z = t / nrb;
   const double2* X = Xall + z * sX;
   double2* Yo = Yall + z * sY;
   const double2* LU = LUall + z * sLU;
   const int* ipiv = ipiv_all + z * sP;
-  const int r0 = blockIdx.x * RS_ROWS;
+  const int r0 = (t % nrb) * RS_ROWS;
   const int nr = min(RS_ROWS, n - r0);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int il = lane & 15, kl = lane >> 4;
@@ -753,10 +789,11 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
   for (int i = tid; i < n; i += RS_NT) perm[i] = upper_only ? i : ipiv[i];
   for (int idx = tid; idx < RS_ROWS * n; idx += RS_NT) {
     const int r = idx / n, c = idx % n;
-    Zs[idx] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
+    Zs[r * zl + c] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   const int nJ = (n + 15) / 16;
+  const double2 zero2 = make_double2(0.0, 0.0);
   for (int phase = 0; phase < (upper_only ? 1 : 2); ++phase) {
     for (int jj = 0; jj < nJ; ++jj) {
       const int J = phase == 0 ? jj : nJ - 1 - jj;
@@ -767,15 +804,19 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
 #pragma unroll
       for (int it = 0; it < RS_MAXIT; ++it) {
         const int k = klo + wid * 4 + it * 4 * RS_NW + kl;
-        bb[it] = (k < khi && il < bw) ? LU[(long long)perm[k] * ldlu + c0 + il] : make_double2(0.0, 0.0);
+        const bool ok = k < khi && il < bw;
+        bb[it] = LU[ok ? (long long)perm[k] * ldlu + c0 + il : 0];
       }
+      const bool okd = rr < bw && cc < bw;
+      const double2 dv = LU[okd ? (long long)perm[c0 + rr] * ldlu + c0 + cc : 0];
       d4v are = Mfma<double>::zero(), aim = Mfma<double>::zero();
 #pragma unroll
       for (int it = 0; it < RS_MAXIT; ++it) {
         const int k = klo + wid * 4 + it * 4 * RS_NW + kl;
         if (klo + wid * 4 + it * 4 * RS_NW < khi) {
-          const double2 a = k < khi ? Zs[il * n + k] : make_double2(0.0, 0.0);
-          const double2 b = bb[it];
+          const bool ok = k < khi;
+          const double2 a = ok ? Zs[il * zl + k] : zero2;
+          const double2 b = ok && il < bw ? bb[it] : zero2;
           are = Mfma<double>::mma(a.x, b.x, are);
           are = Mfma<double>::mma(-a.y, b.y, are);
           aim = Mfma<double>::mma(a.x, b.y, aim);
@@ -784,21 +825,17 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wid][Mfma<double>::row(lane, q)][il] = make_double2(are[q], aim[q]);
-      if (rr < 16)
-        Db[rr][cc] = (rr < bw && cc < bw) ? LU[(long long)perm[c0 + rr] * ldlu + c0 + cc]
-                                          : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+      const double2 dd = okd ? dv : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+      Db[rr][cc] = dd;
+      // reciprocals of the diagonal, one division per lane in parallel
+      if (phase == 0 && rr == cc) Dr[cc] = crcp(dd);
       __syncthreads();
-      double2 y = make_double2(0.0, 0.0);
-      if (rr < 16) {
-        y = Zs[rr * n + c0 + min(cc, bw - 1)];
-        for (int w = 0; w < RS_NW; ++w) y = csub(y, red[w][rr][cc]);
-      }
-      if (rr >= 16) {
-        // waves beyond the 16 x 16 block solve only join the barriers
-      } else if (phase == 0) {
+      double2 y = Zs[rr * zl + c0 + min(cc, bw - 1)];
+      for (int w = 0; w < RS_NW; ++w) y = csub(y, red[w][rr][cc]);
+      if (phase == 0) {
         // z U_JJ = y, columns ascending
         for (int cp = 0; cp < 16; ++cp) {
-          double2 zv = cdiv(y, Db[cp][cp]);
+          double2 zv = cmul(y, Dr[cp]);
           zv.x = __shfl(zv.x, (lane & ~15) + cp, 64);
           zv.y = __shfl(zv.y, (lane & ~15) + cp, 64);
           if (cc == cp) y = zv;
@@ -814,13 +851,13 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
         }
       }
       __syncthreads();
-      if (rr < 16 && cc < bw) Zs[rr * n + c0 + cc] = y;
+      if (cc < bw) Zs[rr * zl + c0 + cc] = y;
       __syncthreads();
     }
   }
   for (int idx = tid; idx < nr * n; idx += RS_NT) {
     const int r = idx / n, c = idx % n;
-    Yo[(long long)(r0 + r) * ldy + perm[c]] = Zs[r * n + c];
+    Yo[(long long)(r0 + r) * ldy + perm[c]] = Zs[r * zl + c];
   }
 }
 
@@ -878,15 +915,16 @@ void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy,
                    int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only, int nbatch,
                    hipStream_t s) {
   dim3 grid((n + RS_ROWS - 1) / RS_ROWS, nbatch);
-  const size_t shm = (size_t)RS_ROWS * n * sizeof(double2);
+  const size_t shm = (size_t)RS_ROWS * (n | 1) * sizeof(double2);
   if (!set_lds_limit((const void*)rsolve_kernel, shm)) {
     dim3 g2((n + RSS_ROWS - 1) / RSS_ROWS, nbatch);
     hipLaunchKernelGGL(rsolve_simple_kernel, g2, dim3(RSS_NT), (size_t)RSS_ROWS * n * sizeof(double2), s, X, ldx, sX,
                        Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n, upper_only); cfqmc_post_launch("rsolve_simple_kernel");
     return;
   }
-  hipLaunchKernelGGL(rsolve_kernel, grid, dim3(RS_NT), shm, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n,
-                     upper_only); cfqmc_post_launch("rsolve_kernel");
+  const int nblk = (int)(((long long)grid.x * nbatch + 7) / 8 * 8);
+  hipLaunchKernelGGL(rsolve_kernel, dim3(nblk), dim3(RS_NT), shm, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP,
+                     n, upper_only, nbatch); cfqmc_post_launch("rsolve_kernel");
 }
 
 // ------------------------------------------------------------------ elementwise helpers

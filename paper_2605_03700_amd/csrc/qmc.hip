@@ -212,11 +212,25 @@ CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, do
 
 #define DR_MAXROW 1024
 
+// (row, channel, chain) of this workgroup: all workgroups of a chain on one XCD
+// (consecutive workgroups go to the eight XCDs in turn), so its frames share an L2.
+CF_DEV bool drift_block(int nrow, int nchain, int& row, int& ch, int& z) {
+  const int per_chain = 4 * nrow, T = per_chain * nchain, per = (T + 7) / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= T) return false;
+  z = t / per_chain;
+  ch = (t % per_chain) / nrow;
+  row = t % nrow;
+  return true;
+}
+
 __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepArgs a) {
   __shared__ double2 d1[DR_MAXN], d2[DR_MAXN];
   __shared__ double Dl[DR_MAXROW];
   __shared__ double red[DR_NT / 64];
-  const int row = blockIdx.x, ch = blockIdx.y, z = blockIdx.z, nq = m.nq;
+  int row, ch, z;
+  if (!drift_block(m.nrow, a.nchain, row, ch, z)) return;
+  const int nq = m.nq;
   const double2* G = a.G[ch] + z * a.sG;
   const double* phi = a.phi + z * a.sphi + ch * nq;
   double* phip = a.phip + z * a.sphip + ch * nq;
@@ -251,7 +265,9 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
   __shared__ double Dl[DR_MAXROW];
   __shared__ double red[DR_NT / 64];
   __shared__ unsigned last;
-  const int row = blockIdx.x, ch = blockIdx.y, z = blockIdx.z, nq = m.nq;
+  int row, ch, z;
+  if (!drift_block(m.nrow, a.nchain, row, ch, z)) return;
+  const int nq = m.nq;
   const double2* G = a.G[ch] + z * a.sG;
   const double* phi = a.phi + z * a.sphi + ch * nq;
   const double* phip = a.phip + z * a.sphip + ch * nq;
@@ -310,12 +326,16 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
 }
 
 void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s) {
-  dim3 grid(m.nrow, 4, nchain);
-  hipLaunchKernelGGL(drift_propose_kernel, grid, dim3(DR_NT), 0, s, m, a); cfqmc_post_launch("drift_propose_kernel");
+  StepArgs b = a;
+  b.nchain = nchain;
+  const int nblk = (int)(((long long)m.nrow * 4 * nchain + 7) / 8 * 8);
+  hipLaunchKernelGGL(drift_propose_kernel, dim3(nblk), dim3(DR_NT), 0, s, m, b); cfqmc_post_launch("drift_propose_kernel");
 }
 void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s) {
-  dim3 grid(m.nrow, 4, nchain);
-  hipLaunchKernelGGL(drift_mh_kernel, grid, dim3(DR_NT), 0, s, m, a); cfqmc_post_launch("drift_mh_kernel");
+  StepArgs b = a;
+  b.nchain = nchain;
+  const int nblk = (int)(((long long)m.nrow * 4 * nchain + 7) / 8 * 8);
+  hipLaunchKernelGGL(drift_mh_kernel, dim3(nblk), dim3(DR_NT), 0, s, m, b); cfqmc_post_launch("drift_mh_kernel");
 }
 
 // ------------------------------------------------------------------ commit
