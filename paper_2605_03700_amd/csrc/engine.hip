@@ -228,7 +228,6 @@ struct cfqmc_ctx {
   double* lnA;
   int* accept;
   double* stat;
-  unsigned* done;
   double* part;
   double* obs;
   double* stab_err;
@@ -363,26 +362,35 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
     launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
   }
   {
+    // P, Q = E +- alpha h O; matrices with squaring count 0 go straight to out
     GemmArgs g = gemm0(N, N, N);
     g.mode = GEMM_PQ;
     g.A = mref(hb, N, s4, NN); g.B = mref(c->Oo, N, s4, NN); g.C = mref(c->Eo, N, s4, NN);
     g.alpha_dev = (const double2*)(c->coef + 14);
     g.ad_s1 = 4 * EXP_NC / 2; g.ad_s2 = EXP_NC / 2;
     g.nz2 = 4;
-    double2* dst = c->smax > 0 ? c->Wa : out;
-    const long long sd = c->smax > 0 ? 8 * NN : sOut;
-    g.D = mref(dst, N, sd, 2 * NN);
-    g.D2 = mref(dst + NN, N, sd, 2 * NN);
+    g.E = mref(out, N, sOut, 2 * NN);
+    g.E2 = mref(out + NN, N, sOut, 2 * NN);
+    if (c->smax > 0) {
+      g.D = mref(c->Wa, N, 8 * NN, 2 * NN);
+      g.D2 = mref(c->Wa + NN, N, 8 * NN, 2 * NN);
+      g.pred = c->sq; g.pred_s1 = 8; g.pred_s2 = 2;
+    } else {
+      g.D = g.E;
+      g.D2 = g.E2;
+    }
     launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
   }
+  // squaring step j on the matrices that need more than j squarings; the last
+  // step of each matrix writes it to out
   for (int j = 0; j < c->smax; ++j) {
     double2* src = (j % 2 == 0) ? c->Wa : c->Wb;
-    double2* dst = (j == c->smax - 1) ? out : ((j % 2 == 0) ? c->Wb : c->Wa);
-    const long long sd = (j == c->smax - 1) ? sOut : 8 * NN;
+    double2* dst = (j % 2 == 0) ? c->Wb : c->Wa;
     GemmArgs g = gemm0(N, N, N);
-    g.mode = GEMM_SQUARE_OR_COPY;
+    g.mode = GEMM_SQUARE;
     g.A = mref(src, N, 8 * NN, NN); g.B = mref(src, N, 8 * NN, NN);
-    g.D = mref(dst, N, sd, NN);
+    g.D = mref(dst, N, 8 * NN, NN);
+    g.E = mref(out, N, sOut, NN);
     g.nz2 = 8;
     g.pred = c->sq; g.pred_s1 = 8; g.pred_s2 = 1; g.pred_thresh = j;
     launch_zgemm(g, nent * 8, 0, c->cfg_small, c->s);
@@ -538,7 +546,7 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   a.snoise = (long long)c->L * (4 * c->nq + 1);
   a.seed = c->p.seed;
   a.counter = c->sweep_counter * c->L + t;
-  a.part = c->part; a.nblk = 4 * c->md.nrow; a.done = c->done;
+  a.part = c->part; a.nblk = 4 * c->md.nrow;
   a.lndetM = c->lndet; a.lnA = c->lnA; a.accept = c->accept; a.stat = c->stat;
   launch_drift_propose(c->md, a, c->nch, c->s);
   // 3. exponentials of the proposed fields
@@ -572,7 +580,7 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   for (int i = 0; i < 4; ++i) a.G[i] = c->Fp[i];
   launch_drift_mh(c->md, a, c->nch, c->s);
   // 8. commit
-  launch_commit(c->accept, c->nch, c->Fp[0], c->F[0], c->G, nn, nn, c->phip, 4 * c->nq,
+  launch_commit(a, c->nch, c->Fp[0], c->F[0], c->G, nn, nn, c->phip, 4 * c->nq,
                 c->phi + (long long)t * 4 * c->nq, (long long)c->L * 4 * c->nq, 4 * c->nq, c->PQp, sPQp,
                 c->PQ + (long long)t * 8 * NN, sPQ, 8 * NN, c->acc_count, c->s);
   // history of this slice
@@ -801,7 +809,6 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->lnA, (size_t)B);
   rc |= dalloc(c, &c->accept, (size_t)B);
   rc |= dalloc(c, &c->stat, (size_t)B * 8);
-  rc |= dalloc(c, &c->done, (size_t)B);
   rc |= dalloc(c, &c->part, (size_t)B * 4 * 4 * 1024);
   rc |= dalloc(c, &c->obs, (size_t)B * 8);
   rc |= dalloc(c, &c->stab_err, (size_t)B * 4);
@@ -893,7 +900,6 @@ int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
   HIPCHK(hipMemsetAsync(c->acc_count, 0, B * sizeof(int), c->s));
   HIPCHK(hipMemsetAsync(c->stat, 0, B * 8 * sizeof(double), c->s));
   HIPCHK(hipMemsetAsync(c->stab_err, 0, B * 4 * sizeof(double), c->s));
-  HIPCHK(hipMemsetAsync(c->done, 0, B * sizeof(unsigned), c->s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   int ef = 0;

@@ -124,8 +124,9 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   const double2* A = mat_at(g.A, z1, z2);
   const double2* B = mat_at(g.B, z1, z2);
 
-  bool do_mul = true;
-  if (g.mode == GEMM_SQUARE_OR_COPY) do_mul = g.pred[z1 * g.pred_s1 + z2 * g.pred_s2] > g.pred_thresh;
+  // squaring count of this matrix: a squaring step past it has nothing to do
+  const int nsq = g.pred ? g.pred[z1 * g.pred_s1 + z2 * g.pred_s2] : 0;
+  if (g.mode == GEMM_SQUARE && nsq <= g.pred_thresh) return;
 
   constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
   double2 ra[EA], rb[EB];
@@ -178,7 +179,7 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   };
   Acc<double, WTM, WTN> acc;
   acc.zero();
-  if (do_mul) {
+  {
     fetch(0);
     for (int k0 = 0; k0 < g.K; k0 += BK) {
       stage(k0);
@@ -198,9 +199,12 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   }
   double2 alpha = g.alpha;
   if (g.alpha_dev) alpha = cmul(alpha, g.alpha_dev[z1 * g.ad_s1 + z2 * g.ad_s2]);
-  double2* D = mat_at(g.D, z1, z2);
+  // with squaring counts: a matrix whose last step this is goes to its final place
+  const bool fin = g.pred && (g.mode == GEMM_SQUARE ? nsq == g.pred_thresh + 1 : nsq == 0);
+  double2* D = fin ? mat_at(g.E, z1, z2) : mat_at(g.D, z1, z2);
   const double2* Cm = g.C.p ? mat_at(g.C, z1, z2) : nullptr;
-  double2* D2 = g.D2.p ? mat_at(g.D2, z1, z2) : nullptr;
+  double2* D2 = fin ? (g.E2.p ? mat_at(g.E2, z1, z2) : nullptr) : (g.D2.p ? mat_at(g.D2, z1, z2) : nullptr);
+  const int ldd = fin ? g.E.ld : g.D.ld, ldd2 = fin ? g.E2.ld : g.D2.ld;
 #pragma unroll
   for (int si = 0; si < WTM; ++si)
 #pragma unroll
@@ -211,17 +215,17 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
         const int j = n0 + wn0 + sj * 16 + (lane & 15);
         if (i >= g.M || j >= g.N) continue;
         double2 p = make_double2(acc.re[si][sj][r], acc.im[si][sj][r]);
-        if (g.mode == GEMM_SQUARE_OR_COPY) {
-          D[(long long)i * g.D.ld + j] = do_mul ? p : B[(long long)i * g.B.ld + j];
+        if (g.mode == GEMM_SQUARE) {
+          D[(long long)i * ldd + j] = p;
         } else if (g.mode == GEMM_PQ) {
           double2 x = cmul(alpha, p);
           double2 c = Cm[(long long)i * g.C.ld + j];
-          D[(long long)i * g.D.ld + j] = cadd(c, x);
-          D2[(long long)i * g.D2.ld + j] = csub(c, x);
+          D[(long long)i * ldd + j] = cadd(c, x);
+          D2[(long long)i * ldd2 + j] = csub(c, x);
         } else {
           double2 v = cmul(alpha, p);
           if (Cm) v = cadd(v, cmul(g.beta, Cm[(long long)i * g.C.ld + j]));
-          D[(long long)i * g.D.ld + j] = v;
+          D[(long long)i * ldd + j] = v;
         }
       }
 }

@@ -5,7 +5,10 @@
 
 #include "common.h"
 
-enum { GEMM_NORMAL = 0, GEMM_PQ = 1, GEMM_SQUARE_OR_COPY = 2 };
+// GEMM_PQ: D = C + alpha A B, D2 = C - alpha A B.
+// GEMM_SQUARE: one step of repeated squaring, step number pred_thresh, of the
+// matrices whose squaring count pred[...] exceeds it (the others return at once).
+enum { GEMM_NORMAL = 0, GEMM_PQ = 1, GEMM_SQUARE = 2 };
 
 // Launch checking: with CFQMC_DEBUG_SYNC=1 in the environment every launch is
 // followed by a device synchronisation and an error check naming the kernel.
@@ -16,12 +19,13 @@ struct GemmArgs {
   int M, N, K;
   int opA, opB;             // 0: as stored, 1: conjugate transpose
   MatRef A, B, C, D, D2;    // C may have p == nullptr (beta ignored)
+  MatRef E, E2;             // with pred: final destinations of matrices that need no further squaring
   int nz2;                  // inner batch count (z = z1 * nz2 + z2)
   double2 alpha, beta;
   const double2* alpha_dev; // optional per-batch factor, index z1*ad_s1 + z2*ad_s2
   int ad_s1, ad_s2;
   int mode;
-  const int* pred;          // GEMM_SQUARE_OR_COPY: multiply iff pred[...] > pred_thresh
+  const int* pred;          // squaring count per matrix (GEMM_PQ, GEMM_SQUARE), index z1*pred_s1 + z2*pred_s2
   int pred_s1, pred_s2, pred_thresh;
 };
 
@@ -134,7 +138,6 @@ struct StepArgs {
   uint64_t seed; long long counter;      // RNG counter base (sweep/slice)
   double* part;              // partial sums [chain][nblk][4]
   int nblk;
-  unsigned* done;            // [chain] arrival counter
   const double2* lndetM;     // [chain]
   double* lnA;               // [chain]
   int* accept;               // [chain]
@@ -144,8 +147,9 @@ struct StepArgs {
 void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s);
 void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s);
 
-// commit accepted slice move
-void launch_commit(const int* accept, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
+// Metropolis-Hastings decision from the drift kernels' partial sums, then
+// commit of the accepted slice move
+void launch_commit(const StepArgs& a, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
                    long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi, int nphi,
                    const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ, long long npq,
                    int* acc_count, hipStream_t s);

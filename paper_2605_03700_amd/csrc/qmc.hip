@@ -15,6 +15,8 @@
 //                eps <- eps + (r_a - r_0) d_eps after each sweep.
 //  observables   S^i_{q=0} and m^2_SO(5) by Wick's theorem from G.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include "common.h"
 #include "kernels.h"
 
@@ -75,19 +77,30 @@ void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double
 __global__ void exp_coef_kernel(const double2* X2all, const double2* X3all, int N, const double2* alpha,
                                 int alpha_div, double* coef, int* sq, int smax, double theta, int* err) {
   __shared__ double red[4];
+  __shared__ double cs2[256], cs3[256];
   const int b4 = blockIdx.x;   // batch * 4 + channel
   const double2* X2 = X2all + (long long)b4 * N * N;
   const double2* X3 = X3all + (long long)b4 * N * N;
-  double n2 = 0.0, n3 = 0.0;
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    double s2 = 0.0, s3 = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < N; ++i) {
+  // 1-norms (max column sums of |x|), N <= 256 (n_phi <= 140): R = 256 / N
+  // row groups of threads per column, partial sums combined in LDS
+  const int R = 256 / N;
+  const int t = threadIdx.x, c = t % N, r0 = t / N;
+  double s2 = 0.0, s3 = 0.0;
+  if (r0 < R) {
+#pragma unroll 4
+    for (int i = r0; i < N; i += R) {
       s2 += sqrt(cabs2(X2[(long long)i * N + c]));
       s3 += sqrt(cabs2(X3[(long long)i * N + c]));
     }
-    n2 = fmax(n2, s2);
-    n3 = fmax(n3, s3);
+  }
+  cs2[t] = s2;
+  cs3[t] = s3;
+  __syncthreads();
+  double n2 = 0.0, n3 = 0.0;
+  if (r0 == 0) {
+    for (int r = 1; r < R; ++r) { s2 += cs2[t + r * N]; s3 += cs3[t + r * N]; }
+    n2 = s2;
+    n3 = s3;
   }
   for (int o = 32; o > 0; o >>= 1) { n2 = fmax(n2, __shfl_xor(n2, o, 64)); n3 = fmax(n3, __shfl_xor(n3, o, 64)); }
   __shared__ double r3[4];
@@ -120,6 +133,7 @@ __global__ void exp_coef_kernel(const double2* X2all, const double2* X3all, int 
 }
 void launch_exp_coef(const double2* X2, const double2* X3, int N, const double2* alpha, int alpha_div,
                      double* coef, int* sq, int smax, double theta, int* err, int nbatch4, hipStream_t s) {
+  if (N > 256) { std::fprintf(stderr, "exp_coef: N = %d exceeds 256\n", N); std::abort(); }
   hipLaunchKernelGGL(exp_coef_kernel, dim3(nbatch4), dim3(256), 0, s, X2, X3, N, alpha, alpha_div, coef, sq, smax,
                      theta, err); cfqmc_post_launch("exp_coef_kernel");
 }
@@ -169,43 +183,46 @@ CF_DEV double2 ytilde(const double2* G, int N, int n, int ch, int a, int b) {
 #define DR_MAXN 288
 
 // Drift D = -phi + 2 Re[alpha Tr((1 - G_i)(o_i kron q_c))] of all components in
-// trace row `row` of channel `ch`, written to Dl[t - toff[row]].
+// trace row `row` of channel `ch`, written to Dl[t - toff[row]]. One thread per
+// component: the trace is a length-N phase sum over the two shifted diagonals
+// d1, d2 held in LDS (all lanes of a wave read the same k: broadcast), with the
+// phase table in LDS and its index advanced by 2 q_x (mod 2N) per k.
 CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, double2 alpha, int ch, int row,
-                      double* Dl, double2* d1, double2* d2) {
-  const int N = m.N, n = m.n, qy = m.t_qy[row];
+                      double* Dl, double2* d1, double2* d2, double2* ph) {
+  const int N = m.N, n = m.n, qy = m.t_qy[row], N2 = 2 * N;
   const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
   for (int k = threadIdx.x; k < N; k += DR_NT) {
     d1[k] = ytilde(G, N, n, ch, ((k - qy) % N + N) % N, k);
     d2[k] = ytilde(G, N, n, ch, k, ((k - qy) % N + N) % N);
   }
+  for (int i = threadIdx.x; i < N2; i += DR_NT) ph[i] = m.phase[i];
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int t = c_lo + w; t < c_hi; t += DR_NT / 64) {
+  for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
     const int qx = m.t_qx[t];
-    double2 tp = make_double2(0.0, 0.0), tm = tp;
-    for (int k = lane; k < N; k += 64) {
-      int mm = ((2 * (k + 1) - qy) * qx) % (2 * N);
-      if (mm < 0) mm += 2 * N;
-      const double2 ph = m.phase[mm];
-      tp = cadd(tp, cmul(d1[k], ph));
-      tm = cadd(tm, cmul(d2[k], cconj(ph)));
+    // phase index ((2 (k + 1) - q_y) q_x) mod 2N at k = 0, and its step
+    int mm = ((2 - qy) * qx) % N2;
+    if (mm < 0) mm += N2;
+    int st = (2 * qx) % N2;
+    if (st < 0) st += N2;
+    double tpx = 0.0, tpy = 0.0, tmx = 0.0, tmy = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double2 p = ph[mm], a1 = d1[k], a2 = d2[k];
+      tpx += a1.x * p.x - a1.y * p.y;
+      tpy += a1.x * p.y + a1.y * p.x;
+      tmx += a2.x * p.x + a2.y * p.y;     // d2 conj(p)
+      tmy += a2.y * p.x - a2.x * p.y;
+      mm += st;
+      if (mm >= N2) mm -= N2;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      tp.x += __shfl_xor(tp.x, o, 64); tp.y += __shfl_xor(tp.y, o, 64);
-      tm.x += __shfl_xor(tm.x, o, 64); tm.y += __shfl_xor(tm.y, o, 64);
-    }
-    if (lane == 0) {
-      const double f = m.t_F[t];
-      tp = cscale(tp, f);
-      tm = cscale(tm, f);
-      double2 v;
-      const int kind = m.t_kind[t];
-      if (kind == 0) v = cscale(tp, sqrt(2.0));                                  // sqrt(2) m_q
-      else if (kind == 1) v = cadd(tp, tm);                                      // m_q + m_q^dagger
-      else { const double2 d = csub(tp, tm); v = make_double2(-d.y, d.x); }      // i (m_q - m_q^dagger)
-      const double2 av = cmul(alpha, v);
-      Dl[t - c_lo] = -phi[m.t_comp[t]] + 2.0 * av.x;
-    }
+    const double f = m.t_F[t];
+    const double2 tp = make_double2(tpx * f, tpy * f), tm = make_double2(tmx * f, tmy * f);
+    double2 v;
+    const int kind = m.t_kind[t];
+    if (kind == 0) v = cscale(tp, sqrt(2.0));                                  // sqrt(2) m_q
+    else if (kind == 1) v = cadd(tp, tm);                                      // m_q + m_q^dagger
+    else { const double2 d = csub(tp, tm); v = make_double2(-d.y, d.x); }      // i (m_q - m_q^dagger)
+    const double2 av = cmul(alpha, v);
+    Dl[t - c_lo] = -phi[m.t_comp[t]] + 2.0 * av.x;
   }
   __syncthreads();
 }
@@ -225,7 +242,7 @@ CF_DEV bool drift_block(int nrow, int nchain, int& row, int& ch, int& z) {
 }
 
 __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepArgs a) {
-  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN];
+  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN], ph[2 * DR_MAXN];
   __shared__ double Dl[DR_MAXROW];
   __shared__ double red[DR_NT / 64];
   int row, ch, z;
@@ -235,7 +252,7 @@ __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepAr
   const double* phi = a.phi + z * a.sphi + ch * nq;
   double* phip = a.phip + z * a.sphip + ch * nq;
   const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
-  row_drift(m, G, phi, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2);
+  row_drift(m, G, phi, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2, ph);
   const double eps = a.eps[z];
   double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0;
   for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
@@ -261,10 +278,9 @@ __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepAr
 }
 
 __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a) {
-  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN];
+  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN], ph[2 * DR_MAXN];
   __shared__ double Dl[DR_MAXROW];
   __shared__ double red[DR_NT / 64];
-  __shared__ unsigned last;
   int row, ch, z;
   if (!drift_block(m.nrow, a.nchain, row, ch, z)) return;
   const int nq = m.nq;
@@ -272,7 +288,7 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
   const double* phi = a.phi + z * a.sphi + ch * nq;
   const double* phip = a.phip + z * a.sphip + ch * nq;
   const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
-  row_drift(m, G, phip, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2);   // drift at the proposed fields
+  row_drift(m, G, phip, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2, ph);   // drift at the proposed fields
   const double eps = a.eps[z];
   double s_rev = 0.0;
   for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
@@ -281,29 +297,29 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
     s_rev += r * r;
   }
   s_rev = block_sum<DR_NT>(s_rev, red);
-  if (threadIdx.x == 0) {
-    double* p = a.part + ((long long)z * a.nblk + ch * m.nrow + row) * 4;
-    p[3] = s_rev;
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.done[z], 1u);
-    last = (prev == (unsigned)a.nblk - 1) ? 1u : 0u;
+  if (threadIdx.x == 0) a.part[((long long)z * a.nblk + ch * m.nrow + row) * 4 + 3] = s_rev;
+}
+
+// Metropolis-Hastings decision of chain z from the partial sums the two drift
+// kernels left per workgroup (read after the kernel boundary, so no fence or
+// arrival counter is needed). Every workgroup that calls it gets the same
+// result (same data, same reduction order); only the one with `write` stores
+// ln A, the decision and the running statistics. Block size DR_NT.
+CF_DEV int mh_decide(const StepArgs& a, int z, bool write, double* red, int* acc_s) {
+  double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0, s_r = 0.0;
+  const double* pp = a.part + (long long)z * a.nblk * 4;
+  for (int b = threadIdx.x; b < a.nblk; b += DR_NT) {
+    s_norm += pp[b * 4 + 0];
+    s_eta += pp[b * 4 + 1];
+    s_bg += pp[b * 4 + 2];
+    s_r += pp[b * 4 + 3];
   }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0, s_r = 0.0;
-    const volatile double* pp = a.part + (long long)z * a.nblk * 4;
-    for (int b = threadIdx.x; b < a.nblk; b += DR_NT) {
-      s_norm += pp[b * 4 + 0];
-      s_eta += pp[b * 4 + 1];
-      s_bg += pp[b * 4 + 2];
-      s_r += pp[b * 4 + 3];
-    }
-    s_norm = block_sum<DR_NT>(s_norm, red);
-    s_eta = block_sum<DR_NT>(s_eta, red);
-    s_bg = block_sum<DR_NT>(s_bg, red);
-    s_r = block_sum<DR_NT>(s_r, red);
-    if (threadIdx.x != 0) return;
+  s_norm = block_sum<DR_NT>(s_norm, red);
+  s_eta = block_sum<DR_NT>(s_eta, red);
+  s_bg = block_sum<DR_NT>(s_bg, red);
+  s_r = block_sum<DR_NT>(s_r, red);
+  if (threadIdx.x == 0) {
+    const double eps = a.eps[z];
     const double2 ldm = a.lndetM[z];
     const double2 al0 = a.alpha[z * 4 + 0];
     // ln R = 2 ln det M + (c' - c); real for the sign-free model, the phase is monitored
@@ -312,17 +328,21 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
     if (ph > M_PI) ph -= 2.0 * M_PI;
     if (ph < -M_PI) ph += 2.0 * M_PI;
     const double lnA = -0.5 * s_norm + lnR - s_r / (2.0 * eps * eps) + 0.5 * s_eta;
-    const double u = a.noise ? a.noise[z * a.snoise + 4 * nq] : rng_uniform(a.seed, z, a.counter);
+    const double u = a.noise ? a.noise[z * a.snoise + 4 * a.nq] : rng_uniform(a.seed, z, a.counter);
     const int acc = (u <= 0.0) ? 1 : (log(u) < lnA ? 1 : 0);
-    a.lnA[z] = lnA;
-    a.accept[z] = acc;
-    if (a.u_out) a.u_out[z] = u;
-    double* st = a.stat + z * 8;
-    st[0] = fmax(st[0], fabs(ph));
-    st[1] += 1.0;
-    st[2] += acc;
-    a.done[z] = 0u;
+    *acc_s = acc;
+    if (write) {
+      a.lnA[z] = lnA;
+      a.accept[z] = acc;
+      if (a.u_out) a.u_out[z] = u;
+      double* st = a.stat + z * 8;
+      st[0] = fmax(st[0], fabs(ph));
+      st[1] += 1.0;
+      st[2] += acc;
+    }
   }
+  __syncthreads();
+  return *acc_s;
 }
 
 void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s) {
@@ -339,12 +359,18 @@ void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream
 }
 
 // ------------------------------------------------------------------ commit
-__global__ void commit_kernel(const int* accept, const double2* Gp, const double2* G0, double2* G, long long nn,
-                              long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi,
-                              int nphi, const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ,
-                              long long npq, int* acc_count) {
+// Takes the Metropolis-Hastings decision of the slice move (every workgroup of
+// a chain recomputes it; workgroup 0 records it) and commits the accepted move:
+// G <- G', the slice exponentials and fields <- the proposed ones.
+__global__ void __launch_bounds__(DR_NT) commit_kernel(StepArgs a, const double2* Gp, const double2* G0, double2* G,
+                                                       long long nn, long long sG, const double* phip,
+                                                       long long sphip, double* phi_tau, long long sphi, int nphi,
+                                                       const double2* PQp, long long sPQp, double2* PQ_tau,
+                                                       long long sPQ, long long npq, int* acc_count) {
+  __shared__ double red[DR_NT / 64];
+  __shared__ int acc_s;
   const int z = blockIdx.y;
-  const int acc = accept[z];
+  const int acc = mh_decide(a, z, blockIdx.x == 0, red, &acc_s);
   const long long tot = nn + npq + nphi;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
     if (i < nn) {
@@ -357,13 +383,15 @@ __global__ void commit_kernel(const int* accept, const double2* Gp, const double
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) acc_count[z] += acc;
 }
-void launch_commit(const int* accept, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
+void launch_commit(const StepArgs& a, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
                    long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi, int nphi,
                    const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ, long long npq,
                    int* acc_count, hipStream_t s) {
+  StepArgs b = a;
+  b.nchain = nchain;
   const long long tot = nn + npq + nphi;
-  dim3 grid((unsigned)std::min<long long>((tot + 255) / 256, 512), nchain);
-  hipLaunchKernelGGL(commit_kernel, grid, dim3(256), 0, s, accept, Gp, G0, G, nn, sG, phip, sphip, phi_tau, sphi,
+  dim3 grid((unsigned)std::min<long long>((tot + DR_NT - 1) / DR_NT, 64), nchain);
+  hipLaunchKernelGGL(commit_kernel, grid, dim3(DR_NT), 0, s, b, Gp, G0, G, nn, sG, phip, sphip, phi_tau, sphi,
                      nphi, PQp, sPQp, PQ_tau, sPQ, npq, acc_count); cfqmc_post_launch("commit_kernel");
 }
 

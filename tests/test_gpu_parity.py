@@ -155,6 +155,27 @@ def test_exponential_scaling_and_squaring_path():
     g.close()
 
 
+def test_exponential_mixed_squaring_counts():
+    """Slices whose fields are scaled from 0.1 to 8 need 0 up to several
+    squarings inside the same batched exponential launch (each matrix leaves
+    the squaring chain at its own step); G and ln w at every slice boundary
+    match the oracle's exact exponentials."""
+    CFQMC = _gpu()
+    n_phi, L, u = 5, 8, 3.0
+    m = Model(n_phi, L, 0.2, u0=1.0, uk=u, un=u)
+    scales = np.array([0.1, 8.0, 1.0, 3.0, 0.5, 6.0, 2.0, 0.2])
+    phi = synth.fields(21, L, m.n_q) * scales[:, None, None]
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.2, u0=1.0, uk=u, un=u, n_stab=4, exp_squarings=6, tile_cfg=1)
+    g.init_fields(phi[None])
+    Bs = dqmc.propagators(m, phi)
+    for tau in range(L + 1):
+        G = g.measure_G(0, tau)[:2 * n_phi, :2 * n_phi]
+        assert rel(G, dqmc.green(m, phi, tau, Bs)) < 1e-10, tau
+    ld, ldr = g.logdet(0), dqmc.logdet(m, phi, Bs)
+    assert abs(ld.real - ldr.real) < 1e-10 * abs(ldr.real)
+    g.close()
+
+
 def test_device_rng_sweep_invariants():
     """Without replay (device Philox noise): sign-free phase, particle-hole
     symmetry, finite stabilisation error, acceptance in (0, 1)."""
