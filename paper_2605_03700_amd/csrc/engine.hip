@@ -218,6 +218,7 @@ struct cfqmc_ctx {
   double2* Cb;
   Udt Ls, Rs;
   double2 *W1, *A1, *Gr, *Q1, *Q2, *R1, *R2, *Rt, *Tp, *K1, *M1, *Yl, *Wm, *X1, *Gs;
+  double2* rs_ws;   // inverted diagonal blocks for the right solves
   double *nrm, *sqd1, *sqd2, *dinvL, *dinvR, *tmpd;
   int* perm;
   // scalars per chain
@@ -410,12 +411,12 @@ void udt_acc(cfqmc_ctx* c, const double2* C, long long sC, int opC, const double
   gemm_nn(c, c->A1, 1, nn, c->A1, 0, nn, c->Gr, nn, B);
   launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
   launch_chol_from_lu(c->Gr, n, nn, c->R1, c->sqd1, B, c->s);
-  launch_rsolve(c->A1, n, nn, c->Q1, n, nn, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s);
+  launch_rsolve(c->A1, n, nn, c->Q1, n, nn, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s, c->rs_ws);
   launch_colscale(c->Q1, n, nn, c->Q1, n, nn, c->sqd1, n, n, n, 0, B, c->s);
   gemm_nn(c, c->Q1, 1, nn, c->Q1, 0, nn, c->Gr, nn, B);
   launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
   launch_chol_from_lu(c->Gr, n, nn, c->R2, c->sqd2, B, c->s);
-  launch_rsolve(c->Q1, n, nn, Uo, n, sU, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s);
+  launch_rsolve(c->Q1, n, nn, Uo, n, sU, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s, c->rs_ws);
   launch_colscale(Uo, n, sU, Uo, n, sU, c->sqd2, n, n, n, 0, B, c->s);
   gemm_nn(c, c->R2, 0, nn, c->R1, 0, nn, c->Rt, nn, B);
   launch_udt_finish(c->Rt, n, nn, c->nrm, c->perm, Do, sD, c->Tp, B, c->s);
@@ -435,7 +436,7 @@ void green_udt(cfqmc_ctx* c, int bl, int br, double2* Gout) {
   launch_dmax_inv(DR, sD, c->dinvR, n, B, c->s);
   launch_dmax_inv(DL, sD, c->dinvL, n, B, c->s);
   launch_colscale(UR, n, sU, c->Wm, n, nn, c->dinvR, n, n, n, 0, B, c->s);
-  launch_rsolve(c->Wm, n, nn, c->X1, n, nn, c->Yl, n, nn, c->ipiv, n, n, 0, B, c->s);
+  launch_rsolve(c->Wm, n, nn, c->X1, n, nn, c->Yl, n, nn, c->ipiv, n, n, 0, B, c->s, c->rs_ws);
   launch_colscale(c->X1, n, nn, c->X1, n, nn, c->dinvL, n, n, n, 0, B, c->s);
   gemm_nn(c, c->X1, 0, nn, UL, 1, sU, Gout, nn, B);
 }
@@ -571,7 +572,8 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   launch_lu_np(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, c->lu_flag, 8.0, c->nch, c->s);
   launch_lu(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, 1, c->nch, c->s, c->lu_flag, c->Mb);
   // 6. G' = G_0 M^{-1}
-  launch_rsolve(c->F[0], c->n, nn, c->Fp[0], c->n, nn, c->Mw, c->n, nn, c->ipiv, c->n, c->n, 0, c->nch, c->s);
+  launch_rsolve(c->F[0], c->n, nn, c->Fp[0], c->n, nn, c->Mw, c->n, nn, c->ipiv, c->n, c->n, 0, c->nch, c->s,
+                c->rs_ws);
   // 7. frames of G' for the drift at phi'
   for (int ch = 0; ch < 3; ++ch) {
     chan(c, 1, ch, true, c->PQp + ch * 2 * NN, sPQp, c->Fp[ch], c->S1, false, nullptr, mixed);
@@ -800,6 +802,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->Rs.D, (size_t)B * (nb + 1) * n);
   double2** sbufs[] = {&c->W1, &c->A1, &c->Gr, &c->Q1, &c->Q2, &c->R1, &c->R2, &c->Rt, &c->Tp, &c->K1, &c->M1, &c->Yl, &c->Wm, &c->X1, &c->Gs};
   for (auto bp : sbufs) rc |= dalloc(c, bp, (size_t)B * nn);
+  rc |= dalloc(c, &c->rs_ws, (size_t)B * rsolve_work_size(n));
   double** dbufs[] = {&c->nrm, &c->sqd1, &c->sqd2, &c->dinvL, &c->dinvR, &c->tmpd};
   for (auto bp : dbufs) rc |= dalloc(c, bp, (size_t)B * n);
   rc |= dalloc(c, &c->perm, (size_t)B * n);

@@ -336,19 +336,22 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   const long long bstep = LEFT ? (long long)c.ldM : (long long)c.ldX;
 
   double2 ra[EA][2], rb[EB][2];
-  // bare loads (out-of-range elements read the tile origin and are zeroed when staged)
+  // bare loads; an out-of-range element reads k = 0 of its own row (A) or
+  // column (B), which is inside the operand (the base pointers already carry
+  // the thread's offset within the slab, which can exceed N when N < BKC), and
+  // is zeroed when staged
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const bool ok = arow[e] && k0 + ak[e] < N;
-      const long long o = ok ? k0 : 0;
+      const long long o = ok ? k0 : -ak[e];
       ra[e][0] = pa0[e][o];
       ra[e][1] = pa1[e][o];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const bool ok = bcol[e] && k0 + bk[e] < N;
-      const long long o = ok ? (long long)k0 * bstep : 0;
+      const long long o = (long long)(ok ? k0 : -bk[e]) * bstep;
       rb[e][0] = pb0[e][o];
       rb[e][1] = pb1[e][o];
     }

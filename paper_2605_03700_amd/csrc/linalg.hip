@@ -718,6 +718,15 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
 }
 
 static bool set_lds_limit(const void* fn, size_t shm);
+// right-solve kernel: 1 right-looking (default), 0 left-looking (CFQMC_RSOLVE=0)
+static int rsolve_variant() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("CFQMC_RSOLVE");
+    v = (e && e[0] == '0') ? 0 : 1;
+  }
+  return v;
+}
 
 void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int* flag,
                   double lmax_allowed, int nbatch, hipStream_t s) {
@@ -862,6 +871,179 @@ __global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int 
 }
 
 // Fallback when the large-LDS configuration is refused: one column at a time.
+// Inverses of the 16 x 16 diagonal blocks of U and of the unit-lower L of a
+// factorisation from launch_lu / launch_lu_np (rows addressed through ipiv):
+// Ui_J = U_JJ^{-1}, Li_J = L_JJ^{-1}, padded with the identity past n. Row r of
+// an inverse solves z T = e_r, by the same substitution as the blocked solve.
+// inv layout: [batch][nJ][2][16][16] (U then L).
+__global__ void __launch_bounds__(256) tri_inv_kernel(const double2* LUall, int ldlu, long long sLU,
+                                                      const int* ipiv_all, int sP, int n, int upper_only,
+                                                      double2* inv_all) {
+  __shared__ double2 Db[16][17];
+  __shared__ double2 Dr[16];
+  const int J = blockIdx.x, z = blockIdx.y, nJ = gridDim.x;
+  const double2* LU = LUall + z * sLU;
+  const int* ipiv = ipiv_all + z * sP;
+  double2* inv = inv_all + ((long long)z * nJ + J) * 512;
+  const int tid = threadIdx.x, lane = tid & 63, rr = tid >> 4, cc = tid & 15;
+  const int c0 = 16 * J, bw = min(16, n - c0);
+  const bool okd = rr < bw && cc < bw;
+  const double2 dd = okd ? LU[(long long)(upper_only ? c0 + rr : ipiv[c0 + rr]) * ldlu + c0 + cc]
+                         : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+  Db[rr][cc] = dd;
+  if (rr == cc) Dr[cc] = crcp(dd);
+  __syncthreads();
+  double2 y = make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+  for (int cp = 0; cp < 16; ++cp) {
+    double2 zv = cmul(y, Dr[cp]);
+    zv.x = __shfl(zv.x, (lane & ~15) + cp, 64);
+    zv.y = __shfl(zv.y, (lane & ~15) + cp, 64);
+    if (cc == cp) y = zv;
+    else if (cc > cp) y = csub(y, cmul(zv, Db[cp][cc]));
+  }
+  inv[rr * 16 + cc] = y;
+  if (upper_only) return;
+  y = make_double2(rr == cc ? 1.0 : 0.0, 0.0);
+  for (int cp = 15; cp >= 0; --cp) {
+    double2 wv;
+    wv.x = __shfl(y.x, (lane & ~15) + cp, 64);
+    wv.y = __shfl(y.y, (lane & ~15) + cp, 64);
+    if (cc < cp) y = csub(y, cmul(wv, Db[cp][cc]));
+  }
+  inv[256 + rr * 16 + cc] = y;
+}
+
+// Right-looking form of the same solve with the inverted diagonal blocks. The
+// 16-row block of the right-hand side lives in MFMA accumulators: column tile t
+// belongs to wave t % 4. At step J the owner wave multiplies its tile by the
+// inverse diagonal block (one 16 x 16 x 16 product instead of a 16-step
+// substitution) and publishes the solved block in LDS; after one barrier every
+// wave subtracts it times row block J of U (phase 0) or L (phase 1) from the
+// tiles it owns that are not solved yet. The published block is double-buffered.
+#define RL_NT 256
+template <int MAXT>
+__global__ void __launch_bounds__(RL_NT) rsolve_rl_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
+                                                          int ldy, long long sY, const double2* LUall, int ldlu,
+                                                          long long sLU, const int* ipiv_all, int sP, int n,
+                                                          int upper_only, const double2* inv_all, int nbatch) {
+  __shared__ double2 Tb[2][16][17];        // solved block of the step
+  __shared__ double2 Tw[4][16][17];        // per-wave layout change of the owner's tile
+  __shared__ int perm[LU_MAXN];
+  const int nrb = (n + RS_ROWS - 1) / RS_ROWS, T = nrb * nbatch, per = (T + 7) / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= T) return;
+  const int z = t / nrb;
+  const int nJ = (n + 15) / 16;
+  const double2* X = Xall + z * sX;
+  double2* Yo = Yall + z * sY;
+  const double2* LU = LUall + z * sLU;
+  const int* ipiv = ipiv_all + z * sP;
+  const double2* inv = inv_all + (long long)z * nJ * 512;
+  const int r0 = (t % nrb) * RS_ROWS;
+  const int nr = min(RS_ROWS, n - r0);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int il = lane & 15, kl = lane >> 4;
+  for (int i = tid; i < n; i += RL_NT) perm[i] = upper_only ? i : ipiv[i];
+  const double2 zero2 = make_double2(0.0, 0.0);
+  d4v are[MAXT], aim[MAXT];
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) {
+    const int tc = wid + 4 * i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = Mfma<double>::row(lane, q), c = 16 * tc + il;
+      const bool ok = tc < nJ && r < nr && c < n;
+      const double2 v = X[ok ? (long long)(r0 + r) * ldx + c : 0];
+      are[i][q] = ok ? v.x : 0.0;
+      aim[i][q] = ok ? v.y : 0.0;
+    }
+  }
+  __syncthreads();
+  const int last_phase = upper_only ? 0 : 1;
+  int step = 0;
+  for (int phase = 0; phase <= last_phase; ++phase) {
+    for (int jj = 0; jj < nJ; ++jj, ++step) {
+      const int J = phase == 0 ? jj : nJ - 1 - jj;
+      const int c0 = 16 * J, bw = min(16, n - c0), buf = step & 1;
+      const bool owner = (J & 3) == wid;
+      // loads of this step: row block J for the tiles still to update, and
+      // (owner) the inverse diagonal block
+      double2 bb[MAXT][4];
+#pragma unroll
+      for (int i = 0; i < MAXT; ++i) {
+        const int tc = wid + 4 * i;
+        const bool upd = phase == 0 ? (tc > J && tc < nJ) : (tc < J);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + kl, c = 16 * tc + il;
+          const bool ok = upd && k < bw && c < n;
+          bb[i][s4] = LU[ok ? (long long)perm[c0 + k] * ldlu + c : 0];
+          if (!ok) bb[i][s4] = zero2;
+        }
+      }
+      if (owner) {
+        const double2* ib = inv + (long long)J * 512 + phase * 256;
+        double2 bi[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) bi[s4] = ib[(4 * s4 + kl) * 16 + il];
+        // the owner's tile J: accumulator layout -> A-operand layout through LDS
+        const int io = J >> 2;
+#pragma unroll
+        for (int i = 0; i < MAXT; ++i)
+          if (i == io)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Tw[wid][Mfma<double>::row(lane, q)][il] = make_double2(are[i][q], aim[i][q]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        d4v zr = Mfma<double>::zero(), zi = Mfma<double>::zero();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double2 a = Tw[wid][il][4 * s4 + kl], b = bi[s4];
+          zr = Mfma<double>::mma(a.x, b.x, zr);
+          zr = Mfma<double>::mma(-a.y, b.y, zr);
+          zi = Mfma<double>::mma(a.x, b.y, zi);
+          zi = Mfma<double>::mma(a.y, b.x, zi);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = Mfma<double>::row(lane, q);
+          const double2 v = make_double2(zr[q], zi[q]);
+          Tb[buf][r][il] = v;
+          // the last phase's solved block is final: columns perm[c0 + il] of the output
+          if (phase == last_phase && r < nr && il < bw) Yo[(long long)(r0 + r) * ldy + perm[c0 + il]] = v;
+        }
+        // tile J after phase 0 is the input of phase 1
+        if (phase == 0) {
+#pragma unroll
+          for (int i = 0; i < MAXT; ++i)
+            if (i == io) { are[i] = zr; aim[i] = zi; }
+        }
+      }
+      __syncthreads();
+      // A operand: the solved block (m = il, k = 4 s4 + kl)
+      double2 av[4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) av[s4] = Tb[buf][il][4 * s4 + kl];
+#pragma unroll
+      for (int i = 0; i < MAXT; ++i) {
+        const int tc = wid + 4 * i;
+        const bool upd = phase == 0 ? (tc > J && tc < nJ) : (tc < J);
+        if (upd) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const double2 a = av[s4], b = bb[i][s4];
+            are[i] = Mfma<double>::mma(-a.x, b.x, are[i]);
+            are[i] = Mfma<double>::mma(a.y, b.y, are[i]);
+            aim[i] = Mfma<double>::mma(-a.x, b.y, aim[i]);
+            aim[i] = Mfma<double>::mma(-a.y, b.x, aim[i]);
+          }
+        }
+      }
+    }
+  }
+}
+
 #define RSS_ROWS 8
 #define RSS_NT 256
 
@@ -913,7 +1095,7 @@ __global__ void __launch_bounds__(RSS_NT) rsolve_simple_kernel(const double2* Xa
 
 void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY, const double2* LU,
                    int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only, int nbatch,
-                   hipStream_t s) {
+                   hipStream_t s, double2* work) {
   dim3 grid((n + RS_ROWS - 1) / RS_ROWS, nbatch);
   const size_t shm = (size_t)RS_ROWS * (n | 1) * sizeof(double2);
   if (!set_lds_limit((const void*)rsolve_kernel, shm)) {
@@ -923,6 +1105,19 @@ void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy,
     return;
   }
   const int nblk = (int)(((long long)grid.x * nbatch + 7) / 8 * 8);
+  if (work && rsolve_variant() == 1) {
+    const int nJ = (n + 15) / 16;
+    hipLaunchKernelGGL(tri_inv_kernel, dim3(nJ, nbatch), dim3(256), 0, s, LU, ldlu, sLU, ipiv, sP, n, upper_only,
+                       work); cfqmc_post_launch("tri_inv_kernel");
+    if (n <= 256)
+      hipLaunchKernelGGL(rsolve_rl_kernel<4>, dim3(nblk), dim3(RL_NT), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
+                         ipiv, sP, n, upper_only, (const double2*)work, nbatch);
+    else
+      hipLaunchKernelGGL(rsolve_rl_kernel<5>, dim3(nblk), dim3(RL_NT), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
+                         ipiv, sP, n, upper_only, (const double2*)work, nbatch);
+    cfqmc_post_launch("rsolve_rl_kernel");
+    return;
+  }
   hipLaunchKernelGGL(rsolve_kernel, dim3(nblk), dim3(RS_NT), shm, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP,
                      n, upper_only, nbatch); cfqmc_post_launch("rsolve_kernel");
 }

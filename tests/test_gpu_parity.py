@@ -108,6 +108,13 @@ def test_sweep_replay_parity_fp64_small():
     assert st[0]["max_stab_err"] < 1e-9 and st[0]["max_stab_rel"] <= st[0]["max_stab_err"] / 0.1
 
 
+def test_sweep_replay_parity_large_spin_block():
+    """N_phi = 130: spin block n = 260 > 256 (five column tiles per wave in the
+    right solve) with a ragged last 16-column block; FP64 replay parity."""
+    CFQMC = _gpu()
+    _replay_compare(CFQMC, 130, 3, 2, Q_RADIUS, 1.0, [1.0], 0, 1, 1e-10)
+
+
 def test_sweep_replay_parity_batched_u_grid():
     """Five chains of one shape at u = 0.5..2.5 in one context (one launch per step)."""
     CFQMC = _gpu()
