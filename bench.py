@@ -1,6 +1,6 @@
 """Benchmark of the CF-DQMC sweep on one MI355X.
 
-Workload (default): 64 independent chains of the torus N_phi = 100 model
+Workload (default): 256 independent chains of the torus N_phi = 100 model
 (spin block n = 200, 4N = 400), paper momentum cutoff (933 HS components per
 channel), L = 400 slices of dtau = 0.1, u = 1.5 on the SO(5) line, FP64
 recomputation every 8 slices, complex FP32 MFMA wraps with FP64 accumulation
@@ -90,7 +90,8 @@ def main():
     ap.add_argument("--dtau", type=float, default=0.1)
     ap.add_argument("--u", type=float, default=1.5)
     ap.add_argument("--n-stab", type=int, default=8)
-    ap.add_argument("--chains", type=int, default=64)
+    ap.add_argument("--chains", type=int, default=256,
+                    help="independent chains in one context; 256 N_phi = 100 chains take about 190 GB of HBM")
     ap.add_argument("--groups", type=int, default=1, help="split the chains over this many streams")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
     ap.add_argument("--workload", choices=["c3", "batched"], default="c3",
