@@ -22,11 +22,12 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
 
-# HBM bytes per launch of the timed channel application, (FETCH_SIZE + WRITE_SIZE)
-# from rocprofv3 PMC runs of this command scaled by the copy-kernel factor
-# (profiles/chan_apply_traffic_c3.txt); keyed by (N_phi, chains per context,
-# precision, tile configuration). Absent key: traffic not measured for that case.
-TRAFFIC = {}
+# HBM bytes per launch of the timed channel application, FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (KiB, factors from a 1 GiB copy) from rocprofv3 PMC runs of
+# this script (profiles/chan_apply_traffic_n100_256chains.md); keyed by
+# (N_phi, chains per context, precision, tile configuration). Absent key, or a
+# kernel changed since the counters were taken: traffic not measured (null).
+TRAFFIC = {(100, 256, "mixed", 1): (167489.07 * 2.0 + 160000.0 * 1.0) * 1024}
 
 
 def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
@@ -177,7 +178,8 @@ def main():
         out["roofline"] = {"bound": "mfma", "kernel": "chan_apply", "achieved": ach,
                            "peak": PEAK[args.precision], "unit": "TFLOP/s", "frac": ach / PEAK[args.precision],
                            "traffic": traffic, "avg_launch_ms": k_ms, "launches_timed": k_count,
-                           "flops_per_launch": k_flops}
+                           "flops_per_launch": k_flops,
+                           "hbm_gbps_at_traffic": traffic / (k_ms * 1e-3) / 1e9 if traffic else None}
     tau = None
     if args.tau_sweeps > 0:
         n0 = [len(q.series(0)) for q in b.groups]
