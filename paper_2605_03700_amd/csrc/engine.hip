@@ -240,7 +240,7 @@ struct cfqmc_ctx {
   double2* bg;
   double2* ldtmp;
   long long sweep_counter;
-  int cfg_chan, cfg_gemm, cfg_small;
+  int cfg_chan, cfg_chan64, cfg_gemm, cfg_small;   // cfg_chan64: FP64 applications in a mixed context
   // sampled HIP-event timing of the channel application (one launch per slice)
   bool timing;
   std::vector<hipEvent_t> ev;
@@ -323,7 +323,7 @@ void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, lon
     std::fprintf(stderr, "cfqmc: internal error: 1 - M requested for a rotating or right channel\n");
     std::abort();
   }
-  launch_chan_apply(a, left, rot, c->nch, mixed, c->cfg_chan, c->s);
+  launch_chan_apply(a, left, rot, c->nch, mixed, mixed ? c->cfg_chan : c->cfg_chan64, c->s);
 }
 
 // C = op(A) op(B) on n x n per chain (FP64)
@@ -341,10 +341,13 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
           long long sOut) {
   const int N = c->N;
   const long long NN = c->NN, s4 = 4 * NN;
+  // h is Hermitian, so are its powers and the even / odd polynomials in h^2
+  // (real coefficients): those products compute the upper tile triangle only
   auto sq = [&](const double2* A, const double2* B, double2* D) {
     GemmArgs g = gemm0(N, N, N);
     g.A = mref(A, N, s4, NN); g.B = mref(B, N, s4, NN); g.D = mref(D, N, s4, NN);
     g.nz2 = 4;
+    g.herm = 1;
     launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
   };
   sq(hb, hb, c->H2);
@@ -358,6 +361,7 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
     g.D = mref(c->Eo, N, s4, NN);
     g.beta = make_double2(1.0, 0.0);
     g.nz2 = 4;
+    g.herm = 1;
     launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
     g.B = mref(c->hiO, N, s4, NN); g.C = mref(c->loO, N, s4, NN); g.D = mref(c->Oo, N, s4, NN);
     launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
@@ -692,6 +696,20 @@ int autotune(cfqmc_ctx* c) {
     });
     if (tc < best_c) { best_c = tc; bc = cfg; }
   }
+  // a mixed context also runs FP64 applications (Woodbury product, block
+  // products): their tiles are tuned on their own
+  int bc64 = bc;
+  if (c->mixed) {
+    float best = 1e30f;
+    for (int cfg = 0; cfg < CFQMC_CHAN_CFGS; ++cfg) {
+      c->cfg_chan64 = cfg;
+      const float tc = timeit([&]() {
+        chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, 0);
+        chan(c, 1, 0, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, 0);
+      });
+      if (tc < best) { best = tc; bc64 = cfg; }
+    }
+  }
   for (int cfg = 0; cfg < CFQMC_GEMM_CFGS; ++cfg) {
     c->cfg_gemm = cfg;
     const float tg = timeit([&]() { gemm_nn(c, c->F[0], 0, c->nn, c->F[1], 0, c->nn, c->S1, c->nn, c->nch); });
@@ -705,6 +723,7 @@ int autotune(cfqmc_ctx* c) {
     if (ts < best_s) { best_s = ts; bs = cfg; }
   }
   c->cfg_chan = bc;
+  c->cfg_chan64 = bc64;
   c->cfg_gemm = bg;
   c->cfg_small = bs;
   hipEventDestroy(e0);
@@ -840,6 +859,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
     return CFQMC_EHIP;
   }
   c->cfg_chan = p.tile_cfg >= 0 ? p.tile_cfg : 1;
+  c->cfg_chan64 = c->cfg_chan;
   c->cfg_gemm = p.tile_cfg >= 0 ? std::min(p.tile_cfg, CFQMC_GEMM_CFGS - 1) : 1;
   c->cfg_small = 0;
   if (hipStreamSynchronize(c->s) != hipSuccess) { cfqmc_destroy(c); return CFQMC_EHIP; }

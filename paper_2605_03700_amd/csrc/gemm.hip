@@ -18,6 +18,9 @@
 // FP64 before rounding; ||X_a - 1|| is the small channel exponent) and adds
 // the FP64 input back in the epilogue, E M = M + (E - 1) M, so the FP32
 // rounding only touches the increment.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -117,6 +120,13 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   __shared__ C2 Bs[BK * LDB];
   int z, ty, tx;
   if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  if (g.herm) {
+    // tiles_x counts the upper triangle (row-major) of a herm x herm tile grid
+    int r = tx, a = 0;
+    while (r >= g.herm - a) { r -= g.herm - a; ++a; }
+    ty = a;
+    tx = a + r;
+  }
   const int z1 = z / g.nz2, z2 = z % g.nz2;
   const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -226,6 +236,7 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
           double2 v = cmul(alpha, p);
           if (Cm) v = cadd(v, cmul(g.beta, Cm[(long long)i * g.C.ld + j]));
           D[(long long)i * ldd + j] = v;
+          if (g.herm && ty < tx) D[(long long)j * ldd + i] = make_double2(v.x, -v.y);
         }
       }
 }
@@ -482,9 +493,19 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
 // ------------------------------------------------------------------ launchers
 
 template <typename CT, int BM, int BN, int WTM, int WTN>
-static void run_gemm(const GemmArgs& g, int nbatch, hipStream_t s) {
+static void run_gemm(const GemmArgs& g0, int nbatch, hipStream_t s) {
   constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
-  const int tx = (g.N + BN - 1) / BN, ty = (g.M + BM - 1) / BM;
+  GemmArgs g = g0;
+  int tx = (g.N + BN - 1) / BN, ty = (g.M + BM - 1) / BM;
+  if (g.herm) {
+    if (BM != BN || g.M != g.N || g.mode != GEMM_NORMAL) {
+      std::fprintf(stderr, "zgemm: Hermitian output needs square tiles and a square GEMM_NORMAL product\n");
+      std::abort();
+    }
+    g.herm = tx;
+    tx = tx * (tx + 1) / 2;
+    ty = 1;
+  }
   const long long T = (long long)tx * ty * nbatch;
   const int nblk = (int)((T + 7) / 8 * 8);
   hipLaunchKernelGGL((zgemm_kernel<CT, BM, BN, WTM, WTN>), dim3(nblk), dim3(NT), 0, s, g, tx, ty, nbatch);

@@ -915,19 +915,22 @@ __global__ void __launch_bounds__(256) tri_inv_kernel(const double2* LUall, int 
 
 // Right-looking form of the same solve with the inverted diagonal blocks. The
 // 16-row block of the right-hand side lives in MFMA accumulators: column tile t
-// belongs to wave t % 4. At step J the owner wave multiplies its tile by the
+// belongs to wave t % NW. At step J the owner wave multiplies its tile by the
 // inverse diagonal block (one 16 x 16 x 16 product instead of a 16-step
 // substitution) and publishes the solved block in LDS; after one barrier every
 // wave subtracts it times row block J of U (phase 0) or L (phase 1) from the
-// tiles it owns that are not solved yet. The published block is double-buffered.
-#define RL_NT 256
-template <int MAXT>
-__global__ void __launch_bounds__(RL_NT) rsolve_rl_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
-                                                          int ldy, long long sY, const double2* LUall, int ldlu,
-                                                          long long sLU, const int* ipiv_all, int sP, int n,
-                                                          int upper_only, const double2* inv_all, int nbatch) {
+// tiles it owns that are not solved yet. The published block is double-buffered;
+// the owner's layout change goes through one LDS tile (one owner per step, and
+// the barrier separates consecutive owners).
+template <int NW, int MAXT>
+__global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall, int ldx, long long sX,
+                                                            double2* Yall, int ldy, long long sY,
+                                                            const double2* LUall, int ldlu, long long sLU,
+                                                            const int* ipiv_all, int sP, int n, int upper_only,
+                                                            const double2* inv_all, int nbatch) {
+  constexpr int NT = NW * 64;
   __shared__ double2 Tb[2][16][17];        // solved block of the step
-  __shared__ double2 Tw[4][16][17];        // per-wave layout change of the owner's tile
+  __shared__ double2 Tw[16][17];           // owner's layout change
   __shared__ int perm[LU_MAXN];
   const int nrb = (n + RS_ROWS - 1) / RS_ROWS, T = nrb * nbatch, per = (T + 7) / 8;
   const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -943,12 +946,12 @@ __global__ void __launch_bounds__(RL_NT) rsolve_rl_kernel(const double2* Xall, i
   const int nr = min(RS_ROWS, n - r0);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int il = lane & 15, kl = lane >> 4;
-  for (int i = tid; i < n; i += RL_NT) perm[i] = upper_only ? i : ipiv[i];
+  for (int i = tid; i < n; i += NT) perm[i] = upper_only ? i : ipiv[i];
   const double2 zero2 = make_double2(0.0, 0.0);
   d4v are[MAXT], aim[MAXT];
 #pragma unroll
   for (int i = 0; i < MAXT; ++i) {
-    const int tc = wid + 4 * i;
+    const int tc = wid + NW * i;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = Mfma<double>::row(lane, q), c = 16 * tc + il;
@@ -965,13 +968,13 @@ __global__ void __launch_bounds__(RL_NT) rsolve_rl_kernel(const double2* Xall, i
     for (int jj = 0; jj < nJ; ++jj, ++step) {
       const int J = phase == 0 ? jj : nJ - 1 - jj;
       const int c0 = 16 * J, bw = min(16, n - c0), buf = step & 1;
-      const bool owner = (J & 3) == wid;
+      const bool owner = (J % NW) == wid;
       // loads of this step: row block J for the tiles still to update, and
       // (owner) the inverse diagonal block
       double2 bb[MAXT][4];
 #pragma unroll
       for (int i = 0; i < MAXT; ++i) {
-        const int tc = wid + 4 * i;
+        const int tc = wid + NW * i;
         const bool upd = phase == 0 ? (tc > J && tc < nJ) : (tc < J);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
@@ -987,19 +990,19 @@ __global__ void __launch_bounds__(RL_NT) rsolve_rl_kernel(const double2* Xall, i
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) bi[s4] = ib[(4 * s4 + kl) * 16 + il];
         // the owner's tile J: accumulator layout -> A-operand layout through LDS
-        const int io = J >> 2;
+        const int io = J / NW;
 #pragma unroll
         for (int i = 0; i < MAXT; ++i)
           if (i == io)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Tw[wid][Mfma<double>::row(lane, q)][il] = make_double2(are[i][q], aim[i][q]);
+            for (int q = 0; q < 4; ++q) Tw[Mfma<double>::row(lane, q)][il] = make_double2(are[i][q], aim[i][q]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         d4v zr = Mfma<double>::zero(), zi = Mfma<double>::zero();
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
-          const double2 a = Tw[wid][il][4 * s4 + kl], b = bi[s4];
+          const double2 a = Tw[il][4 * s4 + kl], b = bi[s4];
           zr = Mfma<double>::mma(a.x, b.x, zr);
           zr = Mfma<double>::mma(-a.y, b.y, zr);
           zi = Mfma<double>::mma(a.x, b.y, zi);
@@ -1027,7 +1030,7 @@ __global__ void __launch_bounds__(RL_NT) rsolve_rl_kernel(const double2* Xall, i
       for (int s4 = 0; s4 < 4; ++s4) av[s4] = Tb[buf][il][4 * s4 + kl];
 #pragma unroll
       for (int i = 0; i < MAXT; ++i) {
-        const int tc = wid + 4 * i;
+        const int tc = wid + NW * i;
         const bool upd = phase == 0 ? (tc > J && tc < nJ) : (tc < J);
         if (upd) {
 #pragma unroll
@@ -1109,11 +1112,12 @@ void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy,
     const int nJ = (n + 15) / 16;
     hipLaunchKernelGGL(tri_inv_kernel, dim3(nJ, nbatch), dim3(256), 0, s, LU, ldlu, sLU, ipiv, sP, n, upper_only,
                        work); cfqmc_post_launch("tri_inv_kernel");
+    // eight waves, each owning at most ceil(nJ / 8) column tiles (2 for n <= 256)
     if (n <= 256)
-      hipLaunchKernelGGL(rsolve_rl_kernel<4>, dim3(nblk), dim3(RL_NT), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
+      hipLaunchKernelGGL((rsolve_rl_kernel<8, 2>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
                          ipiv, sP, n, upper_only, (const double2*)work, nbatch);
     else
-      hipLaunchKernelGGL(rsolve_rl_kernel<5>, dim3(nblk), dim3(RL_NT), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
+      hipLaunchKernelGGL((rsolve_rl_kernel<8, 3>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
                          ipiv, sP, n, upper_only, (const double2*)work, nbatch);
     cfqmc_post_launch("rsolve_rl_kernel");
     return;
