@@ -25,7 +25,6 @@
 #include "../../include/cfqmc.h"
 #include "kernels.h"
 
-#define EXP_NC 16
 
 namespace {
 
@@ -210,7 +209,7 @@ struct cfqmc_ctx {
   double2* h;
   // exp work
   int exp_cap;        // capacity in (entry) units of 4 channels
-  double2 *H2, *X2, *X3, *loE, *hiE, *loO, *hiO, *Eo, *Oo, *Wa, *Wb;
+  double2 *H2, *X2, *X3, *Eo, *Oo, *Wa, *Wb;
   double* coef;
   int* sq;
   int* d_err;
@@ -354,18 +353,7 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
   sq(c->H2, c->H2, c->X2);
   sq(c->X2, c->H2, c->X3);
   launch_exp_coef(c->X2, c->X3, N, alpha, alpha_div, c->coef, c->sq, c->smax, 0.4, c->d_err, nent * 4, c->s);
-  launch_exp_poly(c->H2, c->X2, c->X3, c->coef, N, c->loE, c->hiE, c->loO, c->hiO, nent * 4, c->s);
-  {
-    GemmArgs g = gemm0(N, N, N);
-    g.A = mref(c->X3, N, s4, NN); g.B = mref(c->hiE, N, s4, NN); g.C = mref(c->loE, N, s4, NN);
-    g.D = mref(c->Eo, N, s4, NN);
-    g.beta = make_double2(1.0, 0.0);
-    g.nz2 = 4;
-    g.herm = 1;
-    launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
-    g.B = mref(c->hiO, N, s4, NN); g.C = mref(c->loO, N, s4, NN); g.D = mref(c->Oo, N, s4, NN);
-    launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
-  }
+  launch_exp_eo(c->H2, c->X2, c->X3, c->coef, N, c->Eo, c->Oo, nent * 4, c->s);
   {
     // P, Q = E +- alpha h O; matrices with squaring count 0 go straight to out
     GemmArgs g = gemm0(N, N, N);
@@ -805,7 +793,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->phip, (size_t)B * 4 * nq);
   rc |= dalloc(c, &c->PQp, (size_t)B * 8 * NN);
   rc |= dalloc(c, &c->h, (size_t)ecap);
-  double2** ebufs[] = {&c->H2, &c->X2, &c->X3, &c->loE, &c->hiE, &c->loO, &c->hiO, &c->Eo, &c->Oo};
+  double2** ebufs[] = {&c->H2, &c->X2, &c->X3, &c->Eo, &c->Oo};
   for (auto bp : ebufs) rc |= dalloc(c, bp, (size_t)ecap);
   rc |= dalloc(c, &c->Wa, (size_t)2 * ecap);
   rc |= dalloc(c, &c->Wb, (size_t)2 * ecap);

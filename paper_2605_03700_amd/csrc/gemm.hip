@@ -72,6 +72,68 @@ CF_DEV void mma_slab(const typename cplx_t<CT>::type* As, int lda, const typenam
   }
 }
 
+// FP64 complex products with three real MFMAs per k step (Gauss): with
+// a = ar + i ai, b = br + i bi the sums P = sum ar br, Q = sum ai bi and
+// S = sum (ar + ai)(br + bi) give re = P - Q, im = S - P - Q. The operand sums
+// are two VALU adds per k step; the MFMA work drops by a quarter. Used for the
+// FP64 products only (the FP32 path keeps four products: its rounding budget
+// is set by the correction form).
+template <int WTM, int WTN>
+struct Acc3 {
+  d4v p[WTM][WTN], q[WTM][WTN], t[WTM][WTN];
+  CF_DEV void zero() {
+#pragma unroll
+    for (int a = 0; a < WTM; ++a)
+#pragma unroll
+      for (int b = 0; b < WTN; ++b) { p[a][b] = Mfma<double>::zero(); q[a][b] = p[a][b]; t[a][b] = p[a][b]; }
+  }
+  CF_DEV void to(Acc<double, WTM, WTN>& o) const {
+#pragma unroll
+    for (int a = 0; a < WTM; ++a)
+#pragma unroll
+      for (int b = 0; b < WTN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          o.re[a][b][r] = p[a][b][r] - q[a][b][r];
+          o.im[a][b][r] = t[a][b][r] - p[a][b][r] - q[a][b][r];
+        }
+  }
+};
+
+template <int WTM, int WTN, int KD = BK>
+CF_DEV void mma_slab3(const double2* As, int lda, const double2* Bs, int ldb, int wm0, int wn0, int lane,
+                      Acc3<WTM, WTN>& acc, int mrem = 1 << 30, int nrem = 1 << 30, int krem = 1 << 30) {
+  const int il = lane & 15, kl = lane >> 4;
+  mrem = __builtin_amdgcn_readfirstlane(mrem);
+  nrem = __builtin_amdgcn_readfirstlane(nrem);
+  krem = __builtin_amdgcn_readfirstlane(krem);
+#pragma unroll
+  for (int kk = 0; kk < KD; kk += 4) {
+    if (kk >= krem) break;
+    double2 a[WTM], b[WTN];
+    double sa[WTM], sb[WTN];
+#pragma unroll
+    for (int s = 0; s < WTM; ++s) {
+      a[s] = As[(kk + kl) * lda + wm0 + s * 16 + il];
+      sa[s] = a[s].x + a[s].y;
+    }
+#pragma unroll
+    for (int s = 0; s < WTN; ++s) {
+      b[s] = Bs[(kk + kl) * ldb + wn0 + s * 16 + il];
+      sb[s] = b[s].x + b[s].y;
+    }
+#pragma unroll
+    for (int si = 0; si < WTM; ++si)
+#pragma unroll
+      for (int sj = 0; sj < WTN; ++sj) {
+        if (si * 16 >= mrem || sj * 16 >= nrem) continue;
+        acc.p[si][sj] = Mfma<double>::mma(a[si].x, b[sj].x, acc.p[si][sj]);
+        acc.q[si][sj] = Mfma<double>::mma(a[si].y, b[sj].y, acc.q[si][sj]);
+        acc.t[si][sj] = Mfma<double>::mma(sa[si], sb[sj], acc.t[si][sj]);
+      }
+  }
+}
+
 // FP64 accumulation point: add an FP32 slab accumulator into FP64 registers.
 template <int WTM, int WTN>
 CF_DEV void flush(Acc<float, WTM, WTN>& a32, Acc<double, WTM, WTN>& a64) {
@@ -189,6 +251,8 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   };
   Acc<double, WTM, WTN> acc;
   acc.zero();
+  Acc3<WTM, WTN> acc3;
+  acc3.zero();
   {
     fetch(0);
     for (int k0 = 0; k0 < g.K; k0 += BK) {
@@ -197,7 +261,7 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
       if (k0 + BK < g.K) fetch(k0 + BK);
       const int mr = g.M - m0 - wm0, nr = g.N - n0 - wn0, kr = g.K - k0;
       if constexpr (sizeof(CT) == 8) {
-        mma_slab<double, WTM, WTN>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc, mr, nr, kr);
+        mma_slab3<WTM, WTN>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc3, mr, nr, kr);
       } else {
         Acc<float, WTM, WTN> a32;
         a32.zero();
@@ -207,6 +271,7 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
       __syncthreads();
     }
   }
+  if constexpr (sizeof(CT) == 8) acc3.to(acc);
   double2 alpha = g.alpha;
   if (g.alpha_dev) alpha = cmul(alpha, g.alpha_dev[z1 * g.ad_s1 + z2 * g.ad_s2]);
   // with squaring counts: a matrix whose last step this is goes to its final place
@@ -239,6 +304,133 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
           if (g.herm && ty < tx) D[(long long)j * ldd + i] = make_double2(v.x, -v.y);
         }
       }
+}
+
+// ------------------------------------------------------------------ exp_eo
+// Even and odd Taylor parts of the exponential in one pass (x = h^2, X2 = x^2,
+// X3 = x^3, coefficients e_k = w^k/(2k)!, o_k = w^k/(2k+1)! per matrix):
+//   E = (e0 + e1 x + e2 X2) + X3 (e3 + e4 x + e5 X2 + e6 X3)
+//   O = (o0 + o1 x + o2 X2) + X3 (o3 + o4 x + o5 X2 + o6 X3)
+// X3 is the shared A operand; the two polynomial B operands are formed from
+// x, X2, X3 while staging, the low-order parts in the epilogue. Both results are
+// Hermitian (h Hermitian, real coefficients): only tiles on and above the
+// diagonal are computed, each strictly upper tile also writing its conjugate
+// transpose. FP64, three-MFMA complex products.
+template <int BT>
+__global__ void __launch_bounds__((BT / 16) * (BT / 16) * 64)
+exp_eo_kernel(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N, double2* Eo,
+              double2* Oo, int ntri, int tiles, int nbatch) {
+  constexpr int WX = BT / 16, NT = WX * WX * 64;
+  constexpr int LD = BT + 2;
+  __shared__ double2 As[BK * LD];
+  __shared__ double2 Be[BK * LD], Bo[BK * LD];
+  int z, ty, tx;
+  if (!xcd_tile(ntri, 1, nbatch, z, ty, tx)) return;
+  {
+    int r = tx, a = 0;
+    while (r >= tiles - a) { r -= tiles - a; ++a; }
+    ty = a;
+    tx = a + r;
+  }
+  const long long NN = (long long)N * N, off = z * NN;
+  const double* cf = coef + (long long)z * EXP_NC;
+  const double e3 = cf[3], e4 = cf[4], e5 = cf[5], e6 = cf[6];
+  const double o3 = cf[10], o4 = cf[11], o5 = cf[12], o6 = cf[13];
+  const int m0 = ty * BT, n0 = tx * BT;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm0 = (wid / WX) * 16, wn0 = (wid % WX) * 16;
+  constexpr int EA = BT * BK / NT;
+  static_assert(EA * NT == BT * BK, "tile / thread mismatch");
+  double2 ra[EA], rh[EA], rx[EA], ry[EA];
+  // bare loads from clamped offsets (out-of-range elements read element 0 of
+  // the matrix and are zeroed when staged)
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      {
+        const int k = idx % BK, m = idx / BK;   // A: X3 (m, k)
+        const bool ok = m0 + m < N && k0 + k < N;
+        ra[e] = X3[off + (ok ? (long long)(m0 + m) * N + k0 + k : 0)];
+      }
+      {
+        const int n = idx % BT, k = idx / BT;   // B sources (k, n)
+        const bool ok = n0 + n < N && k0 + k < N;
+        const long long o = off + (ok ? (long long)(k0 + k) * N + n0 + n : 0);
+        rh[e] = H2[o];
+        rx[e] = X2[o];
+        ry[e] = X3[o];
+      }
+    }
+  };
+  auto stage = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      {
+        const int k = idx % BK, m = idx / BK;
+        const bool ok = m0 + m < N && k0 + k < N;
+        As[k * LD + m] = make_double2(ok ? ra[e].x : 0.0, ok ? ra[e].y : 0.0);
+      }
+      {
+        const int n = idx % BT, k = idx / BT;
+        const bool ok = n0 + n < N && k0 + k < N;
+        const double d = (k0 + k == n0 + n) ? 1.0 : 0.0;
+        // the padding (whose loads read element 0) is zeroed component-wise
+        const double ber = e3 * d + e4 * rh[e].x + e5 * rx[e].x + e6 * ry[e].x;
+        const double bei = e4 * rh[e].y + e5 * rx[e].y + e6 * ry[e].y;
+        const double bor = o3 * d + o4 * rh[e].x + o5 * rx[e].x + o6 * ry[e].x;
+        const double boi = o4 * rh[e].y + o5 * rx[e].y + o6 * ry[e].y;
+        Be[k * LD + n] = make_double2(ok ? ber : 0.0, ok ? bei : 0.0);
+        Bo[k * LD + n] = make_double2(ok ? bor : 0.0, ok ? boi : 0.0);
+      }
+    }
+  };
+  Acc3<1, 1> ae, ao;
+  ae.zero();
+  ao.zero();
+  const int mr = N - m0 - wm0, nr = N - n0 - wn0;
+  fetch(0);
+  for (int k0 = 0; k0 < N; k0 += BK) {
+    stage(k0);
+    __syncthreads();
+    if (k0 + BK < N) fetch(k0 + BK);
+    mma_slab3<1, 1>(As, LD, Be, LD, wm0, wn0, lane, ae, mr, nr, N - k0);
+    mma_slab3<1, 1>(As, LD, Bo, LD, wm0, wn0, lane, ao, mr, nr, N - k0);
+    __syncthreads();
+  }
+  const double e0 = cf[0], e1 = cf[1], e2 = cf[2], o0 = cf[7], o1 = cf[8], o2 = cf[9];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double er = ae.p[0][0][r] - ae.q[0][0][r], ei = ae.t[0][0][r] - ae.p[0][0][r] - ae.q[0][0][r];
+    const double or_ = ao.p[0][0][r] - ao.q[0][0][r], oi = ao.t[0][0][r] - ao.p[0][0][r] - ao.q[0][0][r];
+    const int i = m0 + wm0 + Mfma<double>::row(lane, r);
+    const int j = n0 + wn0 + (lane & 15);
+    if (i >= N || j >= N) continue;
+    const long long o = off + (long long)i * N + j;
+    const double2 h = H2[o], x = X2[o];
+    const double d = (i == j) ? 1.0 : 0.0;
+    const double2 ve = make_double2(er + e0 * d + e1 * h.x + e2 * x.x, ei + e1 * h.y + e2 * x.y);
+    const double2 vo = make_double2(or_ + o0 * d + o1 * h.x + o2 * x.x, oi + o1 * h.y + o2 * x.y);
+    Eo[o] = ve;
+    Oo[o] = vo;
+    if (ty < tx) {
+      const long long ot = off + (long long)j * N + i;
+      Eo[ot] = make_double2(ve.x, -ve.y);
+      Oo[ot] = make_double2(vo.x, -vo.y);
+    }
+  }
+}
+
+void launch_exp_eo(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N, double2* Eo,
+                   double2* Oo, int nmat, hipStream_t s) {
+  constexpr int BT = 32;
+  const int tiles = (N + BT - 1) / BT, ntri = tiles * (tiles + 1) / 2;
+  const long long T = (long long)ntri * nmat;
+  const int nblk = (int)((T + 7) / 8 * 8);
+  hipLaunchKernelGGL((exp_eo_kernel<BT>), dim3(nblk), dim3((BT / 16) * (BT / 16) * 64), 0, s, H2, X2, X3, coef, N, Eo,
+                     Oo, ntri, tiles, nmat);
+  cfqmc_post_launch("exp_eo_kernel");
 }
 
 // ------------------------------------------------------------------ chan_apply
@@ -311,8 +503,11 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   static_assert(EA * NT == BM * BKC && EB * NT == BN * BKC, "tile / thread mismatch");
   // staging elements of this thread: A tile (m, k) with k fastest, B tile (k, n) with n fastest
   int am[EA], ak[EA], bn_[EB], bk[EB];
-  const double2 *pa0[EA], *pa1[EA], *pb0[EB], *pb1[EB];
+  const double2 *pa0[EA], *pb0[EB];
   bool arow[EA], bcol[EB];
+  // the second valley's operand is the first one's plus a uniform offset
+  const long long da = LEFT ? (long long)(X1 - X0) : (long long)N;
+  const long long db = LEFT ? (long long)N * c.ldM : (long long)(X1 - X0);
 #pragma unroll
   for (int e = 0; e < EA; ++e) {
     const int idx = tid + e * NT;
@@ -320,13 +515,7 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
     am[e] = idx / BKC;
     arow[e] = m0 + am[e] < rows;
     const int mr = arow[e] ? m0 + am[e] : 0;
-    if (LEFT) {
-      pa0[e] = X0 + (long long)mr * c.ldX + ak[e];
-      pa1[e] = X1 + (long long)mr * c.ldX + ak[e];
-    } else {
-      pa0[e] = M + (long long)mr * c.ldM + ak[e];
-      pa1[e] = pa0[e] + N;
-    }
+    pa0[e] = LEFT ? X0 + (long long)mr * c.ldX + ak[e] : M + (long long)mr * c.ldM + ak[e];
   }
 #pragma unroll
   for (int e = 0; e < EB; ++e) {
@@ -335,13 +524,7 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
     bk[e] = idx / BN;
     bcol[e] = n0 + bn_[e] < cols;
     const int nc = bcol[e] ? n0 + bn_[e] : 0;
-    if (LEFT) {
-      pb0[e] = M + (long long)bk[e] * c.ldM + nc;
-      pb1[e] = pb0[e] + (long long)N * c.ldM;
-    } else {
-      pb0[e] = X0 + (long long)bk[e] * c.ldX + nc;
-      pb1[e] = X1 + (long long)bk[e] * c.ldX + nc;
-    }
+    pb0[e] = LEFT ? M + (long long)bk[e] * c.ldM + nc : X0 + (long long)bk[e] * c.ldX + nc;
   }
   // k advances along a row of A and down a column of B
   const long long bstep = LEFT ? (long long)c.ldM : (long long)c.ldX;
@@ -357,14 +540,14 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       const bool ok = arow[e] && k0 + ak[e] < N;
       const long long o = ok ? k0 : -ak[e];
       ra[e][0] = pa0[e][o];
-      ra[e][1] = pa1[e][o];
+      ra[e][1] = pa0[e][o + da];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const bool ok = bcol[e] && k0 + bk[e] < N;
       const long long o = (long long)(ok ? k0 : -bk[e]) * bstep;
       rb[e][0] = pb0[e][o];
-      rb[e][1] = pb1[e][o];
+      rb[e][1] = pb0[e][o + db];
     }
   };
   const double2 zero2 = make_double2(0.0, 0.0);
@@ -423,13 +606,16 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   Acc<double, WTM, WTN> acc[2];
   acc[0].zero();
   acc[1].zero();
+  Acc3<WTM, WTN> acc3[2];
+  acc3[0].zero();
+  acc3[1].zero();
   const int mr = rows - m0 - wm0, nr = cols - n0 - wn0;
   auto mma = [&](int st, int k0) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if constexpr (sizeof(CT) == 8) {
-        mma_slab<double, WTM, WTN, BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
-                                        acc[a], mr, nr, N - k0);
+        mma_slab3<WTM, WTN, BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
+                                 acc3[a], mr, nr, N - k0);
       } else {
         Acc<float, WTM, WTN> a32;
         a32.zero();
@@ -460,6 +646,10 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       mma(0, k0);
       __syncthreads();
     }
+  }
+  if constexpr (sizeof(CT) == 8) {
+    acc3[0].to(acc[0]);
+    acc3[1].to(acc[1]);
   }
   // combine T_0, T_1 into the two valley blocks of the output
   double2* Y = c.Y + z * c.sY;

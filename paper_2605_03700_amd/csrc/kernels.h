@@ -127,8 +127,13 @@ void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double
 // exponential helper: norm estimate and Taylor coefficients per (batch, channel)
 void launch_exp_coef(const double2* X2, const double2* X3, int N, const double2* alpha, int alpha_per_batch,
                      double* coef, int* sq, int smax, double theta, int* err, int nbatch4, hipStream_t s);
-void launch_exp_poly(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
-                     double2* loE, double2* hiE, double2* loO, double2* hiO, int nbatch4, hipStream_t s);
+// Coefficients of the exponential per (entry, channel) matrix: e_0..e_6 (even part),
+// o_0..o_6 (odd part), then the complex scale of h (alpha / 2^s).
+#define EXP_NC 16
+// E and O of the exponential's even/odd split from x = h^2, x^2, x^3 and the
+// coefficients of exp_coef (one fused pass; Hermitian tiles only)
+void launch_exp_eo(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N, double2* Eo,
+                   double2* Oo, int nmat, hipStream_t s);
 
 struct StepArgs {
   int N, n, nq, L, tau;      // tau 0-based slice index

@@ -718,7 +718,8 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
 }
 
 static bool set_lds_limit(const void* fn, size_t shm);
-// right-solve kernel: 1 right-looking (default), 0 left-looking (CFQMC_RSOLVE=0)
+// right-solve kernel: 1 right-looking with inverted diagonal blocks (default),
+// 0 the left-looking substitution kernel (CFQMC_RSOLVE=0)
 static int rsolve_variant() {
   static int v = -1;
   if (v < 0) {
@@ -1028,6 +1029,8 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
       double2 av[4];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) av[s4] = Tb[buf][il][4 * s4 + kl];
+      // tile -= solved block x row block (four real products per k step: a
+      // three-product form needs registers that cost a wave per SIMD here)
 #pragma unroll
       for (int i = 0; i < MAXT; ++i) {
         const int tc = wid + NW * i;

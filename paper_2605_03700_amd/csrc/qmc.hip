@@ -21,58 +21,84 @@
 #include "kernels.h"
 
 // ------------------------------------------------------------------ build_h
-// One workgroup per (shift d, channel, batch entry): the terms whose matrix
-// has its nonzeros on the diagonal col = row - d (mod N) are staged in LDS with
-// their field weights, each thread then sums them for one row.
-#define BH_NT 256
-__global__ void __launch_bounds__(BH_NT) build_h_kernel(ModelDev m, const double* phi_all, long long sphi,
-                                                         double2* h_all, long long sh) {
-  __shared__ double s_wr[BH_NT], s_wi[BH_NT], s_f[BH_NT];
-  __shared__ int s_qx[BH_NT], s_qy[BH_NT], s_dag[BH_NT];
-  const int d = blockIdx.x, ch = blockIdx.y, z = blockIdx.z, N = m.N;
-  const double* phi = phi_all + z * sphi + ch * m.nq;
-  double2* h = h_all + z * sh + (long long)ch * N * N;
+// h = sum_c phi_c q_c: the terms whose matrix has its nonzeros on the diagonal
+// col = row - d (mod N) are grouped by the shift d.
+#define BH_CPB 4     // chains per workgroup
+#define BH_TC 64     // terms per LDS chunk
+#define BH_MAXN 288
+// One workgroup per (diagonal d, group of BH_CPB entries), one thread per row.
+// The terms of a diagonal and their phases do not depend on the channel or the
+// entry, so each thread computes a term's phase once (table in LDS) and adds
+// it into the 4 x BH_CPB (channel, entry) accumulators with weights staged in
+// LDS (read by all lanes at the same address).
+__global__ void __launch_bounds__(256) build_h_kernel(ModelDev m, const double* phi_all, long long sphi,
+                                                      double2* h_all, long long sh, int nbatch) {
+  __shared__ double2 s_w[BH_TC][4 * BH_CPB];
+  __shared__ int s_qx[BH_TC], s_qy[BH_TC], s_dag[BH_TC];
+  __shared__ double2 s_ph[2 * BH_MAXN];
+  const int d = blockIdx.x, z0 = blockIdx.y * BH_CPB, N = m.N, N2 = 2 * N;
   const int r = threadIdx.x;
   const int col = ((r - d) % N + N) % N;
-  double2 acc = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < N2; i += blockDim.x) s_ph[i] = m.phase[i];
+  double2 acc[4 * BH_CPB];
+#pragma unroll
+  for (int j = 0; j < 4 * BH_CPB; ++j) acc[j] = make_double2(0.0, 0.0);
   const int tb = m.hoff[d], te = m.hoff[d + 1];
-  for (int c0 = tb; c0 < te; c0 += BH_NT) {
-    const int t = c0 + threadIdx.x;
-    if (t < te) {
-      s_wr[threadIdx.x] = m.h_scale[t] * phi[m.h_cre[t]];
-      s_wi[threadIdx.x] = m.h_cim[t] >= 0 ? m.h_scale[t] * m.h_sgn[t] * phi[m.h_cim[t]] : 0.0;
-      s_f[threadIdx.x] = m.h_F[t];
-      s_qx[threadIdx.x] = m.h_qx[t];
-      s_qy[threadIdx.x] = m.h_qy[t];
-      s_dag[threadIdx.x] = m.h_dag[t];
+  for (int c0 = tb; c0 < te; c0 += BH_TC) {
+    const int cnt = min(BH_TC, te - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < cnt * 4 * BH_CPB; idx += blockDim.x) {
+      const int k = idx / (4 * BH_CPB), j = idx % (4 * BH_CPB), ch = j / BH_CPB, z = z0 + j % BH_CPB;
+      const int t = c0 + k;
+      double2 w = make_double2(0.0, 0.0);
+      if (z < nbatch) {
+        const double* phi = phi_all + z * sphi + ch * m.nq;
+        const double f = m.h_F[t] * m.h_scale[t];
+        w.x = f * phi[m.h_cre[t]];
+        w.y = m.h_cim[t] >= 0 ? f * m.h_sgn[t] * phi[m.h_cim[t]] : 0.0;
+      }
+      s_w[k][j] = w;
+    }
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+      s_qx[k] = m.h_qx[c0 + k];
+      s_qy[k] = m.h_qy[c0 + k];
+      s_dag[k] = m.h_dag[c0 + k];
     }
     __syncthreads();
-    const int cnt = min(BH_NT, te - c0);
     if (r < N) {
       for (int k = 0; k < cnt; ++k) {
         const int qx = s_qx[k], qy = s_qy[k];
         const int row = s_dag[k] ? col : r;        // orbital whose phase enters
-        int mm = ((2 * (row + 1) - qy) * qx) % (2 * N);
-        if (mm < 0) mm += 2 * N;
-        double2 ph = m.phase[mm];
+        int mm = ((2 * (row + 1) - qy) * qx) % N2;
+        if (mm < 0) mm += N2;
+        double2 ph = s_ph[mm];
         if (s_dag[k]) ph.y = -ph.y;
-        const double f = s_f[k], wr = s_wr[k], wi = s_wi[k];
-        acc.x += f * (wr * ph.x - wi * ph.y);
-        acc.y += f * (wr * ph.y + wi * ph.x);
+#pragma unroll
+        for (int j = 0; j < 4 * BH_CPB; ++j) {
+          const double2 w = s_w[k][j];
+          acc[j].x += w.x * ph.x - w.y * ph.y;
+          acc[j].y += w.x * ph.y + w.y * ph.x;
+        }
       }
     }
-    __syncthreads();
   }
-  if (r < N) h[(long long)r * N + col] = acc;
+  if (r < N) {
+#pragma unroll
+    for (int j = 0; j < 4 * BH_CPB; ++j) {
+      const int ch = j / BH_CPB, z = z0 + j % BH_CPB;
+      if (z < nbatch) h_all[z * sh + (long long)ch * N * N + (long long)r * N + col] = acc[j];
+    }
+  }
 }
 void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double2* h, long long sh, int nbatch,
                     hipStream_t s) {
-  dim3 grid(m.N, 4, nbatch);
-  hipLaunchKernelGGL(build_h_kernel, grid, dim3(BH_NT), 0, s, m, phi, sphi, h, sh); cfqmc_post_launch("build_h_kernel");
+  if (m.N > BH_MAXN || m.N > 256) { std::fprintf(stderr, "build_h: N = %d too large\n", m.N); std::abort(); }
+  const int nt = (m.N + 63) / 64 * 64;
+  dim3 grid(m.N, (nbatch + BH_CPB - 1) / BH_CPB);
+  hipLaunchKernelGGL(build_h_kernel, grid, dim3(nt), 0, s, m, phi, sphi, h, sh, nbatch); cfqmc_post_launch("build_h_kernel");
 }
 
 // ------------------------------------------------------------------ exponential helpers
-#define EXP_NC 16   // per (batch, channel): a[0..6], b[0..6], oscale (re, im)
 
 __global__ void exp_coef_kernel(const double2* X2all, const double2* X3all, int N, const double2* alpha,
                                 int alpha_div, double* coef, int* sq, int smax, double theta, int* err) {
@@ -136,29 +162,6 @@ void launch_exp_coef(const double2* X2, const double2* X3, int N, const double2*
   if (N > 256) { std::fprintf(stderr, "exp_coef: N = %d exceeds 256\n", N); std::abort(); }
   hipLaunchKernelGGL(exp_coef_kernel, dim3(nbatch4), dim3(256), 0, s, X2, X3, N, alpha, alpha_div, coef, sq, smax,
                      theta, err); cfqmc_post_launch("exp_coef_kernel");
-}
-
-__global__ void exp_poly_kernel(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
-                                double2* loE, double2* hiE, double2* loO, double2* hiO) {
-  const int b4 = blockIdx.y;
-  const double* cf = coef + (long long)b4 * EXP_NC;
-  const long long off = (long long)b4 * N * N;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
-    const int i = idx / N, j = idx % N;
-    const double id = (i == j) ? 1.0 : 0.0;
-    const double2 w1 = H2[off + idx], w2 = X2[off + idx], w3 = X3[off + idx];
-    loE[off + idx] = make_double2(cf[0] * id + cf[1] * w1.x + cf[2] * w2.x, cf[1] * w1.y + cf[2] * w2.y);
-    hiE[off + idx] = make_double2(cf[3] * id + cf[4] * w1.x + cf[5] * w2.x + cf[6] * w3.x,
-                                  cf[4] * w1.y + cf[5] * w2.y + cf[6] * w3.y);
-    loO[off + idx] = make_double2(cf[7] * id + cf[8] * w1.x + cf[9] * w2.x, cf[8] * w1.y + cf[9] * w2.y);
-    hiO[off + idx] = make_double2(cf[10] * id + cf[11] * w1.x + cf[12] * w2.x + cf[13] * w3.x,
-                                  cf[11] * w1.y + cf[12] * w2.y + cf[13] * w3.y);
-  }
-}
-void launch_exp_poly(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
-                     double2* loE, double2* hiE, double2* loO, double2* hiO, int nbatch4, hipStream_t s) {
-  dim3 grid(min((N * N + 255) / 256, 64), nbatch4);
-  hipLaunchKernelGGL(exp_poly_kernel, grid, dim3(256), 0, s, H2, X2, X3, coef, N, loE, hiE, loO, hiO); cfqmc_post_launch("exp_poly_kernel");
 }
 
 // ------------------------------------------------------------------ drift, proposal, MH test
