@@ -27,7 +27,7 @@ PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFM
 # this script (profiles/chan_apply_traffic_n100_256chains.md); keyed by
 # (N_phi, chains per context, precision, tile configuration). Absent key, or a
 # kernel changed since the counters were taken: traffic not measured (null).
-TRAFFIC = {(100, 256, "mixed", 1): (167489.07 * 2.0 + 160000.0 * 1.0) * 1024}
+TRAFFIC = {(100, 256, "mixed", 1): (166617.07 * 2.0 + 160000.0 * 1.0) * 1024}
 
 
 def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
