@@ -7,7 +7,9 @@ recomputation every 8 slices, complex FP32 MFMA wraps with FP64 accumulation
 (--precision fp64 for the all-FP64 path). A step is one sweep of every chain:
 L Langevin slice moves of 4 n_q fields each, with wraps, Woodbury updates and
 stabilisation. After the timed sweeps: tau_int of m^2_SO(5) over untimed
-sweeps, a one-chain FP64 reference sweep, and the FP64 oracle on the host.
+sweeps, (with --fp64-compare) the same chains with every product in FP64, a
+one-chain FP64 reference sweep, and the FP64 oracle on the host.
+--workload batched and --workload learned run the other two workloads.
 
 Prints one JSON line (see the fields below). Synthetic fields N(0,1).
 """
@@ -95,12 +97,19 @@ def main():
                     help="independent chains in one context; 256 N_phi = 100 chains take about 190 GB of HBM")
     ap.add_argument("--groups", type=int, default=1, help="split the chains over this many streams")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
-    ap.add_argument("--workload", choices=["c3", "batched"], default="c3",
-                    help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid")
+    ap.add_argument("--workload", choices=["c3", "batched", "learned"], default="c3",
+                    help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid; "
+                         "learned: N_phi=140, L=600 with the learned global proposal")
+    ap.add_argument("--learned-chains", type=int, default=16)
+    ap.add_argument("--learned-sweeps", type=int, default=12)
+    ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--tile-cfg", type=int, default=-1)
     ap.add_argument("--tau-sweeps", type=int, default=10, help="untimed sweeps after the timed ones for tau_int")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-chain FP64 reference sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-compare", action="store_true",
+                    help="after the timed mixed sweeps, time the same chains with every product in FP64 (it runs "
+                         "after a minute of load, so clocks may differ from the timed part)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB between two fresh device buffers three times (reference for the "
@@ -128,6 +137,8 @@ def main():
     prec = {"fp64": FP64, "mixed": MIXED, "mixed_all": MIXED_ALL}[args.precision]
     if args.workload == "batched":
         return bench_batched(args, prec)
+    if args.workload == "learned":
+        return bench_learned(args, prec)
     if args.chains % args.groups:
         raise SystemExit("--chains must be a multiple of --groups")
     nper = args.chains // args.groups
@@ -191,6 +202,19 @@ def main():
         out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
         progress("tau_int sweeps done")
     b.close()
+    if prec != FP64 and args.fp64_compare:
+        # the same chains with every product in FP64 (warm-up sweep, then two timed sweeps)
+        f = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+                        n_stab=args.n_stab, precision=FP64, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
+                        tile_cfg=args.tile_cfg) for k in range(args.groups)])
+        f.init_fields()
+        f.sweep(1)
+        dtf, _, gef = sweep_each(f, 2)
+        out["fp64_same_chains"] = {"precision": "fp64", "chains": args.chains,
+                                   "field_updates_per_s": args.chains * args.l_tau * 4 * g.n_q * 2 / dtf,
+                                   "ms_per_sweep": 1000.0 * dtf / 2, "g_err_max": max(gef)}
+        f.close()
+        progress("FP64 comparison on the same chains done")
     if not args.no_plain:
         # the plain path for comparison: one chain, FP64, same workload
         p = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
@@ -262,6 +286,94 @@ def bench_batched(args, prec):
                            "traffic": None, "avg_launch_ms": k_ms, "launches_timed": k_count,
                            "flops_per_launch": k_flops}
     b.close()
+    print(json.dumps(out))
+
+
+def bench_learned(args, prec):
+    """Learned global proposal at N_phi = 140 (spin block n = 280), L = 600,
+    paper cutoff, u on the SO(5) line: plain local sweeps of --learned-chains
+    chains (timed: the value), every sweep's configurations collected with
+    their exact FP64 ln w_F, the effective-action network (three layers,
+    hidden 256, BF16 products, FP32 Adam) trained on the GPU, its held-out R^2
+    against -ln w_F, and global moves (HMC on S_eff, exact determinant test)
+    with the trained network and with the Gaussian proposal (network = 0) at a
+    few trajectory lengths. The collection is --learned-sweeps sweeps, far
+    below the 10^4 configurations a production training set would hold."""
+    import numpy as np
+    import torch
+    from paper_2605_03700_amd import CFQMC, Slmc
+    n_phi, l_tau, nch = 140, 600, args.learned_chains
+    g = CFQMC(n_phi=n_phi, l_tau=l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u, n_stab=args.n_stab,
+              precision=prec, n_chains=nch, seed=7, eps0=0.3, adapt_eps=True, tile_cfg=args.tile_cfg)
+    n_sw = args.learned_sweeps
+    s = Slmc(g, hidden=256, n_qbins=16, n_wbins=16, capacity=nch * (n_sw + 4), max_batch=256, seed=11)
+    g.init_fields(None)
+    progress("learned workload: context and network created")
+    if args.warmup:
+        g.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc, prop = 0, 0
+    for _ in range(n_sw):
+        st = g.sweep(1)
+        acc += sum(x["accepted"] for x in st)
+        prop += sum(x["proposed"] for x in st)
+        s.collect()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    progress("learned workload: %d sweeps collected (%.1f s per sweep)" % (n_sw, dt / n_sw))
+    w0 = s.get_params()
+    t1 = time.perf_counter()
+    loss0 = s.train(epochs=1, batch=32, lr=1e-3, refit_norm=True)
+    s.set_params(w0)
+    loss = s.train(epochs=args.learned_epochs, batch=32, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    w_trained = s.get_params()
+    res, lnw = [], []
+    for _ in range(2):
+        g.sweep(1)
+        snn = s.action(g.get_fields())
+        for z in range(nch):
+            lw = g.logdet(z).real
+            lnw.append(lw)
+            res.append(snn[z] + lw)
+    r2 = 1.0 - float(np.var(res) / np.var(lnw))
+    progress("learned workload: trained (R^2 %.3f)" % r2)
+    moves = []
+    for step in (0.002, 0.01, 0.05):
+        row = {"step": step, "n_leap": 4}
+        for name, w in (("trained", w_trained), ("gaussian", np.zeros_like(w_trained))):
+            s.set_params(w)
+            a, n_mv = 0, 0
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(2):
+                mv = s.global_move(1, 4, step)
+                a += sum(m["accepted"] for m in mv)
+                n_mv += len(mv)
+            torch.cuda.synchronize()
+            row["acceptance_" + name] = a / n_mv
+            row["ms_per_move_" + name] = 1000.0 * (time.perf_counter() - t2) / 2
+        moves.append(row)
+        progress("learned workload: global moves at step %g done" % step)
+    fields = nch * l_tau * 4 * g.n_q * n_sw
+    out = {
+        "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
+        "value": fields / dt, "unit": "field updates/s", "n_gpus": 1, "steps": n_sw, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / n_sw, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "learned: torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chains, "
+                               "FP64 recompute every %d slices; MLP hidden 256 on 16 x 16 periodogram bins"
+                               % (n_phi, l_tau, args.dtau, args.u, g.n_q, nch, args.n_stab),
+                   "chains": nch, "precision": args.precision, "n_q": g.n_q, "tile_cfg": list(g.tile_config())},
+        "acceptance": acc / max(1, prop),
+        "learned": {"configurations": s.n_data(), "train_epochs": args.learned_epochs,
+                    "train_loss_first_epoch": loss0, "train_loss_last": loss, "train_s": t_train,
+                    "heldout_r2": r2, "heldout_points": len(lnw), "global_moves": moves},
+    }
+    s.close()
+    g.close()
     print(json.dumps(out))
 
 
