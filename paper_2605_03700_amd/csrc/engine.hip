@@ -187,6 +187,7 @@ struct cfqmc_ctx {
   cfqmc_params p;
   hipStream_t s;
   int N, n, nq, L, nch, nstab, nblk_stab, mixed, mixed_m, smax;
+  int hband;   // h = sum_c phi_c q_c vanishes outside |(col - row) mod N| <= hband (-1: dense)
   long long nn, NN;
   HostTables ht;
   ModelDev md;
@@ -291,6 +292,7 @@ GemmArgs gemm0(int M, int N, int K) {
   g.alpha = make_double2(1.0, 0.0);
   g.beta = make_double2(0.0, 0.0);
   g.mode = GEMM_NORMAL;
+  g.bandA = g.bandB = -1;
   return g;
 }
 MatRef mref(const double2* p, int ld, long long s1, long long s2 = 0) {
@@ -327,9 +329,10 @@ void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, lon
 
 // C = op(A) op(B) on n x n per chain (FP64)
 void gemm_nn(cfqmc_ctx* c, const double2* A, int opA, long long sA, const double2* B, int opB, long long sB,
-             double2* D, long long sD, int nbatch) {
+             double2* D, long long sD, int nbatch, bool herm = false) {
   GemmArgs g = gemm0(c->n, c->n, c->n);
   g.opA = opA; g.opB = opB;
+  g.herm = herm ? 1 : 0;
   g.A = mref(A, c->n, sA); g.B = mref(B, c->n, sB); g.D = mref(D, c->n, sD);
   launch_zgemm(g, nbatch, 0, c->cfg_gemm, c->s);
 }
@@ -342,16 +345,19 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
   const long long NN = c->NN, s4 = 4 * NN;
   // h is Hermitian, so are its powers and the even / odd polynomials in h^2
   // (real coefficients): those products compute the upper tile triangle only
-  auto sq = [&](const double2* A, const double2* B, double2* D) {
+  // h has band b = hband, h^2 band 2b: slabs of exact zeros are skipped
+  const int b1 = c->hband, b2 = (b1 >= 0 && 4 * b1 < N) ? 2 * b1 : -1;
+  auto sq = [&](const double2* A, const double2* B, double2* D, int bandA, int bandB) {
     GemmArgs g = gemm0(N, N, N);
     g.A = mref(A, N, s4, NN); g.B = mref(B, N, s4, NN); g.D = mref(D, N, s4, NN);
     g.nz2 = 4;
     g.herm = 1;
+    g.bandA = bandA; g.bandB = bandB;
     launch_zgemm(g, nent * 4, 0, c->cfg_small, c->s);
   };
-  sq(hb, hb, c->H2);
-  sq(c->H2, c->H2, c->X2);
-  sq(c->X2, c->H2, c->X3);
+  sq(hb, hb, c->H2, b1, b1);
+  sq(c->H2, c->H2, c->X2, b2, b2);
+  sq(c->X2, c->H2, c->X3, -1, b2);
   launch_exp_coef(c->X2, c->X3, N, alpha, alpha_div, c->coef, c->sq, c->smax, 0.4, c->d_err, nent * 4, c->s);
   launch_exp_eo(c->H2, c->X2, c->X3, c->coef, N, c->Eo, c->Oo, nent * 4, c->s);
   {
@@ -359,6 +365,7 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
     GemmArgs g = gemm0(N, N, N);
     g.mode = GEMM_PQ;
     g.A = mref(hb, N, s4, NN); g.B = mref(c->Oo, N, s4, NN); g.C = mref(c->Eo, N, s4, NN);
+    g.bandA = b1;
     g.alpha_dev = (const double2*)(c->coef + 14);
     g.ad_s1 = 4 * EXP_NC / 2; g.ad_s2 = EXP_NC / 2;
     g.nz2 = 4;
@@ -400,12 +407,12 @@ void udt_acc(cfqmc_ctx* c, const double2* C, long long sC, int opC, const double
   launch_colnorm_sort(c->W1, n, nn, c->nrm, c->perm, B, c->s);
   launch_permute_normalize(c->W1, n, nn, c->nrm, c->perm, c->A1, B, c->s);
   // Cholesky-QR, twice
-  gemm_nn(c, c->A1, 1, nn, c->A1, 0, nn, c->Gr, nn, B);
+  gemm_nn(c, c->A1, 1, nn, c->A1, 0, nn, c->Gr, nn, B, true);   // Gram matrix: Hermitian
   launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
   launch_chol_from_lu(c->Gr, n, nn, c->R1, c->sqd1, B, c->s);
   launch_rsolve(c->A1, n, nn, c->Q1, n, nn, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s, c->rs_ws);
   launch_colscale(c->Q1, n, nn, c->Q1, n, nn, c->sqd1, n, n, n, 0, B, c->s);
-  gemm_nn(c, c->Q1, 1, nn, c->Q1, 0, nn, c->Gr, nn, B);
+  gemm_nn(c, c->Q1, 1, nn, c->Q1, 0, nn, c->Gr, nn, B, true);
   launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
   launch_chol_from_lu(c->Gr, n, nn, c->R2, c->sqd2, B, c->s);
   launch_rsolve(c->Q1, n, nn, Uo, n, sU, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s, c->rs_ws);
@@ -702,10 +709,19 @@ int autotune(cfqmc_ctx* c) {
     c->cfg_gemm = cfg;
     const float tg = timeit([&]() { gemm_nn(c, c->F[0], 0, c->nn, c->F[1], 0, c->nn, c->S1, c->nn, c->nch); });
     if (tg < best_g) { best_g = tg; bg = cfg; }
+    // the exponential's products as the sweep runs them: Hermitian tiles with
+    // the band of h (h^2) and of h^2 (x^3), and the banded h O
+    const int b1 = c->hband, b2 = (b1 >= 0 && 4 * b1 < c->N) ? 2 * b1 : -1;
     const float ts = timeit([&]() {
       GemmArgs g = gemm0(c->N, c->N, c->N);
       g.A = mref(c->H2, c->N, s4, NN); g.B = mref(c->X2, c->N, s4, NN); g.D = mref(c->X3, c->N, s4, NN);
       g.nz2 = 4;
+      g.herm = 1;
+      g.bandA = g.bandB = b1;
+      launch_zgemm(g, c->nch * 4, 0, cfg, c->s);
+      g.bandA = -1; g.bandB = b2;
+      launch_zgemm(g, c->nch * 4, 0, cfg, c->s);
+      g.herm = 0; g.bandA = b1; g.bandB = -1;
       launch_zgemm(g, c->nch * 4, 0, cfg, c->s);
     });
     if (ts < best_s) { best_s = ts; bs = cfg; }
@@ -763,6 +779,11 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->sweep_counter = 0;
   if (!build_components(p, c->ht, c->err)) { delete c; return CFQMC_EINVAL; }
   c->nq = (int)c->ht.comp_kind.size();
+  // band of h: the largest circular shift that carries a term
+  c->hband = 0;
+  for (int d = 0; d < c->N; ++d)
+    if (c->ht.hoff[d + 1] > c->ht.hoff[d]) c->hband = std::max(c->hband, std::min(d, c->N - d));
+  if (4 * c->hband >= c->N) c->hband = -1;
   // valley rotations: columns are the +1 / -1 eigenvectors of o_i
   const double r = 1.0 / std::sqrt(2.0);
   for (int ch = 0; ch < 4; ++ch) {

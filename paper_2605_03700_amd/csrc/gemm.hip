@@ -168,6 +168,17 @@ CF_DEV bool xcd_tile(int tiles_x, int tiles_y, int nbatch, int& z, int& ty, int&
   return true;
 }
 
+// Does the block rows [r0, r0 + nr) x cols [c0, c0 + nc) meet the wrap-around
+// band |(col - row) mod K| <= b? The differences col - row fill [dlo, dhi]; the
+// band is the union of [mK - b, mK + b] over integers m.
+CF_DEV bool band_meets(int r0, int nr, int c0, int nc, int b, int K) {
+  if (b < 0) return true;
+  const int dlo = c0 - (r0 + nr - 1), dhi = c0 + nc - 1 - r0;
+  // smallest m with mK + b >= dlo, then check mK - b <= dhi
+  int m = (dlo - b) >= 0 ? (dlo - b + K - 1) / K : -((b - dlo) / K);
+  return m * K - b <= dhi;
+}
+
 // ------------------------------------------------------------------ zgemm
 
 template <typename CT, int BM, int BN, int WTM, int WTN>
@@ -254,11 +265,24 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
   Acc3<WTM, WTN> acc3;
   acc3.zero();
   {
-    fetch(0);
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    // k slabs whose A block (tile rows) and B block (tile columns) can be
+    // nonzero; the test is uniform over the workgroup
+    auto live = [&](int k0) {
+      const int kw = min(BK, g.K - k0);
+      return band_meets(m0, min(BM, g.M - m0), k0, kw, g.bandA, g.K) &&
+             band_meets(k0, kw, n0, min(BN, g.N - n0), g.bandB, g.K);
+    };
+    auto next_live = [&](int k0) {
+      while (k0 < g.K && !live(k0)) k0 += BK;
+      return k0;
+    };
+    int k0 = next_live(0);
+    if (k0 < g.K) fetch(k0);
+    for (; k0 < g.K;) {
       stage(k0);
       __syncthreads();
-      if (k0 + BK < g.K) fetch(k0 + BK);
+      const int k1 = next_live(k0 + BK);
+      if (k1 < g.K) fetch(k1);
       const int mr = g.M - m0 - wm0, nr = g.N - n0 - wn0, kr = g.K - k0;
       if constexpr (sizeof(CT) == 8) {
         mma_slab3<WTM, WTN>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc3, mr, nr, kr);
@@ -269,6 +293,7 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
         flush(a32, acc);
       }
       __syncthreads();
+      k0 = k1;
     }
   }
   if constexpr (sizeof(CT) == 8) acc3.to(acc);

@@ -26,6 +26,9 @@ struct GemmArgs {
   int ad_s1, ad_s2;
   int mode;
   const int* pred;          // squaring count per matrix (GEMM_PQ, GEMM_SQUARE), index z1*pred_s1 + z2*pred_s2
+  int bandA, bandB;         // >= 0: A (resp. B) vanishes outside the wrap-around band
+                            // |(col - row) mod K| <= band; k slabs that meet no band entry of
+                            // the tile's rows (columns) are skipped (their terms are exact zeros)
   int herm;                 // GEMM_NORMAL with a Hermitian result (M == N; alpha, beta real): only the
                             // tiles on and above the diagonal are computed, each strictly upper tile
                             // also writes its conjugate transpose
