@@ -718,16 +718,7 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
 }
 
 static bool set_lds_limit(const void* fn, size_t shm);
-// right-solve kernel: 1 right-looking with inverted diagonal blocks (default),
-// 0 the left-looking substitution kernel (CFQMC_RSOLVE=0)
-static int rsolve_variant() {
-  static int v = -1;
-  if (v < 0) {
-    const char* e = std::getenv("CFQMC_RSOLVE");
-    v = (e && e[0] == '0') ? 0 : 1;
-  }
-  return v;
-}
+
 
 void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int* flag,
                   double lmax_allowed, int nbatch, hipStream_t s) {
@@ -761,117 +752,9 @@ void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, doub
 // ------------------------------------------------------------------ right solve
 // Y = X A^{-1} with P A = L U, (P A)[i] = A[perm[i]] (lu_kernel): Y = X U^{-1} L^{-1} P,
 // i.e. W = X U^{-1} L^{-1} and Y[:, perm[i]] = W[:, i]. Row k of the factors is
-// physical row perm[k]. A workgroup owns 16 rows of X in LDS and eliminates
-// 16-column blocks: the coupling to the solved blocks is one MFMA product (K
-// split over 4 waves, operands prefetched into registers), the 16 x 16 diagonal
-// block is solved wave-synchronously with shuffles.
+// physical row perm[k]. A workgroup owns 16 rows of X.
 #define RS_ROWS 16
-#define RS_NT 256
-#define RS_NW 4
-#define RS_MAXIT ((LU_MAXN + 4 * RS_NW - 1) / (4 * RS_NW))
 
-__global__ void __launch_bounds__(RS_NT) rsolve_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
-                                                       int ldy, long long sY, const double2* LUall, int ldlu,
-                                                       long long sLU, const int* ipiv_all, int sP, int n,
-                                                       int upper_only, int nbatch) {
-  extern __shared__ double2 Zs[];          // 16 x n row block, rows padded to an odd length
-  const int zl = n | 1;                    // odd row stride: a quarter wave reading one column hits 16 banks
-  __shared__ double2 red[RS_NW][16][16];
-  __shared__ double2 Db[16][16];           // diagonal block of U or L
-  __shared__ double2 Dr[16];               // reciprocals of the diagonal of U_JJ
-  __shared__ int perm[LU_MAXN];
-  // all row blocks of one chain on one XCD (consecutive workgroups go to the
-  // eight XCDs in turn), so the chain's factors are read into one L2
-  const int nrb = (n + RS_ROWS - 1) / RS_ROWS, T = nrb * nbatch, per = (T + 7) / 8;
-  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (t >= T) return;
-  const int z = t / nrb;
-  const double2* X = Xall + z * sX;
-  double2* Yo = Yall + z * sY;
-  const double2* LU = LUall + z * sLU;
-  const int* ipiv = ipiv_all + z * sP;
-  const int r0 = (t % nrb) * RS_ROWS;
-  const int nr = min(RS_ROWS, n - r0);
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int il = lane & 15, kl = lane >> 4;
-  // thread layout of the block solve: row rr = wid*4 + lane/16, column cc = lane%16
-  const int rr = wid * 4 + (lane >> 4), cc = lane & 15;
-  for (int i = tid; i < n; i += RS_NT) perm[i] = upper_only ? i : ipiv[i];
-  for (int idx = tid; idx < RS_ROWS * n; idx += RS_NT) {
-    const int r = idx / n, c = idx % n;
-    Zs[r * zl + c] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int nJ = (n + 15) / 16;
-  const double2 zero2 = make_double2(0.0, 0.0);
-  for (int phase = 0; phase < (upper_only ? 1 : 2); ++phase) {
-    for (int jj = 0; jj < nJ; ++jj) {
-      const int J = phase == 0 ? jj : nJ - 1 - jj;
-      const int c0 = 16 * J, bw = min(16, n - c0);
-      // coupling: acc[r][c] = sum_k Z[r][k] T[k][c0+c] over the solved columns k
-      const int klo = phase == 0 ? 0 : c0 + 16, khi = phase == 0 ? c0 : n;
-      double2 bb[RS_MAXIT];
-#pragma unroll
-      for (int it = 0; it < RS_MAXIT; ++it) {
-        const int k = klo + wid * 4 + it * 4 * RS_NW + kl;
-        const bool ok = k < khi && il < bw;
-        bb[it] = LU[ok ? (long long)perm[k] * ldlu + c0 + il : 0];
-      }
-      const bool okd = rr < bw && cc < bw;
-      const double2 dv = LU[okd ? (long long)perm[c0 + rr] * ldlu + c0 + cc : 0];
-      d4v are = Mfma<double>::zero(), aim = Mfma<double>::zero();
-#pragma unroll
-      for (int it = 0; it < RS_MAXIT; ++it) {
-        const int k = klo + wid * 4 + it * 4 * RS_NW + kl;
-        if (klo + wid * 4 + it * 4 * RS_NW < khi) {
-          const bool ok = k < khi;
-          const double2 a = ok ? Zs[il * zl + k] : zero2;
-          const double2 b = ok && il < bw ? bb[it] : zero2;
-          are = Mfma<double>::mma(a.x, b.x, are);
-          are = Mfma<double>::mma(-a.y, b.y, are);
-          aim = Mfma<double>::mma(a.x, b.y, aim);
-          aim = Mfma<double>::mma(a.y, b.x, aim);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) red[wid][Mfma<double>::row(lane, q)][il] = make_double2(are[q], aim[q]);
-      const double2 dd = okd ? dv : make_double2(rr == cc ? 1.0 : 0.0, 0.0);
-      Db[rr][cc] = dd;
-      // reciprocals of the diagonal, one division per lane in parallel
-      if (phase == 0 && rr == cc) Dr[cc] = crcp(dd);
-      __syncthreads();
-      double2 y = Zs[rr * zl + c0 + min(cc, bw - 1)];
-      for (int w = 0; w < RS_NW; ++w) y = csub(y, red[w][rr][cc]);
-      if (phase == 0) {
-        // z U_JJ = y, columns ascending
-        for (int cp = 0; cp < 16; ++cp) {
-          double2 zv = cmul(y, Dr[cp]);
-          zv.x = __shfl(zv.x, (lane & ~15) + cp, 64);
-          zv.y = __shfl(zv.y, (lane & ~15) + cp, 64);
-          if (cc == cp) y = zv;
-          else if (cc > cp) y = csub(y, cmul(zv, Db[cp][cc]));
-        }
-      } else {
-        // w L_JJ = y with unit diagonal, columns descending
-        for (int cp = 15; cp >= 0; --cp) {
-          double2 wv;
-          wv.x = __shfl(y.x, (lane & ~15) + cp, 64);
-          wv.y = __shfl(y.y, (lane & ~15) + cp, 64);
-          if (cc < cp) y = csub(y, cmul(wv, Db[cp][cc]));
-        }
-      }
-      __syncthreads();
-      if (cc < bw) Zs[rr * zl + c0 + cc] = y;
-      __syncthreads();
-    }
-  }
-  for (int idx = tid; idx < nr * n; idx += RS_NT) {
-    const int r = idx / n, c = idx % n;
-    Yo[(long long)(r0 + r) * ldy + perm[c]] = Zs[r * zl + c];
-  }
-}
-
-// Fallback when the large-LDS configuration is refused: one column at a time.
 // Inverses of the 16 x 16 diagonal blocks of U and of the unit-lower L of a
 // factorisation from launch_lu / launch_lu_np (rows addressed through ipiv):
 // Ui_J = U_JJ^{-1}, Li_J = L_JJ^{-1}, padded with the identity past n. Row r of
@@ -1050,83 +933,25 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
   }
 }
 
-#define RSS_ROWS 8
-#define RSS_NT 256
-
-__global__ void __launch_bounds__(RSS_NT) rsolve_simple_kernel(const double2* Xall, int ldx, long long sX, double2* Yall,
-                                                       int ldy, long long sY, const double2* LUall, int ldlu,
-                                                       long long sLU, const int* ipiv_all, int sP, int n,
-                                                       int upper_only) {
-  extern __shared__ double2 Ysm[];          // RSS_ROWS x n
-  const int z = blockIdx.y;
-  const double2* X = Xall + z * sX;
-  double2* Yo = Yall + z * sY;
-  const double2* LU = LUall + z * sLU;
-  const int* ipiv = ipiv_all + z * sP;
-  const int r0 = blockIdx.x * RSS_ROWS;
-  const int nr = min(RSS_ROWS, n - r0);
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < RSS_ROWS * n; idx += RSS_NT) {
-    const int r = idx / n, c = idx % n;
-    Ysm[idx] = r < nr ? X[(long long)(r0 + r) * ldx + c] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  // z U = x, columns ascending
-  for (int j = 0; j < n; ++j) {
-    const double2 d = LU[(long long)(upper_only ? j : ipiv[j]) * ldlu + j];
-    if (tid < RSS_ROWS) Ysm[tid * n + j] = cdiv(Ysm[tid * n + j], d);
-    __syncthreads();
-    const int w = n - j - 1;
-    for (int idx = tid; idx < RSS_ROWS * w; idx += RSS_NT) {
-      const int r = idx / w, c = j + 1 + idx % w;
-      Ysm[r * n + c] = csub(Ysm[r * n + c], cmul(Ysm[r * n + j], LU[(long long)(upper_only ? j : ipiv[j]) * ldlu + c]));
-    }
-    __syncthreads();
-  }
-  if (!upper_only) {
-    // w L = z (unit lower), columns descending
-    for (int j = n - 1; j > 0; --j) {
-      for (int idx = tid; idx < RSS_ROWS * j; idx += RSS_NT) {
-        const int r = idx / j, c = idx % j;
-        Ysm[r * n + c] = csub(Ysm[r * n + c], cmul(Ysm[r * n + j], LU[(long long)ipiv[j] * ldlu + c]));
-      }
-      __syncthreads();
-    }
-  }
-  for (int idx = tid; idx < nr * n; idx += RSS_NT) {
-    const int r = idx / n, c = idx % n;
-    Yo[(long long)(r0 + r) * ldy + (upper_only ? c : ipiv[c])] = Ysm[r * n + c];
-  }
-}
-
 void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY, const double2* LU,
                    int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only, int nbatch,
                    hipStream_t s, double2* work) {
-  dim3 grid((n + RS_ROWS - 1) / RS_ROWS, nbatch);
-  const size_t shm = (size_t)RS_ROWS * (n | 1) * sizeof(double2);
-  if (!set_lds_limit((const void*)rsolve_kernel, shm)) {
-    dim3 g2((n + RSS_ROWS - 1) / RSS_ROWS, nbatch);
-    hipLaunchKernelGGL(rsolve_simple_kernel, g2, dim3(RSS_NT), (size_t)RSS_ROWS * n * sizeof(double2), s, X, ldx, sX,
-                       Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n, upper_only); cfqmc_post_launch("rsolve_simple_kernel");
-    return;
+  if (!work || n > LU_MAXN) {
+    std::fprintf(stderr, "rsolve: workspace missing or n = %d above %d\n", n, LU_MAXN);
+    std::abort();
   }
-  const int nblk = (int)(((long long)grid.x * nbatch + 7) / 8 * 8);
-  if (work && rsolve_variant() == 1) {
-    const int nJ = (n + 15) / 16;
-    hipLaunchKernelGGL(tri_inv_kernel, dim3(nJ, nbatch), dim3(256), 0, s, LU, ldlu, sLU, ipiv, sP, n, upper_only,
-                       work); cfqmc_post_launch("tri_inv_kernel");
-    // eight waves, each owning at most ceil(nJ / 8) column tiles (2 for n <= 256)
-    if (n <= 256)
-      hipLaunchKernelGGL((rsolve_rl_kernel<8, 2>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
-                         ipiv, sP, n, upper_only, (const double2*)work, nbatch);
-    else
-      hipLaunchKernelGGL((rsolve_rl_kernel<8, 3>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
-                         ipiv, sP, n, upper_only, (const double2*)work, nbatch);
-    cfqmc_post_launch("rsolve_rl_kernel");
-    return;
-  }
-  hipLaunchKernelGGL(rsolve_kernel, dim3(nblk), dim3(RS_NT), shm, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP,
-                     n, upper_only, nbatch); cfqmc_post_launch("rsolve_kernel");
+  const int nrb = (n + RS_ROWS - 1) / RS_ROWS, nJ = (n + 15) / 16;
+  const int nblk = (int)(((long long)nrb * nbatch + 7) / 8 * 8);
+  hipLaunchKernelGGL(tri_inv_kernel, dim3(nJ, nbatch), dim3(256), 0, s, LU, ldlu, sLU, ipiv, sP, n, upper_only, work);
+  cfqmc_post_launch("tri_inv_kernel");
+  // eight waves, each owning at most ceil(nJ / 8) column tiles (2 for n <= 256)
+  if (n <= 256)
+    hipLaunchKernelGGL((rsolve_rl_kernel<8, 2>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
+                       ipiv, sP, n, upper_only, (const double2*)work, nbatch);
+  else
+    hipLaunchKernelGGL((rsolve_rl_kernel<8, 3>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
+                       ipiv, sP, n, upper_only, (const double2*)work, nbatch);
+  cfqmc_post_launch("rsolve_rl_kernel");
 }
 
 // ------------------------------------------------------------------ elementwise helpers
