@@ -182,7 +182,16 @@ def main():
         "g_err_abs_median_chain": float(np.median([max(st[z]["max_stab_err"] for st in stats)
                                                     for z in range(len(stats[0]))])),
         "sweeps_per_s_per_chain": sweeps_per_s,
+        "accepted_field_updates_per_s": value * acc,
     }
+    # whole-path figure: W_slice = 64 n^3 real flops per slice move (8 complex
+    # n x n x n GEMM-equivalents: wrap 2, B' 3, Delta 1, M 1, solve 1), n = 2 N_phi
+    n_sp = 2 * args.n_phi
+    w_slice = 64.0 * n_sp ** 3
+    path_tf = args.chains * args.l_tau * args.steps / dt * w_slice / 1e12
+    out["path_roofline"] = {"work_per_slice_move_flop": w_slice, "achieved": path_tf, "unit": "TFLOP/s",
+                            "peak": PEAK[args.precision], "frac": path_tf / PEAK[args.precision],
+                            "definition": "64 n^3 real flops per slice move, n = 2 N_phi"}
     if k_count > 0 and k_ms > 0:
         ach = k_flops / (k_ms * 1e-3) / 1e12
         traffic = TRAFFIC.get((args.n_phi, nper, args.precision, g.tile_config()[0]))

@@ -115,6 +115,18 @@ int cfqmc_sizes(const cfqmc_ctx* c, int32_t* n_q, int32_t* n_chains, int32_t* di
 int cfqmc_init_fields(cfqmc_ctx* c, const double* phi);
 int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out);
 
+/* Checkpoint / resume of a Markov chain set. cfqmc_checkpoint writes to the
+ * file `path` (created or truncated) the fields, each chain's step size eps,
+ * the couplings, the device-RNG position (seed and sweep count) and the m^2
+ * series; it needs initialised fields (else CFQMC_ESTATE). cfqmc_restore reads
+ * such a file into a context of the same shape and couplings (else
+ * CFQMC_EINVAL, context unchanged), rebuilds every slice propagator, both UDT
+ * stacks and G(0) in FP64 from the fields (as cfqmc_init_fields) and then
+ * continues eps, the RNG stream and the series: later sweeps with device noise
+ * draw the same noise as the uninterrupted run. Synchronise. */
+int cfqmc_checkpoint(cfqmc_ctx* c, const char* path);
+int cfqmc_restore(cfqmc_ctx* c, const char* path);
+
 /* Run n_sweeps sweeps (slices tau = 1..L each) on all chains.
  * replay: NULL (device Philox noise) or host [n_chains][n_sweeps][l_tau][4 n_q + 1]
  * holding per slice the 4 n_q proposal normals (channel-major) and the

@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
-           "cfqmc_get_fields", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
+           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
@@ -85,6 +85,8 @@ def load():
                                 ctypes.POINTER(ctypes.c_int32)]
     lib.cfqmc_init_fields.argtypes = [P, P]
     lib.cfqmc_get_fields.argtypes = [P, P]
+    lib.cfqmc_checkpoint.argtypes = [P, ctypes.c_char_p]
+    lib.cfqmc_restore.argtypes = [P, ctypes.c_char_p]
     lib.cfqmc_sweep.argtypes = [P, ctypes.c_int32, P, P]
     lib.cfqmc_measure_G.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32]
     lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -226,6 +228,14 @@ class CFQMC:
         out = np.empty((self.n_chains, self.l_tau, 4, self.n_q))
         self._check(self.lib.cfqmc_get_fields(self.h, _ptr(out)))
         return out
+
+    def checkpoint(self, path):
+        """Write fields, step sizes, RNG position and series to `path`."""
+        self._check(self.lib.cfqmc_checkpoint(self.h, os.fsencode(path)))
+
+    def restore(self, path):
+        """Continue the chains stored in `path` (same shape and couplings)."""
+        self._check(self.lib.cfqmc_restore(self.h, os.fsencode(path)))
 
     def sweep(self, n_sweeps=1, replay=None):
         if replay is not None:

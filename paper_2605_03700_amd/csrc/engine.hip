@@ -954,6 +954,93 @@ int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out) {
   return CFQMC_OK;
 }
 
+// Checkpoint file: header, then fields [B][L][4][n_q], eps [B], couplings
+// alpha [B][4] (complex), series [B][series_len]; all FP64, native byte order.
+struct CkptHeader {
+  char magic[8];
+  int32_t version, n_phi, l_tau, n_q, n_chains, n_stab;
+  uint64_t seed;
+  int64_t sweep_counter;
+  int32_t series_len, pad;
+};
+static const char kCkptMagic[8] = {'C', 'F', 'Q', 'M', 'C', 'C', 'K', '1'};
+
+int cfqmc_checkpoint(cfqmc_ctx* c, const char* path) {
+  if (!c || !path) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "checkpoint: no fields initialised"; return CFQMC_ESTATE; }
+  const int B = c->nch;
+  const long long cnt = (long long)B * c->L * 4 * c->nq;
+  std::vector<double> phi(cnt), eps(B), ser((size_t)B * std::max(c->series_len, 0));
+  std::vector<double2> al((size_t)B * 4);
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(phi.data(), c->phi, cnt * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(eps.data(), c->eps, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(al.data(), c->alpha, al.size() * sizeof(double2), hipMemcpyDeviceToHost));
+  for (int z = 0; z < B && c->series_len > 0; ++z)
+    HIPCHK(hipMemcpy(ser.data() + (size_t)z * c->series_len, c->series + (long long)z * c->series_cap,
+                     c->series_len * sizeof(double), hipMemcpyDeviceToHost));
+  CkptHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1; h.n_phi = c->N; h.l_tau = c->L; h.n_q = c->nq; h.n_chains = B; h.n_stab = c->nstab;
+  h.seed = c->p.seed; h.sweep_counter = c->sweep_counter; h.series_len = c->series_len;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) { c->err = std::string("checkpoint: cannot open ") + path; return CFQMC_EINVAL; }
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+            std::fwrite(phi.data(), sizeof(double), cnt, f) == (size_t)cnt &&
+            std::fwrite(eps.data(), sizeof(double), B, f) == (size_t)B &&
+            std::fwrite(al.data(), sizeof(double2), al.size(), f) == al.size() &&
+            std::fwrite(ser.data(), sizeof(double), ser.size(), f) == ser.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) { c->err = std::string("checkpoint: write failed on ") + path; return CFQMC_EINVAL; }
+  return CFQMC_OK;
+}
+
+int cfqmc_restore(cfqmc_ctx* c, const char* path) {
+  if (!c || !path) return CFQMC_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) { c->err = std::string("restore: cannot open ") + path; return CFQMC_EINVAL; }
+  CkptHeader h;
+  const int B = c->nch;
+  const long long cnt = (long long)B * c->L * 4 * c->nq;
+  bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 1;
+  if (ok && (h.n_phi != c->N || h.l_tau != c->L || h.n_q != c->nq || h.n_chains != B || h.series_len < 0 ||
+             h.series_len > c->series_cap)) {
+    std::fclose(f);
+    c->err = "restore: checkpoint shape differs from the context";
+    return CFQMC_EINVAL;
+  }
+  std::vector<double> phi(ok ? cnt : 0), eps(ok ? B : 0), ser(ok ? (size_t)B * h.series_len : 0);
+  std::vector<double2> al(ok ? (size_t)B * 4 : 0), al_ctx((size_t)B * 4);
+  ok = ok && std::fread(phi.data(), sizeof(double), cnt, f) == (size_t)cnt &&
+       std::fread(eps.data(), sizeof(double), B, f) == (size_t)B &&
+       std::fread(al.data(), sizeof(double2), al.size(), f) == al.size() &&
+       std::fread(ser.data(), sizeof(double), ser.size(), f) == ser.size();
+  std::fclose(f);
+  if (!ok) { c->err = std::string("restore: not a readable checkpoint: ") + path; return CFQMC_EINVAL; }
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(al_ctx.data(), c->alpha, al_ctx.size() * sizeof(double2), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < al.size(); ++i)
+    if (al[i].x != al_ctx[i].x || al[i].y != al_ctx[i].y) {
+      c->err = "restore: checkpoint couplings differ from the context";
+      return CFQMC_EINVAL;
+    }
+  for (long long i = 0; i < cnt; ++i)
+    if (!std::isfinite(phi[i])) { c->err = "restore: non-finite field"; return CFQMC_EINVAL; }
+  // the state is rebuilt from the fields (all slice propagators, UDT stacks,
+  // G(0) in FP64); eps, the RNG position and the series continue
+  const int rc = cfqmc_init_fields(c, phi.data());
+  if (rc != CFQMC_OK) return rc;
+  HIPCHK(hipMemcpy(c->eps, eps.data(), B * sizeof(double), hipMemcpyHostToDevice));
+  for (int z = 0; z < B && h.series_len > 0; ++z)
+    HIPCHK(hipMemcpy(c->series + (long long)z * c->series_cap, ser.data() + (size_t)z * h.series_len,
+                     h.series_len * sizeof(double), hipMemcpyHostToDevice));
+  c->series_len = h.series_len;
+  c->sweep_counter = h.sweep_counter;
+  c->p.seed = h.seed;
+  return CFQMC_OK;
+}
+
 }  // extern "C"
 
 namespace {

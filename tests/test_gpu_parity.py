@@ -228,3 +228,46 @@ def test_heterogeneous_batch_matches_standalone_contexts():
         off += kw["n_chains"]
         g.close()
     b.close()
+
+
+def test_checkpoint_restore_continues_the_chains(tmp_path):
+    """Two sweeps in one go vs one sweep, checkpoint, restore into a fresh
+    context, one sweep: same accept sequence (device noise continues from the
+    stored RNG position), same step sizes, fields within rounding (G is rebuilt
+    in FP64 at the restore), same m^2 series; malformed restores are refused
+    and leave the context usable."""
+    CFQMC = _gpu()
+    kw = dict(n_phi=6, l_tau=40, dtau=0.1, q_mode=Q_BZ, n_stab=10, n_chains=2, seed=5, eps0=0.4,
+              adapt_eps=True, tile_cfg=1, chain_u=[(1.0, 1.0, 1.0), (1.0, 2.0, 2.0)])
+    a = CFQMC(**kw)
+    a.init_fields(None)
+    a.sweep(2)
+    fa, ea, acc_a = a.get_fields(), a.get_eps(), [a.last_sweep(z)[0].tolist() for z in range(2)]
+    sa = [a.series(z) for z in range(2)]
+    a.close()
+    b = CFQMC(**kw)
+    with pytest.raises(RuntimeError):
+        b.checkpoint(str(tmp_path / "early.ck"))          # no fields yet
+    b.init_fields(None)
+    b.sweep(1)
+    path = str(tmp_path / "chains.ck")
+    b.checkpoint(path)
+    b.close()
+    c = CFQMC(**kw)
+    with pytest.raises(RuntimeError):
+        c.restore(str(tmp_path / "missing.ck"))
+    other = CFQMC(**dict(kw, l_tau=20))
+    with pytest.raises(RuntimeError):
+        other.restore(path)                               # shape differs
+    other.close()
+    c.restore(path)
+    c.sweep(1)
+    fc, ec = c.get_fields(), c.get_eps()
+    assert [c.last_sweep(z)[0].tolist() for z in range(2)] == acc_a
+    assert np.abs(fc - fa).max() < 1e-9
+    assert np.abs(ec - ea).max() < 1e-12
+    for z in range(2):
+        sc = c.series(z)
+        assert len(sc) == len(sa[z]) == 2
+        assert np.allclose(sc, sa[z], rtol=1e-8, atol=1e-12)
+    c.close()
