@@ -103,8 +103,10 @@ def _replay_compare(CFQMC, n_phi, L, nstab, mode, qmax, u_list, precision, n_swe
 
 
 def test_sweep_replay_parity_fp64_small():
+    """The N_phi = 6 workload: BZ momenta (36 components), L = 40, n_stab = 10,
+    u = 1, one chain, 20 sweeps of replayed noise, FP64."""
     CFQMC = _gpu()
-    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], 0, 3, 1e-10)
+    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], 0, 20, 1e-10)
     assert st[0]["max_stab_err"] < 1e-9 and st[0]["max_stab_rel"] <= st[0]["max_stab_err"] / 0.1
 
 
@@ -271,3 +273,36 @@ def test_checkpoint_restore_continues_the_chains(tmp_path):
         assert len(sc) == len(sa[z]) == 2
         assert np.allclose(sc, sa[z], rtol=1e-8, atol=1e-12)
     c.close()
+
+
+@pytest.mark.parametrize("n_phi,L,mode,qmax,nstab,u_list", [
+    (36, 200, Q_RADIUS, 3.0, 10, [0.5, 1.0, 1.5, 2.0, 2.5]),     # the N_phi = 36 workload, full size
+    (100, 400, Q_PAPER, None, 8, [1.5, 1.5]),                      # the N_phi = 100 shape, two chains
+])
+def test_full_size_invariants(n_phi, L, mode, qmax, nstab, u_list):
+    """At the workloads' full sizes (too large for the oracle's dense products):
+    the updated G equals the FP64 recomputation at every stabilisation point,
+    the weight stays sign-free, Re tr G_4N = 2 N_phi at every boundary checked,
+    G(beta) = G(0) (periodicity of the equal-time G), moves accepted."""
+    CFQMC = _gpu()
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=mode, q_max=qmax or 3.0, n_stab=nstab, eps0=0.3,
+              adapt_eps=True, precision=0, n_chains=len(u_list), seed=21,
+              chain_u=[(1.0, u, u) for u in u_list], tile_cfg=-1)
+    g.init_fields(None)
+    st = g.sweep(1)
+    for k, s in enumerate(st):
+        assert s["max_stab_rel"] < 1e-10, (k, s)        # the FP64 bar, relative in max norm
+        assert s["max_phase_err"] < 1e-6, (k, s)
+        assert 0 <= s["accepted"] <= s["proposed"] == L, (k, s)
+        G0 = g.measure_G(k, 0)
+        assert abs(np.trace(G0).real - 2 * n_phi) < 1e-9
+        assert abs(np.trace(g.measure_G(k, L // 2)).real - 2 * n_phi) < 1e-9
+        assert rel(g.measure_G(k, L), G0) < 1e-10
+        ld = g.logdet(k)
+        # ln w is real for the sign-free model: the imaginary background sum
+        # cancels the phase of det(1 + B)^2 up to rounding of O(1e3)-sized terms
+        assert np.isfinite(ld.real) and wrap_phase(ld.imag) < 1e-5
+    # the first sweep from N(0,1) fields is far from equilibrium: some chains
+    # may reject every move, the set as a whole must move
+    assert 0 < sum(s["accepted"] for s in st) < sum(s["proposed"] for s in st)
+    g.close()
