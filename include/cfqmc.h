@@ -148,8 +148,13 @@ int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im);
  * m^2_SO(5)), from G(l_tau) by Wick's theorem. */
 int cfqmc_observables(cfqmc_ctx* c, int32_t chain, double* s_q0, double* m2);
 
-/* Per-sweep series of m^2_SO(5) recorded at the end of every sweep since the
- * last init: writes up to max_len values, returns the count in *len. */
+/* Per-sweep series recorded at the end of every sweep since the last init (or
+ * continued by cfqmc_restore), for autocorrelation times: writes up to max_len
+ * values, returns the count in *len. which = 0: m^2_SO(5) (Results, order
+ * parameter); 1: the action S = |phi|^2/2 - ln w_F, ln w_F = sum_tau Re c_tau +
+ * 2 ln|det(1 + B(beta, 0))| (FP64 from the UDT stack); 2: the power of the q = 0
+ * fields, sum_i (sum_tau phi^i_{tau,0})^2 / L. cfqmc_series is which = 0. */
+int cfqmc_series_of(cfqmc_ctx* c, int32_t chain, int32_t which, double* out, int32_t max_len, int32_t* len);
 int cfqmc_series(cfqmc_ctx* c, int32_t chain, double* out, int32_t max_len, int32_t* len);
 
 /* Accept flags and ln A of every slice of the last sweep of one chain. */

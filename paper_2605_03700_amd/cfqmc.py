@@ -59,7 +59,7 @@ _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
            "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
-           "cfqmc_series", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
+           "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
            "cfqmc_slmc_create", "cfqmc_slmc_destroy", "cfqmc_slmc_sizes", "cfqmc_slmc_set_params",
@@ -92,6 +92,8 @@ def load():
     lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_observables.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_series.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_series_of.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32)]
     lib.cfqmc_last_sweep.argtypes = [P, ctypes.c_int32, P, P]
     lib.cfqmc_get_eps.argtypes = [P, P]
     lib.cfqmc_set_eps.argtypes = [P, P]
@@ -266,10 +268,14 @@ class CFQMC:
         self._check(self.lib.cfqmc_observables(self.h, chain, _ptr(s), ctypes.byref(m2)))
         return s, m2.value
 
-    def series(self, chain=0, max_len=1 << 16):
+    SERIES = {"m2": 0, "action": 1, "phi_q0_power": 2}
+
+    def series(self, chain=0, which="m2", max_len=1 << 16):
+        """Per-sweep series: "m2" (m^2_SO(5)), "action" (|phi|^2/2 - ln w_F) or
+        "phi_q0_power" (power of the q = 0 fields)."""
         out = np.empty(max_len)
         ln = ctypes.c_int32()
-        self._check(self.lib.cfqmc_series(self.h, chain, _ptr(out), max_len, ctypes.byref(ln)))
+        self._check(self.lib.cfqmc_series_of(self.h, chain, self.SERIES[which], _ptr(out), max_len, ctypes.byref(ln)))
         return out[:ln.value].copy()
 
     def last_sweep(self, chain=0):

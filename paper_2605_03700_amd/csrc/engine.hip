@@ -232,7 +232,11 @@ struct cfqmc_ctx {
   double* part;
   double* obs;
   double* stab_err;
-  double* series;
+  double* series;     // [chain][series_cap] m^2_SO(5) per sweep
+  double* series_s;   // action S = |phi|^2/2 - ln w_F per sweep
+  double* series_p;   // power of the q = 0 fields per sweep
+  double *fsq, *fq0;  // per-chain field sums of the current sweep
+  double2* ldY2;      // ln det Y of the sweep-end weight
   int series_cap, series_len;
   int* hist_acc;
   double* hist_lnA;
@@ -845,6 +849,11 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->stab_err, (size_t)B * 4);
   c->series_cap = 1 << 16;
   rc |= dalloc(c, &c->series, (size_t)B * c->series_cap);
+  rc |= dalloc(c, &c->series_s, (size_t)B * c->series_cap);
+  rc |= dalloc(c, &c->series_p, (size_t)B * c->series_cap);
+  rc |= dalloc(c, &c->fsq, (size_t)B);
+  rc |= dalloc(c, &c->fq0, (size_t)B);
+  rc |= dalloc(c, &c->ldY2, (size_t)B);
   rc |= dalloc(c, &c->hist_acc, (size_t)B * L);
   rc |= dalloc(c, &c->hist_lnA, (size_t)B * L);
   rc |= dalloc(c, &c->noise, (size_t)B * L * (4 * nq + 1));
@@ -955,7 +964,8 @@ int cfqmc_get_fields(cfqmc_ctx* c, double* phi_out) {
 }
 
 // Checkpoint file: header, then fields [B][L][4][n_q], eps [B], couplings
-// alpha [B][4] (complex), series [B][series_len]; all FP64, native byte order.
+// alpha [B][4] (complex), the three series (m^2, action, q = 0 power) each
+// [B][series_len]; all FP64, native byte order.
 struct CkptHeader {
   char magic[8];
   int32_t version, n_phi, l_tau, n_q, n_chains, n_stab;
@@ -970,19 +980,22 @@ int cfqmc_checkpoint(cfqmc_ctx* c, const char* path) {
   if (!c->ready) { c->err = "checkpoint: no fields initialised"; return CFQMC_ESTATE; }
   const int B = c->nch;
   const long long cnt = (long long)B * c->L * 4 * c->nq;
-  std::vector<double> phi(cnt), eps(B), ser((size_t)B * std::max(c->series_len, 0));
+  const size_t ns = (size_t)B * std::max(c->series_len, 0);
+  std::vector<double> phi(cnt), eps(B), ser(3 * ns);
   std::vector<double2> al((size_t)B * 4);
+  const double* srcs[3] = {c->series, c->series_s, c->series_p};
   HIPCHK(hipStreamSynchronize(c->s));
   HIPCHK(hipMemcpy(phi.data(), c->phi, cnt * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(eps.data(), c->eps, B * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(al.data(), c->alpha, al.size() * sizeof(double2), hipMemcpyDeviceToHost));
-  for (int z = 0; z < B && c->series_len > 0; ++z)
-    HIPCHK(hipMemcpy(ser.data() + (size_t)z * c->series_len, c->series + (long long)z * c->series_cap,
-                     c->series_len * sizeof(double), hipMemcpyDeviceToHost));
+  for (int w = 0; w < 3; ++w)
+    for (int z = 0; z < B && c->series_len > 0; ++z)
+      HIPCHK(hipMemcpy(ser.data() + w * ns + (size_t)z * c->series_len, srcs[w] + (long long)z * c->series_cap,
+                       c->series_len * sizeof(double), hipMemcpyDeviceToHost));
   CkptHeader h;
   memset(&h, 0, sizeof(h));
   memcpy(h.magic, kCkptMagic, 8);
-  h.version = 1; h.n_phi = c->N; h.l_tau = c->L; h.n_q = c->nq; h.n_chains = B; h.n_stab = c->nstab;
+  h.version = 2; h.n_phi = c->N; h.l_tau = c->L; h.n_q = c->nq; h.n_chains = B; h.n_stab = c->nstab;
   h.seed = c->p.seed; h.sweep_counter = c->sweep_counter; h.series_len = c->series_len;
   FILE* f = std::fopen(path, "wb");
   if (!f) { c->err = std::string("checkpoint: cannot open ") + path; return CFQMC_EINVAL; }
@@ -1003,14 +1016,15 @@ int cfqmc_restore(cfqmc_ctx* c, const char* path) {
   CkptHeader h;
   const int B = c->nch;
   const long long cnt = (long long)B * c->L * 4 * c->nq;
-  bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 1;
+  bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 2;
   if (ok && (h.n_phi != c->N || h.l_tau != c->L || h.n_q != c->nq || h.n_chains != B || h.series_len < 0 ||
              h.series_len > c->series_cap)) {
     std::fclose(f);
     c->err = "restore: checkpoint shape differs from the context";
     return CFQMC_EINVAL;
   }
-  std::vector<double> phi(ok ? cnt : 0), eps(ok ? B : 0), ser(ok ? (size_t)B * h.series_len : 0);
+  const size_t ns = ok ? (size_t)B * h.series_len : 0;
+  std::vector<double> phi(ok ? cnt : 0), eps(ok ? B : 0), ser(3 * ns);
   std::vector<double2> al(ok ? (size_t)B * 4 : 0), al_ctx((size_t)B * 4);
   ok = ok && std::fread(phi.data(), sizeof(double), cnt, f) == (size_t)cnt &&
        std::fread(eps.data(), sizeof(double), B, f) == (size_t)B &&
@@ -1032,9 +1046,11 @@ int cfqmc_restore(cfqmc_ctx* c, const char* path) {
   const int rc = cfqmc_init_fields(c, phi.data());
   if (rc != CFQMC_OK) return rc;
   HIPCHK(hipMemcpy(c->eps, eps.data(), B * sizeof(double), hipMemcpyHostToDevice));
-  for (int z = 0; z < B && h.series_len > 0; ++z)
-    HIPCHK(hipMemcpy(c->series + (long long)z * c->series_cap, ser.data() + (size_t)z * h.series_len,
-                     h.series_len * sizeof(double), hipMemcpyHostToDevice));
+  double* dsts[3] = {c->series, c->series_s, c->series_p};
+  for (int w = 0; w < 3; ++w)
+    for (int z = 0; z < B && h.series_len > 0; ++z)
+      HIPCHK(hipMemcpy(dsts[w] + (long long)z * c->series_cap, ser.data() + w * ns + (size_t)z * h.series_len,
+                       h.series_len * sizeof(double), hipMemcpyHostToDevice));
   c->series_len = h.series_len;
   c->sweep_counter = h.sweep_counter;
   c->p.seed = h.seed;
@@ -1061,12 +1077,25 @@ void sweep_end(cfqmc_ctx* c) {
   launch_eps_update(c->eps, c->acc_count, c->L, c->p.r0, c->p.deps, c->p.eps_min, c->p.eps_max, c->p.adapt_eps, B,
                     c->s);
   launch_observables(c->G, c->nn, c->N, 1.0 / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, B, c->s);
+  restack_right(c);
   if (c->series_len < c->series_cap) {
-    hipMemcpy2DAsync(c->series + c->series_len, c->series_cap * sizeof(double), c->obs + 5, 8 * sizeof(double),
+    // per-sweep series for the autocorrelation: m^2_SO(5), the action and the
+    // q = 0 field power (ln w_F from the fresh right stack, as cfqmc_logdet)
+    const int k = c->series_len;
+    hipMemcpy2DAsync(c->series + k, c->series_cap * sizeof(double), c->obs + 5, 8 * sizeof(double),
                      sizeof(double), B, hipMemcpyDeviceToDevice, c->s);
+    const long long nn = c->nn, sU = sU_(c), sD = sD_(c);
+    green_udt(c, 0, 0, c->Gs);   // ln det Y in ldtmp
+    launch_copy((const double2*)c->ldtmp, c->ldY2, 1, 1, 1, B, c->s);
+    launch_copy(c->Rs.U, c->Q2, nn, sU, nn, B, c->s);
+    launch_lu(c->Q2, c->n, c->n, nn, c->ipiv, c->n, c->ldtmp, 1, B, c->s);
+    launch_sum_log_dmax(c->Rs.D, sD, c->n, c->tmpd, B, c->s);
+    launch_background(c->md, c->phi, (long long)c->L * 4 * c->nq, c->alpha, c->bg, B, c->s);
+    launch_field_sums(c->phi, (long long)c->L * 4 * c->nq, c->L, c->nq, c->fsq, c->fq0, B, c->s);
+    launch_action_series(c->ldY2, c->ldtmp, c->tmpd, c->bg, c->fsq, c->fq0, c->series_s, c->series_p,
+                         c->series_cap, k, B, c->s);
     c->series_len++;
   }
-  restack_right(c);
   c->sweep_counter++;
 }
 
@@ -1256,13 +1285,18 @@ int cfqmc_observables(cfqmc_ctx* c, int32_t chain, double* s_q0, double* m2) {
   return CFQMC_OK;
 }
 
-int cfqmc_series(cfqmc_ctx* c, int32_t chain, double* out, int32_t max_len, int32_t* len) {
-  if (!c || chain < 0 || chain >= c->nch || !out || max_len < 0) return CFQMC_EINVAL;
+int cfqmc_series_of(cfqmc_ctx* c, int32_t chain, int32_t which, double* out, int32_t max_len, int32_t* len) {
+  if (!c || chain < 0 || chain >= c->nch || !out || max_len < 0 || which < 0 || which > 2) return CFQMC_EINVAL;
+  const double* src = which == 0 ? c->series : which == 1 ? c->series_s : c->series_p;
   const int k = std::min(max_len, c->series_len);
   HIPCHK(hipStreamSynchronize(c->s));
-  if (k > 0) HIPCHK(hipMemcpy(out, c->series + (long long)chain * c->series_cap, k * sizeof(double), hipMemcpyDeviceToHost));
+  if (k > 0) HIPCHK(hipMemcpy(out, src + (long long)chain * c->series_cap, k * sizeof(double), hipMemcpyDeviceToHost));
   if (len) *len = k;
   return CFQMC_OK;
+}
+
+int cfqmc_series(cfqmc_ctx* c, int32_t chain, double* out, int32_t max_len, int32_t* len) {
+  return cfqmc_series_of(c, chain, 0, out, max_len, len);
 }
 
 int cfqmc_last_sweep(cfqmc_ctx* c, int32_t chain, int32_t* accepted, double* ln_a) {

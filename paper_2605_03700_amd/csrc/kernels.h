@@ -174,6 +174,13 @@ void launch_observables(const double2* G, long long sG, int N, double F0, double
 // background sum over slices: c[chain] = sum_tau alpha0 * phi0 . beta
 void launch_background(const ModelDev& m, const double* phi, long long sphi_chain, const double2* alpha,
                        double2* out, int nchain, hipStream_t s);
+// per chain |phi|^2 and the q = 0 power sum_i (sum_tau phi^i_{tau,0})^2 / L
+void launch_field_sums(const double* phi, long long sphi, int L, int nq, double* sq, double* q0, int nchain,
+                       hipStream_t s);
+// series entry k: S = |phi|^2/2 - ln w_F from the UDT pieces, and the q = 0 power
+void launch_action_series(const double2* ldY, const double2* ldU, const double* sdm, const double2* bg,
+                          const double* sq, const double* q0, double* ser_s, double* ser_p, long long cap, int k,
+                          int nchain, hipStream_t s);
 // 4N expansion of the spin block
 void launch_expand4n(const double2* G, int n, double2* G4, hipStream_t s);
 

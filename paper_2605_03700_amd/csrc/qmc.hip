@@ -495,6 +495,55 @@ void launch_background(const ModelDev& m, const double* phi, long long sphi_chai
   hipLaunchKernelGGL(background_kernel, dim3(nchain), dim3(256), 0, s, m, phi, sphi_chain, alpha, out); cfqmc_post_launch("background_kernel");
 }
 
+// Per chain: |phi|^2 (all fields) and the power of the q = 0 components,
+// sum_i (sum_tau phi^i_{tau,0})^2 / L. One workgroup per chain.
+__global__ void __launch_bounds__(256) field_sums_kernel(const double* phi_all, long long sphi, int L, int nq,
+                                                         double* sq, double* q0) {
+  __shared__ double red[4];
+  const int z = blockIdx.x;
+  const double* phi = phi_all + z * sphi;
+  const long long cnt = (long long)L * 4 * nq;
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < cnt; i += 256) s += phi[i] * phi[i];
+  s = block_sum<256>(s, red);
+  double p = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    double m = 0.0;
+    for (int t = threadIdx.x; t < L; t += 256) m += phi[(long long)t * 4 * nq + (long long)i * nq];
+    m = block_sum<256>(m, red);
+    p += m * m;
+  }
+  if (threadIdx.x == 0) {
+    sq[z] = s;
+    q0[z] = p / L;
+  }
+}
+void launch_field_sums(const double* phi, long long sphi, int L, int nq, double* sq, double* q0, int nchain,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(field_sums_kernel, dim3(nchain), dim3(256), 0, s, phi, sphi, L, nq, sq, q0);
+  cfqmc_post_launch("field_sums_kernel");
+}
+
+// Action S = |phi|^2 / 2 - ln w_F with ln w_F = 2 ln|det(1 + B)| + Re sum_tau c_tau,
+// ln|det(1 + B)| = ln|det Y| + sum ln D_R^max - ln|det U_R| (UDT form); written
+// with the q = 0 power to entry k of the per-chain series.
+__global__ void action_series_kernel(const double2* ldY, const double2* ldU, const double* sdm, const double2* bg,
+                                     const double* sq, const double* q0, double* ser_s, double* ser_p,
+                                     long long cap, int k, int nchain) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nchain) return;
+  const double lnw = 2.0 * (ldY[z].x + sdm[z] - ldU[z].x) + bg[z].x;
+  ser_s[z * cap + k] = 0.5 * sq[z] - lnw;
+  ser_p[z * cap + k] = q0[z];
+}
+void launch_action_series(const double2* ldY, const double2* ldU, const double* sdm, const double2* bg,
+                          const double* sq, const double* q0, double* ser_s, double* ser_p, long long cap, int k,
+                          int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(action_series_kernel, dim3((nchain + 63) / 64), dim3(64), 0, s, ldY, ldU, sdm, bg, sq, q0,
+                     ser_s, ser_p, cap, k, nchain);
+  cfqmc_post_launch("action_series_kernel");
+}
+
 __global__ void expand4n_kernel(const double2* G, int n, double2* G4) {
   const int n4 = 2 * n;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n4 * n4; idx += gridDim.x * blockDim.x) {

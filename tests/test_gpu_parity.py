@@ -306,3 +306,24 @@ def test_full_size_invariants(n_phi, L, mode, qmax, nstab, u_list):
     # may reject every move, the set as a whole must move
     assert 0 < sum(s["accepted"] for s in st) < sum(s["proposed"] for s in st)
     g.close()
+
+
+def test_autocorrelation_series_match_their_definitions():
+    """The per-sweep series used for tau_int: after each sweep the action entry
+    is |phi|^2/2 - ln w_F of the current fields (ln w_F as cfqmc_logdet) and
+    the q = 0 power entry is sum_i (sum_tau phi^i_{tau,0})^2 / L."""
+    CFQMC = _gpu()
+    g = CFQMC(n_phi=8, l_tau=24, dtau=0.1, u0=1.0, uk=1.5, un=1.5, q_mode=Q_RADIUS, q_max=3.0, n_stab=6,
+              n_chains=3, tile_cfg=1, seed=13, eps0=0.4)
+    g.init_fields(None)
+    for sw in range(3):
+        g.sweep(1)
+        phi = g.get_fields()
+        for z in range(3):
+            s_act, s_q0, s_m2 = g.series(z, "action"), g.series(z, "phi_q0_power"), g.series(z, "m2")
+            assert len(s_act) == len(s_q0) == len(s_m2) == sw + 1
+            want = 0.5 * np.sum(phi[z] ** 2) - g.logdet(z).real
+            assert abs(s_act[-1] - want) < 1e-9 * max(1.0, abs(want)), (sw, z)
+            q0 = sum(np.sum(phi[z][:, i, 0]) ** 2 for i in range(4)) / 24
+            assert abs(s_q0[-1] - q0) < 1e-12 * max(1.0, q0), (sw, z)
+    g.close()
