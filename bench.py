@@ -6,8 +6,9 @@ channel), L = 400 slices of dtau = 0.1, u = 1.5 on the SO(5) line, FP64
 recomputation every 8 slices, complex FP32 MFMA wraps with FP64 accumulation
 (--precision fp64 for the all-FP64 path). A step is one sweep of every chain:
 L Langevin slice moves of 4 n_q fields each, with wraps, Woodbury updates and
-stabilisation. After the timed sweeps: tau_int of m^2_SO(5) over untimed
-sweeps, (with --fp64-compare) the same chains with every product in FP64, a
+stabilisation. After the timed sweeps: tau_int (the largest of m^2_SO(5), the
+action and the q = 0 field power, autocorrelations pooled over the chains)
+over untimed sweeps, (with --fp64-compare) the same chains with every product in FP64, a
 one-chain FP64 reference sweep, and the FP64 oracle on the host.
 --workload batched and --workload learned run the other two workloads.
 
@@ -111,7 +112,7 @@ def main():
     ap.add_argument("--learned-sweeps", type=int, default=12)
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--tile-cfg", type=int, default=-1)
-    ap.add_argument("--tau-sweeps", type=int, default=10, help="untimed sweeps after the timed ones for tau_int")
+    ap.add_argument("--tau-sweeps", type=int, default=20, help="untimed sweeps after the timed ones for tau_int")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-chain FP64 reference sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-compare", action="store_true",
@@ -139,7 +140,7 @@ def main():
     import numpy as np
     import torch
     from paper_2605_03700_amd import Batch, FP64, MIXED, MIXED_ALL
-    from paper_2605_03700_amd.analysis import tau_int
+    from paper_2605_03700_amd.analysis import tau_int_pooled
     assert torch.cuda.is_available(), "needs the GPU"
     prec = {"fp64": FP64, "mixed": MIXED, "mixed_all": MIXED_ALL}[args.precision]
     if args.workload == "batched":
@@ -214,12 +215,12 @@ def main():
         taus = {}
         for obs in ("m2", "action", "phi_q0_power"):
             series = [q.series(k, obs)[n0[i]:] for i, q in enumerate(b.groups) for k in range(nper)]
-            taus[obs] = float(np.mean([tau_int(x)[0] for x in series]))
+            taus[obs] = float(tau_int_pooled(series)[0])
         tau = max(taus.values())
         out["tau_int_sweeps"] = tau
         out["tau_int_per_observable"] = taus
-        out["tau_int_observable"] = ("max over m2_SO(5), the action S and the q = 0 field power of the mean over "
-                                     "chains of %d-sweep series" % args.tau_sweeps)
+        out["tau_int_observable"] = ("max over m2_SO(5), the action S and the q = 0 field power; autocorrelation "
+                                     "pooled over the %d chains' %d-sweep series" % (args.chains, args.tau_sweeps))
         out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
         progress("tau_int sweeps done")
     b.close()

@@ -36,6 +36,31 @@ def tau_int(x, c=5.0):
     return max(tau, 0.5), n - 1
 
 
+def tau_int_pooled(series, c=5.0):
+    """tau_int of many short, equally long series of one observable from
+    independent chains of one ensemble: deviations from the ensemble mean
+    (per-chain means would bias short series low), autocovariance at lag t
+    averaged over chains and over the n - t pairs of each, then normalised and
+    windowed as in tau_int. Returns (tau_int, window)."""
+    xs = [np.asarray(x, dtype=float) for x in series if len(x) > 1]
+    if not xs:
+        return 0.5, 0
+    n = min(x.size for x in xs)
+    X = np.stack([x[:n] for x in xs])
+    Y = X - X.mean()
+    f = np.fft.rfft(Y, 2 * n, axis=1)
+    acc = np.fft.irfft(f * np.conj(f), axis=1)[:, :n].sum(axis=0) / (n - np.arange(n))
+    if acc[0] <= 0:
+        return 0.5, 0
+    rho = acc / acc[0]
+    tau = 0.5
+    for w in range(1, n):
+        tau += rho[w]
+        if w >= c * tau:
+            return max(tau, 0.5), w
+    return max(tau, 0.5), n - 1
+
+
 def independent_samples_per_s(sweeps_per_s, series_list):
     """sweeps/s divided by 2 tau_int, tau_int the maximum over the given series."""
     taus = [tau_int(s)[0] for s in series_list if len(s) > 1]

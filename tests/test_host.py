@@ -82,3 +82,22 @@ def test_product_path_has_no_oracle_import():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "oracle" not in re.findall(r"^\s*(?:from|import)\s+(\w+)", src, re.M), fn
+
+
+def test_tau_int_pooled_ar1_many_short_chains():
+    """Pooled over 400 independent AR(1) chains of 40 steps the estimator
+    recovers (1+r)/(2(1-r)) up to the bias of per-chain means (O(tau/n))."""
+    from paper_2605_03700_amd.analysis import tau_int_pooled
+    rng = np.random.default_rng(3)
+    r = 0.5
+    chains = []
+    for _ in range(400):
+        x = np.empty(40)
+        x[0] = rng.standard_normal() / np.sqrt(1 - r * r)
+        for t in range(1, 40):
+            x[t] = r * x[t - 1] + rng.standard_normal()
+        chains.append(x)
+    tau, _ = tau_int_pooled(chains)
+    assert abs(tau - 1.5) < 0.25
+    w, _ = tau_int_pooled([rng.standard_normal(40) for _ in range(400)])
+    assert abs(w - 0.5) < 0.1
