@@ -211,16 +211,26 @@ def main():
     tau = None
     if args.tau_sweeps > 0:
         n0 = [len(q.series(0)) for q in b.groups]
-        dt2, _, _ = sweep_each(b, args.tau_sweeps)
-        taus = {}
+        dt2, _, g_err2 = sweep_each(b, args.tau_sweeps)
+        out["g_err_max_later_sweeps"] = max(g_err2)
+        out["g_err_per_later_sweep"] = g_err2
+        taus, open_w = {}, []
         for obs in ("m2", "action", "phi_q0_power"):
             series = [q.series(k, obs)[n0[i]:] for i, q in enumerate(b.groups) for k in range(nper)]
-            taus[obs] = float(tau_int_pooled(series)[0])
+            t_o, _, closed = tau_int_pooled(series)
+            taus[obs] = float(t_o)
+            if not closed:
+                open_w.append(obs)
         tau = max(taus.values())
         out["tau_int_sweeps"] = tau
         out["tau_int_per_observable"] = taus
         out["tau_int_observable"] = ("max over m2_SO(5), the action S and the q = 0 field power; autocorrelation "
-                                     "pooled over the %d chains' %d-sweep series" % (args.chains, args.tau_sweeps))
+                                     "pooled over the %d chains' %d-sweep series, deviations from the per-sweep "
+                                     "ensemble mean" % (args.chains, args.tau_sweeps))
+        # an open window means the series is shorter than that observable's
+        # autocorrelation: tau_int is then a lower bound and the rate an upper one
+        out["tau_int_window_open"] = open_w
+        out["tau_int_is_lower_bound"] = bool(open_w)
         out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
         progress("tau_int sweeps done")
     b.close()

@@ -86,7 +86,7 @@ def test_product_path_has_no_oracle_import():
 
 def test_tau_int_pooled_ar1_many_short_chains():
     """Pooled over 400 independent AR(1) chains of 40 steps the estimator
-    recovers (1+r)/(2(1-r)) up to the bias of per-chain means (O(tau/n))."""
+    recovers (1+r)/(2(1-r)); white noise gives 1/2."""
     from paper_2605_03700_amd.analysis import tau_int_pooled
     rng = np.random.default_rng(3)
     r = 0.5
@@ -97,7 +97,36 @@ def test_tau_int_pooled_ar1_many_short_chains():
         for t in range(1, 40):
             x[t] = r * x[t - 1] + rng.standard_normal()
         chains.append(x)
-    tau, _ = tau_int_pooled(chains)
-    assert abs(tau - 1.5) < 0.25
-    w, _ = tau_int_pooled([rng.standard_normal(40) for _ in range(400)])
-    assert abs(w - 0.5) < 0.1
+    tau, _, closed = tau_int_pooled(chains)
+    assert closed and abs(tau - 1.5) < 0.25
+    w, _, closed = tau_int_pooled([rng.standard_normal(40) for _ in range(400)])
+    assert closed and abs(w - 0.5) < 0.1
+
+
+def test_tau_int_pooled_removes_a_shared_drift_and_flags_short_series():
+    """A relaxation common to all chains (x_t = a e^{-t/5} + AR(1) noise, the
+    same a for every chain) does not enter tau_int; a series much shorter
+    than its autocorrelation time reports an open window (a lower bound)."""
+    from paper_2605_03700_amd.analysis import tau_int_pooled
+    rng = np.random.default_rng(4)
+    r, n = 0.5, 40
+    drift = 10.0 * np.exp(-np.arange(n) / 5.0)
+    chains = []
+    for _ in range(400):
+        x = np.empty(n)
+        x[0] = rng.standard_normal() / np.sqrt(1 - r * r)
+        for t in range(1, n):
+            x[t] = r * x[t - 1] + rng.standard_normal()
+        chains.append(x + drift)
+    tau, _, closed = tau_int_pooled(chains)
+    assert closed and abs(tau - 1.5) < 0.25
+    # r = 0.98: tau_int = 49.5 steps, far beyond 20-step series
+    slow = []
+    for _ in range(200):
+        x = np.empty(20)
+        x[0] = rng.standard_normal() / np.sqrt(1 - 0.98 ** 2)
+        for t in range(1, 20):
+            x[t] = 0.98 * x[t - 1] + rng.standard_normal()
+        slow.append(x)
+    tau, w, closed = tau_int_pooled(slow)
+    assert not closed and w == 19 and tau < 49.5
