@@ -6,6 +6,8 @@ Per-configuration quantities are their plain definitions (Methods,
   B(tau2, tau1) = B_tau2 ... B_{tau1+1}
   w(phi) = exp(-S_0) exp(sum_tau c_tau) det(1 + B(beta,0))^2   (two spins)
   G(tau) = (1 + B(tau,0) B(beta,tau))^{-1}     (eq. green function)
+  G(tau,0) = B(tau,0) G(0),  G(0,tau) = -(1 - G(0)) B(tau,0)^{-1}
+                                               (time-displaced, Suppl. Note 2)
 computed with dense products, inverses and LAPACK determinants.
 
 The Markov chain follows the Methods section "Langevin-based global update
@@ -61,6 +63,36 @@ def green(model: Model, phi, tau, Bs=None):
         Bs = propagators(model, phi)
     A = b_range(Bs, tau, 0, n) @ b_range(Bs, L, tau, n)
     return np.linalg.inv(np.eye(n) + A)
+
+
+def b_range_inv(model: Model, phi, t2, t1):
+    """B(t2, t1)^{-1} = B_{t1+1}^{-1} ... B_{t2}^{-1}, each slice inverse the
+    product of the channel exponentials exp(-V_i) in reverse order."""
+    n = model.n
+    out = np.eye(n, dtype=complex)
+    for t in range(t1 + 1, t2 + 1):
+        _, Einv = slice_exps(model, phi[t - 1])
+        out = out @ (Einv[3] @ Einv[2] @ Einv[1] @ Einv[0])
+    return out
+
+
+def green_displaced(model: Model, phi, tau, Bs=None):
+    """Time-displaced Green's functions of one configuration, 0 <= tau <= L
+    (spin block), from their definitions with G(0) = (1 + B(beta,0))^{-1}:
+      G(tau,0) = <c(tau) c^dagger(0)>           = B(tau,0) G(0)
+      G(0,tau) = -<c^dagger(tau) c(0)> (as [i,j]: -<c_j^dagger(tau) c_i(0)>)
+               = -(1 - G(0)) B(tau,0)^{-1}
+      G(tau,tau) = (1 + B(tau,0) B(beta,tau))^{-1}
+    The imaginary-time correlator of the SO(5) order parameter (Supplementary
+    Note 2) is built from these by Wick's theorem. Returns the three."""
+    n, L = model.n, model.l_tau
+    if Bs is None:
+        Bs = propagators(model, phi)
+    G0 = green(model, phi, 0, Bs)
+    Gt0 = b_range(Bs, tau, 0, n) @ G0
+    G0t = -(np.eye(n) - G0) @ b_range_inv(model, phi, tau, 0)
+    Gtt = green(model, phi, tau, Bs)
+    return Gt0, G0t, Gtt
 
 
 def green_4n(G):

@@ -4,6 +4,14 @@ S^i_q = <n^{Gamma^i}_q n^{Gamma^i}_{-q}> and
 m^2_SO(5) = (1/(5 N^2)) sum_{i=1}^5 S^i_{q=0} (Results, SO(5)-symmetric line),
 evaluated per configuration by Wick's theorem from G_ij = <c_i c_j^dagger>:
   <(c+ A c)(c+ B c)> = Tr[A(1-G)] Tr[B(1-G)] + Tr[A G B (1-G)].
+
+Imaginary-time correlator (Supplementary Note 2):
+  m^2_SO(5)(tau, q=0) = (1/5) sum_i <n^{Gamma^i}_{q=0}(tau) n^{Gamma^i}_{q=0}(0)>,
+with, for one-body operators A at tau and B at 0 (Wick, one configuration),
+  <(c+ A c)(tau) (c+ B c)(0)> = Tr[A(1-G(tau,tau))] Tr[B(1-G(0,0))]
+                               - Tr[A G(tau,0) B G(0,tau)],
+G(tau,0) = <c(tau) c^dagger(0)>, G(0,tau)_ij = -<c_j^dagger(tau) c_i(0)>; at
+tau = 0, G(0,0^-) = -(1 - G) and the equal-time formula is recovered.
 """
 import numpy as np
 
@@ -33,3 +41,26 @@ def so5_observables(G2n, n_phi):
     """Returns (S^1..S^5 at q=0, m^2_SO(5)) for one configuration."""
     s = np.array([structure_factor(G2n, n_phi, gm) for gm in gamma_matrices()])
     return s, s.real.sum() / (5.0 * n_phi * n_phi)
+
+
+def _density_4n(gamma, n_phi, qx=0, qy=0):
+    perm = [0, 2, 1, 3]
+    g = gamma[np.ix_(perm, perm)]
+    return np.kron(g, m_matrix(qx, qy, n_phi))
+
+
+def so5_correlator(Gt0, G0t, Gtt, G00, n_phi):
+    """<n^{Gamma^i}_{q=0}(tau) n^{Gamma^i}_{q=0}(0)> for i = 1..5 (complex, one
+    configuration) and their mean m^2_SO(5)(tau, q=0), from the spin-block
+    Green's functions G(tau,0), G(0,tau), G(tau,tau) and G(0,0)."""
+    E = np.eye(2)
+    Xt0, X0t = np.kron(E, Gt0), np.kron(E, G0t)
+    Xtt, X00 = np.kron(E, Gtt), np.kron(E, G00)
+    I = np.eye(4 * n_phi)
+    c = []
+    for gm in gamma_matrices():
+        A = _density_4n(gm, n_phi)
+        B = A.conj().T                     # n_{-q} at q = 0
+        c.append(np.trace(A @ (I - Xtt)) * np.trace(B @ (I - X00)) - np.trace(A @ Xt0 @ B @ X0t))
+    c = np.array(c)
+    return c, c.sum() / 5.0

@@ -301,6 +301,101 @@ def test_observables_fock_expectation():
     assert m2 > 0
 
 
+def _fock_slices(m, phi, cs):
+    """Fock-space propagators of the slices, B_tau = prod_i exp(alpha_i sum_c
+    phi^i_c Q^i_c) in channel order 0..3, from the second-quantised
+    components (sum-of-squares equation); list index tau - 1."""
+    Qops = [fock.component_operators(cs, m.n_phi, m.comps, PAULI[i], i == 0) for i in range(4)]
+    dim = cs[0].shape[0]
+    out = []
+    for t in range(m.l_tau):
+        Bt = np.eye(dim, dtype=complex)
+        for i in range(4):
+            Bt = Bt @ sla.expm(m.alpha[i] * sum(phi[t, i, c] * Qops[i][c] for c in range(m.n_q)))
+        out.append(Bt)
+    return out
+
+
+def _fock_range(Bf, t2, t1):
+    out = np.eye(Bf[0].shape[0], dtype=complex)
+    for t in range(t1 + 1, t2 + 1):
+        out = Bf[t - 1] @ out
+    return out
+
+
+@pytest.mark.parametrize("tau", [0, 1, 2, 3])
+def test_displaced_green_fock(tau):
+    """G(tau,0)_ij = Tr[B(beta,tau) c_i B(tau,0) c_j^+] / Tr B(beta,0) and
+    G(0,tau)_ij = -Tr[B(beta,tau) c_j^+ B(tau,0) c_i] / Tr B(beta,0) in Fock
+    space (8 modes, 256 states) against the oracle's single-particle formulas,
+    with G_4N = 1_spin kron G (Supplementary Note 2 needs both)."""
+    n, L = 2, 3
+    m = Model(n, L, 0.1, u0=1.0, uk=1.3, un=0.8)
+    cs = fock.annihilators(4 * n)
+    phi = synth.fields(61, L, m.n_q)
+    Bf = _fock_slices(m, phi, cs)
+    left, right = _fock_range(Bf, L, tau), _fock_range(Bf, tau, 0)
+    Z = np.trace(left @ right)
+    Gt0, G0t, Gtt = dqmc.green_displaced(m, phi, tau)
+    E = np.eye(2)
+    X, Y, W = np.kron(E, Gt0), np.kron(E, G0t), np.kron(E, Gtt)
+    for i in range(4 * n):
+        for j in range(4 * n):
+            a = np.trace(left @ cs[i] @ right @ cs[j].T) / Z
+            b = -np.trace(left @ cs[j].T @ right @ cs[i]) / Z
+            c = np.trace(left @ right @ cs[i] @ cs[j].T) / Z if tau == 0 else \
+                np.trace(left @ cs[i] @ cs[j].T @ right) / Z
+            assert abs(a - X[i, j]) < 1e-12
+            assert abs(b - Y[i, j]) < 1e-12
+            assert abs(c - W[i, j]) < 1e-12
+
+
+@pytest.mark.parametrize("tau", [1, 2])
+def test_so5_correlator_fock(tau):
+    """<n^{Gamma^i}_{q=0}(tau) n^{Gamma^i}_{q=0}(0)> = Tr[B(beta,tau) n B(tau,0) n]
+    / Tr B(beta,0) with the density operators of the printed second-quantised
+    formula (Supplementary Note 2), against the Wick evaluation."""
+    from oracle.model import gamma_matrices
+    from oracle.observables import so5_correlator
+    n, L = 2, 3
+    m = Model(n, L, 0.1, u0=1.0, uk=1.1, un=1.1)
+    cs = fock.annihilators(4 * n)
+    phi = synth.fields(62, L, m.n_q)
+    Bf = _fock_slices(m, phi, cs)
+    left, right = _fock_range(Bf, L, tau), _fock_range(Bf, tau, 0)
+    Z = np.trace(left @ right)
+    Gt0, G0t, Gtt = dqmc.green_displaced(m, phi, tau)
+    G00 = dqmc.green(m, phi, 0)
+    c, m2 = so5_correlator(Gt0, G0t, Gtt, G00, n)
+    ex = []
+    for gm in gamma_matrices():
+        a = fock.density_operator(cs, n, 0, 0, gm, False)
+        ex.append(np.trace(left @ a @ right @ a) / Z)
+    ex = np.array(ex)
+    assert np.abs(c - ex).max() < 1e-12
+    assert abs(m2 - ex.mean()) < 1e-12
+
+
+def test_displaced_green_boundaries():
+    """Antiperiodicity in tau of the fermion propagator: G(beta,0) = 1 - G(0),
+    G(0,beta) = -G(0); the bosonic correlator is periodic, C(beta) = C(0), and
+    C(0) is the equal-time S^i_{q=0} (Results)."""
+    from oracle.observables import so5_correlator
+    n, L = 3, 6
+    m = Model(n, L, 0.1, u0=1.0, uk=1.5, un=1.5)
+    phi = synth.fields(63, L, m.n_q)
+    G0 = dqmc.green(m, phi, 0)
+    Gt0, G0t, Gtt = dqmc.green_displaced(m, phi, L)
+    I = np.eye(m.n)
+    assert np.abs(Gt0 - (I - G0)).max() < 1e-12
+    assert np.abs(G0t + G0).max() < 1e-12
+    cb, _ = so5_correlator(Gt0, G0t, Gtt, G0, n)
+    c0, _ = so5_correlator(*dqmc.green_displaced(m, phi, 0), G0, n)
+    s, _ = so5_observables(G0, n)
+    assert np.abs(cb - c0).max() < 1e-12 * np.abs(c0).max()
+    assert np.abs(c0 - s).max() < 1e-14
+
+
 # ---------------------------------------------------------------- the Markov chain
 
 def test_mala_free_gaussian_target():
