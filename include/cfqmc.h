@@ -139,6 +139,32 @@ int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stat
  * UDT stacks. */
 int cfqmc_measure_G(cfqmc_ctx* c, int32_t chain, int32_t tau, void* g_out, int32_t on_device);
 
+/* Time-displaced Green's functions of one chain (Supplementary Note 2 needs
+ * them for the imaginary-time correlator), on the spin block n = 2 N_phi, for
+ * the current configuration, 0 <= tau <= l_tau (slice units):
+ *   gt0 = G(tau,0) = <c(tau) c^dagger(0)> = B(tau,0) G(0),
+ *   g0t = G(0,tau), element [i][j] = -<c_j^dagger(tau) c_i(0)> = -(1 - G(0)) B(tau,0)^-1,
+ *   gtt = G(tau,tau).
+ * Each output is NULL or a host [n][n] complex128 buffer (row-major, re/im
+ * interleaved) owned by the caller. FP64 in every precision mode: recomputed
+ * from the UDT stacks at block boundaries, carried through the slices of a
+ * block by the slice propagators. Call between sweeps. Synchronises. */
+int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0, double* g0t, double* gtt);
+
+/* Imaginary-time correlator of the SO(5) order parameter at q = 0
+ * (Supplementary Note 2), C^i(tau) = <n^{Gamma^i}_{q=0}(tau) n^{Gamma^i}_{q=0}(0)>
+ * for i = 1..5 and tau = 0..l_tau, of the current configuration of every chain
+ * by Wick's theorem from G(tau,0), G(0,tau), G(tau,tau) and G(0) (one pass
+ * over the slices, FP64). m^2_SO(5)(tau, q=0) is the mean over i; C^i(0) is the
+ * equal-time S^i_{q=0}, C^i(l_tau) = C^i(0). Per configuration the values are
+ * complex; their Monte Carlo average is real. out: host
+ * [n_chains][l_tau + 1][5] complex128 (re/im interleaved), owned by the caller.
+ * stab_rel: NULL or host [n_chains][3]: for G(tau,0), G(0,tau), G(tau,tau), the
+ * largest max|carried - recomputed| / max|recomputed| over the block
+ * boundaries (the FP64 accuracy of carrying them through a block).
+ * Call between sweeps. Synchronises. */
+int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel);
+
 /* ln of the fermion weight exp(sum_tau c_tau) det(1 + B(beta,0))^2 of one chain
  * (complex; the imaginary part is 0 mod 2 pi for the sign-free model), FP64. */
 int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im);

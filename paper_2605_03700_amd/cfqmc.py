@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
-           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_logdet", "cfqmc_observables",
+           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
@@ -89,6 +89,8 @@ def load():
     lib.cfqmc_restore.argtypes = [P, ctypes.c_char_p]
     lib.cfqmc_sweep.argtypes = [P, ctypes.c_int32, P, P]
     lib.cfqmc_measure_G.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32]
+    lib.cfqmc_green_displaced.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    lib.cfqmc_measure_tau.argtypes = [P, P, P]
     lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_observables.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_series.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -256,6 +258,23 @@ class CFQMC:
         g = np.empty((self.dim_g4n, self.dim_g4n), dtype=np.complex128)
         self._check(self.lib.cfqmc_measure_G(self.h, chain, tau, _ptr(g), 0))
         return g
+
+    def green_displaced(self, chain=0, tau=0):
+        """(G(tau,0), G(0,tau), G(tau,tau)) of one chain on the spin block, n x n complex128."""
+        n = 2 * self.n_phi
+        out = [np.empty((n, n), dtype=np.complex128) for _ in range(3)]
+        self._check(self.lib.cfqmc_green_displaced(self.h, chain, tau, _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
+        return tuple(out)
+
+    def measure_tau(self, with_stab=False):
+        """C^i(tau) = <n^i_{q=0}(tau) n^i_{q=0}(0)> of every chain: complex128
+        [n_chains][l_tau + 1][5]; m^2_SO(5)(tau) is the mean over the last axis.
+        with_stab: also return [n_chains][3], the relative difference of the
+        carried and recomputed G(tau,0), G(0,tau), G(tau,tau) at block boundaries."""
+        out = np.empty((self.n_chains, self.l_tau + 1, 5), dtype=np.complex128)
+        st = np.empty((self.n_chains, 3))
+        self._check(self.lib.cfqmc_measure_tau(self.h, _ptr(out), _ptr(st)))
+        return (out, st) if with_stab else out
 
     def logdet(self, chain=0):
         re, im = ctypes.c_double(), ctypes.c_double()

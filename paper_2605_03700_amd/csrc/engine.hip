@@ -219,7 +219,11 @@ struct cfqmc_ctx {
   Udt Ls, Rs;
   double2 *W1, *A1, *Gr, *Q1, *Q2, *R1, *R2, *Rt, *Tp, *K1, *M1, *Yl, *Wm, *X1, *Gs;
   double2* rs_ws;   // inverted diagonal blocks for the right solves
-  double *nrm, *sqd1, *sqd2, *dinvL, *dinvR, *tmpd;
+  double *nrm, *sqd1, *sqd2, *dinvL, *dinvR, *tmpd, *dminL, *dminR;
+  // imaginary-time correlator: [chain][L+1][5] values and the traces of G(0)
+  double2* corr;
+  double2* tr0;
+  double* disp_err;   // [chain][3][4] carried vs recomputed at the block boundaries
   int* perm;
   // scalars per chain
   double2* alpha;
@@ -442,6 +446,109 @@ void green_udt(cfqmc_ctx* c, int bl, int br, double2* Gout) {
   launch_rsolve(c->Wm, n, nn, c->X1, n, nn, c->Yl, n, nn, c->ipiv, n, n, 0, B, c->s, c->rs_ws);
   launch_colscale(c->X1, n, nn, c->X1, n, nn, c->dinvL, n, n, n, 0, B, c->s);
   gemm_nn(c, c->X1, 0, nn, UL, 1, sU, Gout, nn, B);
+}
+
+// The three Green's functions at the block boundary tau_b from the same
+// stacks and the same Loh matrix Y (B(tau,0) = U_L D_L T_L, B(beta,tau) =
+// T_R^+ D_R U_R^+, D = D^max D^min with D^max = max(D, 1)):
+//   G(tau,tau) = U_R D_R^max^-1 Y^-1 D_L^max^-1 U_L^+     (as green_udt)
+//   G(tau,0)   = G(tau,tau) B(tau,0)  = U_R D_R^max^-1 Y^-1 D_L^min T_L
+//   G(0,tau)   = -B(beta,tau) G(tau,tau) = -T_R^+ D_R^min Y^-1 D_L^max^-1 U_L^+
+// Every diagonal factor is at most one, so no scale is amplified.
+void green_udt3(cfqmc_ctx* c, int b, double2* Gtt, double2* Gt0, double2* G0t) {
+  const int n = c->n, B = c->nch;
+  const long long nn = c->nn, sU = (long long)(c->nblk_stab + 1) * nn, sD = (long long)(c->nblk_stab + 1) * n;
+  const double2 *UL = c->Ls.U + b * nn, *TL = c->Ls.T + b * nn, *UR = c->Rs.U + b * nn, *TR = c->Rs.T + b * nn;
+  const double *DL = c->Ls.D + b * n, *DR = c->Rs.D + b * n;
+  gemm_nn(c, UL, 1, sU, UR, 0, sU, c->K1, nn, B);
+  gemm_nn(c, TL, 0, sU, TR, 1, sU, c->M1, nn, B);
+  launch_loh_combine(c->K1, c->M1, DL, sD, DR, sD, c->Yl, n, B, c->s);
+  launch_lu(c->Yl, n, n, nn, c->ipiv, n, c->ldtmp, 1, B, c->s);
+  launch_dmax_inv(DR, sD, c->dinvR, n, B, c->s);
+  launch_dmax_inv(DL, sD, c->dinvL, n, B, c->s);
+  launch_dmin1(DL, sD, c->dminL, n, B, c->s);
+  launch_dmin1(DR, sD, c->dminR, n, B, c->s);
+  // W = U_R D_R^max^-1 Y^-1
+  launch_colscale(UR, n, sU, c->Wm, n, nn, c->dinvR, n, n, n, 0, B, c->s);
+  launch_rsolve(c->Wm, n, nn, c->X1, n, nn, c->Yl, n, nn, c->ipiv, n, n, 0, B, c->s, c->rs_ws);
+  launch_colscale(c->X1, n, nn, c->Wm, n, nn, c->dminL, n, n, n, 0, B, c->s);
+  gemm_nn(c, c->Wm, 0, nn, TL, 0, sU, Gt0, nn, B);
+  launch_colscale(c->X1, n, nn, c->X1, n, nn, c->dinvL, n, n, n, 0, B, c->s);
+  gemm_nn(c, c->X1, 0, nn, UL, 1, sU, Gtt, nn, B);
+  // Z = -D_R^min Y^-1 D_L^max^-1 U_L^+, then G(0,tau) = T_R^+ Z
+  launch_diag_set(c->Wm, n, nn, c->dminR, n, -1.0, B, c->s);
+  launch_rsolve(c->Wm, n, nn, c->X1, n, nn, c->Yl, n, nn, c->ipiv, n, n, 0, B, c->s, c->rs_ws);
+  launch_colscale(c->X1, n, nn, c->X1, n, nn, c->dinvL, n, n, n, 0, B, c->s);
+  gemm_nn(c, c->X1, 0, nn, UL, 1, sU, c->Wm, nn, B);
+  gemm_nn(c, TR, 1, sU, c->Wm, 0, nn, G0t, nn, B);
+}
+
+// Imaginary-time pass over tau = 0..L of the current configuration (between
+// sweeps: both stacks and the slice exponentials are current). G(tau,0),
+// G(0,tau) and G(tau,tau) are recomputed from the stacks at every block
+// boundary and carried through the slices of a block by channel applications
+// in FP64: G(tau,0) <- B_tau G(tau-1,0), G(0,tau) <- G(0,tau-1) B_tau^-1,
+// G(tau,tau) <- B_tau G(tau-1,tau-1) B_tau^-1. At each boundary after the
+// first the carried matrices are compared with the recomputed ones (running
+// max |carried - recomputed| and its ratio to max |recomputed| per chain and
+// matrix in err[chain][3][4], when err != nullptr; entries 2, 3 of each
+// quadruple are scratch and must start at zero). With corr != nullptr the
+// correlator of every tau goes to corr[chain][tau][5]; the pass stops after
+// tau_stop (-1: all). out[0..2] receive the buffers holding the final
+// G(tau,0), G(0,tau), G(tau,tau) (two of F / Fp each).
+void displaced_pass(cfqmc_ctx* c, int tau_stop, double2* corr, double* err, double2** out) {
+  const long long nn = c->nn, NN = c->NN, sPQ = (long long)c->L * 8 * NN;
+  double2* cur[3] = {c->Fp[0], c->Fp[1], c->Fp[2]};
+  double2* alt[3] = {c->F[0], c->F[1], c->F[2]};
+  const double F0 = 1.0 / (4.0 * M_PI * std::sqrt((double)c->N));
+  const int last = tau_stop < 0 ? c->L : tau_stop;
+  for (int tau = 0; tau <= last; ++tau) {
+    const bool boundary = tau % c->nstab == 0 || tau == c->L;
+    if (tau > 0) {
+      const int t = tau - 1;   // 0-based slice
+      // B_tau X, X B_tau^-1 and B_tau X B_tau^-1 with B_tau = E_0 E_1 E_2 E_3;
+      // each chain of four applications ends in the buffer it started from
+      const double2* in = cur[0];
+      for (int ch = 3; ch >= 0; --ch) {
+        const double2* pq = c->PQ + (long long)t * 8 * NN + ch * 2 * NN;
+        double2* dst = ch == 0 ? cur[0] : (ch % 2 ? c->S1 : c->S2);
+        chan(c, 1, ch, false, pq, sPQ, in, dst, false, nullptr, 0);
+        in = dst;
+      }
+      in = cur[1];
+      for (int ch = 3; ch >= 0; --ch) {
+        const double2* pq = c->PQ + (long long)t * 8 * NN + ch * 2 * NN;
+        double2* dst = ch == 0 ? cur[1] : (ch % 2 ? c->S1 : c->S2);
+        chan(c, 0, ch, true, pq, sPQ, in, dst, false, nullptr, 0);
+        in = dst;
+      }
+      in = cur[2];
+      for (int ch = 3; ch >= 0; --ch) {
+        const double2* pq = c->PQ + (long long)t * 8 * NN + ch * 2 * NN;
+        chan(c, 1, ch, false, pq, sPQ, in, c->S1, false, nullptr, 0);
+        double2* dst = ch == 0 ? cur[2] : (in == c->S2 ? c->Fp[3] : c->S2);
+        chan(c, 0, ch, true, pq, sPQ, c->S1, dst, false, nullptr, 0);
+        in = dst;
+      }
+    }
+    if (boundary) {
+      const int b = tau == c->L ? c->nblk_stab : tau / c->nstab;
+      if (tau == 0) {
+        green_udt3(c, b, cur[2], cur[0], cur[1]);
+      } else {
+        green_udt3(c, b, alt[2], alt[0], alt[1]);
+        for (int k = 0; k < 3; ++k) {
+          if (err) launch_maxdiff(cur[k], alt[k], c->n, nn, err + 4 * k, c->nch, c->s, 12);
+          std::swap(cur[k], alt[k]);
+        }
+      }
+    }
+    if (corr)
+      launch_disp_corr(cur[0], cur[1], cur[2], nn, c->N, F0, c->tr0, tau == 0, corr + (long long)tau * 5,
+                       (long long)(c->L + 1) * 5, c->nch, c->s);
+  }
+  if (out)
+    for (int k = 0; k < 3; ++k) out[k] = cur[k];
 }
 
 // C_b = B_{tau_{b+1}} ... B_{tau_b + 1} of block b (FP64), all chains.
@@ -835,7 +942,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   double2** sbufs[] = {&c->W1, &c->A1, &c->Gr, &c->Q1, &c->Q2, &c->R1, &c->R2, &c->Rt, &c->Tp, &c->K1, &c->M1, &c->Yl, &c->Wm, &c->X1, &c->Gs};
   for (auto bp : sbufs) rc |= dalloc(c, bp, (size_t)B * nn);
   rc |= dalloc(c, &c->rs_ws, (size_t)B * rsolve_work_size(n));
-  double** dbufs[] = {&c->nrm, &c->sqd1, &c->sqd2, &c->dinvL, &c->dinvR, &c->tmpd};
+  double** dbufs[] = {&c->nrm, &c->sqd1, &c->sqd2, &c->dinvL, &c->dinvR, &c->tmpd, &c->dminL, &c->dminR};
   for (auto bp : dbufs) rc |= dalloc(c, bp, (size_t)B * n);
   rc |= dalloc(c, &c->perm, (size_t)B * n);
   rc |= dalloc(c, &c->alpha, (size_t)B * 4);
@@ -1259,6 +1366,46 @@ int cfqmc_measure_G(cfqmc_ctx* c, int32_t chain, int32_t tau, void* g_out, int32
   for (int i = 0; i < 2 * n; ++i)
     for (int j = 0; j < 2 * n; ++j)
       o[(long long)i * 2 * n + j] = (i / n == j / n) ? tmp[(long long)(i % n) * n + (j % n)] : make_double2(0.0, 0.0);
+  return CFQMC_OK;
+}
+
+int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel) {
+  if (!c || !out) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  const long long cnt = (long long)c->nch * (c->L + 1) * 5;
+  if (!c->corr) {
+    int rc = dalloc(c, &c->corr, (size_t)cnt);
+    rc |= dalloc(c, &c->tr0, (size_t)c->nch * 2);
+    rc |= dalloc(c, &c->disp_err, (size_t)c->nch * 12);
+    if (rc) { c->corr = nullptr; return CFQMC_ENOMEM; }
+  }
+  hipMemsetAsync(c->disp_err, 0, (size_t)c->nch * 12 * sizeof(double), c->s);
+  displaced_pass(c, -1, c->corr, c->disp_err, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpy(out, c->corr, cnt * sizeof(double2), hipMemcpyDeviceToHost));
+  if (stab_rel) {
+    std::vector<double> e((size_t)c->nch * 12);
+    HIPCHK(hipMemcpy(e.data(), c->disp_err, e.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int z = 0; z < c->nch; ++z)
+      for (int k = 0; k < 3; ++k) stab_rel[3 * z + k] = e[12 * z + 4 * k + 1];
+  }
+  for (long long i = 0; i < 2 * cnt; ++i)
+    if (!std::isfinite(out[i])) { c->err = "non-finite correlator"; return CFQMC_ENUMERIC; }
+  return CFQMC_OK;
+}
+
+int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0, double* g0t, double* gtt) {
+  if (!c || chain < 0 || chain >= c->nch || tau < 0 || tau > c->L) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  double2* res[3];
+  displaced_pass(c, tau, nullptr, nullptr, res);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->s));
+  double* outs[3] = {gt0, g0t, gtt};
+  for (int k = 0; k < 3; ++k)
+    if (outs[k])
+      HIPCHK(hipMemcpy(outs[k], res[k] + chain * c->nn, c->nn * sizeof(double2), hipMemcpyDeviceToHost));
   return CFQMC_OK;
 }
 

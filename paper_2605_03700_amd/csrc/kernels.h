@@ -75,10 +75,10 @@ void launch_copy(const double2* X, double2* Y, long long count, long long sX, lo
 // Y[:, k] = X[:, k] * d[k]   (d real, per batch stride sd) ; inv: divide instead
 void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
                      const double* d, long long sd, int n_rows, int n_cols, int inv, int nbatch, hipStream_t s);
-// running max |X - Y| (out[4z]) and max |X - Y| / max |Y| (out[4z+1]) per batch entry;
-// out[4z+2], out[4z+3] are scratch that must start at zero
+// running max |X - Y| (out[so z]) and max |X - Y| / max |Y| (out[so z + 1]) per batch
+// entry; out[so z + 2], out[so z + 3] are scratch that must start at zero
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
-                    hipStream_t s);
+                    hipStream_t s, int so = 4);
 
 // ---- UDT stabilisation helpers (linalg.hip)
 // Column norms of W (n x n) -> nrm; descending-order permutation perm.
@@ -102,6 +102,11 @@ void launch_loh_combine(const double2* K, const double2* Mm, const double* Dl, l
 void launch_dmax_inv(const double* d, long long sd, double* out, int n, int nbatch, hipStream_t s);
 // sum ln max(D,1) per batch
 void launch_sum_log_dmax(const double* d, long long sd, int n, double* out, int nbatch, hipStream_t s);
+// d -> min(d, 1), the small part of the same split (out stride n)
+void launch_dmin1(const double* d, long long sd, double* out, int n, int nbatch, hipStream_t s);
+// A = scale * diag(d), n x n
+void launch_diag_set(double2* A, int n, long long sA, const double* d, long long sd, double scale, int nbatch,
+                     hipStream_t s);
 
 // ---- model kernels (qmc.hip)
 struct ModelDev {
@@ -171,6 +176,11 @@ void launch_eps_update(double* eps, const int* acc_count, int L, double r0, doub
 // S^i_{q=0} (i=1..5) and m^2 from the spin-block G; out [chain][8]
 void launch_observables(const double2* G, long long sG, int N, double F0, double* out, long long sout,
                         int nchain, hipStream_t s);
+// imaginary-time correlator <n^i_{q=0}(tau) n^i_{q=0}(0)>, i = 1..5, of every chain for
+// one tau from X = G(tau,0), Y = G(0,tau), W = G(tau,tau) (spin block); tr0 [chain][2]
+// traces of G(0), written when first != 0; out[chain * sout + i] complex
+void launch_disp_corr(const double2* X, const double2* Y, const double2* W, long long sG, int N, double F0,
+                      double2* tr0, int first, double2* out, long long sout, int nchain, hipStream_t s);
 // background sum over slices: c[chain] = sum_tau alpha0 * phi0 . beta
 void launch_background(const ModelDev& m, const double* phi, long long sphi_chain, const double2* alpha,
                        double2* out, int nchain, hipStream_t s);

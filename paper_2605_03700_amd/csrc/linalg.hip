@@ -999,7 +999,7 @@ void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ld
 // Per chain: out[4z+2] = max |X - Y| and out[4z+3] = max |Y| (atomic max over
 // blocks), then maxdiff_fold folds them into the running maxima out[4z+0]
 // (absolute) and out[4z+1] (relative to max |Y|) and clears the temporaries.
-__global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long long sX, double* out) {
+__global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long long sX, double* out, int so) {
   __shared__ double red[4], redy[4];
   const int z = blockIdx.y;
   double m = 0.0, my = 0.0;
@@ -1018,24 +1018,24 @@ __global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long l
     m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     my = fmax(fmax(redy[0], redy[1]), fmax(redy[2], redy[3]));
     // non-negative doubles order like their bit patterns
-    atomicMax((unsigned long long*)&out[4 * z + 2], (unsigned long long)__double_as_longlong(m));
-    atomicMax((unsigned long long*)&out[4 * z + 3], (unsigned long long)__double_as_longlong(my));
+    atomicMax((unsigned long long*)&out[so * z + 2], (unsigned long long)__double_as_longlong(m));
+    atomicMax((unsigned long long*)&out[so * z + 3], (unsigned long long)__double_as_longlong(my));
   }
 }
-__global__ void maxdiff_fold_kernel(double* out, int nbatch) {
+__global__ void maxdiff_fold_kernel(double* out, int nbatch, int so) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= nbatch) return;
-  const double d = out[4 * z + 2], gm = out[4 * z + 3];
-  out[4 * z + 0] = fmax(out[4 * z + 0], d);
-  out[4 * z + 1] = fmax(out[4 * z + 1], gm > 0.0 ? d / gm : d);
-  out[4 * z + 2] = 0.0;
-  out[4 * z + 3] = 0.0;
+  const double d = out[so * z + 2], gm = out[so * z + 3];
+  out[so * z + 0] = fmax(out[so * z + 0], d);
+  out[so * z + 1] = fmax(out[so * z + 1], gm > 0.0 ? d / gm : d);
+  out[so * z + 2] = 0.0;
+  out[so * z + 3] = 0.0;
 }
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
-                    hipStream_t s) {
+                    hipStream_t s, int so) {
   dim3 grid(min((n * n + 1023) / 1024, 64), nbatch);
-  hipLaunchKernelGGL(maxdiff_kernel, grid, dim3(256), 0, s, X, Y, n, sX, out); cfqmc_post_launch("maxdiff_kernel");
-  hipLaunchKernelGGL(maxdiff_fold_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, out, nbatch);
+  hipLaunchKernelGGL(maxdiff_kernel, grid, dim3(256), 0, s, X, Y, n, sX, out, so); cfqmc_post_launch("maxdiff_kernel");
+  hipLaunchKernelGGL(maxdiff_fold_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, out, nbatch, so);
   cfqmc_post_launch("maxdiff_fold_kernel");
 }
 
@@ -1167,4 +1167,25 @@ void cfqmc_post_launch(const char* name) {
     fprintf(stderr, "[cfqmc] kernel %s failed: %s\n", name, hipGetErrorString(e));
     fflush(stderr);
   }
+}
+
+__global__ void dmin1_kernel(const double* d, long long sd, double* out, int n) {
+  const int z = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[z * n + i] = fmin(d[z * sd + i], 1.0);
+}
+void launch_dmin1(const double* d, long long sd, double* out, int n, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(dmin1_kernel, dim3(nbatch), dim3(256), 0, s, d, sd, out, n); cfqmc_post_launch("dmin1_kernel");
+}
+
+__global__ void diag_set_kernel(double2* A, int n, long long sA, const double* d, long long sd, double scale) {
+  const int z = blockIdx.y;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * n; idx += gridDim.x * blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    A[z * sA + idx] = make_double2(i == j ? scale * d[z * sd + i] : 0.0, 0.0);
+  }
+}
+void launch_diag_set(double2* A, int n, long long sA, const double* d, long long sd, double scale, int nbatch,
+                     hipStream_t s) {
+  dim3 grid(min((n * n + 255) / 256, 1024), nbatch);
+  hipLaunchKernelGGL(diag_set_kernel, grid, dim3(256), 0, s, A, n, sA, d, sd, scale); cfqmc_post_launch("diag_set_kernel");
 }

@@ -555,3 +555,87 @@ __global__ void expand4n_kernel(const double2* G, int n, double2* G4) {
 void launch_expand4n(const double2* G, int n, double2* G4, hipStream_t s) {
   hipLaunchKernelGGL(expand4n_kernel, dim3(min((4 * n * n + 255) / 256, 1024)), dim3(256), 0, s, G, n, G4); cfqmc_post_launch("expand4n_kernel");
 }
+
+// ------------------------------------------------------------------ imaginary-time correlator
+// <n^{Gamma^i}_{q=0}(tau) n^{Gamma^i}_{q=0}(0)> (Supplementary Note 2) of every
+// chain for one tau, by Wick's theorem. With T_o = o kron 1_N on the spin block,
+// G_4N = 1_spin kron G, X = G(tau,0), Y = G(0,tau), W = G(tau,tau):
+//   C^{1,2}   = F0^2 [4 Tr(T W) Tr(T G(0)) - 2 Tr(T X T Y)]   (o = tau_x, tau_y)
+//   C^{3,4,5} = -2 F0^2 Tr(T X T Y)                          (o = tau_z; its spin trace
+//                                                              removes the disconnected part)
+// Tr(T X T Y) = sum o_ab o_cd Tr(X_bc Y_da) over the N x N valley blocks, built
+// from eight block products P(a,b,c,d) = Tr(X_ab Y_cd). tr0[chain] holds
+// Tr(T_x G(0)), Tr(T_y G(0)) and is written from W when first != 0 (tau = 0).
+// One workgroup per chain; out[chain * sout + i], i = 0..4.
+__global__ void __launch_bounds__(256) disp_corr_kernel(const double2* Xall, const double2* Yall,
+                                                        const double2* Wall, long long sG, int N, double F0,
+                                                        double2* tr0, int first, double2* out, long long sout) {
+  constexpr int NV = 20;   // 8 block products + 2 block traces, complex
+  __shared__ double red[4][NV];
+  const int z = blockIdx.x, n = 2 * N;
+  const double2* X = Xall + z * sG;
+  const double2* Y = Yall + z * sG;
+  const double2* W = Wall + z * sG;
+  double2 p[8], t[2];
+  for (int i = 0; i < 8; ++i) p[i] = make_double2(0.0, 0.0);
+  for (int i = 0; i < 2; ++i) t[i] = make_double2(0.0, 0.0);
+  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    const int k = idx / N, kp = idx % N;
+    double2 x[2][2], y[2][2];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        x[a][b] = X[(long long)(a * N + k) * n + b * N + kp];
+        y[a][b] = Y[(long long)(a * N + kp) * n + b * N + k];
+      }
+    p[0] = cadd(p[0], cmul(x[1][0], y[1][0]));
+    p[1] = cadd(p[1], cmul(x[1][1], y[0][0]));
+    p[2] = cadd(p[2], cmul(x[0][0], y[1][1]));
+    p[3] = cadd(p[3], cmul(x[0][1], y[0][1]));
+    p[4] = cadd(p[4], cmul(x[0][0], y[0][0]));
+    p[5] = cadd(p[5], cmul(x[0][1], y[1][0]));
+    p[6] = cadd(p[6], cmul(x[1][0], y[0][1]));
+    p[7] = cadd(p[7], cmul(x[1][1], y[1][1]));
+    if (k == kp) {
+      t[0] = cadd(t[0], W[(long long)k * n + N + k]);         // Tr W_01
+      t[1] = cadd(t[1], W[(long long)(N + k) * n + k]);       // Tr W_10
+    }
+  }
+  double v[NV];
+  for (int i = 0; i < 8; ++i) { v[2 * i] = p[i].x; v[2 * i + 1] = p[i].y; }
+  v[16] = t[0].x; v[17] = t[0].y; v[18] = t[1].x; v[19] = t[1].y;
+  for (int i = 0; i < NV; ++i) {
+    double s = v[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[NV];
+    for (int i = 0; i < NV; ++i) r[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    double2 P[8];
+    for (int i = 0; i < 8; ++i) P[i] = make_double2(r[2 * i], r[2 * i + 1]);
+    const double2 w01 = make_double2(r[16], r[17]), w10 = make_double2(r[18], r[19]);
+    // Tr(tau_x W) = Tr W_10 + Tr W_01 ; Tr(tau_y W) = -i Tr W_10 + i Tr W_01
+    const double2 tx = cadd(w10, w01);
+    const double2 d = csub(w01, w10);
+    const double2 ty = make_double2(-d.y, d.x);
+    if (first) {
+      tr0[2 * z] = tx;
+      tr0[2 * z + 1] = ty;
+    }
+    const double2 tx0 = first ? tx : tr0[2 * z], ty0 = first ? ty : tr0[2 * z + 1];
+    const double2 qx = cadd(cadd(P[0], P[1]), cadd(P[2], P[3]));
+    const double2 qy = cadd(csub(P[1], P[0]), csub(P[2], P[3]));
+    const double2 qz = cadd(csub(P[4], P[5]), csub(P[7], P[6]));
+    const double f2 = F0 * F0;
+    double2* o = out + z * sout;
+    o[0] = cscale(csub(cscale(cmul(tx, tx0), 4.0), cscale(qx, 2.0)), f2);
+    o[1] = cscale(csub(cscale(cmul(ty, ty0), 4.0), cscale(qy, 2.0)), f2);
+    o[2] = o[3] = o[4] = cscale(qz, -2.0 * f2);
+  }
+}
+void launch_disp_corr(const double2* X, const double2* Y, const double2* W, long long sG, int N, double F0,
+                      double2* tr0, int first, double2* out, long long sout, int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(disp_corr_kernel, dim3(nchain), dim3(256), 0, s, X, Y, W, sG, N, F0, tr0, first, out, sout);
+  cfqmc_post_launch("disp_corr_kernel");
+}
