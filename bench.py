@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--fp64-compare", action="store_true",
                     help="after the timed mixed sweeps, time the same chains with every product in FP64 (it runs "
                          "after a minute of load, so clocks may differ from the timed part)")
+    ap.add_argument("--no-tau-correlator", action="store_true",
+                    help="skip the imaginary-time correlator pass after the tau_int sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB between two fresh device buffers three times (reference for the "
@@ -233,6 +235,26 @@ def main():
         out["tau_int_is_lower_bound"] = bool(open_w)
         out["indep_samples_per_s"] = args.chains * (args.tau_sweeps / dt2) / (2 * tau)
         progress("tau_int sweeps done")
+    if not args.no_tau_correlator:
+        # one imaginary-time pass (G(tau,0), G(0,tau), G(tau,tau) for tau = 0..L
+        # and the SO(5) correlator at q = 0) over every chain, FP64
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [q.measure_tau(with_stab=True) for q in b.groups]
+        dtm = time.perf_counter() - t0
+        C = np.concatenate([r[0] for r in res])
+        st = np.concatenate([r[1] for r in res])
+        m2t = C.mean(axis=2).mean(axis=0)
+        pts = sorted({0, 1, 2, 4, 8, 16, 32, 64, 128, args.l_tau // 2} & set(range(args.l_tau + 1)))
+        chan_flops = 12.0 * args.l_tau * 16.0 * args.n_phi ** 2 * n_sp * args.chains
+        out["tau_correlator"] = {
+            "ms_per_pass": 1000.0 * dtm, "chains": args.chains, "pass_over_sweep": dtm / (dt / args.steps),
+            "channel_application_tflops": chan_flops / dtm / 1e12,
+            "carried_vs_recomputed_rel_max": float(st.max()),
+            "m2_so5_tau_mean_over_chains": {str(t): float(m2t[t].real) for t in pts},
+            "definition": "m^2_SO(5)(tau, q=0) = (1/5) sum_i <n^i_{q=0}(tau) n^i_{q=0}(0)>, tau in slices; "
+                          "one pass = L slices x 12 FP64 channel applications + a recomputation per block"}
+        progress("imaginary-time correlator pass done")
     b.close()
     if prec != FP64 and args.fp64_compare:
         # the same chains with every product in FP64 (warm-up sweep, then two timed sweeps)
