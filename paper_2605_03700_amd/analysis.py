@@ -72,3 +72,55 @@ def independent_samples_per_s(sweeps_per_s, series_list):
     taus = [tau_int(s)[0] for s in series_list if len(s) > 1]
     t = max(taus) if taus else 0.5
     return sweeps_per_s / (2.0 * t), t
+
+
+def effective_gap(c, dtau):
+    """Per-tau gap estimate of a bosonic correlator that is periodic in
+    imaginary time, C(tau) = A cosh(Delta (tau - beta/2)) at long times:
+    C(t-1) + C(t+1) = 2 cosh(Delta dtau) C(t), so
+    Delta_eff(t) = arccosh((C(t-1) + C(t+1)) / (2 C(t))) / dtau for
+    t = 1..len(c)-2 (NaN where the ratio is below one). c: C at tau = t dtau,
+    t = 0..L (C(L) = C(0))."""
+    c = np.asarray(c, dtype=float)
+    r = (c[:-2] + c[2:]) / (2.0 * c[1:-1])
+    out = np.full(r.size, np.nan)
+    ok = r >= 1.0
+    out[ok] = np.arccosh(r[ok]) / dtau
+    return out
+
+
+def fit_gap(c, dtau, t_lo, t_hi=None, constant=False):
+    """Gap Delta_SO5 from the long-time tail of m^2_SO(5)(tau, q=0)
+    (Supplementary Note 2: exponential decay at long imaginary times; on the
+    periodic interval the decay from both ends adds to A cosh(Delta (tau -
+    beta/2))). Least squares of A cosh(Delta (tau - beta/2)) (+ B with
+    constant=True) over t_lo <= t <= t_hi (default L - t_lo). Returns
+    (Delta, A[, B])."""
+    from scipy.optimize import curve_fit
+    c = np.asarray(c, dtype=float)
+    L = c.size - 1
+    t_hi = L - t_lo if t_hi is None else t_hi
+    t = np.arange(t_lo, t_hi + 1)
+    half = 0.5 * L * dtau
+    x = t * dtau - half
+    y = c[t]
+    d0 = effective_gap(c, dtau)
+    d0 = d0[max(t_lo - 1, 0):max(t_lo - 1, 0) + 3]
+    d0 = float(np.nanmean(d0)) if np.isfinite(d0).any() else 1.0 / max(half, 1e-9)
+    a0 = float(c[L // 2])
+    if constant:
+        f = lambda x, d, a, b: a * np.cosh(d * x) + b
+        p, _ = curve_fit(f, x, y, p0=[d0, a0, 0.0], maxfev=20000)
+        return float(abs(p[0])), float(p[1]), float(p[2])
+    f = lambda x, d, a: a * np.cosh(d * x)
+    p, _ = curve_fit(f, x, y, p0=[d0, a0], maxfev=20000)
+    return float(abs(p[0])), float(p[1])
+
+
+def dynamic_exponent(n_phis, gaps):
+    """z from Delta_SO5 ~ (sqrt N_phi)^-z (Supplementary Note 2): slope of the
+    least-squares line of ln Delta against ln(1/sqrt N_phi). Returns (z, C)."""
+    x = np.log(1.0 / np.sqrt(np.asarray(n_phis, dtype=float)))
+    y = np.log(np.asarray(gaps, dtype=float))
+    z, c0 = np.polyfit(x, y, 1)
+    return float(z), float(c0)

@@ -130,3 +130,24 @@ def test_tau_int_pooled_removes_a_shared_drift_and_flags_short_series():
         slow.append(x)
     tau, w, closed = tau_int_pooled(slow)
     assert not closed and w == 19 and tau < 49.5
+
+
+def test_gap_fit_recovers_a_cosh_correlator():
+    """A cosh(Delta (tau - beta/2)) (+ constant) on the periodic interval: the
+    effective gap is Delta at every tau and the fit returns Delta; pure
+    power-law gaps Delta = c N^{-z/2} give z back."""
+    from paper_2605_03700_amd.analysis import dynamic_exponent, effective_gap, fit_gap
+    L, dtau, d, a = 120, 0.1, 0.8, 0.3
+    tau = np.arange(L + 1) * dtau
+    c = a * np.cosh(d * (tau - 0.5 * L * dtau))
+    assert np.allclose(effective_gap(c, dtau), d, rtol=1e-9)
+    got = fit_gap(c, dtau, 10)
+    assert abs(got[0] - d) < 1e-8 and abs(got[1] - a) < 1e-8
+    got = fit_gap(c + 0.05, dtau, 5, constant=True)
+    assert abs(got[0] - d) < 1e-6 and abs(got[2] - 0.05) < 1e-6
+    rng = np.random.default_rng(1)
+    noisy = c * (1.0 + 1e-3 * rng.standard_normal(c.size))
+    assert abs(fit_gap(noisy, dtau, 10)[0] - d) < 0.02
+    n = np.array([16, 36, 64, 100, 144])
+    z, _ = dynamic_exponent(n, 2.0 * n ** -0.5)
+    assert abs(z - 1.0) < 1e-12
