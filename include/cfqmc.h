@@ -165,6 +165,18 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
  * Call between sweeps. Synchronises. */
 int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel);
 
+/* Equal-time structure factors S^i_q = <n^{Gamma^i}_q n^{Gamma^i}_{-q}>,
+ * i = 1..5, at the given momenta (Results: S^i_q; the correlation ratio
+ * R = 1 - S(Q + dq) / S(Q) and the VBS (i = 1, 2) and AFM (i = 3, 4, 5) order
+ * parameters off the SO(5) line use them) for the current configuration of
+ * every chain, by Wick's theorem from G(0), FP64. q_xy: host [n_q][2] integer
+ * momenta (qx, qy) in units of the torus grid, used as given (the form factor
+ * depends on q itself, the orbital shift on qy mod N_phi); 1 <= n_q <= 4096.
+ * out: host [n_chains][n_q][5] complex128 (re/im interleaved), owned by the
+ * caller. Per configuration the values are complex; their average is real.
+ * Call between sweeps. Allocates small temporaries. Synchronises. */
+int cfqmc_structure_factors(cfqmc_ctx* c, const int32_t* q_xy, int32_t n_q, double* out);
+
 /* ln of the fermion weight exp(sum_tau c_tau) det(1 + B(beta,0))^2 of one chain
  * (complex; the imaginary part is 0 mod 2 pi for the sign-free model), FP64. */
 int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im);

@@ -124,3 +124,26 @@ def dynamic_exponent(n_phis, gaps):
     y = np.log(np.asarray(gaps, dtype=float))
     z, c0 = np.polyfit(x, y, 1)
     return float(z), float(c0)
+
+
+# ------------------------------------------------------------------ order parameters
+
+TORUS_DQ = ((1, 0), (0, 1), (-1, 0), (0, -1))   # smallest non-zero torus momenta (grid units)
+
+
+def order_parameters(s_q0, n_phi):
+    """From S^i_{q=0}, i = 1..5 (last axis): m^2_SO(5) = sum_i S^i / (5 N^2)
+    (Results), and, off the SO(5) line, the VBS (i = 1, 2) and AFM
+    (i = 3, 4, 5) order parameters normalised the same way,
+    m^2_VBS = (S^1 + S^2) / (2 N^2), m^2_AFM = (S^3 + S^4 + S^5) / (3 N^2).
+    Returns (m2_so5, m2_vbs, m2_afm)."""
+    s = np.real(np.asarray(s_q0))
+    n2 = float(n_phi) ** 2
+    return (s[..., :5].sum(-1) / (5 * n2), s[..., :2].sum(-1) / (2 * n2), s[..., 2:5].sum(-1) / (3 * n2))
+
+
+def correlation_ratio(s_Q, s_Q_dq):
+    """R = 1 - S(Q + dq) / S(Q) (Results), dq the smallest non-zero momentum;
+    arguments are Monte Carlo averages (S(Q + dq) may be averaged over the
+    symmetry-equivalent dq first). R -> 1 with long-range order, -> 0 without."""
+    return 1.0 - np.real(np.asarray(s_Q_dq)) / np.real(np.asarray(s_Q))

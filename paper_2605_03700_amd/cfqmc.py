@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
-           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_logdet", "cfqmc_observables",
+           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
@@ -91,6 +91,7 @@ def load():
     lib.cfqmc_measure_G.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32]
     lib.cfqmc_green_displaced.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.cfqmc_measure_tau.argtypes = [P, P, P]
+    lib.cfqmc_structure_factors.argtypes = [P, P, ctypes.c_int32, P]
     lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_observables.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_series.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -275,6 +276,14 @@ class CFQMC:
         st = np.empty((self.n_chains, 3))
         self._check(self.lib.cfqmc_measure_tau(self.h, _ptr(out), _ptr(st)))
         return (out, st) if with_stab else out
+
+    def structure_factors(self, qs):
+        """S^i_q, i = 1..5, at the momenta qs (sequence of (qx, qy)) for every
+        chain: complex128 [n_chains][len(qs)][5]."""
+        q = np.ascontiguousarray(np.asarray(qs, dtype=np.int32).reshape(-1, 2))
+        out = np.empty((self.n_chains, q.shape[0], 5), dtype=np.complex128)
+        self._check(self.lib.cfqmc_structure_factors(self.h, _ptr(q), q.shape[0], _ptr(out)))
+        return out
 
     def logdet(self, chain=0):
         re, im = ctypes.c_double(), ctypes.c_double()

@@ -1409,6 +1409,27 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
   return CFQMC_OK;
 }
 
+int cfqmc_structure_factors(cfqmc_ctx* c, const int32_t* q_xy, int32_t n_q, double* out) {
+  if (!c || !q_xy || !out || n_q <= 0 || n_q > 4096) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  int* dq = nullptr;
+  double2* dout = nullptr;
+  const long long cnt = (long long)c->nch * n_q * 5;
+  HIPCHK(hipMalloc(&dq, 2 * n_q * sizeof(int)));
+  if (hipMalloc(&dout, cnt * sizeof(double2)) != hipSuccess) { hipFree(dq); return CFQMC_ENOMEM; }
+  int rc = CFQMC_OK;
+  if (hipMemcpyAsync(dq, q_xy, 2 * n_q * sizeof(int), hipMemcpyHostToDevice, c->s) != hipSuccess) rc = CFQMC_EHIP;
+  if (!rc) {
+    launch_structure_factors(c->G, c->nn, c->N, dq, n_q, dout, c->nch, c->s);
+    if (hipStreamSynchronize(c->s) != hipSuccess ||
+        hipMemcpy(out, dout, cnt * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
+      rc = CFQMC_EHIP;
+  }
+  hipFree(dq);
+  hipFree(dout);
+  return rc;
+}
+
 int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im) {
   if (!c || chain < 0 || chain >= c->nch) return CFQMC_EINVAL;
   if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }

@@ -639,3 +639,107 @@ void launch_disp_corr(const double2* X, const double2* Y, const double2* W, long
   hipLaunchKernelGGL(disp_corr_kernel, dim3(nchain), dim3(256), 0, s, X, Y, W, sG, N, F0, tr0, first, out, sout);
   cfqmc_post_launch("disp_corr_kernel");
 }
+
+// ------------------------------------------------------------------ structure factors at any q
+// S^i_q = <n^{Gamma^i}_q n^{Gamma^i}_{-q}> (Results; the correlation ratio uses
+// q = Q + dq) of every chain from the spin-block G by Wick's theorem, with the
+// torus density operator (m_q)[k, k - qy] = F(q) exp(i pi (2k - qy) qx / N)
+// (k = 1..N) and n_{-q} = n_q^dagger. With T = o kron m_q, G_4N = 1_spin kron G:
+//   S^{1,2}_q   = 4 Tr(T_q G) Tr(T_-q G) + 2 [F(q)^2 Tr G - Tr(T_q G T_-q G)]
+//   S^{3,4,5}_q = 2 [F(q)^2 Tr G - Tr(T_q G T_-q G)]        (o = tau_z)
+// using T_-q T_q = F(q)^2 (o^2 = 1, m_q^dagger m_q = F^2). One workgroup per
+// (momentum, chain); out[(chain * nql + iq) * 5 + i].
+__global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long sG, int N, const int* qxy, int nql,
+                                                 double2* out) {
+  constexpr int NV = 16;
+  __shared__ double red[4][NV];
+  const int iq = blockIdx.x, z = blockIdx.y, n = 2 * N;
+  const double2* G = Gall + z * sG;
+  const int qx = qxy[2 * iq], qy = qxy[2 * iq + 1];
+  const int sy = ((qy % N) + N) % N;
+  const double F = exp(-2.0 * M_PI * (double)(qx * qx + qy * qy) / (4.0 * N)) / (4.0 * M_PI * sqrt((double)N));
+  // row a of m_q: column (a - qy) mod N, phase exp(i pi (2(a+1) - qy) qx / N);
+  // row b of m_-q: column (b + qy) mod N, phase exp(-i pi (2(b+1) + qy) qx / N)
+  auto ph = [&](long long num) {   // exp(i pi num / N), num reduced mod 2N
+    long long r = num % (2LL * N);
+    if (r < 0) r += 2LL * N;
+    double s, c;
+    sincospi((double)r / (double)N, &s, &c);
+    return make_double2(c, s);
+  };
+  double2 qo[3], tq[2], tm[2];
+  for (int i = 0; i < 3; ++i) qo[i] = make_double2(0.0, 0.0);
+  for (int i = 0; i < 2; ++i) tq[i] = tm[i] = make_double2(0.0, 0.0);
+  double2 trg = make_double2(0.0, 0.0);
+  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    const int a = idx / N, b = idx % N;
+    const int a2 = (a - sy + N) % N, b4 = (b + sy) % N;
+    const double2 c = cscale(cmul(ph((long long)(2 * (a + 1) - qy) * qx), ph(-(long long)(2 * (b + 1) + qy) * qx)),
+                             F * F);
+    double2 g1[2][2], g2[2][2];
+    for (int v = 0; v < 2; ++v)
+      for (int w = 0; w < 2; ++w) {
+        g1[v][w] = G[(long long)(v * N + a2) * n + w * N + b];    // G[(v, a2), (w, b)]
+        g2[v][w] = G[(long long)(v * N + b4) * n + w * N + a];    // G[(v, b4), (w, a)]
+      }
+    double2 sx = make_double2(0.0, 0.0), syy = sx, sz = sx;
+    for (int v1 = 0; v1 < 2; ++v1)
+      for (int v3 = 0; v3 < 2; ++v3) {
+        const double s = (v1 == v3) ? 1.0 : -1.0;
+        const double2 px = cmul(g1[1 - v1][v3], g2[1 - v3][v1]);
+        sx = cadd(sx, px);
+        syy = cadd(syy, cscale(px, -s));
+        sz = cadd(sz, cscale(cmul(g1[v1][v3], g2[v3][v1]), s));
+      }
+    qo[0] = cadd(qo[0], cmul(c, sx));
+    qo[1] = cadd(qo[1], cmul(c, syy));
+    qo[2] = cadd(qo[2], cmul(c, sz));
+    if (b == 0) {
+      // disconnected parts: Tr(T_q G) and Tr(T_-q G) for o = tau_x, tau_y (row a)
+      const double2 mq = cscale(ph((long long)(2 * (a + 1) - qy) * qx), F);
+      const double2 mm = cscale(ph(-(long long)(2 * (a + 1) + qy) * qx), F);
+      const int am = (a + sy) % N;
+      // sum_{v,w} o_vw m[a, col] G[(w, col), (v, a)]
+      const double2 x10 = G[(long long)(N + a2) * n + a], x01 = G[(long long)a2 * n + N + a];
+      const double2 y10 = G[(long long)(N + am) * n + a], y01 = G[(long long)am * n + N + a];
+      // tau_x: G[(1,c),(0,a)] + G[(0,c),(1,a)] ; tau_y: -i G[(1,c),(0,a)] + i G[(0,c),(1,a)]
+      const double2 dx = csub(x01, x10), dy = csub(y01, y10);
+      tq[0] = cadd(tq[0], cmul(mq, cadd(x10, x01)));
+      tq[1] = cadd(tq[1], cmul(mq, make_double2(-dx.y, dx.x)));
+      tm[0] = cadd(tm[0], cmul(mm, cadd(y10, y01)));
+      tm[1] = cadd(tm[1], cmul(mm, make_double2(-dy.y, dy.x)));
+      trg = cadd(trg, cadd(G[(long long)a * n + a], G[(long long)(N + a) * n + N + a]));
+    }
+  }
+  double v[NV];
+  for (int i = 0; i < 3; ++i) { v[2 * i] = qo[i].x; v[2 * i + 1] = qo[i].y; }
+  for (int i = 0; i < 2; ++i) {
+    v[6 + 2 * i] = tq[i].x; v[7 + 2 * i] = tq[i].y;
+    v[10 + 2 * i] = tm[i].x; v[11 + 2 * i] = tm[i].y;
+  }
+  v[14] = trg.x;
+  v[15] = trg.y;
+  for (int i = 0; i < NV; ++i) {
+    double s = v[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[NV];
+    for (int i = 0; i < NV; ++i) r[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    const double2 Qx = make_double2(r[0], r[1]), Qy = make_double2(r[2], r[3]), Qz = make_double2(r[4], r[5]);
+    const double2 txq = make_double2(r[6], r[7]), tyq = make_double2(r[8], r[9]);
+    const double2 txm = make_double2(r[10], r[11]), tym = make_double2(r[12], r[13]);
+    const double2 f2tr = make_double2(F * F * r[14], F * F * r[15]);
+    double2* o = out + ((long long)z * nql + iq) * 5;
+    o[0] = cadd(cscale(cmul(txq, txm), 4.0), cscale(csub(f2tr, Qx), 2.0));
+    o[1] = cadd(cscale(cmul(tyq, tym), 4.0), cscale(csub(f2tr, Qy), 2.0));
+    o[2] = o[3] = o[4] = cscale(csub(f2tr, Qz), 2.0);
+  }
+}
+void launch_structure_factors(const double2* G, long long sG, int N, const int* qxy, int nql, double2* out,
+                              int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(sq_kernel, dim3(nql, nchain), dim3(256), 0, s, G, sG, N, qxy, nql, out);
+  cfqmc_post_launch("sq_kernel");
+}

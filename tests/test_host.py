@@ -151,3 +151,19 @@ def test_gap_fit_recovers_a_cosh_correlator():
     n = np.array([16, 36, 64, 100, 144])
     z, _ = dynamic_exponent(n, 2.0 * n ** -0.5)
     assert abs(z - 1.0) < 1e-12
+
+
+def test_order_parameters_and_correlation_ratio():
+    """Component sums and normalisations on hand-made S^i: all components
+    equal gives m^2_SO(5) = m^2_VBS = m^2_AFM; a flat S(q) gives R = 0 and a
+    delta peak at Q gives R = 1."""
+    from paper_2605_03700_amd.analysis import correlation_ratio, order_parameters
+    n = 6
+    s = np.full(5, 7.2) + 0.3j
+    a, b, c = order_parameters(s, n)
+    assert abs(a - 7.2 / 36) < 1e-15 and abs(b - a) < 1e-15 and abs(c - a) < 1e-15
+    s2 = np.array([[2.0, 4.0, 1.0, 1.0, 4.0]])
+    a, b, c = order_parameters(s2, 2)
+    assert np.allclose([a[0], b[0], c[0]], [12.0 / 20, 6.0 / 8, 6.0 / 12])
+    assert correlation_ratio(3.0, 3.0) == 0.0 and correlation_ratio(3.0, 0.0) == 1.0
+    assert abs(correlation_ratio(4.0, 1.0) - 0.75) < 1e-15
