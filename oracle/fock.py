@@ -108,3 +108,50 @@ def bilinear(cs, M):
     for x, y in nz:
         out += M[x, y] * (cs[x].T @ cs[y])
     return out
+
+
+def density_operator_sphere(cs, n_phi, l, m, gamma, background):
+    """n^Gamma_{l,m} on the sphere (eq. sphere density operator): sum over
+    orbitals k and flavours a, b of the 3j weight times (c+_{k,a} Gamma_ab
+    c_{k',b} - background), m_{k'} = m_k + m, background -2 per orbital for
+    Gamma^0 and m = 0."""
+    from .sphere import density_matrix
+    W = density_matrix(l, m, n_phi)
+    dim = cs[0].shape[0]
+    out = np.zeros((dim, dim), dtype=complex)
+    for r, c in np.argwhere(W != 0):
+        for a in range(4):
+            for b in range(4):
+                if gamma[a, b] != 0:
+                    out += W[r, c] * gamma[a, b] * (cs[mode(n_phi, r + 1, a)].T @ cs[mode(n_phi, c + 1, b)])
+        if background and m == 0 and r == c:
+            out -= 2.0 * W[r, c] * np.eye(dim)
+    return out
+
+
+def component_operators_sphere(cs, n_phi, comps, o2, background):
+    """Hermitian HS components of one Fierz channel on the sphere:
+    sqrt(2) n_{l,0}, n_{l,m} + n_{l,m}^+, i (n_{l,m} - n_{l,m}^+)."""
+    gamma = np.kron(o2, PAULI[0])
+    out = []
+    for kind, l, m in comps:
+        nq = density_operator_sphere(cs, n_phi, l, m, gamma, background)
+        if kind == 'S':
+            out.append(np.sqrt(2.0) * nq)
+        else:
+            nmq = nq.conj().T
+            out.append(nq + nmq if kind == 'A' else 1j * (nq - nmq))
+    return out
+
+
+def hamiltonian_sphere(cs, n_phi, coef, gammas, background_first):
+    """sum_i coef_i sum_{l,m} n^{G_i}_{l,m} (n^{G_i}_{l,m})^+ over every (l, m),
+    l <= 2s (the sphere's pair n_q n_{-q})."""
+    from .sphere import momenta
+    dim = cs[0].shape[0]
+    H = np.zeros((dim, dim), dtype=complex)
+    for i, gm in enumerate(gammas):
+        for (l, m) in momenta(n_phi):
+            a = density_operator_sphere(cs, n_phi, l, m, gm, background_first and i == 0)
+            H += coef[i] * (a @ a.conj().T)
+    return H

@@ -23,6 +23,7 @@ Q_PAPER = 0      # all integer (qx,qy) with exp(-2 pi |q|^2/(4N)) > 0.01
 Q_RADIUS = 1     # |q| l_B <= q_max
 Q_BZ = 2         # the N^2 momenta modulo N, representatives in (-N/2, N/2]
 Q_LIST = 3       # explicit list, closed under q -> -q
+Q_SPHERE = 4     # spherical regularisation: every (l, m), l <= 2s (oracle/sphere.py)
 
 PAULI = {
     0: np.eye(2, dtype=complex),
@@ -153,10 +154,16 @@ class Model:
         self.l_tau = int(l_tau)
         self.dtau = float(dtau)
         self.u0, self.uk, self.un = float(u0), float(uk), float(un)
-        self.comps = components(n_phi, q_mode, q_max, q_list)
+        self.sphere = q_mode == Q_SPHERE
+        if self.sphere:
+            from . import sphere
+            self.comps = sphere.components(n_phi)
+            self.qmats = np.stack([sphere.component_matrix(k, l, m, n_phi) for (k, l, m) in self.comps])
+        else:
+            self.comps = components(n_phi, q_mode, q_max, q_list)
+            self.qmats = np.stack([component_matrix(k, qx, qy, n_phi) for (k, qx, qy) in self.comps])
         self.n_q = len(self.comps)
-        self.qmats = np.stack([component_matrix(k, qx, qy, n_phi) for (k, qx, qy) in self.comps])
-        # background c-number of each component: -2 tr(q_c) (torus density operator)
+        # background c-number of each component: -2 tr(q_c) (density operator)
         self.beta = np.array([-2.0 * np.trace(q) for q in self.qmats])
         self.o, self.g, self.alpha = channel_table(u0, uk, un, dtau)
         self.n = 2 * self.n_phi

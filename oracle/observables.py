@@ -25,31 +25,39 @@ def gamma_4n(gamma, n_phi):
     return np.kron(g, np.eye(n_phi))
 
 
-def structure_factor(G2n, n_phi, gamma, qx=0, qy=0):
-    """S_q for one Gamma from the spin-block G (G_4N = 1 kron G)."""
+def _orbital_density(n_phi, qx, qy, sphere):
+    if sphere:
+        from .sphere import density_matrix
+        return density_matrix(qx, qy, n_phi)        # (l, m) on the sphere
+    return m_matrix(qx, qy, n_phi)
+
+
+def structure_factor(G2n, n_phi, gamma, qx=0, qy=0, sphere=False):
+    """S_q for one Gamma from the spin-block G (G_4N = 1 kron G); on the
+    sphere (qx, qy) is (l, m) and n_{-q} is n_{l,m}^dagger."""
     G4 = np.kron(np.eye(2), G2n)
     n4 = 4 * n_phi
     perm = [0, 2, 1, 3]
     g = gamma[np.ix_(perm, perm)]
-    A = np.kron(g, m_matrix(qx, qy, n_phi))
+    A = np.kron(g, _orbital_density(n_phi, qx, qy, sphere))
     B = A.conj().T
     I = np.eye(n4)
     return np.trace(A @ (I - G4)) * np.trace(B @ (I - G4)) + np.trace(A @ G4 @ B @ (I - G4))
 
 
-def so5_observables(G2n, n_phi):
-    """Returns (S^1..S^5 at q=0, m^2_SO(5)) for one configuration."""
-    s = np.array([structure_factor(G2n, n_phi, gm) for gm in gamma_matrices()])
+def so5_observables(G2n, n_phi, sphere=False):
+    """Returns (S^1..S^5 at q=0 (l = m = 0 on the sphere), m^2_SO(5)) for one configuration."""
+    s = np.array([structure_factor(G2n, n_phi, gm, sphere=sphere) for gm in gamma_matrices()])
     return s, s.real.sum() / (5.0 * n_phi * n_phi)
 
 
-def _density_4n(gamma, n_phi, qx=0, qy=0):
+def _density_4n(gamma, n_phi, qx=0, qy=0, sphere=False):
     perm = [0, 2, 1, 3]
     g = gamma[np.ix_(perm, perm)]
-    return np.kron(g, m_matrix(qx, qy, n_phi))
+    return np.kron(g, _orbital_density(n_phi, qx, qy, sphere))
 
 
-def so5_correlator(Gt0, G0t, Gtt, G00, n_phi):
+def so5_correlator(Gt0, G0t, Gtt, G00, n_phi, sphere=False):
     """<n^{Gamma^i}_{q=0}(tau) n^{Gamma^i}_{q=0}(0)> for i = 1..5 (complex, one
     configuration) and their mean m^2_SO(5)(tau, q=0), from the spin-block
     Green's functions G(tau,0), G(0,tau), G(tau,tau) and G(0,0)."""
@@ -59,7 +67,7 @@ def so5_correlator(Gt0, G0t, Gtt, G00, n_phi):
     I = np.eye(4 * n_phi)
     c = []
     for gm in gamma_matrices():
-        A = _density_4n(gm, n_phi)
+        A = _density_4n(gm, n_phi, sphere=sphere)
         B = A.conj().T                     # n_{-q} at q = 0
         c.append(np.trace(A @ (I - Xtt)) * np.trace(B @ (I - X00)) - np.trace(A @ Xt0 @ B @ X0t))
     c = np.array(c)
