@@ -52,7 +52,13 @@ enum {
   CFQMC_ENOTIMPL = -6
 };
 
-enum { CFQMC_Q_PAPER = 0, CFQMC_Q_RADIUS = 1, CFQMC_Q_BZ = 2, CFQMC_Q_LIST = 3 };
+/* Momentum sets. The first four are torus geometries (Methods, toric
+ * regularization). CFQMC_Q_SPHERE is the spherical regularization (Methods):
+ * N_phi = 2s + 1 orbitals m_k = k - 1 - s, density operators n_{l,m} from
+ * Wigner 3j symbols for every 0 <= l <= 2s, |m| <= l (N_phi^2 per channel);
+ * components per channel sqrt(2) n_{l,0} (l = 0..2s), then for m = 1..2s and
+ * l = m..2s the pair n_{l,m} + n_{l,m}^+ and i (n_{l,m} - n_{l,m}^+). */
+enum { CFQMC_Q_PAPER = 0, CFQMC_Q_RADIUS = 1, CFQMC_Q_BZ = 2, CFQMC_Q_LIST = 3, CFQMC_Q_SPHERE = 4 };
 /* Precision of the slice work. FP64: everything in FP64. MIXED: the wraps and
  * the drift frames in complex FP32 on MFMA with FP64 accumulation (FP64 master
  * G), the Woodbury product M in FP64. MIXED_ALL: M in FP32 as well. LU,
@@ -67,7 +73,7 @@ typedef struct {
   double dtau;           /* Trotter step (eq. Trotter decomposition) */
   double u0, uk, un;     /* couplings U_0, U_K, U_N (Results: U_0 = 1, SO(5) line U_K = U_N = u) */
   int32_t q_mode;        /* CFQMC_Q_*: paper cutoff exp(-2 pi |q|^2/(4N)) > 0.01, |q| l_B <= q_max,
-                            the N^2 Brillouin-zone momenta, or an explicit list */
+                            the N^2 Brillouin-zone momenta, an explicit list, or the sphere */
   double q_max;          /* CFQMC_Q_RADIUS only */
   const int32_t* q_list; /* CFQMC_Q_LIST: pairs (qx, qy), closed under q -> -q; host, read at create */
   int32_t n_q_list;
@@ -174,7 +180,8 @@ int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel);
  * depends on q itself, the orbital shift on qy mod N_phi); 1 <= n_q <= 4096.
  * out: host [n_chains][n_q][5] complex128 (re/im interleaved), owned by the
  * caller. Per configuration the values are complex; their average is real.
- * Call between sweeps. Allocates small temporaries. Synchronises. */
+ * Torus geometries only (CFQMC_ENOTIMPL on the sphere). Call between
+ * sweeps. Allocates small temporaries. Synchronises. */
 int cfqmc_structure_factors(cfqmc_ctx* c, const int32_t* q_xy, int32_t n_q, double* out);
 
 /* ln of the fermion weight exp(sum_tau c_tau) det(1 + B(beta,0))^2 of one chain

@@ -55,8 +55,14 @@ def wigner3j(tj1, tj2, tj3, tm1, tm2, tm3):
     for k in range(max(0, -x1, -x2), min(x3, x4, x5) + 1):
         den = f(k) * f(x1 + k) * f(x2 + k) * f(x3 - k) * f(x4 - k) * f(x5 - k)
         s += Fraction((-1) ** k, den)
+    if s == 0:
+        return 0.0
     sign = -1 if ((tj1 - tj2 - tm3) // 2) % 2 else 1
-    return sign * math.sqrt(tri * pre) * float(s) if s != 0 else 0.0
+    if s < 0:
+        sign = -sign
+    # the square tri * pre * s^2 is a rational of moderate size (|3j| <= 1)
+    # even where tri * pre alone exceeds the float range
+    return sign * math.sqrt(float(tri * pre * s * s))
 
 
 def orbital_m2(n_phi):

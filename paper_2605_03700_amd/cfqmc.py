@@ -12,7 +12,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcfqmc.so")
 
-Q_PAPER, Q_RADIUS, Q_BZ, Q_LIST = 0, 1, 2, 3
+Q_PAPER, Q_RADIUS, Q_BZ, Q_LIST, Q_SPHERE = 0, 1, 2, 3, 4
 FP64, MIXED, MIXED_ALL = 0, 1, 2
 
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "ESTATE", -6: "ENOTIMPL"}

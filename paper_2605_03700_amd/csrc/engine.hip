@@ -31,6 +31,11 @@ namespace {
 struct HostTables {
   std::vector<int> comp_kind, comp_qx, comp_qy;   // kind 0 S, 1 A, 2 C
   std::vector<double> comp_F, beta;
+  std::vector<long long> comp_r2;   // |q|^2 (torus) or l (l + 1) (sphere): shells of the learned features
+  // sphere: per component the orbital weights w[c * N + r] = n_{l,m}[r, r + m]
+  // (q_x = 0, q_y = -m and F = 1 in the tables, so phases are 1 and the
+  // weights carry the density operator)
+  std::vector<double> comp_w;
   // h table
   std::vector<int> hoff, h_cre, h_cim, h_qx, h_qy, h_dag;
   std::vector<double> h_sgn, h_scale, h_F;
@@ -49,84 +54,157 @@ int wrap_bz(int v, int N) {
   return r > N / 2 ? r - N : r;
 }
 
+// Orbital weights of the sphere's density operators (Methods, spherical
+// regularization): n_{l,m}[r, r + m] for 0 <= m <= l <= 2s = N - 1, rows r of
+// the LLL orbitals m_r = r - s, in W[(l * N + m) * N + r] (zero where r + m >= N),
+// from the printed 3j form
+//   n_{l,m}[r, r+m] = (-1)^(r+m) (2s+1) sqrt(2l+1)/2 3j(s l s; -m_r, -m, m_r+m) 3j(s l s; -s, 0, s).
+// Each 3j family f(l) = 3j(s l s; a, b, c) over l = |b|..2s (cyclically
+// 3j(l s s; b, c, a)) follows from the Schulten-Gordon three-term recursion
+//   l A(l+1) f(l+1) + B(l) f(l) + (l+1) A(l) f(l-1) = 0,
+//   A(l) = sqrt(l^2 ((2s+1)^2 - l^2)(l^2 - b^2)), B(l) = -(2l+1) l(l+1)(c - a),
+// run downwards from l = 2s (A(2s+1) = 0) in extended precision, normalised by
+// sum_l (2l+1) f(l)^2 = 1, with sign f(2s) = (-1)^(b) (the closed form at the
+// largest l).
+std::vector<double> sphere_weights(int N) {
+  typedef long double R;
+  const int ts = N - 1;
+  std::vector<double> W((size_t)N * N * N, 0.0);
+  // family of 3j(s l s; a, b, c) with doubled a, c and integer b = -m
+  auto family = [&](int ta, int m, std::vector<R>& f) {
+    const int b = -m, lmin = std::abs(b);
+    f.assign(N + 1, 0.0L);
+    const R a = ta / 2.0L, c = -(a + b);
+    auto A = [&](int l) { return std::sqrt((R)l * l * ((R)(ts + 1) * (ts + 1) - (R)l * l) * ((R)l * l - (R)b * b)); };
+    auto Bc = [&](int l) { return -(2.0L * l + 1) * l * (l + 1.0L) * (c - a); };
+    f[ts] = 1.0L;
+    for (int l = ts; l > lmin; --l) f[l - 1] = -(l * A(l + 1) * f[l + 1] + Bc(l) * f[l]) / ((l + 1) * A(l));
+    R nrm = 0.0L;
+    for (int l = lmin; l <= ts; ++l) nrm += (2.0L * l + 1) * f[l] * f[l];
+    const R sc = ((std::abs(b) % 2) ? -1.0L : 1.0L) / std::sqrt(nrm);
+    for (int l = lmin; l <= ts; ++l) f[l] *= sc;
+  };
+  std::vector<R> g, f;
+  family(-ts, 0, g);   // 3j(s l s; -s, 0, s)
+  for (int m = 0; m < N; ++m)
+    for (int r = 0; r + m < N; ++r) {
+      const int tmr = 2 * r - ts;   // 2 m_r
+      family(-tmr, m, f);           // 3j(s l s; -m_r, -m, m_r + m)
+      for (int l = m; l <= ts; ++l) {
+        const R v = (((r + m) % 2) ? -1.0L : 1.0L) * (R)(ts + 1) * std::sqrt(2.0L * l + 1) / 2.0L * f[l] * g[l];
+        W[((size_t)l * N + m) * N + r] = (double)v;
+      }
+    }
+  return W;
+}
+
+// Components on the sphere, per channel: sqrt(2) n_{l,0} for l = 0..2s, then
+// for m = 1..2s and l = m..2s the pair n_{l,m} + n_{l,m}^+ (A) and
+// i (n_{l,m} - n_{l,m}^+) (C). Background -2 tr of each m = 0 component.
+void sphere_components(int N, HostTables& T) {
+  const std::vector<double> W = sphere_weights(N);
+  auto add = [&](int kind, int l, int m) {
+    T.comp_kind.push_back(kind); T.comp_qx.push_back(0); T.comp_qy.push_back(-m);
+    T.comp_F.push_back(1.0);
+    T.comp_r2.push_back((long long)l * (l + 1));
+    double tr = 0.0;
+    for (int r = 0; r < N; ++r) {
+      const double w = W[((size_t)l * N + m) * N + r];
+      T.comp_w.push_back(w);
+      if (m == 0) tr += w;
+    }
+    T.beta.push_back(kind == 0 ? -2.0 * std::sqrt(2.0) * tr : 0.0);
+  };
+  for (int l = 0; l < N; ++l) add(0, l, 0);
+  for (int m = 1; m < N; ++m)
+    for (int l = m; l < N; ++l) { add(1, l, m); add(2, l, m); }
+}
+
 // Momentum set and components (see cfqmc.h for the ordering).
 bool build_components(const cfqmc_params& p, HostTables& T, std::string& err) {
   const int N = p.n_phi;
-  std::vector<std::pair<int, int>> qs;
-  if (p.q_mode == CFQMC_Q_PAPER || p.q_mode == CFQMC_Q_RADIUS) {
-    int R;
-    if (p.q_mode == CFQMC_Q_PAPER) R = (int)std::ceil(std::sqrt(4.0 * N * std::log(100.0) / (2.0 * M_PI))) + 1;
-    else R = (int)std::ceil(p.q_max * std::sqrt(N / (2.0 * M_PI))) + 1;
-    for (int qy = -R; qy <= R; ++qy)
-      for (int qx = -R; qx <= R; ++qx) {
-        const double q2 = (double)(qx * qx + qy * qy);
-        bool keep;
-        if (p.q_mode == CFQMC_Q_PAPER) keep = std::exp(-2.0 * M_PI * q2 / (4.0 * N)) > 0.01;
-        else keep = (2.0 * M_PI / N) * q2 <= p.q_max * p.q_max * (1 + 1e-12);
-        if (keep) qs.push_back({qx, qy});
-      }
-  } else if (p.q_mode == CFQMC_Q_BZ) {
-    const int lo = -(N / 2) + (N % 2 == 0 ? 1 : 0), hi = N / 2;
-    for (int qy = lo; qy <= hi; ++qy)
-      for (int qx = lo; qx <= hi; ++qx) qs.push_back({qx, qy});
-  } else if (p.q_mode == CFQMC_Q_LIST) {
-    if (!p.q_list || p.n_q_list <= 0) { err = "q_list missing"; return false; }
-    for (int i = 0; i < p.n_q_list; ++i) qs.push_back({p.q_list[2 * i], p.q_list[2 * i + 1]});
-    for (auto& q : qs) {
-      if (std::count(qs.begin(), qs.end(), q) != 1) { err = "q_list has duplicates"; return false; }
-      if (std::find(qs.begin(), qs.end(), std::make_pair(-q.first, -q.second)) == qs.end()) {
-        err = "q_list not closed under q -> -q";
-        return false;
-      }
-    }
+  if (p.q_mode == CFQMC_Q_SPHERE) {
+    sphere_components(N, T);
   } else {
-    err = "unknown q_mode";
-    return false;
-  }
-  // (kind 'P' pair or 'S' self) items, q = 0 first
-  struct Item { int self, qx, qy; };
-  std::vector<Item> items;
-  bool has0 = false;
-  for (auto& q : qs) {
-    if (q.first == 0 && q.second == 0) { has0 = true; continue; }
-    if (p.q_mode == CFQMC_Q_BZ) {
-      const int px = wrap_bz(-q.first, N), py = wrap_bz(-q.second, N);
-      if (px == q.first && py == q.second) items.push_back({1, q.first, q.second});
-      else if (std::make_pair(q.second, q.first) > std::make_pair(py, px)) items.push_back({0, q.first, q.second});
-    } else if (q.second > 0 || (q.second == 0 && q.first > 0)) {
-      items.push_back({0, q.first, q.second});
+    std::vector<std::pair<int, int>> qs;
+    if (p.q_mode == CFQMC_Q_PAPER || p.q_mode == CFQMC_Q_RADIUS) {
+      int R;
+      if (p.q_mode == CFQMC_Q_PAPER) R = (int)std::ceil(std::sqrt(4.0 * N * std::log(100.0) / (2.0 * M_PI))) + 1;
+      else R = (int)std::ceil(p.q_max * std::sqrt(N / (2.0 * M_PI))) + 1;
+      for (int qy = -R; qy <= R; ++qy)
+        for (int qx = -R; qx <= R; ++qx) {
+          const double q2 = (double)(qx * qx + qy * qy);
+          bool keep;
+          if (p.q_mode == CFQMC_Q_PAPER) keep = std::exp(-2.0 * M_PI * q2 / (4.0 * N)) > 0.01;
+          else keep = (2.0 * M_PI / N) * q2 <= p.q_max * p.q_max * (1 + 1e-12);
+          if (keep) qs.push_back({qx, qy});
+        }
+    } else if (p.q_mode == CFQMC_Q_BZ) {
+      const int lo = -(N / 2) + (N % 2 == 0 ? 1 : 0), hi = N / 2;
+      for (int qy = lo; qy <= hi; ++qy)
+        for (int qx = lo; qx <= hi; ++qx) qs.push_back({qx, qy});
+    } else if (p.q_mode == CFQMC_Q_LIST) {
+      if (!p.q_list || p.n_q_list <= 0) { err = "q_list missing"; return false; }
+      for (int i = 0; i < p.n_q_list; ++i) qs.push_back({p.q_list[2 * i], p.q_list[2 * i + 1]});
+      for (auto& q : qs) {
+        if (std::count(qs.begin(), qs.end(), q) != 1) { err = "q_list has duplicates"; return false; }
+        if (std::find(qs.begin(), qs.end(), std::make_pair(-q.first, -q.second)) == qs.end()) {
+          err = "q_list not closed under q -> -q";
+          return false;
+        }
+      }
+    } else {
+      err = "unknown q_mode";
+      return false;
     }
-  }
-  std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-    return std::make_pair(a.qy, a.qx) < std::make_pair(b.qy, b.qx);
-  });
-  if (has0) { T.comp_kind.push_back(0); T.comp_qx.push_back(0); T.comp_qy.push_back(0); }
-  for (auto& it : items) {
-    if (it.self) { T.comp_kind.push_back(0); T.comp_qx.push_back(it.qx); T.comp_qy.push_back(it.qy); }
-    else {
-      for (int k = 1; k <= 2; ++k) { T.comp_kind.push_back(k); T.comp_qx.push_back(it.qx); T.comp_qy.push_back(it.qy); }
+    // (kind 'P' pair or 'S' self) items, q = 0 first
+    struct Item { int self, qx, qy; };
+    std::vector<Item> items;
+    bool has0 = false;
+    for (auto& q : qs) {
+      if (q.first == 0 && q.second == 0) { has0 = true; continue; }
+      if (p.q_mode == CFQMC_Q_BZ) {
+        const int px = wrap_bz(-q.first, N), py = wrap_bz(-q.second, N);
+        if (px == q.first && py == q.second) items.push_back({1, q.first, q.second});
+        else if (std::make_pair(q.second, q.first) > std::make_pair(py, px)) items.push_back({0, q.first, q.second});
+      } else if (q.second > 0 || (q.second == 0 && q.first > 0)) {
+        items.push_back({0, q.first, q.second});
+      }
+    }
+    std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+      return std::make_pair(a.qy, a.qx) < std::make_pair(b.qy, b.qx);
+    });
+    if (has0) { T.comp_kind.push_back(0); T.comp_qx.push_back(0); T.comp_qy.push_back(0); }
+    for (auto& it : items) {
+      if (it.self) { T.comp_kind.push_back(0); T.comp_qx.push_back(it.qx); T.comp_qy.push_back(it.qy); }
+      else {
+        for (int k = 1; k <= 2; ++k) { T.comp_kind.push_back(k); T.comp_qx.push_back(it.qx); T.comp_qy.push_back(it.qy); }
+      }
+    }
+    const int nq = (int)T.comp_kind.size();
+    if (nq == 0) { err = "empty momentum set"; return false; }
+    T.comp_F.resize(nq);
+    T.beta.resize(nq);
+    T.comp_r2.resize(nq);
+    for (int c = 0; c < nq; ++c) {
+      T.comp_r2[c] = (long long)T.comp_qx[c] * T.comp_qx[c] + (long long)T.comp_qy[c] * T.comp_qy[c];
+      const int qx = T.comp_qx[c], qy = T.comp_qy[c];
+      const double F = form_factor(qx, qy, N);
+      T.comp_F[c] = F;
+      // background c-number -2 tr(q_c): only shifts q_y = 0 (mod N) have a diagonal
+      double tr_re = 0.0, tr_im = 0.0;
+      if (((qy % N) + N) % N == 0) {
+        for (int k = 1; k <= N; ++k) {
+          const double a = M_PI * (double)((2 * k - qy) * qx) / N;
+          tr_re += F * std::cos(a);
+          tr_im += F * std::sin(a);
+        }
+      }
+      const int kind = T.comp_kind[c];
+      T.beta[c] = kind == 0 ? -2.0 * std::sqrt(2.0) * tr_re : (kind == 1 ? -4.0 * tr_re : 4.0 * tr_im);
     }
   }
   const int nq = (int)T.comp_kind.size();
-  if (nq == 0) { err = "empty momentum set"; return false; }
-  T.comp_F.resize(nq);
-  T.beta.resize(nq);
-  for (int c = 0; c < nq; ++c) {
-    const int qx = T.comp_qx[c], qy = T.comp_qy[c];
-    const double F = form_factor(qx, qy, N);
-    T.comp_F[c] = F;
-    // background c-number -2 tr(q_c): only shifts q_y = 0 (mod N) have a diagonal
-    double tr_re = 0.0, tr_im = 0.0;
-    if (((qy % N) + N) % N == 0) {
-      for (int k = 1; k <= N; ++k) {
-        const double a = M_PI * (double)((2 * k - qy) * qx) / N;
-        tr_re += F * std::cos(a);
-        tr_im += F * std::sin(a);
-      }
-    }
-    const int kind = T.comp_kind[c];
-    T.beta[c] = kind == 0 ? -2.0 * std::sqrt(2.0) * tr_re : (kind == 1 ? -4.0 * tr_re : 4.0 * tr_im);
-  }
   // h table grouped by shift d = (row - col) mod N
   std::vector<std::vector<int>> by_shift(N);
   struct HT { int cre, cim, qx, qy, dag; double sgn, scale, F; };
@@ -405,6 +483,12 @@ void exps(cfqmc_ctx* c, const double2* hb, int nent, const double2* alpha, int a
   }
 }
 
+// The q = 0 density operator is a multiple of the identity on the orbitals:
+// F(0) = 1 / (4 pi sqrt N) on the torus, the l = m = 0 weight on the sphere.
+double q0_weight(const cfqmc_ctx* c) {
+  return c->ht.comp_w.empty() ? 1.0 / (4.0 * M_PI * std::sqrt((double)c->N)) : c->ht.comp_w[0];
+}
+
 // UDT accumulation: (Uo, Do, To) <- decomposition of op(C) * (Ui Di Ti), all [chain] batched.
 void udt_acc(cfqmc_ctx* c, const double2* C, long long sC, int opC, const double2* Ui, const double* Di,
              const double2* Ti, double2* Uo, double* Do, double2* To, long long sU, long long sD) {
@@ -500,7 +584,7 @@ void displaced_pass(cfqmc_ctx* c, int tau_stop, double2* corr, double* err, doub
   const long long nn = c->nn, NN = c->NN, sPQ = (long long)c->L * 8 * NN;
   double2* cur[3] = {c->Fp[0], c->Fp[1], c->Fp[2]};
   double2* alt[3] = {c->F[0], c->F[1], c->F[2]};
-  const double F0 = 1.0 / (4.0 * M_PI * std::sqrt((double)c->N));
+  const double F0 = q0_weight(c);
   const int last = tau_stop < 0 ? c->L : tau_stop;
   for (int tau = 0; tau <= last; ++tau) {
     const bool boundary = tau % c->nstab == 0 || tau == c->L;
@@ -616,6 +700,12 @@ int build_model_dev(cfqmc_ctx* c) {
   m.nrow = (int)T.t_qy.size();
   m.toff = p_toff; m.t_qy = p_tqy; m.t_qx = p_tqx; m.t_kind = p_tk; m.t_comp = p_tc; m.t_F = p_tF;
   m.beta = p_beta; m.phase = p_ph;
+  m.cw = nullptr;
+  if (!T.comp_w.empty()) {
+    double* p_cw;
+    if (upload(c, &p_cw, T.comp_w)) return CFQMC_ENOMEM;
+    m.cw = p_cw;
+  }
   return CFQMC_OK;
 }
 
@@ -1183,7 +1273,7 @@ void sweep_end(cfqmc_ctx* c) {
   const int B = c->nch;
   launch_eps_update(c->eps, c->acc_count, c->L, c->p.r0, c->p.deps, c->p.eps_min, c->p.eps_max, c->p.adapt_eps, B,
                     c->s);
-  launch_observables(c->G, c->nn, c->N, 1.0 / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, B, c->s);
+  launch_observables(c->G, c->nn, c->N, q0_weight(c), c->obs, 8, B, c->s);
   restack_right(c);
   if (c->series_len < c->series_cap) {
     // per-sweep series for the autocorrelation: m^2_SO(5), the action and the
@@ -1412,6 +1502,7 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
 int cfqmc_structure_factors(cfqmc_ctx* c, const int32_t* q_xy, int32_t n_q, double* out) {
   if (!c || !q_xy || !out || n_q <= 0 || n_q > 4096) return CFQMC_EINVAL;
   if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  if (!c->ht.comp_w.empty()) { c->err = "structure factors at q != 0: torus only"; return CFQMC_ENOTIMPL; }
   int* dq = nullptr;
   double2* dout = nullptr;
   const long long cnt = (long long)c->nch * n_q * 5;
@@ -1444,7 +1535,7 @@ int cfqmc_logdet(cfqmc_ctx* c, int32_t chain, double* re, double* im) {
 int cfqmc_observables(cfqmc_ctx* c, int32_t chain, double* s_q0, double* m2) {
   if (!c || chain < 0 || chain >= c->nch) return CFQMC_EINVAL;
   if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
-  launch_observables(c->G, c->nn, c->N, 1.0 / (4.0 * M_PI * std::sqrt((double)c->N)), c->obs, 8, c->nch, c->s);
+  launch_observables(c->G, c->nn, c->N, q0_weight(c), c->obs, 8, c->nch, c->s);
   std::vector<double> o(8);
   HIPCHK(hipStreamSynchronize(c->s));
   HIPCHK(hipMemcpy(o.data(), c->obs + chain * 8, 8 * sizeof(double), hipMemcpyDeviceToHost));
@@ -1708,10 +1799,9 @@ int cfqmc_slmc_create(cfqmc_ctx* c, const cfqmc_slmc_params* pp, cfqmc_slmc** ou
   const HostTables& T = c->ht;
   std::vector<int> sh(s->nq), wb(s->nw);
   long long r2max = 0;
-  for (int q = 0; q < s->nq; ++q)
-    r2max = std::max(r2max, (long long)T.comp_qx[q] * T.comp_qx[q] + (long long)T.comp_qy[q] * T.comp_qy[q]);
+  for (int q = 0; q < s->nq; ++q) r2max = std::max(r2max, T.comp_r2[q]);
   for (int q = 0; q < s->nq; ++q) {
-    const long long r2 = (long long)T.comp_qx[q] * T.comp_qx[q] + (long long)T.comp_qy[q] * T.comp_qy[q];
+    const long long r2 = T.comp_r2[q];
     sh[q] = (int)((s->nqb * r2) / (r2max + 1));
   }
   for (int w = 0; w < s->nw; ++w) wb[w] = (int)(((long long)s->nwb * w) / s->nw);

@@ -121,6 +121,7 @@ struct ModelDev {
   const double* t_F;
   const double* beta;       // background c-number per component [nq]
   const double2* phase;     // exp(i pi m / N), m = 0..2N-1
+  const double* cw;         // sphere: orbital weights [nq][N] replacing F e^{i phase} (nullptr on the torus)
 };
 
 struct ChainDev {

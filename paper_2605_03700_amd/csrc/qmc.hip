@@ -34,7 +34,7 @@
 __global__ void __launch_bounds__(256) build_h_kernel(ModelDev m, const double* phi_all, long long sphi,
                                                       double2* h_all, long long sh, int nbatch) {
   __shared__ double2 s_w[BH_TC][4 * BH_CPB];
-  __shared__ int s_qx[BH_TC], s_qy[BH_TC], s_dag[BH_TC];
+  __shared__ int s_qx[BH_TC], s_qy[BH_TC], s_dag[BH_TC], s_cmp[BH_TC];
   __shared__ double2 s_ph[2 * BH_MAXN];
   const int d = blockIdx.x, z0 = blockIdx.y * BH_CPB, N = m.N, N2 = 2 * N;
   const int r = threadIdx.x;
@@ -63,16 +63,22 @@ __global__ void __launch_bounds__(256) build_h_kernel(ModelDev m, const double* 
       s_qx[k] = m.h_qx[c0 + k];
       s_qy[k] = m.h_qy[c0 + k];
       s_dag[k] = m.h_dag[c0 + k];
+      s_cmp[k] = m.h_cre[c0 + k];
     }
     __syncthreads();
     if (r < N) {
       for (int k = 0; k < cnt; ++k) {
         const int qx = s_qx[k], qy = s_qy[k];
         const int row = s_dag[k] ? col : r;        // orbital whose phase enters
-        int mm = ((2 * (row + 1) - qy) * qx) % N2;
-        if (mm < 0) mm += N2;
-        double2 ph = s_ph[mm];
-        if (s_dag[k]) ph.y = -ph.y;
+        double2 ph;
+        if (m.cw) {
+          ph = make_double2(m.cw[(long long)s_cmp[k] * N + row], 0.0);   // real sphere weight
+        } else {
+          int mm = ((2 * (row + 1) - qy) * qx) % N2;
+          if (mm < 0) mm += N2;
+          ph = s_ph[mm];
+          if (s_dag[k]) ph.y = -ph.y;
+        }
 #pragma unroll
         for (int j = 0; j < 4 * BH_CPB; ++j) {
           const double2 w = s_w[k][j];
@@ -208,8 +214,9 @@ CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, do
     int st = (2 * qx) % N2;
     if (st < 0) st += N2;
     double tpx = 0.0, tpy = 0.0, tmx = 0.0, tmy = 0.0;
+    const double* cw = m.cw ? m.cw + (long long)m.t_comp[t] * N : nullptr;   // sphere weights
     for (int k = 0; k < N; ++k) {
-      const double2 p = ph[mm], a1 = d1[k], a2 = d2[k];
+      const double2 p = cw ? make_double2(cw[k], 0.0) : ph[mm], a1 = d1[k], a2 = d2[k];
       tpx += a1.x * p.x - a1.y * p.y;
       tpy += a1.x * p.y + a1.y * p.x;
       tmx += a2.x * p.x + a2.y * p.y;     // d2 conj(p)

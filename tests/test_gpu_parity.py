@@ -66,15 +66,16 @@ def test_green_and_logdet_at_init(n_phi, L, nstab, mode, qmax, u):
     g.close()
 
 
-def _replay_compare(CFQMC, n_phi, L, nstab, mode, qmax, u_list, precision, n_sweeps, tol_g, seed=7, eps0=0.4):
+def _replay_compare(CFQMC, n_phi, L, nstab, mode, qmax, u_list, precision, n_sweeps, tol_g, seed=7, eps0=0.4,
+                    dtau=0.1, **ctx_kw):
     nch = len(u_list)
-    models = [Model(n_phi, L, 0.1, u0=1.0, uk=u, un=u, q_mode=mode, q_max=qmax) for u in u_list]
+    models = [Model(n_phi, L, dtau, u0=1.0, uk=u, un=u, q_mode=mode, q_max=qmax) for u in u_list]
     nq = models[0].n_q
     phi = np.stack([synth.fields(seed + 10 * k, L, nq) for k in range(nch)])
     rp = np.stack([synth.replay(seed + 10 * k + 1, n_sweeps, L, nq) for k in range(nch)])
-    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=mode, q_max=qmax or 3.0, n_stab=nstab, eps0=eps0,
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=dtau, q_mode=mode, q_max=qmax or 3.0, n_stab=nstab, eps0=eps0,
               adapt_eps=True, precision=precision, n_chains=nch,
-              chain_u=[(1.0, u, u) for u in u_list], tile_cfg=1)
+              chain_u=[(1.0, u, u) for u in u_list], tile_cfg=1, **ctx_kw)
     g.init_fields(phi)
     chains = [dqmc.Chain(models[k], phi[k], eps0=eps0, adapt=True) for k in range(nch)]
     for sw in range(n_sweeps):
