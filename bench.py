@@ -33,7 +33,7 @@ PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFM
 TRAFFIC = {(100, 256, "mixed", 1): (166617.07 * 2.0 + 160000.0 * 1.0) * 1024}
 
 
-def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
+def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0, sphere=False):
     """The FP64 oracle timed on the host on a bounded sample of the same
     workload: a chain with the same N_phi, momentum set and couplings and at
     most 40 slices. Its sweep set-up (all slice exponentials and suffix
@@ -42,14 +42,14 @@ def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0):
     move), the oracle's full-sweep rate at any L."""
     import synth
     from oracle import dqmc
-    from oracle.model import Model
+    from oracle.model import Model, Q_PAPER, Q_SPHERE
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
     ls = min(l_tau, 40)
-    m = Model(n_phi, ls, dtau, u0=1.0, uk=u, un=u)
+    m = Model(n_phi, ls, dtau, u0=1.0, uk=u, un=u, q_mode=Q_SPHERE if sphere else Q_PAPER)
     phi = synth.fields(1, ls, m.n_q)
     rp = synth.replay(2, 1, ls, m.n_q)[0]
     # set-up plus one move, then set-up plus k moves: the difference gives the
@@ -112,6 +112,10 @@ def main():
     ap.add_argument("--learned-sweeps", type=int, default=12)
     ap.add_argument("--learned-epochs", type=int, default=30)
     ap.add_argument("--tile-cfg", type=int, default=-1)
+    ap.add_argument("--geometry", choices=["torus", "sphere"], default="torus",
+                    help="torus (paper momentum cutoff) or sphere (every (l, m), l <= 2s)")
+    ap.add_argument("--exp-squarings", type=int, default=2,
+                    help="max scaling-and-squaring steps of the slice exponentials (the sphere needs more)")
     ap.add_argument("--tau-sweeps", type=int, default=20, help="untimed sweeps after the timed ones for tau_int")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-chain FP64 reference sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -141,7 +145,7 @@ def main():
         return
     import numpy as np
     import torch
-    from paper_2605_03700_amd import Batch, FP64, MIXED, MIXED_ALL
+    from paper_2605_03700_amd import Batch, FP64, MIXED, MIXED_ALL, Q_PAPER, Q_SPHERE
     from paper_2605_03700_amd.analysis import tau_int_pooled
     assert torch.cuda.is_available(), "needs the GPU"
     prec = {"fp64": FP64, "mixed": MIXED, "mixed_all": MIXED_ALL}[args.precision]
@@ -152,9 +156,10 @@ def main():
     if args.chains % args.groups:
         raise SystemExit("--chains must be a multiple of --groups")
     nper = args.chains // args.groups
+    geo = dict(q_mode=Q_SPHERE if args.geometry == "sphere" else Q_PAPER, exp_squarings=args.exp_squarings)
     b = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
                     n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
-                    tile_cfg=args.tile_cfg) for k in range(args.groups)])
+                    tile_cfg=args.tile_cfg, **geo) for k in range(args.groups)])
     g = b.groups[0]
     progress("contexts created (tiles %s)" % (g.tile_config(),))
     b.init_fields()
@@ -177,10 +182,11 @@ def main():
         "value": value, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == FP64 else "f32+f64", "data": "synthetic",
-        "config": {"workload": "torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff n_q=%d, %d chain(s) in %d "
+        "config": {"workload": "%s N_phi=%d L_tau=%d dtau=%g u=%g %s n_q=%d, %d chain(s) in %d "
                                "stream group(s), FP64 recompute every %d slices"
-                               % (args.n_phi, args.l_tau, args.dtau, args.u, g.n_q, args.chains, args.groups,
-                                  args.n_stab),
+                               % (args.geometry, args.n_phi, args.l_tau, args.dtau, args.u,
+                                  "all (l, m)" if args.geometry == "sphere" else "paper cutoff", g.n_q,
+                                  args.chains, args.groups, args.n_stab),
                    "chains": args.chains, "groups": args.groups, "precision": args.precision, "n_q": g.n_q,
                    "tile_cfg": list(g.tile_config())},
         "acceptance": acc,
@@ -260,7 +266,7 @@ def main():
         # the same chains with every product in FP64 (warm-up sweep, then two timed sweeps)
         f = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
                         n_stab=args.n_stab, precision=FP64, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
-                        tile_cfg=args.tile_cfg) for k in range(args.groups)])
+                        tile_cfg=args.tile_cfg, **geo) for k in range(args.groups)])
         f.init_fields()
         f.sweep(1)
         dtf, _, gef = sweep_each(f, 2)
@@ -273,7 +279,7 @@ def main():
         # the plain path for comparison: one chain, FP64, same workload
         p = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
                         n_stab=args.n_stab, precision=FP64, eps0=0.3, adapt_eps=True, seed=99, n_chains=1,
-                        tile_cfg=args.tile_cfg)])
+                        tile_cfg=args.tile_cfg, **geo)])
         p.init_fields()
         p.sweep(1)
         dtp, stp, gep = sweep_each(p, 2)
@@ -285,7 +291,8 @@ def main():
         p.close()
         progress("one-chain FP64 reference done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds,
+                                           args.geometry == "sphere")
         progress("CPU oracle baseline done")
     print(json.dumps(out))
 

@@ -86,7 +86,7 @@ typedef struct {
   uint64_t seed;         /* Philox4x32-10 key of the proposal noise; seeds the host draw of initial fields */
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
-  int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential (default 2) */
+  int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential, 0..16 (default 2) */
   int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..7 fixed channel-application
                             configuration (GEMMs use min(tile_cfg, 3)) */
 } cfqmc_params;
@@ -170,6 +170,13 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
  * boundaries (the FP64 accuracy of carrying them through a block).
  * Call between sweeps. Synchronises. */
 int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel);
+
+/* Orbital weights of the sphere's density operators (Methods, eq. sphere
+ * density operator), the table behind CFQMC_Q_SPHERE: out[(l N + m) N + r] =
+ * n_{l,m}[r, r + m] for 0 <= m <= l <= N - 1 and rows r of the orbitals
+ * m_r = r - s (zero where r + m >= N). out: host buffer of N^3 doubles owned by
+ * the caller; 1 <= n_phi <= 288. Host computation only (no device use). */
+int cfqmc_sphere_weights(int32_t n_phi, double* out);
 
 /* Equal-time structure factors S^i_q = <n^{Gamma^i}_q n^{Gamma^i}_{-q}>,
  * i = 1..5, at the given momenta (Results: S^i_q; the correlation ratio

@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
-           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_logdet", "cfqmc_observables",
+           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_sphere_weights", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
@@ -92,6 +92,7 @@ def load():
     lib.cfqmc_green_displaced.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.cfqmc_measure_tau.argtypes = [P, P, P]
     lib.cfqmc_structure_factors.argtypes = [P, P, ctypes.c_int32, P]
+    lib.cfqmc_sphere_weights.argtypes = [ctypes.c_int32, P]
     lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_observables.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_series.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -380,7 +381,12 @@ class Batch:
         st = (Stats * self.n_chains)()
         rc = self.lib.cfqmc_batch_sweep(self.h, n_sweeps, int(bool(equal_time)), ctypes.cast(st, ctypes.c_void_p))
         if rc != 0:
-            raise RuntimeError("cfqmc_batch_sweep failed: %s" % ERRORS.get(rc, rc))
+            msgs = []
+            for g in self.groups:
+                m = self.lib.cfqmc_last_error(g.h)
+                if m:
+                    msgs.append(m.decode())
+            raise RuntimeError("cfqmc_batch_sweep failed: %s (%s)" % (ERRORS.get(rc, rc), "; ".join(msgs)))
         return [s.as_dict() for s in st]
 
     def close(self):
@@ -509,3 +515,14 @@ class Slmc:
             self.close()
         except Exception:
             pass
+
+
+def sphere_weights(n_phi):
+    """The sphere's density-operator weights n_{l,m}[r, r + m] as a
+    [l][m][r] array (N x N x N, zero outside 0 <= m <= l, r + m < N)."""
+    lib = load()
+    out = np.zeros((n_phi, n_phi, n_phi))
+    rc = lib.cfqmc_sphere_weights(int(n_phi), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("cfqmc_sphere_weights failed: %s" % ERRORS.get(rc, rc))
+    return out

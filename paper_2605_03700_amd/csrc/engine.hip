@@ -959,7 +959,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   *out = nullptr;
   const cfqmc_params& p = *pin;
   if (p.n_phi < 1 || p.n_phi > 140 || p.l_tau < 1 || !(p.dtau > 0) || p.n_chains < 1 || p.n_stab < 1 ||
-      !(p.eps0 > 0) || p.eps_min <= 0 || p.eps_max < p.eps_min || p.exp_squarings < 0 || p.exp_squarings > 8 ||
+      !(p.eps0 > 0) || p.eps_min <= 0 || p.eps_max < p.eps_min || p.exp_squarings < 0 || p.exp_squarings > 16 ||
       (p.precision < CFQMC_FP64 || p.precision > CFQMC_MIXED_ALL) || p.tile_cfg < -1 || p.tile_cfg >= CFQMC_CHAN_CFGS)
     return CFQMC_EINVAL;
   cfqmc_ctx* c = new cfqmc_ctx();
@@ -1496,6 +1496,13 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
   for (int k = 0; k < 3; ++k)
     if (outs[k])
       HIPCHK(hipMemcpy(outs[k], res[k] + chain * c->nn, c->nn * sizeof(double2), hipMemcpyDeviceToHost));
+  return CFQMC_OK;
+}
+
+int cfqmc_sphere_weights(int32_t n_phi, double* out) {
+  if (n_phi < 1 || n_phi > 288 || !out) return CFQMC_EINVAL;
+  const std::vector<double> W = sphere_weights(n_phi);
+  std::memcpy(out, W.data(), W.size() * sizeof(double));
   return CFQMC_OK;
 }
 

@@ -167,3 +167,18 @@ def test_order_parameters_and_correlation_ratio():
     assert np.allclose([a[0], b[0], c[0]], [12.0 / 20, 6.0 / 8, 6.0 / 12])
     assert correlation_ratio(3.0, 3.0) == 0.0 and correlation_ratio(3.0, 0.0) == 1.0
     assert abs(correlation_ratio(4.0, 1.0) - 0.75) < 1e-15
+
+
+@pytest.mark.parametrize("n_phi", [1, 2, 5, 12, 33])
+def test_sphere_weight_table_matches_the_oracle(n_phi):
+    """The library's sphere weight table (three-term recursion of the 3j
+    symbols in extended precision, host code) against the oracle's exact
+    Racah evaluation of the printed density operator."""
+    from oracle.sphere import density_matrix
+    from paper_2605_03700_amd.cfqmc import sphere_weights
+    W = sphere_weights(n_phi)
+    for l in range(n_phi):
+        for m in range(n_phi):
+            D = density_matrix(l, m, n_phi) if m <= l else np.zeros((n_phi, n_phi))
+            ref = np.array([D[r, r + m].real if r + m < n_phi else 0.0 for r in range(n_phi)])
+            assert np.abs(W[l, m] - ref).max() < 1e-14, (l, m)
