@@ -105,9 +105,10 @@ def main():
                     help="independent chains in one context; 256 N_phi = 100 chains take about 190 GB of HBM")
     ap.add_argument("--groups", type=int, default=1, help="split the chains over this many streams")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
-    ap.add_argument("--workload", choices=["c3", "batched", "learned"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "batched", "learned", "tau"], default="c3",
                     help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid; "
-                         "learned: N_phi=140, L=600 with the learned global proposal")
+                         "learned: N_phi=140, L=600 with the learned global proposal; tau: imaginary-time "
+                         "correlator passes over the c3 chains (no sweeps)")
     ap.add_argument("--learned-chains", type=int, default=16)
     ap.add_argument("--learned-sweeps", type=int, default=12)
     ap.add_argument("--learned-epochs", type=int, default=30)
@@ -153,6 +154,8 @@ def main():
         return bench_batched(args, prec)
     if args.workload == "learned":
         return bench_learned(args, prec)
+    if args.workload == "tau":
+        return bench_tau(args, prec)
     if args.chains % args.groups:
         raise SystemExit("--chains must be a multiple of --groups")
     nper = args.chains // args.groups
@@ -295,6 +298,43 @@ def main():
                                            args.geometry == "sphere")
         progress("CPU oracle baseline done")
     print(json.dumps(out))
+
+
+def bench_tau(args, prec):
+    """Imaginary-time correlator passes (G(tau,0), G(0,tau), G(tau,tau) and
+    m^2_SO(5)(tau, q=0) for tau = 0..L) over the chains of the c3 workload at
+    their initial fields: one untimed pass, then --steps timed passes."""
+    import numpy as np
+    import torch
+    from paper_2605_03700_amd import Batch, Q_PAPER, Q_SPHERE
+    geo = dict(q_mode=Q_SPHERE if args.geometry == "sphere" else Q_PAPER, exp_squarings=args.exp_squarings)
+    b = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+                    n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3, n_chains=args.chains,
+                    tile_cfg=args.tile_cfg, **geo)])
+    g = b.groups[0]
+    b.init_fields()
+    g.measure_tau()
+    progress("warm-up pass done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_max = 0.0
+    for _ in range(args.steps):
+        _, st = g.measure_tau(with_stab=True)
+        st_max = max(st_max, float(st.max()))
+    dt = (time.perf_counter() - t0) / args.steps
+    n_sp = 2 * args.n_phi
+    chan_flops = 12.0 * args.l_tau * 16.0 * args.n_phi ** 2 * n_sp * args.chains
+    print(json.dumps({
+        "metric": "imaginary-time correlator passes (G(tau,0), G(0,tau), G(tau,tau), m^2_SO(5)(tau)) per second",
+        "value": args.chains / dt, "unit": "chain-passes/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1000.0 * dt, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%s N_phi=%d L_tau=%d dtau=%g u=%g, %d chains, recompute every %d slices"
+                               % (args.geometry, args.n_phi, args.l_tau, args.dtau, args.u, args.chains,
+                                  args.n_stab)},
+        "channel_application_tflops": chan_flops / dt / 1e12,
+        "carried_vs_recomputed_rel_max": st_max}))
+    b.close()
 
 
 def bench_batched(args, prec):

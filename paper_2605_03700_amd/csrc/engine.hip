@@ -34,8 +34,9 @@ struct HostTables {
   std::vector<long long> comp_r2;   // |q|^2 (torus) or l (l + 1) (sphere): shells of the learned features
   // sphere: per component the orbital weights w[c * N + r] = n_{l,m}[r, r + m]
   // (q_x = 0, q_y = -m and F = 1 in the tables, so phases are 1 and the
-  // weights carry the density operator)
-  std::vector<double> comp_w;
+  // weights carry the density operator); t_w the same per trace-table entry,
+  // orbital-major (t_w[k * n_t + t]) so the drift's threads read it coalesced
+  std::vector<double> comp_w, t_w;
   // h table
   std::vector<int> hoff, h_cre, h_cim, h_qx, h_qy, h_dag;
   std::vector<double> h_sgn, h_scale, h_F;
@@ -247,6 +248,12 @@ bool build_components(const cfqmc_params& p, HostTables& T, std::string& err) {
     T.t_qy.push_back(qy);
     T.toff.push_back((int)T.t_qx.size());
     if (T.toff.back() - T.toff[T.toff.size() - 2] > 1024) { err = "too many components in one momentum row"; return false; }
+  }
+  if (!T.comp_w.empty()) {
+    const size_t nt = T.t_comp.size();
+    T.t_w.assign((size_t)N * nt, 0.0);
+    for (size_t t = 0; t < nt; ++t)
+      for (int k = 0; k < N; ++k) T.t_w[(size_t)k * nt + t] = T.comp_w[(size_t)T.t_comp[t] * N + k];
   }
   T.phase.resize(2 * N);
   for (int m = 0; m < 2 * N; ++m) T.phase[m] = make_double2(std::cos(M_PI * m / N), std::sin(M_PI * m / N));
@@ -701,10 +708,13 @@ int build_model_dev(cfqmc_ctx* c) {
   m.toff = p_toff; m.t_qy = p_tqy; m.t_qx = p_tqx; m.t_kind = p_tk; m.t_comp = p_tc; m.t_F = p_tF;
   m.beta = p_beta; m.phase = p_ph;
   m.cw = nullptr;
+  m.tw = nullptr;
+  m.ntw = (int)T.t_comp.size();
   if (!T.comp_w.empty()) {
-    double* p_cw;
-    if (upload(c, &p_cw, T.comp_w)) return CFQMC_ENOMEM;
+    double *p_cw, *p_tw;
+    if (upload(c, &p_cw, T.comp_w) || upload(c, &p_tw, T.t_w)) return CFQMC_ENOMEM;
     m.cw = p_cw;
+    m.tw = p_tw;
   }
   return CFQMC_OK;
 }

@@ -122,6 +122,8 @@ struct ModelDev {
   const double* beta;       // background c-number per component [nq]
   const double2* phase;     // exp(i pi m / N), m = 0..2N-1
   const double* cw;         // sphere: orbital weights [nq][N] replacing F e^{i phase} (nullptr on the torus)
+  const double* tw;         // sphere: the same per trace-table entry t, orbital-major [N][ntw]
+  int ntw;
 };
 
 struct ChainDev {

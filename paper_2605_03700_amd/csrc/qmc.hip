@@ -214,9 +214,9 @@ CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, do
     int st = (2 * qx) % N2;
     if (st < 0) st += N2;
     double tpx = 0.0, tpy = 0.0, tmx = 0.0, tmy = 0.0;
-    const double* cw = m.cw ? m.cw + (long long)m.t_comp[t] * N : nullptr;   // sphere weights
+    const double* tw = m.tw ? m.tw + t : nullptr;   // sphere weights, stride ntw per orbital
     for (int k = 0; k < N; ++k) {
-      const double2 p = cw ? make_double2(cw[k], 0.0) : ph[mm], a1 = d1[k], a2 = d2[k];
+      const double2 p = tw ? make_double2(tw[(long long)k * m.ntw], 0.0) : ph[mm], a1 = d1[k], a2 = d2[k];
       tpx += a1.x * p.x - a1.y * p.y;
       tpy += a1.x * p.y + a1.y * p.x;
       tmx += a2.x * p.x + a2.y * p.y;     // d2 conj(p)
