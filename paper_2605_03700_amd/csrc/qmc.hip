@@ -214,15 +214,34 @@ CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, do
     int st = (2 * qx) % N2;
     if (st < 0) st += N2;
     double tpx = 0.0, tpy = 0.0, tmx = 0.0, tmy = 0.0;
-    const double* tw = m.tw ? m.tw + t : nullptr;   // sphere weights, stride ntw per orbital
-    for (int k = 0; k < N; ++k) {
-      const double2 p = tw ? make_double2(tw[(long long)k * m.ntw], 0.0) : ph[mm], a1 = d1[k], a2 = d2[k];
-      tpx += a1.x * p.x - a1.y * p.y;
-      tpy += a1.x * p.y + a1.y * p.x;
-      tmx += a2.x * p.x + a2.y * p.y;     // d2 conj(p)
-      tmy += a2.y * p.x - a2.x * p.y;
-      mm += st;
-      if (mm >= N2) mm -= N2;
+    if (m.tw) {
+      // sphere: real weights from global memory, eight loads issued ahead of
+      // their products (a load per step would expose its latency N times)
+      const double* tw = m.tw + t;
+      for (int k0 = 0; k0 < N; k0 += 8) {
+        double w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = k0 + j < N ? tw[(long long)(k0 + j) * m.ntw] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (k0 + j >= N) break;
+          const double2 a1 = d1[k0 + j], a2 = d2[k0 + j];
+          tpx += a1.x * w[j];
+          tpy += a1.y * w[j];
+          tmx += a2.x * w[j];
+          tmy += a2.y * w[j];
+        }
+      }
+    } else {
+      for (int k = 0; k < N; ++k) {
+        const double2 p = ph[mm], a1 = d1[k], a2 = d2[k];
+        tpx += a1.x * p.x - a1.y * p.y;
+        tpy += a1.x * p.y + a1.y * p.x;
+        tmx += a2.x * p.x + a2.y * p.y;     // d2 conj(p)
+        tmy += a2.y * p.x - a2.x * p.y;
+        mm += st;
+        if (mm >= N2) mm -= N2;
+      }
     }
     const double f = m.t_F[t];
     const double2 tp = make_double2(tpx * f, tpy * f), tm = make_double2(tmx * f, tmy * f);
