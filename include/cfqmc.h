@@ -182,13 +182,14 @@ int cfqmc_sphere_weights(int32_t n_phi, double* out);
  * i = 1..5, at the given momenta (Results: S^i_q; the correlation ratio
  * R = 1 - S(Q + dq) / S(Q) and the VBS (i = 1, 2) and AFM (i = 3, 4, 5) order
  * parameters off the SO(5) line use them) for the current configuration of
- * every chain, by Wick's theorem from G(0), FP64. q_xy: host [n_q][2] integer
- * momenta (qx, qy) in units of the torus grid, used as given (the form factor
- * depends on q itself, the orbital shift on qy mod N_phi); 1 <= n_q <= 4096.
- * out: host [n_chains][n_q][5] complex128 (re/im interleaved), owned by the
- * caller. Per configuration the values are complex; their average is real.
- * Torus geometries only (CFQMC_ENOTIMPL on the sphere). Call between
- * sweeps. Allocates small temporaries. Synchronises. */
+ * every chain, by Wick's theorem from G(0), FP64. q_xy: host [n_q][2] integers:
+ * on the torus momenta (qx, qy) in units of the grid, used as given (the form
+ * factor depends on q itself, the orbital shift on qy mod N_phi); on the
+ * sphere (l, m) with 0 <= m <= l <= N_phi - 1 and n_{-q} read as
+ * n_{l,m}^dagger; 1 <= n_q <= 4096. out: host [n_chains][n_q][5] complex128
+ * (re/im interleaved), owned by the caller. Per configuration the values are
+ * complex; their average is real. Call between sweeps. Allocates small
+ * temporaries. Synchronises. */
 int cfqmc_structure_factors(cfqmc_ctx* c, const int32_t* q_xy, int32_t n_q, double* out);
 
 /* ln of the fermion weight exp(sum_tau c_tau) det(1 + B(beta,0))^2 of one chain

@@ -1519,21 +1519,39 @@ int cfqmc_sphere_weights(int32_t n_phi, double* out) {
 int cfqmc_structure_factors(cfqmc_ctx* c, const int32_t* q_xy, int32_t n_q, double* out) {
   if (!c || !q_xy || !out || n_q <= 0 || n_q > 4096) return CFQMC_EINVAL;
   if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
-  if (!c->ht.comp_w.empty()) { c->err = "structure factors at q != 0: torus only"; return CFQMC_ENOTIMPL; }
+  const bool sphere = !c->ht.comp_w.empty();
+  const int N = c->N;
+  std::vector<double> qw;
+  if (sphere) {
+    // rows' weights n_{l,m}[k, k + m] of the requested (l, m), 0 <= m <= l <= N - 1
+    const std::vector<double> W = sphere_weights(N);
+    qw.assign((size_t)n_q * N, 0.0);
+    for (int i = 0; i < n_q; ++i) {
+      const int l = q_xy[2 * i], m = q_xy[2 * i + 1];
+      if (l < 0 || l >= N || m < 0 || m > l) { c->err = "sphere momenta need 0 <= m <= l <= N_phi - 1"; return CFQMC_EINVAL; }
+      for (int r = 0; r < N; ++r) qw[(size_t)i * N + r] = W[((size_t)l * N + m) * N + r];
+    }
+  }
   int* dq = nullptr;
+  double* dw = nullptr;
   double2* dout = nullptr;
   const long long cnt = (long long)c->nch * n_q * 5;
-  HIPCHK(hipMalloc(&dq, 2 * n_q * sizeof(int)));
-  if (hipMalloc(&dout, cnt * sizeof(double2)) != hipSuccess) { hipFree(dq); return CFQMC_ENOMEM; }
   int rc = CFQMC_OK;
-  if (hipMemcpyAsync(dq, q_xy, 2 * n_q * sizeof(int), hipMemcpyHostToDevice, c->s) != hipSuccess) rc = CFQMC_EHIP;
+  if (hipMalloc(&dq, 2 * n_q * sizeof(int)) != hipSuccess || hipMalloc(&dout, cnt * sizeof(double2)) != hipSuccess ||
+      (sphere && hipMalloc(&dw, qw.size() * sizeof(double)) != hipSuccess))
+    rc = CFQMC_ENOMEM;
+  if (!rc && (hipMemcpyAsync(dq, q_xy, 2 * n_q * sizeof(int), hipMemcpyHostToDevice, c->s) != hipSuccess ||
+              (sphere && hipMemcpyAsync(dw, qw.data(), qw.size() * sizeof(double), hipMemcpyHostToDevice, c->s) !=
+                             hipSuccess)))
+    rc = CFQMC_EHIP;
   if (!rc) {
-    launch_structure_factors(c->G, c->nn, c->N, dq, n_q, dout, c->nch, c->s);
+    launch_structure_factors(c->G, c->nn, N, dq, n_q, dw, dout, c->nch, c->s);
     if (hipStreamSynchronize(c->s) != hipSuccess ||
         hipMemcpy(out, dout, cnt * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
       rc = CFQMC_EHIP;
   }
   hipFree(dq);
+  hipFree(dw);
   hipFree(dout);
   return rc;
 }

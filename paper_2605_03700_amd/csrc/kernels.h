@@ -185,9 +185,10 @@ void launch_observables(const double2* G, long long sG, int N, double F0, double
 void launch_disp_corr(const double2* X, const double2* Y, const double2* W, long long sG, int N, double F0,
                       double2* tr0, int first, double2* out, long long sout, int nchain, hipStream_t s);
 // S^i_q (i = 1..5) at the momenta qxy[2 iq], qxy[2 iq + 1] (device) of every chain from
-// the spin-block G; out[(chain * nql + iq) * 5 + i] complex
-void launch_structure_factors(const double2* G, long long sG, int N, const int* qxy, int nql, double2* out,
-                              int nchain, hipStream_t s);
+// the spin-block G; on the sphere the pairs are (l, m) and qw [nql][N] holds the rows'
+// weights n_{l,m}[k, k + m] (nullptr on the torus); out[(chain * nql + iq) * 5 + i] complex
+void launch_structure_factors(const double2* G, long long sG, int N, const int* qxy, int nql, const double* qw,
+                              double2* out, int nchain, hipStream_t s);
 // background sum over slices: c[chain] = sum_tau alpha0 * phi0 . beta
 void launch_background(const ModelDev& m, const double* phi, long long sphi_chain, const double2* alpha,
                        double2* out, int nchain, hipStream_t s);

@@ -673,17 +673,23 @@ void launch_disp_corr(const double2* X, const double2* Y, const double2* W, long
 // (k = 1..N) and n_{-q} = n_q^dagger. With T = o kron m_q, G_4N = 1_spin kron G:
 //   S^{1,2}_q   = 4 Tr(T_q G) Tr(T_-q G) + 2 [F(q)^2 Tr G - Tr(T_q G T_-q G)]
 //   S^{3,4,5}_q = 2 [F(q)^2 Tr G - Tr(T_q G T_-q G)]        (o = tau_z)
-// using T_-q T_q = F(q)^2 (o^2 = 1, m_q^dagger m_q = F^2). One workgroup per
-// (momentum, chain); out[(chain * nql + iq) * 5 + i].
+// using T_-q T_q = F(q)^2 (o^2 = 1, m_q^dagger m_q = F^2). On the sphere (qw
+// non-null) q = (l, m) and the orbital matrix is n_{l,m}[k, k + m] = qw[iq][k]
+// (no wrap: zero where k + m >= N), n_{-q} = n_{l,m}^dagger, and F^2 Tr G
+// becomes Tr((n^+ n kron 1) G) = sum_j qw[j - m]^2 (G_00 + G_11)[j, j].
+// One workgroup per (momentum, chain); out[(chain * nql + iq) * 5 + i].
 __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long sG, int N, const int* qxy, int nql,
-                                                 double2* out) {
+                                                 const double* qw, double2* out) {
   constexpr int NV = 16;
   __shared__ double red[4][NV];
   const int iq = blockIdx.x, z = blockIdx.y, n = 2 * N;
   const double2* G = Gall + z * sG;
-  const int qx = qxy[2 * iq], qy = qxy[2 * iq + 1];
+  const double* w = qw ? qw + (long long)iq * N : nullptr;
+  // sphere: (l, m) -> shift as q_y = -m, phases 1, weights from the table
+  const int qx = w ? 0 : qxy[2 * iq], qy = w ? -qxy[2 * iq + 1] : qxy[2 * iq + 1];
   const int sy = ((qy % N) + N) % N;
-  const double F = exp(-2.0 * M_PI * (double)(qx * qx + qy * qy) / (4.0 * N)) / (4.0 * M_PI * sqrt((double)N));
+  const double F = w ? 1.0 : exp(-2.0 * M_PI * (double)(qx * qx + qy * qy) / (4.0 * N)) / (4.0 * M_PI * sqrt((double)N));
+  const int mm_ = -qy;   // sphere: m
   // row a of m_q: column (a - qy) mod N, phase exp(i pi (2(a+1) - qy) qx / N);
   // row b of m_-q: column (b + qy) mod N, phase exp(-i pi (2(b+1) + qy) qx / N)
   auto ph = [&](long long num) {   // exp(i pi num / N), num reduced mod 2N
@@ -700,8 +706,10 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
   for (int idx = threadIdx.x; idx < N * N; idx += 256) {
     const int a = idx / N, b = idx % N;
     const int a2 = (a - sy + N) % N, b4 = (b + sy) % N;
-    const double2 c = cscale(cmul(ph((long long)(2 * (a + 1) - qy) * qx), ph(-(long long)(2 * (b + 1) + qy) * qx)),
-                             F * F);
+    // m_q[a, a2] m_-q[b, b4]; sphere: w(a) (a + m < N) and w(b - m) (b >= m)
+    const double2 c = w ? make_double2((a + mm_ < N ? w[a] : 0.0) * (b >= mm_ ? w[b - mm_] : 0.0), 0.0)
+                        : cscale(cmul(ph((long long)(2 * (a + 1) - qy) * qx), ph(-(long long)(2 * (b + 1) + qy) * qx)),
+                                 F * F);
     double2 g1[2][2], g2[2][2];
     for (int v = 0; v < 2; ++v)
       for (int w = 0; w < 2; ++w) {
@@ -722,8 +730,9 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
     qo[2] = cadd(qo[2], cmul(c, sz));
     if (b == 0) {
       // disconnected parts: Tr(T_q G) and Tr(T_-q G) for o = tau_x, tau_y (row a)
-      const double2 mq = cscale(ph((long long)(2 * (a + 1) - qy) * qx), F);
-      const double2 mm = cscale(ph(-(long long)(2 * (a + 1) + qy) * qx), F);
+      const double2 mq = w ? make_double2(a + mm_ < N ? w[a] : 0.0, 0.0) : cscale(ph((long long)(2 * (a + 1) - qy) * qx), F);
+      const double2 mm = w ? make_double2(a >= mm_ ? w[a - mm_] : 0.0, 0.0)
+                           : cscale(ph(-(long long)(2 * (a + 1) + qy) * qx), F);
       const int am = (a + sy) % N;
       // sum_{v,w} o_vw m[a, col] G[(w, col), (v, a)]
       const double2 x10 = G[(long long)(N + a2) * n + a], x01 = G[(long long)a2 * n + N + a];
@@ -734,7 +743,9 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
       tq[1] = cadd(tq[1], cmul(mq, make_double2(-dx.y, dx.x)));
       tm[0] = cadd(tm[0], cmul(mm, cadd(y10, y01)));
       tm[1] = cadd(tm[1], cmul(mm, make_double2(-dy.y, dy.x)));
-      trg = cadd(trg, cadd(G[(long long)a * n + a], G[(long long)(N + a) * n + N + a]));
+      // F^2 Tr G (torus) or sum_j w(j - m)^2 (G_00 + G_11)[j, j] (sphere), F^2 applied later
+      const double dj = w ? (a >= mm_ ? w[a - mm_] * w[a - mm_] : 0.0) : 1.0;
+      trg = cadd(trg, cscale(cadd(G[(long long)a * n + a], G[(long long)(N + a) * n + N + a]), dj));
     }
   }
   double v[NV];
@@ -764,8 +775,8 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
     o[2] = o[3] = o[4] = cscale(csub(f2tr, Qz), 2.0);
   }
 }
-void launch_structure_factors(const double2* G, long long sG, int N, const int* qxy, int nql, double2* out,
-                              int nchain, hipStream_t s) {
-  hipLaunchKernelGGL(sq_kernel, dim3(nql, nchain), dim3(256), 0, s, G, sG, N, qxy, nql, out);
+void launch_structure_factors(const double2* G, long long sG, int N, const int* qxy, int nql, const double* qw,
+                              double2* out, int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(sq_kernel, dim3(nql, nchain), dim3(256), 0, s, G, sG, N, qxy, nql, qw, out);
   cfqmc_post_launch("sq_kernel");
 }

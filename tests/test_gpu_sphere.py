@@ -95,3 +95,30 @@ def test_sphere_tau_correlator_parity():
                      for t in range(L + 1)])
     assert rel(c[0], want) < 1e-10
     g.close()
+
+
+@pytest.mark.parametrize("n_phi,L", [(3, 8), (6, 20)])
+def test_sphere_structure_factors_parity(n_phi, L):
+    """S^i_{l,m} on the sphere (the correlation ratio uses l = 1) for chains on
+    and off the SO(5) line against the oracle's Wick evaluation."""
+    from oracle.model import gamma_matrices
+    from oracle.observables import structure_factor
+    CFQMC = _gpu()
+    us = [(1.0, 0.3, 0.3), (1.0, 0.2, 0.5)]
+    models = [Model(n_phi, L, DT, u0=a, uk=b, un=c, q_mode=Q_SPHERE) for (a, b, c) in us]
+    phi = np.stack([synth.fields(560 + 3 * k + n_phi, L, models[0].n_q) for k in range(len(us))])
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=DT, q_mode=Q_SPHERE, n_stab=4, n_chains=len(us), chain_u=us, tile_cfg=1,
+              exp_squarings=6)
+    g.init_fields(phi)
+    qs = [(0, 0), (1, 0), (1, 1), (2, 1), (n_phi - 1, n_phi - 1), (n_phi - 1, 0)]
+    s = g.structure_factors(qs)
+    for k in range(len(us)):
+        G = dqmc.green(models[k], phi[k], 0)
+        want = np.array([[structure_factor(G, n_phi, gm, l, m, sphere=True) for gm in gamma_matrices()]
+                         for (l, m) in qs])
+        assert rel(s[k], want) < 1e-10, (k, rel(s[k], want))
+        s0, _ = g.observables(k)
+        assert np.abs(s[k, 0].real - s0).max() < 1e-10 * np.abs(s0).max()
+    with pytest.raises(RuntimeError):
+        g.structure_factors([(1, 2)])            # m > l
+    g.close()
