@@ -122,3 +122,31 @@ def test_sphere_structure_factors_parity(n_phi, L):
     with pytest.raises(RuntimeError):
         g.structure_factors([(1, 2)])            # m > l
     g.close()
+
+
+def test_sphere_n59_at_init_against_the_oracle():
+    """The paper's largest sphere, N_phi = 59 (3481 components per channel,
+    spin block 118), on a short imaginary-time axis: G(tau), ln w and
+    S^i_{l,m} at l = 0, 1 within 1e-10 of the oracle."""
+    from oracle.model import gamma_matrices
+    from oracle.observables import structure_factor
+    CFQMC = _gpu()
+    n_phi, L, nstab = 59, 6, 3
+    m = Model(n_phi, L, 0.01, u0=1.0, uk=0.2, un=0.2, q_mode=Q_SPHERE)
+    phi = synth.fields(590, L, m.n_q)
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.01, u0=1.0, uk=0.2, un=0.2, q_mode=Q_SPHERE, n_stab=nstab,
+              exp_squarings=10)
+    g.init_fields(phi[None])
+    Bs = dqmc.propagators(m, phi)
+    n = 2 * n_phi
+    for tau in (0, 2, nstab, L):
+        assert rel(g.measure_G(0, tau)[:n, :n], dqmc.green(m, phi, tau, Bs)) < 1e-10, tau
+    ld, ldr = g.logdet(0), dqmc.logdet(m, phi, Bs)
+    assert abs(ld.real - ldr.real) < 1e-10 * abs(ldr.real)
+    G = dqmc.green(m, phi, 0, Bs)
+    qs = [(0, 0), (1, 0), (1, 1)]
+    s = g.structure_factors(qs)
+    want = np.array([[structure_factor(G, n_phi, gm, l, mm, sphere=True) for gm in gamma_matrices()]
+                     for (l, mm) in qs])
+    assert rel(s[0], want) < 1e-10
+    g.close()

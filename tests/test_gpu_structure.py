@@ -41,3 +41,20 @@ def test_structure_factors_parity(n_phi, L, nstab, mode):
         s0, _ = g.observables(k)
         assert np.abs(s[k, 0].real - s0).max() < 1e-10 * np.abs(s0).max()
     g.close()
+
+
+def test_structure_factors_n100_against_the_oracle():
+    """N_phi = 100, paper cutoff: S^i_q at the zero, smallest and a large
+    momentum within 1e-10 of the oracle."""
+    CFQMC = _gpu()
+    n_phi, L = 100, 8
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=1.5, un=1.5, q_mode=Q_PAPER)
+    phi = synth.fields(452, L, m.n_q)
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, u0=1.0, uk=1.5, un=1.5, q_mode=Q_PAPER, n_stab=4)
+    g.init_fields(phi[None])
+    qs = [(0, 0), (1, 0), (0, 1), (7, -5)]
+    s = g.structure_factors(qs)
+    G = dqmc.green(m, phi, 0)
+    want = np.array([[structure_factor(G, n_phi, gm, qx, qy) for gm in gamma_matrices()] for (qx, qy) in qs])
+    assert np.abs(s[0] - want).max() / np.abs(want).max() < 1e-10
+    g.close()

@@ -120,3 +120,22 @@ def test_tau_correlator_full_size_invariants(n_phi, L, nstab, nch):
     assert np.abs(gt0 - (np.eye(n) - G0)).max() < 1e-9
     assert np.abs(g0t + G0).max() < 1e-9
     g.close()
+
+
+def test_tau_correlator_n100_against_the_oracle():
+    """The N_phi = 100 shape of the main workload (paper cutoff, 933
+    components, spin block 200: thirteen 16-wide tiles with a ragged tail) on
+    a short imaginary-time axis the oracle evaluates directly: every tau
+    within 1e-10."""
+    CFQMC = _gpu()
+    n_phi, L, nstab = 100, 12, 4
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=1.5, un=1.5, q_mode=Q_PAPER)
+    phi = synth.fields(351, L, m.n_q)
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, u0=1.0, uk=1.5, un=1.5, q_mode=Q_PAPER, n_stab=nstab)
+    g.init_fields(phi[None])
+    c = g.measure_tau()
+    Bs = dqmc.propagators(m, phi)
+    G00 = dqmc.green(m, phi, 0, Bs)
+    want = np.array([so5_correlator(*dqmc.green_displaced(m, phi, t, Bs), G00, n_phi)[0] for t in range(L + 1)])
+    assert rel(c[0], want) < 1e-10, rel(c[0], want)
+    g.close()
