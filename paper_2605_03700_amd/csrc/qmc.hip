@@ -689,7 +689,7 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
   const int qx = w ? 0 : qxy[2 * iq], qy = w ? -qxy[2 * iq + 1] : qxy[2 * iq + 1];
   const int sy = ((qy % N) + N) % N;
   const double F = w ? 1.0 : exp(-2.0 * M_PI * (double)(qx * qx + qy * qy) / (4.0 * N)) / (4.0 * M_PI * sqrt((double)N));
-  const int mm_ = -qy;   // sphere: m
+  const int msph = -qy;   // sphere: m
   // row a of m_q: column (a - qy) mod N, phase exp(i pi (2(a+1) - qy) qx / N);
   // row b of m_-q: column (b + qy) mod N, phase exp(-i pi (2(b+1) + qy) qx / N)
   auto ph = [&](long long num) {   // exp(i pi num / N), num reduced mod 2N
@@ -707,7 +707,7 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
     const int a = idx / N, b = idx % N;
     const int a2 = (a - sy + N) % N, b4 = (b + sy) % N;
     // m_q[a, a2] m_-q[b, b4]; sphere: w(a) (a + m < N) and w(b - m) (b >= m)
-    const double2 c = w ? make_double2((a + mm_ < N ? w[a] : 0.0) * (b >= mm_ ? w[b - mm_] : 0.0), 0.0)
+    const double2 c = w ? make_double2((a + msph < N ? w[a] : 0.0) * (b >= msph ? w[b - msph] : 0.0), 0.0)
                         : cscale(cmul(ph((long long)(2 * (a + 1) - qy) * qx), ph(-(long long)(2 * (b + 1) + qy) * qx)),
                                  F * F);
     double2 g1[2][2], g2[2][2];
@@ -730,8 +730,8 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
     qo[2] = cadd(qo[2], cmul(c, sz));
     if (b == 0) {
       // disconnected parts: Tr(T_q G) and Tr(T_-q G) for o = tau_x, tau_y (row a)
-      const double2 mq = w ? make_double2(a + mm_ < N ? w[a] : 0.0, 0.0) : cscale(ph((long long)(2 * (a + 1) - qy) * qx), F);
-      const double2 mm = w ? make_double2(a >= mm_ ? w[a - mm_] : 0.0, 0.0)
+      const double2 mq = w ? make_double2(a + msph < N ? w[a] : 0.0, 0.0) : cscale(ph((long long)(2 * (a + 1) - qy) * qx), F);
+      const double2 mm = w ? make_double2(a >= msph ? w[a - msph] : 0.0, 0.0)
                            : cscale(ph(-(long long)(2 * (a + 1) + qy) * qx), F);
       const int am = (a + sy) % N;
       // sum_{v,w} o_vw m[a, col] G[(w, col), (v, a)]
@@ -744,7 +744,7 @@ __global__ void __launch_bounds__(256) sq_kernel(const double2* Gall, long long 
       tm[0] = cadd(tm[0], cmul(mm, cadd(y10, y01)));
       tm[1] = cadd(tm[1], cmul(mm, make_double2(-dy.y, dy.x)));
       // F^2 Tr G (torus) or sum_j w(j - m)^2 (G_00 + G_11)[j, j] (sphere), F^2 applied later
-      const double dj = w ? (a >= mm_ ? w[a - mm_] * w[a - mm_] : 0.0) : 1.0;
+      const double dj = w ? (a >= msph ? w[a - msph] * w[a - msph] : 0.0) : 1.0;
       trg = cadd(trg, cscale(cadd(G[(long long)a * n + a], G[(long long)(N + a) * n + N + a]), dj));
     }
   }
