@@ -182,3 +182,16 @@ def test_sphere_weight_table_matches_the_oracle(n_phi):
             D = density_matrix(l, m, n_phi) if m <= l else np.zeros((n_phi, n_phi))
             ref = np.array([D[r, r + m].real if r + m < n_phi else 0.0 for r in range(n_phi)])
             assert np.abs(W[l, m] - ref).max() < 1e-14, (l, m)
+
+
+def test_host_only_entry_points_reject_bad_arguments():
+    """Host-only calls of the C ABI validate their arguments (no device use)."""
+    import ctypes
+    from paper_2605_03700_amd.cfqmc import load
+    lib = load()
+    buf = np.zeros(8)
+    assert lib.cfqmc_sphere_weights(0, buf.ctypes.data) == -1          # CFQMC_EINVAL
+    assert lib.cfqmc_sphere_weights(289, buf.ctypes.data) == -1
+    assert lib.cfqmc_sphere_weights(2, None) == -1
+    assert lib.cfqmc_sphere_weights(2, buf.ctypes.data) == 0
+    assert abs(abs(buf[0]) - 0.5) < 1e-15                                # n_{0,0} = +-1/2 on the orbitals
