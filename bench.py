@@ -458,6 +458,41 @@ def bench_learned(args, prec):
             row["ms_per_move_" + name] = 1000.0 * (time.perf_counter() - t2) / 2
         moves.append(row)
         progress("learned workload: global moves at step %g done" % step)
+    # the uniform q = 0 amplitudes A_i = sum_tau phi^i_{tau,0} / sqrt(L) relax
+    # slowest under local moves: their mean squared change per local sweep and
+    # per global move restricted to the q = 0 subspace (same network)
+    def amps():
+        return g.get_fields()[:, :, :, 0].sum(axis=1) / np.sqrt(l_tau)      # [chain][4]
+    s.set_params(w_trained)
+    a_0 = amps()
+    g.sweep(1)
+    a_1 = amps()
+    local_msd = float(np.mean(np.sum((a_1 - a_0) ** 2, axis=1)))
+    sub_moves = []
+    for sub, steps, reps in (("q0", (0.05, 0.2), 2), ("uniform_q0", (0.25, 0.5, 0.75), 4)):
+        s.set_subspace(sub)
+        for step in steps:
+            row = {"subspace": sub, "step": step, "n_leap": 4}
+            for name, w in (("trained", w_trained), ("gaussian", np.zeros_like(w_trained))):
+                s.set_params(w)
+                a, n_mv, msd = 0, 0, 0.0
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                for _ in range(reps):
+                    before = amps()
+                    mv = s.global_move(1, 4, step)
+                    after = amps()
+                    a += sum(m["accepted"] for m in mv)
+                    n_mv += len(mv)
+                    msd += float(np.sum((after - before) ** 2))
+                t_mv = (time.perf_counter() - t3) / reps
+                row["acceptance_" + name] = a / n_mv
+                row["q0_amplitude_msd_" + name] = msd / n_mv
+                # per unit of sweep time, against the local sweep's
+                row["msd_per_sweep_time_" + name] = (msd / n_mv) / (t_mv / (dt / n_sw))
+            sub_moves.append(row)
+            progress("learned workload: %s subspace moves at step %g done" % (sub, step))
+    s.set_subspace("all")
     fields = nch * l_tau * 4 * g.n_q * n_sw
     out = {
         "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
@@ -471,7 +506,11 @@ def bench_learned(args, prec):
         "acceptance": acc / max(1, prop),
         "learned": {"configurations": s.n_data(), "train_epochs": args.learned_epochs,
                     "train_loss_first_epoch": loss0, "train_loss_last": loss, "train_s": t_train,
-                    "heldout_r2": r2, "heldout_points": len(lnw), "global_moves": moves},
+                    "heldout_r2": r2, "heldout_points": len(lnw), "global_moves": moves,
+                    "subspace_moves": {"local_sweep_q0_amplitude_msd": local_msd, "global_moves": sub_moves,
+                                    "definition": "mean over chains of sum_i (A_i' - A_i)^2, A_i = sum_tau "
+                                                  "phi^i_{tau,q=0} / sqrt(L), per local sweep and per global "
+                                                  "move (rejections count as zero change)"}},
     }
     s.close()
     g.close()

@@ -302,6 +302,16 @@ int cfqmc_slmc_clear_data(cfqmc_slmc* s);
  * refit_norm = 1 (or the first call) sets mu, sigma, y_bar, s_y from the data.
  * loss_out: mean minibatch loss of the last epoch. */
 int cfqmc_slmc_train(cfqmc_slmc* s, int32_t epochs, int32_t batch, double lr, int32_t refit_norm, double* loss_out);
+/* Subspace of the learned global move. mode 0 moves every field (the
+ * default); 1 moves only component 0 of every channel and slice (q = 0 on the
+ * torus, (l, m) = (0, 0) on the sphere); 2 moves only the four slice-uniform
+ * amplitudes A_i = sum_tau phi^i_{tau,0} / sqrt(L) per chain (every slice's
+ * component 0 shifted together), the field modes local whole-slice moves relax
+ * most slowly. The HMC on the effective action runs in that subspace (its
+ * momenta alone are nonzero); the exact Metropolis test is unchanged.
+ * EINVAL for another mode. */
+int cfqmc_slmc_set_subspace(cfqmc_slmc* s, int32_t mode);
+
 /* One global move of every chain: n_traj HMC trajectories of n_leap leapfrog steps
  * of size step on S_eff, each with its own Metropolis test, then the exact test.
  * Accepted chains keep phi', rejected chains return to phi; the chain state (UDT

@@ -230,28 +230,65 @@ def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 # ------------------------------------------------------------------ HMC and the global move
 
-def hmc_trajectory(phi, p0, grad_s, s_eff, step, n_leap):
-    """Leapfrog trajectory for H = S_eff(phi) + |p|^2 / 2. Returns (phi', dH)."""
+def hmc_trajectory_uniform(phi, p0, grad_s, s_eff, step, n_leap):
+    """Leapfrog for H = S_eff + |p|^2 / 2 in the four coordinates
+    A_i = sum_tau phi^i_{tau,0} / sqrt(L) of fields [L][4][n_q] (every slice's
+    component 0 shifted together); p0 holds their momenta at [0][i][0], the
+    force on A_i is sum_tau dS_eff/dphi^i_{tau,0} / sqrt(L). Returns (phi', dH)."""
     q = np.array(phi, dtype=float)
-    p = np.array(p0, dtype=float)
+    L = q.shape[0]
+    r = 1.0 / np.sqrt(L)
+    p = np.array(p0, dtype=float)[0, :, 0].copy()
+    force = lambda x: grad_s(x)[:, :, 0].sum(axis=0) * r
     h0 = s_eff(q) + 0.5 * np.sum(p * p)
-    p = p - 0.5 * step * grad_s(q)
+    p = p - 0.5 * step * force(q)
     for k in range(n_leap):
-        q = q + step * p
+        q[:, :, 0] += step * p * r
         if k < n_leap - 1:
-            p = p - step * grad_s(q)
-    p = p - 0.5 * step * grad_s(q)
+            p = p - step * force(q)
+    p = p - 0.5 * step * force(q)
     h1 = s_eff(q) + 0.5 * np.sum(p * p)
     return q, h1 - h0
 
 
-def inner_chain(phi, momenta, uniforms, grad_s, s_eff, step, n_leap):
+def hmc_trajectory(phi, p0, grad_s, s_eff, step, n_leap, mask=None):
+    """Leapfrog trajectory for H = S_eff(phi) + |p|^2 / 2. Returns (phi', dH).
+    mask (same shape as phi, 0/1): only the coordinates with mask 1 carry
+    momentum and move; the rest stay fixed (HMC on the conditional of the
+    masked coordinates, still reversible for exp(-S_eff)). mask = "uniform":
+    the four slice-uniform q = 0 amplitudes (hmc_trajectory_uniform)."""
+    if isinstance(mask, str):
+        return hmc_trajectory_uniform(phi, p0, grad_s, s_eff, step, n_leap)
+    q = np.array(phi, dtype=float)
+    p = np.array(p0, dtype=float)
+    m = np.ones_like(q) if mask is None else np.asarray(mask, dtype=float)
+    p = p * m
+    h0 = s_eff(q) + 0.5 * np.sum(p * p)
+    p = p - 0.5 * step * grad_s(q) * m
+    for k in range(n_leap):
+        q = q + step * p
+        if k < n_leap - 1:
+            p = p - step * grad_s(q) * m
+    p = p - 0.5 * step * grad_s(q) * m
+    h1 = s_eff(q) + 0.5 * np.sum(p * p)
+    return q, h1 - h0
+
+
+def q0_mask(shape):
+    """Mask of component 0 (q = 0) of every channel and slice for fields of
+    shape [L][4][n_q]."""
+    m = np.zeros(shape)
+    m[..., 0] = 1.0
+    return m
+
+
+def inner_chain(phi, momenta, uniforms, grad_s, s_eff, step, n_leap, mask=None):
     """HMC trajectories with their own Metropolis test (reversible for
     exp(-S_eff)); momenta [n_traj][...] and uniforms [n_traj] are inputs."""
     q = np.array(phi, dtype=float)
     acc = 0
     for p0, u in zip(momenta, uniforms):
-        qn, dh = hmc_trajectory(q, p0, grad_s, s_eff, step, n_leap)
+        qn, dh = hmc_trajectory(q, p0, grad_s, s_eff, step, n_leap, mask)
         if np.log(u) < -dh:
             q, acc = qn, acc + 1
     return q, acc

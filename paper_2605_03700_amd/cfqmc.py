@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
-           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_sphere_weights", "cfqmc_logdet", "cfqmc_observables",
+           "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_sphere_weights", "cfqmc_slmc_set_subspace", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
@@ -93,6 +93,7 @@ def load():
     lib.cfqmc_measure_tau.argtypes = [P, P, P]
     lib.cfqmc_structure_factors.argtypes = [P, P, ctypes.c_int32, P]
     lib.cfqmc_sphere_weights.argtypes = [ctypes.c_int32, P]
+    lib.cfqmc_slmc_set_subspace.argtypes = [P, ctypes.c_int32]
     lib.cfqmc_logdet.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_observables.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     lib.cfqmc_series.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -492,6 +493,14 @@ class Slmc:
         self._check(self.lib.cfqmc_slmc_train(self.h, epochs, batch, lr, int(bool(refit_norm)), ctypes.byref(loss)),
                     "train")
         return loss.value
+
+    SUBSPACES = {"all": 0, "q0": 1, "uniform_q0": 2}
+
+    def set_subspace(self, mode="all"):
+        """Global moves on every field ("all"), on component 0 of every channel
+        and slice ("q0"), or on the four slice-uniform q = 0 amplitudes
+        ("uniform_q0")."""
+        self._check(self.lib.cfqmc_slmc_set_subspace(self.h, self.SUBSPACES[mode]), "set_subspace")
 
     def global_move(self, n_traj=1, n_leap=8, step=0.2, replay=None):
         rp = None if replay is None else np.ascontiguousarray(replay, dtype=np.float64)

@@ -1682,6 +1682,7 @@ struct cfqmc_slmc {
   int* flag;
   long long move_counter;
   uint64_t rng;
+  int sub;   // subspace of the global moves: 0 all fields, 1 q = 0 components, 2 slice-uniform q = 0 amplitudes
 };
 
 namespace {
@@ -2115,6 +2116,12 @@ int cfqmc_slmc_train(cfqmc_slmc* s, int32_t epochs, int32_t batch, double lr, in
   return CFQMC_OK;
 }
 
+int cfqmc_slmc_set_subspace(cfqmc_slmc* s, int32_t mode) {
+  if (!s || mode < 0 || mode > 2) return CFQMC_EINVAL;
+  s->sub = mode;
+  return CFQMC_OK;
+}
+
 int cfqmc_slmc_global_move(cfqmc_slmc* s, int32_t n_traj, int32_t n_leap, double step, const double* replay,
                            cfqmc_slmc_move* out) {
   if (!s || n_traj < 1 || n_traj > 1024 || n_leap < 1 || n_leap > 100000 || !(step > 0)) return CFQMC_EINVAL;
@@ -2139,7 +2146,8 @@ int cfqmc_slmc_global_move(cfqmc_slmc* s, int32_t n_traj, int32_t n_leap, double
                               nf * sizeof(double), B, hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
     }
-    launch_slmc_momenta(s->mom, nf, B, key, s->move_counter * 1024 + k, replay ? s->rp : nullptr, nf, st);
+    launch_slmc_momenta(s->mom, nf, B, key, s->move_counter * 1024 + k, replay ? s->rp : nullptr, nf, s->sub, s->nq,
+                        st);
     launch_slmc_sumsq(s->phi_cur, nf, s->sumsq, B, st);
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(q0.data(), s->sumsq, B * sizeof(double), hipMemcpyDeviceToHost));
@@ -2149,12 +2157,13 @@ int cfqmc_slmc_global_move(cfqmc_slmc* s, int32_t n_traj, int32_t n_leap, double
     HIPCHK(hipMemcpyAsync(s->prop, s->phi_cur, B * nf * sizeof(double), hipMemcpyDeviceToDevice, st));
     rc = slmc_action_dev(s, s->prop, B, snn_new, true);
     if (rc) return rc;
-    launch_slmc_kick(s->mom, s->prop, s->grad, 0.5 * step, B * nf, st);
+    launch_slmc_kick(s->mom, s->prop, s->grad, 0.5 * step, B * nf, s->sub, s->nq, s->L, B, st);
     for (int l = 1; l <= n_leap; ++l) {
-      launch_slmc_drift(s->prop, s->mom, step, B * nf, st);
+      launch_slmc_drift(s->prop, s->mom, step, B * nf, s->sub, s->nq, s->L, B, st);
       rc = slmc_action_dev(s, s->prop, B, snn_new, true);
       if (rc) return rc;
-      launch_slmc_kick(s->mom, s->prop, s->grad, l < n_leap ? step : 0.5 * step, B * nf, st);
+      launch_slmc_kick(s->mom, s->prop, s->grad, l < n_leap ? step : 0.5 * step, B * nf, s->sub, s->nq, s->L, B,
+                       st);
     }
     launch_slmc_sumsq(s->prop, nf, s->sumsq, B, st);
     HIPCHK(hipStreamSynchronize(st));

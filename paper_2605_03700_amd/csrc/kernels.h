@@ -232,8 +232,12 @@ void launch_slmc_vjp(const float* Xre, const float* Xim, long long sX, const flo
                      int nqb, int nwb, const int* shell, const int* wbin, const float* inv_cnt, const float* twc,
                      const float* tws, double* grad, long long sg, int nb, hipStream_t s);
 void launch_slmc_momenta(double* p, long long n, int nb, uint64_t key, long long counter, const double* replay,
-                         long long s_replay, hipStream_t s);
-void launch_slmc_kick(double* p, const double* phi, const double* g, double h, long long n, hipStream_t s);
-void launch_slmc_drift(double* phi, const double* p, double h, long long n, hipStream_t s);
+                         long long s_replay, int mode, int nq, hipStream_t s);
+// subspace mode: 0 every field, 1 component 0 of every channel and slice, 2 the four
+// slice-uniform component-0 amplitudes per chain (momenta at slice 0)
+void launch_slmc_kick(double* p, const double* phi, const double* g, double h, long long n, int mode, int nq, int L,
+                      int nb, hipStream_t s);
+void launch_slmc_drift(double* phi, const double* p, double h, long long n, int mode, int nq, int L, int nb,
+                       hipStream_t s);
 void launch_slmc_sumsq(const double* x, long long n, double* out, int nb, hipStream_t s);
 void launch_slmc_select(const int* flag, int want, const double* src, double* dst, long long n, int nb, hipStream_t s);

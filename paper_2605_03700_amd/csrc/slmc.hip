@@ -465,19 +465,51 @@ void launch_slmc_vjp(const float* Xre, const float* Xim, long long sX, const flo
 
 // ------------------------------------------------------------------ HMC
 // Momenta: replay [b][n] or N(0,1) from Philox (own key), counter per trajectory.
+// Subspace (mode, nq): 0 every coordinate; 1 only component 0 (q = 0) of every
+// channel and slice; 2 the four slice-uniform q = 0 amplitudes
+// A_i = sum_tau phi^i_{tau,0} / sqrt(L), whose momenta sit at slice 0.
 __global__ void slmc_momenta_kernel(double* p, long long n, int nb, uint64_t key, long long counter,
-                                    const double* replay, long long s_replay) {
+                                    const double* replay, long long s_replay, int mode, int nq) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)nb * n) return;
   const int b = (int)(e / n);
   const long long j = e % n;
-  p[e] = replay ? replay[b * s_replay + j] : rng_normal(key, b, counter, (int)j);
+  const double v = replay ? replay[b * s_replay + j] : rng_normal(key, b, counter, (int)j);
+  const bool keep = mode == 0 || (j % nq == 0 && (mode == 1 || j < 4LL * nq));
+  p[e] = keep ? v : 0.0;
 }
-// p <- p - h (phi + g)   (gradient of S_eff = |phi|^2/2 + S_NN)
-__global__ void slmc_kick_kernel(double* p, const double* phi, const double* g, double h, long long n) {
+// p <- p - h (phi + g)   (gradient of S_eff = |phi|^2/2 + S_NN), on the moving
+// coordinates only (modes 0 and 1 above; the field length per chain is a
+// multiple of nq)
+__global__ void slmc_kick_kernel(double* p, const double* phi, const double* g, double h, long long n, int mode,
+                                 int nq) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  if (mode == 1 && e % nq != 0) return;
   p[e] -= h * (phi[e] + g[e]);
+}
+// Mode 2: p_i <- p_i - h sum_tau (phi + g)^i_{tau,0} / sqrt(L), one workgroup
+// per (chain, channel), fixed summation order
+__global__ void __launch_bounds__(256) slmc_kick_uniform_kernel(double* p, const double* phi, const double* g,
+                                                                double h, int L, int nq) {
+  __shared__ double red[4];
+  const int z = blockIdx.x / 4, i = blockIdx.x % 4;
+  const long long base = (long long)z * L * 4 * nq + (long long)i * nq;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < L; t += 256) {
+    const long long e = base + (long long)t * 4 * nq;
+    acc += phi[e] + g[e];
+  }
+  const double sum = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) p[base] -= h * sum / sqrt((double)L);
+}
+// Mode 2: phi^i_{tau,0} <- phi^i_{tau,0} + h p_i / sqrt(L) for every tau
+__global__ void slmc_drift_uniform_kernel(double* phi, const double* p, double h, int L, int nq, int nb) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nb * L * 4) return;
+  const int z = (int)(e / (4LL * L)), r = (int)(e % (4LL * L)), t = r / 4, i = r % 4;
+  const long long chain = (long long)z * L * 4 * nq;
+  phi[chain + (long long)t * 4 * nq + (long long)i * nq] += h * p[chain + (long long)i * nq] / sqrt((double)L);
 }
 // phi <- phi + h p
 __global__ void slmc_drift_kernel(double* phi, const double* p, double h, long long n) {
@@ -505,16 +537,30 @@ __global__ void slmc_select_kernel(const int* flag, int want, const double* src,
 }
 
 void launch_slmc_momenta(double* p, long long n, int nb, uint64_t key, long long counter, const double* replay,
-                         long long s_replay, hipStream_t s) {
+                         long long s_replay, int mode, int nq, hipStream_t s) {
   const long long t = (long long)nb * n;
   hipLaunchKernelGGL(slmc_momenta_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, p, n, nb, key, counter,
-                     replay, s_replay); cfqmc_post_launch("slmc_momenta_kernel");
+                     replay, s_replay, mode, nq); cfqmc_post_launch("slmc_momenta_kernel");
 }
-void launch_slmc_kick(double* p, const double* phi, const double* g, double h, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(slmc_kick_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, phi, g, h, n);
+void launch_slmc_kick(double* p, const double* phi, const double* g, double h, long long n, int mode, int nq, int L,
+                      int nb, hipStream_t s) {
+  if (mode == 2) {
+    hipLaunchKernelGGL(slmc_kick_uniform_kernel, dim3(nb * 4), dim3(256), 0, s, p, phi, g, h, L, nq);
+    cfqmc_post_launch("slmc_kick_uniform_kernel");
+    return;
+  }
+  hipLaunchKernelGGL(slmc_kick_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, phi, g, h, n, mode, nq);
   cfqmc_post_launch("slmc_kick_kernel");
 }
-void launch_slmc_drift(double* phi, const double* p, double h, long long n, hipStream_t s) {
+void launch_slmc_drift(double* phi, const double* p, double h, long long n, int mode, int nq, int L, int nb,
+                       hipStream_t s) {
+  if (mode == 2) {
+    const long long t = (long long)nb * L * 4;
+    hipLaunchKernelGGL(slmc_drift_uniform_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, phi, p, h, L,
+                       nq, nb);
+    cfqmc_post_launch("slmc_drift_uniform_kernel");
+    return;
+  }
   hipLaunchKernelGGL(slmc_drift_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phi, p, h, n);
   cfqmc_post_launch("slmc_drift_kernel");
 }

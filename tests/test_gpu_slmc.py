@@ -139,7 +139,11 @@ def test_training_step_is_adam_on_the_oracle_gradient():
     g.close()
 
 
-def test_global_move_replay_matches_oracle():
+@pytest.mark.parametrize("sub", ["all", "q0", "uniform_q0"])
+def test_global_move_replay_matches_oracle(sub):
+    """A replayed global move (every field, or the q = 0 subspace only)
+    reproduces the oracle's HMC trajectory, inner accept count, exact weight
+    change, ln A and decision, and leaves the rebuilt state."""
     m, g, s, fm = _setup(nch=2, hidden=32, L=16)
     L, nq = 16, m.n_q
     g.init_fields(None)
@@ -151,6 +155,7 @@ def test_global_move_replay_matches_oracle():
     net.set_flat(np.float32(net.flat()).astype(np.float64))
     s.set_params(net.flat())
     s.set_norm(net.mu, net.sigma, net.y_bar, net.s_y)
+    s.set_subspace(sub)
     n_traj, n_leap, step = 2, 4, 0.25
     nf = L * 4 * nq
     rp = np.empty((2, n_traj * nf + n_traj + 1))
@@ -166,7 +171,14 @@ def test_global_move_replay_matches_oracle():
         sf = lambda q: 0.5 * np.sum(q * q) + net.action_grad(fm, q, bf16=True)[0]
         gf = lambda q: q + net.action_grad(fm, q, bf16=True)[1]
         mom = rp[z, :n_traj * nf].reshape(n_traj, L, 4, nq)
-        q, acc = slmc.inner_chain(phi0[z], mom, rp[z, n_traj * nf:n_traj * nf + n_traj], gf, sf, step, n_leap)
+        mask = {"all": None, "q0": slmc.q0_mask(phi0[z].shape), "uniform_q0": "uniform"}[sub]
+        q, acc = slmc.inner_chain(phi0[z], mom, rp[z, n_traj * nf:n_traj * nf + n_traj], gf, sf, step, n_leap,
+                                  mask)
+        if sub != "all":
+            assert np.array_equal(prop[..., 1:], phi0[z][..., 1:])
+        if sub == "uniform_q0":
+            d = prop[:, :, 0] - phi0[z][:, :, 0]
+            assert np.abs(d - d[0]).max() < 1e-12          # every slice shifted by the same amount
         assert acc == mv["inner_accepted"]
         assert relmax(prop, q) < 1e-4
         # exact weight of the proposal (FP64 from scratch) and the test itself

@@ -185,3 +185,89 @@ def test_global_move_chain_samples_the_exact_law():
     assert 0.2 < acc / 6000 < 0.99
     assert abs(x.var() - 1.0 / (1.0 + a)) < 0.04
     assert abs(x.var() - 1.0 / (1.0 + b)) > 0.08
+
+
+def test_masked_global_move_moves_only_its_subspace_and_samples_its_law():
+    """With a mask (the q = 0 subspace of the learned move) the unmasked
+    coordinates never change and the masked ones sample the exact conditional
+    law 1 / (1 + a), not the model's 1 / (1 + b); the masked leapfrog is still
+    reversible."""
+    a, b = 0.5, 0.25
+    shape = (6, 4, 3)                      # [L][4][n_q]
+    mask = slmc.q0_mask(shape)
+    assert mask.sum() == 24 and np.all(mask[..., 1:] == 0)
+    lnw = lambda q: -0.5 * a * np.sum(q * q)
+    snn = lambda q: 0.5 * b * np.sum(q * q)
+    s_eff = lambda q: 0.5 * np.sum(q * q) + snn(q)
+    g_eff = lambda q: (1.0 + b) * q
+    rng = np.random.default_rng(10)
+    q = rng.normal(size=shape)
+    fixed = q[..., 1:].copy()
+    p0 = rng.normal(size=shape)
+    q1, _ = slmc.hmc_trajectory(q, p0, g_eff, s_eff, 0.2, 6, mask)
+    assert np.array_equal(q1[..., 1:], fixed)
+    # reverse: end momentum flipped returns to the start (masked leapfrog)
+    p = p0 * mask - 0.1 * g_eff(q) * mask
+    qq = q.copy()
+    for k in range(6):
+        qq = qq + 0.2 * p
+        p = p - (0.2 if k < 5 else 0.1) * g_eff(qq) * mask
+    qb, _ = slmc.hmc_trajectory(q1, -p, g_eff, s_eff, 0.2, 6, mask)
+    assert np.abs(qb - q).max() < 1e-12
+    acc, samples = 0, []
+    for it in range(4000):
+        qn, _ = slmc.inner_chain(q, rng.normal(size=(1,) + shape), rng.random(1), g_eff, s_eff, 0.3, 5, mask)
+        la = slmc.global_move_lnA(lnw(q), lnw(qn), snn(q), snn(qn))
+        if np.log(rng.random()) < la:
+            q, acc = qn, acc + 1
+        samples.append(q[..., 0].copy())
+    assert np.array_equal(q[..., 1:], fixed)
+    x = np.array(samples[300:])
+    assert 0.2 < acc / 4000 < 0.99
+    assert abs(x.var() - 1.0 / (1.0 + a)) < 0.04
+
+
+def test_uniform_mode_global_move_shifts_all_slices_together_and_samples_its_law():
+    """The slice-uniform q = 0 subspace: every slice's component 0 moves by the
+    same amount, everything else stays, the leapfrog is reversible, and on a
+    Gaussian target the amplitude A_i = sum_tau phi / sqrt(L) samples its exact
+    conditional law 1 / (1 + a) (the model says 1 / (1 + b))."""
+    a, b = 0.5, 0.25
+    shape = (6, 4, 3)
+    lnw = lambda q: -0.5 * a * np.sum(q * q)
+    snn = lambda q: 0.5 * b * np.sum(q * q)
+    s_eff = lambda q: 0.5 * np.sum(q * q) + snn(q)
+    g_eff = lambda q: (1.0 + b) * q
+    rng = np.random.default_rng(12)
+    q = rng.normal(size=shape)
+    p0 = rng.normal(size=shape)
+    q1, _ = slmc.hmc_trajectory(q, p0, g_eff, s_eff, 0.3, 5, "uniform")
+    d = q1[:, :, 0] - q[:, :, 0]
+    assert np.abs(d - d[0]).max() < 1e-14 and np.abs(d[0]).max() > 1e-3
+    assert np.array_equal(q1[..., 1:], q[..., 1:])
+    # reversibility: rerun from the end with the flipped final momentum of A
+    L = shape[0]
+    force = lambda x: g_eff(x)[:, :, 0].sum(axis=0) / np.sqrt(L)
+    p = p0[0, :, 0] - 0.15 * force(q)
+    qq = q.copy()
+    for k in range(5):
+        qq[:, :, 0] += 0.3 * p / np.sqrt(L)
+        p = p - (0.3 if k < 4 else 0.15) * force(qq)
+    pb = np.zeros(shape)
+    pb[0, :, 0] = -p
+    qb, _ = slmc.hmc_trajectory(q1, pb, g_eff, s_eff, 0.3, 5, "uniform")
+    assert np.abs(qb - q).max() < 1e-12
+    centred = q[:, :, 0] - q[:, :, 0].mean(axis=0)
+    fixed = q[..., 1:].copy()
+    samples, acc = [], 0
+    for it in range(4000):
+        qn, _ = slmc.inner_chain(q, rng.normal(size=(1,) + shape), rng.random(1), g_eff, s_eff, 0.4, 4, "uniform")
+        la = slmc.global_move_lnA(lnw(q), lnw(qn), snn(q), snn(qn))
+        if np.log(rng.random()) < la:
+            q, acc = qn, acc + 1
+        samples.append(q[:, :, 0].sum(axis=0) / np.sqrt(L))
+    assert np.array_equal(q[..., 1:], fixed)
+    assert np.abs(q[:, :, 0] - q[:, :, 0].mean(axis=0) - centred).max() < 1e-12
+    x = np.array(samples[300:])
+    assert 0.2 < acc / 4000 < 0.99
+    assert abs(x.var() - 1.0 / (1.0 + a)) < 0.05
