@@ -155,3 +155,13 @@ def hamiltonian_sphere(cs, n_phi, coef, gammas, background_first):
             a = density_operator_sphere(cs, n_phi, l, m, gm, background_first and i == 0)
             H += coef[i] * (a @ a.conj().T)
     return H
+
+
+def thermal_expectation(H, O, beta):
+    """Tr[e^{-beta H} O] / Tr[e^{-beta H}] by exact diagonalisation of the
+    Hermitian Fock-space Hamiltonian H (all particle numbers, as the
+    determinant weight of the auxiliary-field method)."""
+    ev, V = np.linalg.eigh(H)
+    w = np.exp(-beta * (ev - ev.min()))
+    ov = np.einsum("ij,jk,ki->i", V.conj().T, O, V)
+    return float(np.real(np.sum(w * ov) / np.sum(w)))
