@@ -174,6 +174,7 @@ def main():
     dt, stats, g_err = sweep_each(b, args.steps)
     progress("timed sweeps done: %.1f ms per sweep" % (1000.0 * dt / args.steps))
     k_ms, k_count, k_flops = g.kernel_timing_read()
+    w_ms, w_count, w_flops = g.kernel_timing_read(woodbury=True)
     g.kernel_timing(False)
     fields = args.chains * args.l_tau * 4 * g.n_q * args.steps
     value = fields / dt
@@ -219,6 +220,16 @@ def main():
                            "traffic": traffic, "avg_launch_ms": k_ms, "launches_timed": k_count,
                            "flops_per_launch": k_flops,
                            "hbm_gbps_at_traffic": traffic / (k_ms * 1e-3) / 1e9 if traffic else None}
+    if w_count > 0 and w_ms > 0:
+        # the same kernel family in the Woodbury product M = G + B'B^-1(1 - G),
+        # FP64 unless every product runs in FP32
+        w_peak = PEAK["mixed"] if args.precision == "mixed_all" else PEAK["fp64"]
+        w_ach = w_flops / (w_ms * 1e-3) / 1e12
+        out["roofline_woodbury_application"] = {
+            "bound": "mfma", "kernel": "chan_apply (Woodbury product, %s)" % (
+                "FP32" if args.precision == "mixed_all" else "FP64"),
+            "achieved": w_ach, "peak": w_peak, "unit": "TFLOP/s", "frac": w_ach / w_peak,
+            "avg_launch_ms": w_ms, "launches_timed": w_count, "flops_per_launch": w_flops}
     tau = None
     if args.tau_sweeps > 0:
         n0 = [len(q.series(0)) for q in b.groups]

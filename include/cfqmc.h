@@ -227,6 +227,10 @@ int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable);
 /* Mean duration (ms) and count of the sampled launches, and the algorithmic
  * real flops of one launch (16 N^2 n per chain). Synchronises. */
 int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch);
+/* The same for one channel application per slice of the Woodbury product
+ * M = G + B'B^-1 (1 - G) (the left application of channel 2's inverse,
+ * FP64 except in CFQMC_MIXED_ALL): the FP64 application's rate in a mixed run. */
+int cfqmc_kernel_timing_read_woodbury(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch);
 
 /* Heterogeneous batch: groups of chains with different shapes (N_phi, L_tau,
  * q-set, couplings), one context per group on its own HIP stream (default

@@ -60,7 +60,7 @@ _lib = None
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
            "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_sphere_weights", "cfqmc_slmc_set_subspace", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
-           "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_batch_create",
+           "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_kernel_timing_read_woodbury", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
            "cfqmc_slmc_create", "cfqmc_slmc_destroy", "cfqmc_slmc_sizes", "cfqmc_slmc_set_params",
            "cfqmc_slmc_get_params", "cfqmc_slmc_set_norm", "cfqmc_slmc_get_norm", "cfqmc_slmc_features",
@@ -106,6 +106,7 @@ def load():
     lib.cfqmc_kernel_timing.argtypes = [P, ctypes.c_int32]
     lib.cfqmc_kernel_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_double)]
+    lib.cfqmc_kernel_timing_read_woodbury.argtypes = lib.cfqmc_kernel_timing_read.argtypes
     lib.cfqmc_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(P)]
     lib.cfqmc_batch_context.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.cfqmc_batch_sweep.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
@@ -331,10 +332,13 @@ class CFQMC:
     def kernel_timing(self, enable=True):
         self._check(self.lib.cfqmc_kernel_timing(self.h, int(bool(enable))))
 
-    def kernel_timing_read(self):
-        """(mean ms per sampled channel-application launch, count, flops per launch)."""
+    def kernel_timing_read(self, woodbury=False):
+        """(mean ms per sampled channel-application launch, count, flops per
+        launch) of the wrap's timed application, or (woodbury=True) of the
+        Woodbury product's."""
         a, k, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-        self._check(self.lib.cfqmc_kernel_timing_read(self.h, ctypes.byref(a), ctypes.byref(k), ctypes.byref(f)))
+        fn = self.lib.cfqmc_kernel_timing_read_woodbury if woodbury else self.lib.cfqmc_kernel_timing_read
+        self._check(fn(self.h, ctypes.byref(a), ctypes.byref(k), ctypes.byref(f)))
         return a.value, k.value, f.value
 
     def close(self):

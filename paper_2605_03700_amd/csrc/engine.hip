@@ -338,6 +338,8 @@ struct cfqmc_ctx {
   bool timing;
   std::vector<hipEvent_t> ev;
   size_t ev_used;
+  std::vector<hipEvent_t> ev2;   // the same for one application of the Woodbury product per slice
+  size_t ev2_used;
   bool ready;
   std::string err;
 };
@@ -767,8 +769,11 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   double2* y = c->S1;
   double2* y2 = c->S2;
   chan(c, 1, 0, true, pq + 0 * 2 * NN, sPQ, c->F[0], y, true, nullptr, mixed_m);
+  const bool tm2 = c->timing && c->ev2_used + 2 <= c->ev2.size();
   for (int ch = 1; ch <= 3; ++ch) {
+    if (tm2 && ch == 2) hipEventRecord(c->ev2[c->ev2_used], c->s);
     chan(c, 1, ch, true, pq + ch * 2 * NN, sPQ, y, y2, false, nullptr, mixed_m);
+    if (tm2 && ch == 2) { hipEventRecord(c->ev2[c->ev2_used + 1], c->s); c->ev2_used += 2; }
     std::swap(y, y2);
   }
   for (int ch = 3; ch >= 1; --ch) {
@@ -1097,6 +1102,7 @@ int cfqmc_destroy(cfqmc_ctx* c) {
   if (!c) return CFQMC_EINVAL;
   hipStreamSynchronize(c->s);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  for (hipEvent_t e : c->ev2) hipEventDestroy(e);
   for (void* q : c->allocs) hipFree(q);
   delete c;
   return CFQMC_OK;
@@ -1630,9 +1636,12 @@ int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable) {
   if (enable && c->ev.empty()) {
     c->ev.resize(2 * 4096);
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    c->ev2.resize(2 * 4096);
+    for (auto& e : c->ev2) HIPCHK(hipEventCreate(&e));
   }
   c->timing = enable != 0;
   c->ev_used = 0;
+  c->ev2_used = 0;
   return CFQMC_OK;
 }
 
@@ -1649,6 +1658,22 @@ int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, doubl
   if (avg_ms) *avg_ms = k ? tot / k : 0.0;
   if (count) *count = k;
   // two N x N x n complex products per chain = 8 * 2 N^2 n real flops
+  if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
+  return CFQMC_OK;
+}
+
+int cfqmc_kernel_timing_read_woodbury(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch) {
+  if (!c) return CFQMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->s));
+  double tot = 0.0;
+  const int64_t k = (int64_t)(c->ev2_used / 2);
+  for (int64_t i = 0; i < k; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev2[2 * i], c->ev2[2 * i + 1]));
+    tot += ms;
+  }
+  if (avg_ms) *avg_ms = k ? tot / k : 0.0;
+  if (count) *count = k;
   if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
   return CFQMC_OK;
 }
