@@ -1352,6 +1352,25 @@ struct cfqmc_batch {
   std::string err;
 };
 
+// Average duration of the event pairs [0, used) of ev (one timed channel
+// application each) and the flops of one such application: two N x N x n
+// complex products per chain, 8 * 2 N^2 n real flops.
+static int timing_average(cfqmc_ctx* c, const std::vector<hipEvent_t>& ev, size_t used, double* avg_ms,
+                          int64_t* count, double* flops_per_launch) {
+  HIPCHK(hipStreamSynchronize(c->s));
+  double tot = 0.0;
+  const int64_t k = (int64_t)(used / 2);
+  for (int64_t i = 0; i < k; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+    tot += ms;
+  }
+  if (avg_ms) *avg_ms = k ? tot / k : 0.0;
+  if (count) *count = k;
+  if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
+  return CFQMC_OK;
+}
+
 extern "C" {
 
 int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stats* stats) {
@@ -1647,35 +1666,12 @@ int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable) {
 
 int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch) {
   if (!c) return CFQMC_EINVAL;
-  HIPCHK(hipStreamSynchronize(c->s));
-  double tot = 0.0;
-  const int64_t k = (int64_t)(c->ev_used / 2);
-  for (int64_t i = 0; i < k; ++i) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
-    tot += ms;
-  }
-  if (avg_ms) *avg_ms = k ? tot / k : 0.0;
-  if (count) *count = k;
-  // two N x N x n complex products per chain = 8 * 2 N^2 n real flops
-  if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
-  return CFQMC_OK;
+  return timing_average(c, c->ev, c->ev_used, avg_ms, count, flops_per_launch);
 }
 
 int cfqmc_kernel_timing_read_woodbury(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch) {
   if (!c) return CFQMC_EINVAL;
-  HIPCHK(hipStreamSynchronize(c->s));
-  double tot = 0.0;
-  const int64_t k = (int64_t)(c->ev2_used / 2);
-  for (int64_t i = 0; i < k; ++i) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev2[2 * i], c->ev2[2 * i + 1]));
-    tot += ms;
-  }
-  if (avg_ms) *avg_ms = k ? tot / k : 0.0;
-  if (count) *count = k;
-  if (flops_per_launch) *flops_per_launch = 8.0 * 2.0 * (double)c->N * c->N * c->n * c->nch;
-  return CFQMC_OK;
+  return timing_average(c, c->ev2, c->ev2_used, avg_ms, count, flops_per_launch);
 }
 
 }  // extern "C"

@@ -328,3 +328,25 @@ def test_autocorrelation_series_match_their_definitions():
             q0 = sum(np.sum(phi[z][:, i, 0]) ** 2 for i in range(4)) / 24
             assert abs(s_q0[-1] - q0) < 1e-12 * max(1.0, q0), (sw, z)
     g.close()
+
+
+def test_kernel_timing_records_one_launch_per_slice_move():
+    """The live HIP-event timing brackets one wrap application (FP32 in the
+    mixed path) and one Woodbury-product application (FP64) per slice move;
+    flops per launch are two N x N x n complex products per chain. Disabling
+    it clears the record."""
+    CFQMC = _gpu()
+    n_phi, L, nch = 6, 8, 2
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=Q_BZ, n_stab=4, precision=1, n_chains=nch,
+              chain_u=[(1.0, 1.0, 1.0)] * nch, tile_cfg=1)
+    g.init_fields(np.stack([synth.fields(40 + k, L, g.n_q) for k in range(nch)]))
+    g.kernel_timing(True)
+    g.sweep(2)
+    for woodbury in (False, True):
+        ms, count, flops = g.kernel_timing_read(woodbury=woodbury)
+        assert count == 2 * L and 0.0 < ms < 1e3
+        assert flops == 8.0 * 2.0 * n_phi ** 2 * (2 * n_phi) * nch
+    g.kernel_timing(False)
+    g.sweep(1)
+    assert g.kernel_timing_read()[1] == 0 and g.kernel_timing_read(woodbury=True)[1] == 0
+    g.close()
