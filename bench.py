@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--therm", type=int, default=4,
+                    help="thermalisation sweeps from the N(0,1) start before the warm-up (untimed; their G "
+                         "errors are reported apart)")
     ap.add_argument("--n-phi", type=int, default=100)
     ap.add_argument("--l-tau", type=int, default=400)
     ap.add_argument("--dtau", type=float, default=0.1)
@@ -167,6 +170,10 @@ def main():
     progress("contexts created (tiles %s)" % (g.tile_config(),))
     b.init_fields()
     progress("fields initialised")
+    g_err_therm = []
+    if args.therm > 0:
+        _, _, g_err_therm = sweep_each(b, args.therm)
+        progress("thermalisation done")
     if args.warmup:
         b.sweep(args.warmup)
         progress("warm-up done")
@@ -197,6 +204,8 @@ def main():
         "eps": float(np.mean(np.concatenate([q.get_eps() for q in b.groups]))),
         "g_err_max": max(g_err),
         "g_err_per_sweep": g_err,
+        "thermalization_sweeps": args.therm,
+        "g_err_per_thermalization_sweep": g_err_therm,
         "g_err_definition": "max over chains and recomputation points of max|G - G_FP64| / max|G_FP64|",
         "g_err_abs_max": max(x["max_stab_err"] for x in flat),
         "g_err_abs_median_chain": float(np.median([max(st[z]["max_stab_err"] for st in stats)
