@@ -33,6 +33,9 @@
  * values, exponential range exceeded) marks the chain state invalid until
  * cfqmc_init_fields is called again.
  * Threading: one context per host thread at a time; no global state.
+ * Debugging: with CFQMC_DEBUG_SYNC=1 in the environment every kernel launch
+ * is followed by a device synchronisation, and a failing launch prints the
+ * kernel's name to stderr (slow; for locating a fault).
  */
 #ifndef CFQMC_H
 #define CFQMC_H
