@@ -195,3 +195,15 @@ def test_host_only_entry_points_reject_bad_arguments():
     assert lib.cfqmc_sphere_weights(2, None) == -1
     assert lib.cfqmc_sphere_weights(2, buf.ctypes.data) == 0
     assert abs(abs(buf[0]) - 0.5) < 1e-15                                # n_{0,0} = +-1/2 on the orbitals
+
+
+def test_product_path_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises at load and at context
+    creation: there is no CPU fallback."""
+    from paper_2605_03700_amd import cfqmc
+    monkeypatch.setattr(cfqmc, "_lib", None)
+    monkeypatch.setattr(cfqmc, "LIB_PATH", str(tmp_path / "missing" / "libcfqmc.so"))
+    with pytest.raises(RuntimeError, match="not found"):
+        cfqmc.load()
+    with pytest.raises(RuntimeError, match="not found"):
+        cfqmc.CFQMC(n_phi=4, l_tau=8)
