@@ -134,8 +134,9 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (chains shard "
-              "independently; see the design notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the chains are independent, so "
+              "several GPUs would each run their own contexts with no communication). Use --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         import torch
