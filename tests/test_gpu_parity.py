@@ -382,3 +382,13 @@ def test_bench_launch_configuration_256_chains_mixed():
         assert abs(ld.real - ldr.real) < 1e-10 * abs(ldr.real), k
         ref.close()
     g.close()
+
+
+@pytest.mark.parametrize("n_phi,L,nstab", [(1, 3, 2), (2, 1, 1)])
+def test_degenerate_shapes_replay(n_phi, L, nstab):
+    """The smallest shapes: one orbital per flavour (n = 2, the single q = 0
+    component) with a ragged stabilisation block, and a single time slice.
+    Replayed FP64 sweeps of two chains against the oracle: identical
+    accept/reject sequences, G and ln w within 1e-10."""
+    CFQMC = _gpu()
+    _replay_compare(CFQMC, n_phi, L, nstab, Q_BZ, None, [1.0, 1.3], 0, 3, 1e-10)
