@@ -35,8 +35,8 @@ def rel(a, b):
 DT = 0.02
 
 
-@pytest.mark.parametrize("n_phi,L,nstab,u", [(2, 6, 3, 0.5), (3, 8, 4, 0.3), (4, 10, 4, 0.2), (6, 40, 5, 0.2),
-                                             (12, 20, 4, 0.3)])
+@pytest.mark.parametrize("n_phi,L,nstab,u", [(1, 4, 3, 0.5), (2, 6, 3, 0.5), (3, 8, 4, 0.3), (4, 10, 4, 0.2),
+                                             (6, 40, 5, 0.2), (12, 20, 4, 0.3)])
 def test_sphere_green_logdet_observables_at_init(n_phi, L, nstab, u):
     CFQMC = _gpu()
     m = Model(n_phi, L, DT, u0=1.0, uk=u, un=u, q_mode=Q_SPHERE)
@@ -66,6 +66,12 @@ def test_sphere_sweep_replay_parity_fp64():
     accept/reject sequences, fields, G and ln w within 1e-10."""
     CFQMC = _gpu()
     _replay_compare(CFQMC, 6, 40, 4, Q_SPHERE, None, [0.2, 0.5], 0, 6, 1e-10, dtau=DT, exp_squarings=6)
+
+
+def test_sphere_sweep_replay_parity_single_orbital():
+    """N_phi = 1 (s = 0: one orbital, the single l = 0 component), ragged block."""
+    CFQMC = _gpu()
+    _replay_compare(CFQMC, 1, 5, 2, Q_SPHERE, None, [0.3, 0.5], 0, 3, 1e-10, dtau=DT, exp_squarings=6)
 
 
 def test_sphere_sweep_replay_parity_odd_orbitals():
