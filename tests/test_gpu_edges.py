@@ -68,3 +68,35 @@ def test_u_zero_is_the_free_projected_band(precision):
         assert abs(ld.real - 2 * (2 * n_phi) * np.log(2.0)) < 1e-12 and abs(ld.imag) < 1e-12
     assert np.abs(g.get_fields() - phi0).max() > 0.0
     g.close()
+
+
+def test_error_paths_leave_the_context_usable():
+    """Calls before the fields exist report a state error, out-of-range
+    chains, slices and sphere momenta report invalid arguments, and none of
+    these changes the context: it then initialises, sweeps and measures as
+    usual."""
+    CFQMC = _gpu()
+    from paper_2605_03700_amd import Q_SPHERE
+    n_phi, L = 4, 8
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=Q_BZ, n_stab=4, n_chains=2, seed=4)
+    with pytest.raises(RuntimeError, match="ESTATE"):
+        g.sweep(1)
+    with pytest.raises(RuntimeError, match="ESTATE"):
+        g.measure_G(0, 0)
+    g.init_fields()
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        g.measure_G(2, 0)
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        g.measure_G(0, L + 1)
+    st = g.sweep(1)
+    assert all(s["max_stab_rel"] < 1e-10 for s in st)
+    assert abs(np.trace(g.measure_G(1, L)).real - 2 * n_phi) < 1e-10
+    g.close()
+    s = CFQMC(n_phi=3, l_tau=4, dtau=0.02, uk=0.3, un=0.3, q_mode=Q_SPHERE, n_stab=2, exp_squarings=6)
+    s.init_fields()
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        s.structure_factors([(3, 0)])          # l = N_phi exceeds 2s = N_phi - 1
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        s.structure_factors([(1, 2)])          # m > l
+    assert np.isfinite(s.structure_factors([(1, 1)])).all()
+    s.close()
