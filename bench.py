@@ -74,19 +74,22 @@ def progress(msg):
     print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
-def sweep_each(b, steps):
+def sweep_each(b, steps, report_every=0):
     """Run `steps` sweeps one at a time; returns wall time, stats of every
     chain over all sweeps, and per sweep the max over chains of
     max|G_updated - G_FP64| / max|G_FP64| (relative, max norm) at the
-    recomputation points."""
+    recomputation points. report_every > 0 prints a progress line every that
+    many sweeps."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats, g_err = [], []
-    for _ in range(steps):
+    for i in range(steps):
         st = b.sweep(1)
         stats.append(st)
         g_err.append(max(x["max_stab_rel"] for x in st))
+        if report_every > 0 and (i + 1) % report_every == 0:
+            progress("%d of %d sweeps" % (i + 1, steps))
     torch.cuda.synchronize()
     return time.perf_counter() - t0, stats, g_err
 
@@ -243,7 +246,7 @@ def main():
     tau = None
     if args.tau_sweeps > 0:
         n0 = [len(q.series(0)) for q in b.groups]
-        dt2, _, g_err2 = sweep_each(b, args.tau_sweeps)
+        dt2, _, g_err2 = sweep_each(b, args.tau_sweeps, report_every=10)
         out["g_err_max_later_sweeps"] = max(g_err2)
         out["g_err_per_later_sweep"] = g_err2
         taus, open_w = {}, []
