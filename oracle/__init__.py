@@ -12,10 +12,15 @@ order the paper's Methods section states. Readings of silent or garbled
 passages are listed in the design notes of the repository.
 
 Parity status per module:
-  model.py        pinned (Fock-space construction, Hermiticity, counts)
+  model.py        pinned (Fock-space construction, Hermiticity, counts; the
+                  torus density operator against the overlap integrals of the
+                  printed LLL wave functions over one periodic cell)
   fock.py         pinned (Fierz identity exact on one orbital; HS quadrature)
   dqmc.py         pinned (closed forms, Fock-trace identity, mpmath brute
-                  force, finite-difference gradient, Gaussian MALA limit)
+                  force, finite-difference gradient, Gaussian MALA limit;
+                  the interacting chain at N = 2, L = 1: every ln A against
+                  its closed form, the stationary law against quadrature,
+                  the step-size controller settling at the set point)
   observables.py  pinned (Fock-space expectation values at small size)
   slmc.py         pinned (Parseval, closed-form periodogram, translation
                   invariance, finite differences, torch bfloat16 and Adam,

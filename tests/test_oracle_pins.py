@@ -430,3 +430,193 @@ def test_sweep_bookkeeping_consistent():
     assert 0 < len(acc) <= 2 * L
     # ln A of accepted moves obeys its definition on the final state
     assert np.isfinite([h[1] for h in ch.history]).all()
+
+
+# ---------------------------------------------------------------- torus density operator from the wave functions
+
+def _lll_torus(n_phi, xs, ys, k, images=6):
+    """Printed LLL wave function of orbital k (Methods, toric regularization;
+    l_B = 1, square cell L_x = L_y = sqrt(2 pi N)) made periodic in x by the
+    sum over magnetic translations k -> k + j N, evaluated on the grid."""
+    ly = np.sqrt(2 * np.pi * n_phi)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    out = np.zeros_like(X, dtype=complex)
+    for j in range(-images, images + 1):
+        kj = k + j * n_phi
+        out += np.exp(-(X - 2 * np.pi * kj / ly) ** 2 / 2) * np.exp(2j * np.pi * kj * Y / ly)
+    return out / np.sqrt(ly * np.sqrt(np.pi))
+
+
+@pytest.mark.parametrize("n_phi", [3, 4])
+def test_torus_density_operator_from_wave_functions(n_phi):
+    """Eq. torus density operator against its definition n_q = int dr e^{iq.r}
+    psi^dagger psi: the matrix elements int e^{iq.r} phi_k^* phi_k' over one
+    periodic cell of the printed LLL wave functions (q = sqrt(2 pi / N) (qx, qy)).
+    The trapezoid rule is spectrally exact for these periodic integrands. The
+    integral fixes the Gaussian exponent, the orbital shift and the phase; the
+    printed overall factor 1 / (4 pi sqrt N) multiplies it (a normalisation of
+    the couplings, taken as printed)."""
+    n = n_phi
+    lc = np.sqrt(2 * np.pi * n)
+    ng = 96
+    xs = np.arange(ng) * lc / ng
+    ys = np.arange(ng) * lc / ng
+    wf = [_lll_torus(n, xs, ys, k) for k in range(1, n + 1)]
+    dA = (lc / ng) ** 2
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    # normalisation of the periodic states over one cell
+    for k in range(n):
+        for kp in range(n):
+            ov = np.sum(wf[k].conj() * wf[kp]) * dA
+            assert abs(ov - (k == kp)) < 1e-12
+    for (qx, qy) in [(0, 0), (1, 0), (0, 1), (1, 2), (-2, 1), (2, -3), (3, 3)]:
+        qv = np.sqrt(2 * np.pi / n) * np.array([qx, qy])
+        ph = np.exp(1j * (qv[0] * X + qv[1] * Y))
+        M = np.array([[np.sum(ph * wf[k].conj() * wf[kp]) * dA for kp in range(n)] for k in range(n)])
+        ref = m_matrix(qx, qy, n) * (4 * np.pi * np.sqrt(n))
+        assert np.abs(M - ref).max() < 1e-11, (qx, qy)
+        assert abs(form_factor(qx, qy, n) * 4 * np.pi * np.sqrt(n) - np.exp(-np.sum(qv ** 2) / 4)) < 1e-15
+
+
+# ---------------------------------------------------------------- the interacting chain at N = 2, L = 1
+
+# One q = 0 component per channel: q_0 = sqrt(2) F(0) 1, so the slice propagator
+# is a function of a valley 2x2 matrix and the fermion weight is closed form:
+#   channel 0 alone (g = (g0, 0, 0, 0)): w_F = (2 cos(a phi_0 / 2))^{4N},
+#   channels 1, 2 (g = (0, -K, -K, 0)): det(1 + e^{a phi_1 tau_x} e^{a phi_2 tau_y})
+#     = 2 + 2 cosh(a phi_1) cosh(a phi_2), w_F = (2 + 2 cosh cosh)^{2N},
+# with a = sqrt(dtau |g|) sqrt(2) F(0). Derived by hand from B = E_0 E_1 E_2 E_3.
+
+def _closed_lnw(case, a, n_phi, ph):
+    if case == 0:
+        return 4 * n_phi * np.log(np.abs(2 * np.cos(a * ph[0, 0] / 2)))
+    return 2 * n_phi * np.log(2 + 2 * np.cosh(a * ph[1, 0]) * np.cosh(a * ph[2, 0]))
+
+
+def _closed_grad(case, a, n_phi, ph):
+    g = np.zeros_like(ph)
+    if case == 0:
+        g[0, 0] = -2 * n_phi * a * np.tan(a * ph[0, 0] / 2)
+    else:
+        x, y = a * ph[1, 0], a * ph[2, 0]
+        den = 1 + np.cosh(x) * np.cosh(y)
+        g[1, 0] = 2 * n_phi * a * np.sinh(x) * np.cosh(y) / den
+        g[2, 0] = 2 * n_phi * a * np.cosh(x) * np.sinh(y) / den
+    return g
+
+
+def _tiny_model(case, a):
+    from oracle.model import Q_LIST
+    f0 = form_factor(0, 0, 2) * np.sqrt(2)
+    dtau = 0.1
+    gabs = (a / f0) ** 2 / dtau
+    if case == 0:
+        return Model(2, 1, dtau, u0=gabs, uk=0.0, un=0.0, q_mode=Q_LIST, q_list=[(0, 0)])
+    return Model(2, 1, dtau, u0=0.0, uk=gabs, un=0.0, q_mode=Q_LIST, q_list=[(0, 0)])
+
+
+@pytest.mark.parametrize("case,a", [(0, 0.5), (1, 0.4)])
+def test_interacting_chain_lna_closed_form(case, a):
+    """Langevin proposal, proposal density and Metropolis-Hastings test (Methods,
+    Langevin-based global update scheme) with a live fermion weight: every
+    recorded ln A of the oracle's chain equals the closed form
+      -(|phi'|^2 - |phi|^2)/2 + Delta ln w_F + ln f(phi | phi') - ln f(phi' | phi)
+    with phi' = phi + eps^2/2 D + eps eta and D = -phi + grad ln w_F, all in
+    closed form (a sign or factor error in Delta ln w_F or the drift fails)."""
+    m = _tiny_model(case, a)
+    assert m.n_q == 1
+    n_phi = m.n_phi
+    eps = 0.9
+    ch = dqmc.Chain(m, synth.fields(51 + case, 1, 1), eps0=eps, adapt=False)
+    rp = synth.replay(61 + case, 200, 1, 1)
+    for s in range(200):
+        ph = ch.phi[0].copy()
+        ch.sweep(rp[s])
+        eta = rp[s, 0, :4].reshape(4, 1)
+        D = -ph + _closed_grad(case, a, n_phi, ph)
+        php = ph + 0.5 * eps * eps * D + eps * eta
+        Dp = -php + _closed_grad(case, a, n_phi, php)
+        lnA = (-0.5 * (np.sum(php ** 2) - np.sum(ph ** 2))
+               + _closed_lnw(case, a, n_phi, php) - _closed_lnw(case, a, n_phi, ph)
+               - np.sum((ph - php - 0.5 * eps * eps * Dp) ** 2) / (2 * eps * eps)
+               + np.sum((php - ph - 0.5 * eps * eps * D) ** 2) / (2 * eps * eps))
+        got = ch.history[-1][1]
+        assert abs(got - lnA) < 1e-9 * max(1.0, abs(lnA)), (s, got, lnA)
+        assert ch.history[-1][2] == (np.log(rp[s, 0, 4]) < lnA)
+    assert ch.phase_err < 1e-10
+
+
+def _marginal_cdf(case, a, n_phi, grid):
+    """CDF of the stationary marginal of the active field (phi_0 for channel 0,
+    phi_1 for channels 1, 2) from e^{-|phi|^2/2} w_F by quadrature."""
+    if case == 0:
+        dens = np.exp(-grid ** 2 / 2) * np.abs(2 * np.cos(a * grid / 2)) ** (4 * n_phi)
+    else:
+        y, wy = np.polynomial.hermite_e.hermegauss(80)
+        dens = np.array([np.sum(wy * (2 + 2 * np.cosh(a * x) * np.cosh(a * y)) ** (2 * n_phi))
+                         for x in grid]) * np.exp(-grid ** 2 / 2)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (dens[1:] + dens[:-1]) * np.diff(grid))])
+    return cdf / cdf[-1]
+
+
+@pytest.mark.parametrize("case,a", [(0, 0.5), (1, 0.4)])
+def test_interacting_chain_stationary_law(case, a):
+    """The chain samples e^{-|phi|^2/2} w_F(phi) (Methods, continuous HS transform
+    and Langevin update): 2e4 sweeps at N = 2, L = 1 with one active channel
+    component, thinned by 4, against the exact 1D marginal by quadrature
+    (Kolmogorov-Smirnov distance) and its second moment; the inactive channels
+    stay N(0, 1). With ln w_F doubled the exact variance of the active field
+    moves from 0.66 to 0.49 (channel 0) and from 1.46 to 2.70 (channels 1, 2);
+    with its sign flipped, to a non-normalisable law and to 0.76."""
+    m = _tiny_model(case, a)
+    ch = dqmc.Chain(m, synth.fields(71 + case, 1, 1), eps0=1.2, adapt=False)
+    n_sw = 20000
+    rp = synth.replay(81 + case, n_sw, 1, 1)
+    xs = np.empty((n_sw, 4))
+    for s in range(n_sw):
+        ch.sweep(rp[s])
+        xs[s] = ch.phi[0, :, 0]
+    acc = sum(h[2] for h in ch.history) / n_sw
+    assert 0.3 < acc < 0.95
+    act = 0 if case == 0 else 1
+    x = np.sort(xs[500::4, act])
+    grid = np.linspace(-8, 8, 4001)
+    cdf = _marginal_cdf(case, a, m.n_phi, grid)
+    emp = np.arange(1, x.size + 1) / x.size
+    ks = np.max(np.abs(np.interp(x, grid, cdf) - emp))
+    assert ks < 0.03, ks
+    # second moment of the exact marginal
+    pdf = np.gradient(cdf, grid)
+    var = np.sum(pdf * grid ** 2) * (grid[1] - grid[0])
+    assert abs(np.mean(x ** 2) - var) < 0.06 * var
+    assert abs(var - 1.0) > 0.3   # the fermion weight is visible in the law
+    for free in ([3] if case == 0 else [0, 3]):
+        y = xs[500::4, free]
+        assert abs(np.mean(y)) < 0.06 and abs(np.var(y) - 1.0) < 0.08
+
+
+def test_eps_controller_settles():
+    """Adaptive step (Methods, Langevin-based global update scheme): eps <- eps +
+    (r_a - 0.574) * 0.1 after each sweep drives the acceptance to the set point
+    from a step that is too large and from one that is too small; with eps frozen
+    at the settled value the acceptance is the set point."""
+    m = _tiny_model(1, 0.4)
+    from oracle.model import Q_LIST
+    L4 = Model(2, 4, m.dtau, u0=0.0, uk=m.uk, un=0.0, q_mode=Q_LIST, q_list=[(0, 0)])
+    settled = []
+    for eps0, seed in ((3.0, 91), (0.05, 92)):
+        ch = dqmc.Chain(L4, synth.fields(seed, 4, 1), eps0=eps0, adapt=True)
+        rp = synth.replay(seed + 10, 1500, 4, 1)
+        eps_hist = []
+        for s in range(1500):
+            ch.sweep(rp[s])
+            eps_hist.append(ch.eps)
+        acc = np.array([h[2] for h in ch.history[-4 * 1000:]])
+        assert abs(acc.mean() - 0.574) < 0.02, (eps0, acc.mean())
+        settled.append(np.mean(eps_hist[500:]))
+    assert abs(settled[0] - settled[1]) < 0.15 * settled[0]
+    ch = dqmc.Chain(L4, synth.fields(95, 4, 1), eps0=np.mean(settled), adapt=False)
+    rp = synth.replay(96, 1500, 4, 1)
+    ch.run(rp)
+    acc = np.array([h[2] for h in ch.history[400:]])
+    assert abs(acc.mean() - 0.574) < 0.04, acc.mean()
