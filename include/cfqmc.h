@@ -35,7 +35,11 @@
  * Threading: one context per host thread at a time; no global state.
  * Debugging: with CFQMC_DEBUG_SYNC=1 in the environment every kernel launch
  * is followed by a device synchronisation, and a failing launch prints the
- * kernel's name to stderr (slow; for locating a fault).
+ * kernel's name to stderr (slow; for locating a fault). CFQMC_LU_NP_LMAX
+ * (read at cfqmc_create, default 8) is the largest multiplier the
+ * non-pivoted LU of the Woodbury matrix M accepts before a chain is
+ * refactorised with partial pivoting; 0 sends every chain to the pivoted
+ * path (for testing that path).
  */
 #ifndef CFQMC_H
 #define CFQMC_H
@@ -92,6 +96,15 @@ typedef struct {
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential, 0..16 (default 2) */
   int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..7 fixed channel-application
                             configuration (GEMMs use min(tile_cfg, 3)) */
+  int32_t dense4n;       /* 0 (only value): the spin-block form n = 2 N_phi. The Fierz channels act as
+                            the identity on spin (eq. newmodel), so G_4N = 1_spin (x) G_2N exactly and
+                            every output is expanded to 4N; 1 (the un-Fierzed dense 4N coupling, which
+                            has a sign problem) returns CFQMC_ENOTIMPL from cfqmc_create */
+  int32_t exact_drift;   /* 0 (only value): the Langevin drift differentiates each channel exponential to
+                            first order, D = -phi + 2 Re alpha_i Tr[(1 - G_i)(o_i (x) q_c)] with G_i the
+                            frame of channel i. 1 (the exact Frechet gradient of the printed gradient
+                            equation) returns CFQMC_ENOTIMPL: any deterministic drift leaves the
+                            Metropolis-Hastings chain exact, only its acceptance differs */
 } cfqmc_params;
 
 typedef struct {
@@ -106,11 +119,13 @@ typedef struct {
 
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
  * n_stab=10, FP64, eps0=0.5, r0=0.574, deps=0.1, eps in [1e-3, 5], adapt on,
- * one chain, exp_squarings=2, tile_cfg=-1). */
+ * one chain, exp_squarings=2, tile_cfg=-1, dense4n=0, exact_drift=0). */
 void cfqmc_default_params(cfqmc_params* p);
 
 /* Create a context: builds the model tables on the host, allocates device
- * state. hip_stream: a hipStream_t (NULL = default stream). No fields yet. */
+ * state. hip_stream: a hipStream_t (NULL = default stream). No fields yet.
+ * CFQMC_EINVAL for invalid parameters, CFQMC_ENOTIMPL for dense4n or
+ * exact_drift other than 0 (*out stays NULL in both cases). */
 int cfqmc_create(const cfqmc_params* p, void* hip_stream, cfqmc_ctx** out);
 int cfqmc_destroy(cfqmc_ctx* c);
 
@@ -248,6 +263,17 @@ int cfqmc_batch_context(cfqmc_batch* b, int32_t group, cfqmc_ctx** ctx);
  * group runs the same number of slice steps (equal_time = 1). stats: NULL or
  * [total chains], group-major. Synchronises. */
 int cfqmc_batch_sweep(cfqmc_batch* b, int32_t n_sweeps, int32_t equal_time, cfqmc_stats* stats);
+/* The same interleaved sweep (n_sweeps per group) with replayed noise: replay
+ * NULL (device noise for every group) or an array of n_groups host pointers,
+ * entry g NULL or the group's buffer [n_chains_g][n_sweeps][l_tau_g][4 n_q_g + 1]
+ * in the layout of cfqmc_sweep. stats as cfqmc_batch_sweep. Synchronises. */
+int cfqmc_batch_sweep_replay(cfqmc_batch* b, int32_t n_sweeps, const double* const* replay, cfqmc_stats* stats);
+/* The context holding chain `chain` of the batch (chains numbered group-major,
+ * as the stats of cfqmc_batch_sweep) and the chain's index inside it
+ * (local_chain may be NULL): a view for cfqmc_measure_G, cfqmc_logdet and the
+ * other per-context calls, owned by the batch. CFQMC_EINVAL if chain is out of
+ * range. */
+int cfqmc_batch_get(cfqmc_batch* b, int32_t chain, cfqmc_ctx** view, int32_t* local_chain);
 int cfqmc_batch_destroy(cfqmc_batch* b);
 
 /* ---- Learned global proposal (self-learning Monte Carlo).
@@ -297,6 +323,13 @@ int cfqmc_slmc_get_norm(cfqmc_slmc* s, float* mu, float* sigma, double* y_bar, d
 int cfqmc_slmc_features(cfqmc_slmc* s, const double* phi, int32_t n, float* feat);
 /* S_NN of n host configurations, and dS_NN/dphi [n][l_tau][4][n_q] if grad_phi != NULL. */
 int cfqmc_slmc_action(cfqmc_slmc* s, const double* phi, int32_t n, double* s_nn, double* grad_phi);
+/* Gradient check of the learned action against a CPU reference: for n >= 1 host
+ * configurations phi [n][l_tau][4][n_q], the GPU forward value fwd_out[n] =
+ * S_NN(phi) and its field gradient grad_out [n][l_tau][4][n_q] = dS_NN/dphi
+ * (features, BF16 network and the backward pass through the binning and the
+ * DFT run in the library's kernels; outputs FP64, host, owned by the caller).
+ * Both outputs are required (else CFQMC_EINVAL). Synchronises. */
+int cfqmc_slmc_grad_check(cfqmc_slmc* s, const double* phi, int32_t n, double* fwd_out, double* grad_out);
 /* Mean squared error of the network on n <= max_batch standardised inputs x [n][n_feat]
  * against standardised targets y [n], its parameter gradient [n_params] and the outputs
  * [n] (any output may be NULL). No parameter update. */
@@ -330,6 +363,16 @@ int cfqmc_slmc_global_move(cfqmc_slmc* s, int32_t n_traj, int32_t n_leap, double
                            cfqmc_slmc_move* out);
 /* Proposal phi' of the last global move of one chain (host [l_tau][4][n_q]). */
 int cfqmc_slmc_last_proposal(cfqmc_slmc* s, int32_t chain, double* phi_out);
+
+/* The stabilisation check the sweep applies at every FP64 recomputation, on
+ * caller data: for count pairs of n x n complex128 matrices X_z, Y_z (device,
+ * contiguous, row-major, stride n*n, owned by the caller), out[2z] =
+ * max|X_z - Y_z| and out[2z + 1] = max|X_z - Y_z| / max|Y_z| (host [count][2]).
+ * A non-finite entry of X_z or Y_z gives +inf in both and the call returns
+ * CFQMC_ENUMERIC, as a sweep does for such a state. hip_stream: a hipStream_t
+ * (NULL = default). Allocates a small temporary. Synchronises. */
+int cfqmc_green_maxdiff(const void* x_dev, const void* y_dev, int32_t n, int32_t count, void* hip_stream,
+                        double* out);
 
 const char* cfqmc_last_error(const cfqmc_ctx* c);
 

@@ -2,7 +2,8 @@
 
 Every source is compiled with packed FP32 instructions disabled
 (-Xclang -target-feature -Xclang -packed-fp32-ops) and linked into one
-shared library next to this file.
+shared library next to this file; the kernel microbenchmark driver kbench
+(csrc/kbench.cpp) is linked against it.
 """
 import concurrent.futures
 import os
@@ -37,8 +38,16 @@ def build(verbose=True):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr[-4000:])
     os.replace(OUT + ".tmp", OUT)
+    # the kernel microbenchmark driver (timing and hardware-counter runs of single kernels)
+    kb = os.path.join(HERE, "kbench")
+    cmd = ["hipcc"] + FLAGS + [os.path.join(CSRC, "kbench.cpp"), "-L", HERE, "-lcfqmc", "-Wl,-rpath,$ORIGIN",
+                               "-o", kb + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for kbench.cpp:\n" + r.stderr[-4000:])
+    os.replace(kb + ".tmp", kb)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", kb)
     return OUT
 
 

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
         ("eps_min", ctypes.c_double), ("eps_max", ctypes.c_double),
         ("adapt_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_chains", ctypes.c_int32),
         ("chain_u", ctypes.POINTER(ctypes.c_double)), ("exp_squarings", ctypes.c_int32),
-        ("tile_cfg", ctypes.c_int32),
+        ("tile_cfg", ctypes.c_int32), ("dense4n", ctypes.c_int32), ("exact_drift", ctypes.c_int32),
     ]
 
 
@@ -61,11 +61,13 @@ EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes
            "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_sphere_weights", "cfqmc_slmc_set_subspace", "cfqmc_logdet", "cfqmc_observables",
            "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_kernel_timing_read_woodbury", "cfqmc_batch_create",
-           "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
+           "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_sweep_replay", "cfqmc_batch_get",
+           "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
            "cfqmc_slmc_create", "cfqmc_slmc_destroy", "cfqmc_slmc_sizes", "cfqmc_slmc_set_params",
            "cfqmc_slmc_get_params", "cfqmc_slmc_set_norm", "cfqmc_slmc_get_norm", "cfqmc_slmc_features",
            "cfqmc_slmc_action", "cfqmc_slmc_loss_grad", "cfqmc_slmc_collect", "cfqmc_slmc_clear_data",
-           "cfqmc_slmc_train", "cfqmc_slmc_global_move", "cfqmc_slmc_last_proposal"]
+           "cfqmc_slmc_train", "cfqmc_slmc_global_move", "cfqmc_slmc_last_proposal", "cfqmc_slmc_grad_check",
+           "cfqmc_green_maxdiff"]
 
 
 def load():
@@ -110,6 +112,8 @@ def load():
     lib.cfqmc_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(P)]
     lib.cfqmc_batch_context.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.cfqmc_batch_sweep.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
+    lib.cfqmc_batch_sweep_replay.argtypes = [P, ctypes.c_int32, P, P]
+    lib.cfqmc_batch_get.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int32)]
     lib.cfqmc_batch_destroy.argtypes = [P]
     D = ctypes.c_double
     lib.cfqmc_slmc_default_params.argtypes = [ctypes.POINTER(SlmcParams)]
@@ -124,12 +128,14 @@ def load():
     lib.cfqmc_slmc_get_norm.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.cfqmc_slmc_features.argtypes = [P, P, ctypes.c_int32, P]
     lib.cfqmc_slmc_action.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.cfqmc_slmc_grad_check.argtypes = [P, P, ctypes.c_int32, P, P]
     lib.cfqmc_slmc_loss_grad.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(D), P, P]
     lib.cfqmc_slmc_collect.argtypes = [P]
     lib.cfqmc_slmc_clear_data.argtypes = [P]
     lib.cfqmc_slmc_train.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, ctypes.c_int32, ctypes.POINTER(D)]
     lib.cfqmc_slmc_global_move.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, P, P]
     lib.cfqmc_slmc_last_proposal.argtypes = [P, ctypes.c_int32, P]
+    lib.cfqmc_green_maxdiff.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P]
     lib.cfqmc_last_error.argtypes = [P]
     lib.cfqmc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -145,7 +151,8 @@ def _ptr(a):
 
 def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                 q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
-                eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1):
+                eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1,
+                dense4n=0, exact_drift=0):
     """Fill a Params structure; returns (params, keep-alive arrays)."""
     lib = load()
     p = Params()
@@ -167,6 +174,7 @@ def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PA
         keep.append(cu)
         p.chain_u = cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
+    p.dense4n, p.exact_drift = int(dense4n), int(exact_drift)
     return p, keep
 
 
@@ -176,7 +184,7 @@ class CFQMC:
     def __init__(self, n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                  q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                  eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
-                 tile_cfg=-1, stream=None, _handle=None):
+                 tile_cfg=-1, dense4n=0, exact_drift=0, stream=None, _handle=None):
         lib = load()
         self.lib = lib
         if _handle is not None:          # view of a context owned by a batch
@@ -203,6 +211,7 @@ class CFQMC:
             self._cu = np.ascontiguousarray(np.asarray(chain_u, dtype=np.float64).reshape(n_chains, 3))
             p.chain_u = self._cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
+        p.dense4n, p.exact_drift = int(dense4n), int(exact_drift)
         if stream is None:
             import torch
             if not torch.cuda.is_available():
@@ -382,9 +391,28 @@ class Batch:
         for g in self.groups:
             g.init_fields(None)
 
-    def sweep(self, n_sweeps=1, equal_time=False):
+    def get(self, chain):
+        """(group context view, chain index inside it) of a batch-wide chain index."""
+        c, loc = ctypes.c_void_p(), ctypes.c_int32()
+        rc = self.lib.cfqmc_batch_get(self.h, chain, ctypes.byref(c), ctypes.byref(loc))
+        if rc != 0:
+            raise RuntimeError("cfqmc_batch_get failed: %s" % ERRORS.get(rc, rc))
+        for g in self.groups:
+            if g.h.value == c.value:
+                return g, loc.value
+        raise RuntimeError("cfqmc_batch_get returned an unknown context")
+
+    def sweep(self, n_sweeps=1, equal_time=False, replay=None):
+        """Interleaved sweep of all groups; replay: None or one buffer (or None) per
+        group, [n_chains][n_sweeps][l_tau][4 n_q + 1] each (n_sweeps per group)."""
         st = (Stats * self.n_chains)()
-        rc = self.lib.cfqmc_batch_sweep(self.h, n_sweeps, int(bool(equal_time)), ctypes.cast(st, ctypes.c_void_p))
+        if replay is not None:
+            bufs = [None if r is None else np.ascontiguousarray(r, dtype=np.float64) for r in replay]
+            ptrs = (ctypes.c_void_p * len(bufs))(*[None if r is None else r.ctypes.data for r in bufs])
+            rc = self.lib.cfqmc_batch_sweep_replay(self.h, n_sweeps, ctypes.cast(ptrs, ctypes.c_void_p),
+                                                   ctypes.cast(st, ctypes.c_void_p))
+        else:
+            rc = self.lib.cfqmc_batch_sweep(self.h, n_sweeps, int(bool(equal_time)), ctypes.cast(st, ctypes.c_void_p))
         if rc != 0:
             msgs = []
             for g in self.groups:
@@ -476,6 +504,15 @@ class Slmc:
             return s, g.reshape(n, self.ctx.l_tau, 4, self.ctx.n_q)
         return s
 
+    def grad_check(self, phi):
+        """(S_NN, dS_NN/dphi) of configurations phi [n][l_tau][4][n_q] from the GPU kernels."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, self.fields_per_chain)
+        n = phi.shape[0]
+        f = np.empty(n)
+        g = np.empty_like(phi)
+        self._check(self.lib.cfqmc_slmc_grad_check(self.h, _ptr(phi), n, _ptr(f), _ptr(g)), "grad_check")
+        return f, g.reshape(n, self.ctx.l_tau, 4, self.ctx.n_q)
+
     def loss_grad(self, x, y):
         x = np.ascontiguousarray(x, dtype=np.float32)
         y = np.ascontiguousarray(y, dtype=np.float64)
@@ -528,6 +565,21 @@ class Slmc:
             self.close()
         except Exception:
             pass
+
+
+def green_maxdiff(x, y, stream=None):
+    """(return code, [count][2] max|X - Y| and max|X - Y| / max|Y|) of two torch
+    complex128 device tensors [count][n][n] by the library's stabilisation check
+    (non-finite entries give +inf and CFQMC_ENUMERIC = -4)."""
+    lib = load()
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    assert x.shape == y.shape and x.dim() == 3 and x.shape[1] == x.shape[2]
+    out = np.empty((x.shape[0], 2))
+    rc = lib.cfqmc_green_maxdiff(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.shape[1],
+                                 x.shape[0], ctypes.c_void_p(stream), _ptr(out))
+    return rc, out
 
 
 def sphere_weights(n_phi):

@@ -341,6 +341,7 @@ struct cfqmc_ctx {
   std::vector<hipEvent_t> ev2;   // the same for one application of the Woodbury product per slice
   size_t ev2_used;
   bool ready;
+  double lu_lmax;   // largest multiplier the non-pivoted LU of M accepts before the pivoted refactorisation
   std::string err;
 };
 
@@ -510,12 +511,12 @@ void udt_acc(cfqmc_ctx* c, const double2* C, long long sC, int opC, const double
   // Cholesky-QR, twice
   gemm_nn(c, c->A1, 1, nn, c->A1, 0, nn, c->Gr, nn, B, true);   // Gram matrix: Hermitian
   launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
-  launch_chol_from_lu(c->Gr, n, nn, c->R1, c->sqd1, B, c->s);
+  launch_chol_from_lu(c->Gr, n, nn, c->R1, c->sqd1, B, c->s, c->d_err);
   launch_rsolve(c->A1, n, nn, c->Q1, n, nn, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s, c->rs_ws);
   launch_colscale(c->Q1, n, nn, c->Q1, n, nn, c->sqd1, n, n, n, 0, B, c->s);
   gemm_nn(c, c->Q1, 1, nn, c->Q1, 0, nn, c->Gr, nn, B, true);
   launch_lu_np(c->Gr, n, n, nn, c->ipiv, n, nullptr, nullptr, 1e300, B, c->s);
-  launch_chol_from_lu(c->Gr, n, nn, c->R2, c->sqd2, B, c->s);
+  launch_chol_from_lu(c->Gr, n, nn, c->R2, c->sqd2, B, c->s, c->d_err);
   launch_rsolve(c->Q1, n, nn, Uo, n, sU, c->Gr, n, nn, c->ipiv, n, n, 1, B, c->s, c->rs_ws);
   launch_colscale(Uo, n, sU, Uo, n, sU, c->sqd2, n, n, n, 0, B, c->s);
   gemm_nn(c, c->R2, 0, nn, c->R1, 0, nn, c->Rt, nn, B);
@@ -588,8 +589,9 @@ void green_udt3(cfqmc_ctx* c, int b, double2* Gtt, double2* Gt0, double2* G0t) {
 // quadruple are scratch and must start at zero). With corr != nullptr the
 // correlator of every tau goes to corr[chain][tau][5]; the pass stops after
 // tau_stop (-1: all). out[0..2] receive the buffers holding the final
-// G(tau,0), G(0,tau), G(tau,tau) (two of F / Fp each).
-void displaced_pass(cfqmc_ctx* c, int tau_stop, double2* corr, double* err, double2** out) {
+// G(tau,0), G(0,tau), G(tau,tau) (two of F / Fp each). tr0 [chain][2]: the
+// correlator's traces of G(0) (needed when corr != nullptr).
+void displaced_pass(cfqmc_ctx* c, int tau_stop, double2* corr, double* err, double2** out, double2* tr0) {
   const long long nn = c->nn, NN = c->NN, sPQ = (long long)c->L * 8 * NN;
   double2* cur[3] = {c->Fp[0], c->Fp[1], c->Fp[2]};
   double2* alt[3] = {c->F[0], c->F[1], c->F[2]};
@@ -637,7 +639,7 @@ void displaced_pass(cfqmc_ctx* c, int tau_stop, double2* corr, double* err, doub
       }
     }
     if (corr)
-      launch_disp_corr(cur[0], cur[1], cur[2], nn, c->N, F0, c->tr0, tau == 0, corr + (long long)tau * 5,
+      launch_disp_corr(cur[0], cur[1], cur[2], nn, c->N, F0, tr0, tau == 0, corr + (long long)tau * 5,
                        (long long)(c->L + 1) * 5, c->nch, c->s);
   }
   if (out)
@@ -721,6 +723,15 @@ int build_model_dev(cfqmc_ctx* c) {
   return CFQMC_OK;
 }
 
+// Message of the device error flags: bit 1 an exponential needed more
+// squarings than allowed, bit 2 a Cholesky-QR of the stabilisation broke down.
+std::string dev_err_msg(int ef) {
+  std::string m;
+  if (ef & 1) m = "exponential range exceeded";
+  if (ef & 2) m += std::string(m.empty() ? "" : "; ") + "Cholesky-QR breakdown in the stabilisation (Gram pivot not positive)";
+  return m;
+}
+
 int check_finite_host(cfqmc_ctx* c, const double* dptr, long long count) {
   std::vector<double> h(count);
   HIPCHK(hipMemcpy(h.data(), dptr, count * sizeof(double), hipMemcpyDeviceToHost));
@@ -784,7 +795,7 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   // 5. LU of M: ln det M. M is close to the identity, so the blocked LU without
   //    pivoting is tried first; chains whose multipliers exceed the threshold
   //    are refactorised with partial pivoting from the saved copy.
-  launch_lu_np(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, c->lu_flag, 8.0, c->nch, c->s);
+  launch_lu_np(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, c->lu_flag, c->lu_lmax, c->nch, c->s);
   launch_lu(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, 1, c->nch, c->s, c->lu_flag, c->Mb);
   // 6. G' = G_0 M^{-1}
   launch_rsolve(c->F[0], c->n, nn, c->Fp[0], c->n, nn, c->Mw, c->n, nn, c->ipiv, c->n, c->n, 0, c->nch, c->s,
@@ -967,6 +978,7 @@ void cfqmc_default_params(cfqmc_params* p) {
   p->eps0 = 0.5; p->r0 = 0.574; p->deps = 0.1; p->eps_min = 1e-3; p->eps_max = 5.0;
   p->adapt_eps = 1; p->seed = 1; p->n_chains = 1;
   p->exp_squarings = 2; p->tile_cfg = -1;
+  p->dense4n = 0; p->exact_drift = 0;
 }
 
 int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
@@ -977,6 +989,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
       !(p.eps0 > 0) || p.eps_min <= 0 || p.eps_max < p.eps_min || p.exp_squarings < 0 || p.exp_squarings > 16 ||
       (p.precision < CFQMC_FP64 || p.precision > CFQMC_MIXED_ALL) || p.tile_cfg < -1 || p.tile_cfg >= CFQMC_CHAN_CFGS)
     return CFQMC_EINVAL;
+  if (p.dense4n < 0 || p.dense4n > 1 || p.exact_drift < 0 || p.exact_drift > 1) return CFQMC_EINVAL;
+  if (p.dense4n || p.exact_drift) return CFQMC_ENOTIMPL;
   cfqmc_ctx* c = new cfqmc_ctx();
   c->p = p;
   c->p.q_list = nullptr;
@@ -990,6 +1004,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->nn = (long long)c->n * c->n;
   c->NN = (long long)c->N * c->N;
   c->ready = false;
+  c->lu_lmax = 8.0;
+  if (const char* e = std::getenv("CFQMC_LU_NP_LMAX")) c->lu_lmax = std::atof(e);
   c->timing = false;
   c->ev_used = 0;
   c->sweep_counter = 0;
@@ -1160,7 +1176,7 @@ int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
   HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
   c->series_len = 0;
   c->sweep_counter = 0;
-  if (ef) { c->err = "exponential range exceeded at init"; c->ready = false; return CFQMC_ENUMERIC; }
+  if (ef) { c->err = dev_err_msg(ef) + " at init"; c->ready = false; return CFQMC_ENUMERIC; }
   std::vector<double2> g(c->nn);
   HIPCHK(hipMemcpy(g.data(), c->G, c->nn * sizeof(double2), hipMemcpyDeviceToHost));
   for (auto& v : g)
@@ -1338,7 +1354,7 @@ int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
   }
   if (bad) {
     c->ready = false;
-    c->err = ef ? "exponential range exceeded" : "non-finite state";
+    c->err = ef ? dev_err_msg(ef) : "non-finite state (G, its FP64 recomputation or the step size)";
     return CFQMC_ENUMERIC;
   }
   return CFQMC_OK;
@@ -1419,6 +1435,58 @@ int cfqmc_batch_context(cfqmc_batch* b, int32_t group, cfqmc_ctx** ctx) {
   if (!b || !ctx || group < 0 || group >= (int)b->g.size()) return CFQMC_EINVAL;
   *ctx = b->g[group];
   return CFQMC_OK;
+}
+
+int cfqmc_batch_get(cfqmc_batch* b, int32_t chain, cfqmc_ctx** view, int32_t* local_chain) {
+  if (!b || !view || chain < 0) return CFQMC_EINVAL;
+  int off = 0;
+  for (cfqmc_ctx* c : b->g) {
+    if (chain < off + c->nch) {
+      *view = c;
+      if (local_chain) *local_chain = chain - off;
+      return CFQMC_OK;
+    }
+    off += c->nch;
+  }
+  return CFQMC_EINVAL;
+}
+
+int cfqmc_batch_sweep_replay(cfqmc_batch* b, int32_t n_sweeps, const double* const* replay, cfqmc_stats* stats) {
+  if (!b || n_sweeps < 0) return CFQMC_EINVAL;
+  const int G = (int)b->g.size();
+  int Lmax = 0;
+  for (auto c : b->g) {
+    if (!c->ready) { b->err = "fields not initialised"; return CFQMC_ESTATE; }
+    Lmax = std::max(Lmax, c->L);
+    sweep_reset_stats(c);
+  }
+  // every group runs n_sweeps sweeps; slice steps interleaved as in cfqmc_batch_sweep
+  const long long kmax = (long long)n_sweeps * Lmax;
+  for (long long k = 0; k < kmax; ++k)
+    for (int q = 0; q < G; ++q) {
+      cfqmc_ctx* c = b->g[q];
+      if (k >= (long long)n_sweeps * c->L) continue;
+      const int t = (int)(k % c->L);
+      const double* rp = replay ? replay[q] : nullptr;
+      if (rp && t == 0) {
+        const int W = 4 * c->nq + 1, sw = (int)(k / c->L);
+        if (hipMemcpy2DAsync(c->noise, (size_t)c->L * W * sizeof(double), rp + (size_t)sw * c->L * W,
+                             (size_t)n_sweeps * c->L * W * sizeof(double), (size_t)c->L * W * sizeof(double), c->nch,
+                             hipMemcpyHostToDevice, c->s) != hipSuccess) {
+          b->err = "replay upload failed";
+          return CFQMC_EHIP;
+        }
+      }
+      sweep_slice(c, t, rp ? c->noise : nullptr);
+      if (t == c->L - 1) sweep_end(c);
+    }
+  int rc = CFQMC_OK, off = 0;
+  for (int q = 0; q < G; ++q) {
+    const int r = sweep_collect(b->g[q], stats ? stats + off : nullptr);
+    if (r && !rc) rc = r;
+    off += b->g[q]->nch;
+  }
+  return rc;
 }
 
 int cfqmc_batch_sweep(cfqmc_batch* b, int32_t n_sweeps, int32_t equal_time, cfqmc_stats* stats) {
@@ -1505,7 +1573,7 @@ int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel) {
     if (rc) { c->corr = nullptr; return CFQMC_ENOMEM; }
   }
   hipMemsetAsync(c->disp_err, 0, (size_t)c->nch * 12 * sizeof(double), c->s);
-  displaced_pass(c, -1, c->corr, c->disp_err, nullptr);
+  displaced_pass(c, -1, c->corr, c->disp_err, nullptr, c->tr0);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   HIPCHK(hipMemcpy(out, c->corr, cnt * sizeof(double2), hipMemcpyDeviceToHost));
@@ -1524,7 +1592,7 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
   if (!c || chain < 0 || chain >= c->nch || tau < 0 || tau > c->L) return CFQMC_EINVAL;
   if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
   double2* res[3];
-  displaced_pass(c, tau, nullptr, nullptr, res);
+  displaced_pass(c, tau, nullptr, nullptr, res, nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   double* outs[3] = {gt0, g0t, gtt};
@@ -2015,6 +2083,11 @@ int cfqmc_slmc_action(cfqmc_slmc* s, const double* phi, int32_t n, double* s_nn,
   return CFQMC_OK;
 }
 
+int cfqmc_slmc_grad_check(cfqmc_slmc* s, const double* phi, int32_t n, double* fwd_out, double* grad_out) {
+  if (!s || !phi || !fwd_out || !grad_out || n < 1) return CFQMC_EINVAL;
+  return cfqmc_slmc_action(s, phi, n, fwd_out, grad_out);
+}
+
 int cfqmc_slmc_loss_grad(cfqmc_slmc* s, const float* x, const double* y, int32_t n, double* loss, float* grad,
                          float* out) {
   if (!s || !x || !y || n < 1 || n > s->Bmax) return CFQMC_EINVAL;
@@ -2249,6 +2322,31 @@ int cfqmc_slmc_last_proposal(cfqmc_slmc* s, int32_t chain, double* phi_out) {
   HIPCHK(hipStreamSynchronize(c->s));
   HIPCHK(hipMemcpy(phi_out, s->phi_cur + (long long)chain * s->nf, s->nf * sizeof(double), hipMemcpyDeviceToHost));
   return CFQMC_OK;
+}
+
+int cfqmc_green_maxdiff(const void* x_dev, const void* y_dev, int32_t n, int32_t count, void* hip_stream,
+                        double* out) {
+  if (!x_dev || !y_dev || !out || n < 1 || count < 1) return CFQMC_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* d = nullptr;
+  if (hipMalloc(&d, (size_t)4 * count * sizeof(double)) != hipSuccess) return CFQMC_ENOMEM;
+  std::vector<double> h((size_t)4 * count, 0.0);
+  int rc = CFQMC_OK;
+  if (hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) rc = CFQMC_EHIP;
+  if (!rc) {
+    launch_maxdiff((const double2*)x_dev, (const double2*)y_dev, n, (long long)n * n, d, count, st, 4);
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      rc = CFQMC_EHIP;
+  }
+  hipFree(d);
+  if (rc) return rc;
+  for (int z = 0; z < count; ++z) {
+    out[2 * z] = h[4 * z];
+    out[2 * z + 1] = h[4 * z + 1];
+    if (!std::isfinite(h[4 * z]) || !std::isfinite(h[4 * z + 1])) rc = CFQMC_ENUMERIC;
+  }
+  return rc;
 }
 
 const char* cfqmc_last_error(const cfqmc_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -1,0 +1,165 @@
+// Kernel microbenchmark of the sweep's hot kernels at a given shape, for
+// per-kernel timing and hardware-counter runs (rocprofv3) outside a sweep.
+//
+//   kbench <kernel> [n_phi] [chains] [iters] [cfg]
+//   kernel: chan32 | chan64   channel application Y = E X (left, tau_y rotation,
+//                             the wrap's timed launch), FP32 correction form or FP64
+//           chan32r | chan64r the right application X E^-1 (tau_x rotation)
+//           lu_np             LU of M = 1 + small (non-pivoted, in place)
+//           rsolve            G' = G M^-1 from that LU
+//
+// Inputs are seeded random matrices of the sweep's shapes: M (n x n, n =
+// 2 n_phi, entries O(1)), the orbital blocks X = 1 + A with ||A|| ~ 0.3 (the
+// channel exponentials of typical fields). Every launch covers all chains, as
+// in the sweep. The driver times `iters` launches after two warm-up launches
+// with a device synchronisation on each side (no HIP events), and prints the
+// mean duration and the launch's algorithmic work: for the channel
+// application 2 n^3 real flops per chain (one of the eight applications that
+// make up the two n x n x n complex products of the wrap) next to the 4 n^3
+// the kernel issues (two N x N x n complex products).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace {
+
+void fill_random(std::vector<double2>& v, uint64_t seed, double scale) {
+  uint64_t s = seed * 0x9E3779B97F4A7C15ull + 1;
+  for (auto& x : v) {
+    s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+    const double a = ((s >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+    s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+    const double b = ((s >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+    x = make_double2(scale * a, scale * b);
+  }
+}
+
+#define CK(x)                                                                      \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) {                                                        \
+      std::fprintf(stderr, "kbench: %s at %s\n", hipGetErrorString(e_), #x);     \
+      std::exit(1);                                                                \
+    }                                                                              \
+  } while (0)
+
+double2* upload(const std::vector<double2>& h) {
+  double2* d = nullptr;
+  CK(hipMalloc(&d, h.size() * sizeof(double2)));
+  CK(hipMemcpy(d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice));
+  return d;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc < 2) {
+    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|lu_np|rsolve [n_phi] [chains] [iters] [cfg]\n");
+    return 2;
+  }
+  const std::string k = argv[1];
+  const int N = argc > 2 ? std::atoi(argv[2]) : 100;
+  const int B = argc > 3 ? std::atoi(argv[3]) : 256;
+  const int iters = argc > 4 ? std::atoi(argv[4]) : 20;
+  const int cfg = argc > 5 ? std::atoi(argv[5]) : 1;
+  if (N < 1 || N > 140 || B < 1 || B > 512 || iters < 1 || cfg < 0 || cfg >= CFQMC_CHAN_CFGS) {
+    std::fprintf(stderr, "kbench: n_phi 1..140, chains 1..512, iters >= 1, cfg 0..%d\n", CFQMC_CHAN_CFGS - 1);
+    return 2;
+  }
+  const int n = 2 * N;
+  const long long nn = (long long)n * n, NN = (long long)N * N;
+  hipStream_t s = nullptr;
+  std::vector<double2> hM((size_t)B * nn);
+  fill_random(hM, 1, 1.0);
+  std::function<void()> run;
+  double algo = 0.0, issued = 0.0;
+  const char* what = "";
+  std::vector<void*> bufs;
+  if (k.rfind("chan", 0) == 0) {
+    const bool mixed = k.find("32") != std::string::npos;
+    const bool right = k.back() == 'r';
+    std::vector<double2> hX((size_t)B * 2 * NN);
+    fill_random(hX, 2, 0.3 / N);   // entries ~ 0.3 / N: a matrix norm ~ 0.3
+    for (int z = 0; z < 2 * B; ++z)
+      for (int i = 0; i < N; ++i) hX[(size_t)z * NN + (size_t)i * N + i].x += 1.0;
+    double2* dM = upload(hM);
+    double2* dX = upload(hX);
+    double2* dY = nullptr;
+    CK(hipMalloc(&dY, (size_t)B * nn * sizeof(double2)));
+    bufs = {dM, dX, dY};
+    ChanArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.N = N; a.n_other = n;
+    a.M = dM; a.ldM = n; a.sM = nn;
+    a.X0 = dX; a.X1 = dX + NN; a.ldX = N; a.sX = 2 * NN;
+    a.Y = dY; a.ldY = n; a.sY = nn;
+    const int left = right ? 0 : 1, rot = right ? 1 : 2;
+    run = [=]() { launch_chan_apply(a, left, rot, B, mixed ? 1 : 0, cfg, s); };
+    algo = 2.0 * (double)n * n * n * B;
+    issued = 16.0 * (double)N * N * n * B;
+    what = mixed ? "channel application, FP32 correction form" : "channel application, FP64 (3-product MFMA)";
+  } else if (k == "lu_np" || k == "rsolve") {
+    // M = 1 + 0.05 R: close to the identity, as the Woodbury matrix of a slice move
+    std::vector<double2> hA((size_t)B * nn);
+    fill_random(hA, 3, 0.05 / std::sqrt((double)n));
+    for (int z = 0; z < B; ++z)
+      for (int i = 0; i < n; ++i) hA[(size_t)z * nn + (size_t)i * n + i].x += 1.0;
+    double2* dA0 = upload(hA);
+    double2* dA = nullptr;
+    double2* dld = nullptr;
+    int *dpiv = nullptr, *dflag = nullptr;
+    CK(hipMalloc(&dA, (size_t)B * nn * sizeof(double2)));
+    CK(hipMalloc(&dld, (size_t)B * sizeof(double2)));
+    CK(hipMalloc(&dpiv, (size_t)B * n * sizeof(int)));
+    CK(hipMalloc(&dflag, (size_t)B * sizeof(int)));
+    CK(hipMemcpy(dA, dA0, (size_t)B * nn * sizeof(double2), hipMemcpyDeviceToDevice));
+    bufs = {dA0, dA, dld, dpiv, dflag};
+    if (k == "lu_np") {
+      // the factorisation works in place: restore A before every launch (a copy kernel, timed apart)
+      run = [=]() {
+        launch_copy(dA0, dA, nn, nn, nn, B, s);
+        launch_lu_np(dA, n, n, nn, dpiv, n, dld, dflag, 8.0, B, s);
+      };
+      algo = 8.0 / 3.0 * (double)n * n * n * B;
+      issued = algo;
+      what = "non-pivoted LU (plus the restoring copy)";
+    } else {
+      launch_lu_np(dA, n, n, nn, dpiv, n, dld, dflag, 8.0, B, s);
+      double2* dG = upload(hM);
+      double2 *dY = nullptr, *ws = nullptr;
+      CK(hipMalloc(&dY, (size_t)B * nn * sizeof(double2)));
+      CK(hipMalloc(&ws, (size_t)B * rsolve_work_size(n) * sizeof(double2)));
+      bufs.push_back(dG);
+      bufs.push_back(dY);
+      bufs.push_back(ws);
+      run = [=]() { launch_rsolve(dG, n, nn, dY, n, nn, dA, n, nn, dpiv, n, n, 0, B, s, ws); };
+      algo = 8.0 * (double)n * n * n * B;
+      issued = algo;
+      what = "right solve G M^-1 (two triangular solves)";
+    }
+  } else {
+    std::fprintf(stderr, "kbench: unknown kernel %s\n", k.c_str());
+    return 2;
+  }
+  for (int w = 0; w < 2; ++w) run();
+  CK(hipDeviceSynchronize());
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < iters; ++i) run();
+  CK(hipDeviceSynchronize());
+  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / iters;
+  CK(hipGetLastError());
+  std::printf("{\"kernel\": \"%s\", \"what\": \"%s\", \"n_phi\": %d, \"chains\": %d, \"cfg\": %d, \"iters\": %d, "
+              "\"us_per_launch\": %.2f, \"algorithmic_tflops\": %.3f, \"issued_tflops\": %.3f}\n",
+              k.c_str(), what, N, B, cfg, iters, us, algo / us * 1e-6, issued / us * 1e-6);
+  for (void* p : bufs) hipFree(p);
+  return 0;
+}

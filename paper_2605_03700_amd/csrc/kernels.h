@@ -72,11 +72,14 @@ inline long long rsolve_work_size(int n) { return (long long)((n + 15) / 16) * 5
 void launch_set_identity(double2* A, int n, int lda, long long sA, int nbatch, hipStream_t s);
 void launch_copy(const double2* X, double2* Y, long long count, long long sX, long long sY, int nbatch,
                  hipStream_t s);
+// p[0..count) = v (a kernel, so that callers under stream capture record no memset node)
+void launch_fill(double* p, long long count, double v, hipStream_t s);
 // Y[:, k] = X[:, k] * d[k]   (d real, per batch stride sd) ; inv: divide instead
 void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
                      const double* d, long long sd, int n_rows, int n_cols, int inv, int nbatch, hipStream_t s);
 // running max |X - Y| (out[so z]) and max |X - Y| / max |Y| (out[so z + 1]) per batch
-// entry; out[so z + 2], out[so z + 3] are scratch that must start at zero
+// entry; out[so z + 2], out[so z + 3] are scratch that must start at zero. A
+// non-finite entry of X or Y makes both maxima +inf.
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
                     hipStream_t s, int so = 4);
 
@@ -89,8 +92,9 @@ void launch_permute_normalize(const double2* W, int n, long long sW, const doubl
                               double2* A, int nbatch, hipStream_t s);
 // Cholesky factor from an unpivoted LU of a Hermitian PD Gram matrix:
 // R = diag(1/sqrt(u_kk)) U (upper triangle of LU), sqrtd[k] = sqrt(u_kk).
+// A pivot that is not positive and finite sets bit 2 of *err (when err != nullptr).
 void launch_chol_from_lu(const double2* LU, int n, long long sLU, double2* R, double* sqrtd, int nbatch,
-                         hipStream_t s);
+                         hipStream_t s, int* err);
 // From Rt (upper, n x n), norms and permutation: D' = |diag(Rt) * nrm|,
 // T'[i][perm[k]] = Rt[i][k] * nrm[perm[k]] / D'[i].
 void launch_udt_finish(const double2* Rt, int n, long long sR, const double* nrm, const int* perm,

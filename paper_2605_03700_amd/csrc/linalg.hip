@@ -968,6 +968,16 @@ void launch_set_identity(double2* A, int n, int lda, long long sA, int nbatch, h
   hipLaunchKernelGGL(set_identity_kernel, grid, dim3(256), 0, s, A, n, lda, sA); cfqmc_post_launch("set_identity_kernel");
 }
 
+__global__ void fill_kernel(double* p, long long count, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+void launch_fill(double* p, long long count, double v, hipStream_t s) {
+  if (count <= 0) return;
+  const int nblk = (int)std::min<long long>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk), dim3(256), 0, s, p, count, v); cfqmc_post_launch("fill_kernel");
+}
+
 __global__ void copy_kernel(const double2* X, double2* Y, long long count, long long sX, long long sY) {
   const double2* x = X + blockIdx.y * sX;
   double2* y = Y + blockIdx.y * sY;
@@ -1005,8 +1015,12 @@ __global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long l
   double m = 0.0, my = 0.0;
   for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
     const double2 a = X[z * sX + idx], b = Y[z * sX + idx];
-    m = fmax(m, sqrt(cabs2(csub(a, b))));
-    my = fmax(my, sqrt(cabs2(b)));
+    // fmax drops a NaN operand: a non-finite difference or entry counts as +inf
+    double d = sqrt(cabs2(csub(a, b))), y = sqrt(cabs2(b));
+    if (!(d <= 1.7976931348623157e308)) d = INFINITY;
+    if (!(y <= 1.7976931348623157e308)) y = INFINITY;
+    m = fmax(m, d);
+    my = fmax(my, y);
   }
   for (int o = 32; o > 0; o >>= 1) {
     m = fmax(m, __shfl_xor(m, o, 64));
@@ -1026,8 +1040,10 @@ __global__ void maxdiff_fold_kernel(double* out, int nbatch, int so) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= nbatch) return;
   const double d = out[so * z + 2], gm = out[so * z + 3];
+  // +inf (a non-finite entry on either side) stays +inf in both maxima
+  const double r = (isinf(d) || isinf(gm)) ? INFINITY : (gm > 0.0 ? d / gm : d);
   out[so * z + 0] = fmax(out[so * z + 0], d);
-  out[so * z + 1] = fmax(out[so * z + 1], gm > 0.0 ? d / gm : d);
+  out[so * z + 1] = fmax(out[so * z + 1], r);
   out[so * z + 2] = 0.0;
   out[so * z + 3] = 0.0;
 }
@@ -1078,20 +1094,22 @@ void launch_permute_normalize(const double2* W, int n, long long sW, const doubl
   hipLaunchKernelGGL(permute_normalize_kernel, grid, dim3(256), 0, s, W, n, sW, nrm, perm, A); cfqmc_post_launch("permute_normalize_kernel");
 }
 
-__global__ void chol_from_lu_kernel(const double2* LU, int n, long long sLU, double2* R, double* sqrtd) {
+__global__ void chol_from_lu_kernel(const double2* LU, int n, long long sLU, double2* R, double* sqrtd, int* err) {
   const int z = blockIdx.y;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * n; idx += gridDim.x * blockDim.x) {
     const int i = idx / n, j = idx % n;
     const double u = LU[z * sLU + (long long)i * n + i].x;
+    // a Gram pivot that is not positive and finite: the Cholesky-QR broke down
+    if (j == i && err && !(u > 0.0 && u <= 1.7976931348623157e308)) atomicOr(err, 2);
     const double sq = sqrt(u);
     R[z * sLU + idx] = j >= i ? cscale(LU[z * sLU + idx], 1.0 / sq) : make_double2(0.0, 0.0);
     if (j == i) sqrtd[z * n + i] = sq;
   }
 }
 void launch_chol_from_lu(const double2* LU, int n, long long sLU, double2* R, double* sqrtd, int nbatch,
-                         hipStream_t s) {
+                         hipStream_t s, int* err) {
   dim3 grid(min((n * n + 255) / 256, 1024), nbatch);
-  hipLaunchKernelGGL(chol_from_lu_kernel, grid, dim3(256), 0, s, LU, n, sLU, R, sqrtd); cfqmc_post_launch("chol_from_lu_kernel");
+  hipLaunchKernelGGL(chol_from_lu_kernel, grid, dim3(256), 0, s, LU, n, sLU, R, sqrtd, err); cfqmc_post_launch("chol_from_lu_kernel");
 }
 
 __global__ void udt_finish_kernel(const double2* Rt, int n, long long sR, const double* nrm, const int* perm,

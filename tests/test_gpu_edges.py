@@ -100,3 +100,63 @@ def test_error_paths_leave_the_context_usable():
         s.structure_factors([(1, 2)])          # m > l
     assert np.isfinite(s.structure_factors([(1, 1)])).all()
     s.close()
+
+
+def test_stabilisation_check_reports_non_finite_entries():
+    """The check applied at every FP64 recomputation (max |G_updated - G_FP64|)
+    must not hide a NaN: a non-finite entry on either side gives +inf and
+    CFQMC_ENUMERIC, finite pairs give the plain maxima."""
+    _gpu()
+    import torch
+    from paper_2605_03700_amd.cfqmc import green_maxdiff
+    rng = np.random.default_rng(5)
+    n, cnt = 20, 4
+    a = rng.normal(size=(cnt, n, n)) + 1j * rng.normal(size=(cnt, n, n))
+    b = a + 1e-7 * (rng.normal(size=(cnt, n, n)) + 1j * rng.normal(size=(cnt, n, n)))
+    x = torch.tensor(a, device="cuda")
+    y = torch.tensor(b, device="cuda")
+    rc, out = green_maxdiff(x, y)
+    assert rc == 0
+    d = np.abs(a - b).max(axis=(1, 2))
+    assert np.allclose(out[:, 0], d, rtol=1e-14, atol=0)
+    assert np.allclose(out[:, 1], d / np.abs(b).max(axis=(1, 2)), rtol=1e-14, atol=0)
+    a2, b2 = a.copy(), b.copy()
+    a2[1, 3, 4] = complex(np.nan, 0.0)      # NaN in the updated G
+    b2[2, 0, 0] = complex(0.0, np.inf)      # inf in the recomputation
+    a2[3] = complex(np.nan, np.nan)         # a whole NaN matrix
+    rc, out = green_maxdiff(torch.tensor(a2, device="cuda"), torch.tensor(b2, device="cuda"))
+    assert rc == -4
+    assert np.allclose(out[0], [d[0], d[0] / np.abs(b[0]).max()], rtol=1e-14)
+    for z in (1, 2, 3):
+        assert np.isinf(out[z, 0]) and np.isinf(out[z, 1]), (z, out[z])
+
+
+def test_woodbury_pivoted_fallback_replay_parity(monkeypatch):
+    """The Woodbury determinant's pivoted path: with the non-pivoted LU's
+    multiplier limit set to 0 every chain is refactorised with partial pivoting
+    from the saved copy of M. Replayed sweeps against the oracle: identical
+    accept/reject sequences, G and ln w within 1e-10."""
+    CFQMC = _gpu()
+    monkeypatch.setenv("CFQMC_LU_NP_LMAX", "0")
+    n_phi, L, nstab, u = 6, 12, 4, 1.2
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=u, un=u, q_mode=Q_BZ)
+    phi = np.stack([synth.fields(700 + k, L, m.n_q) for k in range(2)])
+    rp = np.stack([synth.replay(710 + k, 2, L, m.n_q) for k in range(2)])
+    g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, u0=1.0, uk=u, un=u, q_mode=Q_BZ, n_stab=nstab, eps0=0.4,
+              n_chains=2, tile_cfg=1)
+    g.init_fields(phi)
+    chains = [dqmc.Chain(m, phi[k], eps0=0.4, adapt=True) for k in range(2)]
+    for sw in range(2):
+        st = g.sweep(1, rp[:, sw:sw + 1])
+        for k in range(2):
+            chains[k].sweep(rp[k, sw])
+            acc, lna = g.last_sweep(k)
+            hist = chains[k].history[-L:]
+            assert acc.tolist() == [int(h[2]) for h in hist], (k, sw)
+            assert np.abs(lna - np.array([h[1] for h in hist])).max() < 1e-7
+            assert st[k]["max_stab_err"] < 1e-9
+    for k in range(2):
+        assert rel(g.measure_G(k, L)[:2 * n_phi, :2 * n_phi], dqmc.green(m, chains[k].phi, L)) < 1e-10
+        ld, ldr = g.logdet(k), dqmc.logdet(m, chains[k].phi)
+        assert abs(ld.real - ldr.real) < 1e-10 * abs(ldr.real)
+    g.close()

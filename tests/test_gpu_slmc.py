@@ -73,7 +73,10 @@ def test_action_and_field_gradient_match_oracle():
     net = _random_net(fm, 48, rng, phis)
     s.set_params(net.flat())
     s.set_norm(net.mu, net.sigma, net.y_bar, net.s_y)
-    S, G = s.action(np.stack(phis), grad=True)
+    # the gradient-check entry point (cfqmc_slmc_grad_check) against the oracle
+    S, G = s.grad_check(np.stack(phis))
+    S2, G2 = s.action(np.stack(phis), grad=True)
+    assert np.array_equal(S, S2) and np.array_equal(G, G2)
     for k, phi in enumerate(phis):
         sr, gr = net.action_grad(fm, phi, bf16=True)
         assert abs(S[k] - sr) < 2e-3 * net.s_y

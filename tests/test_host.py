@@ -56,6 +56,21 @@ def test_param_struct_layout_and_validation(lib):
     q.q_mode = 3       # explicit list missing
     assert L.cfqmc_create(ctypes.byref(q), None, ctypes.byref(h)) == -1
     assert L.cfqmc_destroy(None) == -1
+    # the dense 4N form and the exact drift are declared and not implemented
+    assert p.dense4n == 0 and p.exact_drift == 0
+    for field, val, rc in [("dense4n", 1, -6), ("exact_drift", 1, -6), ("dense4n", 2, -1), ("exact_drift", -1, -1)]:
+        q = cfqmc.Params()
+        L.cfqmc_default_params(ctypes.byref(q))
+        setattr(q, field, val)
+        h = ctypes.c_void_p()
+        assert L.cfqmc_create(ctypes.byref(q), None, ctypes.byref(h)) == rc, field
+        assert h.value is None
+    # argument checks that need no GPU
+    assert L.cfqmc_batch_get(None, 0, ctypes.byref(h), None) == -1
+    assert L.cfqmc_batch_sweep_replay(None, 1, None, None) == -1
+    out = np.empty(2)
+    assert L.cfqmc_green_maxdiff(None, None, 4, 1, None, out.ctypes.data_as(ctypes.c_void_p)) == -1
+    assert L.cfqmc_slmc_grad_check(None, None, 1, None, None) == -1
 
 
 def test_tau_int_ar1_closed_form():
