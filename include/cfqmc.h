@@ -189,6 +189,22 @@ int cfqmc_green_displaced(cfqmc_ctx* c, int32_t chain, int32_t tau, double* gt0,
  * Call between sweeps. Synchronises. */
 int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel);
 
+/* Allocation-free variant of cfqmc_measure_tau, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same pass and kernels, with the
+ * correlator's per-chain partial results (traces of G(0), running maxima of
+ * the carried-vs-recomputed check) in a fixed device array of the library
+ * (64 KiB per GPU: at most 512 chains, else CFQMC_EINVAL with a message) and
+ * the outputs in caller-owned device memory:
+ *   out_dev       device [n_chains][l_tau + 1][5] complex128 (re/im interleaved),
+ *   stab_rel_dev  NULL or device [n_chains][3] doubles (as stab_rel above).
+ * Calls no hipMalloc/hipFree and does not synchronise: the results are ready
+ * when the context's stream reaches them. Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (different streams or threads) race;
+ * the array keeps the last call's contents and each call clears what must
+ * start at zero. Call between sweeps. */
+int cfqmc_measure_tau_noalloc(cfqmc_ctx* c, void* out_dev, void* stab_rel_dev);
+
 /* Orbital weights of the sphere's density operators (Methods, eq. sphere
  * density operator), the table behind CFQMC_Q_SPHERE: out[(l N + m) N + r] =
  * n_{l,m}[r, r + m] for 0 <= m <= l <= N - 1 and rows r of the orbitals

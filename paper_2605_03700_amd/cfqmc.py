@@ -67,7 +67,7 @@ EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes
            "cfqmc_slmc_get_params", "cfqmc_slmc_set_norm", "cfqmc_slmc_get_norm", "cfqmc_slmc_features",
            "cfqmc_slmc_action", "cfqmc_slmc_loss_grad", "cfqmc_slmc_collect", "cfqmc_slmc_clear_data",
            "cfqmc_slmc_train", "cfqmc_slmc_global_move", "cfqmc_slmc_last_proposal", "cfqmc_slmc_grad_check",
-           "cfqmc_green_maxdiff"]
+           "cfqmc_green_maxdiff", "cfqmc_measure_tau_noalloc"]
 
 
 def load():
@@ -93,6 +93,7 @@ def load():
     lib.cfqmc_measure_G.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32]
     lib.cfqmc_green_displaced.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P]
     lib.cfqmc_measure_tau.argtypes = [P, P, P]
+    lib.cfqmc_measure_tau_noalloc.argtypes = [P, P, P]
     lib.cfqmc_structure_factors.argtypes = [P, P, ctypes.c_int32, P]
     lib.cfqmc_sphere_weights.argtypes = [ctypes.c_int32, P]
     lib.cfqmc_slmc_set_subspace.argtypes = [P, ctypes.c_int32]

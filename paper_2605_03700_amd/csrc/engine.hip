@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -262,6 +263,17 @@ bool build_components(const cfqmc_params& p, HostTables& T, std::string& err) {
 
 }  // namespace
 
+// Device scratch of the allocation-free correlator entry point
+// (cfqmc_measure_tau_noalloc): per chain the two traces of G(0) the correlator
+// kernel keeps (2 x 16 B) and the twelve running maxima of the carried-vs-
+// recomputed check (12 x 8 B), 128 B per chain, at most 512 chains. Each GPU
+// holds its own copy until the process ends. Host code never passes the
+// symbol itself to a kernel: it uses the device address from
+// hipGetSymbolAddress, resolved once per device.
+constexpr size_t kScratchBytes = 64 * 1024;
+constexpr size_t kScratchPerChain = 2 * sizeof(double2) + 12 * sizeof(double);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct Udt {
   double2* U;   // [chain][nb+1][n][n]
   double2* T;
@@ -342,6 +354,7 @@ struct cfqmc_ctx {
   size_t ev2_used;
   bool ready;
   double lu_lmax;   // largest multiplier the non-pivoted LU of M accepts before the pivoted refactorisation
+  int dev;   // device current at creation (owner of the stream's memory)
   std::string err;
 };
 
@@ -1004,6 +1017,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->nn = (long long)c->n * c->n;
   c->NN = (long long)c->N * c->N;
   c->ready = false;
+  c->dev = 0;
+  hipGetDevice(&c->dev);
   c->lu_lmax = 8.0;
   if (const char* e = std::getenv("CFQMC_LU_NP_LMAX")) c->lu_lmax = std::atof(e);
   c->timing = false;
@@ -1585,6 +1600,57 @@ int cfqmc_measure_tau(cfqmc_ctx* c, double* out, double* stab_rel) {
   }
   for (long long i = 0; i < 2 * cnt; ++i)
     if (!std::isfinite(out[i])) { c->err = "non-finite correlator"; return CFQMC_ENUMERIC; }
+  return CFQMC_OK;
+}
+
+namespace {
+// Device address of `scratch` on device dev, from hipGetSymbolAddress with that
+// device current (each GPU holds its own copy of the array); resolved once per
+// device and kept.
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64] = {};
+
+int scratch_address(cfqmc_ctx* c, void** out) {
+  if (c->dev < 0 || c->dev >= 64) { c->err = "scratch: device index out of range"; return CFQMC_EINVAL; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[c->dev]) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != c->dev) HIPCHK(hipSetDevice(c->dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != c->dev) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess || !p) {
+      c->err = std::string("scratch: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+      return CFQMC_EHIP;
+    }
+    g_scratch_addr[c->dev] = p;
+  }
+  *out = g_scratch_addr[c->dev];
+  return CFQMC_OK;
+}
+}  // namespace
+
+int cfqmc_measure_tau_noalloc(cfqmc_ctx* c, void* out_dev, void* stab_rel_dev) {
+  if (!c || !out_dev) return CFQMC_EINVAL;
+  if (!c->ready) { c->err = "fields not initialised"; return CFQMC_ESTATE; }
+  if ((size_t)c->nch * kScratchPerChain > kScratchBytes) {
+    c->err = "measure_tau_noalloc: " + std::to_string(c->nch) + " chains exceed the " +
+             std::to_string(kScratchBytes / kScratchPerChain) + " chains its fixed scratch holds";
+    return CFQMC_EINVAL;
+  }
+  void* base = nullptr;
+  const int rc = scratch_address(c, &base);
+  if (rc) return rc;
+  double2* tr0 = (double2*)base;
+  double* derr = (double*)(tr0 + 2 * c->nch);
+  // the running maxima start at zero (a fill kernel: no memset node under capture)
+  launch_fill(derr, 12LL * c->nch, 0.0, c->s);
+  displaced_pass(c, -1, (double2*)out_dev, derr, nullptr, tr0);
+  if (stab_rel_dev)
+    HIPCHK(hipMemcpy2DAsync(stab_rel_dev, sizeof(double), derr + 1, 4 * sizeof(double), sizeof(double), 3 * c->nch,
+                            hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(hipGetLastError());
   return CFQMC_OK;
 }
 
