@@ -94,8 +94,10 @@ typedef struct {
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential, 0..16 (default 2) */
-  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..7 fixed channel-application
-                            configuration (GEMMs use min(tile_cfg, 3)) */
+  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..11 fixed channel-application
+                            configuration (GEMMs use min(tile_cfg, 3)). In the FP32 applications
+                            0..7 add each 16-deep k slab into FP64 registers, 8..11 accumulate in
+                            FP32 over the whole k range (the autotuner picks among 0..7 there) */
   int32_t dense4n;       /* 0 (only value): the spin-block form n = 2 N_phi. The Fierz channels act as
                             the identity on spin (eq. newmodel), so G_4N = 1_spin (x) G_2N exactly and
                             every output is expanded to 4N; 1 (the un-Fierzed dense 4N coupling, which
@@ -105,6 +107,13 @@ typedef struct {
                             frame of channel i. 1 (the exact Frechet gradient of the printed gradient
                             equation) returns CFQMC_ENOTIMPL: any deterministic drift leaves the
                             Metropolis-Hastings chain exact, only its acceptance differs */
+  int32_t precision_guard; /* mixed modes: 1 (default) runs the FP32 applications of a chain in FP64 for
+                            the next block of n_stab slices when, at the last FP64 recomputation, its
+                            max|G_FP64| exceeded guard_gmax or its max|G_updated - G_FP64| exceeded
+                            guard_err (the FP32 rounding error of G scales with |G|); 0: FP32 for every
+                            chain. Ignored in CFQMC_FP64 */
+  double guard_gmax;     /* default 1.0 */
+  double guard_err;      /* default 5e-7 */
 } cfqmc_params;
 
 typedef struct {
@@ -115,11 +124,15 @@ typedef struct {
   int32_t exp_range_flag;     /* 1 if an exponential needed more squarings than allowed */
   int32_t pad;
   double max_stab_rel;        /* max over recomputation points of max|G_updated - G_FP64| / max|G_FP64| */
+  double max_abs_g;           /* max over recomputation points of max|G_FP64| */
+  double fp64_guard_frac;     /* fraction of the chain's stabilisation blocks run with FP64 applications
+                                 by the precision guard (mixed modes) */
 } cfqmc_stats;
 
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
  * n_stab=10, FP64, eps0=0.5, r0=0.574, deps=0.1, eps in [1e-3, 5], adapt on,
- * one chain, exp_squarings=2, tile_cfg=-1, dense4n=0, exact_drift=0). */
+ * one chain, exp_squarings=2, tile_cfg=-1, dense4n=0, exact_drift=0,
+ * precision_guard=1, guard_gmax=1, guard_err=5e-7). */
 void cfqmc_default_params(cfqmc_params* p);
 
 /* Create a context: builds the model tables on the host, allocates device
@@ -258,8 +271,11 @@ int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg);
  * one launch per slice is bracketed by events on the context's stream (up to
  * 4096 launches per sample set). enable = 1 starts a new sample set. */
 int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable);
-/* Mean duration (ms) and count of the sampled launches, and the algorithmic
- * real flops of one launch (16 N^2 n per chain). Synchronises. */
+/* Mean duration (ms) and count of the sampled launches, and the real flops one
+ * launch performs: two N x N x n complex products per chain, 8 flops per complex
+ * multiply-add, 16 N^2 n = 4 n^3 per chain (n = 2N). One application carries an
+ * eighth of the wrap G -> B G B^-1, whose algorithmic work counted as two dense
+ * n x n x n complex products is 16 n^3: 2 n^3 per application. Synchronises. */
 int cfqmc_kernel_timing_read(cfqmc_ctx* c, double* avg_ms, int64_t* count, double* flops_per_launch);
 /* The same for one channel application per slice of the Woodbury product
  * M = G + B'B^-1 (1 - G) (the left application of channel 2's inverse,
@@ -358,6 +374,19 @@ int cfqmc_slmc_clear_data(cfqmc_slmc* s);
  * refit_norm = 1 (or the first call) sets mu, sigma, y_bar, s_y from the data.
  * loss_out: mean minibatch loss of the last epoch. */
 int cfqmc_slmc_train(cfqmc_slmc* s, int32_t epochs, int32_t batch, double lr, int32_t refit_norm, double* loss_out);
+/* Adam training with a held-out set and early stopping: the last n_val stored
+ * configurations (collected last, e.g. the final sweeps of every chain) are
+ * never trained on; after each epoch over the others (shuffled minibatches)
+ * the validation MSE on them is evaluated, and training stops once it has not
+ * improved for `patience` epochs (or after max_epochs). The parameters of the
+ * best validation epoch are kept. refit_norm = 1 (or the first call) sets mu,
+ * sigma, y_bar, s_y from the training configurations only. Outputs (any may be
+ * NULL): the last epoch's mean minibatch training loss, the best validation
+ * loss (standardised targets) and its epoch (0-based). CFQMC_ESTATE with fewer
+ * than two training configurations. Synchronises. */
+int cfqmc_slmc_train_heldout(cfqmc_slmc* s, int32_t max_epochs, int32_t batch, double lr, int32_t refit_norm,
+                             int32_t n_val, int32_t patience, double* train_loss, double* val_loss,
+                             int32_t* best_epoch);
 /* Subspace of the learned global move. mode 0 moves every field (the
  * default); 1 moves only component 0 of every channel and slice (q = 0 on the
  * torus, (l, m) = (0, 0) on the sphere); 2 moves only the four slice-uniform

@@ -147,3 +147,53 @@ def correlation_ratio(s_Q, s_Q_dq):
     arguments are Monte Carlo averages (S(Q + dq) may be averaged over the
     symmetry-equivalent dq first). R -> 1 with long-range order, -> 0 without."""
     return 1.0 - np.real(np.asarray(s_Q_dq)) / np.real(np.asarray(s_Q))
+
+
+def fss_scaling_variable(u, n_phi, u_c, delta_s):
+    """Finite-size scaling variable of the SO(5) line (Results, eqs.
+    finite-size-scaling-R and finite-size-scaling-m): x = (u / u_c - 1)
+    sqrt(N_phi)^(3 - Delta_s), with sqrt(N_phi) the linear size."""
+    u = np.asarray(u, dtype=float)
+    n = np.asarray(n_phi, dtype=float)
+    return (u / u_c - 1.0) * np.sqrt(n) ** (3.0 - delta_s)
+
+
+def fss_collapse_r2(u, n_phi, y, u_c, delta_s, delta_v=None, degree=3):
+    """Quality of the data collapse at (u_c, Delta_s): the scaled observable
+    Y = y (correlation ratio R) or Y = y N_phi^Delta_v (m^2_SO(5), with
+    Delta_v given) is fitted by one polynomial F(x) of the given degree (third
+    order, as the paper approximates the universal scaling function near u_c)
+    in the scaling variable x; returns (R^2 = 1 - SS_res / SS_tot, polynomial
+    coefficients, highest power first)."""
+    y = np.asarray(y, dtype=float)
+    Y = y if delta_v is None else y * np.asarray(n_phi, dtype=float) ** delta_v
+    x = fss_scaling_variable(u, n_phi, u_c, delta_s)
+    coef = np.polyfit(x, Y, degree)
+    res = Y - np.polyval(coef, x)
+    tot = Y - Y.mean()
+    ss_tot = float(np.dot(tot, tot))
+    r2 = 1.0 - float(np.dot(res, res)) / ss_tot if ss_tot > 0 else 0.0
+    return r2, coef
+
+
+def fss_grid_scan(u, n_phi, y, u_c_grid, delta_s_grid, delta_v=None, degree=3):
+    """R^2-optimised grid scan over (u_c, Delta_s) (Results, phase structure
+    along the SO(5)-symmetric line; Supplementary Note 3): the R^2 map
+    [len(u_c_grid)][len(delta_s_grid)] of fss_collapse_r2 and the best
+    (u_c, Delta_s, R^2)."""
+    r2 = np.empty((len(u_c_grid), len(delta_s_grid)))
+    for i, uc in enumerate(u_c_grid):
+        for j, ds in enumerate(delta_s_grid):
+            r2[i, j] = fss_collapse_r2(u, n_phi, y, uc, ds, delta_v, degree)[0]
+    i, j = np.unravel_index(np.argmax(r2), r2.shape)
+    return r2, (float(u_c_grid[i]), float(delta_s_grid[j]), float(r2[i, j]))
+
+
+def data_collapse(u, n_phi, y, u_c, delta_s, delta_v=None, degree=3):
+    """Collapsed data at (u_c, Delta_s): (x, Y, fitted F(x), R^2) with x the
+    scaling variable and Y the scaled observable of fss_collapse_r2."""
+    r2, coef = fss_collapse_r2(u, n_phi, y, u_c, delta_s, delta_v, degree)
+    y = np.asarray(y, dtype=float)
+    Y = y if delta_v is None else y * np.asarray(n_phi, dtype=float) ** delta_v
+    x = fss_scaling_variable(u, n_phi, u_c, delta_s)
+    return x, Y, np.polyval(coef, x), r2

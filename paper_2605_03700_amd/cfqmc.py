@@ -30,6 +30,7 @@ class Params(ctypes.Structure):
         ("adapt_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_chains", ctypes.c_int32),
         ("chain_u", ctypes.POINTER(ctypes.c_double)), ("exp_squarings", ctypes.c_int32),
         ("tile_cfg", ctypes.c_int32), ("dense4n", ctypes.c_int32), ("exact_drift", ctypes.c_int32),
+        ("precision_guard", ctypes.c_int32), ("guard_gmax", ctypes.c_double), ("guard_err", ctypes.c_double),
     ]
 
 
@@ -49,7 +50,8 @@ class SlmcMove(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("eps", ctypes.c_double),
                 ("max_stab_err", ctypes.c_double), ("max_phase_err", ctypes.c_double),
-                ("exp_range_flag", ctypes.c_int32), ("pad", ctypes.c_int32), ("max_stab_rel", ctypes.c_double)]
+                ("exp_range_flag", ctypes.c_int32), ("pad", ctypes.c_int32), ("max_stab_rel", ctypes.c_double),
+                ("max_abs_g", ctypes.c_double), ("fp64_guard_frac", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -67,7 +69,7 @@ EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes
            "cfqmc_slmc_get_params", "cfqmc_slmc_set_norm", "cfqmc_slmc_get_norm", "cfqmc_slmc_features",
            "cfqmc_slmc_action", "cfqmc_slmc_loss_grad", "cfqmc_slmc_collect", "cfqmc_slmc_clear_data",
            "cfqmc_slmc_train", "cfqmc_slmc_global_move", "cfqmc_slmc_last_proposal", "cfqmc_slmc_grad_check",
-           "cfqmc_green_maxdiff", "cfqmc_measure_tau_noalloc"]
+           "cfqmc_green_maxdiff", "cfqmc_measure_tau_noalloc", "cfqmc_slmc_train_heldout"]
 
 
 def load():
@@ -134,6 +136,9 @@ def load():
     lib.cfqmc_slmc_collect.argtypes = [P]
     lib.cfqmc_slmc_clear_data.argtypes = [P]
     lib.cfqmc_slmc_train.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, ctypes.c_int32, ctypes.POINTER(D)]
+    lib.cfqmc_slmc_train_heldout.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.POINTER(D), ctypes.POINTER(D),
+                                             ctypes.POINTER(ctypes.c_int32)]
     lib.cfqmc_slmc_global_move.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, P, P]
     lib.cfqmc_slmc_last_proposal.argtypes = [P, ctypes.c_int32, P]
     lib.cfqmc_green_maxdiff.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P]
@@ -153,7 +158,7 @@ def _ptr(a):
 def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                 q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                 eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1,
-                dense4n=0, exact_drift=0):
+                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=5e-7):
     """Fill a Params structure; returns (params, keep-alive arrays)."""
     lib = load()
     p = Params()
@@ -176,6 +181,7 @@ def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PA
         p.chain_u = cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
     p.dense4n, p.exact_drift = int(dense4n), int(exact_drift)
+    p.precision_guard, p.guard_gmax, p.guard_err = int(precision_guard), float(guard_gmax), float(guard_err)
     return p, keep
 
 
@@ -185,7 +191,8 @@ class CFQMC:
     def __init__(self, n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                  q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                  eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
-                 tile_cfg=-1, dense4n=0, exact_drift=0, stream=None, _handle=None):
+                 tile_cfg=-1, dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=5e-7,
+                 stream=None, _handle=None):
         lib = load()
         self.lib = lib
         if _handle is not None:          # view of a context owned by a batch
@@ -213,6 +220,7 @@ class CFQMC:
             p.chain_u = self._cu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
         p.dense4n, p.exact_drift = int(dense4n), int(exact_drift)
+        p.precision_guard, p.guard_gmax, p.guard_err = int(precision_guard), float(guard_gmax), float(guard_err)
         if stream is None:
             import torch
             if not torch.cuda.is_available():
@@ -535,6 +543,15 @@ class Slmc:
         self._check(self.lib.cfqmc_slmc_train(self.h, epochs, batch, lr, int(bool(refit_norm)), ctypes.byref(loss)),
                     "train")
         return loss.value
+
+    def train_heldout(self, max_epochs=200, batch=64, lr=1e-3, n_val=256, patience=10, refit_norm=True):
+        """Early-stopped training with the last n_val stored configurations held out:
+        (last training loss, best validation loss, best epoch)."""
+        tl, vl, be = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        self._check(self.lib.cfqmc_slmc_train_heldout(self.h, max_epochs, batch, lr, int(bool(refit_norm)), n_val,
+                                                      patience, ctypes.byref(tl), ctypes.byref(vl), ctypes.byref(be)),
+                    "train_heldout")
+        return tl.value, vl.value, be.value
 
     SUBSPACES = {"all": 0, "q0": 1, "uniform_q0": 2}
 

@@ -353,6 +353,12 @@ struct cfqmc_ctx {
   std::vector<hipEvent_t> ev2;   // the same for one application of the Woodbury product per slice
   size_t ev2_used;
   bool ready;
+  int guard;            // precision guard active (mixed context with precision_guard = 1)
+  int* sel64;           // [chain] 1: the chain's FP32 applications run in FP64 in the current block
+  int* guard_cnt;       // [chain] blocks run under the guard since the last stats reset
+  double* gmax_run;     // [chain] running max |G_FP64| since the last stats reset
+  double* blk_last;     // [chain][2] max |G_updated - G_FP64|, max |G_FP64| of the last block
+  long long blocks_in_call;
   double lu_lmax;   // largest multiplier the non-pivoted LU of M accepts before the pivoted refactorisation
   int dev;   // device current at creation (owner of the stream's memory)
   std::string err;
@@ -432,6 +438,15 @@ void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, lon
   if (one_minus && (!left || rot)) {                // 1 - M exists only for the left, non-rotating application
     std::fprintf(stderr, "cfqmc: internal error: 1 - M requested for a rotating or right channel\n");
     std::abort();
+  }
+  if (mixed && c->guard) {
+    // FP32 for the chains the guard leaves in FP32, FP64 for the others
+    a.chain_sel = c->sel64;
+    a.sel_want = 0;
+    launch_chan_apply(a, left, rot, c->nch, 1, c->cfg_chan, c->s);
+    a.sel_want = 1;
+    launch_chan_apply(a, left, rot, c->nch, 0, c->cfg_chan64, c->s);
+    return;
   }
   launch_chan_apply(a, left, rot, c->nch, mixed, mixed ? c->cfg_chan : c->cfg_chan64, c->s);
 }
@@ -836,8 +851,14 @@ void block_end(cfqmc_ctx* c, int b) {
   block_product(c, b);
   left_acc(c, b);
   green_udt(c, b + 1, b + 1, c->Gs);
-  launch_maxdiff(c->G, c->Gs, c->n, c->nn, c->stab_err, c->nch, c->s);
+  launch_maxdiff(c->G, c->Gs, c->n, c->nn, c->stab_err, c->nch, c->s, 4, c->blk_last);
   launch_copy(c->Gs, c->G, c->nn, c->nn, c->nn, c->nch, c->s);
+  if (c->guard)
+    launch_precision_guard(c->blk_last, c->sel64, c->guard_cnt, c->gmax_run, c->p.guard_gmax, c->p.guard_err, c->nch,
+                           c->s);
+  else
+    launch_precision_guard(c->blk_last, c->sel64, c->guard_cnt, c->gmax_run, INFINITY, INFINITY, c->nch, c->s);
+  c->blocks_in_call++;
 }
 
 int build_all_exps(cfqmc_ctx* c) {
@@ -923,7 +944,10 @@ int autotune(cfqmc_ctx* c) {
     hipEventElapsedTime(&ms, e0, e1);
     return ms;
   };
-  for (int cfg = 0; cfg < CFQMC_CHAN_CFGS; ++cfg) {
+  // the FP32 applications keep their FP64 accumulation points (configurations
+  // 0..7) unless a configuration is fixed by the caller
+  const int ncfg_app = c->mixed ? CFQMC_CHAN_CFGS_ACC64 : CFQMC_CHAN_CFGS;
+  for (int cfg = 0; cfg < ncfg_app; ++cfg) {
     c->cfg_chan = cfg;
     const float tc = timeit([&]() {
       chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
@@ -992,6 +1016,7 @@ void cfqmc_default_params(cfqmc_params* p) {
   p->adapt_eps = 1; p->seed = 1; p->n_chains = 1;
   p->exp_squarings = 2; p->tile_cfg = -1;
   p->dense4n = 0; p->exact_drift = 0;
+  p->precision_guard = 1; p->guard_gmax = 1.0; p->guard_err = 5e-7;
 }
 
 int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
@@ -1003,6 +1028,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
       (p.precision < CFQMC_FP64 || p.precision > CFQMC_MIXED_ALL) || p.tile_cfg < -1 || p.tile_cfg >= CFQMC_CHAN_CFGS)
     return CFQMC_EINVAL;
   if (p.dense4n < 0 || p.dense4n > 1 || p.exact_drift < 0 || p.exact_drift > 1) return CFQMC_EINVAL;
+  if (p.precision_guard < 0 || p.precision_guard > 1 || !(p.guard_gmax > 0) || !(p.guard_err > 0)) return CFQMC_EINVAL;
   if (p.dense4n || p.exact_drift) return CFQMC_ENOTIMPL;
   cfqmc_ctx* c = new cfqmc_ctx();
   c->p = p;
@@ -1013,6 +1039,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->nblk_stab = (p.l_tau + p.n_stab - 1) / p.n_stab;
   c->mixed = p.precision != CFQMC_FP64;
   c->mixed_m = p.precision == CFQMC_MIXED_ALL;
+  c->guard = c->mixed && p.precision_guard;
+  c->blocks_in_call = 0;
   c->smax = p.exp_squarings;
   c->nn = (long long)c->n * c->n;
   c->NN = (long long)c->N * c->N;
@@ -1101,6 +1129,10 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->hist_lnA, (size_t)B * L);
   rc |= dalloc(c, &c->noise, (size_t)B * L * (4 * nq + 1));
   rc |= dalloc(c, &c->bg, (size_t)B);
+  rc |= dalloc(c, &c->sel64, (size_t)B);
+  rc |= dalloc(c, &c->guard_cnt, (size_t)B);
+  rc |= dalloc(c, &c->gmax_run, (size_t)B);
+  rc |= dalloc(c, &c->blk_last, (size_t)B * 2);
   if (rc) { cfqmc_destroy(c); return CFQMC_ENOMEM; }
   if (build_model_dev(c)) { cfqmc_destroy(c); return CFQMC_ENOMEM; }
   if (c->md.nrow * 4 > 4 * 1024) { c->err = "too many momentum rows"; cfqmc_destroy(c); return CFQMC_EINVAL; }
@@ -1176,6 +1208,7 @@ int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
   }
   HIPCHK(hipMemcpyAsync(c->phi, h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemsetAsync(c->d_err, 0, sizeof(int), c->s));
+  HIPCHK(hipMemsetAsync(c->sel64, 0, c->nch * sizeof(int), c->s));   // every chain starts in FP32
   HIPCHK(hipGetLastError());
   set_udt_identity(c, c->Rs, c->nblk_stab);
   set_udt_identity(c, c->Ls, 0);
@@ -1309,6 +1342,9 @@ namespace {
 void sweep_reset_stats(cfqmc_ctx* c) {
   hipMemsetAsync(c->stat, 0, c->nch * 8 * sizeof(double), c->s);
   hipMemsetAsync(c->stab_err, 0, c->nch * 4 * sizeof(double), c->s);
+  hipMemsetAsync(c->guard_cnt, 0, c->nch * sizeof(int), c->s);
+  hipMemsetAsync(c->gmax_run, 0, c->nch * sizeof(double), c->s);
+  c->blocks_in_call = 0;
 }
 
 void sweep_slice(cfqmc_ctx* c, int t, const double* noise_dev) {
@@ -1349,10 +1385,13 @@ int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
   HIPCHK(hipStreamSynchronize(c->s));
   int ef = 0;
   HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
-  std::vector<double> st(B * 8), se(B * 4), ep(B);
+  std::vector<double> st(B * 8), se(B * 4), ep(B), gm(B);
+  std::vector<int> gc(B);
   HIPCHK(hipMemcpy(st.data(), c->stat, B * 8 * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(se.data(), c->stab_err, B * 4 * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(ep.data(), c->eps, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(gm.data(), c->gmax_run, B * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(gc.data(), c->guard_cnt, B * sizeof(int), hipMemcpyDeviceToHost));
   bool bad = ef != 0;
   for (int z = 0; z < B; ++z) {
     if (!std::isfinite(se[4 * z]) || !std::isfinite(ep[z])) bad = true;
@@ -1365,6 +1404,9 @@ int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
       stats[z].max_phase_err = st[z * 8 + 0];
       stats[z].exp_range_flag = ef;
       stats[z].pad = 0;
+      stats[z].max_abs_g = gm[z];
+      // the guard's choice at the last block end of a sweep applies to the next sweep
+      stats[z].fp64_guard_frac = c->blocks_in_call ? (double)gc[z] / (double)c->blocks_in_call : 0.0;
     }
   }
   if (bad) {
@@ -2273,6 +2315,128 @@ int cfqmc_slmc_train(cfqmc_slmc* s, int32_t epochs, int32_t batch, double lr, in
   HIPCHK(hipMemcpy(la.data(), s->loss_acc, nl * sizeof(double), hipMemcpyDeviceToHost));
   if (loss_out) *loss_out = la[nl - 1] / nbatches;
   if (!std::isfinite(la[nl - 1])) { c->err = "training diverged"; return CFQMC_ENUMERIC; }
+  return CFQMC_OK;
+}
+
+int cfqmc_slmc_train_heldout(cfqmc_slmc* s, int32_t max_epochs, int32_t batch, double lr, int32_t refit_norm,
+                             int32_t n_val, int32_t patience, double* train_loss, double* val_loss,
+                             int32_t* best_epoch) {
+  if (!s || max_epochs < 1 || max_epochs > 4096 || batch < 1 || batch > s->Bmax || !(lr > 0) || n_val < 1 ||
+      patience < 1)
+    return CFQMC_EINVAL;
+  cfqmc_ctx* c = s->c;
+  hipStream_t st = c->s;
+  const int n = s->n_data, F = s->F, nt = n - n_val;
+  if (nt < 2) { c->err = "SLMC held-out training needs at least two training configurations"; return CFQMC_ESTATE; }
+  if (!s->norm_set || refit_norm) {
+    // standardisation from the training configurations only
+    std::vector<float> fx((long long)nt * F);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(fx.data(), s->dx_raw, fx.size() * sizeof(float), hipMemcpyDeviceToHost));
+    std::vector<float> mu(F), sg(F);
+    for (int j = 0; j < F; ++j) {
+      double a = 0.0, q = 0.0;
+      for (int b = 0; b < nt; ++b) a += fx[(long long)b * F + j];
+      a /= nt;
+      for (int b = 0; b < nt; ++b) {
+        const double d = fx[(long long)b * F + j] - a;
+        q += d * d;
+      }
+      const double sd = std::sqrt(q / nt);
+      mu[j] = (float)a;
+      sg[j] = sd > 1e-12 ? (float)sd : 1.f;
+    }
+    double a = 0.0, q = 0.0;
+    for (int b = 0; b < nt; ++b) a += s->hy[b];
+    a /= nt;
+    for (int b = 0; b < nt; ++b) q += (s->hy[b] - a) * (s->hy[b] - a);
+    const double sy = std::sqrt(q / nt);
+    const int rc = cfqmc_slmc_set_norm(s, mu.data(), sg.data(), a, sy > 1e-12 ? sy : 1.0);
+    if (rc) return rc;
+  }
+  std::vector<float> ys(n);
+  for (int b = 0; b < n; ++b) ys[b] = (float)((s->hy[b] - s->ybar) / s->sy);
+  HIPCHK(hipMemcpyAsync(s->yall, ys.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+  launch_slmc_standardize(s->dx_raw, F, s->Fp, s->mu, s->sig, s->xall, n, st);
+  int* idx = nullptr;
+  float* wbest = nullptr;
+  if (hipMalloc(&idx, (size_t)n * sizeof(int)) != hipSuccess ||
+      hipMalloc(&wbest, (size_t)s->P * sizeof(float)) != hipSuccess) {
+    hipFree(idx);
+    c->err = "device allocation failed";
+    return CFQMC_ENOMEM;
+  }
+  // validation rows (the last n_val stored) after the training rows of each epoch's order
+  std::vector<int> order(n);
+  for (int b = 0; b < n; ++b) order[b] = b;
+  std::vector<float> vout(n_val);
+  double best = INFINITY, last_train = 0.0;
+  int best_e = -1, since = 0, rc = CFQMC_OK;
+  const int nbatches = (nt + batch - 1) / batch;
+  for (int e = 0; e < max_epochs && !rc; ++e) {
+    for (int b = nt - 1; b > 0; --b) std::swap(order[b], order[splitmix(s->rng) % (uint64_t)(b + 1)]);
+    if (hipMemcpyAsync(idx, order.data(), n * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) {
+      rc = CFQMC_EHIP;
+      break;
+    }
+    hipMemsetAsync(s->loss_acc, 0, sizeof(double), st);
+    for (int b0 = 0; b0 < nt; b0 += batch) {
+      const int nb = std::min(batch, nt - b0);
+      launch_slmc_gather(s->xall, s->yall, s->Fp, idx + b0, nb, s->xb, s->yb, st);
+      slmc_forward(s, s->xb, nb);
+      launch_slmc_dout(s->out, s->yb, nb, 0, 0.f, s->dout, s->loss_acc, st);
+      slmc_backward(s, s->xb, nb, true, false);
+      launch_slmc_adam(s->w, s->g, s->m, s->v, s->P, lr, ++s->t_adam, st);
+      slmc_refresh_bf16(s);
+    }
+    // validation loss: forward only, on the held-out rows
+    double vl = 0.0;
+    for (int v0 = 0; v0 < n_val && !rc; v0 += s->Bmax) {
+      const int nb = std::min(s->Bmax, n_val - v0);
+      launch_slmc_gather(s->xall, s->yall, s->Fp, idx + nt + v0, nb, s->xb, s->yb, st);
+      slmc_forward(s, s->xb, nb);
+      if (hipStreamSynchronize(st) != hipSuccess ||
+          hipMemcpy(vout.data(), s->out, nb * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = CFQMC_EHIP;
+        break;
+      }
+      for (int b = 0; b < nb; ++b) {
+        const double r = (double)vout[b] - ys[nt + v0 + b];
+        vl += r * r;
+      }
+    }
+    if (rc) break;
+    vl /= n_val;
+    double tl = 0.0;
+    if (hipMemcpy(&tl, s->loss_acc, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) { rc = CFQMC_EHIP; break; }
+    last_train = tl / nbatches;
+    if (!std::isfinite(vl) || !std::isfinite(last_train)) { c->err = "training diverged"; rc = CFQMC_ENUMERIC; break; }
+    if (vl < best) {
+      best = vl;
+      best_e = e;
+      since = 0;
+      if (hipMemcpyAsync(wbest, s->w, (size_t)s->P * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        rc = CFQMC_EHIP;
+    } else if (++since >= patience) {
+      break;
+    }
+  }
+  if (!rc && best_e >= 0) {
+    // keep the parameters of the best validation epoch
+    if (hipMemcpyAsync(s->w, wbest, (size_t)s->P * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      rc = CFQMC_EHIP;
+    else
+      slmc_refresh_bf16(s);
+  }
+  const hipError_t e1 = hipStreamSynchronize(st);
+  hipFree(idx);
+  hipFree(wbest);
+  if (rc) return rc;
+  HIPCHK(e1);
+  HIPCHK(hipGetLastError());
+  if (train_loss) *train_loss = last_train;
+  if (val_loss) *val_loss = best;
+  if (best_epoch) *best_epoch = best_e;
   return CFQMC_OK;
 }
 

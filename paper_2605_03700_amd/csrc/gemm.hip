@@ -493,9 +493,13 @@ CF_DEV double2 rot_out(double2 t0, double2 t1, int v) {
 // loads of slab k+1 and the LDS stores into the other stage overlap the MFMAs
 // of slab k); otherwise one stage with register prefetch and two barriers.
 // OM: the input is 1 - M instead of M (left, non-rotating channel only).
+// FL (FP32 path): each slab's FP32 MFMA sum is added into FP64 registers (an
+// FP64 accumulation point per slab); without FL the FP32 accumulators run
+// over the whole k range and are converted once in the epilogue, where the
+// FP64 input is added back (correction form).
 // Each thread keeps base pointers to its staging elements; a slab advances
 // them by a constant.
-template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, bool FL>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
 chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   typedef typename cplx_t<CT>::type C2;
@@ -507,6 +511,8 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   __shared__ C2 Bs[NS][2][BKC * LDB];
   int z, ty, tx;
   if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  // chains of the other precision class are computed by the companion launch
+  if (c.chain_sel && c.chain_sel[z] != c.sel_want) return;
   const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
@@ -634,6 +640,9 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   Acc3<WTM, WTN> acc3[2];
   acc3[0].zero();
   acc3[1].zero();
+  Acc<float, WTM, WTN> acc32[2];
+  acc32[0].zero();
+  acc32[1].zero();
   const int mr = rows - m0 - wm0, nr = cols - n0 - wn0;
   auto mma = [&](int st, int k0) {
 #pragma unroll
@@ -641,12 +650,15 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       if constexpr (sizeof(CT) == 8) {
         mma_slab3<WTM, WTN, BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
                                  acc3[a], mr, nr, N - k0);
-      } else {
+      } else if constexpr (FL) {
         Acc<float, WTM, WTN> a32;
         a32.zero();
         mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane, a32,
                                        mr, nr, N - k0);
         flush(a32, acc[a]);
+      } else {
+        mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane,
+                                       acc32[a], mr, nr, N - k0);
       }
     }
   };
@@ -675,6 +687,9 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   if constexpr (sizeof(CT) == 8) {
     acc3[0].to(acc[0]);
     acc3[1].to(acc[1]);
+  } else if constexpr (!FL) {
+    flush(acc32[0], acc[0]);
+    flush(acc32[1], acc[1]);
   }
   // combine T_0, T_1 into the two valley blocks of the output
   double2* Y = c.Y + z * c.sY;
@@ -746,28 +761,30 @@ void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t
   }
 }
 
-template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, bool FL>
 static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
   constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
   const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
   const int tx = (cols + BN - 1) / BN, ty = (rows + BM - 1) / BM;
   const long long T = (long long)tx * ty * nbatch;
   const int nblk = (int)((T + 7) / 8 * 8);
-  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB>), dim3(nblk), dim3(NT), 0, s,
-                     c, tx, ty, nbatch); cfqmc_post_launch("chan_apply_kernel");
+  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, FL>), dim3(nblk), dim3(NT), 0,
+                     s, c, tx, ty, nbatch); cfqmc_post_launch("chan_apply_kernel");
 }
 
-template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB>
+template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB, bool FL = true>
 static void run_chan_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
+  // FP64 has no accumulation points to drop: its variants without FL are the FL ones
+  constexpr bool F = sizeof(CT) == 8 ? true : FL;
   if (left) {
-    if (rot == ROT_X) run_chan<CT, true, ROT_X, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else if (rot == ROT_Y) run_chan<CT, true, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else if (c.one_minus) run_chan<CT, true, ROT_NONE, true, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else run_chan<CT, true, ROT_NONE, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    if (rot == ROT_X) run_chan<CT, true, ROT_X, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
+    else if (rot == ROT_Y) run_chan<CT, true, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
+    else if (c.one_minus) run_chan<CT, true, ROT_NONE, true, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
+    else run_chan<CT, true, ROT_NONE, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
   } else {
-    if (rot == ROT_X) run_chan<CT, false, ROT_X, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else if (rot == ROT_Y) run_chan<CT, false, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
-    else run_chan<CT, false, ROT_NONE, false, BM, BN, WTM, WTN, BKC, DB>(c, nbatch, s);
+    if (rot == ROT_X) run_chan<CT, false, ROT_X, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
+    else if (rot == ROT_Y) run_chan<CT, false, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
+    else run_chan<CT, false, ROT_NONE, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
   }
 }
 
@@ -781,7 +798,12 @@ static void chan_cfg(const ChanArgs& c, int left, int rot, int nbatch, int cfg, 
     case 4: run_chan_any<CT, 64, 32, 1, 1, 16, true>(c, left, rot, nbatch, s); break;
     case 5: run_chan_any<CT, 32, 64, 1, 1, 16, true>(c, left, rot, nbatch, s); break;
     case 6: run_chan_any<CT, 64, 64, 2, 2, 8, true>(c, left, rot, nbatch, s); break;
-    default: run_chan_any<CT, 16, 16, 1, 1, 8, true>(c, left, rot, nbatch, s); break;
+    case 7: run_chan_any<CT, 16, 16, 1, 1, 8, true>(c, left, rot, nbatch, s); break;
+    // FP32 accumulation over the whole k range (FP64 configurations: the same tiles)
+    case 8: run_chan_any<CT, 32, 32, 1, 1, 16, false, false>(c, left, rot, nbatch, s); break;
+    case 9: run_chan_any<CT, 64, 64, 2, 2, 16, true, false>(c, left, rot, nbatch, s); break;
+    case 10: run_chan_any<CT, 64, 32, 2, 1, 16, true, false>(c, left, rot, nbatch, s); break;
+    default: run_chan_any<CT, 32, 64, 1, 2, 16, true, false>(c, left, rot, nbatch, s); break;
   }
 }
 

@@ -44,11 +44,15 @@ struct ChanArgs {
   const double2* Cadd; int ldC; long long sC;   // optional addend
   double2* Y; int ldY; long long sY;
   double2* Y2;              // optional second copy of the output (same layout as Y)
+  const int* chain_sel;     // optional [chain]: only chains with chain_sel[z] == sel_want are computed
+  int sel_want;
 };
 
-// Tile configurations: zgemm 0..3; chan_apply 0..7 (a fixed tile_cfg applies to both).
+// Tile configurations: zgemm 0..3; chan_apply 0..11 (a fixed tile_cfg applies to both;
+// 8..11 accumulate the FP32 path in FP32 over the whole k range).
 #define CFQMC_GEMM_CFGS 4
-#define CFQMC_CHAN_CFGS 8
+#define CFQMC_CHAN_CFGS 12
+#define CFQMC_CHAN_CFGS_ACC64 8
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
 // rot: 0 none (channels 0, 3), 1 tau_x (channel 1), 2 tau_y (channel 2)
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);
@@ -79,9 +83,16 @@ void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ld
                      const double* d, long long sd, int n_rows, int n_cols, int inv, int nbatch, hipStream_t s);
 // running max |X - Y| (out[so z]) and max |X - Y| / max |Y| (out[so z + 1]) per batch
 // entry; out[so z + 2], out[so z + 3] are scratch that must start at zero. A
-// non-finite entry of X or Y makes both maxima +inf.
+// non-finite entry of X or Y makes both maxima +inf. last: optional [batch][2],
+// receives max |X - Y| and max |Y| of this call.
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
-                    hipStream_t s, int so = 4);
+                    hipStream_t s, int so = 4, double* last = nullptr);
+// Precision guard of the mixed path, after a recomputation: from last [batch][2]
+// (max |G_updated - G_FP64|, max |G_FP64| of the block just ended) set
+// sel[z] = 1 (FP64 applications for the next block) if max |G_FP64| > gmax or the
+// error > err, else 0; count[z] += sel[z]; gmax_run[z] = max(gmax_run[z], max |G_FP64|).
+void launch_precision_guard(const double* last, int* sel, int* count, double* gmax_run, double gmax, double err,
+                            int nbatch, hipStream_t s);
 
 // ---- UDT stabilisation helpers (linalg.hip)
 // Column norms of W (n x n) -> nrm; descending-order permutation perm.

@@ -1036,10 +1036,14 @@ __global__ void maxdiff_kernel(const double2* X, const double2* Y, int n, long l
     atomicMax((unsigned long long*)&out[so * z + 3], (unsigned long long)__double_as_longlong(my));
   }
 }
-__global__ void maxdiff_fold_kernel(double* out, int nbatch, int so) {
+__global__ void maxdiff_fold_kernel(double* out, int nbatch, int so, double* last) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= nbatch) return;
   const double d = out[so * z + 2], gm = out[so * z + 3];
+  if (last) {
+    last[2 * z] = d;
+    last[2 * z + 1] = gm;
+  }
   // +inf (a non-finite entry on either side) stays +inf in both maxima
   const double r = (isinf(d) || isinf(gm)) ? INFINITY : (gm > 0.0 ? d / gm : d);
   out[so * z + 0] = fmax(out[so * z + 0], d);
@@ -1048,11 +1052,29 @@ __global__ void maxdiff_fold_kernel(double* out, int nbatch, int so) {
   out[so * z + 3] = 0.0;
 }
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
-                    hipStream_t s, int so) {
+                    hipStream_t s, int so, double* last) {
   dim3 grid(min((n * n + 1023) / 1024, 64), nbatch);
   hipLaunchKernelGGL(maxdiff_kernel, grid, dim3(256), 0, s, X, Y, n, sX, out, so); cfqmc_post_launch("maxdiff_kernel");
-  hipLaunchKernelGGL(maxdiff_fold_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, out, nbatch, so);
+  hipLaunchKernelGGL(maxdiff_fold_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, out, nbatch, so, last);
   cfqmc_post_launch("maxdiff_fold_kernel");
+}
+
+__global__ void precision_guard_kernel(const double* last, int* sel, int* count, double* gmax_run, double gmax,
+                                       double err, int nbatch) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nbatch) return;
+  const double d = last[2 * z], gm = last[2 * z + 1];
+  // a non-finite state (inf) selects FP64 as well
+  const int f = (gm > gmax || d > err) ? 1 : 0;
+  sel[z] = f;
+  count[z] += f;
+  gmax_run[z] = fmax(gmax_run[z], gm);
+}
+void launch_precision_guard(const double* last, int* sel, int* count, double* gmax_run, double gmax, double err,
+                            int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(precision_guard_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, last, sel, count, gmax_run,
+                     gmax, err, nbatch);
+  cfqmc_post_launch("precision_guard_kernel");
 }
 
 // ------------------------------------------------------------------ UDT helpers

@@ -17,7 +17,7 @@
 #include "common.h"
 #include "kernels.h"
 
-typedef short bf4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 CF_DEV uint16_t f2bf(float x) {
   uint32_t u = __float_as_uint(x);
@@ -142,7 +142,7 @@ void launch_slmc_standardize(const float* feat, int F, int Fp, const float* mu, 
 // A(m, k) = A[m * lda + k] (AT = false) or A[k * lda + m] (AT = true);
 // B(k, n) = B[n * ldb + k] (BT = false) or B[k * ldb + n] (BT = true).
 // 64 x 64 tile per workgroup, four waves of 32 x 32, K slabs of 32 in LDS as
-// [row][k] so each lane reads its four consecutive k values in one load.
+// [row][k] so each lane reads its eight consecutive k values in one load.
 #define SG_BK 32
 #define SG_LD (SG_BK + 8)
 template <bool AT, bool BT>
@@ -177,21 +177,23 @@ __global__ void __launch_bounds__(256) slmc_gemm_kernel(int M, int N, int K, con
       Bs[r * SG_LD + k] = v;
     }
     __syncthreads();
+    // gfx950 BF16 MFMA 16x16x32: lane l supplies A[l % 16][8 (l / 16) + 0..7] and
+    // B[8 (l / 16) + 0..7][l % 16] (16-byte LDS reads: rows are 80 B apart)
 #pragma unroll
-    for (int kk = 0; kk < SG_BK; kk += 16) {
-      bf4v a[2], b[2];
+    for (int kk = 0; kk < SG_BK; kk += 32) {
+      bf8v a[2], b[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const uint16_t* pa = As + (wm + s * 16 + (lane & 15)) * SG_LD + kk + 4 * (lane >> 4);
-        const uint16_t* pb = Bs + (wn + s * 16 + (lane & 15)) * SG_LD + kk + 4 * (lane >> 4);
-        a[s] = *(const bf4v*)pa;
-        b[s] = *(const bf4v*)pb;
+        const uint16_t* pa = As + (wm + s * 16 + (lane & 15)) * SG_LD + kk + 8 * (lane >> 4);
+        const uint16_t* pb = Bs + (wn + s * 16 + (lane & 15)) * SG_LD + kk + 8 * (lane >> 4);
+        a[s] = *(const bf8v*)pa;
+        b[s] = *(const bf8v*)pb;
       }
 #pragma unroll
       for (int si = 0; si < 2; ++si)
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj)
-          acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[si], b[sj], acc[si][sj], 0, 0, 0);
+          acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[si], b[sj], acc[si][sj], 0, 0, 0);
     }
     __syncthreads();
   }

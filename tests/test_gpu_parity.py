@@ -141,7 +141,7 @@ def test_tile_configurations_agree():
     phi = synth.fields(3, L, m.n_q)
     rp = synth.replay(4, 1, L, m.n_q)
     out = []
-    for cfg in range(8):
+    for cfg in range(12):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg)
         g.init_fields(phi[None])
         g.sweep(1, rp[None])
@@ -150,6 +150,31 @@ def test_tile_configurations_agree():
     for G, acc in out[1:]:
         assert acc == out[0][1]
         assert rel(G, out[0][0]) < 1e-12
+
+
+def test_mixed_tile_configurations_within_the_bar():
+    """Every channel-application configuration of the FP32 path, with FP64
+    accumulation points (0..7) or FP32 accumulation over the whole k range
+    (8..11): identical accept/reject sequences and the updated G within 1e-6 of
+    its FP64 recomputation; G after the sweep within 1e-8 of the FP64 path."""
+    CFQMC = _gpu()
+    n_phi, L = 7, 12
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=1.0, un=1.0)
+    phi = synth.fields(3, L, m.n_q)
+    rp = synth.replay(4, 1, L, m.n_q)
+    ref = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=1)
+    ref.init_fields(phi[None])
+    ref.sweep(1, rp[None])
+    G0, acc0 = ref.measure_G(0, L), ref.last_sweep(0)[0].tolist()
+    ref.close()
+    for cfg in range(12):
+        g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg, precision=1)
+        g.init_fields(phi[None])
+        st = g.sweep(1, rp[None])
+        assert g.last_sweep(0)[0].tolist() == acc0, cfg
+        assert st[0]["max_stab_err"] < 1e-6, (cfg, st[0]["max_stab_err"])
+        assert rel(g.measure_G(0, L), G0) < 1e-8, cfg
+        g.close()
 
 
 def test_exponential_scaling_and_squaring_path():
@@ -392,3 +417,35 @@ def test_degenerate_shapes_replay(n_phi, L, nstab):
     accept/reject sequences, G and ln w within 1e-10."""
     CFQMC = _gpu()
     _replay_compare(CFQMC, n_phi, L, nstab, Q_BZ, None, [1.0, 1.3], 0, 3, 1e-10)
+
+
+def test_precision_guard_selects_fp64_chains():
+    """The mixed path's precision guard: with a max|G| threshold below every
+    chain's max|G_FP64| each chain's FP32 applications run in FP64 after the
+    first recomputation (guard fraction 1, and the blocks after the first
+    recompute to FP64 rounding); with the guard off the fraction is 0. Both
+    replay the oracle's accept/reject sequence, and max|G_FP64| >= 1/2 (the
+    diagonal of G at half filling)."""
+    CFQMC = _gpu()
+    n_phi, L, nstab = 6, 40, 10
+    m = Model(n_phi, L, 0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_BZ)
+    phi = np.stack([synth.fields(300 + k, L, m.n_q) for k in range(2)])
+    rp = np.stack([synth.replay(310 + k, 2, L, m.n_q) for k in range(2)])
+    ch = [dqmc.Chain(m, phi[k], eps0=0.4, adapt=True) for k in range(2)]
+    for k in range(2):
+        ch[k].run(rp[k])
+    for guard, gmax, want in ((1, 1e-9, 1.0), (0, 1.0, 0.0)):
+        g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=Q_BZ, n_stab=nstab, eps0=0.4, adapt_eps=True, precision=1,
+                  n_chains=2, chain_u=[(1.0, 1.0, 1.0)] * 2, tile_cfg=1, precision_guard=guard, guard_gmax=gmax)
+        g.init_fields(phi)
+        g.sweep(1, rp[:, 0:1])
+        st = g.sweep(1, rp[:, 1:2])       # the guard's choice carries over from the first sweep
+        for k in range(2):
+            assert g.last_sweep(k)[0].tolist() == [int(h[2]) for h in ch[k].history[-L:]]
+            assert abs(st[k]["fp64_guard_frac"] - want) < 1e-12, (guard, st[k]["fp64_guard_frac"])
+            assert st[k]["max_abs_g"] >= 0.5 - 1e-12
+            if guard:
+                assert st[k]["max_stab_err"] < 1e-12     # every block of the second sweep in FP64
+            else:
+                assert 1e-12 < st[k]["max_stab_err"] < 1e-6
+        g.close()

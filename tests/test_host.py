@@ -46,7 +46,7 @@ def test_param_struct_layout_and_validation(lib):
     assert p.exp_squarings == 2 and p.tile_cfg == -1 and p.n_chains == 1
     h = ctypes.c_void_p()
     for field, bad in [("n_phi", 0), ("n_phi", 141), ("l_tau", 0), ("dtau", -1.0), ("eps0", 0.0),
-                       ("n_chains", 0), ("precision", 7), ("tile_cfg", 9), ("n_stab", 0)]:
+                       ("n_chains", 0), ("precision", 7), ("tile_cfg", 12), ("n_stab", 0)]:
         q = cfqmc.Params()
         L.cfqmc_default_params(ctypes.byref(q))
         setattr(q, field, bad)
@@ -223,3 +223,41 @@ def test_product_path_fails_loudly_without_the_library(monkeypatch, tmp_path):
         cfqmc.load()
     with pytest.raises(RuntimeError, match="not found"):
         cfqmc.CFQMC(n_phi=4, l_tau=8)
+
+
+def _fss_data(u_c, d_s, d_v, noise, seed):
+    """Synthetic correlation ratios and order parameters obeying the scaling forms
+    exactly (cubic scaling function), at the paper's torus sizes and u range."""
+    sizes = [16, 20, 24, 28, 32, 40, 48, 56, 64, 72, 96, 112, 128, 140]
+    us = np.linspace(0.17, 0.23, 9)
+    U, N = np.meshgrid(us, sizes, indexing="ij")
+    U, N = U.ravel(), N.ravel().astype(float)
+    x = (U / u_c - 1.0) * np.sqrt(N) ** (3.0 - d_s)
+    rng = np.random.default_rng(seed)
+    R = 0.5 - 0.8 * x + 0.3 * x ** 2 + 0.4 * x ** 3 + noise * rng.standard_normal(x.size)
+    m2 = (0.9 - 0.5 * x + 0.2 * x ** 2 - 0.1 * x ** 3) * N ** (-d_v) * (1 + noise * rng.standard_normal(x.size))
+    return U, N, R, m2
+
+
+def test_fss_grid_scan_recovers_known_critical_point():
+    """Results eqs. finite-size-scaling-R/-m: on data generated with (u_c, Delta_s)
+    = (0.195, 2.65) and a cubic scaling function the R^2-optimised scan over a
+    grid containing the truth returns it with R^2 = 1 (exact data), also for the
+    order parameter at fixed Delta_v; with 1% noise it stays within one grid step;
+    a wrong Delta_s or u_c lowers R^2."""
+    from paper_2605_03700_amd.analysis import data_collapse, fss_collapse_r2, fss_grid_scan
+    ucg = np.round(np.arange(0.175, 0.2151, 0.005), 4)
+    dsg = np.round(np.arange(2.3, 3.001, 0.05), 4)
+    U, N, R, m2 = _fss_data(0.195, 2.65, 0.51, 0.0, 1)
+    r2map, (uc, ds, r2) = fss_grid_scan(U, N, R, ucg, dsg)
+    assert r2map.shape == (ucg.size, dsg.size)
+    assert abs(uc - 0.195) < 1e-9 and abs(ds - 2.65) < 1e-9 and r2 > 1 - 1e-12
+    _, (uc, ds, r2) = fss_grid_scan(U, N, m2, ucg, dsg, delta_v=0.51)
+    assert abs(uc - 0.195) < 1e-9 and abs(ds - 2.65) < 1e-9 and r2 > 1 - 1e-12
+    assert fss_collapse_r2(U, N, R, 0.195, 2.3)[0] < r2 - 1e-3
+    assert fss_collapse_r2(U, N, R, 0.21, 2.65)[0] < r2 - 1e-3
+    U, N, R, m2 = _fss_data(0.195, 2.65, 0.51, 0.01, 2)
+    _, (uc, ds, _) = fss_grid_scan(U, N, R, ucg, dsg)
+    assert abs(uc - 0.195) <= 0.005 + 1e-9 and abs(ds - 2.65) <= 0.1 + 1e-9
+    x, Y, F, r2c = data_collapse(U, N, R, uc, ds)
+    assert x.shape == Y.shape == F.shape and r2c > 0.99
