@@ -3,14 +3,17 @@
 Workload (default): 256 independent chains of the torus N_phi = 100 model
 (spin block n = 200, 4N = 400), paper momentum cutoff (933 HS components per
 channel), L = 400 slices of dtau = 0.1, u = 1.5 on the SO(5) line, FP64
-recomputation every 8 slices, complex FP32 MFMA wraps with FP64 accumulation
-(--precision fp64 for the all-FP64 path). A step is one sweep of every chain:
-L Langevin slice moves of 4 n_q fields each, with wraps, Woodbury updates and
-stabilisation. After the timed sweeps: tau_int (the largest of m^2_SO(5), the
-action and the q = 0 field power, autocorrelations pooled over the chains)
-over untimed sweeps, (with --fp64-compare) the same chains with every product in FP64, a
-one-chain FP64 reference sweep, and the FP64 oracle on the host.
---workload batched and --workload learned run the other two workloads.
+recomputation every 8 slices, complex FP32 MFMA wraps and drift frames with the
+precision guard (chains with large |G| or error run them in FP64; --precision
+fp64 for the all-FP64 path). A step is one sweep of every chain: L Langevin
+slice moves of 4 n_q fields each, with wraps, Woodbury updates and
+stabilisation. After the timed sweeps: the same chains with every product in
+FP64 (timed), then untimed sweeps of re-created mixed chains for a short
+tau_int and for the learned proposal's training set (trained, then tried),
+one imaginary-time correlator pass, a one-chain FP64 reference sweep, and the
+FP64 oracle on the host. The independent-sample rate uses the tau_int of a
+long run of the same shape (--workload tau-long). --workload batched, learned,
+tau, tau-long and oracle-tau run the other workloads.
 
 Prints one JSON line (see the fields below). Synthetic fields N(0,1).
 """
@@ -31,6 +34,15 @@ PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFM
 # (N_phi, chains per context, precision, tile configuration). Absent key, or a
 # kernel changed since the counters were taken: traffic not measured (null).
 TRAFFIC = {(100, 256, "mixed", 1): (166617.07 * 2.0 + 160000.0 * 1.0) * 1024}
+
+# Integrated autocorrelation times at the default workload's shape (N_phi = 100,
+# L = 400, dtau = 0.1, u = 1.5, paper cutoff) from one long run, 32 chains x
+# 1000 sweeps after 8 (bench.py --workload tau-long, profiles/
+# tau_int_n100_32chains_1000sweeps.md); every window closed. tau_int is a
+# property of the Markov chain, not of the kernels' speed, so the default line
+# divides its own sweep rate by 2 x the slowest of these.
+TAU_LONG = {"shape": (100, 400, 0.1, 1.5), "chains": 32, "sweeps": 1000,
+            "tau_int": {"m2": 1.18, "action": 14.33, "phi_q0_power": 69.06}}
 
 
 def cpu_baseline(n_phi, l_tau, dtau, u, seconds=15.0, sphere=False):
@@ -138,7 +150,10 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_all"], default="mixed")
     ap.add_argument("--series-out", default=None,
                     help="tau-long: write the per-sweep series (npz) here every 100 sweeps and at the end")
-    ap.add_argument("--workload", choices=["c3", "batched", "learned", "tau", "tau-long"], default="c3",
+    ap.add_argument("--q-mode", choices=["paper", "bz"], default="paper",
+                    help="tau-long and oracle-tau: momentum set (paper cutoff, or the N^2 Brillouin-zone momenta)")
+    ap.add_argument("--workload", choices=["c3", "batched", "learned", "tau", "tau-long", "oracle-tau"],
+                    default="c3",
                     help="c3: N_phi=100 torus; batched: 64 chains over N_phi 24/48/72 and a 16-point u grid; "
                          "learned: N_phi=140, L=600 with the learned global proposal; tau: imaginary-time "
                          "correlator passes over the c3 chains (no sweeps)")
@@ -164,7 +179,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--guard-gmax", type=float, default=1.0,
                     help="precision guard: FP64 applications for chains with max|G_FP64| above this")
-    ap.add_argument("--guard-err", type=float, default=5e-7,
+    ap.add_argument("--guard-err", type=float, default=2.5e-7,
                     help="precision guard: FP64 applications for chains whose last block error exceeded this")
     ap.add_argument("--no-guard", action="store_true", help="FP32 applications for every chain (mixed modes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -186,6 +201,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.numel() * 8, "copies": 3}))
         return
+    if args.workload == "oracle-tau":
+        return bench_oracle_tau(args)
     import numpy as np
     import torch
     from paper_2605_03700_amd import Batch, FP64, MIXED, MIXED_ALL, Q_PAPER, Q_SPHERE
@@ -200,6 +217,8 @@ def main():
         return bench_tau(args, prec)
     if args.workload == "tau-long":
         return bench_tau_long(args, prec)
+    if args.workload == "oracle-tau":
+        return bench_oracle_tau(args)
     if args.chains % args.groups:
         raise SystemExit("--chains must be a multiple of --groups")
     nper = args.chains // args.groups
@@ -254,6 +273,7 @@ def main():
         "g_err_rel_per_sweep": [e[1] for e in g_err],
         "g_err_median_chain": float(np.median([max(st[z]["max_stab_err"] for st in stats)
                                                for z in range(len(stats[0]))])),
+        "g_err_frac_chain_sweeps_above_1e-6": float(np.mean([x["max_stab_err"] > 1e-6 for x in flat])),
         "thermalization_sweeps": args.therm,
         "g_err_per_thermalization_sweep": [e[0] for e in g_err_therm],
         "g_err_rel_per_thermalization_sweep": [e[1] for e in g_err_therm],
@@ -264,8 +284,9 @@ def main():
         "max_abs_g_max": max(x["max_abs_g"] for x in flat),
         "fp64_guard_frac": float(np.mean([x["fp64_guard_frac"] for x in flat])),
         "fp64_guard_definition": "fraction of (chain, stabilisation block) pairs whose FP32 applications the "
-                                 "precision guard ran in FP64 (max|G_FP64| > %g or block error > %g at the "
-                                 "previous recomputation)" % (args.guard_gmax, args.guard_err),
+                                 "precision guard ran in FP64 from some slice on (an entry of the updated G above "
+                                 "%g, or at the previous recomputation max|G_FP64| > %g or a block error > %g)"
+                                 % (args.guard_gmax, args.guard_gmax, args.guard_err),
     }
     if args.therm > 0:
         out["acceptance_min_chain_thermalization"], out["frozen_chains_thermalization"] = \
@@ -310,6 +331,40 @@ def main():
             "achieved": w_ach, "peak": w_peak, "unit": "TFLOP/s", "frac": w_ach / w_peak,
             "avg_launch_ms": w_ms, "launches_timed": w_count, "flops_per_launch": algo_per_launch,
             "issued_flops_per_launch": w_flops, "issued_tflops": w_iss, "issued_frac": w_iss / w_peak}
+    if prec != FP64 and not args.no_fp64_compare:
+        # the same chains with every product in FP64, right after the timed mixed
+        # sweeps (one context of this size at a time fits in HBM): the FP64
+        # context starts from the mixed chains' fields and step sizes, runs one
+        # warm-up sweep and the same number of timed sweeps; the mixed chains are
+        # then re-created from that same state
+        state = [(q.get_fields(), q.get_eps()) for q in b.groups]
+        b.close()
+
+        def restart(batch):
+            for q, (phi, eps) in zip(batch.groups, state):
+                q.init_fields(phi)
+                q.set_eps(eps)
+        f = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+                        n_stab=args.n_stab, precision=FP64, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
+                        tile_cfg=args.tile_cfg, **geo) for k in range(args.groups)])
+        restart(f)
+        f.sweep(1)
+        dtf, _, gef = sweep_each(f, args.steps)
+        f_rate = args.chains * args.l_tau * 4 * g.n_q * args.steps / dtf
+        out["fp64_same_chains"] = {"precision": "fp64", "chains": args.chains, "field_updates_per_s": f_rate,
+                                   "ms_per_sweep": 1000.0 * dtf / args.steps, "g_err_max": max(e[0] for e in gef),
+                                   "mixed_over_fp64": value / f_rate,
+                                   "start": "the mixed chains' fields and step sizes after the timed sweeps, "
+                                            "one warm-up sweep, %d timed sweeps" % args.steps}
+        f.close()
+        progress("FP64 comparison on the same chains done")
+        b = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
+                        n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
+                        tile_cfg=args.tile_cfg, **geo, **guard) for k in range(args.groups)])
+        g = b.groups[0]
+        restart(b)
+        del state
+        progress("mixed chains re-created from the same state")
     tau = None
     slmc = None
     if args.tau_sweeps > 0:
@@ -348,6 +403,15 @@ def main():
             out["indep_samples_per_s_upper_bound"] = rate
         else:
             out["indep_samples_per_s"] = rate
+        if TAU_LONG["shape"] == (args.n_phi, args.l_tau, args.dtau, args.u) and args.geometry == "torus":
+            # the long run's closed-window tau_int with this run's sweep rate
+            t_long = max(TAU_LONG["tau_int"].values())
+            out["tau_int_long_run"] = dict(TAU_LONG, source="bench.py --workload tau-long (profiles/"
+                                           "tau_int_n100_32chains_1000sweeps.md)")
+            out["indep_samples_per_s"] = args.chains * sweeps_per_s / (2 * t_long)
+            out["indep_samples_per_s_definition"] = ("chains x sweeps/s per chain of the timed sweeps / (2 x the "
+                                                     "long run's tau_int of the q = 0 field power, %.1f sweeps)"
+                                                     % t_long)
         out["acceptance_min_chain_later_sweeps"], out["frozen_chains_later_sweeps"] = chain_acceptance(stats2)
         progress("tau_int sweeps done")
         if slmc is not None:
@@ -378,19 +442,6 @@ def main():
                           "one pass = L slices x 12 FP64 channel applications + a recomputation per block"}
         progress("imaginary-time correlator pass done")
     b.close()
-    if prec != FP64 and not args.no_fp64_compare:
-        # the same chains with every product in FP64 (warm-up sweep, then two timed sweeps)
-        f = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
-                        n_stab=args.n_stab, precision=FP64, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
-                        tile_cfg=args.tile_cfg, **geo) for k in range(args.groups)])
-        f.init_fields()
-        f.sweep(1)
-        dtf, _, gef = sweep_each(f, 2)
-        out["fp64_same_chains"] = {"precision": "fp64", "chains": args.chains,
-                                   "field_updates_per_s": args.chains * args.l_tau * 4 * g.n_q * 2 / dtf,
-                                   "ms_per_sweep": 1000.0 * dtf / 2, "g_err_max": max(e[0] for e in gef)}
-        f.close()
-        progress("FP64 comparison on the same chains done")
     if not args.no_plain:
         # the plain path for comparison: one chain, FP64, same workload
         p = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
@@ -401,7 +452,10 @@ def main():
         dtp, stp, gep = sweep_each(p, 2)
         plain = {"chains": 1, "precision": "fp64", "field_updates_per_s": args.l_tau * 4 * g.n_q * 2 / dtp,
                  "ms_per_sweep": 1000.0 * dtp / 2, "g_err_max": max(e[0] for e in gep)}
-        if tau:
+        if "tau_int_long_run" in out:
+            plain["indep_samples_per_s"] = (2 / dtp) / (2 * max(TAU_LONG["tau_int"].values()))
+            out["indep_samples_ratio_vs_plain_fp64"] = out["indep_samples_per_s"] / plain["indep_samples_per_s"]
+        elif tau:
             key = "indep_samples_per_s_upper_bound" if out.get("tau_int_is_lower_bound") else "indep_samples_per_s"
             plain[key] = (2 / dtp) / (2 * tau)
         out["plain_fp64_1chain"] = plain
@@ -461,14 +515,15 @@ def bench_tau_long(args, prec):
     the chains, with Sokal's window; a window that does not close is reported."""
     import numpy as np
     import torch
-    from paper_2605_03700_amd import Batch, Q_PAPER
+    from paper_2605_03700_amd import Batch, Q_BZ, Q_PAPER
     from paper_2605_03700_amd.analysis import tau_int_pooled
     chains = args.chains if args.chains != 256 else 32
     n_sw = args.tau_sweeps if args.tau_sweeps != 40 else 1000
     b = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
                     n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3, n_chains=chains,
-                    tile_cfg=args.tile_cfg, q_mode=Q_PAPER, precision_guard=0 if args.no_guard else 1,
-                    guard_gmax=args.guard_gmax, guard_err=args.guard_err)])
+                    tile_cfg=args.tile_cfg, q_mode=Q_BZ if args.q_mode == "bz" else Q_PAPER,
+                    precision_guard=0 if args.no_guard else 1, guard_gmax=args.guard_gmax,
+                    guard_err=args.guard_err)])
     g = b.groups[0]
     b.init_fields()
     if args.therm:
@@ -507,13 +562,65 @@ def bench_tau_long(args, prec):
         "n_gpus": 1, "steps": n_sw, "warmup": args.therm, "ms_per_step": 1000.0 * dt / n_sw,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64", "data": "synthetic",
-        "config": {"workload": "tau-long: torus N_phi=%d L_tau=%d dtau=%g u=%g paper cutoff, %d chains, %d sweeps "
-                               "after %d" % (args.n_phi, args.l_tau, args.dtau, args.u, chains, n_sw, args.therm)},
+        "config": {"workload": "tau-long: torus N_phi=%d L_tau=%d dtau=%g u=%g %s, %d chains, %d sweeps "
+                               "after %d" % (args.n_phi, args.l_tau, args.dtau, args.u,
+                                             "Brillouin zone" if args.q_mode == "bz" else "paper cutoff",
+                                             chains, n_sw, args.therm)},
         "tau_int": taus, "acceptance": acc / max(1, prop), "g_err_max": g_abs,
+        "m2_mean": float(ser["m2"].mean()),
+        "m2_stderr": float(ser["m2"].std() * np.sqrt(2 * taus["m2"]["tau_int"] / ser["m2"].size)),
         "sweeps_per_s_per_chain": n_sw / dt,
         "indep_samples_per_s": chains * n_sw / dt / (2 * tau) if all(v["window_closed"] for v in taus.values())
         else None}))
     b.close()
+
+
+def bench_oracle_tau(args):
+    """The FP64 oracle's own Markov chain on the host (the CPU baseline's
+    autocorrelation): one chain of the given shape, --therm sweeps with the step
+    size adapting, then --tau-sweeps sweeps at the frozen step; tau_int of
+    m^2_SO(5), the action and the q = 0 field power with Sokal's window, and
+    the mean of m^2_SO(5) with its autocorrelation-corrected error."""
+    import numpy as np
+    import synth
+    from oracle import dqmc
+    from oracle.model import Model, Q_BZ, Q_PAPER
+    from oracle.observables import so5_observables
+    from paper_2605_03700_amd.analysis import tau_int
+    n_sw = args.tau_sweeps if args.tau_sweeps != 40 else 2000
+    m = Model(args.n_phi, args.l_tau, args.dtau, u0=1.0, uk=args.u, un=args.u,
+              q_mode=Q_BZ if args.q_mode == "bz" else Q_PAPER)
+    ch = dqmc.Chain(m, synth.fields(1, args.l_tau, m.n_q), eps0=0.3, adapt=True)
+    rp = synth.replay(2, args.therm + n_sw, args.l_tau, m.n_q)
+    for i in range(args.therm):
+        ch.sweep(rp[i])
+    ch.adapt = False
+    ser = {"m2": [], "action": [], "phi_q0_power": []}
+    t0 = time.perf_counter()
+    for i in range(n_sw):
+        ch.sweep(rp[args.therm + i])
+        Bs = dqmc.propagators(m, ch.phi)
+        G = dqmc.green(m, ch.phi, args.l_tau, Bs)
+        ser["m2"].append(float(np.real(so5_observables(G, args.n_phi)[1])))
+        ser["action"].append(0.5 * float(np.sum(ch.phi ** 2)) - float(np.real(dqmc.logdet(m, ch.phi, Bs))))
+        ser["phi_q0_power"].append(float(np.sum(ch.phi[:, :, 0].sum(axis=0) ** 2)) / args.l_tau)
+        if (i + 1) % 100 == 0:
+            progress("oracle-tau: %d of %d sweeps (%.1f s)" % (i + 1, n_sw, time.perf_counter() - t0))
+    dt = time.perf_counter() - t0
+    taus = {}
+    for k, v in ser.items():
+        t, w = tau_int(v)
+        taus[k] = {"tau_int": float(t), "window": int(w)}
+    m2 = np.array(ser["m2"])
+    print(json.dumps({
+        "metric": "oracle integrated autocorrelation time (sweeps)", "value": max(v["tau_int"] for v in taus.values()),
+        "unit": "sweeps", "n_gpus": 0, "steps": n_sw, "warmup": args.therm, "ms_per_step": 1000.0 * dt / n_sw,
+        "higher_is_better": False, "data": "synthetic", "dtype": "f64",
+        "config": {"workload": "oracle-tau: torus N_phi=%d L_tau=%d dtau=%g u=%g %s, one chain on the host"
+                               % (args.n_phi, args.l_tau, args.dtau, args.u, args.q_mode)},
+        "tau_int": taus, "eps": ch.eps, "acceptance": float(np.mean([h[2] for h in ch.history[-n_sw * args.l_tau:]])),
+        "m2_mean": float(m2.mean()), "m2_stderr": float(m2.std() * np.sqrt(2 * taus["m2"]["tau_int"] / m2.size)),
+        "sweeps_per_s": n_sw / dt}))
 
 
 def bench_tau(args, prec):

@@ -94,10 +94,12 @@ typedef struct {
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential, 0..16 (default 2) */
-  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..11 fixed channel-application
+  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..14 fixed channel-application
                             configuration (GEMMs use min(tile_cfg, 3)). In the FP32 applications
-                            0..7 add each 16-deep k slab into FP64 registers, 8..11 accumulate in
-                            FP32 over the whole k range (the autotuner picks among 0..7 there) */
+                            0..7 and 14 add each 16-deep k slab into FP64 registers (14 with three
+                            real products per complex step), 8..13 accumulate in FP32 over the whole
+                            k range (12, 13 with three products); the autotuner picks among the
+                            former there unless the precision guard is on */
   int32_t dense4n;       /* 0 (only value): the spin-block form n = 2 N_phi. The Fierz channels act as
                             the identity on spin (eq. newmodel), so G_4N = 1_spin (x) G_2N exactly and
                             every output is expanded to 4N; 1 (the un-Fierzed dense 4N coupling, which
@@ -110,10 +112,11 @@ typedef struct {
   int32_t precision_guard; /* mixed modes: 1 (default) runs the FP32 applications of a chain in FP64 for
                             the next block of n_stab slices when, at the last FP64 recomputation, its
                             max|G_FP64| exceeded guard_gmax or its max|G_updated - G_FP64| exceeded
-                            guard_err (the FP32 rounding error of G scales with |G|); 0: FP32 for every
-                            chain. Ignored in CFQMC_FP64 */
+                            guard_err, and from the next slice to the end of the block once its
+                            updated G has an entry above guard_gmax (the FP32 rounding error of G
+                            scales with |G|); 0: FP32 for every chain. Ignored in CFQMC_FP64 */
   double guard_gmax;     /* default 1.0 */
-  double guard_err;      /* default 5e-7 */
+  double guard_err;      /* default 2.5e-7 */
 } cfqmc_params;
 
 typedef struct {
@@ -126,13 +129,13 @@ typedef struct {
   double max_stab_rel;        /* max over recomputation points of max|G_updated - G_FP64| / max|G_FP64| */
   double max_abs_g;           /* max over recomputation points of max|G_FP64| */
   double fp64_guard_frac;     /* fraction of the chain's stabilisation blocks run with FP64 applications
-                                 by the precision guard (mixed modes) */
+                                 (from some slice on) by the precision guard (mixed modes) */
 } cfqmc_stats;
 
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
  * n_stab=10, FP64, eps0=0.5, r0=0.574, deps=0.1, eps in [1e-3, 5], adapt on,
  * one chain, exp_squarings=2, tile_cfg=-1, dense4n=0, exact_drift=0,
- * precision_guard=1, guard_gmax=1, guard_err=5e-7). */
+ * precision_guard=1, guard_gmax=1, guard_err=2.5e-7). */
 void cfqmc_default_params(cfqmc_params* p);
 
 /* Create a context: builds the model tables on the host, allocates device
@@ -419,6 +422,8 @@ int cfqmc_slmc_last_proposal(cfqmc_slmc* s, int32_t chain, double* phi_out);
 int cfqmc_green_maxdiff(const void* x_dev, const void* y_dev, int32_t n, int32_t count, void* hip_stream,
                         double* out);
 
+/* Message of the last error of a context; with c == NULL, the message of the
+ * last cfqmc_create that failed on the calling thread. */
 const char* cfqmc_last_error(const cfqmc_ctx* c);
 
 #ifdef __cplusplus

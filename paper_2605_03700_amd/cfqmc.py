@@ -79,6 +79,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libcfqmc.so not found at %s; run __graft_entry__.build()" % LIB_PATH)
+    try:
+        # the library must bind to the HIP runtime PyTorch uses (its wheel ships
+        # its own): load torch's first, so there is one runtime in the process
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     lib.cfqmc_default_params.argtypes = [ctypes.POINTER(Params)]
@@ -158,7 +164,7 @@ def _ptr(a):
 def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                 q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                 eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1,
-                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=5e-7):
+                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7):
     """Fill a Params structure; returns (params, keep-alive arrays)."""
     lib = load()
     p = Params()
@@ -191,7 +197,7 @@ class CFQMC:
     def __init__(self, n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                  q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                  eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
-                 tile_cfg=-1, dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=5e-7,
+                 tile_cfg=-1, dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7,
                  stream=None, _handle=None):
         lib = load()
         self.lib = lib
@@ -240,9 +246,10 @@ class CFQMC:
 
     def _check(self, rc, h="self"):
         if rc != 0:
-            msg = ""
             if h is not None and getattr(self, "h", None) is not None:
                 msg = self.lib.cfqmc_last_error(self.h).decode()
+            else:                   # a failed create: the thread's last create message
+                msg = self.lib.cfqmc_last_error(None).decode()
             raise RuntimeError("cfqmc error %s: %s" % (ERRORS.get(rc, rc), msg))
 
     def init_fields(self, phi=None):

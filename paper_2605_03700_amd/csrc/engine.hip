@@ -375,12 +375,20 @@ namespace {
     }                                                                    \
   } while (0)
 
+// Message of the last cfqmc_create that failed on this thread (no context to hold it).
+thread_local std::string g_create_err;
+
 template <typename T>
 int dalloc(cfqmc_ctx* c, T** p, size_t count) {
   void* q = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
-    c->err = "device allocation failed";
+  const hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    size_t fr = 0, tot = 0;
+    (void)hipMemGetInfo(&fr, &tot);
+    c->err = "device allocation of " + std::to_string(count * sizeof(T)) + " B failed (" + hipGetErrorString(e) +
+             "; " + std::to_string(fr >> 20) + " MiB of " + std::to_string(tot >> 20) + " MiB free)";
     return CFQMC_ENOMEM;
   }
   hipMemsetAsync(q, 0, count * sizeof(T), c->s);
@@ -839,6 +847,8 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   launch_commit(a, c->nch, c->Fp[0], c->F[0], c->G, nn, nn, c->phip, 4 * c->nq,
                 c->phi + (long long)t * 4 * c->nq, (long long)c->L * 4 * c->nq, 4 * c->nq, c->PQp, sPQp,
                 c->PQ + (long long)t * 8 * NN, sPQ, 8 * NN, c->acc_count, c->s);
+  // precision guard: a chain whose G grew past the threshold finishes the block in FP64
+  if (c->guard) launch_guard_slice(c->G, nn, (int)nn, c->sel64, c->p.guard_gmax, c->nch, c->s);
   // history of this slice
   hipMemcpy2DAsync(c->hist_acc + t, c->L * sizeof(int), c->accept, sizeof(int), sizeof(int), c->nch,
                    hipMemcpyDeviceToDevice, c->s);
@@ -945,9 +955,11 @@ int autotune(cfqmc_ctx* c) {
     return ms;
   };
   // the FP32 applications keep their FP64 accumulation points (configurations
-  // 0..7) unless a configuration is fixed by the caller
-  const int ncfg_app = c->mixed ? CFQMC_CHAN_CFGS_ACC64 : CFQMC_CHAN_CFGS;
-  for (int cfg = 0; cfg < ncfg_app; ++cfg) {
+  // 0..7) unless the precision guard watches every chain's error (then the
+  // FP32-accumulating configurations compete as well) or a configuration is
+  // fixed by the caller
+  for (int cfg = 0; cfg < CFQMC_CHAN_CFGS; ++cfg) {
+    if (c->mixed && !c->guard && !chan_cfg_acc64(cfg)) continue;
     c->cfg_chan = cfg;
     const float tc = timeit([&]() {
       chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
@@ -1016,7 +1028,7 @@ void cfqmc_default_params(cfqmc_params* p) {
   p->adapt_eps = 1; p->seed = 1; p->n_chains = 1;
   p->exp_squarings = 2; p->tile_cfg = -1;
   p->dense4n = 0; p->exact_drift = 0;
-  p->precision_guard = 1; p->guard_gmax = 1.0; p->guard_err = 5e-7;
+  p->precision_guard = 1; p->guard_gmax = 1.0; p->guard_err = 2.5e-7;
 }
 
 int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
@@ -1052,7 +1064,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   c->timing = false;
   c->ev_used = 0;
   c->sweep_counter = 0;
-  if (!build_components(p, c->ht, c->err)) { delete c; return CFQMC_EINVAL; }
+  if (!build_components(p, c->ht, c->err)) { g_create_err = c->err; delete c; return CFQMC_EINVAL; }
   c->nq = (int)c->ht.comp_kind.size();
   // band of h: the largest circular shift that carries a term
   c->hband = 0;
@@ -1133,9 +1145,13 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->guard_cnt, (size_t)B);
   rc |= dalloc(c, &c->gmax_run, (size_t)B);
   rc |= dalloc(c, &c->blk_last, (size_t)B * 2);
-  if (rc) { cfqmc_destroy(c); return CFQMC_ENOMEM; }
-  if (build_model_dev(c)) { cfqmc_destroy(c); return CFQMC_ENOMEM; }
-  if (c->md.nrow * 4 > 4 * 1024) { c->err = "too many momentum rows"; cfqmc_destroy(c); return CFQMC_EINVAL; }
+  if (rc) { g_create_err = c->err; cfqmc_destroy(c); return CFQMC_ENOMEM; }
+  if (build_model_dev(c)) {
+    g_create_err = "model tables: " + c->err;
+    cfqmc_destroy(c);
+    return CFQMC_ENOMEM;
+  }
+  if (c->md.nrow * 4 > 4 * 1024) { g_create_err = "too many momentum rows"; cfqmc_destroy(c); return CFQMC_EINVAL; }
   // couplings per chain: g = (U0+UN, -(UK+UN), -(UK+UN), 2 UN), alpha = sqrt(-dtau g)
   std::vector<double2> al(B * 4);
   for (int z = 0; z < B; ++z) {
@@ -2579,6 +2595,6 @@ int cfqmc_green_maxdiff(const void* x_dev, const void* y_dev, int32_t n, int32_t
   return rc;
 }
 
-const char* cfqmc_last_error(const cfqmc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* cfqmc_last_error(const cfqmc_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 }  // extern "C"

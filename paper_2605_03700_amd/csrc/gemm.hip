@@ -134,6 +134,66 @@ CF_DEV void mma_slab3(const double2* As, int lda, const double2* Bs, int ldb, in
   }
 }
 
+// The same three-product form with FP32 operands and accumulators (the FP32
+// channel application without accumulation points: P, Q, S stay FP32 over the
+// whole k range and are combined in FP64 in the epilogue).
+template <int WTM, int WTN>
+struct Acc3F {
+  f4v p[WTM][WTN], q[WTM][WTN], t[WTM][WTN];
+  CF_DEV void zero() {
+#pragma unroll
+    for (int a = 0; a < WTM; ++a)
+#pragma unroll
+      for (int b = 0; b < WTN; ++b) { p[a][b] = Mfma<float>::zero(); q[a][b] = p[a][b]; t[a][b] = p[a][b]; }
+  }
+  CF_DEV void to(Acc<double, WTM, WTN>& o) const {
+#pragma unroll
+    for (int a = 0; a < WTM; ++a)
+#pragma unroll
+      for (int b = 0; b < WTN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double P = p[a][b][r], Q = q[a][b][r], T = t[a][b][r];
+          o.re[a][b][r] = P - Q;
+          o.im[a][b][r] = T - P - Q;
+        }
+  }
+};
+
+template <int WTM, int WTN, int KD = BK>
+CF_DEV void mma_slab3f(const float2* As, int lda, const float2* Bs, int ldb, int wm0, int wn0, int lane,
+                       Acc3F<WTM, WTN>& acc, int mrem = 1 << 30, int nrem = 1 << 30, int krem = 1 << 30) {
+  const int il = lane & 15, kl = lane >> 4;
+  mrem = __builtin_amdgcn_readfirstlane(mrem);
+  nrem = __builtin_amdgcn_readfirstlane(nrem);
+  krem = __builtin_amdgcn_readfirstlane(krem);
+#pragma unroll
+  for (int kk = 0; kk < KD; kk += 4) {
+    if (kk >= krem) break;
+    float2 a[WTM], b[WTN];
+    float sa[WTM], sb[WTN];
+#pragma unroll
+    for (int s = 0; s < WTM; ++s) {
+      a[s] = As[(kk + kl) * lda + wm0 + s * 16 + il];
+      sa[s] = a[s].x + a[s].y;
+    }
+#pragma unroll
+    for (int s = 0; s < WTN; ++s) {
+      b[s] = Bs[(kk + kl) * ldb + wn0 + s * 16 + il];
+      sb[s] = b[s].x + b[s].y;
+    }
+#pragma unroll
+    for (int si = 0; si < WTM; ++si)
+#pragma unroll
+      for (int sj = 0; sj < WTN; ++sj) {
+        if (si * 16 >= mrem || sj * 16 >= nrem) continue;
+        acc.p[si][sj] = Mfma<float>::mma(a[si].x, b[sj].x, acc.p[si][sj]);
+        acc.q[si][sj] = Mfma<float>::mma(a[si].y, b[sj].y, acc.q[si][sj]);
+        acc.t[si][sj] = Mfma<float>::mma(sa[si], sb[sj], acc.t[si][sj]);
+      }
+  }
+}
+
 // FP64 accumulation point: add an FP32 slab accumulator into FP64 registers.
 template <int WTM, int WTN>
 CF_DEV void flush(Acc<float, WTM, WTN>& a32, Acc<double, WTM, WTN>& a64) {
@@ -493,13 +553,15 @@ CF_DEV double2 rot_out(double2 t0, double2 t1, int v) {
 // loads of slab k+1 and the LDS stores into the other stage overlap the MFMAs
 // of slab k); otherwise one stage with register prefetch and two barriers.
 // OM: the input is 1 - M instead of M (left, non-rotating channel only).
-// FL (FP32 path): each slab's FP32 MFMA sum is added into FP64 registers (an
-// FP64 accumulation point per slab); without FL the FP32 accumulators run
-// over the whole k range and are converted once in the epilogue, where the
-// FP64 input is added back (correction form).
+// AM (FP32 path): 0 adds each slab's FP32 MFMA sum into FP64 registers (an
+// FP64 accumulation point per slab); 1 runs the FP32 accumulators over the
+// whole k range and converts them once in the epilogue, where the FP64 input
+// is added back (correction form); 2 is 1 with three real products per
+// complex k step (Gauss, as the FP64 path), combined in FP64 in the epilogue;
+// 3 is 0 with the three-product slabs (combined in FP64 at each slab).
 // Each thread keeps base pointers to its staging elements; a slab advances
 // them by a constant.
-template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, bool FL>
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
 chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   typedef typename cplx_t<CT>::type C2;
@@ -643,6 +705,9 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   Acc<float, WTM, WTN> acc32[2];
   acc32[0].zero();
   acc32[1].zero();
+  Acc3F<WTM, WTN> acc3f[2];
+  acc3f[0].zero();
+  acc3f[1].zero();
   const int mr = rows - m0 - wm0, nr = cols - n0 - wn0;
   auto mma = [&](int st, int k0) {
 #pragma unroll
@@ -650,15 +715,35 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       if constexpr (sizeof(CT) == 8) {
         mma_slab3<WTM, WTN, BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
                                  acc3[a], mr, nr, N - k0);
-      } else if constexpr (FL) {
+      } else if constexpr (AM == 0) {
         Acc<float, WTM, WTN> a32;
         a32.zero();
         mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane, a32,
                                        mr, nr, N - k0);
         flush(a32, acc[a]);
-      } else {
+      } else if constexpr (AM == 1) {
         mma_slab<float, WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane,
                                        acc32[a], mr, nr, N - k0);
+      } else if constexpr (AM == 3) {
+        // three-product slab, combined and added into FP64 registers per slab
+        Acc3F<WTM, WTN> a3;
+        a3.zero();
+        mma_slab3f<WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane, a3,
+                                  mr, nr, N - k0);
+        Acc<double, WTM, WTN> d;
+        a3.to(d);
+#pragma unroll
+        for (int si = 0; si < WTM; ++si)
+#pragma unroll
+          for (int sj = 0; sj < WTN; ++sj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              acc[a].re[si][sj][r] += d.re[si][sj][r];
+              acc[a].im[si][sj][r] += d.im[si][sj][r];
+            }
+      } else {
+        mma_slab3f<WTM, WTN, BKC>((const float2*)As[st][a], LDA, (const float2*)Bs[st][a], LDB, wm0, wn0, lane,
+                                  acc3f[a], mr, nr, N - k0);
       }
     }
   };
@@ -687,9 +772,12 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   if constexpr (sizeof(CT) == 8) {
     acc3[0].to(acc[0]);
     acc3[1].to(acc[1]);
-  } else if constexpr (!FL) {
+  } else if constexpr (AM == 1) {
     flush(acc32[0], acc[0]);
     flush(acc32[1], acc[1]);
+  } else if constexpr (AM == 2) {
+    acc3f[0].to(acc[0]);
+    acc3f[1].to(acc[1]);
   }
   // combine T_0, T_1 into the two valley blocks of the output
   double2* Y = c.Y + z * c.sY;
@@ -761,21 +849,21 @@ void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t
   }
 }
 
-template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, bool FL>
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
 static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
   constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
   const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
   const int tx = (cols + BN - 1) / BN, ty = (rows + BM - 1) / BM;
   const long long T = (long long)tx * ty * nbatch;
   const int nblk = (int)((T + 7) / 8 * 8);
-  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, FL>), dim3(nblk), dim3(NT), 0,
+  hipLaunchKernelGGL((chan_apply_kernel<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>), dim3(nblk), dim3(NT), 0,
                      s, c, tx, ty, nbatch); cfqmc_post_launch("chan_apply_kernel");
 }
 
-template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB, bool FL = true>
+template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM = 0>
 static void run_chan_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
-  // FP64 has no accumulation points to drop: its variants without FL are the FL ones
-  constexpr bool F = sizeof(CT) == 8 ? true : FL;
+  // the accumulation modes concern the FP32 path only (FP64 keeps its one form)
+  constexpr int F = sizeof(CT) == 8 ? 0 : AM;
   if (left) {
     if (rot == ROT_X) run_chan<CT, true, ROT_X, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
     else if (rot == ROT_Y) run_chan<CT, true, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
@@ -800,10 +888,15 @@ static void chan_cfg(const ChanArgs& c, int left, int rot, int nbatch, int cfg, 
     case 6: run_chan_any<CT, 64, 64, 2, 2, 8, true>(c, left, rot, nbatch, s); break;
     case 7: run_chan_any<CT, 16, 16, 1, 1, 8, true>(c, left, rot, nbatch, s); break;
     // FP32 accumulation over the whole k range (FP64 configurations: the same tiles)
-    case 8: run_chan_any<CT, 32, 32, 1, 1, 16, false, false>(c, left, rot, nbatch, s); break;
-    case 9: run_chan_any<CT, 64, 64, 2, 2, 16, true, false>(c, left, rot, nbatch, s); break;
-    case 10: run_chan_any<CT, 64, 32, 2, 1, 16, true, false>(c, left, rot, nbatch, s); break;
-    default: run_chan_any<CT, 32, 64, 1, 2, 16, true, false>(c, left, rot, nbatch, s); break;
+    case 8: run_chan_any<CT, 32, 32, 1, 1, 16, false, 1>(c, left, rot, nbatch, s); break;
+    case 9: run_chan_any<CT, 64, 64, 2, 2, 16, true, 1>(c, left, rot, nbatch, s); break;
+    case 10: run_chan_any<CT, 64, 32, 2, 1, 16, true, 1>(c, left, rot, nbatch, s); break;
+    case 11: run_chan_any<CT, 32, 64, 1, 2, 16, true, 1>(c, left, rot, nbatch, s); break;
+    // FP32 three-product form, FP32 accumulation
+    case 12: run_chan_any<CT, 32, 32, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
+    case 13: run_chan_any<CT, 64, 32, 2, 1, 16, true, 2>(c, left, rot, nbatch, s); break;
+    // FP32 three-product slabs with an FP64 accumulation point per slab
+    default: run_chan_any<CT, 32, 32, 1, 1, 16, false, 3>(c, left, rot, nbatch, s); break;
   }
 }
 

@@ -7,12 +7,15 @@
 //           chan32r | chan64r the right application X E^-1 (tau_x rotation)
 //           lu_np             LU of M = 1 + small (non-pivoted, in place)
 //           rsolve            G' = G M^-1 from that LU
+//           copy              a plain device-to-device copy of 1 GiB (the reference
+//                             for scaling the FETCH_SIZE / WRITE_SIZE counters)
 //
 // Inputs are seeded random matrices of the sweep's shapes: M (n x n, n =
 // 2 n_phi, entries O(1)), the orbital blocks X = 1 + A with ||A|| ~ 0.3 (the
 // channel exponentials of typical fields). Every launch covers all chains, as
-// in the sweep. The driver times `iters` launches after two warm-up launches
-// with a device synchronisation on each side (no HIP events), and prints the
+// in the sweep. The driver times `iters` launches after half a second of
+// warm-up launches, with a device synchronisation on each side (no HIP
+// events), and prints the
 // mean duration and the launch's algorithmic work: for the channel
 // application 2 n^3 real flops per chain (one of the eight applications that
 // make up the two n x n x n complex products of the wrap) next to the 4 n^3
@@ -63,10 +66,24 @@ double2* upload(const std::vector<double2>& h) {
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|lu_np|rsolve [n_phi] [chains] [iters] [cfg]\n");
+    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|lu_np|rsolve|copy [n_phi] [chains] [iters] [cfg]\n");
     return 2;
   }
   const std::string k = argv[1];
+  if (k == "copy") {
+    const size_t bytes = (size_t)1 << 30;
+    void *a = nullptr, *b = nullptr;
+    CK(hipMalloc(&a, bytes));
+    CK(hipMalloc(&b, bytes));
+    CK(hipMemset(a, 1, bytes));
+    CK(hipDeviceSynchronize());
+    for (int i = 0; i < 3; ++i) CK(hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr));
+    CK(hipDeviceSynchronize());
+    std::printf("{\"kernel\": \"copy\", \"bytes\": %zu, \"copies\": 3}\n", bytes);
+    hipFree(a);
+    hipFree(b);
+    return 0;
+  }
   const int N = argc > 2 ? std::atoi(argv[2]) : 100;
   const int B = argc > 3 ? std::atoi(argv[3]) : 256;
   const int iters = argc > 4 ? std::atoi(argv[4]) : 20;
@@ -150,8 +167,14 @@ int main(int argc, char** argv) {
     std::fprintf(stderr, "kbench: unknown kernel %s\n", k.c_str());
     return 2;
   }
-  for (int w = 0; w < 2; ++w) run();
-  CK(hipDeviceSynchronize());
+  // warm-up: half a second of launches, so that the clocks have ramped
+  {
+    const auto tw = std::chrono::steady_clock::now();
+    do {
+      for (int w = 0; w < 4; ++w) run();
+      CK(hipDeviceSynchronize());
+    } while (std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count() < 0.5);
+  }
   const auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < iters; ++i) run();
   CK(hipDeviceSynchronize());

@@ -48,11 +48,14 @@ struct ChanArgs {
   int sel_want;
 };
 
-// Tile configurations: zgemm 0..3; chan_apply 0..11 (a fixed tile_cfg applies to both;
-// 8..11 accumulate the FP32 path in FP32 over the whole k range).
+// Tile configurations: zgemm 0..3; chan_apply 0..14 (a fixed tile_cfg applies to both;
+// 8..13 accumulate the FP32 path in FP32 over the whole k range, 12 and 13 with
+// three real products per complex step; 14 has three-product slabs with an FP64
+// accumulation point per slab, as 0..7).
 #define CFQMC_GEMM_CFGS 4
-#define CFQMC_CHAN_CFGS 12
-#define CFQMC_CHAN_CFGS_ACC64 8
+#define CFQMC_CHAN_CFGS 15
+// FP32 path: does configuration cfg keep an FP64 accumulation point per slab?
+inline bool chan_cfg_acc64(int cfg) { return cfg < 8 || cfg == 14; }
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
 // rot: 0 none (channels 0, 3), 1 tau_x (channel 1), 2 tau_y (channel 2)
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);
@@ -87,12 +90,16 @@ void launch_colscale(const double2* X, int ldx, long long sX, double2* Y, int ld
 // receives max |X - Y| and max |Y| of this call.
 void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, double* out, int nbatch,
                     hipStream_t s, int so = 4, double* last = nullptr);
-// Precision guard of the mixed path, after a recomputation: from last [batch][2]
+// Precision guard of the mixed path, after a recomputation: count[z] += sel[z]
+// (the block that ended ran in FP64 from some slice on), then from last [batch][2]
 // (max |G_updated - G_FP64|, max |G_FP64| of the block just ended) set
 // sel[z] = 1 (FP64 applications for the next block) if max |G_FP64| > gmax or the
-// error > err, else 0; count[z] += sel[z]; gmax_run[z] = max(gmax_run[z], max |G_FP64|).
+// error > err, else 0; gmax_run[z] = max(gmax_run[z], max |G_FP64|).
 void launch_precision_guard(const double* last, int* sel, int* count, double* gmax_run, double gmax, double err,
                             int nbatch, hipStream_t s);
+// Within a block: sel[z] = 1 if the updated G of chain z (n x n = nn entries, stride
+// sG) has an entry of modulus above gmax (sel is never cleared here).
+void launch_guard_slice(const double2* G, long long sG, int nn, int* sel, double gmax, int nbatch, hipStream_t s);
 
 // ---- UDT stabilisation helpers (linalg.hip)
 // Column norms of W (n x n) -> nrm; descending-order permutation perm.

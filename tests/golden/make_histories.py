@@ -5,7 +5,7 @@ Writes tests/golden/hist_<name>.npz for the GPU replay tests. Only the oracle
 fields and the replayed proposal noise are regenerated from the seeds stored
 in each file, and every stored value is an oracle output.
 
-Shapes (torus; fields N(0, 1); one Langevin proposal per slice, Methods,
+Shapes (torus unless noted; fields N(0, 1); one Langevin proposal per slice, Methods,
 Langevin-based global update scheme, adaptive step on):
   c2_n36   N_phi = 36, |q| l_B <= 3 (161 components), L = 200, dtau = 0.1,
            five chains at u = 0.5, 1.0, 1.5, 2.0, 2.5, one sweep each
@@ -16,6 +16,10 @@ Langevin-based global update scheme, adaptive step on):
            axes, u = 0.5, 1.667, 3.0 (ends and middle of the 16-point grid
            0.5 + j / 6), one sweep each
   c5_n140  N_phi = 140, paper cutoff (1305), u = 1.5, 8-slice axis, one sweep
+  sphere_n59
+           the paper's largest sphere, N_phi = 59 (3481 components per channel),
+           dtau = 0.01, u = 0.2, 8-slice axis, n_stab = 4, one sweep at eps = 0.05
+           (the sphere's larger exponents need a smaller Langevin step)
 
 Usage: python tests/golden/make_histories.py [name ...]   (default: all)
 Per chain the file holds: acc<k> [sweeps][L] accept flags, lna<k> ln A,
@@ -36,7 +40,7 @@ if ROOT not in sys.path:
 
 import synth  # noqa: E402
 from oracle import dqmc  # noqa: E402
-from oracle.model import Model, Q_PAPER, Q_RADIUS  # noqa: E402
+from oracle.model import Model, Q_PAPER, Q_RADIUS, Q_SPHERE  # noqa: E402
 
 CONFIGS = {
     "c2_n36": dict(n_phi=36, l_tau=200, dtau=0.1, q_mode=Q_RADIUS, q_max=3.0, u=[0.5, 1.0, 1.5, 2.0, 2.5],
@@ -51,6 +55,8 @@ CONFIGS = {
                    eps0=0.4, seed_f=432, seed_r=532),
     "c5_n140": dict(n_phi=140, l_tau=8, dtau=0.1, q_mode=Q_PAPER, q_max=None, u=[1.5], n_stab=4, n_sweeps=1,
                     eps0=0.4, seed_f=5, seed_r=105),
+    "sphere_n59": dict(n_phi=59, l_tau=8, dtau=0.01, q_mode=Q_SPHERE, q_max=None, u=[0.2], n_stab=4, n_sweeps=1,
+                       eps0=0.05, seed_f=59, seed_r=159, exp_squarings=10),
 }
 
 

@@ -46,10 +46,11 @@ def _inputs(cfg, n_q):
     return phi, rp
 
 
-def _kw(cfg, precision):
+def _kw(cfg, precision, tile_cfg=1):
     return dict(n_phi=cfg["n_phi"], l_tau=cfg["l_tau"], dtau=cfg["dtau"], q_mode=cfg["q_mode"],
                 q_max=cfg["q_max"] or 3.0, n_stab=cfg["n_stab"], eps0=cfg["eps0"], adapt_eps=True,
-                precision=precision, n_chains=len(cfg["u"]), chain_u=[(1.0, u, u) for u in cfg["u"]], tile_cfg=1)
+                precision=precision, n_chains=len(cfg["u"]), chain_u=[(1.0, u, u) for u in cfg["u"]],
+                tile_cfg=tile_cfg, exp_squarings=cfg.get("exp_squarings", 2))
 
 
 def rel(a, b):
@@ -87,10 +88,10 @@ def _check_final(g, k, kl, d, cfg, mixed):
     assert abs(ld.real - ldr.real) < tol * abs(ldr.real)
 
 
-def _replay_context(name, precision):
+def _replay_context(name, precision, tile_cfg=1):
     CFQMC, _ = _gpu()
     cfg, d = _load(name)
-    g = CFQMC(**_kw(cfg, precision))
+    g = CFQMC(**_kw(cfg, precision, tile_cfg))
     phi, rp = _inputs(cfg, g.n_q)
     g.init_fields(phi)
     mixed = precision != 0
@@ -114,6 +115,20 @@ def test_n100_paper_cutoff_short_axis(precision):
     """The bench shape: N_phi = 100, paper cutoff (933 components), u = 1.5,
     n_stab = 8, on a 16-slice axis, two sweeps; FP64 and mixed."""
     _replay_context("c3_n100", precision)
+
+
+def test_n100_mixed_fp32_accumulating_tiles():
+    """The same N_phi = 100 replay with the FP32 applications accumulating in
+    FP32 over the whole k range (channel-application configuration 10, 64 x 32
+    tiles): the mixed bar holds."""
+    _replay_context("c3_n100", 1, tile_cfg=10)
+
+
+def test_sphere_n59_largest_sphere_one_sweep():
+    """The paper's largest sphere, N_phi = 59 (3481 components per channel,
+    spin block 118), dtau = 0.01, u = 0.2, on an 8-slice axis with n_stab = 4:
+    one replayed FP64 sweep."""
+    _replay_context("sphere_n59", 0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

@@ -141,7 +141,7 @@ def test_tile_configurations_agree():
     phi = synth.fields(3, L, m.n_q)
     rp = synth.replay(4, 1, L, m.n_q)
     out = []
-    for cfg in range(12):
+    for cfg in range(15):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg)
         g.init_fields(phi[None])
         g.sweep(1, rp[None])
@@ -154,9 +154,10 @@ def test_tile_configurations_agree():
 
 def test_mixed_tile_configurations_within_the_bar():
     """Every channel-application configuration of the FP32 path, with FP64
-    accumulation points (0..7) or FP32 accumulation over the whole k range
-    (8..11): identical accept/reject sequences and the updated G within 1e-6 of
-    its FP64 recomputation; G after the sweep within 1e-8 of the FP64 path."""
+    accumulation points (0..7, 14) or FP32 accumulation over the whole k range
+    (8..13; 12, 13 and 14 in the three-product form): identical accept/reject
+    sequences and the updated G within 1e-6 of its FP64 recomputation; G after
+    the sweep within 1e-8 of the FP64 path."""
     CFQMC = _gpu()
     n_phi, L = 7, 12
     m = Model(n_phi, L, 0.1, u0=1.0, uk=1.0, un=1.0)
@@ -167,7 +168,7 @@ def test_mixed_tile_configurations_within_the_bar():
     ref.sweep(1, rp[None])
     G0, acc0 = ref.measure_G(0, L), ref.last_sweep(0)[0].tolist()
     ref.close()
-    for cfg in range(12):
+    for cfg in range(15):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg, precision=1)
         g.init_fields(phi[None])
         st = g.sweep(1, rp[None])
