@@ -182,6 +182,10 @@ def main():
     ap.add_argument("--guard-err", type=float, default=2.5e-7,
                     help="precision guard: FP64 applications for chains whose last block error exceeded this")
     ap.add_argument("--no-guard", action="store_true", help="FP32 applications for every chain (mixed modes)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every sweep launch by launch (no recorded sweep graphs)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the short batched-workload leg (64 chains over N_phi 24/48/72) of the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB between two fresh device buffers three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -222,7 +226,8 @@ def main():
     if args.chains % args.groups:
         raise SystemExit("--chains must be a multiple of --groups")
     nper = args.chains // args.groups
-    geo = dict(q_mode=Q_SPHERE if args.geometry == "sphere" else Q_PAPER, exp_squarings=args.exp_squarings)
+    geo = dict(q_mode=Q_SPHERE if args.geometry == "sphere" else Q_PAPER, exp_squarings=args.exp_squarings,
+               sweep_graph=0 if args.no_graph else 1)
     guard = dict(precision_guard=0 if args.no_guard else 1, guard_gmax=args.guard_gmax, guard_err=args.guard_err)
     b = Batch([dict(n_phi=args.n_phi, l_tau=args.l_tau, dtau=args.dtau, u0=1.0, uk=args.u, un=args.u,
                     n_stab=args.n_stab, precision=prec, eps0=0.3, adapt_eps=True, seed=3 + k, n_chains=nper,
@@ -461,6 +466,17 @@ def main():
         out["plain_fp64_1chain"] = plain
         p.close()
         progress("one-chain FP64 reference done")
+    if not args.no_batched and args.geometry == "torus":
+        # the batched workload (64 chains over N_phi 24 / 48 / 72), short: one
+        # warm-up and five timed sweeps, with recorded sweep graphs and launch
+        # by launch
+        bg = batched_run(args, prec, True, 5, 1)
+        bl = batched_run(args, prec, False, 5, 1)
+        out["batched"] = {"workload": "64 chains, N_phi 24/48/72 (32/16/16 chains, L_tau 60/120/180), paper cutoff, "
+                                      "u grid 0.5..3.0 (16 points), recompute every 10 slices, %s, 5 timed sweeps"
+                                      % args.precision,
+                          "graph": bg, "launch_by_launch": bl, "graph_speedup": bg["value"] / bl["value"]}
+        progress("batched leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n_phi, args.l_tau, args.dtau, args.u, args.cpu_seconds,
                                            args.geometry == "sphere")
@@ -660,12 +676,14 @@ def bench_tau(args, prec):
     b.close()
 
 
-def bench_batched(args, prec):
+def batched_run(args, prec, graph, steps, warmup):
     """64 independent chains in one job: 32 at N_phi=24 (L=60), 16 at N_phi=48
     (L=120), 16 at N_phi=72 (L=180), paper cutoff, u on the grid 0.5 + j/6
     (j = 0..15), dtau = 0.1. One context per N_phi group, each on its own
-    stream; a step is one sweep of every chain."""
-    import numpy as np
+    stream; a step is one sweep of every chain. graph: each group's sweep is one
+    launch of its recorded graph (else launch by launch, the groups' slice
+    steps interleaved). The kernel timing of the N_phi = 72 group's channel
+    application comes from one more sweep, launch by launch."""
     import torch
     from paper_2605_03700_amd import Batch
     grid = [0.5 + j / 6.0 for j in range(16)]
@@ -674,34 +692,28 @@ def bench_batched(args, prec):
         groups.append(dict(n_phi=n_phi, l_tau=10 * n_phi // 4, dtau=args.dtau, n_stab=10, precision=prec,
                            eps0=0.3, adapt_eps=True, seed=400 + k, n_chains=nch,
                            chain_u=[(1.0, grid[c % 16], grid[c % 16]) for c in range(nch)],
-                           tile_cfg=args.tile_cfg))
+                           tile_cfg=args.tile_cfg, sweep_graph=int(graph)))
     b = Batch(groups)
     b.init_fields()
-    if args.warmup:
-        b.sweep(args.warmup)
+    if warmup:
+        b.sweep(warmup)
     torch.cuda.synchronize()
-    g72 = b.groups[2]
-    g72.kernel_timing(True)
     t0 = time.perf_counter()
-    st = b.sweep(args.steps)
+    st = b.sweep(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    g72 = b.groups[2]
+    g72.kernel_timing(True)
+    b.sweep(1)
     k_ms, k_count, k_flops = g72.kernel_timing_read()
     g72.kernel_timing(False)
-    fields = sum(g.n_chains * g.l_tau * 4 * g.n_q for g in b.groups) * args.steps
+    fields = sum(g.n_chains * g.l_tau * 4 * g.n_q for g in b.groups) * steps
     out = {
-        "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
-        "value": fields / dt, "unit": "field updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": "batched: 64 chains, N_phi 24/48/72 (32/16/16 chains, L_tau 60/120/180), "
-                               "paper cutoff, u grid 0.5..3.0 (16 points), recompute every 10 slices",
-                   "chains": b.n_chains, "precision": args.precision, "n_q": [g.n_q for g in b.groups],
-                   "tile_cfg": [list(g.tile_config()) for g in b.groups]},
+        "value": fields / dt, "ms_per_step": 1000.0 * dt / steps, "sweep_graph": bool(graph),
+        "chains": b.n_chains, "n_q": [g.n_q for g in b.groups],
+        "tile_cfg": [list(g.tile_config()) for g in b.groups],
         "acceptance": sum(s["accepted"] for s in st) / max(1, sum(s["proposed"] for s in st)),
         "g_err_max": max(s["max_stab_err"] for s in st),
-        "g_err_definition": "max over chains and recomputation points of max|G_updated - G_FP64| (absolute, "
-                            "max norm); g_err_rel_max divides by max|G_FP64| of the chain",
         "g_err_rel_max": max(s["max_stab_rel"] for s in st),
         "acceptance_min_chain": chain_acceptance([st])[0],
         "frozen_chains": chain_acceptance([st])[1],
@@ -716,6 +728,26 @@ def bench_batched(args, prec):
                            "flops_per_launch": algo, "issued_flops_per_launch": k_flops,
                            "issued_tflops": issued, "issued_frac": issued / PEAK[args.precision]}
     b.close()
+    return out
+
+
+def bench_batched(args, prec):
+    """The batched workload as its own bench line (see batched_run), recorded
+    sweep graphs unless --no-graph."""
+    r = batched_run(args, prec, not args.no_graph, args.steps, args.warmup)
+    out = {
+        "metric": "field updates/s + indep. samples/s at N_phi=100, plain vs learned/FP32; G err",
+        "value": r.pop("value"), "unit": "field updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "batched: 64 chains, N_phi 24/48/72 (32/16/16 chains, L_tau 60/120/180), "
+                               "paper cutoff, u grid 0.5..3.0 (16 points), recompute every 10 slices",
+                   "chains": r.pop("chains"), "precision": args.precision, "n_q": r.pop("n_q"),
+                   "tile_cfg": r.pop("tile_cfg"), "sweep_graph": r.pop("sweep_graph")},
+        "g_err_definition": "max over chains and recomputation points of max|G_updated - G_FP64| (absolute, "
+                            "max norm); g_err_rel_max divides by max|G_FP64| of the chain",
+    }
+    out.update(r)
     print(json.dumps(out))
 
 

@@ -117,6 +117,11 @@ typedef struct {
                             scales with |G|); 0: FP32 for every chain. Ignored in CFQMC_FP64 */
   double guard_gmax;     /* default 1.0 */
   double guard_err;      /* default 2.5e-7 */
+  int32_t sweep_graph;   /* 1 (default): the launches of one whole sweep are recorded once as a HIP graph
+                            and each later sweep is one graph launch, when the context has a stream of its
+                            own (the groups of a batch; not the null stream) and kernel timing is off;
+                            the device-side sweep counter and series index make every replay the next
+                            sweep. 0: launch by launch. Results are identical either way */
 } cfqmc_params;
 
 typedef struct {
@@ -135,7 +140,7 @@ typedef struct {
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
  * n_stab=10, FP64, eps0=0.5, r0=0.574, deps=0.1, eps in [1e-3, 5], adapt on,
  * one chain, exp_squarings=2, tile_cfg=-1, dense4n=0, exact_drift=0,
- * precision_guard=1, guard_gmax=1, guard_err=2.5e-7). */
+ * precision_guard=1, guard_gmax=1, guard_err=2.5e-7, sweep_graph=1). */
 void cfqmc_default_params(cfqmc_params* p);
 
 /* Create a context: builds the model tables on the host, allocates device

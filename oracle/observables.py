@@ -15,7 +15,7 @@ tau = 0, G(0,0^-) = -(1 - G) and the equal-time formula is recovered.
 """
 import numpy as np
 
-from .model import gamma_matrices, m_matrix
+from .model import PAULI, form_factor, gamma_matrices, m_matrix
 
 
 def gamma_4n(gamma, n_phi):
@@ -72,3 +72,41 @@ def so5_correlator(Gt0, G0t, Gtt, G00, n_phi, sphere=False):
         c.append(np.trace(A @ (I - Xtt)) * np.trace(B @ (I - X00)) - np.trace(A @ Xt0 @ B @ X0t))
     c = np.array(c)
     return c, c.sum() / 5.0
+
+
+def _background(qx, qy, n_phi):
+    """c-number of the O^0 density operator (eq. torus density operator): -2 per
+    orbital at q_y = 0 (mod N), summed with the operator's phases."""
+    if qy % n_phi:
+        return 0.0
+    f = form_factor(qx, qy, n_phi)
+    return 2.0 * sum(f * np.exp(1j * np.pi * (2 * k - qy) * qx / n_phi) for k in range(1, n_phi + 1))
+
+
+def fierz_energy(G2n, n_phi, qs, g):
+    """<H> of one configuration for H = sum_i g_i sum_q n^{O^i}_q n^{O^i}_{-q}
+    (eq. newmodel, O^i = tau^i (x) 1_spin, i = 0..3; the O^0 operator carries its
+    background), by Wick's theorem from the spin-block G (torus). With
+    n = c+ A c - b: <n_q n_{-q}> = Tr[A(1-G)] Tr[B(1-G)] + Tr[A G B (1-G)]
+    - b_{-q} Tr[A(1-G)] - b_q Tr[B(1-G)] + b_q b_{-q}.
+    G2n: one n x n matrix, or a stack [..., n, n] (one energy per matrix)."""
+    G2n = np.asarray(G2n)
+    n2 = 2 * n_phi
+    G4 = np.zeros(G2n.shape[:-2] + (2 * n2, 2 * n2), dtype=complex)
+    G4[..., :n2, :n2] = G2n                 # G_4N = 1_spin (x) G
+    G4[..., n2:, n2:] = G2n
+    IG = np.eye(2 * n2) - G4
+    e = np.zeros(G2n.shape[:-2], dtype=complex)
+    for i in range(4):
+        gamma = np.kron(PAULI[i], PAULI[0])
+        for qx, qy in qs:
+            A = _density_4n(gamma, n_phi, qx, qy)
+            B = _density_4n(gamma, n_phi, -qx, -qy)
+            tA = np.einsum("xy,...yx->...", A, IG)
+            tB = np.einsum("xy,...yx->...", B, IG)
+            w = tA * tB + np.einsum("...xz,...zx->...", A @ G4, B @ IG)
+            if i == 0:
+                bA, bB = _background(qx, qy, n_phi), _background(-qx, -qy, n_phi)
+                w = w + bA * bB - bB * tA - bA * tB
+            e = e + g[i] * w
+    return e

@@ -31,6 +31,7 @@ class Params(ctypes.Structure):
         ("chain_u", ctypes.POINTER(ctypes.c_double)), ("exp_squarings", ctypes.c_int32),
         ("tile_cfg", ctypes.c_int32), ("dense4n", ctypes.c_int32), ("exact_drift", ctypes.c_int32),
         ("precision_guard", ctypes.c_int32), ("guard_gmax", ctypes.c_double), ("guard_err", ctypes.c_double),
+        ("sweep_graph", ctypes.c_int32),
     ]
 
 
@@ -164,7 +165,7 @@ def _ptr(a):
 def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                 q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                 eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1,
-                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7):
+                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7, sweep_graph=1):
     """Fill a Params structure; returns (params, keep-alive arrays)."""
     lib = load()
     p = Params()
@@ -188,6 +189,7 @@ def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PA
     p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
     p.dense4n, p.exact_drift = int(dense4n), int(exact_drift)
     p.precision_guard, p.guard_gmax, p.guard_err = int(precision_guard), float(guard_gmax), float(guard_err)
+    p.sweep_graph = int(sweep_graph)
     return p, keep
 
 
@@ -198,6 +200,7 @@ class CFQMC:
                  q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                  eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
                  tile_cfg=-1, dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7,
+                 sweep_graph=1,
                  stream=None, _handle=None):
         lib = load()
         self.lib = lib
@@ -227,6 +230,7 @@ class CFQMC:
         p.exp_squarings, p.tile_cfg = exp_squarings, tile_cfg
         p.dense4n, p.exact_drift = int(dense4n), int(exact_drift)
         p.precision_guard, p.guard_gmax, p.guard_err = int(precision_guard), float(guard_gmax), float(guard_err)
+        p.sweep_graph = int(sweep_graph)
         if stream is None:
             import torch
             if not torch.cuda.is_available():

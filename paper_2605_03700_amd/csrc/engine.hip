@@ -361,6 +361,15 @@ struct cfqmc_ctx {
   long long blocks_in_call;
   double lu_lmax;   // largest multiplier the non-pivoted LU of M accepts before the pivoted refactorisation
   int dev;   // device current at creation (owner of the stream's memory)
+  // the sweep counter (random-number stream) and the series length in device
+  // memory, so that the recorded graph of a sweep replays unchanged
+  long long* d_counter;
+  int* d_series_len;
+  // recorded graph of one sweep: [0] device noise, [1] replayed noise;
+  // state 0 not recorded yet, 1 recorded, -1 recording failed (launches one by one)
+  hipGraphExec_t gexec[2];
+  int graph_state[2];
+  long long blocks_per_sweep;
   std::string err;
 };
 
@@ -768,6 +777,21 @@ std::string dev_err_msg(int ef) {
   return m;
 }
 
+// Device copies of the host's sweep counter and series length (synchronous).
+hipError_t upload_counters(cfqmc_ctx* c) {
+  const int sl = c->series_len;
+  hipError_t e = hipMemcpy(c->d_counter, &c->sweep_counter, sizeof(long long), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_series_len, &sl, sizeof(int), hipMemcpyHostToDevice);
+  return e;
+}
+
+void drop_graphs(cfqmc_ctx* c) {
+  for (int m = 0; m < 2; ++m) {
+    if (c->graph_state[m] == 1) hipGraphExecDestroy(c->gexec[m]);
+    c->graph_state[m] = 0;
+  }
+}
+
 int check_finite_host(cfqmc_ctx* c, const double* dptr, long long count) {
   std::vector<double> h(count);
   HIPCHK(hipMemcpy(h.data(), dptr, count * sizeof(double), hipMemcpyDeviceToHost));
@@ -806,6 +830,7 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   a.snoise = (long long)c->L * (4 * c->nq + 1);
   a.seed = c->p.seed;
   a.counter = c->sweep_counter * c->L + t;
+  a.counter_dev = c->d_counter;
   a.part = c->part; a.nblk = 4 * c->md.nrow;
   a.lndetM = c->lndet; a.lnA = c->lnA; a.accept = c->accept; a.stat = c->stat;
   launch_drift_propose(c->md, a, c->nch, c->s);
@@ -1029,6 +1054,7 @@ void cfqmc_default_params(cfqmc_params* p) {
   p->exp_squarings = 2; p->tile_cfg = -1;
   p->dense4n = 0; p->exact_drift = 0;
   p->precision_guard = 1; p->guard_gmax = 1.0; p->guard_err = 2.5e-7;
+  p->sweep_graph = 1;
 }
 
 int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
@@ -1041,6 +1067,7 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
     return CFQMC_EINVAL;
   if (p.dense4n < 0 || p.dense4n > 1 || p.exact_drift < 0 || p.exact_drift > 1) return CFQMC_EINVAL;
   if (p.precision_guard < 0 || p.precision_guard > 1 || !(p.guard_gmax > 0) || !(p.guard_err > 0)) return CFQMC_EINVAL;
+  if (p.sweep_graph < 0 || p.sweep_graph > 1) return CFQMC_EINVAL;
   if (p.dense4n || p.exact_drift) return CFQMC_ENOTIMPL;
   cfqmc_ctx* c = new cfqmc_ctx();
   c->p = p;
@@ -1143,6 +1170,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->bg, (size_t)B);
   rc |= dalloc(c, &c->sel64, (size_t)B);
   rc |= dalloc(c, &c->guard_cnt, (size_t)B);
+  rc |= dalloc(c, &c->d_counter, (size_t)1);
+  rc |= dalloc(c, &c->d_series_len, (size_t)1);
   rc |= dalloc(c, &c->gmax_run, (size_t)B);
   rc |= dalloc(c, &c->blk_last, (size_t)B * 2);
   if (rc) { g_create_err = c->err; cfqmc_destroy(c); return CFQMC_ENOMEM; }
@@ -1180,6 +1209,8 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
 int cfqmc_destroy(cfqmc_ctx* c) {
   if (!c) return CFQMC_EINVAL;
   hipStreamSynchronize(c->s);
+  for (int m = 0; m < 2; ++m)
+    if (c->graph_state[m] == 1) hipGraphExecDestroy(c->gexec[m]);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
   for (hipEvent_t e : c->ev2) hipEventDestroy(e);
   for (void* q : c->allocs) hipFree(q);
@@ -1240,6 +1271,7 @@ int cfqmc_init_fields(cfqmc_ctx* c, const double* phi) {
   HIPCHK(hipMemcpy(&ef, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
   c->series_len = 0;
   c->sweep_counter = 0;
+  HIPCHK(upload_counters(c));
   if (ef) { c->err = dev_err_msg(ef) + " at init"; c->ready = false; return CFQMC_ENUMERIC; }
   std::vector<double2> g(c->nn);
   HIPCHK(hipMemcpy(g.data(), c->G, c->nn * sizeof(double2), hipMemcpyDeviceToHost));
@@ -1346,6 +1378,9 @@ int cfqmc_restore(cfqmc_ctx* c, const char* path) {
                        h.series_len * sizeof(double), hipMemcpyHostToDevice));
   c->series_len = h.series_len;
   c->sweep_counter = h.sweep_counter;
+  HIPCHK(upload_counters(c));
+  // the seed is an argument of the recorded sweeps' kernels: record them again
+  if (c->p.seed != h.seed) drop_graphs(c);
   c->p.seed = h.seed;
   return CFQMC_OK;
 }
@@ -1368,31 +1403,92 @@ void sweep_slice(cfqmc_ctx* c, int t, const double* noise_dev) {
   if ((t + 1) % c->nstab == 0 || t == c->L - 1) block_end(c, t / c->nstab);
 }
 
-void sweep_end(cfqmc_ctx* c) {
+// Launches of the end of a sweep (step size, observables, right stack, the
+// series entry, counters advanced on the device).
+void sweep_end_dev(cfqmc_ctx* c) {
   const int B = c->nch;
   launch_eps_update(c->eps, c->acc_count, c->L, c->p.r0, c->p.deps, c->p.eps_min, c->p.eps_max, c->p.adapt_eps, B,
                     c->s);
   launch_observables(c->G, c->nn, c->N, q0_weight(c), c->obs, 8, B, c->s);
   restack_right(c);
-  if (c->series_len < c->series_cap) {
-    // per-sweep series for the autocorrelation: m^2_SO(5), the action and the
-    // q = 0 field power (ln w_F from the fresh right stack, as cfqmc_logdet)
-    const int k = c->series_len;
-    hipMemcpy2DAsync(c->series + k, c->series_cap * sizeof(double), c->obs + 5, 8 * sizeof(double),
-                     sizeof(double), B, hipMemcpyDeviceToDevice, c->s);
-    const long long nn = c->nn, sU = sU_(c), sD = sD_(c);
-    green_udt(c, 0, 0, c->Gs);   // ln det Y in ldtmp
-    launch_copy((const double2*)c->ldtmp, c->ldY2, 1, 1, 1, B, c->s);
-    launch_copy(c->Rs.U, c->Q2, nn, sU, nn, B, c->s);
-    launch_lu(c->Q2, c->n, c->n, nn, c->ipiv, c->n, c->ldtmp, 1, B, c->s);
-    launch_sum_log_dmax(c->Rs.D, sD, c->n, c->tmpd, B, c->s);
-    launch_background(c->md, c->phi, (long long)c->L * 4 * c->nq, c->alpha, c->bg, B, c->s);
-    launch_field_sums(c->phi, (long long)c->L * 4 * c->nq, c->L, c->nq, c->fsq, c->fq0, B, c->s);
-    launch_action_series(c->ldY2, c->ldtmp, c->tmpd, c->bg, c->fsq, c->fq0, c->series_s, c->series_p,
-                         c->series_cap, k, B, c->s);
-    c->series_len++;
-  }
+  // per-sweep series for the autocorrelation: m^2_SO(5), the action and the
+  // q = 0 field power (ln w_F from the fresh right stack, as cfqmc_logdet);
+  // entry *d_series_len, skipped on the device once the series is full
+  const long long nn = c->nn, sU = sU_(c), sD = sD_(c);
+  green_udt(c, 0, 0, c->Gs);   // ln det Y in ldtmp
+  launch_copy((const double2*)c->ldtmp, c->ldY2, 1, 1, 1, B, c->s);
+  launch_copy(c->Rs.U, c->Q2, nn, sU, nn, B, c->s);
+  launch_lu(c->Q2, c->n, c->n, nn, c->ipiv, c->n, c->ldtmp, 1, B, c->s);
+  launch_sum_log_dmax(c->Rs.D, sD, c->n, c->tmpd, B, c->s);
+  launch_background(c->md, c->phi, (long long)c->L * 4 * c->nq, c->alpha, c->bg, B, c->s);
+  launch_field_sums(c->phi, (long long)c->L * 4 * c->nq, c->L, c->nq, c->fsq, c->fq0, B, c->s);
+  launch_action_series(c->ldY2, c->ldtmp, c->tmpd, c->bg, c->fsq, c->fq0, c->obs + 5, 8, c->series, c->series_s,
+                       c->series_p, c->series_cap, c->d_series_len, B, c->s);
+  launch_sweep_advance(c->d_counter, c->d_series_len, c->series_cap, c->s);
+}
+
+// Host copies of the device counters after a sweep.
+void sweep_end_host(cfqmc_ctx* c) {
+  if (c->series_len < c->series_cap) c->series_len++;
   c->sweep_counter++;
+}
+
+void sweep_end(cfqmc_ctx* c) {
+  sweep_end_dev(c);
+  sweep_end_host(c);
+}
+
+bool graph_usable(const cfqmc_ctx* c) {
+  return c->p.sweep_graph && c->s != nullptr && !c->timing && !cfqmc_debug_sync();
+}
+
+// Records the launches of one whole sweep (m = 0: device noise, 1: replayed
+// noise from c->noise) on the context's stream as a graph. Recording runs no
+// kernel; a failure leaves the context on launches one by one.
+void record_sweep(cfqmc_ctx* c, int m) {
+  c->graph_state[m] = -1;
+  const long long blocks0 = c->blocks_in_call;
+  if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  for (int t = 0; t < c->L; ++t) sweep_slice(c, t, m ? c->noise : nullptr);
+  sweep_end_dev(c);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->s, &g);
+  c->blocks_per_sweep = c->blocks_in_call - blocks0;
+  c->blocks_in_call = blocks0;
+  if (e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    if (g) hipGraphDestroy(g);
+    return;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  c->gexec[m] = x;
+  c->graph_state[m] = 1;
+}
+
+// Queues one sweep of all chains: as one launch of the recorded graph where
+// the context allows it, else launch by launch. replay: noise from c->noise.
+void run_sweep(cfqmc_ctx* c, bool replay) {
+  const int m = replay ? 1 : 0;
+  if (graph_usable(c)) {
+    if (c->graph_state[m] == 0) record_sweep(c, m);
+    if (c->graph_state[m] == 1 && hipGraphLaunch(c->gexec[m], c->s) == hipSuccess) {
+      c->blocks_in_call += c->blocks_per_sweep;
+      sweep_end_host(c);
+      return;
+    }
+    (void)hipGetLastError();
+  }
+  for (int t = 0; t < c->L; ++t) sweep_slice(c, t, replay ? c->noise : nullptr);
+  sweep_end(c);
 }
 
 int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
@@ -1473,8 +1569,7 @@ int cfqmc_sweep(cfqmc_ctx* c, int32_t n_sweeps, const double* replay, cfqmc_stat
                               (size_t)n_sweeps * L * W * sizeof(double), (size_t)L * W * sizeof(double), B,
                               hipMemcpyHostToDevice, c->s));
     }
-    for (int t = 0; t < L; ++t) sweep_slice(c, t, replay ? c->noise : nullptr);
-    sweep_end(c);
+    run_sweep(c, replay != nullptr);
   }
   return sweep_collect(c, stats);
 }
@@ -1533,6 +1628,27 @@ int cfqmc_batch_sweep_replay(cfqmc_batch* b, int32_t n_sweeps, const double* con
     Lmax = std::max(Lmax, c->L);
     sweep_reset_stats(c);
   }
+  bool graphs = true;
+  for (auto c : b->g) graphs = graphs && graph_usable(c);
+  if (graphs) {
+    // one recorded sweep per group and sweep, each group on its own stream
+    for (int sw = 0; sw < n_sweeps; ++sw)
+      for (int q = 0; q < G; ++q) {
+        cfqmc_ctx* c = b->g[q];
+        const double* rp = replay ? replay[q] : nullptr;
+        if (rp) {
+          const int W = 4 * c->nq + 1;
+          if (hipMemcpy2DAsync(c->noise, (size_t)c->L * W * sizeof(double), rp + (size_t)sw * c->L * W,
+                               (size_t)n_sweeps * c->L * W * sizeof(double), (size_t)c->L * W * sizeof(double),
+                               c->nch, hipMemcpyHostToDevice, c->s) != hipSuccess) {
+            b->err = "replay upload failed";
+            return CFQMC_EHIP;
+          }
+        }
+        run_sweep(c, rp != nullptr);
+      }
+    Lmax = 0;   // nothing left for the interleaved loop below
+  }
   // every group runs n_sweeps sweeps; slice steps interleaved as in cfqmc_batch_sweep
   const long long kmax = (long long)n_sweeps * Lmax;
   for (long long k = 0; k < kmax; ++k)
@@ -1579,6 +1695,17 @@ int cfqmc_batch_sweep(cfqmc_batch* b, int32_t n_sweeps, int32_t equal_time, cfqm
     steps[k] = ns * c->L;
     kmax = std::max(kmax, steps[k]);
     sweep_reset_stats(b->g[k]);
+  }
+  bool graphs = true;
+  for (auto c : b->g) graphs = graphs && graph_usable(c);
+  if (graphs) {
+    // one recorded sweep per group and sweep, each group on its own stream
+    long long smax = 0;
+    for (int q = 0; q < G; ++q) smax = std::max(smax, steps[q] / b->g[q]->L);
+    for (long long sw = 0; sw < smax; ++sw)
+      for (int q = 0; q < G; ++q)
+        if (sw < steps[q] / b->g[q]->L) run_sweep(b->g[q], false);
+    kmax = 0;
   }
   // interleave slice steps of all groups; each group's kernels go to its own stream
   for (long long k = 0; k < kmax; ++k)

@@ -178,7 +178,8 @@ struct StepArgs {
   const double2* alpha;      // [chain][4]
   const double* eps;         // [chain]
   const double* noise; long long snoise; // replay slice: [4 nq + 1] per chain, or null
-  uint64_t seed; long long counter;      // RNG counter base (sweep/slice)
+  uint64_t seed; long long counter;      // RNG counter (sweep * L + slice) when counter_dev is null
+  const long long* counter_dev;          // sweep counter in device memory: counter = *counter_dev * L + tau
   double* part;              // partial sums [chain][nblk][4]
   int nblk;
   const double2* lndetM;     // [chain]
@@ -219,8 +220,10 @@ void launch_field_sums(const double* phi, long long sphi, int L, int nq, double*
                        hipStream_t s);
 // series entry k: S = |phi|^2/2 - ln w_F from the UDT pieces, and the q = 0 power
 void launch_action_series(const double2* ldY, const double2* ldU, const double* sdm, const double2* bg,
-                          const double* sq, const double* q0, double* ser_s, double* ser_p, long long cap, int k,
-                          int nchain, hipStream_t s);
+                          const double* sq, const double* q0, const double* m2, int m2_stride, double* ser_m,
+                          double* ser_s, double* ser_p, long long cap, const int* k_dev, int nchain, hipStream_t s);
+// sweep counter += 1 and series length += 1 (up to cap), on the device
+void launch_sweep_advance(long long* counter, int* series_len, int cap, hipStream_t s);
 // 4N expansion of the spin block
 void launch_expand4n(const double2* G, int n, double2* G4, hipStream_t s);
 

@@ -10,6 +10,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
+#include <utility>
+#include <vector>
 #include "common.h"
 #include "kernels.h"
 
@@ -734,11 +737,22 @@ void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, d
 }
 
 // Allow more than 64 KB of dynamic LDS (gfx950 has 160 KB per workgroup); returns false if refused.
+// A limit once granted is remembered per kernel, so that later launches (also
+// those recorded into a sweep graph) make no runtime call for it.
 static bool set_lds_limit(const void* fn, size_t shm) {
   if (shm <= 65536 - 24 * 1024) return true;
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> granted;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const auto& g : granted)
+    if (g.first == fn && g.second >= shm) return true;
   const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   (void)hipGetLastError();
-  return e == hipSuccess;
+  if (e != hipSuccess) return false;
+  for (auto& g : granted)
+    if (g.first == fn) { g.second = shm; return true; }
+  granted.emplace_back(fn, shm);
+  return true;
 }
 
 void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int pivot,

@@ -20,6 +20,12 @@
 #include "common.h"
 #include "kernels.h"
 
+// Random-number counter of a slice move: sweep index * L + slice, the sweep
+// index read from device memory when the context keeps it there.
+CF_DEV long long step_counter(const StepArgs& a) {
+  return a.counter_dev ? a.counter_dev[0] * (long long)a.L + a.tau : a.counter;
+}
+
 // ------------------------------------------------------------------ build_h
 // h = sum_c phi_c q_c: the terms whose matrix has its nonzeros on the diagonal
 // col = row - d (mod N) are grouped by the shift d.
@@ -287,7 +293,7 @@ __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepAr
   for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
     const int c = m.t_comp[t];
     const int j = ch * nq + c;
-    const double eta = a.noise ? a.noise[z * a.snoise + j] : rng_normal(a.seed, z, a.counter, j);
+    const double eta = a.noise ? a.noise[z * a.snoise + j] : rng_normal(a.seed, z, step_counter(a), j);
     const double p0 = phi[c];
     const double p1 = p0 + 0.5 * eps * eps * Dl[t - c_lo] + eps * eta;
     phip[c] = p1;
@@ -357,7 +363,7 @@ CF_DEV int mh_decide(const StepArgs& a, int z, bool write, double* red, int* acc
     if (ph > M_PI) ph -= 2.0 * M_PI;
     if (ph < -M_PI) ph += 2.0 * M_PI;
     const double lnA = -0.5 * s_norm + lnR - s_r / (2.0 * eps * eps) + 0.5 * s_eta;
-    const double u = a.noise ? a.noise[z * a.snoise + 4 * a.nq] : rng_uniform(a.seed, z, a.counter);
+    const double u = a.noise ? a.noise[z * a.snoise + 4 * a.nq] : rng_uniform(a.seed, z, step_counter(a));
     const int acc = (u <= 0.0) ? 1 : (log(u) < lnA ? 1 : 0);
     *acc_s = acc;
     if (write) {
@@ -554,20 +560,37 @@ void launch_field_sums(const double* phi, long long sphi, int L, int nq, double*
 // ln|det(1 + B)| = ln|det Y| + sum ln D_R^max - ln|det U_R| (UDT form); written
 // with the q = 0 power to entry k of the per-chain series.
 __global__ void action_series_kernel(const double2* ldY, const double2* ldU, const double* sdm, const double2* bg,
-                                     const double* sq, const double* q0, double* ser_s, double* ser_p,
-                                     long long cap, int k, int nchain) {
+                                     const double* sq, const double* q0, const double* m2, int m2_stride,
+                                     double* ser_m, double* ser_s, double* ser_p, long long cap, const int* k_dev,
+                                     int nchain) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z >= nchain) return;
+  const int k = *k_dev;
+  if (z >= nchain || k >= cap) return;
   const double lnw = 2.0 * (ldY[z].x + sdm[z] - ldU[z].x) + bg[z].x;
+  ser_m[z * cap + k] = m2[(long long)z * m2_stride];
   ser_s[z * cap + k] = 0.5 * sq[z] - lnw;
   ser_p[z * cap + k] = q0[z];
 }
 void launch_action_series(const double2* ldY, const double2* ldU, const double* sdm, const double2* bg,
-                          const double* sq, const double* q0, double* ser_s, double* ser_p, long long cap, int k,
-                          int nchain, hipStream_t s) {
-  hipLaunchKernelGGL(action_series_kernel, dim3((nchain + 63) / 64), dim3(64), 0, s, ldY, ldU, sdm, bg, sq, q0,
-                     ser_s, ser_p, cap, k, nchain);
+                          const double* sq, const double* q0, const double* m2, int m2_stride, double* ser_m,
+                          double* ser_s, double* ser_p, long long cap, const int* k_dev, int nchain, hipStream_t s) {
+  hipLaunchKernelGGL(action_series_kernel, dim3((nchain + 63) / 64), dim3(64), 0, s, ldY, ldU, sdm, bg, sq, q0, m2,
+                     m2_stride, ser_m, ser_s, ser_p, cap, k_dev, nchain);
   cfqmc_post_launch("action_series_kernel");
+}
+
+// End of a sweep on the device: the sweep counter (random-number stream) and
+// the series length advance; both live in device memory so that a captured
+// sweep replays unchanged.
+__global__ void sweep_advance_kernel(long long* counter, int* series_len, int cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counter[0] += 1;
+    if (series_len[0] < cap) series_len[0] += 1;
+  }
+}
+void launch_sweep_advance(long long* counter, int* series_len, int cap, hipStream_t s) {
+  hipLaunchKernelGGL(sweep_advance_kernel, dim3(1), dim3(64), 0, s, counter, series_len, cap);
+  cfqmc_post_launch("sweep_advance_kernel");
 }
 
 __global__ void expand4n_kernel(const double2* G, int n, double2* G4) {

@@ -259,6 +259,48 @@ def test_heterogeneous_batch_matches_standalone_contexts():
     b.close()
 
 
+def test_recorded_sweep_graph_matches_launch_by_launch():
+    """Each sweep of a batch group as one launch of its recorded graph: after
+    three calls (the second with kernel timing on, which runs launch by launch,
+    so the device-side sweep counter carries across both ways) every group is
+    bit-identical to the same batch run launch by launch: fields, G, step sizes,
+    accept counts and the three per-sweep series."""
+    _gpu()
+    from paper_2605_03700_amd import Batch
+    groups = [dict(n_phi=6, l_tau=20, n_stab=5, n_chains=2, seed=3, tile_cfg=1,
+                   chain_u=[(1.0, 0.8, 0.8), (1.0, 1.6, 1.6)]),
+              dict(n_phi=8, l_tau=12, n_stab=4, n_chains=3, seed=5, tile_cfg=1, precision=1)]
+    runs = []
+    for graph in (0, 1):
+        b = Batch([dict(kw, sweep_graph=graph) for kw in groups])
+        b.init_fields()
+        st = [b.sweep(1)]
+        b.groups[0].kernel_timing(True)
+        st.append(b.sweep(2))
+        b.groups[0].kernel_timing(False)
+        st.append(b.sweep(1, equal_time=True))
+        res = {"st": [[(x["accepted"], x["proposed"], x["max_stab_err"]) for x in s] for s in st]}
+        for k, g in enumerate(b.groups):
+            res["phi%d" % k] = g.get_fields()
+            res["eps%d" % k] = g.get_eps()
+            res["G%d" % k] = [g.measure_G(z, 0) for z in range(g.n_chains)]
+            for w in ("m2", "action", "phi_q0_power"):
+                res["%s%d" % (w, k)] = [g.series(z, w) for z in range(g.n_chains)]
+        b.close()
+        runs.append(res)
+    a, b = runs
+    assert a["st"] == b["st"]
+    for key in a:
+        if key == "st":
+            continue
+        va, vb = a[key], b[key]
+        if isinstance(va, list):
+            assert all(np.array_equal(x, y) for x, y in zip(va, vb)), key
+        else:
+            assert np.array_equal(va, vb), key
+    assert len(a["m2%d" % 1][0]) == 1 + 2 + round(20 / 12)
+
+
 def test_checkpoint_restore_continues_the_chains(tmp_path):
     """Two sweeps in one go vs one sweep, checkpoint, restore into a fresh
     context, one sweep: same accept sequence (device noise continues from the

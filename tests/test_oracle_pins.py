@@ -13,7 +13,7 @@ import synth
 from oracle import dqmc, fock
 from oracle.model import (Model, PAULI, Q_BZ, Q_PAPER, Q_RADIUS, components,
                           form_factor, m_matrix, su4_generators)
-from oracle.observables import so5_observables, structure_factor
+from oracle.observables import fierz_energy, so5_observables, structure_factor
 
 
 # ---------------------------------------------------------------- model tables
@@ -620,3 +620,26 @@ def test_eps_controller_settles():
     ch.run(rp)
     acc = np.array([h[2] for h in ch.history[400:]])
     assert abs(acc.mean() - 0.574) < 0.04, acc.mean()
+
+
+@pytest.mark.parametrize("mode", [Q_BZ, Q_PAPER])
+def test_fierz_energy_matches_fock_thermal_state(mode):
+    """Wick evaluation of <H> (eq. newmodel) against the trace in Fock space at
+    N = 2: for a spin-degenerate Gaussian operator rho = exp(-c+ (1 (x) K) c)
+    with K a random complex matrix (not Hermitian, as the propagator products
+    of a field configuration), Tr[H rho] / Tr[rho] equals fierz_energy of
+    G = (1 + e^{-K})^{-1}, the Green's function G_ij = <c_i c_j^dagger> of rho."""
+    n = 2
+    rng = np.random.default_rng(5)
+    K = 0.8 * (rng.normal(size=(2 * n, 2 * n)) + 1j * rng.normal(size=(2 * n, 2 * n)))
+    G = np.linalg.inv(np.eye(2 * n) + sla.expm(-K))
+    cs = fock.annihilators(4 * n)
+    m = Model(n, 2, 0.1, u0=1.0, uk=2.0, un=1.3, q_mode=mode)
+    from oracle.model import momentum_set
+    qs = momentum_set(n, mode)
+    H = fock.hamiltonian_fierz(cs, n, qs, m.g)
+    rho = sla.expm(-fock.bilinear(cs, np.kron(np.eye(2), K)))
+    e_fock = np.trace(H @ rho) / np.trace(rho)
+    e = fierz_energy(G, n, qs, m.g)
+    assert abs(e - e_fock) < 1e-12 * max(1.0, abs(e_fock))
+    assert abs(e_fock) > 1e-3          # the case is not degenerate
