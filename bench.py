@@ -33,7 +33,12 @@ PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFM
 # this script (profiles/chan_apply_traffic_n100_256chains.md); keyed by
 # (N_phi, chains per context, precision, tile configuration). Absent key, or a
 # kernel changed since the counters were taken: traffic not measured (null).
-TRAFFIC = {(100, 256, "mixed", 1): (166617.07 * 2.0 + 160000.0 * 1.0) * 1024}
+# HBM bytes per chain of one channel application at N_phi = 100 (rocprofv3
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch of 256 chains, scaled by
+# the copy calibration; profiles/chan_apply_traffic_n100_256chains.md), keyed
+# by (n_phi, arithmetic, channel-application configuration)
+TRAFFIC = {(100, "f32", 12): (167544.25 * 2.0 + 160000.0) * 1024 / 256,
+           (100, "f64", 1): (124254.67 * 2.0 + 160000.0) * 1024 / 256}
 
 # Integrated autocorrelation times at the default workload's shape (N_phi = 100,
 # L = 400, dtau = 0.1, u = 1.5, paper cutoff) from one long run, 32 chains x
@@ -184,6 +189,9 @@ def main():
     ap.add_argument("--no-guard", action="store_true", help="FP32 applications for every chain (mixed modes)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every sweep launch by launch (no recorded sweep graphs)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="no HIP-event timing of the channel application in the timed sweeps (they then run as "
+                         "recorded sweep graphs; no roofline object)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the short batched-workload leg (64 chains over N_phi 24/48/72) of the default line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -243,7 +251,7 @@ def main():
     if args.warmup:
         b.sweep(args.warmup)
         progress("warm-up done")
-    g.kernel_timing(True)
+    g.kernel_timing(not args.no_kernel_timing)
     dt, stats, g_err = sweep_each(b, args.steps)
     progress("timed sweeps done: %.1f ms per sweep" % (1000.0 * dt / args.steps))
     k_ms, k_count, k_flops = g.kernel_timing_read()
@@ -288,6 +296,9 @@ def main():
                                                    for z in range(len(stats[0]))])),
         "max_abs_g_max": max(x["max_abs_g"] for x in flat),
         "fp64_guard_frac": float(np.mean([x["fp64_guard_frac"] for x in flat])),
+        "sweep_graph_frac": float(np.mean([x["graph_sweep_frac"] for x in flat])),
+        "sweep_graph_definition": "fraction of the timed sweeps run as one launch of the recorded sweep graph "
+                                  "(kernel timing runs them launch by launch)",
         "fp64_guard_definition": "fraction of (chain, stabilisation block) pairs whose FP32 applications the "
                                  "precision guard ran in FP64 from some slice on (an entry of the updated G above "
                                  "%g, or at the previous recomputation max|G_FP64| > %g or a block error > %g)"
@@ -313,7 +324,16 @@ def main():
     if k_count > 0 and k_ms > 0:
         ach = algo_per_launch / (k_ms * 1e-3) / 1e12
         issued = k_flops / (k_ms * 1e-3) / 1e12
-        traffic = TRAFFIC.get((args.n_phi, nper, args.precision, g.tile_config()[0]))
+        # bytes of the timed application: FP32 launches for the chains the guard
+        # leaves in FP32, FP64 launches (configuration 1) for the others
+        t32 = TRAFFIC.get((args.n_phi, "f32", g.tile_config()[0]))
+        t64 = TRAFFIC.get((args.n_phi, "f64", 1))
+        f64 = out["fp64_guard_frac"] if prec != FP64 else 1.0
+        traffic = None
+        if prec == FP64 and g.tile_config()[0] == 1 and t64:
+            traffic = nper * t64
+        elif prec == MIXED and t32 and t64:
+            traffic = nper * ((1.0 - f64) * t32 + f64 * t64)
         out["roofline"] = {"bound": "mfma", "kernel": "chan_apply", "achieved": ach,
                            "peak": PEAK[args.precision], "unit": "TFLOP/s", "frac": ach / PEAK[args.precision],
                            "traffic": traffic, "avg_launch_ms": k_ms, "launches_timed": k_count,
@@ -321,9 +341,18 @@ def main():
                            "issued_flops_per_launch": k_flops, "issued_tflops": issued,
                            "issued_frac": issued / PEAK[args.precision],
                            "hbm_gbps_at_traffic": traffic / (k_ms * 1e-3) / 1e9 if traffic else None,
+                           "traffic_basis": "HBM bytes per chain of the FP32 and the FP64 application (rocprofv3 "
+                                            "FETCH_SIZE / WRITE_SIZE, copy-calibrated, profiles/chan_apply_traffic_"
+                                            "n100_256chains.md) weighted by the fraction of chains in FP64",
                            "definition": "achieved = 2 n^3 real flops per chain (an eighth of the wrap's two "
                                          "n x n x n complex products) / mean HIP-event duration of the timed "
                                          "launch; issued_* count the 4 n^3 the launch performs"}
+        if prec == MIXED:
+            # the timed application runs the guarded chains in FP64: the peak of
+            # that mix (harmonic weighting by the FP64 fraction) beside the FP32 one
+            pk = 1.0 / ((1.0 - f64) / PEAK["mixed"] + f64 / PEAK["fp64"])
+            out["roofline"]["peak_of_precision_mix"] = pk
+            out["roofline"]["frac_of_precision_mix"] = ach / pk
     if w_count > 0 and w_ms > 0:
         # the same kernel family in the Woodbury product M = G + B'B^-1(1 - G),
         # FP64 unless every product runs in FP32
@@ -384,6 +413,7 @@ def main():
         out["g_err_max_later_sweeps"] = max(e[0] for e in g_err2)
         out["g_err_rel_max_later_sweeps"] = max(e[1] for e in g_err2)
         out["g_err_per_later_sweep"] = [e[0] for e in g_err2]
+        out["sweep_graph_frac_later_sweeps"] = float(np.mean([x["graph_sweep_frac"] for st in stats2 for x in st]))
         taus, open_w = {}, []
         for obs in ("m2", "action", "phi_q0_power"):
             series = [q.series(k, obs)[n0[i]:] for i, q in enumerate(b.groups) for k in range(nper)]

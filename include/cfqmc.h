@@ -94,12 +94,13 @@ typedef struct {
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential, 0..16 (default 2) */
-  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..14 fixed channel-application
+  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..18 fixed channel-application
                             configuration (GEMMs use min(tile_cfg, 3)). In the FP32 applications
-                            0..7 and 14 add each 16-deep k slab into FP64 registers (14 with three
-                            real products per complex step), 8..13 accumulate in FP32 over the whole
-                            k range (12, 13 with three products); the autotuner picks among the
-                            former there unless the precision guard is on */
+                            0..7 and 14..16 add each 16-deep k slab into FP64 registers (14 with
+                            three real products per complex step), 8..13, 17 and 18 accumulate in
+                            FP32 over the whole k range (12, 13, 17, 18 with three products); the
+                            autotuner picks among the former there unless the precision guard is
+                            on. 15..18 use 8- or 16-wave workgroups of 16 x 16 wave tiles */
   int32_t dense4n;       /* 0 (only value): the spin-block form n = 2 N_phi. The Fierz channels act as
                             the identity on spin (eq. newmodel), so G_4N = 1_spin (x) G_2N exactly and
                             every output is expanded to 4N; 1 (the un-Fierzed dense 4N coupling, which
@@ -119,9 +120,10 @@ typedef struct {
   double guard_err;      /* default 2.5e-7 */
   int32_t sweep_graph;   /* 1 (default): the launches of one whole sweep are recorded once as a HIP graph
                             and each later sweep is one graph launch, when the context has a stream of its
-                            own (the groups of a batch; not the null stream) and kernel timing is off;
-                            the device-side sweep counter and series index make every replay the next
-                            sweep. 0: launch by launch. Results are identical either way */
+                            own (the groups of a batch; not the null stream); the device-side sweep
+                            counter and series index make every replay the next sweep. With kernel
+                            timing on, sweeps run launch by launch (the timing events are recorded on
+                            the stream). 0: launch by launch. Results are identical either way */
 } cfqmc_params;
 
 typedef struct {
@@ -135,6 +137,8 @@ typedef struct {
   double max_abs_g;           /* max over recomputation points of max|G_FP64| */
   double fp64_guard_frac;     /* fraction of the chain's stabilisation blocks run with FP64 applications
                                  (from some slice on) by the precision guard (mixed modes) */
+  double graph_sweep_frac;    /* fraction of the call's sweeps of the chain's context run as one launch of
+                                 the recorded sweep graph (see sweep_graph) */
 } cfqmc_stats;
 
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,

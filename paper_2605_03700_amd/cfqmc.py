@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("eps", ctypes.c_double),
                 ("max_stab_err", ctypes.c_double), ("max_phase_err", ctypes.c_double),
                 ("exp_range_flag", ctypes.c_int32), ("pad", ctypes.c_int32), ("max_stab_rel", ctypes.c_double),
-                ("max_abs_g", ctypes.c_double), ("fp64_guard_frac", ctypes.c_double)]
+                ("max_abs_g", ctypes.c_double), ("fp64_guard_frac", ctypes.c_double),
+                ("graph_sweep_frac", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

@@ -370,6 +370,8 @@ struct cfqmc_ctx {
   hipGraphExec_t gexec[2];
   int graph_state[2];
   long long blocks_per_sweep;
+  long long sweeps_in_call, graph_sweeps_in_call;
+  bool graph_noted;     // a failed recording or launch has been reported on stderr
   std::string err;
 };
 
@@ -1396,6 +1398,8 @@ void sweep_reset_stats(cfqmc_ctx* c) {
   hipMemsetAsync(c->guard_cnt, 0, c->nch * sizeof(int), c->s);
   hipMemsetAsync(c->gmax_run, 0, c->nch * sizeof(double), c->s);
   c->blocks_in_call = 0;
+  c->sweeps_in_call = 0;
+  c->graph_sweeps_in_call = 0;
 }
 
 void sweep_slice(cfqmc_ctx* c, int t, const double* noise_dev) {
@@ -1431,6 +1435,15 @@ void sweep_end_dev(cfqmc_ctx* c) {
 void sweep_end_host(cfqmc_ctx* c) {
   if (c->series_len < c->series_cap) c->series_len++;
   c->sweep_counter++;
+  c->sweeps_in_call++;
+}
+
+// Reports (once per context) why sweeps run launch by launch.
+void graph_note(cfqmc_ctx* c, const char* step, hipError_t e) {
+  if (c->graph_noted) return;
+  c->graph_noted = true;
+  std::fprintf(stderr, "[cfqmc] recorded sweep graph not used (%s: %s); sweeps run launch by launch\n", step,
+               hipGetErrorString(e));
 }
 
 void sweep_end(cfqmc_ctx* c) {
@@ -1438,6 +1451,8 @@ void sweep_end(cfqmc_ctx* c) {
   sweep_end_host(c);
 }
 
+// Kernel timing keeps launches one by one: the timing events must be recorded
+// by the runtime on the stream (events recorded inside a graph are not timed).
 bool graph_usable(const cfqmc_ctx* c) {
   return c->p.sweep_graph && c->s != nullptr && !c->timing && !cfqmc_debug_sync();
 }
@@ -1448,8 +1463,10 @@ bool graph_usable(const cfqmc_ctx* c) {
 void record_sweep(cfqmc_ctx* c, int m) {
   c->graph_state[m] = -1;
   const long long blocks0 = c->blocks_in_call;
-  if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+  const hipError_t e0 = hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal);
+  if (e0 != hipSuccess) {
     (void)hipGetLastError();
+    graph_note(c, "begin capture", e0);
     return;
   }
   for (int t = 0; t < c->L; ++t) sweep_slice(c, t, m ? c->noise : nullptr);
@@ -1461,13 +1478,18 @@ void record_sweep(cfqmc_ctx* c, int m) {
   if (e != hipSuccess || !g) {
     (void)hipGetLastError();
     if (g) hipGraphDestroy(g);
+    graph_note(c, "end capture", e);
     return;
   }
+  size_t nodes = 0;
+  (void)hipGraphGetNodes(g, nullptr, &nodes);
   hipGraphExec_t x = nullptr;
   const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e2 != hipSuccess) {
     (void)hipGetLastError();
+    std::fprintf(stderr, "[cfqmc] sweep graph of %zu nodes\n", nodes);
+    graph_note(c, "instantiate", e2);
     return;
   }
   c->gexec[m] = x;
@@ -1480,12 +1502,19 @@ void run_sweep(cfqmc_ctx* c, bool replay) {
   const int m = replay ? 1 : 0;
   if (graph_usable(c)) {
     if (c->graph_state[m] == 0) record_sweep(c, m);
-    if (c->graph_state[m] == 1 && hipGraphLaunch(c->gexec[m], c->s) == hipSuccess) {
-      c->blocks_in_call += c->blocks_per_sweep;
-      sweep_end_host(c);
-      return;
+    if (c->graph_state[m] == 1) {
+      const hipError_t e = hipGraphLaunch(c->gexec[m], c->s);
+      if (e == hipSuccess) {
+        c->blocks_in_call += c->blocks_per_sweep;
+        c->graph_sweeps_in_call++;
+        sweep_end_host(c);
+        return;
+      }
+      (void)hipGetLastError();
+      graph_note(c, "launch", e);
+      hipGraphExecDestroy(c->gexec[m]);
+      c->graph_state[m] = -1;
     }
-    (void)hipGetLastError();
   }
   for (int t = 0; t < c->L; ++t) sweep_slice(c, t, replay ? c->noise : nullptr);
   sweep_end(c);
@@ -1519,6 +1548,8 @@ int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
       stats[z].max_abs_g = gm[z];
       // the guard's choice at the last block end of a sweep applies to the next sweep
       stats[z].fp64_guard_frac = c->blocks_in_call ? (double)gc[z] / (double)c->blocks_in_call : 0.0;
+      stats[z].graph_sweep_frac =
+          c->sweeps_in_call ? (double)c->graph_sweeps_in_call / (double)c->sweeps_in_call : 0.0;
     }
   }
   if (bad) {

@@ -896,7 +896,13 @@ static void chan_cfg(const ChanArgs& c, int left, int rot, int nbatch, int cfg, 
     case 12: run_chan_any<CT, 32, 32, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
     case 13: run_chan_any<CT, 64, 32, 2, 1, 16, true, 2>(c, left, rot, nbatch, s); break;
     // FP32 three-product slabs with an FP64 accumulation point per slab
-    default: run_chan_any<CT, 32, 32, 1, 1, 16, false, 3>(c, left, rot, nbatch, s); break;
+    case 14: run_chan_any<CT, 32, 32, 1, 1, 16, false, 3>(c, left, rot, nbatch, s); break;
+    // 8- and 16-wave workgroups of 16 x 16 wave tiles, one LDS stage: each staged
+    // operand element serves more waves for the same LDS per wave
+    case 15: run_chan_any<CT, 64, 32, 1, 1, 16, false>(c, left, rot, nbatch, s); break;
+    case 16: run_chan_any<CT, 64, 64, 1, 1, 16, false>(c, left, rot, nbatch, s); break;
+    case 17: run_chan_any<CT, 64, 32, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
+    default: run_chan_any<CT, 64, 64, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
   }
 }
 

@@ -48,14 +48,15 @@ struct ChanArgs {
   int sel_want;
 };
 
-// Tile configurations: zgemm 0..3; chan_apply 0..14 (a fixed tile_cfg applies to both;
-// 8..13 accumulate the FP32 path in FP32 over the whole k range, 12 and 13 with
-// three real products per complex step; 14 has three-product slabs with an FP64
-// accumulation point per slab, as 0..7).
+// Tile configurations: zgemm 0..3; chan_apply 0..18 (a fixed tile_cfg applies to both;
+// 8..13, 17 and 18 accumulate the FP32 path in FP32 over the whole k range, 12,
+// 13, 17 and 18 with three real products per complex step; 14 has three-product
+// slabs with an FP64 accumulation point per slab, as 0..7, 15 and 16; 15..18 are
+// 8- and 16-wave workgroups of 16 x 16 wave tiles).
 #define CFQMC_GEMM_CFGS 4
-#define CFQMC_CHAN_CFGS 15
+#define CFQMC_CHAN_CFGS 19
 // FP32 path: does configuration cfg keep an FP64 accumulation point per slab?
-inline bool chan_cfg_acc64(int cfg) { return cfg < 8 || cfg == 14; }
+inline bool chan_cfg_acc64(int cfg) { return cfg < 8 || cfg == 14 || cfg == 15 || cfg == 16; }
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
 // rot: 0 none (channels 0, 3), 1 tau_x (channel 1), 2 tau_y (channel 2)
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);

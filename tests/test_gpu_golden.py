@@ -124,6 +124,14 @@ def test_n100_mixed_fp32_accumulating_tiles():
     _replay_context("c3_n100", 1, tile_cfg=10)
 
 
+@pytest.mark.parametrize("precision,tile_cfg", [(0, 16), (1, 18)])
+def test_n100_wide_workgroup_tiles(precision, tile_cfg):
+    """The N_phi = 100 replay with the 16-wave 64 x 64 workgroup tiles of the
+    channel application (configuration 16 in FP64, 18 in the FP32 three-product
+    form): the FP64 and mixed bars hold."""
+    _replay_context("c3_n100", precision, tile_cfg=tile_cfg)
+
+
 def test_sphere_n59_largest_sphere_one_sweep():
     """The paper's largest sphere, N_phi = 59 (3481 components per channel,
     spin block 118), dtau = 0.01, u = 0.2, on an 8-slice axis with n_stab = 4:

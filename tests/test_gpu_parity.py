@@ -134,14 +134,18 @@ def test_sweep_replay_parity_mixed(precision):
     assert st[0]["max_stab_err"] < 1e-6 and st[0]["max_stab_rel"] < 1e-6
 
 
-def test_tile_configurations_agree():
+@pytest.mark.parametrize("n_phi", [7, 36])
+def test_tile_configurations_agree(n_phi):
+    """Every channel-application configuration of the FP64 path (16 x 16 to
+    64 x 64 workgroup tiles, ragged edges at N_phi = 7 and 36): the same accept
+    sequence and G within 1e-12 after a replayed sweep."""
     CFQMC = _gpu()
-    n_phi, L = 7, 12
+    L = 12
     m = Model(n_phi, L, 0.1, u0=1.0, uk=1.0, un=1.0)
     phi = synth.fields(3, L, m.n_q)
     rp = synth.replay(4, 1, L, m.n_q)
     out = []
-    for cfg in range(15):
+    for cfg in range(19):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg)
         g.init_fields(phi[None])
         g.sweep(1, rp[None])
@@ -154,8 +158,9 @@ def test_tile_configurations_agree():
 
 def test_mixed_tile_configurations_within_the_bar():
     """Every channel-application configuration of the FP32 path, with FP64
-    accumulation points (0..7, 14) or FP32 accumulation over the whole k range
-    (8..13; 12, 13 and 14 in the three-product form): identical accept/reject
+    accumulation points (0..7, 14..16) or FP32 accumulation over the whole k
+    range (8..13, 17, 18; 12..14, 17, 18 in the three-product form; 15..18 with
+    8- and 16-wave workgroups): identical accept/reject
     sequences and the updated G within 1e-6 of its FP64 recomputation; G after
     the sweep within 1e-8 of the FP64 path."""
     CFQMC = _gpu()
@@ -168,7 +173,7 @@ def test_mixed_tile_configurations_within_the_bar():
     ref.sweep(1, rp[None])
     G0, acc0 = ref.measure_G(0, L), ref.last_sweep(0)[0].tolist()
     ref.close()
-    for cfg in range(15):
+    for cfg in range(19):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg, precision=1)
         g.init_fields(phi[None])
         st = g.sweep(1, rp[None])
@@ -261,10 +266,11 @@ def test_heterogeneous_batch_matches_standalone_contexts():
 
 def test_recorded_sweep_graph_matches_launch_by_launch():
     """Each sweep of a batch group as one launch of its recorded graph: after
-    three calls (the second with kernel timing on, which runs launch by launch,
-    so the device-side sweep counter carries across both ways) every group is
-    bit-identical to the same batch run launch by launch: fields, G, step sizes,
-    accept counts and the three per-sweep series."""
+    four calls (the middle two with kernel timing on for one group, which then
+    runs launch by launch, so the device-side sweep counter carries across both
+    ways; its timed launches are counted alike) every group is bit-identical to
+    the same batch run launch by launch: fields, G, step sizes, accept counts
+    and the three per-sweep series."""
     _gpu()
     from paper_2605_03700_amd import Batch
     groups = [dict(n_phi=6, l_tau=20, n_stab=5, n_chains=2, seed=3, tile_cfg=1,
@@ -276,9 +282,14 @@ def test_recorded_sweep_graph_matches_launch_by_launch():
         b.init_fields()
         st = [b.sweep(1)]
         b.groups[0].kernel_timing(True)
-        st.append(b.sweep(2))
+        st.append(b.sweep(1))
+        st.append(b.sweep(1))
+        k_ms, k_count, _ = b.groups[0].kernel_timing_read()
+        w_ms, w_count, _ = b.groups[0].kernel_timing_read(woodbury=True)
         b.groups[0].kernel_timing(False)
         st.append(b.sweep(1, equal_time=True))
+        # one timed launch of each kind per slice move, in either way of launching
+        assert k_count == w_count == 2 * groups[0]["l_tau"] and k_ms > 0 and w_ms > 0, (graph, k_count, w_count)
         res = {"st": [[(x["accepted"], x["proposed"], x["max_stab_err"]) for x in s] for s in st]}
         for k, g in enumerate(b.groups):
             res["phi%d" % k] = g.get_fields()
