@@ -273,7 +273,7 @@ def main():
                                   "all (l, m)" if args.geometry == "sphere" else "paper cutoff", g.n_q,
                                   args.chains, args.groups, args.n_stab),
                    "chains": args.chains, "groups": args.groups, "precision": args.precision, "n_q": g.n_q,
-                   "tile_cfg": list(g.tile_config())},
+                   "tile_cfg": list(g.tile_config()), "launch_config": g.launch_config()},
         "acceptance": acc,
         "acceptance_min_chain": chain_acceptance(stats)[0],
         "frozen_chains": chain_acceptance(stats)[1],
@@ -388,6 +388,7 @@ def main():
         out["fp64_same_chains"] = {"precision": "fp64", "chains": args.chains, "field_updates_per_s": f_rate,
                                    "ms_per_sweep": 1000.0 * dtf / args.steps, "g_err_max": max(e[0] for e in gef),
                                    "mixed_over_fp64": value / f_rate,
+                                   "launch_config": f.groups[0].launch_config(),
                                    "start": "the mixed chains' fields and step sizes after the timed sweeps, "
                                             "one warm-up sweep, %d timed sweeps" % args.steps}
         f.close()

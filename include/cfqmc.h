@@ -39,7 +39,10 @@
  * (read at cfqmc_create, default 8) is the largest multiplier the
  * non-pivoted LU of the Woodbury matrix M accepts before a chain is
  * refactorised with partial pivoting; 0 sends every chain to the pivoted
- * path (for testing that path).
+ * path (for testing that path). CFQMC_GUARD_PAIR=1 (read at cfqmc_create)
+ * runs each precision-guarded channel application as two launches, one per
+ * precision class, instead of one launch whose workgroups take their chain's
+ * path (for testing that the two give identical results).
  */
 #ifndef CFQMC_H
 #define CFQMC_H
@@ -277,6 +280,13 @@ int cfqmc_set_eps(cfqmc_ctx* c, const double* eps /* [n_chains] */);
 
 /* Tile configuration chosen for (channel application, n x n GEMM). */
 int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg);
+/* The whole launch configuration chosen at create (autotuned or fixed), out
+ * [5] host: channel-application configuration of the context's precision (the
+ * FP32 one in mixed contexts), that of a mixed context's FP64 applications,
+ * the n x n GEMM configuration, the exponential's N x N GEMM configuration,
+ * and the launch form of precision-guarded applications (0: one launch per
+ * precision class; 1, 2: one launch for both, three or four waves per SIMD). */
+int cfqmc_launch_config(const cfqmc_ctx* c, int32_t* out);
 
 /* Sampled HIP-event timing of the dominant kernel, the channel-exponential
  * application (two N x N x n complex products per chain on MFMA): when enabled,

@@ -63,7 +63,7 @@ _lib = None
 
 EXPORTS = ["cfqmc_default_params", "cfqmc_create", "cfqmc_destroy", "cfqmc_sizes", "cfqmc_init_fields",
            "cfqmc_get_fields", "cfqmc_checkpoint", "cfqmc_restore", "cfqmc_sweep", "cfqmc_measure_G", "cfqmc_green_displaced", "cfqmc_measure_tau", "cfqmc_structure_factors", "cfqmc_sphere_weights", "cfqmc_slmc_set_subspace", "cfqmc_logdet", "cfqmc_observables",
-           "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config",
+           "cfqmc_series", "cfqmc_series_of", "cfqmc_last_sweep", "cfqmc_get_eps", "cfqmc_set_eps", "cfqmc_tile_config", "cfqmc_launch_config",
            "cfqmc_last_error", "cfqmc_kernel_timing", "cfqmc_kernel_timing_read", "cfqmc_kernel_timing_read_woodbury", "cfqmc_batch_create",
            "cfqmc_batch_context", "cfqmc_batch_sweep", "cfqmc_batch_sweep_replay", "cfqmc_batch_get",
            "cfqmc_batch_destroy", "cfqmc_slmc_default_params",
@@ -116,6 +116,7 @@ def load():
     lib.cfqmc_get_eps.argtypes = [P, P]
     lib.cfqmc_set_eps.argtypes = [P, P]
     lib.cfqmc_tile_config.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.cfqmc_launch_config.argtypes = [P, P]
     lib.cfqmc_kernel_timing.argtypes = [P, ctypes.c_int32]
     lib.cfqmc_kernel_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_double)]
@@ -358,6 +359,15 @@ class CFQMC:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         self._check(self.lib.cfqmc_tile_config(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def launch_config(self):
+        """The launch configuration chosen at create: channel application
+        (context precision; FP32 in mixed contexts), FP64 channel application
+        of a mixed context, n x n GEMM, exponential GEMM, guarded launch form."""
+        o = np.zeros(5, dtype=np.int32)
+        self._check(self.lib.cfqmc_launch_config(self.h, _ptr(o)))
+        return {"chan": int(o[0]), "chan_fp64": int(o[1]), "gemm": int(o[2]), "gemm_exp": int(o[3]),
+                "guard_launch": int(o[4])}
 
     def kernel_timing(self, enable=True):
         self._check(self.lib.cfqmc_kernel_timing(self.h, int(bool(enable))))

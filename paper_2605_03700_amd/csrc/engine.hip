@@ -365,13 +365,31 @@ struct cfqmc_ctx {
   // memory, so that the recorded graph of a sweep replays unchanged
   long long* d_counter;
   int* d_series_len;
-  // recorded graph of one sweep: [0] device noise, [1] replayed noise;
-  // state 0 not recorded yet, 1 recorded, -1 recording failed (launches one by one)
-  hipGraphExec_t gexec[2];
+  // recorded graphs of one sweep, [0] device noise, [1] replayed noise: one
+  // graph per chunk of whole stabilisation blocks (the last chunk also holds
+  // the end of the sweep); state 0 not recorded yet, 1 recorded, -1 recording
+  // failed (launches one by one)
+  std::vector<hipGraphExec_t> gexec[2];
   int graph_state[2];
   long long blocks_per_sweep;
   long long sweeps_in_call, graph_sweeps_in_call;
+  int guard_launch;     // guarded applications: 0 one launch per precision class, 1 / 2 one launch
+                        // for both (launch_chan_apply_dual variant)
+  bool guard_pair_only; // testing knob CFQMC_GUARD_PAIR=1: always one launch per class
   bool graph_noted;     // a failed recording or launch has been reported on stderr
+  bool launch_failed;   // a recorded chunk failed to launch: the sweep is incomplete
+  // timing variant of the recorded sweep (kernel timing on): the capture is cut
+  // at the timed launches, each of which becomes a graph of its own, so that
+  // the host records HIP events around it on the stream. Items in launch
+  // order; kind -1 untimed launches, 0 the wrap's timed application, 1 the
+  // Woodbury product's.
+  std::vector<std::pair<hipGraphExec_t, int>> titems[2];
+  int tstate[2];
+  bool seg_rec;              // recording the timing variant
+  int seg_m;                 // of mode seg_m (0 device noise, 1 replayed noise)
+  const char* seg_fail;      // first failing step while recording it
+  hipError_t seg_fail_err;
+  bool seg_broken;           // a capture could not be restarted: launches ran for real
   std::string err;
 };
 
@@ -459,8 +477,12 @@ void chan(cfqmc_ctx* c, int left, int ch, bool inverse, const double2* PQch, lon
     std::abort();
   }
   if (mixed && c->guard) {
-    // FP32 for the chains the guard leaves in FP32, FP64 for the others
+    // FP32 for the chains the guard leaves in FP32, FP64 for the others: one
+    // launch where both tile configurations allow it, else one per class
     a.chain_sel = c->sel64;
+    if (c->guard_launch &&
+        launch_chan_apply_dual(a, left, rot, c->nch, c->cfg_chan, c->cfg_chan64, c->guard_launch, c->s))
+      return;
     a.sel_want = 0;
     launch_chan_apply(a, left, rot, c->nch, 1, c->cfg_chan, c->s);
     a.sel_want = 1;
@@ -789,8 +811,12 @@ hipError_t upload_counters(cfqmc_ctx* c) {
 
 void drop_graphs(cfqmc_ctx* c) {
   for (int m = 0; m < 2; ++m) {
-    if (c->graph_state[m] == 1) hipGraphExecDestroy(c->gexec[m]);
+    for (hipGraphExec_t x : c->gexec[m]) hipGraphExecDestroy(x);
+    c->gexec[m].clear();
     c->graph_state[m] = 0;
+    for (auto& it : c->titems[m]) hipGraphExecDestroy(it.first);
+    c->titems[m].clear();
+    c->tstate[m] = 0;
   }
 }
 
@@ -802,6 +828,54 @@ int check_finite_host(cfqmc_ctx* c, const double* dptr, long long count) {
   return CFQMC_OK;
 }
 
+// Ends the capture of the current piece of the timing variant (kind -1:
+// untimed launches; 0 / 1: a timed launch), keeps it as a graph unless it is
+// empty, and starts capturing the next piece.
+void cut_piece(cfqmc_ctx* c, int kind) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->s, &g);
+  if (e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    if (!c->seg_fail) { c->seg_fail = "end capture"; c->seg_fail_err = e; }
+  } else {
+    size_t nodes = 0;
+    (void)hipGraphGetNodes(g, nullptr, &nodes);
+    if (nodes > 0) {
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) c->titems[c->seg_m].emplace_back(x, kind);
+      else if (!c->seg_fail) { c->seg_fail = "instantiate"; c->seg_fail_err = e; }
+    }
+    hipGraphDestroy(g);
+  }
+  e = hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    // the launches that follow would run for real: the recording pass is no
+    // longer side-effect free
+    c->seg_broken = true;
+    if (!c->seg_fail) { c->seg_fail = "begin capture"; c->seg_fail_err = e; }
+  }
+}
+
+// A timed launch (kind 0: the wrap's application of channel 2; 1: the
+// Woodbury product's) begins or ends. Launch by launch: HIP events on the
+// stream. While the timing variant of the sweep graph is recorded: the
+// capture is cut so that the timed launch becomes a graph of its own.
+void timing_mark(cfqmc_ctx* c, int kind, bool begin) {
+  if (c->seg_rec) {
+    if (!c->seg_broken) cut_piece(c, begin ? -1 : kind);
+    return;
+  }
+  std::vector<hipEvent_t>& ev = kind ? c->ev2 : c->ev;
+  size_t& used = kind ? c->ev2_used : c->ev_used;
+  if (begin) {
+    hipEventRecord(ev[used], c->s);
+  } else {
+    hipEventRecord(ev[used + 1], c->s);
+    used += 2;
+  }
+}
+
 // One slice move of all chains; t is the 0-based slice.
 void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   const int N = c->N, mixed = c->mixed, mixed_m = c->mixed_m;
@@ -810,11 +884,11 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   const double2* pq = c->PQ + (long long)t * 8 * NN;   // chain 0 of slice t
   // 1. wrap through the channels of slice t, keeping the frames
   const double2* cur = c->G;
-  const bool tm = c->timing && c->ev_used + 2 <= c->ev.size();
+  const bool tm = c->timing && (c->seg_rec || c->ev_used + 2 <= c->ev.size());
   for (int ch = 3; ch >= 0; --ch) {
-    if (tm && ch == 2) hipEventRecord(c->ev[c->ev_used], c->s);
+    if (tm && ch == 2) timing_mark(c, 0, true);
     chan(c, 1, ch, false, pq + ch * 2 * NN, sPQ, cur, c->S1, false, nullptr, mixed);
-    if (tm && ch == 2) { hipEventRecord(c->ev[c->ev_used + 1], c->s); c->ev_used += 2; }
+    if (tm && ch == 2) timing_mark(c, 0, false);
     chan(c, 0, ch, true, pq + ch * 2 * NN, sPQ, c->S1, c->F[ch], false, nullptr, mixed);
     cur = c->F[ch];
   }
@@ -843,11 +917,11 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   double2* y = c->S1;
   double2* y2 = c->S2;
   chan(c, 1, 0, true, pq + 0 * 2 * NN, sPQ, c->F[0], y, true, nullptr, mixed_m);
-  const bool tm2 = c->timing && c->ev2_used + 2 <= c->ev2.size();
+  const bool tm2 = c->timing && (c->seg_rec || c->ev2_used + 2 <= c->ev2.size());
   for (int ch = 1; ch <= 3; ++ch) {
-    if (tm2 && ch == 2) hipEventRecord(c->ev2[c->ev2_used], c->s);
+    if (tm2 && ch == 2) timing_mark(c, 1, true);
     chan(c, 1, ch, true, pq + ch * 2 * NN, sPQ, y, y2, false, nullptr, mixed_m);
-    if (tm2 && ch == 2) { hipEventRecord(c->ev2[c->ev2_used + 1], c->s); c->ev2_used += 2; }
+    if (tm2 && ch == 2) timing_mark(c, 1, false);
     std::swap(y, y2);
   }
   for (int ch = 3; ch >= 1; --ch) {
@@ -971,20 +1045,29 @@ int autotune(cfqmc_ctx* c) {
   float best_c = 1e30f, best_g = 1e30f, best_s = 1e30f;
   int bc = 1, bg = 1, bs = 0;
   const long long NN = c->NN, s4 = 4 * NN;
+  // the best of three timings of four calls each after a warm-up call: a
+  // single timing is too noisy to separate configurations a few percent apart
   auto timeit = [&](auto&& fn) {
-    float ms = 0.f;
+    float best = 1e30f;
     fn();   // warm-up
-    hipEventRecord(e0, c->s);
-    for (int k = 0; k < 8; ++k) fn();
-    hipEventRecord(e1, c->s);
-    hipEventSynchronize(e1);
-    hipEventElapsedTime(&ms, e0, e1);
-    return ms;
+    for (int r = 0; r < 3; ++r) {
+      float ms = 0.f;
+      hipEventRecord(e0, c->s);
+      for (int k = 0; k < 4; ++k) fn();
+      hipEventRecord(e1, c->s);
+      hipEventSynchronize(e1);
+      hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
+    }
+    return best;
   };
   // the FP32 applications keep their FP64 accumulation points (configurations
   // 0..7) unless the precision guard watches every chain's error (then the
   // FP32-accumulating configurations compete as well) or a configuration is
-  // fixed by the caller
+  // fixed by the caller; guarded applications are timed as separate launches
+  // here (every chain in FP32), their launch form is chosen below
+  const int gl0 = c->guard_launch;
+  c->guard_launch = 0;
   for (int cfg = 0; cfg < CFQMC_CHAN_CFGS; ++cfg) {
     if (c->mixed && !c->guard && !chan_cfg_acc64(cfg)) continue;
     c->cfg_chan = cfg;
@@ -1033,6 +1116,27 @@ int autotune(cfqmc_ctx* c) {
   c->cfg_chan64 = bc64;
   c->cfg_gemm = bg;
   c->cfg_small = bs;
+  c->guard_launch = gl0;
+  if (c->guard && !c->guard_pair_only) {
+    // guarded applications: one launch per precision class, or one launch for
+    // both in its two register budgets; timed with every other chain in FP64
+    std::vector<int> sel(c->nch);
+    for (int z = 0; z < c->nch; ++z) sel[z] = z & 1;
+    hipMemcpy(c->sel64, sel.data(), c->nch * sizeof(int), hipMemcpyHostToDevice);
+    float best = 1e30f;
+    int bl = 0;
+    for (int v = 0; v < 3; ++v) {
+      c->guard_launch = v;
+      const float t = timeit([&]() {
+        chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
+        chan(c, 0, 2, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, c->mixed);
+      });
+      if (t < best) { best = t; bl = v; }
+    }
+    c->guard_launch = bl;
+    hipMemsetAsync(c->sel64, 0, c->nch * sizeof(int), c->s);
+    hipStreamSynchronize(c->s);
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return CFQMC_OK;
@@ -1090,6 +1194,10 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   hipGetDevice(&c->dev);
   c->lu_lmax = 8.0;
   if (const char* e = std::getenv("CFQMC_LU_NP_LMAX")) c->lu_lmax = std::atof(e);
+  // testing knob: CFQMC_GUARD_PAIR=1 keeps one launch per precision class
+  c->guard_pair_only = false;
+  if (const char* e = std::getenv("CFQMC_GUARD_PAIR")) c->guard_pair_only = e[0] == '1';
+  c->guard_launch = c->guard_pair_only ? 0 : 1;
   c->timing = false;
   c->ev_used = 0;
   c->sweep_counter = 0;
@@ -1211,8 +1319,10 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
 int cfqmc_destroy(cfqmc_ctx* c) {
   if (!c) return CFQMC_EINVAL;
   hipStreamSynchronize(c->s);
-  for (int m = 0; m < 2; ++m)
-    if (c->graph_state[m] == 1) hipGraphExecDestroy(c->gexec[m]);
+  for (int m = 0; m < 2; ++m) {
+    for (hipGraphExec_t x : c->gexec[m]) hipGraphExecDestroy(x);
+    for (auto& it : c->titems[m]) hipGraphExecDestroy(it.first);
+  }
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
   for (hipEvent_t e : c->ev2) hipEventDestroy(e);
   for (void* q : c->allocs) hipFree(q);
@@ -1451,69 +1561,178 @@ void sweep_end(cfqmc_ctx* c) {
   sweep_end_host(c);
 }
 
-// Kernel timing keeps launches one by one: the timing events must be recorded
-// by the runtime on the stream (events recorded inside a graph are not timed).
+// With kernel timing on, the timing variant runs: the timing events must be
+// recorded by the runtime on the stream (events recorded inside a graph are
+// not timed by this runtime).
 bool graph_usable(const cfqmc_ctx* c) {
-  return c->p.sweep_graph && c->s != nullptr && !c->timing && !cfqmc_debug_sync();
+  return c->p.sweep_graph && c->s != nullptr && !cfqmc_debug_sync();
+}
+
+// Slices per recorded chunk: whole stabilisation blocks, at most about 64
+// slices (a few thousand launches per graph).
+int chunk_slices(const cfqmc_ctx* c) {
+  return std::max(1, 64 / c->nstab) * c->nstab;
 }
 
 // Records the launches of one whole sweep (m = 0: device noise, 1: replayed
-// noise from c->noise) on the context's stream as a graph. Recording runs no
-// kernel; a failure leaves the context on launches one by one.
+// noise from c->noise) on the context's stream as graphs, one per chunk of
+// slices. Recording runs no kernel; a failure leaves the context on launches
+// one by one.
 void record_sweep(cfqmc_ctx* c, int m) {
   c->graph_state[m] = -1;
   const long long blocks0 = c->blocks_in_call;
-  const hipError_t e0 = hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal);
-  if (e0 != hipSuccess) {
-    (void)hipGetLastError();
-    graph_note(c, "begin capture", e0);
-    return;
+  const int S = chunk_slices(c);
+  std::vector<hipGraphExec_t> execs;
+  const char* step = nullptr;
+  hipError_t err = hipSuccess;
+  size_t nodes = 0;
+  for (int t0 = 0; t0 < c->L && !step; t0 += S) {
+    err = hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) { step = "begin capture"; break; }
+    const int t1 = std::min(c->L, t0 + S);
+    for (int t = t0; t < t1; ++t) sweep_slice(c, t, m ? c->noise : nullptr);
+    if (t1 == c->L) sweep_end_dev(c);
+    hipGraph_t g = nullptr;
+    err = hipStreamEndCapture(c->s, &g);
+    if (err != hipSuccess || !g) {
+      if (g) hipGraphDestroy(g);
+      step = "end capture";
+      break;
+    }
+    (void)hipGraphGetNodes(g, nullptr, &nodes);
+    hipGraphExec_t x = nullptr;
+    err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (err != hipSuccess) { step = "instantiate"; break; }
+    execs.push_back(x);
   }
-  for (int t = 0; t < c->L; ++t) sweep_slice(c, t, m ? c->noise : nullptr);
-  sweep_end_dev(c);
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(c->s, &g);
   c->blocks_per_sweep = c->blocks_in_call - blocks0;
   c->blocks_in_call = blocks0;
-  if (e != hipSuccess || !g) {
+  if (step) {
     (void)hipGetLastError();
-    if (g) hipGraphDestroy(g);
-    graph_note(c, "end capture", e);
+    for (hipGraphExec_t x : execs) hipGraphExecDestroy(x);
+    std::fprintf(stderr, "[cfqmc] sweep graph chunk of %d slices, %zu nodes\n", S, nodes);
+    graph_note(c, step, err);
     return;
   }
-  size_t nodes = 0;
-  (void)hipGraphGetNodes(g, nullptr, &nodes);
-  hipGraphExec_t x = nullptr;
-  const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
-  if (e2 != hipSuccess) {
-    (void)hipGetLastError();
-    std::fprintf(stderr, "[cfqmc] sweep graph of %zu nodes\n", nodes);
-    graph_note(c, "instantiate", e2);
-    return;
-  }
-  c->gexec[m] = x;
+  c->gexec[m] = execs;
   c->graph_state[m] = 1;
 }
 
-// Queues one sweep of all chains: as one launch of the recorded graph where
-// the context allows it, else launch by launch. replay: noise from c->noise.
+// Records the timing variant of one sweep (see titems). Recording runs no
+// kernel unless a capture cannot be restarted (then the context needs new
+// fields: the call fails).
+void record_timed_sweep(cfqmc_ctx* c, int m) {
+  c->tstate[m] = -1;
+  const long long blocks0 = c->blocks_in_call;
+  c->seg_fail = nullptr;
+  c->seg_broken = false;
+  c->seg_m = m;
+  hipError_t e = hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    graph_note(c, "begin capture (timed sweep)", e);
+    return;
+  }
+  c->seg_rec = true;
+  for (int t = 0; t < c->L; ++t) sweep_slice(c, t, m ? c->noise : nullptr);
+  sweep_end_dev(c);
+  c->seg_rec = false;
+  if (!c->seg_broken) {
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->s, &g);
+    if (e == hipSuccess && g) {
+      size_t nodes = 0;
+      (void)hipGraphGetNodes(g, nullptr, &nodes);
+      hipGraphExec_t x = nullptr;
+      if (nodes > 0) {
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) c->titems[m].emplace_back(x, -1);
+        else if (!c->seg_fail) { c->seg_fail = "instantiate"; c->seg_fail_err = e; }
+      }
+      hipGraphDestroy(g);
+    } else {
+      if (g) hipGraphDestroy(g);
+      if (!c->seg_fail) { c->seg_fail = "end capture"; c->seg_fail_err = e; }
+    }
+  }
+  c->blocks_per_sweep = c->blocks_in_call - blocks0;
+  c->blocks_in_call = blocks0;
+  if (c->seg_broken) {
+    c->err = "recording the timed sweep graph ran launches: fields must be initialised again";
+    c->launch_failed = true;
+  }
+  if (c->seg_fail) {
+    (void)hipGetLastError();
+    for (auto& it : c->titems[m]) hipGraphExecDestroy(it.first);
+    c->titems[m].clear();
+    graph_note(c, c->seg_fail, c->seg_fail_err);
+    return;
+  }
+  c->tstate[m] = 1;
+}
+
+// Queues one sweep of all chains: as launches of the recorded graphs where the
+// context allows it (with kernel timing on: the timing variant, HIP events
+// around its timed pieces), else launch by launch. replay: noise from c->noise.
 void run_sweep(cfqmc_ctx* c, bool replay) {
   const int m = replay ? 1 : 0;
-  if (graph_usable(c)) {
-    if (c->graph_state[m] == 0) record_sweep(c, m);
-    if (c->graph_state[m] == 1) {
-      const hipError_t e = hipGraphLaunch(c->gexec[m], c->s);
+  if (graph_usable(c) && c->timing) {
+    if (c->tstate[m] == 0) record_timed_sweep(c, m);
+    if (c->launch_failed) return;
+    if (c->tstate[m] == 1) {
+      hipError_t e = hipSuccess;
+      for (auto& it : c->titems[m]) {
+        if (e != hipSuccess) break;
+        if (it.second < 0) {
+          e = hipGraphLaunch(it.first, c->s);
+          continue;
+        }
+        std::vector<hipEvent_t>& ev = it.second ? c->ev2 : c->ev;
+        size_t& used = it.second ? c->ev2_used : c->ev_used;
+        const bool rec = used + 2 <= ev.size();
+        if (rec) hipEventRecord(ev[used], c->s);
+        e = hipGraphLaunch(it.first, c->s);
+        if (rec) {
+          hipEventRecord(ev[used + 1], c->s);
+          used += 2;
+        }
+      }
       if (e == hipSuccess) {
         c->blocks_in_call += c->blocks_per_sweep;
         c->graph_sweeps_in_call++;
         sweep_end_host(c);
         return;
       }
-      (void)hipGetLastError();
+      c->err = std::string("timed sweep graph launch failed: ") + hipGetErrorString(e);
+      graph_note(c, "launch (timed sweep)", e);
+      c->launch_failed = true;
+      sweep_end_host(c);
+      return;
+    }
+  }
+  if (graph_usable(c) && !c->timing) {
+    if (c->graph_state[m] == 0) record_sweep(c, m);
+    if (c->graph_state[m] == 1) {
+      hipError_t e = hipSuccess;
+      for (hipGraphExec_t x : c->gexec[m])
+        if (e == hipSuccess) e = hipGraphLaunch(x, c->s);
+      if (e == hipSuccess) {
+        c->blocks_in_call += c->blocks_per_sweep;
+        c->graph_sweeps_in_call++;
+        sweep_end_host(c);
+        return;
+      }
+      // a chunk that failed to launch leaves the sweep incomplete: an error the
+      // caller sees at the end of the call
+      c->err = std::string("sweep graph launch failed: ") + hipGetErrorString(e);
       graph_note(c, "launch", e);
-      hipGraphExecDestroy(c->gexec[m]);
+      for (hipGraphExec_t x : c->gexec[m]) hipGraphExecDestroy(x);
+      c->gexec[m].clear();
       c->graph_state[m] = -1;
+      c->launch_failed = true;
+      sweep_end_host(c);
+      return;
     }
   }
   for (int t = 0; t < c->L; ++t) sweep_slice(c, t, replay ? c->noise : nullptr);
@@ -1522,6 +1741,13 @@ void run_sweep(cfqmc_ctx* c, bool replay) {
 
 int sweep_collect(cfqmc_ctx* c, cfqmc_stats* stats) {
   const int B = c->nch;
+  if (c->launch_failed) {
+    // the fields and G are no longer a consistent Markov-chain state
+    c->launch_failed = false;
+    c->ready = false;
+    (void)hipStreamSynchronize(c->s);
+    return CFQMC_EHIP;
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   int ef = 0;
@@ -1999,6 +2225,16 @@ int cfqmc_tile_config(const cfqmc_ctx* c, int32_t* chan_cfg, int32_t* gemm_cfg) 
   return CFQMC_OK;
 }
 
+int cfqmc_launch_config(const cfqmc_ctx* c, int32_t* out) {
+  if (!c || !out) return CFQMC_EINVAL;
+  out[0] = c->cfg_chan;
+  out[1] = c->cfg_chan64;
+  out[2] = c->cfg_gemm;
+  out[3] = c->cfg_small;
+  out[4] = c->guard ? c->guard_launch : 0;
+  return CFQMC_OK;
+}
+
 int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable) {
   if (!c) return CFQMC_EINVAL;
   HIPCHK(hipStreamSynchronize(c->s));
@@ -2011,6 +2247,16 @@ int cfqmc_kernel_timing(cfqmc_ctx* c, int32_t enable) {
   c->timing = enable != 0;
   c->ev_used = 0;
   c->ev2_used = 0;
+  // record the timing variant of the sweep now (recording runs no kernel), so
+  // that the first timed sweep does not pay for it
+  if (c->timing && c->ready && graph_usable(c) && c->tstate[0] == 0) {
+    record_timed_sweep(c, 0);
+    if (c->launch_failed) {
+      c->launch_failed = false;
+      c->ready = false;
+      return CFQMC_EHIP;
+    }
+  }
   return CFQMC_OK;
 }
 

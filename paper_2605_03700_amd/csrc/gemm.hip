@@ -561,20 +561,24 @@ CF_DEV double2 rot_out(double2 t0, double2 t1, int v) {
 // 3 is 0 with the three-product slabs (combined in FP64 at each slab).
 // Each thread keeps base pointers to its staging elements; a slab advances
 // them by a constant.
+// LDS bytes of one workgroup's operand tiles.
+template <typename CT, int BM, int BN, int BKC, bool DB>
+constexpr int chan_lds_bytes() {
+  return (int)sizeof(typename cplx_t<CT>::type) * (DB ? 2 : 1) * 2 * BKC *
+         (BM + (sizeof(CT) == 8 ? 2 : 4) + BN + (sizeof(CT) == 8 ? 2 : 4));
+}
+
+// The application for tile (ty, tx) of chain z; smem holds the workgroup's
+// operand tiles (chan_lds_bytes).
 template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
-__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
-chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
+CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned char* smem) {
   typedef typename cplx_t<CT>::type C2;
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
   constexpr int NT = WX * WY * 64;
   constexpr int NS = DB ? 2 : 1;
   constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
-  __shared__ C2 As[NS][2][BKC * LDA];
-  __shared__ C2 Bs[NS][2][BKC * LDB];
-  int z, ty, tx;
-  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
-  // chains of the other precision class are computed by the companion launch
-  if (c.chain_sel && c.chain_sel[z] != c.sel_want) return;
+  C2 (*As)[2][BKC * LDA] = reinterpret_cast<C2 (*)[2][BKC * LDA]>(smem);
+  C2 (*Bs)[2][BKC * LDB] = reinterpret_cast<C2 (*)[2][BKC * LDB]>(smem + sizeof(C2) * NS * 2 * BKC * LDA);
   const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
@@ -808,6 +812,51 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
       }
 }
 
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
+chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
+  __shared__ __align__(16) unsigned char smem[chan_lds_bytes<CT, BM, BN, BKC, DB>()];
+  int z, ty, tx;
+  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  // chains of the other precision class are computed by the companion launch
+  if (c.chain_sel && c.chain_sel[z] != c.sel_want) return;
+  chan_apply_body<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, z, ty, tx, smem);
+}
+
+// Both precision classes of a precision-guarded context in one launch: the
+// workgroups of a chain the guard runs in FP64 (chain_sel[z] = 1) take the FP64
+// path, the others the FP32 correction form; same tile geometry, one LDS
+// buffer sized for the larger of the two.
+template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
+CF_DEV void chan_apply_dual(const ChanArgs& c, int tiles_x, int tiles_y, int nbatch, unsigned char* smem) {
+  int z, ty, tx;
+  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  if (c.chain_sel[z])
+    chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0>(c, z, ty, tx, smem);
+  else
+    chan_apply_body<float, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, z, ty, tx, smem);
+}
+template <int BM, int BN, int BKC, bool DB>
+constexpr int dual_lds_bytes() {
+  return chan_lds_bytes<double, BM, BN, BKC, DB>() > chan_lds_bytes<float, BM, BN, BKC, DB>()
+             ? chan_lds_bytes<double, BM, BN, BKC, DB>()
+             : chan_lds_bytes<float, BM, BN, BKC, DB>();
+}
+// registers as the compiler allocates them (both paths: three waves per SIMD)
+template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
+chan_apply_dual_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
+  __shared__ __align__(16) unsigned char smem[dual_lds_bytes<BM, BN, BKC, DB>()];
+  chan_apply_dual<LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, tiles_x, tiles_y, nbatch, smem);
+}
+// held to four waves per SIMD (128 registers; the compiler spills a few)
+template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64) __attribute__((amdgpu_waves_per_eu(4)))
+chan_apply_dual4_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
+  __shared__ __align__(16) unsigned char smem[dual_lds_bytes<BM, BN, BKC, DB>()];
+  chan_apply_dual<LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, tiles_x, tiles_y, nbatch, smem);
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename CT, int BM, int BN, int WTM, int WTN>
@@ -910,4 +959,53 @@ void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mix
   if (nbatch <= 0) return;
   if (mixed) chan_cfg<float>(c, left, rot, nbatch, cfg, s);
   else chan_cfg<double>(c, left, rot, nbatch, cfg, s);
+}
+
+template <bool LEFT, int ROTK, bool OM, int AM, bool W4>
+static void run_chan_dual(const ChanArgs& c, int nbatch, hipStream_t s) {
+  constexpr int BM = 32, BN = 32;
+  const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
+  const int tx = (cols + BN - 1) / BN, ty = (rows + BM - 1) / BM;
+  const long long T = (long long)tx * ty * nbatch;
+  const int nblk = (int)((T + 7) / 8 * 8);
+  if (W4)
+    hipLaunchKernelGGL((chan_apply_dual4_kernel<LEFT, ROTK, OM, BM, BN, 1, 1, 16, false, AM>), dim3(nblk), dim3(256),
+                       0, s, c, tx, ty, nbatch);
+  else
+    hipLaunchKernelGGL((chan_apply_dual_kernel<LEFT, ROTK, OM, BM, BN, 1, 1, 16, false, AM>), dim3(nblk), dim3(256),
+                       0, s, c, tx, ty, nbatch);
+  cfqmc_post_launch("chan_apply_dual_kernel");
+}
+
+template <int AM, bool W4>
+static void run_chan_dual_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
+  if (left) {
+    if (rot == ROT_X) run_chan_dual<true, ROT_X, false, AM, W4>(c, nbatch, s);
+    else if (rot == ROT_Y) run_chan_dual<true, ROT_Y, false, AM, W4>(c, nbatch, s);
+    else if (c.one_minus) run_chan_dual<true, ROT_NONE, true, AM, W4>(c, nbatch, s);
+    else run_chan_dual<true, ROT_NONE, false, AM, W4>(c, nbatch, s);
+  } else {
+    if (rot == ROT_X) run_chan_dual<false, ROT_X, false, AM, W4>(c, nbatch, s);
+    else if (rot == ROT_Y) run_chan_dual<false, ROT_Y, false, AM, W4>(c, nbatch, s);
+    else run_chan_dual<false, ROT_NONE, false, AM, W4>(c, nbatch, s);
+  }
+}
+
+// Configurations 1 (FP64 accumulation points) and 12 (three-product FP32
+// accumulation) have single-launch forms; every FP64 configuration of their
+// 32 x 32 single-stage tile (1, 8, 12, 14) can join them.
+bool launch_chan_apply_dual(const ChanArgs& c, int left, int rot, int nbatch, int cfg32, int cfg64, int variant,
+                            hipStream_t s) {
+  const bool geo64 = cfg64 == 1 || cfg64 == 8 || cfg64 == 12 || cfg64 == 14;
+  if ((cfg32 != 1 && cfg32 != 12) || !geo64 || !c.chain_sel || variant < 1 || variant > 2) return false;
+  if (nbatch <= 0) return true;
+  const bool w4 = variant == 2;
+  if (cfg32 == 1) {
+    if (w4) run_chan_dual_any<0, true>(c, left, rot, nbatch, s);
+    else run_chan_dual_any<0, false>(c, left, rot, nbatch, s);
+  } else {
+    if (w4) run_chan_dual_any<2, true>(c, left, rot, nbatch, s);
+    else run_chan_dual_any<2, false>(c, left, rot, nbatch, s);
+  }
+  return true;
 }

@@ -58,6 +58,13 @@ struct ChanArgs {
 // FP32 path: does configuration cfg keep an FP64 accumulation point per slab?
 inline bool chan_cfg_acc64(int cfg) { return cfg < 8 || cfg == 14 || cfg == 15 || cfg == 16; }
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
+// One launch for both precision classes of a guarded mixed context
+// (c.chain_sel[z] = 1: FP64, else the FP32 correction form of configuration
+// cfg32). variant 1: registers as allocated (three waves per SIMD); 2: held to
+// four waves per SIMD. false (nothing launched) unless cfg32 is 1 or 12 and
+// cfg64 one of 1, 8, 12, 14 (the same 32 x 32 single-stage tile).
+bool launch_chan_apply_dual(const ChanArgs& c, int left, int rot, int nbatch, int cfg32, int cfg64, int variant,
+                            hipStream_t s);
 // rot: 0 none (channels 0, 3), 1 tau_x (channel 1), 2 tau_y (channel 2)
 void launch_chan_apply(const ChanArgs& c, int left, int rot, int nbatch, int mixed, int cfg, hipStream_t s);
 

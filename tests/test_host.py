@@ -70,6 +70,7 @@ def test_param_struct_layout_and_validation(lib):
     assert L.cfqmc_batch_get(None, 0, ctypes.byref(h), None) == -1
     assert L.cfqmc_batch_sweep_replay(None, 1, None, None) == -1
     assert L.cfqmc_measure_tau_noalloc(None, None, None) == -1
+    assert L.cfqmc_launch_config(None, None) == -1
     out = np.empty(2)
     assert L.cfqmc_green_maxdiff(None, None, 4, 1, None, out.ctypes.data_as(ctypes.c_void_p)) == -1
     assert L.cfqmc_slmc_grad_check(None, None, 1, None, None) == -1
