@@ -15,6 +15,7 @@
 // in FP64; the difference to the updated G is recorded. After the sweep the
 // right stack is rebuilt from the final slices for the next sweep.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -383,7 +384,12 @@ struct cfqmc_ctx {
   // the host records HIP events around it on the stream. Items in launch
   // order; kind -1 untimed launches, 0 the wrap's timed application, 1 the
   // Woodbury product's.
-  std::vector<std::pair<hipGraphExec_t, int>> titems[2];
+  struct TimedItem {
+    hipGraphExec_t x;              // untimed launches (kind -1)
+    int kind;
+    std::function<void()> launch;  // the timed application, launched as such (kind 0, 1)
+  };
+  std::vector<TimedItem> titems[2];
   int tstate[2];
   bool seg_rec;              // recording the timing variant
   int seg_m;                 // of mode seg_m (0 device noise, 1 replayed noise)
@@ -814,7 +820,8 @@ void drop_graphs(cfqmc_ctx* c) {
     for (hipGraphExec_t x : c->gexec[m]) hipGraphExecDestroy(x);
     c->gexec[m].clear();
     c->graph_state[m] = 0;
-    for (auto& it : c->titems[m]) hipGraphExecDestroy(it.first);
+    for (auto& it : c->titems[m])
+      if (it.x) hipGraphExecDestroy(it.x);
     c->titems[m].clear();
     c->tstate[m] = 0;
   }
@@ -828,10 +835,10 @@ int check_finite_host(cfqmc_ctx* c, const double* dptr, long long count) {
   return CFQMC_OK;
 }
 
-// Ends the capture of the current piece of the timing variant (kind -1:
-// untimed launches; 0 / 1: a timed launch), keeps it as a graph unless it is
-// empty, and starts capturing the next piece.
-void cut_piece(cfqmc_ctx* c, int kind) {
+// Ends the capture of the current piece of untimed launches of the timing
+// variant, keeps it as a graph unless it is empty, and starts capturing the
+// next piece.
+void cut_piece(cfqmc_ctx* c) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->s, &g);
   if (e != hipSuccess || !g) {
@@ -843,7 +850,7 @@ void cut_piece(cfqmc_ctx* c, int kind) {
     if (nodes > 0) {
       hipGraphExec_t x = nullptr;
       e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-      if (e == hipSuccess) c->titems[c->seg_m].emplace_back(x, kind);
+      if (e == hipSuccess) c->titems[c->seg_m].push_back({x, -1, nullptr});
       else if (!c->seg_fail) { c->seg_fail = "instantiate"; c->seg_fail_err = e; }
     }
     hipGraphDestroy(g);
@@ -858,22 +865,24 @@ void cut_piece(cfqmc_ctx* c, int kind) {
 }
 
 // A timed launch (kind 0: the wrap's application of channel 2; 1: the
-// Woodbury product's) begins or ends. Launch by launch: HIP events on the
-// stream. While the timing variant of the sweep graph is recorded: the
-// capture is cut so that the timed launch becomes a graph of its own.
-void timing_mark(cfqmc_ctx* c, int kind, bool begin) {
+// Woodbury product's): launch by launch it runs between two HIP events on the
+// stream. While the timing variant of the sweep graph is recorded it is not
+// captured: the capture is cut there and the launch kept as a call, which each
+// replay issues between the events as it would be issued launch by launch.
+void timed_launch(cfqmc_ctx* c, int kind, std::function<void()> fn) {
   if (c->seg_rec) {
-    if (!c->seg_broken) cut_piece(c, begin ? -1 : kind);
+    if (!c->seg_broken) {
+      cut_piece(c);
+      c->titems[c->seg_m].push_back({nullptr, kind, std::move(fn)});
+    }
     return;
   }
   std::vector<hipEvent_t>& ev = kind ? c->ev2 : c->ev;
   size_t& used = kind ? c->ev2_used : c->ev_used;
-  if (begin) {
-    hipEventRecord(ev[used], c->s);
-  } else {
-    hipEventRecord(ev[used + 1], c->s);
-    used += 2;
-  }
+  hipEventRecord(ev[used], c->s);
+  fn();
+  hipEventRecord(ev[used + 1], c->s);
+  used += 2;
 }
 
 // One slice move of all chains; t is the 0-based slice.
@@ -886,9 +895,13 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   const double2* cur = c->G;
   const bool tm = c->timing && (c->seg_rec || c->ev_used + 2 <= c->ev.size());
   for (int ch = 3; ch >= 0; --ch) {
-    if (tm && ch == 2) timing_mark(c, 0, true);
-    chan(c, 1, ch, false, pq + ch * 2 * NN, sPQ, cur, c->S1, false, nullptr, mixed);
-    if (tm && ch == 2) timing_mark(c, 0, false);
+    const double2* pqc = pq + ch * 2 * NN;
+    if (tm && ch == 2)
+      timed_launch(c, 0, [c, ch, pqc, sPQ, cur, mixed]() {
+        chan(c, 1, ch, false, pqc, sPQ, cur, c->S1, false, nullptr, mixed);
+      });
+    else
+      chan(c, 1, ch, false, pqc, sPQ, cur, c->S1, false, nullptr, mixed);
     chan(c, 0, ch, true, pq + ch * 2 * NN, sPQ, c->S1, c->F[ch], false, nullptr, mixed);
     cur = c->F[ch];
   }
@@ -919,9 +932,13 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   chan(c, 1, 0, true, pq + 0 * 2 * NN, sPQ, c->F[0], y, true, nullptr, mixed_m);
   const bool tm2 = c->timing && (c->seg_rec || c->ev2_used + 2 <= c->ev2.size());
   for (int ch = 1; ch <= 3; ++ch) {
-    if (tm2 && ch == 2) timing_mark(c, 1, true);
-    chan(c, 1, ch, true, pq + ch * 2 * NN, sPQ, y, y2, false, nullptr, mixed_m);
-    if (tm2 && ch == 2) timing_mark(c, 1, false);
+    const double2* pqc = pq + ch * 2 * NN;
+    if (tm2 && ch == 2)
+      timed_launch(c, 1, [c, ch, pqc, sPQ, y, y2, mixed_m]() {
+        chan(c, 1, ch, true, pqc, sPQ, y, y2, false, nullptr, mixed_m);
+      });
+    else
+      chan(c, 1, ch, true, pqc, sPQ, y, y2, false, nullptr, mixed_m);
     std::swap(y, y2);
   }
   for (int ch = 3; ch >= 1; --ch) {
@@ -1074,6 +1091,12 @@ int autotune(cfqmc_ctx* c) {
     const float tc = timeit([&]() {
       chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
       chan(c, 0, 2, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, c->mixed);
+      if (!c->mixed) {
+        // an FP64 sweep's applications are mostly left ones (the Woodbury
+        // product, the block products): weight them as in a slice move
+        chan(c, 1, 0, false, c->PQ, (long long)c->L * 8 * c->NN, c->S2, c->S1, false, nullptr, 0);
+        chan(c, 1, 2, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, 0);
+      }
     });
     if (tc < best_c) { best_c = tc; bc = cfg; }
   }
@@ -1321,7 +1344,8 @@ int cfqmc_destroy(cfqmc_ctx* c) {
   hipStreamSynchronize(c->s);
   for (int m = 0; m < 2; ++m) {
     for (hipGraphExec_t x : c->gexec[m]) hipGraphExecDestroy(x);
-    for (auto& it : c->titems[m]) hipGraphExecDestroy(it.first);
+    for (auto& it : c->titems[m])
+      if (it.x) hipGraphExecDestroy(it.x);
   }
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
   for (hipEvent_t e : c->ev2) hipEventDestroy(e);
@@ -1647,7 +1671,7 @@ void record_timed_sweep(cfqmc_ctx* c, int m) {
       hipGraphExec_t x = nullptr;
       if (nodes > 0) {
         e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) c->titems[m].emplace_back(x, -1);
+        if (e == hipSuccess) c->titems[m].push_back({x, -1, nullptr});
         else if (!c->seg_fail) { c->seg_fail = "instantiate"; c->seg_fail_err = e; }
       }
       hipGraphDestroy(g);
@@ -1664,7 +1688,8 @@ void record_timed_sweep(cfqmc_ctx* c, int m) {
   }
   if (c->seg_fail) {
     (void)hipGetLastError();
-    for (auto& it : c->titems[m]) hipGraphExecDestroy(it.first);
+    for (auto& it : c->titems[m])
+      if (it.x) hipGraphExecDestroy(it.x);
     c->titems[m].clear();
     graph_note(c, c->seg_fail, c->seg_fail_err);
     return;
@@ -1684,15 +1709,15 @@ void run_sweep(cfqmc_ctx* c, bool replay) {
       hipError_t e = hipSuccess;
       for (auto& it : c->titems[m]) {
         if (e != hipSuccess) break;
-        if (it.second < 0) {
-          e = hipGraphLaunch(it.first, c->s);
+        if (it.kind < 0) {
+          e = hipGraphLaunch(it.x, c->s);
           continue;
         }
-        std::vector<hipEvent_t>& ev = it.second ? c->ev2 : c->ev;
-        size_t& used = it.second ? c->ev2_used : c->ev_used;
+        std::vector<hipEvent_t>& ev = it.kind ? c->ev2 : c->ev;
+        size_t& used = it.kind ? c->ev2_used : c->ev_used;
         const bool rec = used + 2 <= ev.size();
         if (rec) hipEventRecord(ev[used], c->s);
-        e = hipGraphLaunch(it.first, c->s);
+        it.launch();
         if (rec) {
           hipEventRecord(ev[used + 1], c->s);
           used += 2;
