@@ -38,7 +38,9 @@ PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFM
 # the copy calibration; profiles/chan_apply_traffic_n100_256chains.md), keyed
 # by (n_phi, arithmetic, channel-application configuration)
 TRAFFIC = {(100, "f32", 12): (167544.25 * 2.0 + 160000.0) * 1024 / 256,
-           (100, "f64", 1): (124254.67 * 2.0 + 160000.0) * 1024 / 256}
+           (100, "f64", 1): (124254.67 * 2.0 + 160000.0) * 1024 / 256,
+           # the guarded one-launch form with 69% of the chains in FP64
+           (100, "dual69", 12): (146820.99 * 2.0 + 179712.0) * 1024 / 256}
 
 # Integrated autocorrelation times at the default workload's shape (N_phi = 100,
 # L = 400, dtau = 0.1, u = 1.5, paper cutoff) from one long run, 32 chains x
@@ -330,8 +332,18 @@ def main():
         t64 = TRAFFIC.get((args.n_phi, "f64", 1))
         f64 = out["fp64_guard_frac"] if prec != FP64 else 1.0
         traffic = None
+        lc = g.launch_config()
+        tdual = TRAFFIC.get((args.n_phi, "dual69", lc["chan"]))
+        traffic_basis = ("HBM bytes per chain of the FP32 and the FP64 application (rocprofv3 FETCH_SIZE / "
+                         "WRITE_SIZE, copy-calibrated, profiles/chan_apply_traffic_n100_256chains.md) weighted by "
+                         "the fraction of chains in FP64")
         if prec == FP64 and g.tile_config()[0] == 1 and t64:
             traffic = nper * t64
+        elif prec == MIXED and lc["guard_launch"] > 0 and tdual and abs(f64 - 0.69) < 0.05:
+            traffic = nper * tdual
+            traffic_basis = ("HBM bytes per chain of the guarded one-launch application with 69% of the chains "
+                             "in FP64 (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated, "
+                             "profiles/chan_apply_traffic_n100_256chains.md)")
         elif prec == MIXED and t32 and t64:
             traffic = nper * ((1.0 - f64) * t32 + f64 * t64)
         out["roofline"] = {"bound": "mfma", "kernel": "chan_apply", "achieved": ach,
@@ -341,9 +353,7 @@ def main():
                            "issued_flops_per_launch": k_flops, "issued_tflops": issued,
                            "issued_frac": issued / PEAK[args.precision],
                            "hbm_gbps_at_traffic": traffic / (k_ms * 1e-3) / 1e9 if traffic else None,
-                           "traffic_basis": "HBM bytes per chain of the FP32 and the FP64 application (rocprofv3 "
-                                            "FETCH_SIZE / WRITE_SIZE, copy-calibrated, profiles/chan_apply_traffic_"
-                                            "n100_256chains.md) weighted by the fraction of chains in FP64",
+                           "traffic_basis": traffic_basis,
                            "definition": "achieved = 2 n^3 real flops per chain (an eighth of the wrap's two "
                                          "n x n x n complex products) / mean HIP-event duration of the timed "
                                          "launch; issued_* count the 4 n^3 the launch performs"}

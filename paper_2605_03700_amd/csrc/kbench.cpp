@@ -1,10 +1,15 @@
 // Kernel microbenchmark of the sweep's hot kernels at a given shape, for
 // per-kernel timing and hardware-counter runs (rocprofv3) outside a sweep.
 //
-//   kbench <kernel> [n_phi] [chains] [iters] [cfg]
+//   kbench <kernel> [n_phi] [chains] [iters] [cfg] [variant] [fp64_percent]
 //   kernel: chan32 | chan64   channel application Y = E X (left, tau_y rotation,
 //                             the wrap's timed launch), FP32 correction form or FP64
 //           chan32r | chan64r the right application X E^-1 (tau_x rotation)
+//           chandual          the precision-guarded form of chan32: one launch in
+//                             which the chains flagged FP64 (fp64_percent of them,
+//                             spread evenly) take the FP64 path; cfg the FP32
+//                             configuration (1 or 12), variant 1 or 2 the register
+//                             budget (launch_chan_apply_dual)
 //           lu_np             LU of M = 1 + small (non-pivoted, in place)
 //           rsolve            G' = G M^-1 from that LU
 //           copy              a plain device-to-device copy of 1 GiB (the reference
@@ -66,7 +71,8 @@ double2* upload(const std::vector<double2>& h) {
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|lu_np|rsolve|copy [n_phi] [chains] [iters] [cfg]\n");
+    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|rsolve|copy [n_phi] [chains] "
+                         "[iters] [cfg] [variant] [fp64_percent]\n");
     return 2;
   }
   const std::string k = argv[1];
@@ -88,8 +94,16 @@ int main(int argc, char** argv) {
   const int B = argc > 3 ? std::atoi(argv[3]) : 256;
   const int iters = argc > 4 ? std::atoi(argv[4]) : 20;
   const int cfg = argc > 5 ? std::atoi(argv[5]) : 1;
-  if (N < 1 || N > 140 || B < 1 || B > 512 || iters < 1 || cfg < 0 || cfg >= CFQMC_CHAN_CFGS) {
-    std::fprintf(stderr, "kbench: n_phi 1..140, chains 1..512, iters >= 1, cfg 0..%d\n", CFQMC_CHAN_CFGS - 1);
+  const int variant = argc > 6 ? std::atoi(argv[6]) : 2;
+  const int pct64 = argc > 7 ? std::atoi(argv[7]) : 50;
+  if (N < 1 || N > 140 || B < 1 || B > 512 || iters < 1 || cfg < 0 || cfg >= CFQMC_CHAN_CFGS || variant < 1 ||
+      variant > 2 || pct64 < 0 || pct64 > 100) {
+    std::fprintf(stderr, "kbench: n_phi 1..140, chains 1..512, iters >= 1, cfg 0..%d, variant 1..2, "
+                 "fp64_percent 0..100\n", CFQMC_CHAN_CFGS - 1);
+    return 2;
+  }
+  if (k == "chandual" && cfg != 1 && cfg != 12) {
+    std::fprintf(stderr, "kbench: chandual needs cfg 1 or 12\n");
     return 2;
   }
   const int n = 2 * N;
@@ -102,7 +116,8 @@ int main(int argc, char** argv) {
   const char* what = "";
   std::vector<void*> bufs;
   if (k.rfind("chan", 0) == 0) {
-    const bool mixed = k.find("32") != std::string::npos;
+    const bool dual = k == "chandual";
+    const bool mixed = dual || k.find("32") != std::string::npos;
     const bool right = k.back() == 'r';
     std::vector<double2> hX((size_t)B * 2 * NN);
     fill_random(hX, 2, 0.3 / N);   // entries ~ 0.3 / N: a matrix norm ~ 0.3
@@ -120,10 +135,23 @@ int main(int argc, char** argv) {
     a.X0 = dX; a.X1 = dX + NN; a.ldX = N; a.sX = 2 * NN;
     a.Y = dY; a.ldY = n; a.sY = nn;
     const int left = right ? 0 : 1, rot = right ? 1 : 2;
-    run = [=]() { launch_chan_apply(a, left, rot, B, mixed ? 1 : 0, cfg, s); };
+    if (dual) {
+      // FP64 flags for fp64_percent of the chains, spread evenly over the batch
+      std::vector<int> sel(B);
+      for (int z = 0; z < B; ++z) sel[z] = ((z + 1) * pct64) / 100 - (z * pct64) / 100;
+      int* dsel = nullptr;
+      CK(hipMalloc(&dsel, B * sizeof(int)));
+      CK(hipMemcpy(dsel, sel.data(), B * sizeof(int), hipMemcpyHostToDevice));
+      bufs.push_back(dsel);
+      a.chain_sel = dsel;
+      run = [=]() { launch_chan_apply_dual(a, left, rot, B, cfg, 1, variant, s); };
+    } else {
+      run = [=]() { launch_chan_apply(a, left, rot, B, mixed ? 1 : 0, cfg, s); };
+    }
     algo = 2.0 * (double)n * n * n * B;
     issued = 16.0 * (double)N * N * n * B;
-    what = mixed ? "channel application, FP32 correction form" : "channel application, FP64 (3-product MFMA)";
+    what = dual ? "channel application, guarded (FP32 / FP64 chains in one launch)"
+                : mixed ? "channel application, FP32 correction form" : "channel application, FP64 (3-product MFMA)";
   } else if (k == "lu_np" || k == "rsolve") {
     // M = 1 + 0.05 R: close to the identity, as the Woodbury matrix of a slice move
     std::vector<double2> hA((size_t)B * nn);
@@ -181,8 +209,10 @@ int main(int argc, char** argv) {
   const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / iters;
   CK(hipGetLastError());
   std::printf("{\"kernel\": \"%s\", \"what\": \"%s\", \"n_phi\": %d, \"chains\": %d, \"cfg\": %d, \"iters\": %d, "
+              "\"variant\": %d, \"fp64_percent\": %d, "
               "\"us_per_launch\": %.2f, \"algorithmic_tflops\": %.3f, \"issued_tflops\": %.3f}\n",
-              k.c_str(), what, N, B, cfg, iters, us, algo / us * 1e-6, issued / us * 1e-6);
+              k.c_str(), what, N, B, cfg, iters, k == "chandual" ? variant : 0, k == "chandual" ? pct64 : 0, us,
+              algo / us * 1e-6, issued / us * 1e-6);
   for (void* p : bufs) hipFree(p);
   return 0;
 }
