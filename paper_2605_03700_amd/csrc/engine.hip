@@ -964,9 +964,9 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   // 8. commit
   launch_commit(a, c->nch, c->Fp[0], c->F[0], c->G, nn, nn, c->phip, 4 * c->nq,
                 c->phi + (long long)t * 4 * c->nq, (long long)c->L * 4 * c->nq, 4 * c->nq, c->PQp, sPQp,
-                c->PQ + (long long)t * 8 * NN, sPQ, 8 * NN, c->acc_count, c->s);
-  // precision guard: a chain whose G grew past the threshold finishes the block in FP64
-  if (c->guard) launch_guard_slice(c->G, nn, (int)nn, c->sel64, c->p.guard_gmax, c->nch, c->s);
+                c->PQ + (long long)t * 8 * NN, sPQ, 8 * NN, c->acc_count, c->s,
+                // precision guard: a chain whose G grew past the threshold finishes the block in FP64
+                c->guard ? c->sel64 : nullptr, c->p.guard_gmax);
   // history of this slice
   hipMemcpy2DAsync(c->hist_acc + t, c->L * sizeof(int), c->accept, sizeof(int), sizeof(int), c->nch,
                    hipMemcpyDeviceToDevice, c->s);
@@ -1088,6 +1088,7 @@ int autotune(cfqmc_ctx* c) {
   for (int cfg = 0; cfg < CFQMC_CHAN_CFGS; ++cfg) {
     if (c->mixed && !c->guard && !chan_cfg_acc64(cfg)) continue;
     c->cfg_chan = cfg;
+    if (!c->mixed) c->cfg_chan64 = cfg;   // an FP64 context's applications use cfg_chan64
     const float tc = timeit([&]() {
       chan(c, 1, 1, false, c->PQ, (long long)c->L * 8 * c->NN, c->F[0], c->S1, false, nullptr, c->mixed);
       chan(c, 0, 2, false, c->PQ, (long long)c->L * 8 * c->NN, c->S1, c->S2, false, nullptr, c->mixed);

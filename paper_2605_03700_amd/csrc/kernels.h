@@ -105,9 +105,6 @@ void launch_maxdiff(const double2* X, const double2* Y, int n, long long sX, dou
 // error > err, else 0; gmax_run[z] = max(gmax_run[z], max |G_FP64|).
 void launch_precision_guard(const double* last, int* sel, int* count, double* gmax_run, double gmax, double err,
                             int nbatch, hipStream_t s);
-// Within a block: sel[z] = 1 if the updated G of chain z (n x n = nn entries, stride
-// sG) has an entry of modulus above gmax (sel is never cleared here).
-void launch_guard_slice(const double2* G, long long sG, int nn, int* sel, double gmax, int nbatch, hipStream_t s);
 
 // ---- UDT stabilisation helpers (linalg.hip)
 // Column norms of W (n x n) -> nrm; descending-order permutation perm.
@@ -200,11 +197,13 @@ void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipS
 void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s);
 
 // Metropolis-Hastings decision from the drift kernels' partial sums, then
-// commit of the accepted slice move
+// commit of the accepted slice move. sel (precision guard, or null): set to 1
+// for a chain whose new G has an entry of modulus above gmax (never cleared
+// here).
 void launch_commit(const StepArgs& a, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
                    long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi, int nphi,
                    const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ, long long npq,
-                   int* acc_count, hipStream_t s);
+                   int* acc_count, hipStream_t s, int* sel = nullptr, double gmax = 0.0);
 void launch_eps_update(double* eps, const int* acc_count, int L, double r0, double deps, double emin,
                        double emax, int adapt, int nchain, hipStream_t s);
 // S^i_{q=0} (i=1..5) and m^2 from the spin-block G; out [chain][8]

@@ -1085,26 +1085,6 @@ __global__ void precision_guard_kernel(const double* last, int* sel, int* count,
   gmax_run[z] = fmax(gmax_run[z], gm);
 }
 
-// Inside a block: a chain whose updated G has an entry above gmax switches to
-// FP64 applications for the rest of the block (one workgroup per chain).
-__global__ void __launch_bounds__(256) guard_slice_kernel(const double2* G, long long sG, int nn, int* sel,
-                                                          double gmax) {
-  __shared__ double red[4];
-  const int z = blockIdx.x;
-  double m = 0.0;
-  for (int i = threadIdx.x; i < nn; i += 256) m = fmax(m, cabs2(G[z * sG + i]));
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    if (!(mx <= gmax * gmax)) sel[z] = 1;
-  }
-}
-void launch_guard_slice(const double2* G, long long sG, int nn, int* sel, double gmax, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(guard_slice_kernel, dim3(nbatch), dim3(256), 0, s, G, sG, nn, sel, gmax);
-  cfqmc_post_launch("guard_slice_kernel");
-}
 void launch_precision_guard(const double* last, int* sel, int* count, double* gmax_run, double gmax, double err,
                             int nbatch, hipStream_t s) {
   hipLaunchKernelGGL(precision_guard_kernel, dim3((nbatch + 63) / 64), dim3(64), 0, s, last, sel, count, gmax_run,

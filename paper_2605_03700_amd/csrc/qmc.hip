@@ -397,19 +397,28 @@ void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream
 // Takes the Metropolis-Hastings decision of the slice move (every workgroup of
 // a chain recomputes it; workgroup 0 records it) and commits the accepted move:
 // G <- G', the slice exponentials and fields <- the proposed ones.
+// sel (precision guard, may be null): a workgroup whose part of the new G has
+// an entry with |G|^2 above gmax2 (or not finite) flags its chain for FP64
+// applications; every flagging workgroup writes the same 1.
 __global__ void __launch_bounds__(DR_NT) commit_kernel(StepArgs a, const double2* Gp, const double2* G0, double2* G,
                                                        long long nn, long long sG, const double* phip,
                                                        long long sphip, double* phi_tau, long long sphi, int nphi,
                                                        const double2* PQp, long long sPQp, double2* PQ_tau,
-                                                       long long sPQ, long long npq, int* acc_count) {
+                                                       long long sPQ, long long npq, int* acc_count, int* sel,
+                                                       double gmax2) {
   __shared__ double red[DR_NT / 64];
+  __shared__ double redm[DR_NT / 64];
   __shared__ int acc_s;
   const int z = blockIdx.y;
   const int acc = mh_decide(a, z, blockIdx.x == 0, red, &acc_s);
   const long long tot = nn + npq + nphi;
+  double m2 = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
     if (i < nn) {
-      G[z * sG + i] = acc ? Gp[z * sG + i] : G0[z * sG + i];
+      const double2 v = acc ? Gp[z * sG + i] : G0[z * sG + i];
+      G[z * sG + i] = v;
+      const double a2 = cabs2(v);
+      m2 = (a2 > m2 || a2 != a2) ? a2 : m2;   // a NaN stays (it fails the threshold test below)
     } else if (i < nn + npq) {
       if (acc) PQ_tau[z * sPQ + (i - nn)] = PQp[z * sPQp + (i - nn)];
     } else {
@@ -417,17 +426,30 @@ __global__ void __launch_bounds__(DR_NT) commit_kernel(StepArgs a, const double2
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) acc_count[z] += acc;
+  if (sel) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const double other = __shfl_xor(m2, o, 64);
+      m2 = (other > m2 || other != other) ? other : m2;
+    }
+    if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      bool big = false;
+      for (int w = 0; w < DR_NT / 64; ++w) big = big || !(redm[w] <= gmax2);
+      if (big) sel[z] = 1;
+    }
+  }
 }
 void launch_commit(const StepArgs& a, int nchain, const double2* Gp, const double2* G0, double2* G, long long nn,
                    long long sG, const double* phip, long long sphip, double* phi_tau, long long sphi, int nphi,
                    const double2* PQp, long long sPQp, double2* PQ_tau, long long sPQ, long long npq,
-                   int* acc_count, hipStream_t s) {
+                   int* acc_count, hipStream_t s, int* sel, double gmax) {
   StepArgs b = a;
   b.nchain = nchain;
   const long long tot = nn + npq + nphi;
   dim3 grid((unsigned)std::min<long long>((tot + DR_NT - 1) / DR_NT, 64), nchain);
   hipLaunchKernelGGL(commit_kernel, grid, dim3(DR_NT), 0, s, b, Gp, G0, G, nn, sG, phip, sphip, phi_tau, sphi,
-                     nphi, PQp, sPQp, PQ_tau, sPQ, npq, acc_count); cfqmc_post_launch("commit_kernel");
+                     nphi, PQp, sPQp, PQ_tau, sPQ, npq, acc_count, sel, gmax * gmax); cfqmc_post_launch("commit_kernel");
 }
 
 __global__ void eps_update_kernel(double* eps, int* acc_count, int L, double r0, double deps, double emin,
