@@ -39,8 +39,9 @@ PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFM
 # by (n_phi, arithmetic, channel-application configuration)
 TRAFFIC = {(100, "f32", 12): (167544.25 * 2.0 + 160000.0) * 1024 / 256,
            (100, "f64", 1): (124254.67 * 2.0 + 160000.0) * 1024 / 256,
-           # the guarded one-launch form with 69% of the chains in FP64
-           (100, "dual69", 12): (146820.99 * 2.0 + 179712.0) * 1024 / 256}
+           # the guarded one-launch form with the given percentage of the chains in FP64
+           (100, "dual", 12, 69): (146820.99 * 2.0 + 179712.0) * 1024 / 256,
+           (100, "dual", 12, 94): (140966.43 * 2.0 + 186880.0) * 1024 / 256}
 
 # Integrated autocorrelation times at the default workload's shape (N_phi = 100,
 # L = 400, dtau = 0.1, u = 1.5, paper cutoff) from one long run, 32 chains x
@@ -184,7 +185,7 @@ def main():
     ap.add_argument("--no-tau-correlator", action="store_true",
                     help="skip the imaginary-time correlator pass after the tau_int sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--guard-gmax", type=float, default=1.0,
+    ap.add_argument("--guard-gmax", type=float, default=0.8,
                     help="precision guard: FP64 applications for chains with max|G_FP64| above this")
     ap.add_argument("--guard-err", type=float, default=2.5e-7,
                     help="precision guard: FP64 applications for chains whose last block error exceeded this")
@@ -333,17 +334,20 @@ def main():
         f64 = out["fp64_guard_frac"] if prec != FP64 else 1.0
         traffic = None
         lc = g.launch_config()
-        tdual = TRAFFIC.get((args.n_phi, "dual69", lc["chan"]))
+        # the measured one-launch form whose FP64 share is closest to this run's
+        duals = [(abs(k[3] - 100.0 * f64), k[3], v) for k, v in TRAFFIC.items()
+                 if len(k) == 4 and k[0] == args.n_phi and k[1] == "dual" and k[2] == lc["chan"]]
+        dual_pct, tdual = (min(duals)[1], min(duals)[2]) if duals else (None, None)
         traffic_basis = ("HBM bytes per chain of the FP32 and the FP64 application (rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE, copy-calibrated, profiles/chan_apply_traffic_n100_256chains.md) weighted by "
                          "the fraction of chains in FP64")
         if prec == FP64 and g.tile_config()[0] == 1 and t64:
             traffic = nper * t64
-        elif prec == MIXED and lc["guard_launch"] > 0 and tdual and abs(f64 - 0.69) < 0.05:
+        elif prec == MIXED and lc["guard_launch"] > 0 and tdual and abs(dual_pct - 100.0 * f64) < 5.0:
             traffic = nper * tdual
-            traffic_basis = ("HBM bytes per chain of the guarded one-launch application with 69% of the chains "
+            traffic_basis = ("HBM bytes per chain of the guarded one-launch application with %d%% of the chains "
                              "in FP64 (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated, "
-                             "profiles/chan_apply_traffic_n100_256chains.md)")
+                             "profiles/chan_apply_traffic_n100_256chains.md)" % dual_pct)
         elif prec == MIXED and t32 and t64:
             traffic = nper * ((1.0 - f64) * t32 + f64 * t64)
         out["roofline"] = {"bound": "mfma", "kernel": "chan_apply", "achieved": ach,

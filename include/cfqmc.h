@@ -97,13 +97,15 @@ typedef struct {
   int32_t n_chains;      /* independent chains of this shape, run together in every launch */
   const double* chain_u; /* optional host [n_chains][3] = (u0, uk, un) per chain; NULL: all equal */
   int32_t exp_squarings; /* max scaling-and-squaring steps of the Taylor exponential, 0..16 (default 2) */
-  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..18 fixed channel-application
+  int32_t tile_cfg;      /* -1: autotune tile shapes at create; 0..19 fixed channel-application
                             configuration (GEMMs use min(tile_cfg, 3)). In the FP32 applications
                             0..7 and 14..16 add each 16-deep k slab into FP64 registers (14 with
                             three real products per complex step), 8..13, 17 and 18 accumulate in
                             FP32 over the whole k range (12, 13, 17, 18 with three products); the
                             autotuner picks among the former there unless the precision guard is
-                            on. 15..18 use 8- or 16-wave workgroups of 16 x 16 wave tiles */
+                            on. 15..18 use 8- or 16-wave workgroups of 16 x 16 wave tiles; 19 splits
+                            the two valley products of a 32 x 32 tile over eight waves in FP64 (1 in
+                            the FP32 applications) */
   int32_t dense4n;       /* 0 (only value): the spin-block form n = 2 N_phi. The Fierz channels act as
                             the identity on spin (eq. newmodel), so G_4N = 1_spin (x) G_2N exactly and
                             every output is expanded to 4N; 1 (the un-Fierzed dense 4N coupling, which
@@ -119,14 +121,17 @@ typedef struct {
                             guard_err, and from the next slice to the end of the block once its
                             updated G has an entry above guard_gmax (the FP32 rounding error of G
                             scales with |G|); 0: FP32 for every chain. Ignored in CFQMC_FP64 */
-  double guard_gmax;     /* default 1.0 */
+  double guard_gmax;     /* default 0.8 */
   double guard_err;      /* default 2.5e-7 */
-  int32_t sweep_graph;   /* 1 (default): the launches of one whole sweep are recorded once as a HIP graph
-                            and each later sweep is one graph launch, when the context has a stream of its
-                            own (the groups of a batch; not the null stream); the device-side sweep
+  int32_t sweep_graph;   /* 1 (default): the launches of one whole sweep are recorded once as HIP graphs
+                            (one per chunk of whole stabilisation blocks, at most about 64 slices) and
+                            each later sweep is those graph launches, when the context has a stream of
+                            its own (the groups of a batch; not the null stream); the device-side sweep
                             counter and series index make every replay the next sweep. With kernel
-                            timing on, sweeps run launch by launch (the timing events are recorded on
-                            the stream). 0: launch by launch. Results are identical either way */
+                            timing on, a second recorded form is cut at the timed launches, which run
+                            as ordinary launches between the HIP events. 0: launch by launch. Results
+                            are identical either way; a recording that fails is reported once on
+                            stderr and the context launches one by one */
 } cfqmc_params;
 
 typedef struct {
@@ -147,7 +152,7 @@ typedef struct {
 /* Fill *p with the defaults (N=6, L=40, dtau=0.1, u0=1, uk=un=1, paper cutoff,
  * n_stab=10, FP64, eps0=0.5, r0=0.574, deps=0.1, eps in [1e-3, 5], adapt on,
  * one chain, exp_squarings=2, tile_cfg=-1, dense4n=0, exact_drift=0,
- * precision_guard=1, guard_gmax=1, guard_err=2.5e-7, sweep_graph=1). */
+ * precision_guard=1, guard_gmax=0.8, guard_err=2.5e-7, sweep_graph=1). */
 void cfqmc_default_params(cfqmc_params* p);
 
 /* Create a context: builds the model tables on the host, allocates device

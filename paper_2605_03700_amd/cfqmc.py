@@ -167,7 +167,7 @@ def _ptr(a):
 def make_params(n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                 q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                 eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2, tile_cfg=-1,
-                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7, sweep_graph=1):
+                dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=0.8, guard_err=2.5e-7, sweep_graph=1):
     """Fill a Params structure; returns (params, keep-alive arrays)."""
     lib = load()
     p = Params()
@@ -201,7 +201,7 @@ class CFQMC:
     def __init__(self, n_phi=6, l_tau=40, dtau=0.1, u0=1.0, uk=1.0, un=1.0, q_mode=Q_PAPER, q_max=3.0,
                  q_list=None, n_stab=10, precision=FP64, eps0=0.5, r0=0.574, deps=0.1, eps_min=1e-3,
                  eps_max=5.0, adapt_eps=True, seed=1, n_chains=1, chain_u=None, exp_squarings=2,
-                 tile_cfg=-1, dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=1.0, guard_err=2.5e-7,
+                 tile_cfg=-1, dense4n=0, exact_drift=0, precision_guard=1, guard_gmax=0.8, guard_err=2.5e-7,
                  sweep_graph=1,
                  stream=None, _handle=None):
         lib = load()

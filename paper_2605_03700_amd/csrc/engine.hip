@@ -1183,7 +1183,7 @@ void cfqmc_default_params(cfqmc_params* p) {
   p->adapt_eps = 1; p->seed = 1; p->n_chains = 1;
   p->exp_squarings = 2; p->tile_cfg = -1;
   p->dense4n = 0; p->exact_drift = 0;
-  p->precision_guard = 1; p->guard_gmax = 1.0; p->guard_err = 2.5e-7;
+  p->precision_guard = 1; p->guard_gmax = 0.8; p->guard_err = 2.5e-7;
   p->sweep_graph = 1;
 }
 

@@ -570,18 +570,25 @@ constexpr int chan_lds_bytes() {
 
 // The application for tile (ty, tx) of chain z; smem holds the workgroup's
 // operand tiles (chan_lds_bytes).
+// AM = 4 (FP64 only): the two valley products of a tile are split over twice
+// the waves (one valley each, half the accumulator registers per wave); the
+// rotating channels exchange the two halves through LDS in the epilogue.
 template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
 CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned char* smem) {
   typedef typename cplx_t<CT>::type C2;
+  constexpr bool VS = AM == 4;
+  static_assert(!VS || sizeof(CT) == 8, "valley split: FP64 only");
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
-  constexpr int NT = WX * WY * 64;
+  constexpr int NT = WX * WY * 64 * (VS ? 2 : 1);
   constexpr int NS = DB ? 2 : 1;
   constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
   C2 (*As)[2][BKC * LDA] = reinterpret_cast<C2 (*)[2][BKC * LDA]>(smem);
   C2 (*Bs)[2][BKC * LDB] = reinterpret_cast<C2 (*)[2][BKC * LDB]>(smem + sizeof(C2) * NS * 2 * BKC * LDA);
   const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wm0 = (wid / WX) * 16 * WTM, wn0 = (wid % WX) * 16 * WTN;
+  const int wt = VS ? wid % (WX * WY) : wid;   // wave tile
+  const int va = VS ? wid / (WX * WY) : 0;     // valley of this wave (split form)
+  const int wm0 = (wt / WX) * 16 * WTM, wn0 = (wt % WX) * 16 * WTN;
   constexpr bool CORR = sizeof(CT) == 4;   // correction form in the mixed path
   const int N = c.N;
   const double2* M = c.M + z * c.sM;
@@ -712,8 +719,15 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
   Acc3F<WTM, WTN> acc3f[2];
   acc3f[0].zero();
   acc3f[1].zero();
+  Acc3<WTM, WTN> accv;   // split form: this wave's valley
+  accv.zero();
   const int mr = rows - m0 - wm0, nr = cols - n0 - wn0;
   auto mma = [&](int st, int k0) {
+    if constexpr (VS) {
+      mma_slab3<WTM, WTN, BKC>((const double2*)As[st][va], LDA, (const double2*)Bs[st][va], LDB, wm0, wn0, lane,
+                               accv, mr, nr, N - k0);
+      return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if constexpr (sizeof(CT) == 8) {
@@ -773,6 +787,58 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
       __syncthreads();
     }
   }
+  if constexpr (VS) {
+    Acc<double, WTM, WTN> av;
+    accv.to(av);
+    double2* Y = c.Y + z * c.sY;
+    const double2* Cadd = c.Cadd ? c.Cadd + z * c.sC : nullptr;
+    // rotating channels need both valleys' products for every output element:
+    // exchange through the (no longer needed) operand tiles
+    constexpr int PER = WX * WY * WTM * WTN * 4 * 64;
+    static_assert(4 * PER * (int)sizeof(double) <= chan_lds_bytes<CT, BM, BN, BKC, DB>(), "exchange buffer");
+    double* xr = reinterpret_cast<double*>(smem);
+    double* xi = xr + 2 * PER;
+    if constexpr (ROTK != ROT_NONE) {
+      __syncthreads();
+#pragma unroll
+      for (int si = 0; si < WTM; ++si)
+#pragma unroll
+        for (int sj = 0; sj < WTN; ++sj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (((wt * WTM + si) * WTN + sj) * 4 + r) * 64 + lane;
+            xr[va * PER + e] = av.re[si][sj][r];
+            xi[va * PER + e] = av.im[si][sj][r];
+          }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int si = 0; si < WTM; ++si)
+#pragma unroll
+      for (int sj = 0; sj < WTN; ++sj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = m0 + wm0 + si * 16 + out_row<CT>(lane, r);
+          const int j = n0 + wn0 + sj * 16 + (lane & 15);
+          if (i >= rows || j >= cols) continue;
+          const double2 mine = make_double2(av.re[si][sj][r], av.im[si][sj][r]);
+          double2 y = mine;
+          if constexpr (ROTK != ROT_NONE) {
+            const int e = (((wt * WTM + si) * WTN + sj) * 4 + r) * 64 + lane;
+            const double2 other = make_double2(xr[(1 - va) * PER + e], xi[(1 - va) * PER + e]);
+            y = rot_out<LEFT, ROTK>(va == 0 ? mine : other, va == 0 ? other : mine, va);
+          }
+          const int v = va;
+          const long long off = LEFT ? (long long)(v * N + i) * c.ldY + j : (long long)i * c.ldY + v * N + j;
+          if (Cadd) {
+            const long long offc = LEFT ? (long long)(v * N + i) * c.ldC + j : (long long)i * c.ldC + v * N + j;
+            y = cadd(y, Cadd[offc]);
+          }
+          Y[off] = y;
+          if (c.Y2) c.Y2[z * c.sY + off] = y;
+        }
+    return;
+  }
   if constexpr (sizeof(CT) == 8) {
     acc3[0].to(acc[0]);
     acc3[1].to(acc[1]);
@@ -813,7 +879,7 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
 }
 
 template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
-__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64 * (AM == 4 ? 2 : 1))
 chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   __shared__ __align__(16) unsigned char smem[chan_lds_bytes<CT, BM, BN, BKC, DB>()];
   int z, ty, tx;
@@ -900,7 +966,7 @@ void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t
 
 template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
 static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
-  constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64;
+  constexpr int NT = (BM / (16 * WTM)) * (BN / (16 * WTN)) * 64 * (AM == 4 ? 2 : 1);
   const int rows = LEFT ? c.N : c.n_other, cols = LEFT ? c.n_other : c.N;
   const int tx = (cols + BN - 1) / BN, ty = (rows + BM - 1) / BM;
   const long long T = (long long)tx * ty * nbatch;
@@ -911,8 +977,9 @@ static void run_chan(const ChanArgs& c, int nbatch, hipStream_t s) {
 
 template <typename CT, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM = 0>
 static void run_chan_any(const ChanArgs& c, int left, int rot, int nbatch, hipStream_t s) {
-  // the accumulation modes concern the FP32 path only (FP64 keeps its one form)
-  constexpr int F = sizeof(CT) == 8 ? 0 : AM;
+  // the accumulation modes concern the FP32 path only (FP64 keeps its one form);
+  // AM = 4 is the FP64 valley split (FP32: accumulation mode 0)
+  constexpr int F = sizeof(CT) == 8 ? (AM == 4 ? 4 : 0) : (AM == 4 ? 0 : AM);
   if (left) {
     if (rot == ROT_X) run_chan<CT, true, ROT_X, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
     else if (rot == ROT_Y) run_chan<CT, true, ROT_Y, false, BM, BN, WTM, WTN, BKC, DB, F>(c, nbatch, s);
@@ -951,7 +1018,9 @@ static void chan_cfg(const ChanArgs& c, int left, int rot, int nbatch, int cfg, 
     case 15: run_chan_any<CT, 64, 32, 1, 1, 16, false>(c, left, rot, nbatch, s); break;
     case 16: run_chan_any<CT, 64, 64, 1, 1, 16, false>(c, left, rot, nbatch, s); break;
     case 17: run_chan_any<CT, 64, 32, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
-    default: run_chan_any<CT, 64, 64, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
+    case 18: run_chan_any<CT, 64, 64, 1, 1, 16, false, 2>(c, left, rot, nbatch, s); break;
+    // FP64: the 32 x 32 tile with its two valley products on eight waves
+    default: run_chan_any<CT, 32, 32, 1, 1, 16, false, 4>(c, left, rot, nbatch, s); break;
   }
 }
 
@@ -993,10 +1062,10 @@ static void run_chan_dual_any(const ChanArgs& c, int left, int rot, int nbatch, 
 
 // Configurations 1 (FP64 accumulation points) and 12 (three-product FP32
 // accumulation) have single-launch forms; every FP64 configuration of their
-// 32 x 32 single-stage tile (1, 8, 12, 14) can join them.
+// 32 x 32 single-stage tile (1, 8, 12, 14, 19) can join them.
 bool launch_chan_apply_dual(const ChanArgs& c, int left, int rot, int nbatch, int cfg32, int cfg64, int variant,
                             hipStream_t s) {
-  const bool geo64 = cfg64 == 1 || cfg64 == 8 || cfg64 == 12 || cfg64 == 14;
+  const bool geo64 = cfg64 == 1 || cfg64 == 8 || cfg64 == 12 || cfg64 == 14 || cfg64 == 19;
   if ((cfg32 != 1 && cfg32 != 12) || !geo64 || !c.chain_sel || variant < 1 || variant > 2) return false;
   if (nbatch <= 0) return true;
   const bool w4 = variant == 2;

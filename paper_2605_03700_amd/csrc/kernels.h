@@ -48,15 +48,16 @@ struct ChanArgs {
   int sel_want;
 };
 
-// Tile configurations: zgemm 0..3; chan_apply 0..18 (a fixed tile_cfg applies to both;
+// Tile configurations: zgemm 0..3; chan_apply 0..19 (a fixed tile_cfg applies to both;
 // 8..13, 17 and 18 accumulate the FP32 path in FP32 over the whole k range, 12,
 // 13, 17 and 18 with three real products per complex step; 14 has three-product
-// slabs with an FP64 accumulation point per slab, as 0..7, 15 and 16; 15..18 are
-// 8- and 16-wave workgroups of 16 x 16 wave tiles).
+// slabs with an FP64 accumulation point per slab, as 0..7, 15, 16 and 19; 15..18
+// are 8- and 16-wave workgroups of 16 x 16 wave tiles; 19 splits the two valley
+// products of a 32 x 32 tile over eight waves in FP64 and is 1 in FP32).
 #define CFQMC_GEMM_CFGS 4
-#define CFQMC_CHAN_CFGS 19
+#define CFQMC_CHAN_CFGS 20
 // FP32 path: does configuration cfg keep an FP64 accumulation point per slab?
-inline bool chan_cfg_acc64(int cfg) { return cfg < 8 || cfg == 14 || cfg == 15 || cfg == 16; }
+inline bool chan_cfg_acc64(int cfg) { return cfg < 8 || cfg == 14 || cfg == 15 || cfg == 16 || cfg == 19; }
 void launch_zgemm(const GemmArgs& g, int nbatch, int mixed, int cfg, hipStream_t s);
 // One launch for both precision classes of a guarded mixed context
 // (c.chain_sel[z] = 1: FP64, else the FP32 correction form of configuration

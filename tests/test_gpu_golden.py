@@ -124,11 +124,12 @@ def test_n100_mixed_fp32_accumulating_tiles():
     _replay_context("c3_n100", 1, tile_cfg=10)
 
 
-@pytest.mark.parametrize("precision,tile_cfg", [(0, 16), (1, 18)])
+@pytest.mark.parametrize("precision,tile_cfg", [(0, 16), (1, 18), (0, 19)])
 def test_n100_wide_workgroup_tiles(precision, tile_cfg):
     """The N_phi = 100 replay with the 16-wave 64 x 64 workgroup tiles of the
     channel application (configuration 16 in FP64, 18 in the FP32 three-product
-    form): the FP64 and mixed bars hold."""
+    form) and with the FP64 valley split over eight waves (19): the FP64 and
+    mixed bars hold."""
     _replay_context("c3_n100", precision, tile_cfg=tile_cfg)
 
 

@@ -137,15 +137,16 @@ def test_sweep_replay_parity_mixed(precision):
 @pytest.mark.parametrize("n_phi", [7, 36])
 def test_tile_configurations_agree(n_phi):
     """Every channel-application configuration of the FP64 path (16 x 16 to
-    64 x 64 workgroup tiles, ragged edges at N_phi = 7 and 36): the same accept
-    sequence and G within 1e-12 after a replayed sweep."""
+    64 x 64 workgroup tiles, the valley split over eight waves, ragged edges at
+    N_phi = 7 and 36): the same accept sequence and G within 1e-12 after a
+    replayed sweep."""
     CFQMC = _gpu()
     L = 12
     m = Model(n_phi, L, 0.1, u0=1.0, uk=1.0, un=1.0)
     phi = synth.fields(3, L, m.n_q)
     rp = synth.replay(4, 1, L, m.n_q)
     out = []
-    for cfg in range(19):
+    for cfg in range(20):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg)
         g.init_fields(phi[None])
         g.sweep(1, rp[None])
@@ -173,7 +174,7 @@ def test_mixed_tile_configurations_within_the_bar():
     ref.sweep(1, rp[None])
     G0, acc0 = ref.measure_G(0, L), ref.last_sweep(0)[0].tolist()
     ref.close()
-    for cfg in range(19):
+    for cfg in range(20):
         g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, n_stab=4, eps0=0.4, adapt_eps=False, tile_cfg=cfg, precision=1)
         g.init_fields(phi[None])
         st = g.sweep(1, rp[None])

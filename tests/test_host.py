@@ -46,7 +46,7 @@ def test_param_struct_layout_and_validation(lib):
     assert p.exp_squarings == 2 and p.tile_cfg == -1 and p.n_chains == 1 and p.sweep_graph == 1
     h = ctypes.c_void_p()
     for field, bad in [("n_phi", 0), ("n_phi", 141), ("l_tau", 0), ("dtau", -1.0), ("eps0", 0.0),
-                       ("n_chains", 0), ("precision", 7), ("tile_cfg", 19), ("n_stab", 0),
+                       ("n_chains", 0), ("precision", 7), ("tile_cfg", 20), ("n_stab", 0),
                        ("sweep_graph", 2), ("sweep_graph", -1)]:
         q = cfqmc.Params()
         L.cfqmc_default_params(ctypes.byref(q))
