@@ -27,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "mixed": 157.3, "mixed_all": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
+# what a loop of nothing but independent 16x16x4 MFMAs sustains on one MI355X
+# (kbench mfma, profiles/mfma_sustained_rate.md): the practical ceiling
+SUSTAINED = {"fp64": 49.2, "mixed": 135.5, "mixed_all": 135.5}
 
 # HBM bytes per launch of the timed channel application, FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (KiB, factors from a 1 GiB copy) from rocprofv3 PMC runs of
@@ -361,12 +364,21 @@ def main():
                            "definition": "achieved = 2 n^3 real flops per chain (an eighth of the wrap's two "
                                          "n x n x n complex products) / mean HIP-event duration of the timed "
                                          "launch; issued_* count the 4 n^3 the launch performs"}
+        sus = SUSTAINED[args.precision]
         if prec == MIXED:
             # the timed application runs the guarded chains in FP64: the peak of
             # that mix (harmonic weighting by the FP64 fraction) beside the FP32 one
             pk = 1.0 / ((1.0 - f64) / PEAK["mixed"] + f64 / PEAK["fp64"])
             out["roofline"]["peak_of_precision_mix"] = pk
             out["roofline"]["frac_of_precision_mix"] = ach / pk
+            sus = 1.0 / ((1.0 - f64) / SUSTAINED["mixed"] + f64 / SUSTAINED["fp64"])
+        out["roofline"]["peak_sustained"] = sus
+        out["roofline"]["frac_of_sustained"] = ach / sus
+        out["roofline"]["issued_frac_of_sustained"] = issued / sus
+        out["roofline"]["peak_sustained_basis"] = ("16x16x4 MFMA loop with no memory traffic, FP64 %.1f and FP32 "
+                                                   "%.1f TFLOP/s (kbench mfma, profiles/mfma_sustained_rate.md); "
+                                                   "for a mixed run weighted by the FP64 fraction"
+                                                   % (SUSTAINED["fp64"], SUSTAINED["mixed"]))
     if w_count > 0 and w_ms > 0:
         # the same kernel family in the Woodbury product M = G + B'B^-1(1 - G),
         # FP64 unless every product runs in FP32
@@ -379,6 +391,10 @@ def main():
             "achieved": w_ach, "peak": w_peak, "unit": "TFLOP/s", "frac": w_ach / w_peak,
             "avg_launch_ms": w_ms, "launches_timed": w_count, "flops_per_launch": algo_per_launch,
             "issued_flops_per_launch": w_flops, "issued_tflops": w_iss, "issued_frac": w_iss / w_peak}
+        w_sus = SUSTAINED["mixed_all"] if args.precision == "mixed_all" else SUSTAINED["fp64"]
+        out["roofline_woodbury_application"]["peak_sustained"] = w_sus
+        out["roofline_woodbury_application"]["frac_of_sustained"] = w_ach / w_sus
+        out["roofline_woodbury_application"]["issued_frac_of_sustained"] = w_iss / w_sus
     if prec != FP64 and not args.no_fp64_compare:
         # the same chains with every product in FP64, right after the timed mixed
         # sweeps (one context of this size at a time fits in HBM): the FP64

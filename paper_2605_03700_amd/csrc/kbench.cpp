@@ -14,6 +14,10 @@
 //           rsolve            G' = G M^-1 from that LU
 //           copy              a plain device-to-device copy of 1 GiB (the reference
 //                             for scaling the FETCH_SIZE / WRITE_SIZE counters)
+//           mfma              the sustained rate of the 16 x 16 x 4 MFMA in FP64 and
+//                             FP32: waves of six independent accumulator chains and
+//                             no memory traffic but one store per lane (the ceiling
+//                             the MFMA-bound kernels can approach on this chip)
 //
 // Inputs are seeded random matrices of the sweep's shapes: M (n x n, n =
 // 2 n_phi, entries O(1)), the orbital blocks X = 1 + A with ||A|| ~ 0.3 (the
@@ -67,15 +71,84 @@ double2* upload(const std::vector<double2>& h) {
   return d;
 }
 
+// Six independent accumulator chains per wave, `iters` rounds; the operands
+// stay in registers. One store per lane keeps the chains live.
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) mfma_rate64(double* out, int iters, double x) {
+  mf64x4 acc[6];
+  for (int i = 0; i < 6; ++i) acc[i] = mf64x4{0.0, 0.0, 0.0, 0.0};
+  const double a = x + threadIdx.x * 1e-9, b = x - threadIdx.x * 1e-9;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+  }
+  double s = 0.0;
+  for (int i = 0; i < 6; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+__global__ void __launch_bounds__(256) mfma_rate32(float* out, int iters, float x) {
+  mf32x4 acc[6];
+  for (int i = 0; i < 6; ++i) acc[i] = mf32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const float a = x + threadIdx.x * 1e-6f, b = x - threadIdx.x * 1e-6f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
+  }
+  float s = 0.0f;
+  for (int i = 0; i < 6; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// 4 and 8 four-wave workgroups per CU (4 and 8 waves per SIMD), FP64 then FP32;
+// five timed launches each between HIP events after one untimed launch.
+int mfma_rates() {
+  int cus = 0;
+  CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+  const int iters = 4000, maxb = cus * 8;
+  void* out = nullptr;
+  CK(hipMalloc(&out, (size_t)maxb * 256 * sizeof(double)));
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  for (int prec = 0; prec < 2; ++prec) {
+    for (int per_cu : {4, 8}) {
+      const int nb = cus * per_cu;
+      auto run = [&]() {
+        if (prec == 0) hipLaunchKernelGGL(mfma_rate64, dim3(nb), dim3(256), 0, nullptr, (double*)out, iters, 1.0);
+        else hipLaunchKernelGGL(mfma_rate32, dim3(nb), dim3(256), 0, nullptr, (float*)out, iters, 1.0f);
+      };
+      run();
+      CK(hipDeviceSynchronize());
+      CK(hipEventRecord(e0, nullptr));
+      for (int r = 0; r < 5; ++r) run();
+      CK(hipEventRecord(e1, nullptr));
+      CK(hipEventSynchronize(e1));
+      CK(hipGetLastError());
+      float ms = 0.0f;
+      CK(hipEventElapsedTime(&ms, e0, e1));
+      const double flops = 5.0 * nb * 4.0 * iters * 6.0 * (16.0 * 16.0 * 4.0 * 2.0);
+      std::printf("{\"kernel\": \"mfma\", \"what\": \"%s 16x16x4, 6 chains per wave\", \"cus\": %d, "
+                  "\"waves_per_simd\": %d, \"us_per_launch\": %.1f, \"tflops\": %.2f}\n",
+                  prec == 0 ? "f64" : "f32", cus, per_cu, ms * 1e3 / 5, flops / (ms * 1e-3) * 1e-12);
+    }
+  }
+  CK(hipEventDestroy(e0));
+  CK(hipEventDestroy(e1));
+  CK(hipFree(out));
+  return 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|rsolve|copy [n_phi] [chains] "
+    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|rsolve|copy|mfma [n_phi] [chains] "
                          "[iters] [cfg] [variant] [fp64_percent]\n");
     return 2;
   }
   const std::string k = argv[1];
+  if (k == "mfma") return mfma_rates();
   if (k == "copy") {
     const size_t bytes = (size_t)1 << 30;
     void *a = nullptr, *b = nullptr;
