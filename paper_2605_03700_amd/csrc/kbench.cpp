@@ -15,9 +15,10 @@
 //           copy              a plain device-to-device copy of 1 GiB (the reference
 //                             for scaling the FETCH_SIZE / WRITE_SIZE counters)
 //           mfma              the sustained rate of the 16 x 16 x 4 MFMA in FP64 and
-//                             FP32: waves of six independent accumulator chains and
-//                             no memory traffic but one store per lane (the ceiling
-//                             the MFMA-bound kernels can approach on this chip)
+//                             FP32 and of the FP64 4 x 4 x 4 four-block MFMA: waves
+//                             of six independent accumulator chains and no memory
+//                             traffic but one store per lane (the ceiling the
+//                             MFMA-bound kernels can approach on this chip)
 //
 // Inputs are seeded random matrices of the sweep's shapes: M (n x n, n =
 // 2 n_phi, entries O(1)), the orbital blocks X = 1 + A with ||A|| ~ 0.3 (the
@@ -87,6 +88,18 @@ __global__ void __launch_bounds__(256) mfma_rate64(double* out, int iters, doubl
   for (int i = 0; i < 6; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
   out[blockIdx.x * 256 + threadIdx.x] = s;
 }
+__global__ void __launch_bounds__(256) mfma_rate64q(double* out, int iters, double x) {
+  double acc[6];
+  for (int i = 0; i < 6; ++i) acc[i] = 0.0;
+  const double a = x + threadIdx.x * 1e-9, b = x - threadIdx.x * 1e-9;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[i], 0, 0, 0);
+  }
+  double s = 0.0;
+  for (int i = 0; i < 6; ++i) s += acc[i];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
 __global__ void __launch_bounds__(256) mfma_rate32(float* out, int iters, float x) {
   mf32x4 acc[6];
   for (int i = 0; i < 6; ++i) acc[i] = mf32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -100,8 +113,9 @@ __global__ void __launch_bounds__(256) mfma_rate32(float* out, int iters, float 
   out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
-// 4 and 8 four-wave workgroups per CU (4 and 8 waves per SIMD), FP64 then FP32;
-// five timed launches each between HIP events after one untimed launch.
+// 4 and 8 four-wave workgroups per CU (4 and 8 waves per SIMD): FP64 16x16x4,
+// FP32 16x16x4, FP64 4x4x4 (four blocks); five timed launches each between HIP
+// events after one untimed launch.
 int mfma_rates() {
   int cus = 0;
   CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
@@ -111,12 +125,13 @@ int mfma_rates() {
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  for (int prec = 0; prec < 2; ++prec) {
+  for (int prec = 0; prec < 3; ++prec) {
     for (int per_cu : {4, 8}) {
       const int nb = cus * per_cu;
       auto run = [&]() {
         if (prec == 0) hipLaunchKernelGGL(mfma_rate64, dim3(nb), dim3(256), 0, nullptr, (double*)out, iters, 1.0);
-        else hipLaunchKernelGGL(mfma_rate32, dim3(nb), dim3(256), 0, nullptr, (float*)out, iters, 1.0f);
+        else if (prec == 1) hipLaunchKernelGGL(mfma_rate32, dim3(nb), dim3(256), 0, nullptr, (float*)out, iters, 1.0f);
+        else hipLaunchKernelGGL(mfma_rate64q, dim3(nb), dim3(256), 0, nullptr, (double*)out, iters, 1.0);
       };
       run();
       CK(hipDeviceSynchronize());
@@ -127,10 +142,12 @@ int mfma_rates() {
       CK(hipGetLastError());
       float ms = 0.0f;
       CK(hipEventElapsedTime(&ms, e0, e1));
-      const double flops = 5.0 * nb * 4.0 * iters * 6.0 * (16.0 * 16.0 * 4.0 * 2.0);
-      std::printf("{\"kernel\": \"mfma\", \"what\": \"%s 16x16x4, 6 chains per wave\", \"cus\": %d, "
+      const double per_instr = prec == 2 ? 4.0 * 4.0 * 4.0 * 4.0 * 2.0 : 16.0 * 16.0 * 4.0 * 2.0;
+      const double flops = 5.0 * nb * 4.0 * iters * 6.0 * per_instr;
+      std::printf("{\"kernel\": \"mfma\", \"what\": \"%s, 6 chains per wave\", \"cus\": %d, "
                   "\"waves_per_simd\": %d, \"us_per_launch\": %.1f, \"tflops\": %.2f}\n",
-                  prec == 0 ? "f64" : "f32", cus, per_cu, ms * 1e3 / 5, flops / (ms * 1e-3) * 1e-12);
+                  prec == 0 ? "f64 16x16x4" : prec == 1 ? "f32 16x16x4" : "f64 4x4x4 4 blocks", cus, per_cu,
+                  ms * 1e3 / 5, flops / (ms * 1e-3) * 1e-12);
     }
   }
   CK(hipEventDestroy(e0));
