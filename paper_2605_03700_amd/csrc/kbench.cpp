@@ -11,6 +11,7 @@
 //                             configuration (1 or 12), variant 1 or 2 the register
 //                             budget (launch_chan_apply_dual)
 //           lu_np             LU of M = 1 + small (non-pivoted, in place)
+//           lu                the same matrices by the partially pivoted LU
 //           rsolve            G' = G M^-1 from that LU
 //           copy              a plain device-to-device copy of 1 GiB (the reference
 //                             for scaling the FETCH_SIZE / WRITE_SIZE counters)
@@ -160,7 +161,7 @@ int mfma_rates() {
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|rsolve|copy|mfma [n_phi] [chains] "
+    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|lu|rsolve|copy|mfma [n_phi] [chains] "
                          "[iters] [cfg] [variant] [fp64_percent]\n");
     return 2;
   }
@@ -242,7 +243,7 @@ int main(int argc, char** argv) {
     issued = 16.0 * (double)N * N * n * B;
     what = dual ? "channel application, guarded (FP32 / FP64 chains in one launch)"
                 : mixed ? "channel application, FP32 correction form" : "channel application, FP64 (3-product MFMA)";
-  } else if (k == "lu_np" || k == "rsolve") {
+  } else if (k == "lu_np" || k == "lu" || k == "rsolve") {
     // M = 1 + 0.05 R: close to the identity, as the Woodbury matrix of a slice move
     std::vector<double2> hA((size_t)B * nn);
     fill_random(hA, 3, 0.05 / std::sqrt((double)n));
@@ -267,6 +268,14 @@ int main(int argc, char** argv) {
       algo = 8.0 / 3.0 * (double)n * n * n * B;
       issued = algo;
       what = "non-pivoted LU (plus the restoring copy)";
+    } else if (k == "lu") {
+      run = [=]() {
+        launch_copy(dA0, dA, nn, nn, nn, B, s);
+        launch_lu(dA, n, n, nn, dpiv, n, dld, 1, B, s, nullptr, nullptr);
+      };
+      algo = 8.0 / 3.0 * (double)n * n * n * B;
+      issued = algo;
+      what = "partially pivoted LU (plus the restoring copy)";
     } else {
       launch_lu_np(dA, n, n, nn, dpiv, n, dld, dflag, 8.0, B, s);
       double2* dG = upload(hM);
