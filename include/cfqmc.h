@@ -71,8 +71,11 @@ enum {
 enum { CFQMC_Q_PAPER = 0, CFQMC_Q_RADIUS = 1, CFQMC_Q_BZ = 2, CFQMC_Q_LIST = 3, CFQMC_Q_SPHERE = 4 };
 /* Precision of the slice work. FP64: everything in FP64. MIXED: the wraps and
  * the drift frames in complex FP32 on MFMA with FP64 accumulation (FP64 master
- * G), the Woodbury product M in FP64. MIXED_ALL: M in FP32 as well. LU,
- * G' = G M^-1, exponentials, stabilisation and recomputation stay FP64. */
+ * G), the Woodbury product M in FP64. MIXED_ALL: M and the rank-k update
+ * G' = G M^-1 in FP32 as well (the solve's block products in FP32, an FP64
+ * accumulation point per 16-deep step). The LU of M, the exponentials,
+ * stabilisation and recomputation stay FP64. With the precision guard on, a
+ * chain it moves to FP64 runs all of these in FP64. */
 enum { CFQMC_FP64 = 0, CFQMC_MIXED = 1, CFQMC_MIXED_ALL = 2 };
 
 typedef struct cfqmc_ctx cfqmc_ctx;

@@ -951,9 +951,10 @@ void slice_step(cfqmc_ctx* c, int t, const double* noise_dev) {
   //    are refactorised with partial pivoting from the saved copy.
   launch_lu_np(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, c->lu_flag, c->lu_lmax, c->nch, c->s);
   launch_lu(c->Mw, c->n, c->n, nn, c->ipiv, c->n, c->lndet, 1, c->nch, c->s, c->lu_flag, c->Mb);
-  // 6. G' = G_0 M^{-1}
+  // 6. G' = G_0 M^{-1} (MIXED_ALL: FP32 block products for the chains the
+  //    guard leaves in FP32)
   launch_rsolve(c->F[0], c->n, nn, c->Fp[0], c->n, nn, c->Mw, c->n, nn, c->ipiv, c->n, c->n, 0, c->nch, c->s,
-                c->rs_ws);
+                c->rs_ws, mixed_m, c->guard ? c->sel64 : nullptr);
   // 7. frames of G' for the drift at phi'
   for (int ch = 0; ch < 3; ++ch) {
     chan(c, 1, ch, true, c->PQp + ch * 2 * NN, sPQp, c->Fp[ch], c->S1, false, nullptr, mixed);

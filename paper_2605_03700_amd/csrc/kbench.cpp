@@ -13,6 +13,7 @@
 //           lu_np             LU of M = 1 + small (non-pivoted, in place)
 //           lu                the same matrices by the partially pivoted LU
 //           rsolve            G' = G M^-1 from that LU
+//           rsolve32          the same with FP32 block products (FP64 accumulation)
 //           copy              a plain device-to-device copy of 1 GiB (the reference
 //                             for scaling the FETCH_SIZE / WRITE_SIZE counters)
 //           mfma              the sustained rate of the 16 x 16 x 4 MFMA in FP64 and
@@ -161,7 +162,7 @@ int mfma_rates() {
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|lu|rsolve|copy|mfma [n_phi] [chains] "
+    std::fprintf(stderr, "usage: kbench chan32|chan64|chan32r|chan64r|chandual|lu_np|lu|rsolve|rsolve32|copy|mfma [n_phi] [chains] "
                          "[iters] [cfg] [variant] [fp64_percent]\n");
     return 2;
   }
@@ -243,7 +244,7 @@ int main(int argc, char** argv) {
     issued = 16.0 * (double)N * N * n * B;
     what = dual ? "channel application, guarded (FP32 / FP64 chains in one launch)"
                 : mixed ? "channel application, FP32 correction form" : "channel application, FP64 (3-product MFMA)";
-  } else if (k == "lu_np" || k == "lu" || k == "rsolve") {
+  } else if (k == "lu_np" || k == "lu" || k == "rsolve" || k == "rsolve32") {
     // M = 1 + 0.05 R: close to the identity, as the Woodbury matrix of a slice move
     std::vector<double2> hA((size_t)B * nn);
     fill_random(hA, 3, 0.05 / std::sqrt((double)n));
@@ -285,10 +286,11 @@ int main(int argc, char** argv) {
       bufs.push_back(dG);
       bufs.push_back(dY);
       bufs.push_back(ws);
-      run = [=]() { launch_rsolve(dG, n, nn, dY, n, nn, dA, n, nn, dpiv, n, n, 0, B, s, ws); };
+      const int m32 = k == "rsolve32" ? 1 : 0;
+      run = [=]() { launch_rsolve(dG, n, nn, dY, n, nn, dA, n, nn, dpiv, n, n, 0, B, s, ws, m32, nullptr); };
       algo = 8.0 * (double)n * n * n * B;
       issued = algo;
-      what = "right solve G M^-1 (two triangular solves)";
+      what = m32 ? "right solve G M^-1, FP32 block products" : "right solve G M^-1 (two triangular solves)";
     }
   } else {
     std::fprintf(stderr, "kbench: unknown kernel %s\n", k.c_str());

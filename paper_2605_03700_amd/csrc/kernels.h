@@ -80,9 +80,12 @@ void launch_lu(double2* A, int n, int lda, long long sA, int* ipiv, int sP, doub
 void launch_lu_np(double2* A, int n, int lda, long long sA, int* ipiv, int sP, double2* logdet, int* flag,
                   double lmax_allowed, int nbatch, hipStream_t s);
 // X <- X * A^{-1} with A = P^T L U from launch_lu. upper_only: X <- X U^{-1}.
+// mixed: the block products in FP32 with an FP64 accumulation point per
+// 16-deep step, for every chain or, with sel64, for the chains with
+// sel64[z] == 0 (the others in FP64).
 void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY,
                    const double2* LU, int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only,
-                   int nbatch, hipStream_t s, double2* work);
+                   int nbatch, hipStream_t s, double2* work, int mixed = 0, const int* sel64 = nullptr);
 // Workspace of launch_rsolve (inverted diagonal blocks), in double2 per batch entry.
 inline long long rsolve_work_size(int n) { return (long long)((n + 15) / 16) * 512; }
 void launch_set_identity(double2* A, int n, int lda, long long sA, int nbatch, hipStream_t s);

@@ -820,12 +820,19 @@ __global__ void __launch_bounds__(256) tri_inv_kernel(const double2* LUall, int 
 // tiles it owns that are not solved yet. The published block is double-buffered;
 // the owner's layout change goes through one LDS tile (one owner per step, and
 // the barrier separates consecutive owners).
-template <int NW, int MAXT>
+// CT = float (the rank-k update in FP32): the operands are rounded to FP32 as
+// they enter the MFMAs, each 16-deep step's product is formed in FP32 and
+// subtracted from the FP64 right-hand-side tile (an FP64 accumulation point per
+// step); the tile then follows the FP32 instruction's result layout. sel: only
+// the chains with sel[z] == want (the precision guard's classes), else all.
+template <int NW, int MAXT, typename CT>
 __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall, int ldx, long long sX,
                                                             double2* Yall, int ldy, long long sY,
                                                             const double2* LUall, int ldlu, long long sLU,
                                                             const int* ipiv_all, int sP, int n, int upper_only,
-                                                            const double2* inv_all, int nbatch) {
+                                                            const double2* inv_all, int nbatch, const int* sel,
+                                                            int want) {
+  typedef Mfma<CT> MF;
   constexpr int NT = NW * 64;
   __shared__ double2 Tb[2][16][17];        // solved block of the step
   __shared__ double2 Tw[16][17];           // owner's layout change
@@ -834,6 +841,7 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
   const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= T) return;
   const int z = t / nrb;
+  if (sel && sel[z] != want) return;
   const int nJ = (n + 15) / 16;
   const double2* X = Xall + z * sX;
   double2* Yo = Yall + z * sY;
@@ -852,7 +860,7 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
     const int tc = wid + NW * i;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = Mfma<double>::row(lane, q), c = 16 * tc + il;
+      const int r = MF::row(lane, q), c = 16 * tc + il;
       const bool ok = tc < nJ && r < nr && c < n;
       const double2 v = X[ok ? (long long)(r0 + r) * ldx + c : 0];
       are[i][q] = ok ? v.x : 0.0;
@@ -893,22 +901,41 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
         for (int i = 0; i < MAXT; ++i)
           if (i == io)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Tw[Mfma<double>::row(lane, q)][il] = make_double2(are[i][q], aim[i][q]);
+            for (int q = 0; q < 4; ++q) Tw[MF::row(lane, q)][il] = make_double2(are[i][q], aim[i][q]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        d4v zr = Mfma<double>::zero(), zi = Mfma<double>::zero();
+        d4v zr, zi;
+        if constexpr (sizeof(CT) == 8) {
+          zr = Mfma<double>::zero();
+          zi = Mfma<double>::zero();
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          const double2 a = Tw[il][4 * s4 + kl], b = bi[s4];
-          zr = Mfma<double>::mma(a.x, b.x, zr);
-          zr = Mfma<double>::mma(-a.y, b.y, zr);
-          zi = Mfma<double>::mma(a.x, b.y, zi);
-          zi = Mfma<double>::mma(a.y, b.x, zi);
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const double2 a = Tw[il][4 * s4 + kl], b = bi[s4];
+            zr = Mfma<double>::mma(a.x, b.x, zr);
+            zr = Mfma<double>::mma(-a.y, b.y, zr);
+            zi = Mfma<double>::mma(a.x, b.y, zi);
+            zi = Mfma<double>::mma(a.y, b.x, zi);
+          }
+        } else {
+          f4v zr32 = Mfma<float>::zero(), zi32 = Mfma<float>::zero();
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const float2 a = to_ct<float>(Tw[il][4 * s4 + kl]), b = to_ct<float>(bi[s4]);
+            zr32 = Mfma<float>::mma(a.x, b.x, zr32);
+            zr32 = Mfma<float>::mma(-a.y, b.y, zr32);
+            zi32 = Mfma<float>::mma(a.x, b.y, zi32);
+            zi32 = Mfma<float>::mma(a.y, b.x, zi32);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            zr[q] = zr32[q];
+            zi[q] = zi32[q];
+          }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int r = Mfma<double>::row(lane, q);
+          const int r = MF::row(lane, q);
           const double2 v = make_double2(zr[q], zi[q]);
           Tb[buf][r][il] = v;
           // the last phase's solved block is final: columns perm[c0 + il] of the output
@@ -933,13 +960,30 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
         const int tc = wid + NW * i;
         const bool upd = phase == 0 ? (tc > J && tc < nJ) : (tc < J);
         if (upd) {
+          if constexpr (sizeof(CT) == 8) {
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            const double2 a = av[s4], b = bb[i][s4];
-            are[i] = Mfma<double>::mma(-a.x, b.x, are[i]);
-            are[i] = Mfma<double>::mma(a.y, b.y, are[i]);
-            aim[i] = Mfma<double>::mma(-a.x, b.y, aim[i]);
-            aim[i] = Mfma<double>::mma(-a.y, b.x, aim[i]);
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const double2 a = av[s4], b = bb[i][s4];
+              are[i] = Mfma<double>::mma(-a.x, b.x, are[i]);
+              are[i] = Mfma<double>::mma(a.y, b.y, are[i]);
+              aim[i] = Mfma<double>::mma(-a.x, b.y, aim[i]);
+              aim[i] = Mfma<double>::mma(-a.y, b.x, aim[i]);
+            }
+          } else {
+            f4v pr = Mfma<float>::zero(), pi = Mfma<float>::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const float2 a = to_ct<float>(av[s4]), b = to_ct<float>(bb[i][s4]);
+              pr = Mfma<float>::mma(a.x, b.x, pr);
+              pr = Mfma<float>::mma(-a.y, b.y, pr);
+              pi = Mfma<float>::mma(a.x, b.y, pi);
+              pi = Mfma<float>::mma(a.y, b.x, pi);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              are[i][q] -= pr[q];
+              aim[i][q] -= pi[q];
+            }
           }
         }
       }
@@ -947,25 +991,42 @@ __global__ void __launch_bounds__(NW * 64) rsolve_rl_kernel(const double2* Xall,
   }
 }
 
+template <typename CT>
+static void run_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY, const double2* LU,
+                       int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only, int nbatch,
+                       hipStream_t s, const double2* inv, const int* sel, int want) {
+  const int nrb = (n + RS_ROWS - 1) / RS_ROWS;
+  const int nblk = (int)(((long long)nrb * nbatch + 7) / 8 * 8);
+  // eight waves, each owning at most ceil(nJ / 8) column tiles (2 for n <= 256)
+  if (n <= 256)
+    hipLaunchKernelGGL((rsolve_rl_kernel<8, 2, CT>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu,
+                       sLU, ipiv, sP, n, upper_only, inv, nbatch, sel, want);
+  else
+    hipLaunchKernelGGL((rsolve_rl_kernel<8, 3, CT>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu,
+                       sLU, ipiv, sP, n, upper_only, inv, nbatch, sel, want);
+  cfqmc_post_launch("rsolve_rl_kernel");
+}
+
 void launch_rsolve(const double2* X, int ldx, long long sX, double2* Y, int ldy, long long sY, const double2* LU,
                    int ldlu, long long sLU, const int* ipiv, int sP, int n, int upper_only, int nbatch,
-                   hipStream_t s, double2* work) {
+                   hipStream_t s, double2* work, int mixed, const int* sel64) {
   if (!work || n > LU_MAXN) {
     std::fprintf(stderr, "rsolve: workspace missing or n = %d above %d\n", n, LU_MAXN);
     std::abort();
   }
-  const int nrb = (n + RS_ROWS - 1) / RS_ROWS, nJ = (n + 15) / 16;
-  const int nblk = (int)(((long long)nrb * nbatch + 7) / 8 * 8);
+  const int nJ = (n + 15) / 16;
   hipLaunchKernelGGL(tri_inv_kernel, dim3(nJ, nbatch), dim3(256), 0, s, LU, ldlu, sLU, ipiv, sP, n, upper_only, work);
   cfqmc_post_launch("tri_inv_kernel");
-  // eight waves, each owning at most ceil(nJ / 8) column tiles (2 for n <= 256)
-  if (n <= 256)
-    hipLaunchKernelGGL((rsolve_rl_kernel<8, 2>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
-                       ipiv, sP, n, upper_only, (const double2*)work, nbatch);
-  else
-    hipLaunchKernelGGL((rsolve_rl_kernel<8, 3>), dim3(nblk), dim3(512), 0, s, X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU,
-                       ipiv, sP, n, upper_only, (const double2*)work, nbatch);
-  cfqmc_post_launch("rsolve_rl_kernel");
+  const double2* inv = work;
+  if (!mixed) {
+    run_rsolve<double>(X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n, upper_only, nbatch, s, inv, nullptr, 0);
+    return;
+  }
+  // FP32 products for every chain, or with sel64 for the chains it leaves at 0
+  // (the FP64 ones in a launch of their own)
+  run_rsolve<float>(X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n, upper_only, nbatch, s, inv, sel64, 0);
+  if (sel64)
+    run_rsolve<double>(X, ldx, sX, Y, ldy, sY, LU, ldlu, sLU, ipiv, sP, n, upper_only, nbatch, s, inv, sel64, 1);
 }
 
 // ------------------------------------------------------------------ elementwise helpers

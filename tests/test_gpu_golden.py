@@ -110,10 +110,11 @@ def test_n36_full_size_five_couplings_fp64():
     _replay_context("c2_n36", 0)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_n100_paper_cutoff_short_axis(precision):
     """The bench shape: N_phi = 100, paper cutoff (933 components), u = 1.5,
-    n_stab = 8, on a 16-slice axis, two sweeps; FP64 and mixed."""
+    n_stab = 8, on a 16-slice axis, two sweeps; FP64, mixed, and mixed with the
+    Woodbury product and the rank-k update in FP32 as well."""
     _replay_context("c3_n100", precision)
 
 

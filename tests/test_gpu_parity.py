@@ -124,14 +124,18 @@ def test_sweep_replay_parity_batched_u_grid():
     _replay_compare(CFQMC, 8, 24, 6, Q_RADIUS, 3.0, [0.5, 1.0, 1.5, 2.0, 2.5], 0, 2, 1e-10)
 
 
-@pytest.mark.parametrize("precision", [1, 2])
-def test_sweep_replay_parity_mixed(precision):
-    """Mixed paths: FP32 MFMA wraps and frames (1), also the Woodbury product (2),
-    with FP64 accumulation and FP64 recomputation. G after a sweep (recomputed
-    in FP64) within 1e-6 and the G drift between recomputations within 1e-6."""
+@pytest.mark.parametrize("precision,guard", [(1, 1), (2, 1), (2, 0)])
+def test_sweep_replay_parity_mixed(precision, guard):
+    """Mixed paths: FP32 MFMA wraps and frames (1), also the Woodbury product and
+    the rank-k update G' = G M^-1 (2), with FP64 accumulation and FP64
+    recomputation; with the precision guard off every chain takes the FP32
+    products. G after a sweep (recomputed in FP64) within 1e-6 and the G drift
+    between recomputations within 1e-6."""
     CFQMC = _gpu()
-    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], precision, 2, 1e-6)
+    st = _replay_compare(CFQMC, 6, 40, 10, Q_BZ, None, [1.0], precision, 2, 1e-6, precision_guard=guard)
     assert st[0]["max_stab_err"] < 1e-6 and st[0]["max_stab_rel"] < 1e-6
+    if not guard:
+        assert st[0]["fp64_guard_frac"] == 0.0 and st[0]["max_stab_err"] > 1e-12
 
 
 @pytest.mark.parametrize("n_phi", [7, 36])
@@ -523,7 +527,8 @@ def test_guarded_applications_one_launch_equals_two(tile_cfg, monkeypatch):
     assert min(fr) < 1.0 and max(fr) > 0.0          # both classes occurred
 
 
-def test_precision_guard_selects_fp64_chains():
+@pytest.mark.parametrize("precision", [1, 2])
+def test_precision_guard_selects_fp64_chains(precision):
     """The mixed path's precision guard: with a max|G| threshold below every
     chain's max|G_FP64| each chain's FP32 applications run in FP64 after the
     first recomputation (guard fraction 1, and the blocks after the first
@@ -539,8 +544,9 @@ def test_precision_guard_selects_fp64_chains():
     for k in range(2):
         ch[k].run(rp[k])
     for guard, gmax, want in ((1, 1e-9, 1.0), (0, 1.0, 0.0)):
-        g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=Q_BZ, n_stab=nstab, eps0=0.4, adapt_eps=True, precision=1,
-                  n_chains=2, chain_u=[(1.0, 1.0, 1.0)] * 2, tile_cfg=1, precision_guard=guard, guard_gmax=gmax)
+        g = CFQMC(n_phi=n_phi, l_tau=L, dtau=0.1, q_mode=Q_BZ, n_stab=nstab, eps0=0.4, adapt_eps=True,
+                  precision=precision, n_chains=2, chain_u=[(1.0, 1.0, 1.0)] * 2, tile_cfg=1,
+                  precision_guard=guard, guard_gmax=gmax)
         g.init_fields(phi)
         g.sweep(1, rp[:, 0:1])
         st = g.sweep(1, rp[:, 1:2])       # the guard's choice carries over from the first sweep
