@@ -134,6 +134,33 @@ CF_DEV void mma_slab3(const double2* As, int lda, const double2* Bs, int ldb, in
   }
 }
 
+// The same products for a wave tile with 0 < mrem < 16 valid rows: one FP64
+// 4x4x4 four-block MFMA per 4-row group that holds valid rows (the blocks are
+// the four 4-column groups and share the B operand) instead of the 16x16x4
+// instruction over all 16 rows. Group r lands in accumulator element r, where
+// the 16x16x4 instruction puts rows 4r .. 4r + 3.
+template <int KD = BK>
+CF_DEV void mma_slab3_rows(const double2* As, int lda, const double2* Bs, int ldb, int wm0, int wn0, int lane,
+                           Acc3<1, 1>& acc, int mrem, int krem) {
+  const int il = lane & 15, kl = lane >> 4, i4 = lane & 3;
+  mrem = __builtin_amdgcn_readfirstlane(mrem);
+  krem = __builtin_amdgcn_readfirstlane(krem);
+#pragma unroll
+  for (int kk = 0; kk < KD; kk += 4) {
+    if (kk >= krem) break;
+    const double2 b = Bs[(kk + kl) * ldb + wn0 + il];
+    const double sb = b.x + b.y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (4 * r >= mrem) break;
+      const double2 a = As[(kk + kl) * lda + wm0 + 4 * r + i4];
+      acc.p[0][0][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.x, acc.p[0][0][r], 0, 0, 0);
+      acc.q[0][0][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, b.y, acc.q[0][0][r], 0, 0, 0);
+      acc.t[0][0][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x + a.y, sb, acc.t[0][0][r], 0, 0, 0);
+    }
+  }
+}
+
 // The same three-product form with FP32 operands and accumulators (the FP32
 // channel application without accumulation points: P, Q, S stay FP32 over the
 // whole k range and are combined in FP64 in the epilogue).
@@ -573,7 +600,13 @@ constexpr int chan_lds_bytes() {
 // AM = 4 (FP64 only): the two valley products of a tile are split over twice
 // the waves (one valley each, half the accumulator registers per wave); the
 // rotating channels exchange the two halves through LDS in the epilogue.
-template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
+// RR (FP64, 16 x 16 wave tiles): the workgroup lies in the last row tile,
+// which holds fewer than 16 valid rows, so that its waves either have no valid
+// row or take mma_slab3_rows; a separate instantiation holding only that form,
+// so that the register allocation of the other workgroups stays that of the
+// 16x16x4 form.
+template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM,
+          bool RR = false>
 CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned char* smem) {
   typedef typename cplx_t<CT>::type C2;
   constexpr bool VS = AM == 4;
@@ -728,6 +761,15 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
                                accv, mr, nr, N - k0);
       return;
     }
+    if constexpr (RR && sizeof(CT) == 8 && WTM == 1 && WTN == 1) {
+      if (mr > 0 && nr > 0) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          mma_slab3_rows<BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
+                              acc3[a], mr, N - k0);
+      }
+      return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if constexpr (sizeof(CT) == 8) {
@@ -880,12 +922,20 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
 
 template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64 * (AM == 4 ? 2 : 1))
+__attribute__((amdgpu_waves_per_eu(sizeof(CT) == 8 && AM != 4 && WTM == 1 && WTN == 1 ? 4 : 1)))
 chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   __shared__ __align__(16) unsigned char smem[chan_lds_bytes<CT, BM, BN, BKC, DB>()];
   int z, ty, tx;
   if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
   // chains of the other precision class are computed by the companion launch
   if (c.chain_sel && c.chain_sel[z] != c.sel_want) return;
+  if constexpr (sizeof(CT) == 8 && AM != 4 && WTM == 1 && WTN == 1) {
+    const int rows = LEFT ? c.N : c.n_other;
+    if (ty == tiles_y - 1 && rows - ty * BM < 16) {
+      chan_apply_body<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM, true>(c, z, ty, tx, smem);
+      return;
+    }
+  }
   chan_apply_body<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, z, ty, tx, smem);
 }
 
@@ -893,13 +943,20 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
 // workgroups of a chain the guard runs in FP64 (chain_sel[z] = 1) take the FP64
 // path, the others the FP32 correction form; same tile geometry, one LDS
 // buffer sized for the larger of the two.
-template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
+// RR: FP64 workgroups of a last row tile with fewer than 16 valid rows take
+// the 4x4x4 form (the four-wave register budget only: it costs the
+// compiler-allocated form a wave per SIMD).
+template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM, bool RR>
 CF_DEV void chan_apply_dual(const ChanArgs& c, int tiles_x, int tiles_y, int nbatch, unsigned char* smem) {
   int z, ty, tx;
   if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
-  if (c.chain_sel[z])
-    chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0>(c, z, ty, tx, smem);
-  else
+  if (c.chain_sel[z]) {
+    const int rows = LEFT ? c.N : c.n_other;
+    if (RR && WTM == 1 && WTN == 1 && ty == tiles_y - 1 && rows - ty * BM < 16)
+      chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0, RR>(c, z, ty, tx, smem);
+    else
+      chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0>(c, z, ty, tx, smem);
+  } else
     chan_apply_body<float, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, z, ty, tx, smem);
 }
 template <int BM, int BN, int BKC, bool DB>
@@ -913,14 +970,14 @@ template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BK
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
 chan_apply_dual_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   __shared__ __align__(16) unsigned char smem[dual_lds_bytes<BM, BN, BKC, DB>()];
-  chan_apply_dual<LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, tiles_x, tiles_y, nbatch, smem);
+  chan_apply_dual<LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM, false>(c, tiles_x, tiles_y, nbatch, smem);
 }
 // held to four waves per SIMD (128 registers; the compiler spills a few)
 template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM>
 __global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64) __attribute__((amdgpu_waves_per_eu(4)))
 chan_apply_dual4_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   __shared__ __align__(16) unsigned char smem[dual_lds_bytes<BM, BN, BKC, DB>()];
-  chan_apply_dual<LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM>(c, tiles_x, tiles_y, nbatch, smem);
+  chan_apply_dual<LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM, true>(c, tiles_x, tiles_y, nbatch, smem);
 }
 
 // ------------------------------------------------------------------ launchers
