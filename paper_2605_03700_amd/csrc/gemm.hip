@@ -161,6 +161,44 @@ CF_DEV void mma_slab3_rows(const double2* As, int lda, const double2* Bs, int ld
   }
 }
 
+// The same products for a wave tile with 0 < nrem < 16 valid columns: the
+// four blocks of the 4x4x4 MFMA lie along the rows (block b = rows 4b .. 4b+3,
+// whose A operand is the 16x16x4 instruction's), one instruction per 4-column
+// group c that holds valid columns, into accumulator element c. Element c of
+// lane l then holds row 4 ((l >> 2) & 3) + (l >> 4), column 4c + (l & 3).
+template <int KD = BK>
+CF_DEV void mma_slab3_cols(const double2* As, int lda, const double2* Bs, int ldb, int wm0, int wn0, int lane,
+                           Acc3<1, 1>& acc, int nrem, int krem) {
+  const int il = lane & 15, kl = lane >> 4, j4 = lane & 3;
+  nrem = __builtin_amdgcn_readfirstlane(nrem);
+  krem = __builtin_amdgcn_readfirstlane(krem);
+#pragma unroll
+  for (int kk = 0; kk < KD; kk += 4) {
+    if (kk >= krem) break;
+    const double2 a = As[(kk + kl) * lda + wm0 + il];
+    const double sa = a.x + a.y;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (4 * c >= nrem) break;
+      const double2 b = Bs[(kk + kl) * ldb + wn0 + 4 * c + j4];
+      acc.p[0][0][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.x, acc.p[0][0][c], 0, 0, 0);
+      acc.q[0][0][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, b.y, acc.q[0][0][c], 0, 0, 0);
+      acc.t[0][0][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(sa, b.x + b.y, acc.t[0][0][c], 0, 0, 0);
+    }
+  }
+}
+
+// Which body a workgroup of an FP64 application with 16 x 16 wave tiles runs:
+// 0 the 16x16x4 form; 1 the last row tile with fewer than 16 valid rows
+// (mma_slab3_rows); 2 the last column tile with fewer than 16 valid columns
+// (mma_slab3_cols). At a tile that is both, the form with fewer instructions.
+CF_DEV int partial_mode(int rows, int cols, int ty, int tx, int tiles_y, int tiles_x, int BMv, int BNv) {
+  const int rr = ty == tiles_y - 1 ? rows - ty * BMv : 16, rc = tx == tiles_x - 1 ? cols - tx * BNv : 16;
+  const bool pr = rr < 16, pc = rc < 16;
+  if (pr && pc) return (rc + 3) / 4 < (rr + 3) / 4 ? 2 : 1;
+  return pr ? 1 : pc ? 2 : 0;
+}
+
 // The same three-product form with FP32 operands and accumulators (the FP32
 // channel application without accumulation points: P, Q, S stay FP32 over the
 // whole k range and are combined in FP64 in the epilogue).
@@ -600,13 +638,14 @@ constexpr int chan_lds_bytes() {
 // AM = 4 (FP64 only): the two valley products of a tile are split over twice
 // the waves (one valley each, half the accumulator registers per wave); the
 // rotating channels exchange the two halves through LDS in the epilogue.
-// RR (FP64, 16 x 16 wave tiles): the workgroup lies in the last row tile,
-// which holds fewer than 16 valid rows, so that its waves either have no valid
-// row or take mma_slab3_rows; a separate instantiation holding only that form,
-// so that the register allocation of the other workgroups stays that of the
-// 16x16x4 form.
+// RM (FP64, 16 x 16 wave tiles; partial_mode): 1, the workgroup lies in the
+// last row tile, which holds fewer than 16 valid rows, so that its waves either
+// have no valid row or take mma_slab3_rows; 2, the same for the last column
+// tile and mma_slab3_cols (whose accumulator layout the epilogue follows).
+// Separate instantiations holding only that form, so that the register
+// allocation of the other workgroups stays that of the 16x16x4 form.
 template <typename CT, bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM,
-          bool RR = false>
+          int RM = 0>
 CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned char* smem) {
   typedef typename cplx_t<CT>::type C2;
   constexpr bool VS = AM == 4;
@@ -761,12 +800,17 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
                                accv, mr, nr, N - k0);
       return;
     }
-    if constexpr (RR && sizeof(CT) == 8 && WTM == 1 && WTN == 1) {
+    if constexpr (RM != 0 && sizeof(CT) == 8 && WTM == 1 && WTN == 1) {
       if (mr > 0 && nr > 0) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-          mma_slab3_rows<BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
-                              acc3[a], mr, N - k0);
+        for (int a = 0; a < 2; ++a) {
+          if constexpr (RM == 1)
+            mma_slab3_rows<BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
+                                acc3[a], mr, N - k0);
+          else
+            mma_slab3_cols<BKC>((const double2*)As[st][a], LDA, (const double2*)Bs[st][a], LDB, wm0, wn0, lane,
+                                acc3[a], nr, N - k0);
+        }
       }
       return;
     }
@@ -900,8 +944,8 @@ CF_DEV void chan_apply_body(const ChanArgs& c, int z, int ty, int tx, unsigned c
     for (int sj = 0; sj < WTN; ++sj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm0 + si * 16 + out_row<CT>(lane, r);
-        const int j = n0 + wn0 + sj * 16 + (lane & 15);
+        const int i = m0 + wm0 + si * 16 + (RM == 2 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : out_row<CT>(lane, r));
+        const int j = n0 + wn0 + sj * 16 + (RM == 2 ? 4 * r + (lane & 3) : (lane & 15));
         if (i >= rows || j >= cols) continue;
         const double2 t0 = make_double2(acc[0].re[si][sj][r], acc[0].im[si][sj][r]);
         const double2 t1 = make_double2(acc[1].re[si][sj][r], acc[1].im[si][sj][r]);
@@ -930,9 +974,13 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
   // chains of the other precision class are computed by the companion launch
   if (c.chain_sel && c.chain_sel[z] != c.sel_want) return;
   if constexpr (sizeof(CT) == 8 && AM != 4 && WTM == 1 && WTN == 1) {
-    const int rows = LEFT ? c.N : c.n_other;
-    if (ty == tiles_y - 1 && rows - ty * BM < 16) {
-      chan_apply_body<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM, true>(c, z, ty, tx, smem);
+    const int pm = partial_mode(LEFT ? c.N : c.n_other, LEFT ? c.n_other : c.N, ty, tx, tiles_y, tiles_x, BM, BN);
+    if (pm == 1) {
+      chan_apply_body<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM, 1>(c, z, ty, tx, smem);
+      return;
+    }
+    if (pm == 2) {
+      chan_apply_body<CT, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, AM, 2>(c, z, ty, tx, smem);
       return;
     }
   }
@@ -943,17 +991,21 @@ chan_apply_kernel(ChanArgs c, int tiles_x, int tiles_y, int nbatch) {
 // workgroups of a chain the guard runs in FP64 (chain_sel[z] = 1) take the FP64
 // path, the others the FP32 correction form; same tile geometry, one LDS
 // buffer sized for the larger of the two.
-// RR: FP64 workgroups of a last row tile with fewer than 16 valid rows take
-// the 4x4x4 form (the four-wave register budget only: it costs the
+// RR: FP64 workgroups of a partial last row or column tile take the 4x4x4
+// forms (partial_mode; the four-wave register budget only: they cost the
 // compiler-allocated form a wave per SIMD).
 template <bool LEFT, int ROTK, bool OM, int BM, int BN, int WTM, int WTN, int BKC, bool DB, int AM, bool RR>
 CF_DEV void chan_apply_dual(const ChanArgs& c, int tiles_x, int tiles_y, int nbatch, unsigned char* smem) {
   int z, ty, tx;
   if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
   if (c.chain_sel[z]) {
-    const int rows = LEFT ? c.N : c.n_other;
-    if (RR && WTM == 1 && WTN == 1 && ty == tiles_y - 1 && rows - ty * BM < 16)
-      chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0, RR>(c, z, ty, tx, smem);
+    const int pm = RR && WTM == 1 && WTN == 1
+                       ? partial_mode(LEFT ? c.N : c.n_other, LEFT ? c.n_other : c.N, ty, tx, tiles_y, tiles_x, BM, BN)
+                       : 0;
+    if (pm == 1)
+      chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0, 1>(c, z, ty, tx, smem);
+    else if (pm == 2)
+      chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0, 2>(c, z, ty, tx, smem);
     else
       chan_apply_body<double, LEFT, ROTK, OM, BM, BN, WTM, WTN, BKC, DB, 0>(c, z, ty, tx, smem);
   } else
