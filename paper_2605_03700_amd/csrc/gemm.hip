@@ -306,25 +306,17 @@ CF_DEV bool band_meets(int r0, int nr, int c0, int nc, int b, int K) {
 
 // ------------------------------------------------------------------ zgemm
 
-template <typename CT, int BM, int BN, int WTM, int WTN>
-__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
-zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
+// The product of tile (ty, tx) of matrix z; As / Bs the workgroup's LDS
+// operand tiles. RM (FP64, one 16 x 16 wave tile per wave; partial_mode): 1 a
+// last row tile with fewer than 16 valid rows, 2 a last column tile with fewer
+// than 16 valid columns, on the FP64 4x4x4 MFMA.
+template <typename CT, int BM, int BN, int WTM, int WTN, int RM>
+CF_DEV void zgemm_body(const GemmArgs& g, int z, int ty, int tx, typename cplx_t<CT>::type* As,
+                       typename cplx_t<CT>::type* Bs) {
   typedef typename cplx_t<CT>::type C2;
   constexpr int WX = BN / (16 * WTN), WY = BM / (16 * WTM);
   constexpr int NT = WX * WY * 64;
-  // padded rows: the k-fastest staging stores of a quarter wave hit distinct banks
   constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
-  __shared__ C2 As[BK * LDA];
-  __shared__ C2 Bs[BK * LDB];
-  int z, ty, tx;
-  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
-  if (g.herm) {
-    // tiles_x counts the upper triangle (row-major) of a herm x herm tile grid
-    int r = tx, a = 0;
-    while (r >= g.herm - a) { r -= g.herm - a; ++a; }
-    ty = a;
-    tx = a + r;
-  }
   const int z1 = z / g.nz2, z2 = z % g.nz2;
   const int m0 = ty * BM, n0 = tx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -409,7 +401,13 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
       const int k1 = next_live(k0 + BK);
       if (k1 < g.K) fetch(k1);
       const int mr = g.M - m0 - wm0, nr = g.N - n0 - wn0, kr = g.K - k0;
-      if constexpr (sizeof(CT) == 8) {
+      if constexpr (sizeof(CT) == 8 && RM == 1) {
+        if (mr > 0 && nr > 0)
+          mma_slab3_rows<BK>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc3, mr, kr);
+      } else if constexpr (sizeof(CT) == 8 && RM == 2) {
+        if (mr > 0 && nr > 0)
+          mma_slab3_cols<BK>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc3, nr, kr);
+      } else if constexpr (sizeof(CT) == 8) {
         mma_slab3<WTM, WTN>((const double2*)As, LDA, (const double2*)Bs, LDB, wm0, wn0, lane, acc3, mr, nr, kr);
       } else {
         Acc<float, WTM, WTN> a32;
@@ -436,8 +434,8 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
     for (int sj = 0; sj < WTN; ++sj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm0 + si * 16 + out_row<CT>(lane, r);
-        const int j = n0 + wn0 + sj * 16 + (lane & 15);
+        const int i = m0 + wm0 + si * 16 + (RM == 2 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : out_row<CT>(lane, r));
+        const int j = n0 + wn0 + sj * 16 + (RM == 2 ? 4 * r + (lane & 3) : (lane & 15));
         if (i >= g.M || j >= g.N) continue;
         double2 p = make_double2(acc.re[si][sj][r], acc.im[si][sj][r]);
         if (g.mode == GEMM_SQUARE) {
@@ -454,6 +452,38 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
           if (g.herm && ty < tx) D[(long long)j * ldd + i] = make_double2(v.x, -v.y);
         }
       }
+}
+
+template <typename CT, int BM, int BN, int WTM, int WTN>
+__global__ void __launch_bounds__((BM / (16 * WTM)) * (BN / (16 * WTN)) * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(CT) == 8 && WTM == 1 && WTN == 1 ? (BM == 16 ? 4 : 5) : 1)))
+zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
+  typedef typename cplx_t<CT>::type C2;
+  // padded rows: the k-fastest staging stores of a quarter wave hit distinct banks
+  constexpr int LDA = BM + (sizeof(C2) == 16 ? 2 : 4), LDB = BN + (sizeof(C2) == 16 ? 2 : 4);
+  __shared__ C2 As[BK * LDA];
+  __shared__ C2 Bs[BK * LDB];
+  int z, ty, tx;
+  if (!xcd_tile(tiles_x, tiles_y, nbatch, z, ty, tx)) return;
+  if (g.herm) {
+    // tiles_x counts the upper triangle (row-major) of a herm x herm tile grid
+    int r = tx, a = 0;
+    while (r >= g.herm - a) { r -= g.herm - a; ++a; }
+    ty = a;
+    tx = a + r;
+  }
+  if constexpr (sizeof(CT) == 8 && WTM == 1 && WTN == 1) {
+    const int pm = partial_mode(g.M, g.N, ty, tx, g.herm ? g.herm : tiles_y, g.herm ? g.herm : tiles_x, BM, BN);
+    if (pm == 1) {
+      zgemm_body<CT, BM, BN, WTM, WTN, 1>(g, z, ty, tx, As, Bs);
+      return;
+    }
+    if (pm == 2) {
+      zgemm_body<CT, BM, BN, WTM, WTN, 2>(g, z, ty, tx, As, Bs);
+      return;
+    }
+  }
+  zgemm_body<CT, BM, BN, WTM, WTN, 0>(g, z, ty, tx, As, Bs);
 }
 
 // ------------------------------------------------------------------ exp_eo
