@@ -41,9 +41,9 @@ SUSTAINED = {"fp64": 49.2, "mixed": 135.5, "mixed_all": 135.5}
 # the copy calibration; profiles/chan_apply_traffic_n100_256chains.md), keyed
 # by (n_phi, arithmetic, channel-application configuration)
 TRAFFIC = {(100, "f32", 12): (167544.25 * 2.0 + 160000.0) * 1024 / 256,
-           (100, "f64", 1): (126297.81 * 2.0 + 165376.0) * 1024 / 256,
+           (100, "f64", 1): (126926.55 * 2.0 + 171777.13) * 1024 / 256,
            # the guarded one-launch form with the given percentage of the chains in FP64
-           (100, "dual", 12, 94): (126069.04 * 2.0 + 160000.0) * 1024 / 256}
+           (100, "dual", 12, 94): (126374.02 * 2.0 + 160000.67) * 1024 / 256}
 
 # Integrated autocorrelation times at the default workload's shape (N_phi = 100,
 # L = 400, dtau = 0.1, u = 1.5, paper cutoff) from one long run, 32 chains x
