@@ -41,6 +41,7 @@ struct HostTables {
   std::vector<double> comp_w, t_w;
   // h table
   std::vector<int> hoff, h_cre, h_cim, h_qx, h_qy, h_dag;
+  std::vector<int> hdiag;   // shifts d that carry a term
   std::vector<double> h_sgn, h_scale, h_F;
   // trace table
   std::vector<int> toff, t_qy, t_qx, t_kind, t_comp;
@@ -780,8 +781,15 @@ int build_model_dev(cfqmc_ctx* c) {
   r |= upload(c, &p_toff, T.toff); r |= upload(c, &p_tqy, T.t_qy); r |= upload(c, &p_tqx, T.t_qx);
   r |= upload(c, &p_tk, T.t_kind); r |= upload(c, &p_tc, T.t_comp); r |= upload(c, &p_tF, T.t_F);
   r |= upload(c, &p_beta, T.beta); r |= upload(c, &p_ph, T.phase);
+  T.hdiag.clear();
+  for (int d = 0; d < c->N; ++d)
+    if (T.hoff[d + 1] > T.hoff[d]) T.hdiag.push_back(d);
+  int* p_hdiag = nullptr;
+  if (!T.hdiag.empty()) r |= upload(c, &p_hdiag, T.hdiag);
   if (r) return CFQMC_ENOMEM;
   m.hoff = p_hoff; m.h_cre = p_cre; m.h_cim = p_cim; m.h_qx = p_qx; m.h_qy = p_qy; m.h_dag = p_dag;
+  m.hdiag = p_hdiag;
+  m.nhdiag = (int)T.hdiag.size();
   m.h_sgn = p_sgn; m.h_scale = p_sc; m.h_F = p_F;
   m.nrow = (int)T.t_qy.size();
   m.toff = p_toff; m.t_qy = p_tqy; m.t_qx = p_tqx; m.t_kind = p_tk; m.t_comp = p_tc; m.t_F = p_tF;
@@ -1310,6 +1318,13 @@ int cfqmc_create(const cfqmc_params* pin, void* hip_stream, cfqmc_ctx** out) {
   rc |= dalloc(c, &c->gmax_run, (size_t)B);
   rc |= dalloc(c, &c->blk_last, (size_t)B * 2);
   if (rc) { g_create_err = c->err; cfqmc_destroy(c); return CFQMC_ENOMEM; }
+  // h is zero on the diagonals without terms, which build_h never writes
+  if (hipMemsetAsync(c->h, 0, (size_t)ecap * sizeof(double2), c->s) != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_err = "clearing the h buffer failed";
+    cfqmc_destroy(c);
+    return CFQMC_EHIP;
+  }
   if (build_model_dev(c)) {
     g_create_err = "model tables: " + c->err;
     cfqmc_destroy(c);

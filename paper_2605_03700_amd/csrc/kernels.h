@@ -142,8 +142,11 @@ void launch_diag_set(double2* A, int n, long long sA, const double* d, long long
 // ---- model kernels (qmc.hip)
 struct ModelDev {
   int N, n, nq, L;
-  // h-building table: per shift d (0..N-1) terms [hoff[d], hoff[d+1])
+  // h-building table: per shift d (0..N-1) terms [hoff[d], hoff[d+1]); hdiag the
+  // nhdiag shifts that carry a term (h is zero on every other diagonal)
   const int* hoff;
+  const int* hdiag;
+  int nhdiag;
   const int* h_cre; const int* h_cim; const int* h_qx; const int* h_qy; const int* h_dag;
   const double* h_sgn; const double* h_scale; const double* h_F;
   // trace table: per row r (0..nrow-1) components [toff[r], toff[r+1])
@@ -163,7 +166,9 @@ struct ChainDev {
   const double2* U;         // [4][2][2] valley rotations
 };
 
-// h_i = sum_c phi^i_c q_c for all batch entries; phi [batch][4][nq] (stride sphi), h [batch][4][N][N]
+// h_i = sum_c phi^i_c q_c for all batch entries; phi [batch][4][nq] (stride sphi), h [batch][4][N][N].
+// Writes the diagonals listed in m.hdiag only: the others must hold zeros
+// (the caller clears h once).
 void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double2* h, long long sh, int nbatch,
                     hipStream_t s);
 // exponential helper: norm estimate and Taylor coefficients per (batch, channel)

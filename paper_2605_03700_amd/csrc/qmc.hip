@@ -32,7 +32,8 @@ CF_DEV long long step_counter(const StepArgs& a) {
 #define BH_CPB 4     // chains per workgroup
 #define BH_TC 64     // terms per LDS chunk
 #define BH_MAXN 288
-// One workgroup per (diagonal d, group of BH_CPB entries), one thread per row.
+// One workgroup per (diagonal d carrying terms, group of BH_CPB entries), one
+// thread per row; the diagonals without terms are never written (zero).
 // The terms of a diagonal and their phases do not depend on the channel or the
 // entry, so each thread computes a term's phase once (table in LDS) and adds
 // it into the 4 x BH_CPB (channel, entry) accumulators with weights staged in
@@ -42,7 +43,7 @@ __global__ void __launch_bounds__(256) build_h_kernel(ModelDev m, const double* 
   __shared__ double2 s_w[BH_TC][4 * BH_CPB];
   __shared__ int s_qx[BH_TC], s_qy[BH_TC], s_dag[BH_TC], s_cmp[BH_TC];
   __shared__ double2 s_ph[2 * BH_MAXN];
-  const int d = blockIdx.x, z0 = blockIdx.y * BH_CPB, N = m.N, N2 = 2 * N;
+  const int d = m.hdiag[blockIdx.x], z0 = blockIdx.y * BH_CPB, N = m.N, N2 = 2 * N;
   const int r = threadIdx.x;
   const int col = ((r - d) % N + N) % N;
   for (int i = threadIdx.x; i < N2; i += blockDim.x) s_ph[i] = m.phase[i];
@@ -105,8 +106,9 @@ __global__ void __launch_bounds__(256) build_h_kernel(ModelDev m, const double* 
 void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double2* h, long long sh, int nbatch,
                     hipStream_t s) {
   if (m.N > BH_MAXN || m.N > 256) { std::fprintf(stderr, "build_h: N = %d too large\n", m.N); std::abort(); }
+  if (m.nhdiag <= 0 || nbatch <= 0) return;
   const int nt = (m.N + 63) / 64 * 64;
-  dim3 grid(m.N, (nbatch + BH_CPB - 1) / BH_CPB);
+  dim3 grid(m.nhdiag, (nbatch + BH_CPB - 1) / BH_CPB);
   hipLaunchKernelGGL(build_h_kernel, grid, dim3(nt), 0, s, m, phi, sphi, h, sh, nbatch); cfqmc_post_launch("build_h_kernel");
 }
 
