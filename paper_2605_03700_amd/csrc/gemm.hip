@@ -496,22 +496,14 @@ zgemm_kernel(GemmArgs g, int tiles_x, int tiles_y, int nbatch) {
 // Hermitian (h Hermitian, real coefficients): only tiles on and above the
 // diagonal are computed, each strictly upper tile also writing its conjugate
 // transpose. FP64, three-MFMA complex products.
-template <int BT>
-__global__ void __launch_bounds__((BT / 16) * (BT / 16) * 64)
-exp_eo_kernel(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N, double2* Eo,
-              double2* Oo, int ntri, int tiles, int nbatch) {
+// Tile (ty, tx) of matrix z; RM as for chan_apply_body (partial_mode: 1 / 2 a
+// last row / column tile with fewer than 16 valid rows / columns, on the FP64
+// 4x4x4 MFMA).
+template <int BT, int RM>
+CF_DEV void exp_eo_body(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N,
+                        double2* Eo, double2* Oo, int z, int ty, int tx, double2* As, double2* Be, double2* Bo) {
   constexpr int WX = BT / 16, NT = WX * WX * 64;
   constexpr int LD = BT + 2;
-  __shared__ double2 As[BK * LD];
-  __shared__ double2 Be[BK * LD], Bo[BK * LD];
-  int z, ty, tx;
-  if (!xcd_tile(ntri, 1, nbatch, z, ty, tx)) return;
-  {
-    int r = tx, a = 0;
-    while (r >= tiles - a) { r -= tiles - a; ++a; }
-    ty = a;
-    tx = a + r;
-  }
   const long long NN = (long long)N * N, off = z * NN;
   const double* cf = coef + (long long)z * EXP_NC;
   const double e3 = cf[3], e4 = cf[4], e5 = cf[5], e6 = cf[6];
@@ -575,8 +567,20 @@ exp_eo_kernel(const double2* H2, const double2* X2, const double2* X3, const dou
     stage(k0);
     __syncthreads();
     if (k0 + BK < N) fetch(k0 + BK);
-    mma_slab3<1, 1>(As, LD, Be, LD, wm0, wn0, lane, ae, mr, nr, N - k0);
-    mma_slab3<1, 1>(As, LD, Bo, LD, wm0, wn0, lane, ao, mr, nr, N - k0);
+    if constexpr (RM == 1) {
+      if (mr > 0 && nr > 0) {
+        mma_slab3_rows<BK>(As, LD, Be, LD, wm0, wn0, lane, ae, mr, N - k0);
+        mma_slab3_rows<BK>(As, LD, Bo, LD, wm0, wn0, lane, ao, mr, N - k0);
+      }
+    } else if constexpr (RM == 2) {
+      if (mr > 0 && nr > 0) {
+        mma_slab3_cols<BK>(As, LD, Be, LD, wm0, wn0, lane, ae, nr, N - k0);
+        mma_slab3_cols<BK>(As, LD, Bo, LD, wm0, wn0, lane, ao, nr, N - k0);
+      }
+    } else {
+      mma_slab3<1, 1>(As, LD, Be, LD, wm0, wn0, lane, ae, mr, nr, N - k0);
+      mma_slab3<1, 1>(As, LD, Bo, LD, wm0, wn0, lane, ao, mr, nr, N - k0);
+    }
     __syncthreads();
   }
   const double e0 = cf[0], e1 = cf[1], e2 = cf[2], o0 = cf[7], o1 = cf[8], o2 = cf[9];
@@ -584,8 +588,8 @@ exp_eo_kernel(const double2* H2, const double2* X2, const double2* X3, const dou
   for (int r = 0; r < 4; ++r) {
     const double er = ae.p[0][0][r] - ae.q[0][0][r], ei = ae.t[0][0][r] - ae.p[0][0][r] - ae.q[0][0][r];
     const double or_ = ao.p[0][0][r] - ao.q[0][0][r], oi = ao.t[0][0][r] - ao.p[0][0][r] - ao.q[0][0][r];
-    const int i = m0 + wm0 + Mfma<double>::row(lane, r);
-    const int j = n0 + wn0 + (lane & 15);
+    const int i = m0 + wm0 + (RM == 2 ? 4 * ((lane >> 2) & 3) + (lane >> 4) : Mfma<double>::row(lane, r));
+    const int j = n0 + wn0 + (RM == 2 ? 4 * r + (lane & 3) : (lane & 15));
     if (i >= N || j >= N) continue;
     const long long o = off + (long long)i * N + j;
     const double2 h = H2[o], x = X2[o];
@@ -600,6 +604,30 @@ exp_eo_kernel(const double2* H2, const double2* X2, const double2* X3, const dou
       Oo[ot] = make_double2(vo.x, -vo.y);
     }
   }
+}
+
+template <int BT>
+__global__ void __launch_bounds__((BT / 16) * (BT / 16) * 64) __attribute__((amdgpu_waves_per_eu(3)))
+exp_eo_kernel(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N, double2* Eo,
+              double2* Oo, int ntri, int tiles, int nbatch) {
+  constexpr int LD = BT + 2;
+  __shared__ double2 As[BK * LD];
+  __shared__ double2 Be[BK * LD], Bo[BK * LD];
+  int z, ty, tx;
+  if (!xcd_tile(ntri, 1, nbatch, z, ty, tx)) return;
+  {
+    int r = tx, a = 0;
+    while (r >= tiles - a) { r -= tiles - a; ++a; }
+    ty = a;
+    tx = a + r;
+  }
+  const int pm = partial_mode(N, N, ty, tx, tiles, tiles, BT, BT);
+  if (pm == 1)
+    exp_eo_body<BT, 1>(H2, X2, X3, coef, N, Eo, Oo, z, ty, tx, As, Be, Bo);
+  else if (pm == 2)
+    exp_eo_body<BT, 2>(H2, X2, X3, coef, N, Eo, Oo, z, ty, tx, As, Be, Bo);
+  else
+    exp_eo_body<BT, 0>(H2, X2, X3, coef, N, Eo, Oo, z, ty, tx, As, Be, Bo);
 }
 
 void launch_exp_eo(const double2* H2, const double2* X2, const double2* X3, const double* coef, int N, double2* Eo,
