@@ -43,7 +43,13 @@ __global__ void __launch_bounds__(256) build_h_kernel(ModelDev m, const double* 
   __shared__ double2 s_w[BH_TC][4 * BH_CPB];
   __shared__ int s_qx[BH_TC], s_qy[BH_TC], s_dag[BH_TC], s_cmp[BH_TC];
   __shared__ double2 s_ph[2 * BH_MAXN];
-  const int d = m.hdiag[blockIdx.x], z0 = blockIdx.y * BH_CPB, N = m.N, N2 = 2 * N;
+  // all diagonals of one group of entries on one XCD (consecutive workgroups go
+  // to the eight XCDs in turn): the rows they write in 16-byte pieces merge in
+  // that XCD's L2
+  const int ngrp = (nbatch + BH_CPB - 1) / BH_CPB, T = m.nhdiag * ngrp, per = (T + 7) / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= T) return;
+  const int d = m.hdiag[t % m.nhdiag], z0 = (t / m.nhdiag) * BH_CPB, N = m.N, N2 = 2 * N;
   const int r = threadIdx.x;
   const int col = ((r - d) % N + N) % N;
   for (int i = threadIdx.x; i < N2; i += blockDim.x) s_ph[i] = m.phase[i];
@@ -108,7 +114,8 @@ void launch_build_h(const ModelDev& m, const double* phi, long long sphi, double
   if (m.N > BH_MAXN || m.N > 256) { std::fprintf(stderr, "build_h: N = %d too large\n", m.N); std::abort(); }
   if (m.nhdiag <= 0 || nbatch <= 0) return;
   const int nt = (m.N + 63) / 64 * 64;
-  dim3 grid(m.nhdiag, (nbatch + BH_CPB - 1) / BH_CPB);
+  const long long T = (long long)m.nhdiag * ((nbatch + BH_CPB - 1) / BH_CPB);
+  dim3 grid((unsigned)((T + 7) / 8 * 8));
   hipLaunchKernelGGL(build_h_kernel, grid, dim3(nt), 0, s, m, phi, sphi, h, sh, nbatch); cfqmc_post_launch("build_h_kernel");
 }
 
