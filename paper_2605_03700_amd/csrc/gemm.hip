@@ -11,9 +11,14 @@
 //             are staged into LDS, so one pass costs two N x N x n products
 //             instead of one n x n x n product.
 //
-// Complex products use four real MFMAs per 16x16x4 step. In the mixed path
-// (CT = float) operands are rounded to FP32 when staged, each 16-deep k slab
-// is accumulated by FP32 MFMA and then added into FP64 registers. chan_apply
+// FP64 complex products take three real 16x16x4 MFMAs per k step (Gauss:
+// re = P - Q, im = S - P - Q); a tile whose last 16 rows or columns are only
+// partly valid takes the FP64 4x4x4 four-block MFMA for its valid 4-row or
+// 4-column groups instead (mma_slab3_rows / mma_slab3_cols). In the mixed path
+// (CT = float) operands are rounded to FP32 when staged and multiplied on the
+// FP32 MFMA (four real products per complex one, or three in the three-product
+// configurations), each 16-deep k slab added into FP64 registers or, in the
+// FP32-accumulating configurations, the whole k range. chan_apply
 // additionally works in correction form there: it stages X_a - 1 (formed in
 // FP64 before rounding; ||X_a - 1|| is the small channel exponent) and adds
 // the FP64 input back in the epilogue, E M = M + (E - 1) M, so the FP32
