@@ -492,8 +492,8 @@ __global__ void __launch_bounds__(NP_NT) lu_np_global_kernel(double2* Aall, int 
 // padded to 17 entries against bank conflicts) and U12 (16 x columns) of each
 // panel are kept in LDS, so every trailing tile reads only its own A tile from
 // memory; 8 waves share the tiles, each loading the A tile of its next pass
-// while it multiplies the current one. L11^{-1} and U11^{-1} are formed column
-// by column in registers.
+// while it multiplies the current one. L11^{-1} and U11^{-1} are formed by
+// column elimination in one wave each, four entries per lane.
 #define NP2_NT 512
 #define NP2_LD 17
 __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int lda, long long sA, int* ipiv_all,
@@ -513,67 +513,77 @@ __global__ void __launch_bounds__(NP2_NT) lu_np_kernel(double2* Aall, int n, int
   double lmax = 0.0;
   for (int k0 = 0; k0 < n; k0 += NP_NB) {
     const int nb = min(NP_NB, n - k0);
-    if (tid < NP_NB * NP_NB) {
-      const int r = tid / NP_NB, c = tid % NP_NB;
-      D[r][c] = (r < nb && c < nb) ? A[(long long)(k0 + r) * lda + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
     if (wid == 0) {
-      for (int j = 0; j < nb; ++j) {
-        const double2 inv = crcp(D[j][j]);
-        double2 nv[4];
+      // the diagonal block in registers, entries (r, c) = (lane/16 + 4q, lane%16)
+      // (identity padding past nb, on which the remaining steps act as the
+      // identity); step j takes the pivot row and the multipliers' column from
+      // the lanes that hold them
+      const int r0 = lane >> 4, c = lane & 15;
+      double2 x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + 4 * q;
+        x[q] = (r < nb && c < nb) ? A[(long long)(k0 + r) * lda + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
+      }
+#pragma unroll
+      for (int j = 0; j < NP_NB - 1; ++j) {
+        const int sj = (j & 3) * 16;
+        const double2 djj = make_double2(__shfl(x[j >> 2].x, sj + j, 64), __shfl(x[j >> 2].y, sj + j, 64));
+        const double2 djc = make_double2(__shfl(x[j >> 2].x, sj + c, 64), __shfl(x[j >> 2].y, sj + c, 64));
+        const double2 inv = crcp(djj);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int e = lane + 64 * q, r = e / NP_NB, c = e % NP_NB;
-          nv[q] = D[r][c];
-          if (r > j) {
-            const double2 l = cmul(D[r][j], inv);
-            if (c == j) nv[q] = l;
-            else if (c > j) nv[q] = csub(nv[q], cmul(l, D[j][c]));
+          const double2 drj = make_double2(__shfl(x[q].x, r0 * 16 + j, 64), __shfl(x[q].y, r0 * 16 + j, 64));
+          if (r0 + 4 * q > j) {
+            const double2 l = cmul(drj, inv);
+            if (c == j) x[q] = l;
+            else if (c > j) x[q] = csub(x[q], cmul(l, djc));
           }
         }
-        lds_order();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = lane + 64 * q;
-          D[e / NP_NB][e % NP_NB] = nv[q];
-        }
-        lds_order();
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) D[r0 + 4 * q][c] = x[q];
     }
     __syncthreads();
-    if (wid == 0 && lane < NP_NB) {
-      // column t of L11^{-1} in registers, forward substitution (rows of D broadcast from LDS)
-      const int t = lane;
-      double2 x[NP_NB];
+    if (wid < 2) {
+      // L11^{-1} (wave 0, forward) and U11^{-1} (wave 1, backward) by column
+      // elimination from the identity: lane holds entries (r, c) = (lane/16 +
+      // 4q, lane%16), q < 4; step j takes row j, final at that step, from the
+      // lanes that hold it (for U scaled by 1/U_jj) and subtracts its multiples
+      // from the rows still open. Rows and columns past nb are identity padding.
+      const int r0 = lane >> 4, c = lane & 15;
+      double2 x[4];
 #pragma unroll
-      for (int i = 0; i < NP_NB; ++i) {
-        double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
-        if (i < nb) {
+      for (int q = 0; q < 4; ++q) x[q] = make_double2(r0 + 4 * q == c ? 1.0 : 0.0, 0.0);
+      if (wid == 0) {
 #pragma unroll
-          for (int l = 0; l < i; ++l) v = csub(v, cmul(D[i][l], x[l]));
+        for (int j = 0; j < NP_NB - 1; ++j) {
+          const int src = (j & 3) * 16 + c;
+          const double2 xj = make_double2(__shfl(x[j >> 2].x, src, 64), __shfl(x[j >> 2].y, src, 64));
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (r0 + 4 * q > j) x[q] = csub(x[q], cmul(D[r0 + 4 * q][j], xj));
+          asm volatile("" ::: "memory");   // one step's loads at a time (register budget)
         }
-        x[i] = v;
-      }
 #pragma unroll
-      for (int i = 0; i < NP_NB; ++i) Li[i][t] = x[i];
-    } else if (wid == 1 && lane < NP_NB) {
-      // column t of U11^{-1}, backward substitution
-      const int t = lane;
-      double2 x[NP_NB];
+        for (int q = 0; q < 4; ++q) Li[r0 + 4 * q][c] = x[q];
+      } else {
 #pragma unroll
-      for (int ii = 0; ii < NP_NB; ++ii) {
-        const int i = NP_NB - 1 - ii;
-        double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
-        if (i < nb) {
+        for (int j = NP_NB - 1; j >= 0; --j) {
+          const int src = (j & 3) * 16 + c;
+          const double2 xj = cmul(make_double2(__shfl(x[j >> 2].x, src, 64), __shfl(x[j >> 2].y, src, 64)),
+                                  crcp(D[j][j]));
 #pragma unroll
-          for (int l = i + 1; l < NP_NB; ++l) v = csub(v, cmul(D[i][l], x[l]));
-          v = cmul(v, crcp(D[i][i]));
+          for (int q = 0; q < 4; ++q) {
+            const int r = r0 + 4 * q;
+            if (r == j) x[q] = xj;
+            else if (r < j) x[q] = csub(x[q], cmul(D[r][j], xj));
+          }
+          asm volatile("" ::: "memory");
         }
-        x[i] = v;
-      }
 #pragma unroll
-      for (int i = 0; i < NP_NB; ++i) Ui[i][t] = x[i];
+        for (int q = 0; q < 4; ++q) Ui[r0 + 4 * q][c] = x[q];
+      }
     } else if (wid == 2) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
