@@ -75,8 +75,10 @@ def _cpu_rate(n_phi, l_tau, dtau, u, seconds, sphere):
     """A chain with the same N_phi, momentum set and couplings and at most 16
     slices. Its sweep set-up alone (all slice exponentials and suffix products,
     cost proportional to L: a sweep stopped before its first move), the set-up
-    plus one move, and the set-up plus k moves (k from the one-move estimate so
-    that the moves take about a quarter of the time budget) are timed. The reported rate is
+    plus one move, and the set-up plus k moves are timed; k is as large as the
+    time budget allows, up to every slice of the chain, so that the moves'
+    time stands well above the run-to-run noise of the set-up (best of two
+    runs), from which it is taken as a difference. The reported rate is
     4 n_q / (set-up per slice + time per slice move), the oracle's full-sweep
     rate at any L."""
     import synth
@@ -95,9 +97,9 @@ def _cpu_rate(n_phi, l_tau, dtau, u, seconds, sphere):
         t0 = time.perf_counter()
         dqmc.Chain(m, phi, eps0=0.3, adapt=False).sweep(rp, max_slices=k)
         return time.perf_counter() - t0
-    t_set = timed(0)                          # the set-up alone
+    t_set = min(timed(0), timed(0))           # the set-up alone
     t_1 = timed(1)                            # set-up and one move: the estimate of a move
-    k = max(2, min(ls, int(0.25 * seconds / max(t_1 - t_set, 1e-3)) + 1))
+    k = max(4, min(ls, int((seconds - t_set) / max(t_1 - t_set, 1e-3))))
     t_k = timed(k)
     per_move = max(t_k - t_set, 1e-9) / k
     per_slice = t_set / ls + per_move
