@@ -792,6 +792,8 @@ int build_model_dev(cfqmc_ctx* c) {
   m.nhdiag = (int)T.hdiag.size();
   m.h_sgn = p_sgn; m.h_scale = p_sc; m.h_F = p_F;
   m.nrow = (int)T.t_qy.size();
+  m.maxrow = 1;
+  for (size_t r = 0; r + 1 < T.toff.size(); ++r) m.maxrow = std::max(m.maxrow, T.toff[r + 1] - T.toff[r]);
   m.toff = p_toff; m.t_qy = p_tqy; m.t_qx = p_tqx; m.t_kind = p_tk; m.t_comp = p_tc; m.t_F = p_tF;
   m.beta = p_beta; m.phase = p_ph;
   m.cw = nullptr;

@@ -150,7 +150,7 @@ struct ModelDev {
   const int* h_cre; const int* h_cim; const int* h_qx; const int* h_qy; const int* h_dag;
   const double* h_sgn; const double* h_scale; const double* h_F;
   // trace table: per row r (0..nrow-1) components [toff[r], toff[r+1])
-  int nrow;
+  int nrow, maxrow;   // rows and the largest component count of one row
   const int* toff; const int* t_qy; const int* t_qx; const int* t_kind; const int* t_comp;
   const double* t_F;
   const double* beta;       // background c-number per component [nq]

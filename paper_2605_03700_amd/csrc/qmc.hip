@@ -205,6 +205,10 @@ CF_DEV double2 ytilde(const double2* G, int N, int n, int ch, int a, int b) {
 
 #define DR_NT 256
 #define DR_MAXN 288
+// drift workgroups: one (chain, channel, momentum row) each, a thread per
+// component of the row (at most about 2 N / 3 of them at the paper's cut), so
+// two waves; LDS sized from N and the widest row (drift_lds_bytes)
+#define DRIFT_NT 128
 
 // Drift D = -phi + 2 Re[alpha Tr((1 - G_i)(o_i kron q_c))] of all components in
 // trace row `row` of channel `ch`, written to Dl[t - toff[row]]. One thread per
@@ -215,13 +219,13 @@ CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, do
                       double* Dl, double2* d1, double2* d2, double2* ph) {
   const int N = m.N, n = m.n, qy = m.t_qy[row], N2 = 2 * N;
   const int c_lo = m.toff[row], c_hi = m.toff[row + 1];
-  for (int k = threadIdx.x; k < N; k += DR_NT) {
+  for (int k = threadIdx.x; k < N; k += DRIFT_NT) {
     d1[k] = ytilde(G, N, n, ch, ((k - qy) % N + N) % N, k);
     d2[k] = ytilde(G, N, n, ch, k, ((k - qy) % N + N) % N);
   }
-  for (int i = threadIdx.x; i < N2; i += DR_NT) ph[i] = m.phase[i];
+  for (int i = threadIdx.x; i < N2; i += DRIFT_NT) ph[i] = m.phase[i];
   __syncthreads();
-  for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
+  for (int t = c_lo + threadIdx.x; t < c_hi; t += DRIFT_NT) {
     const int qx = m.t_qx[t];
     // phase index ((2 (k + 1) - q_y) q_x) mod 2N at k = 0, and its step
     int mm = ((2 - qy) * qx) % N2;
@@ -271,7 +275,6 @@ CF_DEV void row_drift(const ModelDev& m, const double2* G, const double* phi, do
   __syncthreads();
 }
 
-#define DR_MAXROW 1024
 
 // (row, channel, chain) of this workgroup: all workgroups of a chain on one XCD
 // (consecutive workgroups go to the eight XCDs in turn), so its frames share an L2.
@@ -285,10 +288,17 @@ CF_DEV bool drift_block(int nrow, int nchain, int& row, int& ch, int& z) {
   return true;
 }
 
-__global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepArgs a) {
-  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN], ph[2 * DR_MAXN];
-  __shared__ double Dl[DR_MAXROW];
-  __shared__ double red[DR_NT / 64];
+// LDS of a drift workgroup: the two gathered diagonals (N each), the phase
+// table (2 N) and the row's drifts (widest row)
+static size_t drift_lds_bytes(const ModelDev& m) {
+  return (size_t)4 * m.N * sizeof(double2) + (size_t)m.maxrow * sizeof(double);
+}
+
+__global__ void __launch_bounds__(DRIFT_NT) drift_propose_kernel(ModelDev m, StepArgs a) {
+  extern __shared__ double2 drift_lds[];
+  double2 *d1 = drift_lds, *d2 = d1 + m.N, *ph = d2 + m.N;
+  double* Dl = (double*)(ph + 2 * m.N);
+  __shared__ double red[DRIFT_NT / 64];
   int row, ch, z;
   if (!drift_block(m.nrow, a.nchain, row, ch, z)) return;
   const int nq = m.nq;
@@ -299,7 +309,7 @@ __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepAr
   row_drift(m, G, phi, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2, ph);
   const double eps = a.eps[z];
   double s_norm = 0.0, s_eta = 0.0, s_bg = 0.0;
-  for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
+  for (int t = c_lo + threadIdx.x; t < c_hi; t += DRIFT_NT) {
     const int c = m.t_comp[t];
     const int j = ch * nq + c;
     const double eta = a.noise ? a.noise[z * a.snoise + j] : rng_normal(a.seed, z, step_counter(a), j);
@@ -310,9 +320,9 @@ __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepAr
     s_eta += eta * eta;
     if (ch == 0) s_bg += (p1 - p0) * m.beta[c];
   }
-  s_norm = block_sum<DR_NT>(s_norm, red);
-  s_eta = block_sum<DR_NT>(s_eta, red);
-  s_bg = block_sum<DR_NT>(s_bg, red);
+  s_norm = block_sum<DRIFT_NT>(s_norm, red);
+  s_eta = block_sum<DRIFT_NT>(s_eta, red);
+  s_bg = block_sum<DRIFT_NT>(s_bg, red);
   if (threadIdx.x == 0) {
     double* p = a.part + ((long long)z * a.nblk + ch * m.nrow + row) * 4;
     p[0] = s_norm;
@@ -321,10 +331,11 @@ __global__ void __launch_bounds__(DR_NT) drift_propose_kernel(ModelDev m, StepAr
   }
 }
 
-__global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a) {
-  __shared__ double2 d1[DR_MAXN], d2[DR_MAXN], ph[2 * DR_MAXN];
-  __shared__ double Dl[DR_MAXROW];
-  __shared__ double red[DR_NT / 64];
+__global__ void __launch_bounds__(DRIFT_NT) drift_mh_kernel(ModelDev m, StepArgs a) {
+  extern __shared__ double2 drift_lds[];
+  double2 *d1 = drift_lds, *d2 = d1 + m.N, *ph = d2 + m.N;
+  double* Dl = (double*)(ph + 2 * m.N);
+  __shared__ double red[DRIFT_NT / 64];
   int row, ch, z;
   if (!drift_block(m.nrow, a.nchain, row, ch, z)) return;
   const int nq = m.nq;
@@ -335,12 +346,12 @@ __global__ void __launch_bounds__(DR_NT) drift_mh_kernel(ModelDev m, StepArgs a)
   row_drift(m, G, phip, a.alpha[z * 4 + ch], ch, row, Dl, d1, d2, ph);   // drift at the proposed fields
   const double eps = a.eps[z];
   double s_rev = 0.0;
-  for (int t = c_lo + threadIdx.x; t < c_hi; t += DR_NT) {
+  for (int t = c_lo + threadIdx.x; t < c_hi; t += DRIFT_NT) {
     const int c = m.t_comp[t];
     const double r = phi[c] - phip[c] - 0.5 * eps * eps * Dl[t - c_lo];
     s_rev += r * r;
   }
-  s_rev = block_sum<DR_NT>(s_rev, red);
+  s_rev = block_sum<DRIFT_NT>(s_rev, red);
   if (threadIdx.x == 0) a.part[((long long)z * a.nblk + ch * m.nrow + row) * 4 + 3] = s_rev;
 }
 
@@ -393,13 +404,13 @@ void launch_drift_propose(const ModelDev& m, const StepArgs& a, int nchain, hipS
   StepArgs b = a;
   b.nchain = nchain;
   const int nblk = (int)(((long long)m.nrow * 4 * nchain + 7) / 8 * 8);
-  hipLaunchKernelGGL(drift_propose_kernel, dim3(nblk), dim3(DR_NT), 0, s, m, b); cfqmc_post_launch("drift_propose_kernel");
+  hipLaunchKernelGGL(drift_propose_kernel, dim3(nblk), dim3(DRIFT_NT), drift_lds_bytes(m), s, m, b); cfqmc_post_launch("drift_propose_kernel");
 }
 void launch_drift_mh(const ModelDev& m, const StepArgs& a, int nchain, hipStream_t s) {
   StepArgs b = a;
   b.nchain = nchain;
   const int nblk = (int)(((long long)m.nrow * 4 * nchain + 7) / 8 * 8);
-  hipLaunchKernelGGL(drift_mh_kernel, dim3(nblk), dim3(DR_NT), 0, s, m, b); cfqmc_post_launch("drift_mh_kernel");
+  hipLaunchKernelGGL(drift_mh_kernel, dim3(nblk), dim3(DRIFT_NT), drift_lds_bytes(m), s, m, b); cfqmc_post_launch("drift_mh_kernel");
 }
 
 // ------------------------------------------------------------------ commit
