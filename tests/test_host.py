@@ -263,3 +263,16 @@ def test_fss_grid_scan_recovers_known_critical_point():
     assert abs(uc - 0.195) <= 0.005 + 1e-9 and abs(ds - 2.65) <= 0.1 + 1e-9
     x, Y, F, r2c = data_collapse(U, N, R, uc, ds)
     assert x.shape == Y.shape == F.shape and r2c > 0.99
+
+
+def test_cpu_baseline_times_several_moves():
+    """The host oracle's rate takes the slice-move time as the difference of
+    two separately timed runs (set-up plus k moves, set-up alone), so k must
+    be large enough for the moves to stand above the set-up's run-to-run
+    noise: at least four moves, up to every slice of the chain."""
+    import bench
+    r = bench._cpu_rate(4, 8, 0.1, 1.5, seconds=2.0, sphere=False)
+    k = int(re.search(r"first (\d+) slice moves", r["sample"]).group(1))
+    assert 4 <= k <= 8
+    assert np.isfinite(r["value"]) and r["value"] > 0
+    assert r["kind"] == "oracle" and r["unit"] == "field updates/s"
